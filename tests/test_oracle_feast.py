@@ -1,0 +1,250 @@
+"""Pins of the oracle's contour filter and FEAST iteration.
+
+Every check compares the oracle with something other than itself: matrices with
+prescribed spectra (the filter then has the closed form X rho_a(Lambda) Xh^H B Y
+of eq:q00 / eq:qhat0), brute-force QZ eigendecompositions, the closed-form
+spectrum of the 2D convection-diffusion operator, and the invariants the paper
+states (Xh^H B X = I, Uh^H B U = I, B_Q = (Yh^H B X) rho_a^2 (Xh^H B Y)).
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import workloads as W
+from oracle import contour as ct
+from oracle import feast as F
+from oracle import linsolve as L
+
+
+def _prescribed(n=60, n_in=6, seed=11):
+    return W.dense_prescribed(n=n, n_in=n_in, center=0.1 + 0.1j, radius=0.25, ne=8, m0=10, seed=seed)
+
+
+def test_filter_prescribed_spectrum_standard():
+    p = _prescribed()
+    V, lam = p.info["V"], p.info["lam"]
+    z, w = ct.ellipse_nodes(p.contour.center, p.contour.a, 1.0, 0.0, 8)
+    Q, Qh = F.contour_filter(p.A, None, z, w, p.Y0, p.Yh0)
+    rho = ct.rational(z, w, lam)
+    Vi = np.linalg.inv(V)
+    Qx = V @ (rho[:, None] * (Vi @ p.Y0))                       # eq:q00
+    Qhx = Vi.conj().T @ (np.conj(rho)[:, None] * (V.conj().T @ p.Yh0))   # eq:qhat0
+    assert np.linalg.norm(Q - Qx) / np.linalg.norm(Qx) < 1e-11
+    assert np.linalg.norm(Qh - Qhx) / np.linalg.norm(Qhx) < 1e-11
+    # the same through the sparse (SuperLU) path on the dense pattern
+    n = p.n
+    As = L.csr_matrix({"n": n, "rowptr": np.arange(0, n * n + 1, n), "colind": np.tile(np.arange(n), n),
+                       "val": p.A.ravel()})
+    Q2, Qh2 = F.contour_filter(As, None, z, w, p.Y0, p.Yh0)
+    assert np.linalg.norm(Q2 - Qx) / np.linalg.norm(Qx) < 1e-11
+    assert np.linalg.norm(Qh2 - Qhx) / np.linalg.norm(Qhx) < 1e-11
+
+
+def test_filter_prescribed_spectrum_generalized():
+    # B^{-1} A = V Lambda V^{-1} with a general B: Xh^H = V^{-1} B^{-1}
+    rng = np.random.default_rng(4)
+    n = 50
+    V = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    lam = 0.9 * (rng.random(n) - 0.5 + 1j * (rng.random(n) - 0.5)) * 2
+    B = np.eye(n) + 0.2 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    A = B @ V @ np.diag(lam) @ np.linalg.inv(V)
+    z, w = ct.ellipse_nodes(0.05 - 0.1j, 0.4, 0.6, 0.3, 12)
+    Y = W.subspace(n, 7, 1)
+    Yh = W.subspace(n, 7, 2)
+    Q, Qh = F.contour_filter(A, B, z, w, Y, Yh)
+    rho = ct.rational(z, w, lam)
+    Vi = np.linalg.inv(V)
+    Bi = np.linalg.inv(B)
+    Qx = V @ (rho[:, None] * (Vi @ Y))
+    Xh_H = Vi @ Bi
+    Qhx = (Yh.conj().T @ B @ V @ np.diag(rho) @ Xh_H).conj().T
+    assert np.linalg.norm(Q - Qx) / np.linalg.norm(Qx) < 1e-10
+    assert np.linalg.norm(Qh - Qhx) / np.linalg.norm(Qhx) < 1e-10
+    # B_Q closed form (eq:bdiag1)
+    BQ = Qh.conj().T @ B @ Q
+    BQx = Yh.conj().T @ B @ V @ np.diag(rho ** 2) @ Xh_H @ B @ Y
+    assert np.linalg.norm(BQ - BQx) / np.linalg.norm(BQx) < 1e-10
+
+
+def test_per_node_backward_error():
+    p = _prescribed(n=80)
+    z, w = ct.ellipse_nodes(p.contour.center, p.contour.a, 1.0, 0.0, 8)
+    for zj in z:
+        Fj = L.DirectFactor(L.shifted(p.A, None, zj))
+        M = zj * np.eye(p.n) - p.A
+        X = Fj.solve(p.Y0, "N")
+        be = np.linalg.norm(p.Y0 - M @ X) / (np.linalg.norm(M) * np.linalg.norm(X) + np.linalg.norm(p.Y0))
+        assert be < 1e-14
+        Xh = Fj.solve(p.Yh0, "H")
+        be = np.linalg.norm(p.Yh0 - M.conj().T @ Xh) / (np.linalg.norm(M) * np.linalg.norm(Xh) + np.linalg.norm(p.Yh0))
+        assert be < 1e-14
+
+
+def test_biorthonormalization_and_resize():
+    p = _prescribed()
+    z, w = ct.ellipse_nodes(p.contour.center, p.contour.a, 1.0, 0.0, 8)
+    Q, Qh = F.contour_filter(p.A, None, z, w, p.Y0, p.Yh0)
+    BQ = Qh.conj().T @ Q
+    rb = F.resize_biortho(Q, Qh, BQ)
+    m = rb["m0t"]
+    assert m == p.m0
+    assert np.max(np.abs(rb["Uh"].conj().T @ rb["U"] - np.eye(m))) < 1e-10
+    assert np.all(np.diff(np.abs(rb["gamma"])) <= 0)
+    # B_Q = V Gamma Vh^H
+    np.testing.assert_allclose(rb["V"] @ np.diag(rb["gamma"]) @ rb["Vh"].conj().T, BQ, atol=1e-12)
+    # duplicated start columns -> rank-deficient B_Q -> subspace shrinks
+    Y = p.Y0.copy(); Yh = p.Yh0.copy()
+    Y[:, 7:] = Y[:, :3]
+    Yh[:, 7:] = Yh[:, :3]
+    Q, Qh = F.contour_filter(p.A, None, z, w, Y, Yh)
+    rb = F.resize_biortho(Q, Qh, Qh.conj().T @ Q)
+    assert rb["m0t"] < p.m0
+    # the rank-7 well-resolved part stays bi-orthonormal; directions kept at the
+    # eta = 1e-16 edge are rounding noise and are not checked
+    k = 7
+    assert np.max(np.abs(rb["Uh"][:, :k].conj().T @ rb["U"][:, :k] - np.eye(k))) < 1e-6
+
+
+def test_spurious_criterion():
+    rho_prev = np.array([1.0, 0.9, 0.5, 1e-3 + 1e-3j])
+    bq = np.array([1.0, 0.81 * 1.05, 0.25 * 2.0, ((1e-3 + 1e-3j) ** 2) * 1.2])
+    flags = F.spurious_flags(bq, rho_prev)
+    assert flags.tolist() == [False, False, True, True]
+    # around the threshold mu = 0.1 (flagged when the relative gap is >= mu)
+    assert F.spurious_flags(np.array([1.1 + 0j, 1.0999 + 0j]), np.array([1.0 + 0j, 1.0 + 0j])).tolist() == [True, False]
+
+
+def test_rayleigh_ritz_normalization():
+    rng = np.random.default_rng(8)
+    m = 9
+    AU = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    BU = np.eye(m) + 0.05 * (rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)))
+    U = np.eye(m, dtype=complex)
+    rr = F.rayleigh_ritz(AU, BU, U, U)
+    W_, Wh, lam = rr["W"], rr["Wh"], rr["lam"]
+    np.testing.assert_allclose(Wh.conj().T @ BU @ W_, np.eye(m), atol=1e-12)
+    np.testing.assert_allclose(AU @ W_, BU @ W_ * lam[None, :], atol=1e-12)
+    np.testing.assert_allclose(AU.conj().T @ Wh, BU.conj().T @ Wh * np.conj(lam)[None, :], atol=1e-12)
+    ref = sla.eigvals(np.linalg.solve(BU, AU))
+    np.testing.assert_allclose(np.sort_complex(lam), np.sort_complex(ref), atol=1e-12)
+
+
+def test_feast_dense_prescribed_against_truth():
+    p = W.dense_prescribed(n=150, n_in=8, center=0.1 + 0.1j, radius=0.25, ne=8, m0=16, seed=21)
+    cont = F.Contour(p.contour.center, p.contour.a, 1.0, 0.0, 8)
+    r = F.feast(p.A, None, cont, p.Y0, p.Yh0, eps=1e-12, max_iter=60)
+    assert r.info == 0
+    lam_true = p.info["lam"][: p.info["n_in"]]
+    lam_true = lam_true[np.lexsort((lam_true.imag, lam_true.real))]
+    assert len(r.lam) == len(lam_true)
+    assert np.max(np.abs(r.lam - lam_true)) < 1e-10 * cont.alpha()
+    assert np.max(np.abs(r.Xh.conj().T @ r.X - np.eye(len(r.lam)))) < 1e-10
+    # brute force with both sides (LAPACK QZ on the full matrix)
+    ev = sla.eigvals(p.A)
+    ev = ev[cont.inside(ev)]
+    ev = ev[np.lexsort((ev.imag, ev.real))]
+    assert np.max(np.abs(ev - r.lam)) < 1e-10 * cont.alpha()
+    # eigen-residual in the spec form, right and left, 1-norms
+    nA = np.abs(p.A).sum(axis=0).max()
+    rr = np.abs(p.A @ r.X - r.X * r.lam).sum(axis=0) / (nA * np.abs(r.X).sum(axis=0))
+    rl = np.abs(p.A.conj().T @ r.Xh - r.Xh * np.conj(r.lam)).sum(axis=0) / (nA * np.abs(r.Xh).sum(axis=0))
+    assert rr.max() < 1e-10 and rl.max() < 1e-10
+    # one factorization per node, two solves per node per iteration
+    assert r.counters.factorizations == 8 and r.counters.solves == 2 * 8 * r.iters
+
+
+def test_feast_generalized_brute_force():
+    rng = np.random.default_rng(31)
+    n = 90
+    A = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2 * n)
+    B = np.eye(n) + 0.1 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2 * n)
+    ev = sla.eigvals(A, B)
+    c = 0.2 - 0.1j
+    d = np.sort(np.abs(ev - c))
+    r = 0.5 * (d[5] + d[6])                     # exactly 6 inside, radius in the gap
+    cont = F.Contour(c, r, 1.0, 0.0, 16)
+    res = F.feast(A, B, cont, W.subspace(n, 12, 5), W.subspace(n, 12, 6), eps=1e-12, max_iter=40)
+    assert res.info == 0 and len(res.lam) == 6
+    evi = ev[cont.inside(ev)]
+    evi = evi[np.lexsort((evi.imag, evi.real))]
+    assert np.max(np.abs(evi - res.lam)) < 1e-10 * cont.alpha()
+    np.testing.assert_allclose(res.Xh.conj().T @ B @ res.X, np.eye(6), atol=1e-10)
+    np.testing.assert_allclose(A @ res.X, B @ res.X * res.lam, atol=1e-10)
+    np.testing.assert_allclose(A.conj().T @ res.Xh, B.conj().T @ res.Xh * np.conj(res.lam), atol=1e-10)
+
+
+def test_feast_convdiff_closed_form():
+    # closed-form spectrum of T(bx) (x) I + I (x) T(by)
+    p = W.convdiff2d(N=24, m_in=10, m0=20)
+    A = L.csr_matrix(p.A)
+    cont = F.Contour(p.contour.center, p.contour.a, p.contour.ratio, 0.0, 16)
+    res = F.feast(A, None, cont, p.Y0, p.Yh0, eps=1e-12, max_iter=30)
+    assert res.info == 0 and len(res.lam) == 10
+    ref = p.info["lam_sorted"][:10]
+    assert np.max(np.abs(np.sort(res.lam.real) - ref)) < 1e-10 * cont.alpha()
+    assert np.max(np.abs(res.lam.imag)) < 1e-10 * cont.alpha()
+    np.testing.assert_allclose(res.Xh.conj().T @ res.X, np.eye(10), atol=1e-10)
+
+
+def test_hermitian_special_case_left_equals_right():
+    rng = np.random.default_rng(41)
+    n = 70
+    Qm, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    lam = np.linspace(-3, 3, n) + 0.01 * rng.standard_normal(n)
+    A = Qm @ np.diag(lam) @ Qm.conj().T
+    A = 0.5 * (A + A.conj().T)
+    ls = np.sort(lam)
+    c = 0.5 * (ls[30] + ls[35])
+    r = 0.5 * ((ls[36] - ls[29])) - 0.5 * min(ls[36] - ls[35], ls[30] - ls[29])
+    cont = F.Contour(complex(c), r, 1.0, 0.0, 16)
+    res = F.feast(A, None, cont, W.subspace(n, 12, 1), W.subspace(n, 12, 2), eps=1e-12, max_iter=40)
+    assert res.info == 0 and len(res.lam) == 6
+    np.testing.assert_allclose(res.Xh, res.X, atol=1e-9)          # Xh = X
+    assert np.max(np.abs(res.lam.imag)) < 1e-12
+
+
+def test_complex_symmetric_left_is_conjugate_right():
+    rng = np.random.default_rng(42)
+    n = 70
+    G = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A = (G + G.T) / np.sqrt(8 * n)
+    ev = sla.eigvals(A)
+    c = ev[np.argmin(np.abs(ev))]
+    d = np.sort(np.abs(ev - c))
+    cont = F.Contour(c, 0.5 * (d[4] + d[5]), 1.0, 0.0, 16)
+    res = F.feast(A, None, cont, W.subspace(n, 10, 3), W.subspace(n, 10, 4), eps=1e-12, max_iter=40)
+    assert res.info == 0 and len(res.lam) == 5
+    for i in range(5):
+        x, xh = res.X[:, i], res.Xh[:, i]
+        cosang = abs(np.vdot(np.conj(x), xh)) / (np.linalg.norm(x) * np.linalg.norm(xh))
+        assert cosang > 1 - 1e-10                                    # Xh = conj(X) up to scale
+
+
+def test_convergence_rate_prediction():
+    # Section 2.3: residuals fall by |rho_a(lam_{m0+1}) / rho_a(lam_i)| per iteration.
+    rng = np.random.default_rng(3)
+    n, n_in, m0 = 200, 6, 8
+    u_in = np.sqrt(rng.uniform(0.04, 0.36, n_in)) * np.exp(2j * np.pi * rng.random(n_in))
+    r_out = np.sqrt(rng.uniform(1.25 ** 2, 4.0 ** 2, n - n_in))
+    u_out = r_out * np.exp(2j * np.pi * rng.random(n - n_in))
+    lam = 0.5 * np.concatenate([u_in, u_out])
+    V = W.subspace(n, n, 77)
+    V /= np.linalg.norm(V, axis=0, keepdims=True)
+    A = np.linalg.solve(V.T, (V * lam[None, :]).T).T
+    cont = F.Contour(0.0, 0.5, 1.0, 0.0, 8)
+    z, w = cont.nodes()
+    rho = np.abs(ct.rational(z, w, lam))
+    srt = np.sort(rho)[::-1]
+    rate = srt[m0] / np.min(rho[:n_in])                     # slowest wanted pair
+    assert 0.02 < rate < 0.5
+    res = F.feast(A, None, cont, W.subspace(n, m0, 1), W.subspace(n, m0, 2), eps=1e-14, max_iter=30)
+    worst = []
+    for h in res.history:
+        r = h["res"][h["inside"]]
+        worst.append(np.sort(r)[n_in - 1] if len(r) >= n_in else np.nan)
+    worst = np.array(worst)
+    idx = np.nonzero(np.isfinite(worst) & (worst > 1e-12))[0]
+    idx = idx[idx >= 2]
+    assert len(idx) >= 3
+    obs = np.exp(np.polyfit(idx, np.log(worst[idx]), 1)[0])
+    assert abs(np.log(obs / rate)) < np.log(1.6), (obs, rate)

@@ -1,0 +1,220 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
+
+This module builds problem instances only: matrices, contours (centre, semi-axes,
+rotation) and start subspaces.  It holds none of the eigensolver's arithmetic
+(no quadrature, no shifted solves, no Rayleigh-Ritz); both the CPU oracle and
+the HIP path receive exactly these arrays.
+
+Recipes (the paper measures on the NEP collection and on CSH4, neither of which
+is available here; these synthetic problems stand in for them, shaped like the
+paper's own dense "eigenvalues inside the unit disk" matrix of the parallelism
+experiments in Section 4.1 and like the sparse operators FEAST is aimed at):
+
+* ``dense_prescribed``  -- A = V diag(lam) V^{-1}, V complex Gaussian with unit
+  2-norm columns; ``n_in`` eigenvalues area-uniform inside a circle, the rest
+  area-uniform in the unit disk outside that circle.
+* ``convdiff2d``        -- -Laplace(u) + b.grad(u) on the unit square, Dirichlet,
+  5-point central differences scaled by 1/h^2, lexicographic order (x fastest),
+  real CSR.
+* ``gen_dense_batch``   -- A = G/sqrt(n), B = I + 0.1 G'/sqrt(n), G complex
+  Gaussian with E|g|^2 = 1.
+* ``subspace``          -- complex Gaussian (N(0,1) + i N(0,1))/sqrt(2) block.
+
+All random draws use numpy's PCG64 (``numpy.random.default_rng``).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def _cgauss(rng, shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / math.sqrt(2.0)
+
+
+def subspace(n: int, m0: int, seed: int) -> np.ndarray:
+    """Complex Gaussian n x m0 start block (row i holds the m0 entries of row i)."""
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(_cgauss(rng, (n, m0)))
+
+
+@dataclass
+class Contour:
+    """Ellipse z(t) = c + e^{i angle} (a cos t + i b sin t), b = ratio * a."""
+    center: complex
+    a: float
+    ratio: float = 1.0
+    angle: float = 0.0
+    ne: int = 8
+
+
+@dataclass
+class Problem:
+    name: str
+    n: int
+    A: object                      # dense ndarray (n x n, complex128) or CSR dict
+    B: object | None               # None means B = I
+    contour: Contour
+    m0: int
+    Y0: np.ndarray
+    Yh0: np.ndarray
+    info: dict = field(default_factory=dict)
+
+
+# --------------------------------------------------------------------------
+# Dense problem with prescribed spectrum (first configuration and its minis)
+# --------------------------------------------------------------------------
+def _area_uniform_disk(rng, count, center, radius):
+    u = rng.random(count)
+    v = rng.random(count)
+    return center + radius * np.sqrt(u) * np.exp(2j * math.pi * v)
+
+
+def dense_prescribed(n=400, n_in=24, center=0.1 + 0.1j, radius=0.25, ne=8, m0=36,
+                     seed=1) -> Problem:
+    rng = np.random.default_rng(seed)
+    V = _cgauss(rng, (n, n))
+    V /= np.linalg.norm(V, axis=0, keepdims=True)
+    lam_in = _area_uniform_disk(rng, n_in, center, radius)
+    out = []
+    while len(out) < n - n_in:
+        cand = _area_uniform_disk(rng, 2 * (n - n_in), 0.0, 1.0)
+        cand = cand[np.abs(cand - center) >= radius]
+        out.extend(cand.tolist())
+    lam = np.concatenate([lam_in, np.array(out[: n - n_in])])
+    # A = V diag(lam) V^{-1}  ->  A^T = V^{-T} (V diag(lam))^T
+    A = np.linalg.solve(V.T, (V * lam[None, :]).T).T
+    Y0 = subspace(n, m0, seed * 100 + 1)
+    Yh0 = subspace(n, m0, seed * 100 + 2)
+    return Problem(name=f"dense_prescribed_n{n}", n=n, A=np.ascontiguousarray(A), B=None,
+                   contour=Contour(center=center, a=radius, ratio=1.0, angle=0.0, ne=ne),
+                   m0=m0, Y0=Y0, Yh0=Yh0,
+                   info={"lam": lam, "V": V, "n_in": n_in})
+
+
+# --------------------------------------------------------------------------
+# 2D convection-diffusion, 5-point central differences (second configuration)
+# --------------------------------------------------------------------------
+def convdiff2d_csr(N: int, bx: float, by: float):
+    """CSR (0-based, sorted columns) of -Lap(u) + (bx, by).grad(u) on an N x N
+    interior grid of the unit square, h = 1/(N+1), index = ix + N*iy."""
+    h = 1.0 / (N + 1)
+    inv_h2 = 1.0 / (h * h)
+    n = N * N
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    cols = []
+    vals = []
+    # coefficients: u_{p-1}: -1/h^2 - b/(2h); u_{p+1}: -1/h^2 + b/(2h)
+    wx, ex = -inv_h2 - bx / (2 * h), -inv_h2 + bx / (2 * h)
+    sy, ny = -inv_h2 - by / (2 * h), -inv_h2 + by / (2 * h)
+    diag = 4.0 * inv_h2
+    idx = 0
+    for iy in range(N):
+        for ix in range(N):
+            r = ix + N * iy
+            if iy > 0:
+                cols.append(r - N); vals.append(sy)
+            if ix > 0:
+                cols.append(r - 1); vals.append(wx)
+            cols.append(r); vals.append(diag)
+            if ix < N - 1:
+                cols.append(r + 1); vals.append(ex)
+            if iy < N - 1:
+                cols.append(r + N); vals.append(ny)
+            idx = len(cols)
+            rowptr[r + 1] = idx
+    return {"n": n, "rowptr": rowptr, "colind": np.asarray(cols, dtype=np.int32),
+            "val": np.asarray(vals, dtype=np.float64)}
+
+
+def convdiff1d_eigs(N: int, b: float) -> np.ndarray:
+    """Eigenvalues of tridiag(-1/h^2 - b/2h, 2/h^2, -1/h^2 + b/2h) (N x N): the
+    Toeplitz closed form 2/h^2 - 2 sqrt(beta*gamma) cos(j pi h), j = 1..N.
+    Used only to place the second configuration's contour in spectral gaps."""
+    h = 1.0 / (N + 1)
+    beta = -1.0 / h**2 - b / (2 * h)
+    gamma = -1.0 / h**2 + b / (2 * h)
+    j = np.arange(1, N + 1)
+    return 2.0 / h**2 - 2.0 * np.sqrt(beta * gamma) * np.cos(j * math.pi * h)
+
+
+def convdiff2d(N=256, bx=20.0, by=10.0, m_in=41, ne=16, m0=64, ratio=0.3, seed=2,
+               left_margin=15.0) -> Problem:
+    """Ellipse on the real axis from lam_1 - left_margin to the midpoint of the
+    gap between eigenvalues m_in and m_in + 1 (sorted, closed form)."""
+    ex = convdiff1d_eigs(N, bx)
+    ey = convdiff1d_eigs(N, by)
+    lam = np.sort((ex[:, None] + ey[None, :]).ravel())
+    left = lam[0] - left_margin
+    right = 0.5 * (lam[m_in - 1] + lam[m_in])
+    c = 0.5 * (left + right)
+    a = 0.5 * (right - left)
+    A = convdiff2d_csr(N, bx, by)
+    n = N * N
+    Y0 = subspace(n, m0, seed * 100 + 1)
+    Yh0 = subspace(n, m0, seed * 100 + 2)
+    return Problem(name=f"convdiff2d_N{N}", n=n, A=A, B=None,
+                   contour=Contour(center=complex(c, 0.0), a=a, ratio=ratio, angle=0.0, ne=ne),
+                   m0=m0, Y0=Y0, Yh0=Yh0,
+                   info={"lam_sorted": lam, "m_in": m_in, "N": N, "b": (bx, by)})
+
+
+# --------------------------------------------------------------------------
+# Batch of dense generalized problems (third configuration)
+# --------------------------------------------------------------------------
+def gen_dense_batch(count=64, nmin=256, nmax=2048, ne=8, m0=32, radius=0.3, seed=3,
+                    scaled_radius=False):
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(nmin, nmax + 1, size=count)
+    probs = []
+    for i, n in enumerate(sizes):
+        n = int(n)
+        A = _cgauss(rng, (n, n)) / math.sqrt(n)
+        B = np.eye(n) + 0.1 * _cgauss(rng, (n, n)) / math.sqrt(n)
+        c = complex(_area_uniform_disk(rng, 1, 0.0, 1.0)[0])
+        r = radius * math.sqrt(nmin / n) if scaled_radius else radius
+        Y0 = subspace(n, m0, seed * 100000 + 2 * i + 1)
+        Yh0 = subspace(n, m0, seed * 100000 + 2 * i + 2)
+        probs.append(Problem(name=f"gen_dense_{i}_n{n}", n=n, A=np.ascontiguousarray(A),
+                             B=np.ascontiguousarray(B),
+                             contour=Contour(center=c, a=r, ratio=1.0, angle=0.0, ne=ne),
+                             m0=m0, Y0=Y0, Yh0=Yh0))
+    return probs
+
+
+# --------------------------------------------------------------------------
+# Small helpers for tests
+# --------------------------------------------------------------------------
+def csr_to_dense(A) -> np.ndarray:
+    n = A["n"]
+    D = np.zeros((n, n), dtype=np.result_type(A["val"].dtype, np.float64))
+    rp, ci, v = A["rowptr"], A["colind"], A["val"]
+    for i in range(n):
+        D[i, ci[rp[i]:rp[i + 1]]] = v[rp[i]:rp[i + 1]]
+    return D
+
+
+def random_sparse_csr(n, density, seed, complex_vals=True, diag_shift=0.0):
+    """Random sparse matrix with a full diagonal (for ILU(0)/SpMM edge cases)."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for i in range(n):
+        k = rng.random(n) < density
+        k[i] = True
+        rows.append(np.nonzero(k)[0].astype(np.int32))
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    rowptr[1:] = np.cumsum([len(r) for r in rows])
+    colind = np.concatenate(rows).astype(np.int32)
+    nnz = len(colind)
+    if complex_vals:
+        val = _cgauss(rng, nnz)
+    else:
+        val = rng.standard_normal(nnz)
+    # make it diagonally heavy so ILU(0) exists
+    for i in range(n):
+        for p in range(rowptr[i], rowptr[i + 1]):
+            if colind[p] == i:
+                val[p] = val[p] + diag_shift
+    return {"n": n, "rowptr": rowptr, "colind": colind, "val": val}
