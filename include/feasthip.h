@@ -1,0 +1,198 @@
+/*
+ * feasthip -- non-Hermitian FEAST (Kestyn, Polizzi, Tang, "FEAST eigensolver
+ * for non-Hermitian problems") on AMD MI355X (gfx950).
+ *
+ * C ABI.  No torch or HIP types appear in the signatures: device buffers are
+ * plain pointers, the stream is an opaque pointer (a hipStream_t).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * complex numbers  interleaved (re, im) pairs of double (complex128) unless a
+ *                  call says otherwise; a "complex array of length k" is 2k
+ *                  doubles.
+ * block vectors    Y, Yh, Q, Qh, X ...: n x m0 complex, ROW-major: entry
+ *                  (i, k) at offset i*ld + k, ld >= m0 (ld = m0 when not given).
+ * dense matrices   n x n complex, ROW-major with leading dimension ld.
+ * CSR matrices     0-based int32 row pointers (n+1) and column indices (nnz),
+ *                  column indices sorted within each row; values real (FH_R64)
+ *                  or complex (FH_C128).
+ * ownership        every buffer passed in belongs to the caller and is never
+ *                  freed by the library; input matrices are never modified.
+ *                  The library allocates its own workspace (device memory) in
+ *                  the handle and in prepared problems, and frees it in
+ *                  fh_destroy / fh_problem_destroy.
+ * streams          all GPU work of a handle runs on the handle's stream; calls
+ *                  return after that work has completed.  A handle is not
+ *                  thread-safe.
+ * return codes     0 success; -k argument k invalid (1-based, LAPACK style);
+ *                  positive codes below; fh_last_error() gives a message.
+ */
+#ifndef FEASTHIP_H
+#define FEASTHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define FH_OK                0
+#define FH_NO_EIG_INSIDE     1   /* no Ritz value inside the contour after max_iter  */
+#define FH_NOT_CONVERGED     2   /* max_iter reached; best pairs and res are filled   */
+#define FH_M0_TOO_SMALL      3   /* m_r >= m0 at exit: the subspace is probably < m   */
+#define FH_SINGULAR_SHIFT    4   /* zero pivot / breakdown at a node (bad_node = j)   */
+#define FH_INNER_FAILED      5   /* an iterative inner solve missed its tolerance     */
+#define FH_NONFINITE         6   /* non-finite input or state                          */
+#define FH_EIG_FAILED        7   /* reduced eigenproblem (QR iteration) did not converge */
+#define FH_HIP_ERROR       100   /* HIP runtime error or out of memory                 */
+
+enum { FH_DENSE = 0, FH_CSR = 1 };
+enum { FH_R64 = 0, FH_C128 = 1 };
+enum { FH_PREC_FP64 = 0, FH_PREC_MIXED = 1 };        /* solve precision            */
+enum { FH_SOLVER_LU = 0, FH_SOLVER_BGMRES = 1 };      /* shifted-system solver      */
+enum { FH_PC_NONE = 0, FH_PC_JACOBI = 1, FH_PC_ILU0 = 2 };
+
+typedef struct fh_ctx*  fh_handle;
+typedef struct fh_prob* fh_problem;
+
+/* A matrix operand; all pointers are DEVICE pointers owned by the caller. */
+typedef struct {
+    int kind;             /* FH_DENSE or FH_CSR                               */
+    int dtype;            /* FH_R64 (CSR only) or FH_C128                     */
+    int n;                /* order                                            */
+    int ld;               /* dense: leading dimension (>= n)                  */
+    long long nnz;        /* CSR: number of stored entries                    */
+    const void* val;      /* dense: n*ld values; CSR: nnz values              */
+    const int* rowptr;    /* CSR: n+1                                         */
+    const int* colind;    /* CSR: nnz                                         */
+} fh_mat;
+
+/* Search contour: ellipse z(t) = c + e^{i angle} (a cos t + i ratio*a sin t).
+ * Paper Section 2.1 (complex midpoint, radius, axis ratio, rotation angle). */
+typedef struct {
+    double c_re, c_im;    /* centre lambda_mid                                */
+    double a;             /* horizontal semi-axis (radius for a circle)       */
+    double ratio;         /* vertical / horizontal semi-axis (1 = circle)     */
+    double angle;         /* rotation in radians                              */
+    int ne;               /* number of quadrature nodes                       */
+} fh_contour;
+
+typedef struct {
+    int m0;               /* search subspace size (columns of Y)              */
+    int max_iter;         /* FEAST iterations                                 */
+    double eps;           /* threshold of eq:res                              */
+    int precision;        /* FH_PREC_FP64 or FH_PREC_MIXED                    */
+    int solver;           /* FH_SOLVER_LU (dense) or FH_SOLVER_BGMRES (CSR)   */
+    int restart;          /* block GMRES restart length (block steps)         */
+    int block;            /* block size s of block GMRES (<= m0; 0 -> m0)     */
+    int precond;          /* FH_PC_*                                          */
+    double inner_tol;     /* relative residual target of each inner solve     */
+    int max_restarts;     /* block GMRES cycles per solve (FP64) / per refinement */
+    double mixed_inner_tol; /* mixed: FP32 inner-solve target per refinement step */
+    int max_refine;       /* mixed: FP64 refinement steps                     */
+    int save_factors;     /* keep per-node factorizations across calls         */
+} fh_opts;
+
+typedef struct {
+    int info;             /* status code of the call                          */
+    int m;                /* converged eigenpairs returned                    */
+    int iters;            /* FEAST iterations performed                       */
+    int m0_final;         /* subspace size after resizing                     */
+    int bad_node;         /* node index for FH_SINGULAR_SHIFT / inner failure  */
+    int m_s;              /* spurious Ritz values flagged in the last iteration */
+    long long n_factor;   /* factorizations performed (Table tab:solve)       */
+    long long n_solve;    /* m0-column shifted solves performed                */
+    long long inner_steps;/* block Krylov steps (all systems) in the last filter */
+    double inner_relres;  /* worst final relative residual of the last filter  */
+    double t_filter_ms;   /* time of the last contour integration             */
+    double t_iter_ms;     /* time of the last full FEAST iteration            */
+} fh_report;
+
+/* ---- handle ----------------------------------------------------------- */
+int         fh_create(fh_handle* h, int device, void* hip_stream);
+int         fh_destroy(fh_handle h);
+int         fh_set_stream(fh_handle h, void* hip_stream);
+const char* fh_last_error(fh_handle h);
+void        fh_default_opts(fh_opts* o);
+
+/* ---- contour (host, FP64) ---------------------------------------------
+ * Trapezoidal nodes t_j = 2 pi (j - 1/2)/ne and weights w_j = z'(t_j)/(i ne):
+ * the rational filter rho_a(z) = sum_j w_j/(z_j - z) of eq:rational
+ * approximating the Cauchy integral eq:cauchy (Sections 1, 2.1, 2.3).
+ * z, w: host complex arrays of length ne. */
+int fh_contour_nodes(const fh_contour* c, double* z, double* w);
+/* rho_a at nlam host points (eq:rational).  lam, rho: host complex arrays. */
+int fh_rational(int ne, const double* z, const double* w, int nlam, const double* lam, double* rho);
+
+/* ---- prepared problem ---------------------------------------------------
+ * Holds A, B (B == NULL means B = I) and, once computed, the per-node
+ * factorizations that the paper keeps across FEAST iterations (Section 4.1:
+ * saving the factorizations).  Dense problems use complex LU with partial
+ * pivoting; CSR problems use ILU(0) of (z_j B - A), natural ordering, as the
+ * preconditioner of block GMRES.  CSR B must be NULL (identity). */
+int fh_problem_create(fh_handle h, const fh_mat* A, const fh_mat* B, fh_problem* p);
+int fh_problem_destroy(fh_problem p);
+
+/* ---- contour filter (the hot path alone), eq:qr and eq:ql ---------------
+ *   Q  = sum_j w_j       (z_j B - A)^{-1}  B   Y
+ *   Qh = sum_j conj(w_j) (z_j B - A)^{-H}  B^H Yh
+ * z, w: host complex arrays of length ne.  Y, Yh, Q, Qh: device n x m0 row-
+ * major blocks (ld = m0).  One factorization per node serves both sides
+ * (Section 2.4).  rep may be NULL. */
+int fh_filter(fh_handle h, fh_problem p, int ne, const double* z, const double* w, int m0,
+              const void* Y, const void* Yh, void* Q, void* Qh, const fh_opts* o, fh_report* rep);
+
+/* ---- non-Hermitian FEAST (complete algorithm figure, steps 0-5) ----------
+ * Y, Yh   in: start subspaces (n x m0, device, step 0); out: the m converged
+ *         right / left eigenvectors in columns 0..m-1 (ld = m0), normalised
+ *         so that Xh^H B X = I (step 5.d).
+ * lambda  device complex array, length m0: eigenvalues in entries 0..m-1,
+ *         sorted by (Re, Im).
+ * res     host array, length m0: eq:res of the returned pairs (may be NULL).
+ * z, w    host nodes/weights (length c->ne) or NULL to generate them from c.
+ * The contour c also defines the inside test (step 5.a) and alpha of eq:res. */
+int fh_feast(fh_handle h, fh_problem p, const fh_contour* c, const double* z, const double* w,
+             const fh_opts* o, void* Y, void* Yh, void* lambda, double* res, fh_report* rep);
+
+/* ---- components (exposed for parity tests of single steps) -------------- */
+
+/* Step 2.a: BQ (m x m, device, row-major) = Qh^H B Q. */
+int fh_reduced_matrix(fh_handle h, fh_problem p, int m, const void* Qh, const void* Q, void* BQ);
+
+/* Steps 3.a-3.c on the GPU: B_Q = V Gamma Vh^H, sort by decreasing |gamma|
+ * (stable), count m0t = #{|gamma_i| >= eta max|gamma|}, and return the
+ * bi-orthonormalizing factors S = V[:, :m0t] Gamma^{-1/2} and
+ * Sh = Vh[:, :m0t] conj(Gamma^{-1/2}) (so that U = Q S, Uh = Qh Sh; eq:uu).
+ * BQ, S, Sh: device m x m row-major; gamma: device complex length m (sorted);
+ * m0t: host int. */
+int fh_biortho_factors(fh_handle h, int m, const void* BQ, double eta, void* gamma, void* S, void* Sh,
+                       int* m0t);
+
+/* Step 4.b on the GPU: A_U W = B_U W Lambda, A_U^H Wh = B_U^H Wh Lambda^*,
+ * Wh^H B_U W = I; W has unit 2-norm columns.  All device, m x m row-major. */
+int fh_reduced_eig(fh_handle h, int m, const void* AU, const void* BU, void* lambda, void* W, void* Wh);
+
+/* Shifted operator on a batch of blocks (sparse or dense A):
+ *   Out_s = shift_s X_s - A X_s       (side 0)
+ *   Out_s = shift_s X_s - A^H X_s     (side 1)
+ * for s = 0..nsys-1, each X_s / Out_s an n x m block (device, contiguous,
+ * system-major).  shifts: host complex array of length nsys. */
+int fh_shifted_apply(fh_handle h, fh_problem p, int side, int nsys, const double* shifts, int m,
+                     const void* X, void* Out);
+
+/* ILU(0) of (z B - A) for a CSR problem (natural ordering): factor values
+ * aligned with A's CSR pattern (L strictly left of the diagonal, unit
+ * diagonal implied; U on and right of it).  lu: device complex, nnz. */
+int fh_ilu0(fh_handle h, fh_problem p, double z_re, double z_im, void* lu);
+
+/* Preconditioner apply: Out = (LU)^{-1} X (side 0) or (LU)^{-H} X (side 1)
+ * with the ILU(0) of (z B - A); X, Out: device n x m blocks. */
+int fh_ilu0_apply(fh_handle h, fh_problem p, double z_re, double z_im, int side, int m,
+                  const void* X, void* Out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEASTHIP_H */

@@ -1,0 +1,341 @@
+"""feasthip: non-Hermitian FEAST on AMD MI355X (gfx950).
+
+Thin ctypes binding of ``libfeasthip.so`` (C ABI in ``include/feasthip.h``).
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream.  Importing this module
+does not load the library; the first call does, and it raises if the library
+has not been built (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfeasthip.so")
+
+FH_DENSE, FH_CSR = 0, 1
+FH_R64, FH_C128 = 0, 1
+FH_PREC_FP64, FH_PREC_MIXED = 0, 1
+FH_SOLVER_LU, FH_SOLVER_BGMRES = 0, 1
+FH_PC_NONE, FH_PC_JACOBI, FH_PC_ILU0 = 0, 1, 2
+
+STATUS = {0: "ok", 1: "no eigenvalue inside", 2: "not converged", 3: "m0 too small",
+          4: "singular shift", 5: "inner solve failed", 6: "non-finite", 7: "reduced eig failed",
+          100: "hip error"}
+
+
+class FeastError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"feasthip error {code} ({STATUS.get(code, 'invalid argument' if code < 0 else '?')}): {msg}")
+        self.code = code
+
+
+class fh_mat(C.Structure):
+    _fields_ = [("kind", C.c_int), ("dtype", C.c_int), ("n", C.c_int), ("ld", C.c_int), ("nnz", C.c_longlong),
+                ("val", C.c_void_p), ("rowptr", C.c_void_p), ("colind", C.c_void_p)]
+
+
+class fh_contour(C.Structure):
+    _fields_ = [("c_re", C.c_double), ("c_im", C.c_double), ("a", C.c_double), ("ratio", C.c_double),
+                ("angle", C.c_double), ("ne", C.c_int)]
+
+
+class fh_opts(C.Structure):
+    _fields_ = [("m0", C.c_int), ("max_iter", C.c_int), ("eps", C.c_double), ("precision", C.c_int),
+                ("solver", C.c_int), ("restart", C.c_int), ("block", C.c_int), ("precond", C.c_int),
+                ("inner_tol", C.c_double), ("max_restarts", C.c_int), ("mixed_inner_tol", C.c_double),
+                ("max_refine", C.c_int), ("save_factors", C.c_int)]
+
+
+class fh_report(C.Structure):
+    _fields_ = [("info", C.c_int), ("m", C.c_int), ("iters", C.c_int), ("m0_final", C.c_int),
+                ("bad_node", C.c_int), ("m_s", C.c_int), ("n_factor", C.c_longlong), ("n_solve", C.c_longlong),
+                ("inner_steps", C.c_longlong), ("inner_relres", C.c_double), ("t_filter_ms", C.c_double),
+                ("t_iter_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libfeasthip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1506_04463_amd.build` "
+                          "(or __graft_entry__.build()); there is no fallback path")
+    L = C.CDLL(LIB_PATH)
+    vp, i, d, dp, ip = C.c_void_p, C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int)
+    sig = {
+        "fh_create": (i, [C.POINTER(vp), i, vp]),
+        "fh_destroy": (i, [vp]),
+        "fh_set_stream": (i, [vp, vp]),
+        "fh_last_error": (C.c_char_p, [vp]),
+        "fh_default_opts": (None, [C.POINTER(fh_opts)]),
+        "fh_contour_nodes": (i, [C.POINTER(fh_contour), dp, dp]),
+        "fh_rational": (i, [i, dp, dp, i, dp, dp]),
+        "fh_problem_create": (i, [vp, C.POINTER(fh_mat), C.POINTER(fh_mat), C.POINTER(vp)]),
+        "fh_problem_destroy": (i, [vp]),
+        "fh_filter": (i, [vp, vp, i, dp, dp, i, vp, vp, vp, vp, C.POINTER(fh_opts), C.POINTER(fh_report)]),
+        "fh_feast": (i, [vp, vp, C.POINTER(fh_contour), dp, dp, C.POINTER(fh_opts), vp, vp, vp, dp,
+                         C.POINTER(fh_report)]),
+        "fh_reduced_matrix": (i, [vp, vp, i, vp, vp, vp]),
+        "fh_biortho_factors": (i, [vp, i, vp, d, vp, vp, vp, ip]),
+        "fh_reduced_eig": (i, [vp, i, vp, vp, vp, vp, vp]),
+        "fh_shifted_apply": (i, [vp, vp, i, i, dp, i, vp, vp]),
+        "fh_ilu0": (i, [vp, vp, d, d, vp]),
+        "fh_ilu0_apply": (i, [vp, vp, d, d, i, i, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _cbuf(arr):
+    """complex128 numpy array -> (keepalive, double*)"""
+    a = np.ascontiguousarray(np.asarray(arr, dtype=np.complex128))
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _check_block(t, n, name):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()
+            and t.dim() == 2 and t.shape[0] == n):
+        raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor of shape (n={n}, m)")
+
+
+class Handle:
+    """Library handle bound to one device and (by default) torch's current stream."""
+
+    def __init__(self, device=0, stream=None):
+        torch = _torch()
+        L = lib()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        rc = L.fh_create(C.byref(h), device, C.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise FeastError(rc, "fh_create")
+        self._h = h
+
+    def check(self, rc, what):
+        if rc != 0:
+            msg = lib().fh_last_error(self._h)
+            raise FeastError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().fh_destroy(self._h)
+        except Exception:
+            pass
+
+
+@dataclass
+class CSR:
+    rowptr: object   # int32 CUDA tensor (n+1)
+    colind: object   # int32 CUDA tensor (nnz)
+    val: object      # float64 or complex128 CUDA tensor (nnz)
+    n: int
+
+
+class Problem:
+    """A (dense complex128 tensor or CSR) and optional dense B, prepared on the GPU."""
+
+    def __init__(self, handle: Handle, A, B=None):
+        torch = _torch()
+        self.handle = handle
+        m = fh_mat()
+        if isinstance(A, CSR):
+            m.kind, m.n, m.nnz = FH_CSR, A.n, A.colind.numel()
+            m.dtype = FH_R64 if A.val.dtype == torch.float64 else FH_C128
+            if A.val.dtype not in (torch.float64, torch.complex128):
+                raise ValueError("CSR values must be float64 or complex128")
+            for t in (A.rowptr, A.colind):
+                if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+                    raise ValueError("CSR index arrays must be contiguous int32 CUDA tensors")
+            m.val, m.rowptr, m.colind = A.val.data_ptr(), A.rowptr.data_ptr(), A.colind.data_ptr()
+            m.ld = 0
+            self.n = A.n
+        else:
+            _check_block(A, A.shape[0], "A")
+            m.kind, m.dtype, m.n, m.ld, m.nnz = FH_DENSE, FH_C128, A.shape[0], A.shape[1], 0
+            m.val = A.data_ptr()
+            self.n = A.shape[0]
+        bm = None
+        if B is not None:
+            _check_block(B, self.n, "B")
+            bm = fh_mat(FH_DENSE, FH_C128, self.n, B.shape[1], 0, B.data_ptr(), None, None)
+        self._keep = (A, B)
+        p = C.c_void_p()
+        rc = lib().fh_problem_create(handle._h, C.byref(m), C.byref(bm) if bm is not None else None, C.byref(p))
+        handle.check(rc, "fh_problem_create")
+        self._p = p
+
+    def __del__(self):
+        try:
+            if getattr(self, "_p", None):
+                lib().fh_problem_destroy(self._p)
+        except Exception:
+            pass
+
+
+def default_opts(m0, **kw) -> fh_opts:
+    o = fh_opts()
+    lib().fh_default_opts(C.byref(o))
+    o.m0 = m0
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def contour_nodes(center, a, ratio=1.0, angle=0.0, ne=8):
+    c = fh_contour(complex(center).real, complex(center).imag, a, ratio, angle, ne)
+    z = np.zeros(ne, np.complex128)
+    w = np.zeros(ne, np.complex128)
+    rc = lib().fh_contour_nodes(C.byref(c), z.ctypes.data_as(C.POINTER(C.c_double)),
+                                w.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != 0:
+        raise FeastError(rc, "fh_contour_nodes")
+    return z, w
+
+
+def rational(z, w, lam):
+    zk, zp = _cbuf(z)
+    wk, wp = _cbuf(w)
+    lk, lp = _cbuf(np.atleast_1d(lam))
+    out = np.zeros(len(lk), np.complex128)
+    rc = lib().fh_rational(len(zk), zp, wp, len(lk), lp, out.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != 0:
+        raise FeastError(rc, "fh_rational")
+    return out
+
+
+def contour_filter(prob: Problem, z, w, Y, Yh, opts: fh_opts | None = None):
+    """Q = sum_j w_j (z_j B - A)^{-1} B Y ;  Qh = sum_j conj(w_j) (z_j B - A)^{-H} B^H Yh."""
+    torch = _torch()
+    n = prob.n
+    _check_block(Y, n, "Y")
+    _check_block(Yh, n, "Yh")
+    m0 = Y.shape[1]
+    Q = torch.empty_like(Y)
+    Qh = torch.empty_like(Yh)
+    zk, zp = _cbuf(z)
+    wk, wp = _cbuf(w)
+    rep = fh_report()
+    rc = lib().fh_filter(prob.handle._h, prob._p, len(zk), zp, wp, m0, _dptr(Y), _dptr(Yh), _dptr(Q), _dptr(Qh),
+                         C.byref(opts) if opts is not None else None, C.byref(rep))
+    prob.handle.check(rc, "fh_filter")
+    return Q, Qh, rep.as_dict()
+
+
+def feast(prob: Problem, center, a, ratio=1.0, angle=0.0, ne=8, Y0=None, Yh0=None, opts: fh_opts | None = None,
+          z=None, w=None):
+    """Non-Hermitian FEAST; returns dict(info, lam, X, Xh, res, report)."""
+    torch = _torch()
+    n = prob.n
+    _check_block(Y0, n, "Y0")
+    _check_block(Yh0, n, "Yh0")
+    m0 = Y0.shape[1]
+    if opts is None:
+        opts = default_opts(m0)
+    Y = Y0.clone()
+    Yh = Yh0.clone()
+    lam = torch.zeros(m0, dtype=torch.complex128, device=Y.device)
+    res = np.zeros(m0)
+    c = fh_contour(complex(center).real, complex(center).imag, a, ratio, angle, ne)
+    zp = wp = None
+    if z is not None:
+        zk, zp = _cbuf(z)
+        wk, wp = _cbuf(w)
+    rep = fh_report()
+    rc = lib().fh_feast(prob.handle._h, prob._p, C.byref(c), zp, wp, C.byref(opts), _dptr(Y), _dptr(Yh),
+                        _dptr(lam), res.ctypes.data_as(C.POINTER(C.c_double)), C.byref(rep))
+    if rc < 0 or rc >= 4:
+        prob.handle.check(rc, "fh_feast")
+    m = rep.m
+    return {"info": rc, "lam": lam[:m].cpu().numpy(), "X": Y[:, :m], "Xh": Yh[:, :m], "res": res[:m],
+            "report": rep.as_dict()}
+
+
+def reduced_matrix(prob: Problem, Qh, Q):
+    torch = _torch()
+    m = Q.shape[1]
+    BQ = torch.empty((m, m), dtype=torch.complex128, device=Q.device)
+    prob.handle.check(lib().fh_reduced_matrix(prob.handle._h, prob._p, m, _dptr(Qh), _dptr(Q), _dptr(BQ)),
+                      "fh_reduced_matrix")
+    return BQ
+
+
+def biortho_factors(handle: Handle, BQ, eta=1e-16):
+    torch = _torch()
+    m = BQ.shape[0]
+    gam = torch.empty(m, dtype=torch.complex128, device=BQ.device)
+    S = torch.empty((m, m), dtype=torch.complex128, device=BQ.device)
+    Sh = torch.empty_like(S)
+    mt = C.c_int()
+    handle.check(lib().fh_biortho_factors(handle._h, m, _dptr(BQ), eta, _dptr(gam), _dptr(S), _dptr(Sh),
+                                          C.byref(mt)), "fh_biortho_factors")
+    return gam, S, Sh, mt.value
+
+
+def reduced_eig(handle: Handle, AU, BU):
+    torch = _torch()
+    m = AU.shape[0]
+    lam = torch.empty(m, dtype=torch.complex128, device=AU.device)
+    W = torch.empty((m, m), dtype=torch.complex128, device=AU.device)
+    Wh = torch.empty_like(W)
+    handle.check(lib().fh_reduced_eig(handle._h, m, _dptr(AU), _dptr(BU), _dptr(lam), _dptr(W), _dptr(Wh)),
+                 "fh_reduced_eig")
+    return lam, W, Wh
+
+
+def shifted_apply(prob: Problem, side, shifts, X):
+    """Out_s = shift_s X_s - op(A) X_s for a (nsys, n, m) complex128 tensor X (op = A or A^H)."""
+    torch = _torch()
+    nsys, n, m = X.shape
+    Out = torch.empty_like(X)
+    sk, sp = _cbuf(shifts)
+    prob.handle.check(lib().fh_shifted_apply(prob.handle._h, prob._p, side, nsys, sp, m, _dptr(X), _dptr(Out)),
+                      "fh_shifted_apply")
+    return Out
+
+
+def ilu0(prob: Problem, z):
+    torch = _torch()
+    nnz = prob._keep[0].colind.numel()
+    lu = torch.empty(nnz, dtype=torch.complex128, device="cuda")
+    prob.handle.check(lib().fh_ilu0(prob.handle._h, prob._p, complex(z).real, complex(z).imag, _dptr(lu)), "fh_ilu0")
+    return lu
+
+
+def ilu0_apply(prob: Problem, z, side, X):
+    torch = _torch()
+    Out = torch.empty_like(X)
+    prob.handle.check(lib().fh_ilu0_apply(prob.handle._h, prob._p, complex(z).real, complex(z).imag, side,
+                                          X.shape[1], _dptr(X), _dptr(Out)), "fh_ilu0_apply")
+    return Out

@@ -1,0 +1,332 @@
+// extern "C" entry points of include/feasthip.h: argument checks, error
+// capture, dispatch to the driver.
+#include <cstring>
+
+#include "fh_internal.h"
+
+using namespace fh;
+
+struct fh_ctx : Ctx {};
+struct fh_prob : Prob {};
+
+namespace fh {
+Prob::~Prob() {
+    if (sp) sparse_destroy(sp);
+    sp = nullptr;
+}
+}  // namespace fh
+
+#define FH_API_BEGIN(hh) \
+    try {
+#define FH_API_END(hh)                                        \
+    }                                                         \
+    catch (const fh::Error& e) {                              \
+        if (hh) (hh)->err = e.what();                         \
+        return e.code;                                        \
+    }                                                         \
+    catch (const std::exception& e) {                         \
+        if (hh) (hh)->err = e.what();                         \
+        return FH_HIP_ERROR;                                  \
+    }
+
+static void set_device(Ctx* c) { FH_HIP(hipSetDevice(c->device)); }
+
+extern "C" {
+
+void fh_default_opts(fh_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->m0 = 0;
+    o->max_iter = 50;
+    o->eps = 1e-12;
+    o->precision = FH_PREC_FP64;
+    o->solver = FH_SOLVER_LU;
+    o->restart = 30;
+    o->block = 0;
+    o->precond = FH_PC_ILU0;
+    o->inner_tol = 1e-12;
+    o->max_restarts = 50;
+    o->mixed_inner_tol = 1e-5;
+    o->max_refine = 8;
+    o->save_factors = 1;
+}
+
+int fh_create(fh_handle* h, int device, void* stream) {
+    if (!h) return -1;
+    *h = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return FH_HIP_ERROR;
+    if (device < 0 || device >= ndev) return -2;
+    fh_ctx* c = new fh_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    *h = c;
+    return FH_OK;
+}
+
+int fh_destroy(fh_handle h) {
+    if (!h) return -1;
+    delete h;
+    return FH_OK;
+}
+
+int fh_set_stream(fh_handle h, void* stream) {
+    if (!h) return -1;
+    h->stream = (hipStream_t)stream;
+    return FH_OK;
+}
+
+const char* fh_last_error(fh_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+int fh_contour_nodes(const fh_contour* c, double* z, double* w) {
+    if (!c) return -1;
+    if (!z) return -2;
+    if (!w) return -3;
+    if (c->ne < 1 || !(c->a > 0) || !(c->ratio > 0)) return -1;
+    std::vector<cplx> zz, ww;
+    contour_nodes(*c, zz, ww);
+    std::memcpy(z, zz.data(), sizeof(cplx) * c->ne);
+    std::memcpy(w, ww.data(), sizeof(cplx) * c->ne);
+    return FH_OK;
+}
+
+int fh_rational(int ne, const double* z, const double* w, int nlam, const double* lam, double* rho) {
+    if (ne < 1) return -1;
+    if (!z) return -2;
+    if (!w) return -3;
+    if (nlam < 0) return -4;
+    if (nlam > 0 && !lam) return -5;
+    if (nlam > 0 && !rho) return -6;
+    const cplx* zc = reinterpret_cast<const cplx*>(z);
+    const cplx* wc = reinterpret_cast<const cplx*>(w);
+    const cplx* lc = reinterpret_cast<const cplx*>(lam);
+    cplx* rc = reinterpret_cast<cplx*>(rho);
+    for (int i = 0; i < nlam; ++i) {
+        cplx s = 0.0;
+        for (int j = 0; j < ne; ++j) s += wc[j] / (zc[j] - lc[i]);
+        rc[i] = s;
+    }
+    return FH_OK;
+}
+
+int fh_problem_create(fh_handle h, const fh_mat* A, const fh_mat* B, fh_problem* out) {
+    if (!h) return -1;
+    if (!A) return -2;
+    if (!out) return -4;
+    *out = nullptr;
+    FH_API_BEGIN(h)
+    set_device(h);
+    if (A->n <= 0) return -2;
+    if (A->kind == FH_DENSE) {
+        if (A->dtype != FH_C128 || !A->val || A->ld < A->n) return -2;
+        if (B && (B->kind != FH_DENSE || B->dtype != FH_C128 || B->n != A->n || !B->val || B->ld < B->n)) return -3;
+    } else if (A->kind == FH_CSR) {
+        if ((A->dtype != FH_R64 && A->dtype != FH_C128) || !A->val || !A->rowptr || !A->colind || A->nnz < A->n)
+            return -2;
+        if (B) return -3;   // sparse problems take B = I
+    } else {
+        return -2;
+    }
+    fh_prob* p = new fh_prob();
+    p->h = h;
+    p->n = A->n;
+    p->A = *A;
+    p->dense = (A->kind == FH_DENSE);
+    p->hasB = (B != nullptr);
+    if (B) p->B = *B;
+    try {
+        if (!p->dense) sparse_prepare(*h, *p);
+    } catch (...) {
+        delete p;
+        throw;
+    }
+    *out = p;
+    return FH_OK;
+    FH_API_END(h)
+}
+
+int fh_problem_destroy(fh_problem p) {
+    if (!p) return -1;
+    delete p;
+    return FH_OK;
+}
+
+static int check_opts(const fh_opts* o, int m0, int n) {
+    if (!o) return 0;
+    if (m0 < 1 || m0 > n || m0 > 1024) return 1;
+    return 0;
+}
+
+int fh_filter(fh_handle h, fh_problem p, int ne, const double* z, const double* w, int m0, const void* Y,
+              const void* Yh, void* Q, void* Qh, const fh_opts* o, fh_report* rep) {
+    if (!h) return -1;
+    if (!p) return -2;
+    if (ne < 1) return -3;
+    if (!z) return -4;
+    if (!w) return -5;
+    if (m0 < 1 || m0 > p->n || m0 > 1024) return -6;
+    if (!Y) return -7;
+    if (!Yh) return -8;
+    if (!Q) return -9;
+    if (!Qh) return -10;
+    fh_opts def;
+    fh_default_opts(&def);
+    def.m0 = m0;
+    if (!o) { o = &def; if (!p->dense) def.solver = FH_SOLVER_BGMRES; }
+    FH_API_BEGIN(h)
+    set_device(h);
+    fh_report local{};
+    fh_report* r = rep ? rep : &local;
+    std::memset(r, 0, sizeof(*r));
+    filter(*h, *p, ne, reinterpret_cast<const cplx*>(z), reinterpret_cast<const cplx*>(w), m0, (const zd*)Y,
+           (const zd*)Yh, (zd*)Q, (zd*)Qh, *o, r);
+    r->info = FH_OK;
+    return FH_OK;
+    FH_API_END(h)
+}
+
+int fh_feast(fh_handle h, fh_problem p, const fh_contour* c, const double* z, const double* w, const fh_opts* o,
+             void* Y, void* Yh, void* lambda, double* res, fh_report* rep) {
+    if (!h) return -1;
+    if (!p) return -2;
+    if (!c || c->ne < 1 || !(c->a > 0) || !(c->ratio > 0)) return -3;
+    if ((z == nullptr) != (w == nullptr)) return -4;
+    if (!o) return -6;
+    if (o->m0 < 1 || o->m0 > p->n || o->m0 > 1024 || o->max_iter < 1 || !(o->eps > 0)) return -6;
+    if (!Y) return -7;
+    if (!Yh) return -8;
+    if (!lambda) return -9;
+    FH_API_BEGIN(h)
+    set_device(h);
+    fh_report local{};
+    fh_report* r = rep ? rep : &local;
+    std::memset(r, 0, sizeof(*r));
+    int info = feast(*h, *p, *c, reinterpret_cast<const cplx*>(z), reinterpret_cast<const cplx*>(w), *o, (zd*)Y,
+                     (zd*)Yh, (zd*)lambda, res, r);
+    r->info = info;
+    return info;
+    FH_API_END(h)
+}
+
+int fh_reduced_matrix(fh_handle h, fh_problem p, int m, const void* Qh, const void* Q, void* BQ) {
+    if (!h) return -1;
+    if (!p) return -2;
+    if (m < 1) return -3;
+    if (!Qh) return -4;
+    if (!Q) return -5;
+    if (!BQ) return -6;
+    FH_API_BEGIN(h)
+    set_device(h);
+    DBuf tmp;
+    const zd* Bq = (const zd*)Q;
+    if (p->hasB) {
+        zd* t = (zd*)tmp.ensure(sizeof(zd) * (size_t)p->n * m);
+        apply_B(*h, *p, 0, m, (const zd*)Q, t);
+        Bq = t;
+    }
+    gemm_hn_tall(h->stream, p->n, m, m, (const zd*)Qh, m, Bq, m, (zd*)BQ, m, h->partial);
+    FH_HIP(hipStreamSynchronize(h->stream));
+    return FH_OK;
+    FH_API_END(h)
+}
+
+int fh_biortho_factors(fh_handle h, int m, const void* BQ, double eta, void* gamma, void* S, void* Sh, int* m0t) {
+    if (!h) return -1;
+    if (m < 1 || m > 1024) return -2;
+    if (!BQ) return -3;
+    if (!(eta >= 0)) return -4;
+    if (!gamma) return -5;
+    if (!S) return -6;
+    if (!Sh) return -7;
+    if (!m0t) return -8;
+    FH_API_BEGIN(h)
+    set_device(h);
+    int* d = (int*)h->small_i.ensure(sizeof(int) * 4);
+    eig_biortho(h->stream, m, (const zd*)BQ, eta, (zd*)gamma, (zd*)S, (zd*)Sh, d, d + 1, h->eig_work);
+    int hv[2];
+    FH_HIP(hipMemcpyAsync(hv, d, sizeof(hv), hipMemcpyDeviceToHost, h->stream));
+    FH_HIP(hipStreamSynchronize(h->stream));
+    *m0t = hv[0];
+    if (hv[1] != 0) throw Error(FH_EIG_FAILED, "eigendecomposition of B_Q failed");
+    return FH_OK;
+    FH_API_END(h)
+}
+
+int fh_reduced_eig(fh_handle h, int m, const void* AU, const void* BU, void* lambda, void* W, void* Wh) {
+    if (!h) return -1;
+    if (m < 1 || m > 1024) return -2;
+    if (!AU) return -3;
+    if (!BU) return -4;
+    if (!lambda) return -5;
+    if (!W) return -6;
+    if (!Wh) return -7;
+    FH_API_BEGIN(h)
+    set_device(h);
+    int* d = (int*)h->small_i.ensure(sizeof(int) * 4);
+    eig_reduced(h->stream, m, (const zd*)AU, (const zd*)BU, (zd*)lambda, (zd*)W, (zd*)Wh, d, h->eig_work);
+    int hv = 0;
+    FH_HIP(hipMemcpyAsync(&hv, d, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    FH_HIP(hipStreamSynchronize(h->stream));
+    if (hv != 0) throw Error(FH_EIG_FAILED, "reduced eigenproblem failed");
+    return FH_OK;
+    FH_API_END(h)
+}
+
+int fh_shifted_apply(fh_handle h, fh_problem p, int side, int nsys, const double* shifts, int m, const void* X,
+                     void* Out) {
+    if (!h) return -1;
+    if (!p) return -2;
+    if (side != 0 && side != 1) return -3;
+    if (nsys < 1) return -4;
+    if (!shifts) return -5;
+    if (m < 1) return -6;
+    if (!X) return -7;
+    if (!Out) return -8;
+    FH_API_BEGIN(h)
+    set_device(h);
+    const cplx* s = reinterpret_cast<const cplx*>(shifts);
+    if (p->dense) {
+        const size_t blk = (size_t)p->n * m;
+        for (int k = 0; k < nsys; ++k) {
+            zd* o = (zd*)Out + k * blk;
+            const zd* x = (const zd*)X + k * blk;
+            apply_A(*h, *p, side, m, x, o);
+            const cplx sh = side ? std::conj(s[k]) : s[k];
+            shift_combine(h->stream, (long)blk, cx(sh.real(), sh.imag()), x, o);   // o = sh x - A x
+        }
+    } else {
+        sparse_shifted_apply(*h, *p, side, nsys, s, m, (const zd*)X, (zd*)Out);
+    }
+    FH_HIP(hipStreamSynchronize(h->stream));
+    return FH_OK;
+    FH_API_END(h)
+}
+
+int fh_ilu0(fh_handle h, fh_problem p, double z_re, double z_im, void* lu) {
+    if (!h) return -1;
+    if (!p || p->dense) return -2;
+    if (!lu) return -5;
+    FH_API_BEGIN(h)
+    set_device(h);
+    sparse_ilu0(*h, *p, cplx(z_re, z_im), (zd*)lu);
+    FH_HIP(hipStreamSynchronize(h->stream));
+    return FH_OK;
+    FH_API_END(h)
+}
+
+int fh_ilu0_apply(fh_handle h, fh_problem p, double z_re, double z_im, int side, int m, const void* X, void* Out) {
+    if (!h) return -1;
+    if (!p || p->dense) return -2;
+    if (side != 0 && side != 1) return -5;
+    if (m < 1) return -6;
+    if (!X) return -7;
+    if (!Out) return -8;
+    FH_API_BEGIN(h)
+    set_device(h);
+    sparse_ilu0_apply(*h, *p, cplx(z_re, z_im), side, m, (const zd*)X, (zd*)Out);
+    FH_HIP(hipStreamSynchronize(h->stream));
+    return FH_OK;
+    FH_API_END(h)
+}
+
+}  // extern "C"

@@ -1,0 +1,309 @@
+// FEAST driver: contour nodes, dense contour filter, and the non-Hermitian
+// FEAST iteration of the paper's complete algorithm figure (steps 0-5).
+// Every step runs in this library's kernels on the handle's stream; the host
+// only takes the O(m0) scalar decisions (spurious count, resize, inside test,
+// convergence) from values copied back once per step.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+
+#include "fh_internal.h"
+
+namespace fh {
+
+static const double PI = 3.14159265358979323846;
+
+// Trapezoidal rule on z(t) = c + e^{i phi}(a cos t + i b sin t), t_j = 2 pi (j - 1/2)/ne,
+// w_j = z'(t_j)/(i ne)  (Sections 1 and 2.1; eq:rational)
+void contour_nodes(const fh_contour& ct, std::vector<cplx>& z, std::vector<cplx>& w) {
+    const int ne = ct.ne;
+    z.resize(ne);
+    w.resize(ne);
+    const cplx c(ct.c_re, ct.c_im), rot = std::polar(1.0, ct.angle);
+    const double a = ct.a, b = ct.ratio * ct.a;
+    for (int j = 0; j < ne; ++j) {
+        const double t = 2.0 * PI * (j + 0.5) / ne;
+        z[j] = c + rot * cplx(a * std::cos(t), b * std::sin(t));
+        const cplx dz = rot * cplx(-a * std::sin(t), b * std::cos(t));
+        w[j] = dz / (cplx(0.0, 1.0) * double(ne));
+    }
+}
+
+static bool inside_contour(const fh_contour& ct, cplx lam) {
+    if (!std::isfinite(lam.real()) || !std::isfinite(lam.imag())) return false;
+    const cplx u = (lam - cplx(ct.c_re, ct.c_im)) * std::polar(1.0, -ct.angle);
+    const double a = ct.a, b = ct.ratio * ct.a;
+    const double q = (u.real() / a) * (u.real() / a) + (u.imag() / b) * (u.imag() / b);
+    return q < 1.0;
+}
+
+static cplx rational(int ne, const cplx* z, const cplx* w, cplx lam) {
+    cplx s = 0.0;
+    for (int j = 0; j < ne; ++j) s += w[j] / (z[j] - lam);
+    return s;
+}
+
+static void sync(Ctx& c) { FH_HIP(hipStreamSynchronize(c.stream)); }
+
+template <typename T>
+static void to_host(Ctx& c, T* dst, const void* src, size_t count) {
+    FH_HIP(hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyDeviceToHost, c.stream));
+    sync(c);
+}
+template <typename T>
+static void to_dev(Ctx& c, void* dst, const T* src, size_t count) {
+    FH_HIP(hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyHostToDevice, c.stream));
+}
+
+// ---------------------------------------------------------------------------
+// operators
+// ---------------------------------------------------------------------------
+void apply_A(Ctx& c, Prob& p, int side, int m, const zd* X, zd* Out) {
+    if (!p.dense) { sparse_apply_A(c, p, side, m, X, Out); return; }
+    const zd* A = (const zd*)p.A.val;
+    gemm<double>(c.stream, side ? 'C' : 'N', 'N', p.n, m, p.n, cx(1.0, 0.0), A, p.A.ld, 0, X, m, 0,
+                 czero<double>(), Out, m, 0, 1);
+}
+
+void apply_B(Ctx& c, Prob& p, int side, int m, const zd* X, zd* Out) {
+    if (!p.hasB) {
+        FH_HIP(hipMemcpyAsync(Out, X, sizeof(zd) * (size_t)p.n * m, hipMemcpyDeviceToDevice, c.stream));
+        return;
+    }
+    const zd* B = (const zd*)p.B.val;
+    gemm<double>(c.stream, side ? 'C' : 'N', 'N', p.n, m, p.n, cx(1.0, 0.0), B, p.B.ld, 0, X, m, 0,
+                 czero<double>(), Out, m, 0, 1);
+}
+
+// ---------------------------------------------------------------------------
+// dense contour filter (step 1): one LU per node, 'N' and 'C' solves
+// ---------------------------------------------------------------------------
+static void dense_factor(Ctx& c, Prob& p, int ne, const cplx* z, const fh_opts& o, fh_report* rep) {
+    const int n = p.n;
+    bool reuse = o.save_factors && (int)p.fact_z.size() == ne;
+    if (reuse)
+        for (int j = 0; j < ne; ++j) reuse = reuse && (p.fact_z[j] == z[j]);
+    if (reuse) return;
+    p.fact_z.clear();
+    zd* M = (zd*)p.lu.ensure(sizeof(zd) * (size_t)ne * n * n);
+    int* ipiv = (int*)p.ipiv.ensure(sizeof(int) * (size_t)ne * n);
+    int* info = (int*)p.info.ensure(sizeof(int) * ne);
+    zd* zd_ = (zd*)c.fb.zdev.ensure(sizeof(zd) * ne);
+    to_dev(c, zd_, reinterpret_cast<const zd*>(z), ne);
+    form_shift(c.stream, n, (const zd*)p.A.val, p.A.ld, p.hasB ? (const zd*)p.B.val : nullptr, p.B.ld, ne, zd_, M);
+    lu_factor(c.stream, n, M, ne, ipiv, info, c.partial);
+    std::vector<int> hinfo(ne);
+    to_host(c, hinfo.data(), info, ne);
+    if (rep) rep->n_factor += ne;
+    for (int j = 0; j < ne; ++j)
+        if (hinfo[j] != 0) {
+            if (rep) rep->bad_node = j;
+            throw Error(FH_SINGULAR_SHIFT, "zero pivot in the LU of (z_j B - A) at node " + std::to_string(j));
+        }
+    p.fact_z.assign(z, z + ne);
+}
+
+
+void filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m0, const zd* Y, const zd* Yh, zd* Q,
+            zd* Qh, const fh_opts& o, fh_report* rep) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!p.dense) {
+        sparse_filter(c, p, ne, z, w, m0, Y, Yh, Q, Qh, o, rep);
+    } else {
+        const int n = p.n;
+        const size_t blk = (size_t)n * m0;
+        dense_factor(c, p, ne, z, o, rep);
+        FilterBufs& b = c.fb;
+        zd* X = (zd*)b.X.ensure(sizeof(zd) * blk * ne);
+        zd* Xh = (zd*)b.Xh.ensure(sizeof(zd) * blk * ne);
+        zd* R = (zd*)b.R.ensure(sizeof(zd) * blk);
+        zd* Rh = (zd*)b.Rh.ensure(sizeof(zd) * blk);
+        zd* wd = (zd*)b.wdev.ensure(sizeof(zd) * ne);
+        to_dev(c, wd, reinterpret_cast<const zd*>(w), ne);
+        apply_B(c, p, 0, m0, Y, R);        // B Y
+        apply_B(c, p, 1, m0, Yh, Rh);      // B^H Yh
+        replicate<double>(c.stream, blk, R, X, ne);
+        replicate<double>(c.stream, blk, Rh, Xh, ne);
+        const zd* M = (const zd*)p.lu.p;
+        const int* ipiv = (const int*)p.ipiv.p;
+        lu_solve(c.stream, 'N', n, M, ipiv, m0, X, ne);     // (z_j B - A) Q_j = B Y
+        lu_solve(c.stream, 'C', n, M, ipiv, m0, Xh, ne);    // (z_j B - A)^H Qh_j = B^H Yh
+        accumulate(c.stream, ne, blk, X, blk, wd, false, Q);
+        accumulate(c.stream, ne, blk, Xh, blk, wd, true, Qh);
+        if (rep) rep->n_solve += 2 * ne;
+        sync(c);
+    }
+    if (rep)
+        rep->t_filter_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ---------------------------------------------------------------------------
+// FEAST (complete algorithm figure)
+// ---------------------------------------------------------------------------
+
+int feast(Ctx& c, Prob& p, const fh_contour& ct, const cplx* zin, const cplx* win, const fh_opts& o, zd* Yio,
+          zd* Yhio, zd* lambda, double* res_out, fh_report* rep) {
+    const int n = p.n, m0in = o.m0, ne = ct.ne;
+    std::vector<cplx> z, w;
+    if (zin) { z.assign(zin, zin + ne); w.assign(win, win + ne); }
+    else contour_nodes(ct, z, w);
+    const double alpha = std::abs(cplx(ct.c_re, ct.c_im)) + std::max(ct.a, ct.ratio * ct.a);
+    FeastBufs& B = c.sb;
+    const size_t big = (size_t)n * m0in;
+    zd* Ycur = (zd*)B.Ycur.ensure(sizeof(zd) * big);
+    zd* Yhcur = (zd*)B.Yhcur.ensure(sizeof(zd) * big);
+    zd* Q = (zd*)B.Q.ensure(sizeof(zd) * big);
+    zd* Qh = (zd*)B.Qh.ensure(sizeof(zd) * big);
+    zd* U = (zd*)B.U.ensure(sizeof(zd) * big);
+    zd* Uh = (zd*)B.Uh.ensure(sizeof(zd) * big);
+    zd* T1 = (zd*)B.T1.ensure(sizeof(zd) * big);
+    zd* T2 = (zd*)B.T2.ensure(sizeof(zd) * big);
+    const size_t sm = (size_t)m0in * m0in;
+    zd* BQ = (zd*)B.BQ.ensure(sizeof(zd) * sm);
+    zd* S = (zd*)B.S.ensure(sizeof(zd) * sm);
+    zd* Sh = (zd*)B.Sh.ensure(sizeof(zd) * sm);
+    zd* gam = (zd*)B.gam.ensure(sizeof(zd) * m0in);
+    zd* AUr = (zd*)B.AUr.ensure(sizeof(zd) * sm);
+    zd* BUr = (zd*)B.BUr.ensure(sizeof(zd) * sm);
+    zd* lam = (zd*)B.lam.ensure(sizeof(zd) * m0in);
+    zd* W = (zd*)B.W.ensure(sizeof(zd) * sm);
+    zd* Wh = (zd*)B.Wh.ensure(sizeof(zd) * sm);
+    double* num = (double*)B.num.ensure(sizeof(double) * m0in);
+    double* den = (double*)B.den.ensure(sizeof(double) * m0in);
+    double* num2 = (double*)B.num2.ensure(sizeof(double) * m0in);
+    double* den2 = (double*)B.den2.ensure(sizeof(double) * m0in);
+    int* ints = (int*)B.ints.ensure(sizeof(int) * 4);
+    int* perm = (int*)B.perm.ensure(sizeof(int) * m0in);
+
+    // step 0: start subspaces
+    FH_HIP(hipMemcpyAsync(Ycur, Yio, sizeof(zd) * big, hipMemcpyDeviceToDevice, c.stream));
+    FH_HIP(hipMemcpyAsync(Yhcur, Yhio, sizeof(zd) * big, hipMemcpyDeviceToDevice, c.stream));
+
+    int mcur = m0in;
+    std::vector<cplx> rho_prev, hlam(m0in), hbq(sm), rho(m0in);
+    std::vector<char> inside_prev, inside(m0in);
+    std::vector<double> res(m0in), hn(m0in), hd(m0in), hn2(m0in), hd2(m0in);
+    int info = FH_NOT_CONVERGED, m_out = 0, it = 0, m_s = 0;
+    std::vector<int> sel;
+    bool converged = false;
+    for (it = 1; it <= o.max_iter; ++it) {
+        auto t0 = std::chrono::steady_clock::now();
+        // step 1: contour integration
+        filter(c, p, ne, z.data(), w.data(), mcur, Ycur, Yhcur, Q, Qh, o, rep);
+        // step 2.a: B_Q = Qh^H B Q
+        const zd* BQin = Q;
+        if (p.hasB) { apply_B(c, p, 0, mcur, Q, T1); BQin = T1; }
+        gemm_hn_tall(c.stream, n, mcur, mcur, Qh, mcur, BQin, mcur, BQ, mcur, c.partial);
+        to_host(c, hbq.data(), BQ, (size_t)mcur * mcur);
+        // step 2.b: spurious detection from the second iteration
+        m_s = 0;
+        if (it >= 2) {
+            for (int i = 0; i < mcur; ++i) {
+                const cplx r2 = rho_prev[i] * rho_prev[i];
+                const double rel = std::abs(r2 - hbq[(size_t)i * mcur + i]) / std::abs(r2);
+                const bool flag = !(rel < 0.1);
+                if (flag && inside_prev[i]) ++m_s;
+            }
+        }
+        // steps 3.a-3.c on the GPU: eig of B_Q, sort, resize, scaled factors
+        eig_biortho(c.stream, mcur, BQ, 1e-16, gam, S, Sh, ints, ints + 1, c.eig_work);
+        int hi[2];
+        to_host(c, hi, ints, 2);
+        if (hi[1] != 0) throw Error(FH_EIG_FAILED, "eigendecomposition of B_Q failed (code " + std::to_string(hi[1]) + ")");
+        const int mt = hi[0];
+        FH_REQUIRE(mt >= 1 && mt <= mcur, FH_EIG_FAILED, "resize produced an empty subspace");
+        // step 3.d: U = Q S, Uh = Qh Sh (n x mt)
+        gemm<double>(c.stream, 'N', 'N', n, mt, mcur, cx(1.0, 0.0), Q, mcur, 0, S, mcur, 0, czero<double>(), U,
+                     mt, 0, 1);
+        gemm<double>(c.stream, 'N', 'N', n, mt, mcur, cx(1.0, 0.0), Qh, mcur, 0, Sh, mcur, 0, czero<double>(), Uh,
+                     mt, 0, 1);
+        // step 4.a: A_U = Uh^H A U, B_U = Uh^H B U
+        apply_A(c, p, 0, mt, U, T1);
+        gemm_hn_tall(c.stream, n, mt, mt, Uh, mt, T1, mt, AUr, mt, c.partial);
+        const zd* BUin = U;
+        if (p.hasB) { apply_B(c, p, 0, mt, U, T2); BUin = T2; }
+        gemm_hn_tall(c.stream, n, mt, mt, Uh, mt, BUin, mt, BUr, mt, c.partial);
+        // step 4.b: reduced eigenproblem
+        eig_reduced(c.stream, mt, AUr, BUr, lam, W, Wh, ints + 2, c.eig_work);
+        int e4 = 0;
+        to_host(c, &e4, ints + 2, 1);
+        if (e4 != 0) throw Error(FH_EIG_FAILED, "reduced eigenproblem failed (code " + std::to_string(e4) + ")");
+        to_host(c, reinterpret_cast<zd*>(hlam.data()), lam, mt);
+        // step 4.c
+        for (int i = 0; i < mt; ++i) rho[i] = rational(ne, z.data(), w.data(), hlam[i]);
+        // step 4.d: Y = U W, Yh = Uh Wh
+        gemm<double>(c.stream, 'N', 'N', n, mt, mt, cx(1.0, 0.0), U, mt, 0, W, mt, 0, czero<double>(), Ycur, mt, 0, 1);
+        gemm<double>(c.stream, 'N', 'N', n, mt, mt, cx(1.0, 0.0), Uh, mt, 0, Wh, mt, 0, czero<double>(), Yhcur, mt, 0,
+                     1);
+        // step 5.b: residuals eq:res
+        apply_A(c, p, 0, mt, Ycur, T1);
+        const zd* BY = Ycur;
+        if (p.hasB) { apply_B(c, p, 0, mt, Ycur, T2); BY = T2; }
+        res_colnorms(c.stream, n, mt, T1, BY, mt, lam, false, num, den, c.partial);
+        apply_A(c, p, 1, mt, Yhcur, T1);
+        const zd* BhYh = Yhcur;
+        if (p.hasB) { apply_B(c, p, 1, mt, Yhcur, T2); BhYh = T2; }
+        res_colnorms(c.stream, n, mt, T1, BhYh, mt, lam, true, num2, den2, c.partial2);
+        to_host(c, hn.data(), num, mt);
+        to_host(c, hd.data(), den, mt);
+        to_host(c, hn2.data(), num2, mt);
+        to_host(c, hd2.data(), den2, mt);
+        int m_r = 0;
+        for (int i = 0; i < mt; ++i) {
+            double r1 = hn[i] / (alpha * hd[i]), r2 = hn2[i] / (alpha * hd2[i]);
+            double r = std::max(r1, r2);
+            if (!std::isfinite(r)) r = INFINITY;
+            res[i] = r;
+            inside[i] = inside_contour(ct, hlam[i]);   // step 5.a
+            m_r += inside[i];
+        }
+        // step 5.c: the m = m_r - m_s smallest inside residuals below eps
+        const int m = m_r - m_s;
+        sel.clear();
+        for (int i = 0; i < mt; ++i)
+            if (inside[i]) sel.push_back(i);
+        std::stable_sort(sel.begin(), sel.end(), [&](int a, int b) { return res[a] < res[b]; });
+        if (m > 0) sel.resize(m);
+        else sel.clear();
+        converged = m > 0;
+        for (int i : sel) converged = converged && (res[i] < o.eps);
+        mcur = mt;
+        if (rep) {
+            rep->iters = it;
+            rep->m0_final = mt;
+            rep->m_s = m_s;
+            rep->m = (int)sel.size();
+            rep->t_iter_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (converged) { info = FH_OK; break; }
+        rho_prev.assign(rho.begin(), rho.begin() + mt);
+        inside_prev.assign(inside.begin(), inside.begin() + mt);
+        if (it == o.max_iter) info = (m_r == 0) ? FH_NO_EIG_INSIDE : FH_NOT_CONVERGED;
+    }
+    if (it > o.max_iter) it = o.max_iter;
+    // step 5.d: converged pairs in the first m columns, sorted by (Re, Im)
+    std::stable_sort(sel.begin(), sel.end(), [&](int a, int b) {
+        if (hlam[a].real() != hlam[b].real()) return hlam[a].real() < hlam[b].real();
+        return hlam[a].imag() < hlam[b].imag();
+    });
+    m_out = (int)sel.size();
+    if (m_out > 0) {
+        to_dev(c, perm, sel.data(), m_out);
+        gather_cols(c.stream, n, m_out, Ycur, mcur, perm, Yio, m0in);
+        gather_cols(c.stream, n, m_out, Yhcur, mcur, perm, Yhio, m0in);
+        std::vector<cplx> lo(m_out);
+        for (int k = 0; k < m_out; ++k) lo[k] = hlam[sel[k]];
+        to_dev(c, lambda, reinterpret_cast<const zd*>(lo.data()), m_out);
+        if (res_out)
+            for (int k = 0; k < m_out; ++k) res_out[k] = res[sel[k]];
+    }
+    sync(c);
+    if (rep) {
+        rep->m = m_out;
+        rep->info = info;
+    }
+    return info;
+}
+
+}  // namespace fh

@@ -1,0 +1,69 @@
+// Internal state of handles and prepared problems.
+#pragma once
+#include <complex>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/feasthip.h"
+#include "fh_kernels.h"
+
+namespace fh {
+
+struct SparseState;   // k_sparse.hip / sparse.cpp
+
+struct FilterBufs {
+    DBuf X, Xh, R, Rh, wdev, zdev;
+};
+struct FeastBufs {
+    DBuf Ycur, Yhcur, Q, Qh, U, Uh, T1, T2, BQ, S, Sh, gam, AUr, BUr, lam, W, Wh, num, den, num2, den2, ints,
+        perm;
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // scratch shared by the steps of one call
+    DBuf eig_work, partial, partial2, small_i;
+    FilterBufs fb;
+    FeastBufs sb;
+};
+
+struct Prob {
+    Ctx* h = nullptr;
+    int n = 0;
+    bool dense = true;
+    fh_mat A{};
+    fh_mat B{};
+    bool hasB = false;
+    // dense: cached LU of (z_j B - A) for the node set fact_z
+    std::vector<std::complex<double>> fact_z;
+    DBuf lu, ipiv, info;
+    // sparse state (CSR)
+    SparseState* sp = nullptr;
+    ~Prob();
+};
+
+using cplx = std::complex<double>;
+
+// driver.cpp
+void filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m0, const zd* Y, const zd* Yh, zd* Q,
+            zd* Qh, const fh_opts& o, fh_report* rep);
+int feast(Ctx& c, Prob& p, const fh_contour& ct, const cplx* z, const cplx* w, const fh_opts& o, zd* Y, zd* Yh,
+          zd* lambda, double* res, fh_report* rep);
+void apply_A(Ctx& c, Prob& p, int side, int m, const zd* X, zd* Out);
+void apply_B(Ctx& c, Prob& p, int side, int m, const zd* X, zd* Out);
+void contour_nodes(const fh_contour& ct, std::vector<cplx>& z, std::vector<cplx>& w);
+
+// sparse.cpp
+void sparse_prepare(Ctx& c, Prob& p);
+void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m0, const zd* Y, const zd* Yh,
+                   zd* Q, zd* Qh, const fh_opts& o, fh_report* rep);
+void sparse_apply_A(Ctx& c, Prob& p, int side, int m, const zd* X, zd* Out);
+void sparse_shifted_apply(Ctx& c, Prob& p, int side, int nsys, const cplx* shifts, int m, const zd* X, zd* Out);
+void sparse_ilu0(Ctx& c, Prob& p, cplx z, zd* lu_out);
+void sparse_ilu0_apply(Ctx& c, Prob& p, cplx z, int side, int m, const zd* X, zd* Out);
+void sparse_destroy(SparseState* s);
+
+}  // namespace fh

@@ -1,0 +1,61 @@
+// Host-side launchers of the feasthip HIP kernels (gfx950).
+#pragma once
+#include "fh_common.h"
+
+namespace fh {
+
+// ----------------------------- k_blas.hip ----------------------------------
+// C = alpha op(A) op(B) + beta C, row-major, batched (blockIdx.z) with strides.
+// opA/opB: 'N' or 'C' (conjugate transpose).
+template <typename T>
+void gemm(hipStream_t st, char opA, char opB, int M, int N, int K, Cx<T> alpha, const Cx<T>* A, long lda,
+          long sA, const Cx<T>* B, long ldb, long sB, Cx<T> beta, Cx<T>* C, long ldc, long sC, int batch);
+
+// C (p x q) = X^H Y for tall n x p X and n x q Y (row-major), split over n and
+// reduced in a fixed order (deterministic).
+void gemm_hn_tall(hipStream_t st, int n, int p, int q, const zd* X, long ldx, const zd* Y, long ldy, zd* C,
+                  long ldc, DBuf& partial);
+
+// Column 1-norms for eq:res: num_c = sum_i |AY_ic - lam_c BY_ic|,
+// den_c = sum_i |BY_ic| over an n x m block (ld).  lam: device, m.
+void res_colnorms(hipStream_t st, int n, int m, const zd* AY, const zd* BY, long ld, const zd* lam,
+                  bool conj_lam, double* num, double* den, DBuf& partial);
+
+// Q = sum_j c_j X_j   with c_j = w_j (or conj(w_j) when conj_w), X_j at X + j*strideX
+void accumulate(hipStream_t st, int ne, long len, const zd* X, long strideX, const zd* w_dev, bool conj_w,
+                zd* Q);
+
+// dst_j = src for j = 0..copies-1 (stride len)
+template <typename T>
+void replicate(hipStream_t st, long len, const Cx<T>* src, Cx<T>* dst, int copies);
+
+// cast between complex precisions
+template <typename D, typename S>
+void cast(hipStream_t st, long len, const Cx<S>* src, Cx<D>* dst);
+
+// Out = s X - Out (elementwise, len entries)
+void shift_combine(hipStream_t st, long len, zd s, const zd* X, zd* Out);
+
+// dst[i][k] = src[i][perm[k]] for k < mout (rows n; lds, ldd leading dims)
+void gather_cols(hipStream_t st, int n, int mout, const zd* src, long lds, const int* perm_dev, zd* dst,
+                 long ldd);
+
+// ----------------------------- k_dense.hip ---------------------------------
+// M_j = z_j B - A (B == nullptr: identity) for j = 0..ne-1, stride n*n, ld n
+void form_shift(hipStream_t st, int n, const zd* A, long lda, const zd* B, long ldb, int ne, const zd* z_dev,
+                zd* M);
+// LU with partial pivoting of `batch` n x n matrices (stride n*n, ld n), in place.
+// ipiv: batch*n (0-based), info: batch (0 or first zero pivot + 1).
+void lu_factor(hipStream_t st, int n, zd* M, int batch, int* ipiv, int* info, DBuf& scratch);
+// Solve op(M_j) X_j = X_j (op 'N' or 'C'), X_j n x m (ld m), stride n*m.
+void lu_solve(hipStream_t st, char op, int n, const zd* M, const int* ipiv, int m, zd* X, int batch);
+
+// ----------------------------- k_eig.hip -----------------------------------
+// Steps 3.a-3.c (see fh_biortho_factors); work: device scratch
+void eig_biortho(hipStream_t st, int m, const zd* BQ, double eta, zd* gamma, zd* S, zd* Sh, int* m0t,
+                 int* info, DBuf& work);
+// Step 4.b (see fh_reduced_eig)
+void eig_reduced(hipStream_t st, int m, const zd* AU, const zd* BU, zd* lam, zd* W, zd* Wh, int* info,
+                 DBuf& work);
+
+}  // namespace fh

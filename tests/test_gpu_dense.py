@@ -1,0 +1,193 @@
+"""GPU parity of the dense path (LU filter, Rayleigh-Ritz steps, full FEAST)
+against the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import workloads as W
+from oracle import contour as ct
+from oracle import feast as F
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+fh = pytest.importorskip("paper_1506_04463_amd")
+
+
+@pytest.fixture(scope="module")
+def handle():
+    return fh.Handle(0)
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _kappa_max(A, B, z):
+    n = A.shape[0]
+    Bm = np.eye(n) if B is None else B
+    return max(np.linalg.cond(zj * Bm - A) for zj in z)
+
+
+@pytest.mark.parametrize("n,m0,ne,gen", [(150, 16, 8, False), (97, 13, 5, False), (33, 7, 3, True),
+                                         (64, 64, 8, True), (1, 1, 4, False), (200, 40, 16, True)])
+def test_filter_dense_parity(handle, n, m0, ne, gen):
+    rng = np.random.default_rng(n + m0)
+    if n == 1:
+        A = np.array([[0.05 + 0.02j]])
+    else:
+        A = W.dense_prescribed(n=n, n_in=min(6, n // 2), m0=m0, ne=ne, seed=n).A
+    B = None
+    if gen:
+        B = np.eye(n) + 0.1 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2 * n)
+    z, w = ct.ellipse_nodes(0.1 + 0.1j, 0.25, 0.7, 0.3, ne)
+    Y = W.subspace(n, m0, 1)
+    Yh = W.subspace(n, m0, 2)
+    Qo, Qho = F.contour_filter(A, B, z, w, Y, Yh)
+    prob = fh.Problem(handle, _cuda(A), None if B is None else _cuda(B))
+    Q, Qh, rep = fh.contour_filter(prob, z, w, _cuda(Y), _cuda(Yh))
+    Q, Qh = Q.cpu().numpy(), Qh.cpu().numpy()
+    tol = 100 * _kappa_max(A, B, z) * np.finfo(float).eps
+    assert np.linalg.norm(Q - Qo) / np.linalg.norm(Qo) < tol
+    assert np.linalg.norm(Qh - Qho) / np.linalg.norm(Qho) < tol
+    assert rep["n_factor"] == ne and rep["n_solve"] == 2 * ne
+
+
+def test_filter_reuses_saved_factorizations(handle):
+    p = W.dense_prescribed(n=80, n_in=5, m0=8, seed=3)
+    z, w = ct.ellipse_nodes(p.contour.center, p.contour.a, 1.0, 0.0, 8)
+    prob = fh.Problem(handle, _cuda(p.A))
+    _, _, r1 = fh.contour_filter(prob, z, w, _cuda(p.Y0), _cuda(p.Yh0))
+    Q, Qh, r2 = fh.contour_filter(prob, z, w, _cuda(p.Y0), _cuda(p.Yh0))
+    assert r1["n_factor"] == 8 and r2["n_factor"] == 0
+    Qo, Qho = F.contour_filter(p.A, None, z, w, p.Y0, p.Yh0)
+    assert np.linalg.norm(Q.cpu().numpy() - Qo) / np.linalg.norm(Qo) < 1e-10
+
+
+def test_reduced_steps_match_oracle(handle):
+    p = W.dense_prescribed(n=120, n_in=6, m0=12, seed=5)
+    z, w = ct.ellipse_nodes(p.contour.center, p.contour.a, 1.0, 0.0, 8)
+    Qo, Qho = F.contour_filter(p.A, None, z, w, p.Y0, p.Yh0)
+    prob = fh.Problem(handle, _cuda(p.A))
+    BQ = fh.reduced_matrix(prob, _cuda(Qho), _cuda(Qo)).cpu().numpy()
+    BQo = Qho.conj().T @ Qo
+    np.testing.assert_allclose(BQ, BQo, rtol=0, atol=1e-13 * np.abs(BQo).max())
+    # steps 3.a-3.c
+    gam, S, Sh, mt = fh.biortho_factors(handle, _cuda(BQo))
+    rb = F.resize_biortho(Qo, Qho, BQo)
+    assert mt == rb["m0t"]
+    gam = gam.cpu().numpy()
+    np.testing.assert_allclose(np.abs(gam), np.abs(rb["gamma"]), rtol=1e-9)
+    np.testing.assert_allclose(gam, rb["gamma"], rtol=1e-8)
+    S, Sh = S.cpu().numpy()[:, :mt], Sh.cpu().numpy()[:, :mt]
+    np.testing.assert_allclose(Sh.conj().T @ BQo @ S, np.eye(mt), atol=1e-10)
+    # U columns span the same directions as the oracle's (gauge: column phase)
+    U = Qo @ S
+    for k in range(mt):
+        u, uo = U[:, k], rb["U"][:, k]
+        c = abs(np.vdot(u, uo)) / (np.linalg.norm(u) * np.linalg.norm(uo))
+        assert c > 1 - 1e-9
+    # step 4.b on the oracle's U
+    rr = F.rayleigh_ritz(p.A, None, rb["U"], rb["Uh"])
+    lam, Wm, Whm = fh.reduced_eig(handle, _cuda(rr["AU"]), _cuda(rr["BU"]))
+    lam, Wm, Whm = lam.cpu().numpy(), Wm.cpu().numpy(), Whm.cpu().numpy()
+    AU, BU = rr["AU"], rr["BU"]
+    np.testing.assert_allclose(np.sort_complex(lam), np.sort_complex(rr["lam"]), atol=1e-11)
+    np.testing.assert_allclose(AU @ Wm, BU @ Wm * lam[None, :], atol=1e-10)
+    np.testing.assert_allclose(AU.conj().T @ Whm, BU.conj().T @ Whm * np.conj(lam)[None, :], atol=1e-10)
+    np.testing.assert_allclose(Whm.conj().T @ BU @ Wm, np.eye(len(lam)), atol=1e-10)
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 36, 64, 100])
+def test_reduced_eig_random(handle, m):
+    rng = np.random.default_rng(m)
+    AU = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    BU = np.eye(m) + 0.05 * (rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)))
+    lam, Wm, Whm = [t.cpu().numpy() for t in fh.reduced_eig(handle, _cuda(AU), _cuda(BU))]
+    ref = sla.eigvals(AU, BU)
+    d = np.abs(lam[:, None] - ref[None, :]).min(axis=1)
+    assert d.max() < 1e-10 * np.abs(ref).max()
+    assert np.max(np.abs(AU @ Wm - BU @ Wm * lam[None, :])) < 1e-10 * np.abs(AU).max()
+    np.testing.assert_allclose(Whm.conj().T @ BU @ Wm, np.eye(m), atol=1e-9)
+
+
+def _gauge(X, Xh):
+    return F.gauge_normalize(X, Xh)
+
+
+def _compare_feast(p, A, B, out, ref, cont):
+    assert out["info"] == 0 and ref.info == 0
+    assert len(out["lam"]) == len(ref.lam)
+    alpha = cont.alpha()
+    assert np.max(np.abs(out["lam"] - ref.lam)) < 1e-10 * alpha
+    X, Xh = out["X"].cpu().numpy(), out["Xh"].cpu().numpy()
+    Bm = np.eye(A.shape[0]) if B is None else B
+    m = len(out["lam"])
+    assert np.max(np.abs(Xh.conj().T @ Bm @ X - np.eye(m))) < 1e-10
+    nA = np.abs(A).sum(axis=0).max()
+    lam = out["lam"]
+    rr = np.abs(A @ X - Bm @ X * lam).sum(axis=0) / (nA * np.abs(X).sum(axis=0))
+    rl = np.abs(A.conj().T @ Xh - Bm.conj().T @ Xh * np.conj(lam)).sum(axis=0) / (nA * np.abs(Xh).sum(axis=0))
+    assert rr.max() <= 1e-10 and rl.max() <= 1e-10
+    assert out["res"].max() < 1e-12 * 10
+    # vectors: gauge-normalized right vectors agree with the oracle's
+    Xg, _ = _gauge(X, Xh)
+    for k in range(m):
+        assert abs(abs(np.vdot(Xg[:, k], ref.X[:, k])) - 1) < 1e-8
+
+
+def test_feast_dense_first_config(handle):
+    """Dense n=400, 24 eigenvalues in the circle (0.1+0.1i, 0.25), Ne=8, m0=36."""
+    p = W.dense_prescribed()
+    cont = F.Contour(p.contour.center, p.contour.a, 1.0, 0.0, 8)
+    ref = F.feast(p.A, None, cont, p.Y0, p.Yh0, eps=1e-12, max_iter=60)
+    prob = fh.Problem(handle, _cuda(p.A))
+    out = fh.feast(prob, p.contour.center, p.contour.a, 1.0, 0.0, 8, _cuda(p.Y0), _cuda(p.Yh0),
+                   fh.default_opts(36, eps=1e-12, max_iter=60))
+    _compare_feast(p, p.A, None, out, ref, cont)
+    assert len(out["lam"]) == 24
+    lam_true = p.info["lam"][:24]
+    lam_true = lam_true[np.lexsort((lam_true.imag, lam_true.real))]
+    assert np.max(np.abs(out["lam"] - lam_true)) < 1e-10 * cont.alpha()
+    assert out["report"]["n_factor"] == 8
+
+
+def test_feast_dense_generalized(handle):
+    rng = np.random.default_rng(31)
+    n = 90
+    A = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2 * n)
+    B = np.eye(n) + 0.1 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2 * n)
+    ev = sla.eigvals(A, B)
+    c = 0.2 - 0.1j
+    d = np.sort(np.abs(ev - c))
+    r = 0.5 * (d[5] + d[6])
+    cont = F.Contour(c, r, 1.0, 0.0, 16)
+    Y0, Yh0 = W.subspace(n, 12, 5), W.subspace(n, 12, 6)
+    ref = F.feast(A, B, cont, Y0, Yh0, eps=1e-12, max_iter=40)
+    prob = fh.Problem(handle, _cuda(A), _cuda(B))
+    out = fh.feast(prob, c, r, 1.0, 0.0, 16, _cuda(Y0), _cuda(Yh0), fh.default_opts(12, max_iter=40))
+    _compare_feast(None, A, B, out, ref, cont)
+
+
+def test_singular_shift_reported(handle):
+    n = 40
+    lam = np.linspace(-1, 1, n) + 0.3j
+    z, w = ct.ellipse_nodes(0.0, 0.5, 1.0, 0.0, 4)
+    lam[7] = z[2]                                     # a node exactly on an eigenvalue
+    A = np.diag(lam)
+    prob = fh.Problem(handle, _cuda(A))
+    Y = _cuda(W.subspace(n, 4, 1))
+    with pytest.raises(fh.FeastError) as e:
+        fh.contour_filter(prob, z, w, Y, Y.clone())
+    assert e.value.code == 4
+
+
+def test_bad_shapes_rejected(handle):
+    p = W.dense_prescribed(n=40, n_in=4, m0=4, seed=2)
+    prob = fh.Problem(handle, _cuda(p.A))
+    z, w = ct.ellipse_nodes(0.1, 0.2, 1.0, 0.0, 4)
+    with pytest.raises(ValueError):
+        fh.contour_filter(prob, z, w, _cuda(p.Y0[:10]), _cuda(p.Yh0))
+    import ctypes as C
+    rc = fh.lib().fh_filter(handle._h, prob._p, 4, None, None, 0, None, None, None, None, None, None)
+    assert rc == -4
