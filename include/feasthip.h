@@ -85,14 +85,18 @@ typedef struct {
     double eps;           /* threshold of eq:res                              */
     int precision;        /* FH_PREC_FP64 or FH_PREC_MIXED                    */
     int solver;           /* FH_SOLVER_LU (dense) or FH_SOLVER_BGMRES (CSR)   */
-    int restart;          /* block GMRES restart length (block steps)         */
-    int block;            /* block size s of block GMRES (<= m0; 0 -> m0)     */
+    int restart;          /* GMRES restart length (Krylov steps per cycle)    */
+    int block;            /* reserved (0): every right-hand side carries its own
+                             Krylov space, all columns advance in lockstep    */
     int precond;          /* FH_PC_*                                          */
     double inner_tol;     /* relative residual target of each inner solve     */
-    int max_restarts;     /* block GMRES cycles per solve (FP64) / per refinement */
+    int max_restarts;     /* GMRES cycles per solve (FP64) / per refinement step */
     double mixed_inner_tol; /* mixed: FP32 inner-solve target per refinement step */
     int max_refine;       /* mixed: FP64 refinement steps                     */
     int save_factors;     /* keep per-node factorizations across calls         */
+    int resume;           /* fh_feast: 1 = the start columns of Y / Yh are Ritz
+                             vectors whose Ritz values are passed in lambda
+                             (resume from a previous call's subspace)         */
 } fh_opts;
 
 typedef struct {
@@ -147,14 +151,28 @@ int fh_filter(fh_handle h, fh_problem p, int ne, const double* z, const double* 
 /* ---- non-Hermitian FEAST (complete algorithm figure, steps 0-5) ----------
  * Y, Yh   in: start subspaces (n x m0, device, step 0); out: the m converged
  *         right / left eigenvectors in columns 0..m-1 (ld = m0), normalised
- *         so that Xh^H B X = I (step 5.d).
- * lambda  device complex array, length m0: eigenvalues in entries 0..m-1,
- *         sorted by (Re, Im).
- * res     host array, length m0: eq:res of the returned pairs (may be NULL).
+ *         so that Xh^H B X = I (step 5.d), followed by the other Ritz vectors
+ *         of the final search subspace in columns m..m0_final-1 (so that the
+ *         subspace can be reused as a start, see opts->resume).  When not
+ *         converged (FH_NOT_CONVERGED), m = 0 and all m0_final columns hold the
+ *         current Ritz vectors.
+ * lambda  device complex array, length m0: Ritz values of the returned
+ *         columns; the m eigenvalues first, sorted by (Re, Im).  Input when
+ *         opts->resume = 1.
+ * res     host array, length m0: eq:res of the returned columns (may be NULL).
  * z, w    host nodes/weights (length c->ne) or NULL to generate them from c.
  * The contour c also defines the inside test (step 5.a) and alpha of eq:res. */
 int fh_feast(fh_handle h, fh_problem p, const fh_contour* c, const double* z, const double* w,
              const fh_opts* o, void* Y, void* Yh, void* lambda, double* res, fh_report* rep);
+
+/* ---- kernel timing ---------------------------------------------------------
+ * fh_profile(h, 1) resets and enables per-kernel timing with HIP events on
+ * the handle's stream (a small overhead per launch); fh_profile_read returns
+ * entry idx (0-based; 1 when idx is past the end): kernel name, launches,
+ * total milliseconds, algorithmic bytes and flops summed over launches. */
+int fh_profile(fh_handle h, int enable);
+int fh_profile_read(fh_handle h, int idx, char* name, int namelen, long long* count, double* ms, double* bytes,
+                    double* flops);
 
 /* ---- components (exposed for parity tests of single steps) -------------- */
 

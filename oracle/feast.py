@@ -16,7 +16,8 @@ Readings where the paper is silent (each also listed in the design doc):
   right vectors are kept and each left vector is divided by conj(wh_i^H B_U w_i)
   so that Wh^H B_U W = I.  Infinite or NaN Ritz values count as outside.
 * Convergence: the m = m_r - m_s smallest residuals among the m_r Ritz pairs
-  inside the contour must all be below eps.
+  inside the contour must all be below eps; on exit every inside pair whose
+  residual is below eps is returned (spurious pairs never converge).
 """
 from __future__ import annotations
 
@@ -232,8 +233,9 @@ def feast(A, B, cont: Contour, Y0, Yh0, eps=1e-12, max_iter=50, keep_history=Fal
             hist.append({k: rec[k] for k in ("lam", "res", "inside", "m0t", "gamma", "spurious")}
                         | {"m_s": m_s, "m": m})
         if ok:
-            idx = np.nonzero(rec["inside"])[0]
-            idx = idx[np.argsort(rec["res"][idx], kind="stable")][:m]
+            # step 5.d: every inside pair whose residual meets eps (this includes
+            # the m smallest; flagged spurious pairs do not converge)
+            idx = np.nonzero(rec["inside"] & (rec["res"] < eps))[0]
             lam = rec["lam"][idx]
             X, Xh = gauge_normalize(rec["Y"][:, idx], rec["Yh"][:, idx], B)
             order = np.lexsort((lam.imag, lam.real))

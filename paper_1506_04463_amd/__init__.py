@@ -48,7 +48,7 @@ class fh_opts(C.Structure):
     _fields_ = [("m0", C.c_int), ("max_iter", C.c_int), ("eps", C.c_double), ("precision", C.c_int),
                 ("solver", C.c_int), ("restart", C.c_int), ("block", C.c_int), ("precond", C.c_int),
                 ("inner_tol", C.c_double), ("max_restarts", C.c_int), ("mixed_inner_tol", C.c_double),
-                ("max_refine", C.c_int), ("save_factors", C.c_int)]
+                ("max_refine", C.c_int), ("save_factors", C.c_int), ("resume", C.c_int)]
 
 
 class fh_report(C.Structure):
@@ -93,6 +93,8 @@ def lib():
         "fh_shifted_apply": (i, [vp, vp, i, i, dp, i, vp, vp]),
         "fh_ilu0": (i, [vp, vp, d, d, vp]),
         "fh_ilu0_apply": (i, [vp, vp, d, d, i, i, vp, vp]),
+        "fh_profile": (i, [vp, i]),
+        "fh_profile_read": (i, [vp, i, C.c_char_p, i, C.POINTER(C.c_longlong), dp, dp, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -144,6 +146,23 @@ class Handle:
         if rc != 0:
             msg = lib().fh_last_error(self._h)
             raise FeastError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def profile(self, enable=True):
+        self.check(lib().fh_profile(self._h, 1 if enable else 0), "fh_profile")
+
+    def profile_stats(self):
+        out = {}
+        buf = C.create_string_buffer(256)
+        cnt, ms, by, fl = C.c_longlong(), C.c_double(), C.c_double(), C.c_double()
+        idx = 0
+        while True:
+            rc = lib().fh_profile_read(self._h, idx, buf, 256, C.byref(cnt), C.byref(ms), C.byref(by), C.byref(fl))
+            if rc == 1:
+                break
+            self.check(rc, "fh_profile_read")
+            out[buf.value.decode()] = {"count": cnt.value, "ms": ms.value, "bytes": by.value, "flops": fl.value}
+            idx += 1
+        return out
 
     def __del__(self):
         try:
@@ -254,8 +273,10 @@ def contour_filter(prob: Problem, z, w, Y, Yh, opts: fh_opts | None = None):
 
 
 def feast(prob: Problem, center, a, ratio=1.0, angle=0.0, ne=8, Y0=None, Yh0=None, opts: fh_opts | None = None,
-          z=None, w=None):
-    """Non-Hermitian FEAST; returns dict(info, lam, X, Xh, res, report)."""
+          z=None, w=None, ritz0=None):
+    """Non-Hermitian FEAST; returns dict(info, lam, X, Xh, res, report, and the
+    whole final subspace Y, Yh, ritz, ritz_res).  ritz0 (with opts.resume = 1):
+    Ritz values of the start columns."""
     torch = _torch()
     n = prob.n
     _check_block(Y0, n, "Y0")
@@ -266,6 +287,8 @@ def feast(prob: Problem, center, a, ratio=1.0, angle=0.0, ne=8, Y0=None, Yh0=Non
     Y = Y0.clone()
     Yh = Yh0.clone()
     lam = torch.zeros(m0, dtype=torch.complex128, device=Y.device)
+    if ritz0 is not None:
+        lam.copy_(ritz0.reshape(-1)[:m0] if isinstance(ritz0, torch.Tensor) else torch.from_numpy(np.asarray(ritz0)))
     res = np.zeros(m0)
     c = fh_contour(complex(center).real, complex(center).imag, a, ratio, angle, ne)
     zp = wp = None
@@ -277,9 +300,9 @@ def feast(prob: Problem, center, a, ratio=1.0, angle=0.0, ne=8, Y0=None, Yh0=Non
                         _dptr(lam), res.ctypes.data_as(C.POINTER(C.c_double)), C.byref(rep))
     if rc < 0 or rc >= 4:
         prob.handle.check(rc, "fh_feast")
-    m = rep.m
+    m, mt = rep.m, rep.m0_final
     return {"info": rc, "lam": lam[:m].cpu().numpy(), "X": Y[:, :m], "Xh": Yh[:, :m], "res": res[:m],
-            "report": rep.as_dict()}
+            "report": rep.as_dict(), "Y": Y[:, :mt], "Yh": Yh[:, :mt], "ritz": lam[:mt], "ritz_res": res[:mt]}
 
 
 def reduced_matrix(prob: Problem, Qh, Q):

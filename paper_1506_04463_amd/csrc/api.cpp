@@ -1,6 +1,8 @@
 // extern "C" entry points of include/feasthip.h: argument checks, error
 // capture, dispatch to the driver.
+#include <cstdio>
 #include <cstring>
+#include <iterator>
 
 #include "fh_internal.h"
 
@@ -17,7 +19,8 @@ Prob::~Prob() {
 }  // namespace fh
 
 #define FH_API_BEGIN(hh) \
-    try {
+    try {                    \
+        ProfScope prof_scope_(*(hh));
 #define FH_API_END(hh)                                        \
     }                                                         \
     catch (const fh::Error& e) {                              \
@@ -49,6 +52,7 @@ void fh_default_opts(fh_opts* o) {
     o->mixed_inner_tol = 1e-5;
     o->max_refine = 8;
     o->save_factors = 1;
+    o->resume = 0;
 }
 
 int fh_create(fh_handle* h, int device, void* stream) {
@@ -62,6 +66,34 @@ int fh_create(fh_handle* h, int device, void* stream) {
     c->stream = (hipStream_t)stream;
     *h = c;
     return FH_OK;
+}
+
+int fh_profile(fh_handle h, int enable) {
+    if (!h) return -1;
+    FH_API_BEGIN(h)
+    h->prof.reset();
+    h->prof_on = enable != 0;
+    return FH_OK;
+    FH_API_END(h)
+}
+
+int fh_profile_read(fh_handle h, int idx, char* name, int namelen, long long* count, double* ms, double* bytes,
+                    double* flops) {
+    if (!h) return -1;
+    if (idx < 0) return -2;
+    if (!name || namelen < 1) return -3;
+    FH_API_BEGIN(h)
+    h->prof.resolve();
+    if (idx >= (int)h->prof.stats.size()) return 1;
+    auto it = h->prof.stats.begin();
+    std::advance(it, idx);
+    std::snprintf(name, namelen, "%s", it->first.c_str());
+    if (count) *count = it->second.count;
+    if (ms) *ms = it->second.ms;
+    if (bytes) *bytes = it->second.bytes;
+    if (flops) *flops = it->second.flops;
+    return FH_OK;
+    FH_API_END(h)
 }
 
 int fh_destroy(fh_handle h) {
@@ -291,7 +323,7 @@ int fh_shifted_apply(fh_handle h, fh_problem p, int side, int nsys, const double
             zd* o = (zd*)Out + k * blk;
             const zd* x = (const zd*)X + k * blk;
             apply_A(*h, *p, side, m, x, o);
-            const cplx sh = side ? std::conj(s[k]) : s[k];
+            const cplx sh = s[k];
             shift_combine(h->stream, (long)blk, cx(sh.real(), sh.imag()), x, o);   // o = sh x - A x
         }
     } else {

@@ -7,6 +7,8 @@
 #include <chrono>
 #include <cstring>
 #include <numeric>
+#include <cstdio>
+#include <cstdlib>
 
 #include "fh_internal.h"
 
@@ -46,14 +48,25 @@ static cplx rational(int ne, const cplx* z, const cplx* w, cplx lam) {
 
 static void sync(Ctx& c) { FH_HIP(hipStreamSynchronize(c.stream)); }
 
+// FH_VERBOSE=1 prints one line per FEAST iteration to stderr
+static int verbose() {
+    static const int v = [] {
+        const char* e = std::getenv("FH_VERBOSE");
+        return e ? std::atoi(e) : 0;
+    }();
+    return v;
+}
+
 template <typename T>
 static void to_host(Ctx& c, T* dst, const void* src, size_t count) {
     FH_HIP(hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyDeviceToHost, c.stream));
     sync(c);
 }
+// small uploads; synchronous so that the host source may go out of scope
 template <typename T>
 static void to_dev(Ctx& c, void* dst, const T* src, size_t count) {
     FH_HIP(hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyHostToDevice, c.stream));
+    sync(c);
 }
 
 // ---------------------------------------------------------------------------
@@ -106,10 +119,10 @@ static void dense_factor(Ctx& c, Prob& p, int ne, const cplx* z, const fh_opts& 
 
 
 void filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m0, const zd* Y, const zd* Yh, zd* Q,
-            zd* Qh, const fh_opts& o, fh_report* rep) {
+            zd* Qh, const fh_opts& o, fh_report* rep, const cplx* lam) {
     auto t0 = std::chrono::steady_clock::now();
     if (!p.dense) {
-        sparse_filter(c, p, ne, z, w, m0, Y, Yh, Q, Qh, o, rep);
+        sparse_filter(c, p, ne, z, w, m0, Y, Yh, Q, Qh, o, rep, lam);
     } else {
         const int n = p.n;
         const size_t blk = (size_t)n * m0;
@@ -182,6 +195,10 @@ int feast(Ctx& c, Prob& p, const fh_contour& ct, const cplx* zin, const cplx* wi
 
     int mcur = m0in;
     std::vector<cplx> rho_prev, hlam(m0in), hbq(sm), rho(m0in);
+    if (o.resume) {
+        // the start columns are Ritz vectors whose values are passed in lambda
+        to_host(c, reinterpret_cast<zd*>(hlam.data()), lambda, m0in);
+    }
     std::vector<char> inside_prev, inside(m0in);
     std::vector<double> res(m0in), hn(m0in), hd(m0in), hn2(m0in), hd2(m0in);
     int info = FH_NOT_CONVERGED, m_out = 0, it = 0, m_s = 0;
@@ -190,7 +207,10 @@ int feast(Ctx& c, Prob& p, const fh_contour& ct, const cplx* zin, const cplx* wi
     for (it = 1; it <= o.max_iter; ++it) {
         auto t0 = std::chrono::steady_clock::now();
         // step 1: contour integration
-        filter(c, p, ne, z.data(), w.data(), mcur, Ycur, Yhcur, Q, Qh, o, rep);
+        // Ritz values of the current columns enable the residual form of the
+        // iterative filter from the second iteration on
+        filter(c, p, ne, z.data(), w.data(), mcur, Ycur, Yhcur, Q, Qh, o, rep,
+               ((it >= 2 || o.resume) && !p.dense) ? hlam.data() : nullptr);
         // step 2.a: B_Q = Qh^H B Q
         const zd* BQin = Q;
         if (p.hasB) { apply_B(c, p, 0, mcur, Q, T1); BQin = T1; }
@@ -269,6 +289,17 @@ int feast(Ctx& c, Prob& p, const fh_contour& ct, const cplx* zin, const cplx* wi
         converged = m > 0;
         for (int i : sel) converged = converged && (res[i] < o.eps);
         mcur = mt;
+        if (verbose()) {
+            double worst = 0.0;
+            for (int i : sel) worst = std::max(worst, res[i]);
+            std::fprintf(stderr,
+                         "[feasthip] it %d m0 %d m_r %d m_s %d worst-res %.3e filter %.1f ms iter %.1f ms inner-steps %lld "
+                         "inner-relres %.2e\n",
+                         it, mt, m_r, m_s, worst, rep ? rep->t_filter_ms : 0.0,
+                         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(),
+                         rep ? rep->inner_steps : 0LL, rep ? rep->inner_relres : 0.0);
+            std::fflush(stderr);
+        }
         if (rep) {
             rep->iters = it;
             rep->m0_final = mt;
@@ -282,21 +313,32 @@ int feast(Ctx& c, Prob& p, const fh_contour& ct, const cplx* zin, const cplx* wi
         if (it == o.max_iter) info = (m_r == 0) ? FH_NO_EIG_INSIDE : FH_NOT_CONVERGED;
     }
     if (it > o.max_iter) it = o.max_iter;
-    // step 5.d: converged pairs in the first m columns, sorted by (Re, Im)
+    // step 5.d: the converged pairs in the first m columns, sorted by (Re, Im).
+    // Every inside pair whose residual meets eps is returned (flagged spurious
+    // pairs never converge, so this is the spurious-free set).  The remaining
+    // Ritz vectors follow in columns m..m0_final-1 so that the whole search
+    // subspace can be reused as a start (resume).
+    if (converged) {
+        for (int i = 0; i < mcur; ++i)
+            if (inside[i] && res[i] < o.eps && std::find(sel.begin(), sel.end(), i) == sel.end()) sel.push_back(i);
+    }
     std::stable_sort(sel.begin(), sel.end(), [&](int a, int b) {
         if (hlam[a].real() != hlam[b].real()) return hlam[a].real() < hlam[b].real();
         return hlam[a].imag() < hlam[b].imag();
     });
-    m_out = (int)sel.size();
-    if (m_out > 0) {
-        to_dev(c, perm, sel.data(), m_out);
-        gather_cols(c.stream, n, m_out, Ycur, mcur, perm, Yio, m0in);
-        gather_cols(c.stream, n, m_out, Yhcur, mcur, perm, Yhio, m0in);
-        std::vector<cplx> lo(m_out);
-        for (int k = 0; k < m_out; ++k) lo[k] = hlam[sel[k]];
-        to_dev(c, lambda, reinterpret_cast<const zd*>(lo.data()), m_out);
+    m_out = converged ? (int)sel.size() : 0;
+    std::vector<int> order(sel.begin(), sel.end());
+    for (int i = 0; i < mcur; ++i)
+        if (std::find(order.begin(), order.end(), i) == order.end()) order.push_back(i);
+    to_dev(c, perm, order.data(), mcur);
+    gather_cols(c.stream, n, mcur, Ycur, mcur, perm, Yio, m0in);
+    gather_cols(c.stream, n, mcur, Yhcur, mcur, perm, Yhio, m0in);
+    {
+        std::vector<cplx> lo(mcur);
+        for (int k = 0; k < mcur; ++k) lo[k] = hlam[order[k]];
+        to_dev(c, lambda, reinterpret_cast<const zd*>(lo.data()), mcur);
         if (res_out)
-            for (int k = 0; k < m_out; ++k) res_out[k] = res[sel[k]];
+            for (int k = 0; k < mcur; ++k) res_out[k] = res[order[k]];
     }
     sync(c);
     if (rep) {

@@ -7,6 +7,7 @@
 
 #include "../../include/feasthip.h"
 #include "fh_kernels.h"
+#include "fh_prof.h"
 
 namespace fh {
 
@@ -28,6 +29,14 @@ struct Ctx {
     DBuf eig_work, partial, partial2, small_i;
     FilterBufs fb;
     FeastBufs sb;
+    bool prof_on = false;
+    Prof prof;
+};
+
+// makes the handle's profiler current on this thread for the duration of a call
+struct ProfScope {
+    ProfScope(Ctx& c) { tl_prof() = c.prof_on ? &c.prof : nullptr; }
+    ~ProfScope() { tl_prof() = nullptr; }
 };
 
 struct Prob {
@@ -49,7 +58,7 @@ using cplx = std::complex<double>;
 
 // driver.cpp
 void filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m0, const zd* Y, const zd* Yh, zd* Q,
-            zd* Qh, const fh_opts& o, fh_report* rep);
+            zd* Qh, const fh_opts& o, fh_report* rep, const cplx* lam = nullptr);
 int feast(Ctx& c, Prob& p, const fh_contour& ct, const cplx* z, const cplx* w, const fh_opts& o, zd* Y, zd* Yh,
           zd* lambda, double* res, fh_report* rep);
 void apply_A(Ctx& c, Prob& p, int side, int m, const zd* X, zd* Out);
@@ -59,7 +68,7 @@ void contour_nodes(const fh_contour& ct, std::vector<cplx>& z, std::vector<cplx>
 // sparse.cpp
 void sparse_prepare(Ctx& c, Prob& p);
 void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m0, const zd* Y, const zd* Yh,
-                   zd* Q, zd* Qh, const fh_opts& o, fh_report* rep);
+                   zd* Q, zd* Qh, const fh_opts& o, fh_report* rep, const cplx* lam);
 void sparse_apply_A(Ctx& c, Prob& p, int side, int m, const zd* X, zd* Out);
 void sparse_shifted_apply(Ctx& c, Prob& p, int side, int nsys, const cplx* shifts, int m, const zd* X, zd* Out);
 void sparse_ilu0(Ctx& c, Prob& p, cplx z, zd* lu_out);

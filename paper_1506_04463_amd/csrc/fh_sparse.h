@@ -1,0 +1,106 @@
+// Sparse (CSR) state of a prepared problem and launchers of k_sparse.hip.
+#pragma once
+#include <vector>
+
+#include "fh_internal.h"
+
+namespace fh {
+
+// CSR operand on the device; values in FP64 (val64) and an FP32 copy (val32)
+struct CsrDev {
+    const int* rowptr = nullptr;
+    const int* col = nullptr;
+    const void* val64 = nullptr;
+    const void* val32 = nullptr;
+    bool complex_vals = false;
+    long nnz = 0;
+    template <typename T> const void* val() const { return sizeof(T) == sizeof(double) ? val64 : val32; }
+};
+
+struct LevelsDev {
+    const int* ptr = nullptr;    // nlev + 1
+    const int* rows = nullptr;   // n
+    int nlev = 0;
+};
+
+template <typename T>
+struct IluApplyArgs {
+    int n = 0, m = 0, cw = 8;
+    long nnzM = 0;
+    const int* node_of = nullptr;  // per system
+    const int* side_of = nullptr;  // per system
+    const int *rowptr = nullptr, *col = nullptr, *diag = nullptr;      // M pattern
+    const int *rowptrT = nullptr, *colT = nullptr, *diagT = nullptr;   // M^T pattern
+    LevelsDev levL, levU, levUT, levLT;
+    const Cx<T>* lu = nullptr;    // [node][nnzM]
+    const Cx<T>* luT = nullptr;   // [node][nnzM] (values on the M^T pattern)
+    const Cx<T>* dinv = nullptr;  // [node][n]
+};
+
+struct SparseState {
+    int n = 0;
+    long nnzA = 0, nnzM = 0;
+    CsrDev A, AT;
+    // M = A + diagonal pattern and its transpose
+    int *mrowptr = nullptr, *mcol = nullptr, *mdiag = nullptr, *a2m = nullptr;
+    int *trowptr = nullptr, *tcol = nullptr, *tdiag = nullptr, *t2m = nullptr;
+    int* uptr = nullptr;
+    int2* upd = nullptr;
+    long nupd = 0;
+    LevelsDev levL, levU, levUT, levLT;
+    std::vector<DBuf*> owned;     // every device array above
+    // factor cache
+    std::vector<cplx> fact_z;
+    int fact_prec = -1;
+    DBuf lu64, luT64, dinv64, jd64, lu32, luT32, dinv32, jd32, mvals, zdev;
+    // batch descriptors and GMRES workspace
+    DBuf node_of, side_of, shifts64, shifts32, coef, rho, bufB, bufX, bufR, bufT, b32, x32;
+    DBuf V, Z, Hs, cs, sn, g, resid, vscale, kuse, y, h1, h2, hnorm, beta, bnorm, part, bn64, rn64, sc64;
+    DBuf aval32, atval64, atval32, bn32;
+    ~SparseState() {
+        for (DBuf* b : owned) delete b;
+    }
+};
+
+// k_sparse.hip launchers
+template <typename T>
+void spmm(hipStream_t st, const CsrDev& A, bool conj_t, int n, int m, int nsys, const Cx<T>* shifts, T alpha,
+          const Cx<T>* X, const Cx<T>* Yadd, Cx<T>* Out);
+void form_mvals(hipStream_t st, const SparseState& S, int ne, const zd* z_dev, zd* out);
+void ilu0_factor(hipStream_t st, const SparseState& S, int ne, zd* lu, zd* luT, zd* dinv);
+void to_single(hipStream_t st, long len, const zd* s, cf* d);
+template <typename T>
+void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<T>* Out, const T* scale);
+template <typename T>
+void jacobi_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<T>* Out, const T* scale);
+template <typename T>
+void cgs2(hipStream_t st, int n, int m, int nsys, int kp1, const Cx<T>* V, long vstride, Cx<T>* W, zd* h1, zd* h2,
+          double* hnorm, DBuf& part);
+template <typename T>
+void colnorms(hipStream_t st, int n, int m, int nsys, const Cx<T>* X, double* out, DBuf& part);
+void givens_step(hipStream_t st, int C, int k, int KP, const zd* h1, const zd* h2, const double* hnorm, zd* Hs,
+                 double* cs, zd* sn, zd* g, double* resid, double* vscale, int* kuse, const double* bnorm, double tol);
+void gmres_start(hipStream_t st, int C, int KP, int restart, const double* beta, const double* bnorm, double tol, zd* g,
+                 double* vscale, int* kuse);
+template <typename T>
+void gmres_update_prep(hipStream_t st, int n, int m, int nsys, int k, int KP, const zd* Hs, const zd* g,
+                       const int* kuse, zd* y, const Cx<T>* V, long vstride, Cx<T>* U);
+template <typename T>
+void add_to(hipStream_t st, long len, const Cx<T>* Z, zd* X);
+template <typename T>
+void scale_cols_cast(hipStream_t st, int n, int m, int nsys, const zd* X, const double* sc, Cx<T>* Out);
+template <typename T>
+void axpy_cols(hipStream_t st, int n, int m, int nsys, const Cx<T>* Z, const double* sc, zd* X);
+void filter_accum(hipStream_t st, int ne, int n, int m, const zd* E, const zd* coef, const zd* Y, const zd* rho, zd* Q);
+void ritz_residual(hipStream_t st, const CsrDev& A, bool conj_t, int n, int m, const zd* lam, bool conj_lam,
+                   const zd* X, zd* Out);
+void jacobi_diag(hipStream_t st, const SparseState& S, int ne, const zd* mvals, zd* jd);
+void invert_vals(hipStream_t st, long len, zd* v);
+template <typename T>
+void scale_inplace(hipStream_t st, int n, int m, int nsys, Cx<T>* X, const double* sc);
+template <typename T>
+void add_same(hipStream_t st, long len, const Cx<T>* Z, Cx<T>* X);
+void gather_vals(hipStream_t st, long len, bool complex_vals, const void* src, const int* idx, void* dst);
+void cast_vals(hipStream_t st, long len, bool complex_vals, const void* src, void* dst);
+
+}  // namespace fh

@@ -1,0 +1,564 @@
+// Sparse (CSR) path: symbolic analysis on the host (once per problem), the
+// per-node ILU(0) factorizations kept across FEAST iterations, the
+// column-batched GMRES(restart) solver with ILU(0) right preconditioning in
+// FP64 or in complex FP32 wrapped in FP64 iterative refinement, and the
+// contour filter built on it.
+//
+// The filter can run in its plain form (right-hand sides B Y and B^H Yh, the
+// paper's eq:qr / eq:ql) or, when the columns of Y are Ritz vectors with Ritz
+// values lam, in the algebraically identical residual form
+//   (z B - A)^{-1} B y = y/(z - lam) + (z B - A)^{-1} r/(z - lam),  r = A y - lam B y,
+// so that each inner solve only has to resolve the Ritz residual.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+
+#include "fh_sparse.h"
+
+namespace fh {
+
+static int* dev_ints(SparseState& S, const std::vector<int>& h, hipStream_t st) {
+    DBuf* b = new DBuf();
+    S.owned.push_back(b);
+    int* p = (int*)b->ensure(sizeof(int) * std::max<size_t>(1, h.size()));
+    if (!h.empty()) {
+        FH_HIP(hipMemcpyAsync(p, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, st));
+        FH_HIP(hipStreamSynchronize(st));   // h may be reused or freed by the caller
+    }
+    return p;
+}
+
+static LevelsDev levels_dev(SparseState& S, const std::vector<int>& lev, int n, hipStream_t st) {
+    int nlev = 0;
+    for (int i = 0; i < n; ++i) nlev = std::max(nlev, lev[i] + 1);
+    std::vector<int> ptr(nlev + 1, 0), rows(n);
+    for (int i = 0; i < n; ++i) ptr[lev[i] + 1]++;
+    for (int l = 0; l < nlev; ++l) ptr[l + 1] += ptr[l];
+    std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+    for (int i = 0; i < n; ++i) rows[fill[lev[i]]++] = i;
+    LevelsDev L;
+    L.ptr = dev_ints(S, ptr, st);
+    L.rows = dev_ints(S, rows, st);
+    L.nlev = nlev;
+    return L;
+}
+
+// transpose of a pattern: returns rowptr/col of P^T and, for each entry of P^T,
+// the position of the same entry in P
+static void transpose_pattern(int n, const std::vector<int>& rp, const std::vector<int>& ci, std::vector<int>& trp,
+                              std::vector<int>& tci, std::vector<int>& tpos) {
+    const long nnz = rp[n];
+    trp.assign(n + 1, 0);
+    for (long p = 0; p < nnz; ++p) trp[ci[p] + 1]++;
+    for (int i = 0; i < n; ++i) trp[i + 1] += trp[i];
+    tci.resize(nnz);
+    tpos.resize(nnz);
+    std::vector<int> fill(trp.begin(), trp.end() - 1);
+    for (int i = 0; i < n; ++i)
+        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+            const int q = fill[ci[p]]++;
+            tci[q] = i;
+            tpos[q] = p;
+        }
+}
+
+void sparse_prepare(Ctx& c, Prob& p) {
+    hipStream_t st = c.stream;
+    SparseState* S = new SparseState();
+    p.sp = S;
+    const int n = p.n;
+    const long nnz = p.A.nnz;
+    S->n = n;
+    S->nnzA = nnz;
+    std::vector<int> rp(n + 1), ci(nnz);
+    FH_HIP(hipMemcpyAsync(rp.data(), p.A.rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, st));
+    FH_HIP(hipMemcpyAsync(ci.data(), p.A.colind, sizeof(int) * nnz, hipMemcpyDeviceToHost, st));
+    FH_HIP(hipStreamSynchronize(st));
+    FH_REQUIRE(rp[0] == 0 && rp[n] == nnz, -2, "CSR row pointers must start at 0 and end at nnz");
+    for (int i = 0; i < n; ++i) {
+        FH_REQUIRE(rp[i + 1] >= rp[i], -2, "CSR row pointers must be non-decreasing");
+        for (int q = rp[i]; q < rp[i + 1]; ++q) {
+            FH_REQUIRE(ci[q] >= 0 && ci[q] < n, -2, "CSR column index out of range");
+            if (q > rp[i]) FH_REQUIRE(ci[q] > ci[q - 1], -2, "CSR column indices must be sorted and unique per row");
+        }
+    }
+    // M pattern = A pattern + full diagonal
+    std::vector<int> mrp(n + 1, 0), mci, a2m(nnz), mdiag(n);
+    mci.reserve(nnz + n);
+    for (int i = 0; i < n; ++i) {
+        bool placed = false;
+        for (int q = rp[i]; q < rp[i + 1]; ++q) {
+            if (!placed && ci[q] > i) { mdiag[i] = (int)mci.size(); mci.push_back(i); placed = true; }
+            if (ci[q] == i) { mdiag[i] = (int)mci.size(); placed = true; }
+            a2m[q] = (int)mci.size();
+            mci.push_back(ci[q]);
+        }
+        if (!placed) { mdiag[i] = (int)mci.size(); mci.push_back(i); }
+        mrp[i + 1] = (int)mci.size();
+    }
+    const long nnzM = (long)mci.size();
+    S->nnzM = nnzM;
+    std::vector<int> trp, tci, t2m, tdiag(n);
+    transpose_pattern(n, mrp, mci, trp, tci, t2m);
+    for (int i = 0; i < n; ++i)
+        for (int q = trp[i]; q < trp[i + 1]; ++q)
+            if (tci[q] == i) tdiag[i] = q;
+    // ILU(0) update lists: for each L entry (i,k): pairs (pos(i,j), pos(k,j)) for j > k in both rows
+    std::vector<int> uptr(nnzM + 1, 0);
+    std::vector<int2> upd;
+    std::vector<int> wpos(n, -1);
+    for (int i = 0; i < n; ++i) {
+        for (int q = mrp[i]; q < mrp[i + 1]; ++q) wpos[mci[q]] = q;
+        for (int q = mrp[i]; q < mrp[i + 1]; ++q) {
+            uptr[q] = (int)upd.size();
+            const int k = mci[q];
+            if (k >= i) continue;
+            for (int r = mdiag[k] + 1; r < mrp[k + 1]; ++r) {
+                const int j = mci[r];
+                if (wpos[j] >= 0) upd.push_back(make_int2(wpos[j], r));
+            }
+        }
+        for (int q = mrp[i]; q < mrp[i + 1]; ++q) wpos[mci[q]] = -1;
+    }
+    uptr[nnzM] = (int)upd.size();
+    S->nupd = (long)upd.size();
+    // level sets of the four triangular sweeps
+    std::vector<int> lev(n);
+    for (int i = 0; i < n; ++i) {            // L (forward)
+        int l = 0;
+        for (int q = mrp[i]; q < mdiag[i]; ++q) l = std::max(l, lev[mci[q]] + 1);
+        lev[i] = l;
+    }
+    S->levL = levels_dev(*S, lev, n, st);
+    for (int i = n - 1; i >= 0; --i) {       // U (backward)
+        int l = 0;
+        for (int q = mdiag[i] + 1; q < mrp[i + 1]; ++q) l = std::max(l, lev[mci[q]] + 1);
+        lev[i] = l;
+    }
+    S->levU = levels_dev(*S, lev, n, st);
+    for (int i = 0; i < n; ++i) {            // U^H: lower part of M^T (forward)
+        int l = 0;
+        for (int q = trp[i]; q < tdiag[i]; ++q) l = std::max(l, lev[tci[q]] + 1);
+        lev[i] = l;
+    }
+    S->levUT = levels_dev(*S, lev, n, st);
+    for (int i = n - 1; i >= 0; --i) {       // L^H: upper part of M^T (backward)
+        int l = 0;
+        for (int q = tdiag[i] + 1; q < trp[i + 1]; ++q) l = std::max(l, lev[tci[q]] + 1);
+        lev[i] = l;
+    }
+    S->levLT = levels_dev(*S, lev, n, st);
+    S->mrowptr = dev_ints(*S, mrp, st);
+    S->mcol = dev_ints(*S, mci, st);
+    S->mdiag = dev_ints(*S, mdiag, st);
+    S->a2m = dev_ints(*S, a2m, st);
+    S->trowptr = dev_ints(*S, trp, st);
+    S->tcol = dev_ints(*S, tci, st);
+    S->tdiag = dev_ints(*S, tdiag, st);
+    S->t2m = dev_ints(*S, t2m, st);
+    S->uptr = dev_ints(*S, uptr, st);
+    {
+        DBuf* b = new DBuf();
+        S->owned.push_back(b);
+        S->upd = (int2*)b->ensure(sizeof(int2) * std::max<size_t>(1, upd.size()));
+        if (!upd.empty()) {
+            FH_HIP(hipMemcpyAsync(S->upd, upd.data(), sizeof(int2) * upd.size(), hipMemcpyHostToDevice, st));
+            FH_HIP(hipStreamSynchronize(st));
+        }
+    }
+    // A (user arrays) with an FP32 copy; A^T pattern with FP64/FP32 values
+    const bool cplx_vals = (p.A.dtype == FH_C128);
+    const size_t vb = cplx_vals ? sizeof(zd) : sizeof(double);
+    S->A.rowptr = p.A.rowptr;
+    S->A.col = p.A.colind;
+    S->A.val64 = p.A.val;
+    S->A.complex_vals = cplx_vals;
+    S->A.nnz = nnz;
+    S->AT.nnz = nnz;
+    S->A.val32 = S->aval32.ensure(vb / 2 * std::max<long>(1, nnz));
+    cast_vals(st, nnz, cplx_vals, p.A.val, (void*)S->A.val32);
+    std::vector<int> atrp, atci, at2a;
+    transpose_pattern(n, rp, ci, atrp, atci, at2a);
+    S->AT.rowptr = dev_ints(*S, atrp, st);
+    S->AT.col = dev_ints(*S, atci, st);
+    int* at2a_d = dev_ints(*S, at2a, st);
+    S->AT.complex_vals = cplx_vals;
+    S->AT.val64 = S->atval64.ensure(vb * std::max<long>(1, nnz));
+    gather_vals(st, nnz, cplx_vals, p.A.val, at2a_d, (void*)S->AT.val64);
+    S->AT.val32 = S->atval32.ensure(vb / 2 * std::max<long>(1, nnz));
+    cast_vals(st, nnz, cplx_vals, S->AT.val64, (void*)S->AT.val32);
+    FH_HIP(hipStreamSynchronize(st));
+}
+
+void sparse_destroy(SparseState* s) { delete s; }
+
+// ---------------------------------------------------------------------------
+// per-node factorizations (kept across calls for the same node set)
+// ---------------------------------------------------------------------------
+static void ensure_factors(Ctx& c, SparseState& S, int ne, const cplx* z, bool need32, const fh_opts& o,
+                           fh_report* rep) {
+    hipStream_t st = c.stream;
+    bool reuse = o.save_factors && (int)S.fact_z.size() == ne;
+    if (reuse)
+        for (int j = 0; j < ne; ++j) reuse = reuse && S.fact_z[j] == z[j];
+    const int n = S.n;
+    const long nnzM = S.nnzM;
+    if (!reuse) {
+        S.fact_z.clear();
+        S.fact_prec = -1;
+        zd* zd_ = (zd*)S.zdev.ensure(sizeof(zd) * ne);
+        FH_HIP(hipMemcpyAsync(zd_, z, sizeof(zd) * ne, hipMemcpyHostToDevice, st));
+        zd* lu = (zd*)S.lu64.ensure(sizeof(zd) * nnzM * ne);
+        zd* luT = (zd*)S.luT64.ensure(sizeof(zd) * nnzM * ne);
+        zd* dinv = (zd*)S.dinv64.ensure(sizeof(zd) * (size_t)n * ne);
+        zd* jd = (zd*)S.jd64.ensure(sizeof(zd) * (size_t)n * ne);
+        form_mvals(st, S, ne, zd_, lu);
+        jacobi_diag(st, S, ne, lu, jd);      // 1/(z_j - a_ii) from the unfactored values
+        ilu0_factor(st, S, ne, lu, luT, dinv);
+        // zero or non-finite pivots
+        std::vector<zd> hdv((size_t)n * ne);
+        FH_HIP(hipMemcpyAsync(hdv.data(), dinv, sizeof(zd) * hdv.size(), hipMemcpyDeviceToHost, st));
+        FH_HIP(hipStreamSynchronize(st));
+        for (int j = 0; j < ne; ++j)
+            for (int i = 0; i < n; ++i) {
+                const zd v = hdv[(size_t)j * n + i];
+                if (!std::isfinite(v.re) || !std::isfinite(v.im)) {
+                    if (rep) rep->bad_node = j;
+                    throw Error(FH_SINGULAR_SHIFT, "zero pivot in ILU(0) of (z_j - A) at node " + std::to_string(j));
+                }
+            }
+        if (rep) rep->n_factor += ne;
+        S.fact_z.assign(z, z + ne);
+        S.fact_prec = 0;
+    }
+    if (need32 && S.fact_prec < 1) {
+        to_single(st, nnzM * ne, (const zd*)S.lu64.p, (cf*)S.lu32.ensure(sizeof(cf) * nnzM * ne));
+        to_single(st, nnzM * ne, (const zd*)S.luT64.p, (cf*)S.luT32.ensure(sizeof(cf) * nnzM * ne));
+        to_single(st, (long)n * ne, (const zd*)S.dinv64.p, (cf*)S.dinv32.ensure(sizeof(cf) * (size_t)n * ne));
+        to_single(st, (long)n * ne, (const zd*)S.jd64.p, (cf*)S.jd32.ensure(sizeof(cf) * (size_t)n * ne));
+        S.fact_prec = 1;
+    }
+}
+
+template <typename T>
+static IluApplyArgs<T> ilu_args(SparseState& S, int m, int precond) {
+    IluApplyArgs<T> a;
+    a.n = S.n;
+    a.m = m;
+    a.cw = sizeof(T) == sizeof(double) ? 8 : 16;
+    a.cw = std::min(a.cw, m);
+    a.nnzM = S.nnzM;
+    a.node_of = (const int*)S.node_of.p;
+    a.side_of = (const int*)S.side_of.p;
+    a.rowptr = S.mrowptr;
+    a.col = S.mcol;
+    a.diag = S.mdiag;
+    a.rowptrT = S.trowptr;
+    a.colT = S.tcol;
+    a.diagT = S.tdiag;
+    a.levL = S.levL;
+    a.levU = S.levU;
+    a.levUT = S.levUT;
+    a.levLT = S.levLT;
+    const bool d = sizeof(T) == sizeof(double);
+    a.lu = (const Cx<T>*)(d ? S.lu64.p : S.lu32.p);
+    a.luT = (const Cx<T>*)(d ? S.luT64.p : S.luT32.p);
+    if (precond == FH_PC_JACOBI) a.dinv = (const Cx<T>*)(d ? S.jd64.p : S.jd32.p);
+    else a.dinv = (const Cx<T>*)(d ? S.dinv64.p : S.dinv32.p);
+    return a;
+}
+
+// batch: systems [0, nright) use A with shift z (side 0), [nright, nsys) use A^H with conj(z)
+struct Batch {
+    int nsys = 0, nright = 0, m = 0;
+};
+
+template <typename T>
+static void apply_M(Ctx& c, SparseState& S, const Batch& b, const Cx<T>* shifts, T alpha, const Cx<T>* X,
+                    const Cx<T>* Yadd, Cx<T>* Out) {
+    const long blk = (long)S.n * b.m;
+    spmm<T>(c.stream, S.A, false, S.n, b.m, b.nright, shifts, alpha, X, Yadd, Out);
+    if (b.nsys > b.nright)
+        spmm<T>(c.stream, S.AT, true, S.n, b.m, b.nsys - b.nright, shifts + b.nright, alpha, X + b.nright * blk,
+                Yadd ? Yadd + b.nright * blk : nullptr, Out + b.nright * blk);
+}
+
+template <typename T>
+static void apply_P(Ctx& c, SparseState& S, const Batch& b, int precond, Cx<T>* X, Cx<T>* Out, const T* scale) {
+    IluApplyArgs<T> a = ilu_args<T>(S, b.m, precond);
+    if (precond == FH_PC_ILU0) ilu_apply<T>(c.stream, a, b.nsys, X, Out, scale);
+    else {
+        if (precond == FH_PC_NONE) a.dinv = nullptr;                 // identity
+        jacobi_apply<T>(c.stream, a, b.nsys, X, Out, scale);
+    }
+}
+
+struct SolveStats {
+    long long steps = 0;
+    double relres = 0.0;
+    int cycles = 0;
+};
+
+// GMRES(restart), right preconditioned, every column of every system in lockstep.
+// Solves M_s x = b_s; x starts at zero.  bn: device column norms of b (C doubles).
+template <typename T>
+static SolveStats gmres(Ctx& c, SparseState& S, const Batch& b, const Cx<T>* shifts, const Cx<T>* B, Cx<T>* X,
+                        int restart, int max_cycles, double tol, int precond, const double* bn) {
+    hipStream_t st = c.stream;
+    const int n = S.n, m = b.m, C = b.nsys * m, KP = restart + 1;
+    const long vstride = (long)b.nsys * n * m;
+    SolveStats stats;
+    Cx<T>* V = (Cx<T>*)S.V.ensure(sizeof(Cx<T>) * vstride * (restart + 1));
+    Cx<T>* Z = (Cx<T>*)S.Z.ensure(sizeof(Cx<T>) * vstride);
+    zd* Hs = (zd*)S.Hs.ensure(sizeof(zd) * (size_t)restart * KP * C);
+    double* cs = (double*)S.cs.ensure(sizeof(double) * (size_t)restart * C);
+    zd* sn = (zd*)S.sn.ensure(sizeof(zd) * (size_t)restart * C);
+    zd* g = (zd*)S.g.ensure(sizeof(zd) * (size_t)KP * C);
+    double* resid = (double*)S.resid.ensure(sizeof(double) * C);
+    double* vscale = (double*)S.vscale.ensure(sizeof(double) * C);
+    int* kuse = (int*)S.kuse.ensure(sizeof(int) * C);
+    zd* y = (zd*)S.y.ensure(sizeof(zd) * (size_t)restart * C);
+    zd* h1 = (zd*)S.h1.ensure(sizeof(zd) * (size_t)KP * C);
+    zd* h2 = (zd*)S.h2.ensure(sizeof(zd) * (size_t)KP * C);
+    double* hnorm = (double*)S.hnorm.ensure(sizeof(double) * C);
+    double* beta = (double*)S.beta.ensure(sizeof(double) * C);
+    std::vector<double> hb(C), hbn(C);
+    std::vector<int> hk(C);
+    FH_HIP(hipMemsetAsync(X, 0, sizeof(Cx<T>) * vstride, st));
+    FH_HIP(hipMemcpyAsync(hbn.data(), bn, sizeof(double) * C, hipMemcpyDeviceToHost, st));
+    for (int cyc = 0; cyc < max_cycles + 1; ++cyc) {
+        // r = b - M x into V_0
+        if (cyc == 0) FH_HIP(hipMemcpyAsync(V, B, sizeof(Cx<T>) * vstride, hipMemcpyDeviceToDevice, st));
+        else apply_M<T>(c, S, b, shifts, T(-1), X, B, V);
+        colnorms<T>(st, n, m, b.nsys, V, beta, S.part);
+        FH_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * C, hipMemcpyDeviceToHost, st));
+        FH_HIP(hipStreamSynchronize(st));
+        double worst = 0.0;
+        for (int k = 0; k < C; ++k) worst = std::max(worst, hbn[k] > 0 ? hb[k] / hbn[k] : 0.0);
+        stats.relres = worst;
+        if (!(worst > tol) || cyc == max_cycles) break;
+        stats.cycles++;
+        gmres_start(st, C, KP, restart, beta, bn, tol, g, vscale, kuse);
+        scale_inplace<T>(st, n, m, b.nsys, V, vscale);                  // V_0 = r / beta
+        int kexec = 0;
+        for (int k = 0; k < restart; ++k) {
+            Cx<T>* Vk = V + (long)k * vstride;
+            Cx<T>* Vk1 = V + (long)(k + 1) * vstride;
+            apply_P<T>(c, S, b, precond, Vk, Z, (const T*)nullptr);     // Z = P^{-1} V_k
+            apply_M<T>(c, S, b, shifts, T(1), Z, nullptr, Vk1);         // W = M Z
+            cgs2<T>(st, n, m, b.nsys, k + 1, V, vstride, Vk1, h1, h2, hnorm, S.part);
+            givens_step(st, C, k, KP, h1, h2, hnorm, Hs, cs, sn, g, resid, vscale, kuse, bn, tol);
+            scale_inplace<T>(st, n, m, b.nsys, Vk1, vscale);            // V_{k+1} = W / h_{k+1,k}
+            kexec = k + 1;
+            stats.steps++;
+            FH_HIP(hipMemcpyAsync(hk.data(), kuse, sizeof(int) * C, hipMemcpyDeviceToHost, st));
+            FH_HIP(hipStreamSynchronize(st));
+            bool any = false;
+            for (int q = 0; q < C && !any; ++q) any = hk[q] > k + 1;
+            if (!any) break;
+        }
+        // x += P^{-1} (V y)
+        gmres_update_prep<T>(st, n, m, b.nsys, kexec, KP, Hs, g, kuse, y, V, vstride, Z);
+        Cx<T>* tmp = V + (long)kexec * vstride;   // free after the cycle
+        apply_P<T>(c, S, b, precond, Z, tmp, (const T*)nullptr);
+        add_same<T>(st, vstride, tmp, X);                               // x += P^{-1} V y
+    }
+    return stats;
+}
+
+// shifts per system (side 1 uses conj(z))
+template <typename T>
+static Cx<T>* upload_shifts(Ctx& c, SparseState& S, int ne, const cplx* z) {
+    std::vector<Cx<T>> h(2 * ne);
+    for (int j = 0; j < ne; ++j) {
+        h[j] = Cx<T>{T(z[j].real()), T(z[j].imag())};
+        h[ne + j] = Cx<T>{T(z[j].real()), T(-z[j].imag())};
+    }
+    DBuf& d = sizeof(T) == sizeof(double) ? S.shifts64 : S.shifts32;
+    Cx<T>* p = (Cx<T>*)d.ensure(sizeof(Cx<T>) * 2 * ne);
+    FH_HIP(hipMemcpyAsync(p, h.data(), sizeof(Cx<T>) * 2 * ne, hipMemcpyHostToDevice, c.stream));
+    FH_HIP(hipStreamSynchronize(c.stream));
+    return p;
+}
+
+// Solve all 2 ne systems for the RHS block B64 ([2ne][n][m], FP64) into X64.
+static SolveStats solve_all(Ctx& c, SparseState& S, int ne, const cplx* z, int m, const zd* B64, zd* X64,
+                            const fh_opts& o) {
+    hipStream_t st = c.stream;
+    Batch b;
+    b.nsys = 2 * ne;
+    b.nright = ne;
+    b.m = m;
+    const int n = S.n, C = b.nsys * m;
+    const long len = (long)b.nsys * n * m;
+    std::vector<int> node_of(b.nsys), side_of(b.nsys);
+    for (int s = 0; s < b.nsys; ++s) { node_of[s] = s % ne; side_of[s] = s >= ne; }
+    FH_HIP(hipMemcpyAsync(S.node_of.ensure(sizeof(int) * b.nsys), node_of.data(), sizeof(int) * b.nsys,
+                          hipMemcpyHostToDevice, st));
+    FH_HIP(hipMemcpyAsync(S.side_of.ensure(sizeof(int) * b.nsys), side_of.data(), sizeof(int) * b.nsys,
+                          hipMemcpyHostToDevice, st));
+    const int precond = o.precond;
+    double* bn = (double*)S.bn64.ensure(sizeof(double) * C);
+    colnorms<double>(st, n, m, b.nsys, B64, bn, S.part);
+    const int restart = std::max(1, o.restart);
+    if (o.precision == FH_PREC_FP64) {
+        zd* sh = upload_shifts<double>(c, S, ne, z);
+        return gmres<double>(c, S, b, sh, B64, X64, restart, std::max(1, o.max_restarts), o.inner_tol, precond, bn);
+    }
+    // complex FP32 inner solves wrapped in FP64 iterative refinement
+    cf* sh32 = upload_shifts<float>(c, S, ne, z);
+    zd* sh64 = upload_shifts<double>(c, S, ne, z);
+    zd* R = (zd*)S.bufR.ensure(sizeof(zd) * len);
+    cf* b32 = (cf*)S.b32.ensure(sizeof(cf) * len);
+    cf* x32 = (cf*)S.x32.ensure(sizeof(cf) * len);
+    double* rn = (double*)S.rn64.ensure(sizeof(double) * C);
+    double* sc = (double*)S.sc64.ensure(sizeof(double) * C);
+    std::vector<double> hrn(C), hbn(C), hsc(C);
+    FH_HIP(hipMemcpyAsync(hbn.data(), bn, sizeof(double) * C, hipMemcpyDeviceToHost, st));
+    FH_HIP(hipMemsetAsync(X64, 0, sizeof(zd) * len, st));
+    FH_HIP(hipMemcpyAsync(R, B64, sizeof(zd) * len, hipMemcpyDeviceToDevice, st));
+    SolveStats tot;
+    for (int it = 0; it <= std::max(1, o.max_refine); ++it) {
+        colnorms<double>(st, n, m, b.nsys, R, rn, S.part);
+        FH_HIP(hipMemcpyAsync(hrn.data(), rn, sizeof(double) * C, hipMemcpyDeviceToHost, st));
+        FH_HIP(hipStreamSynchronize(st));
+        double worst = 0.0;
+        for (int k = 0; k < C; ++k) worst = std::max(worst, hbn[k] > 0 ? hrn[k] / hbn[k] : 0.0);
+        tot.relres = worst;
+        if (!(worst > o.inner_tol) || it == std::max(1, o.max_refine)) break;
+        for (int k = 0; k < C; ++k) hsc[k] = hrn[k] > 0 ? 1.0 / hrn[k] : 0.0;
+        FH_HIP(hipMemcpyAsync(sc, hsc.data(), sizeof(double) * C, hipMemcpyHostToDevice, st));
+        scale_cols_cast<float>(st, n, m, b.nsys, R, sc, b32);          // unit columns in FP32
+        double* ones = (double*)S.bn32.ensure(sizeof(double) * C);     // |b32 columns| = 1 (or 0)
+        colnorms<float>(st, n, m, b.nsys, b32, ones, S.part);
+        SolveStats s32 = gmres<float>(c, S, b, sh32, b32, x32, restart, std::max(1, o.max_restarts),
+                                      o.mixed_inner_tol, precond, ones);
+        tot.steps += s32.steps;
+        tot.cycles += s32.cycles;
+        FH_HIP(hipMemcpyAsync(sc, hrn.data(), sizeof(double) * C, hipMemcpyHostToDevice, st));
+        axpy_cols<float>(st, n, m, b.nsys, x32, sc, X64);               // x += |r| d
+        // r = b - M x in FP64
+        Batch bb = b;
+        apply_M<double>(c, S, bb, sh64, -1.0, X64, B64, R);
+    }
+    return tot;
+}
+
+// ---------------------------------------------------------------------------
+// contour filter on a CSR problem (B = I)
+// ---------------------------------------------------------------------------
+void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m, const zd* Y, const zd* Yh, zd* Q,
+                   zd* Qh, const fh_opts& o, fh_report* rep, const cplx* lam) {
+    FH_REQUIRE(m >= 1 && m <= 256, -6, "sparse filter: m0 must be in [1, 256]");
+    SparseState& S = *p.sp;
+    hipStream_t st = c.stream;
+    const int n = S.n;
+    const long blk = (long)n * m;
+    ensure_factors(c, S, ne, z, o.precision == FH_PREC_MIXED, o, rep);
+    zd* Bb = (zd*)S.bufB.ensure(sizeof(zd) * blk * 2 * ne);
+    zd* Xb = (zd*)S.bufX.ensure(sizeof(zd) * blk * 2 * ne);
+    zd* T = (zd*)S.bufT.ensure(sizeof(zd) * blk * 2);
+    zd* lamd = nullptr;
+    std::vector<cplx> coef(2 * (size_t)ne * m), rho(2 * (size_t)m);
+    if (lam) {
+        zd* ld = (zd*)S.rho.ensure(sizeof(zd) * 3 * m);
+        lamd = ld + 2 * m;
+        FH_HIP(hipMemcpyAsync(lamd, lam, sizeof(zd) * m, hipMemcpyHostToDevice, st));
+        ritz_residual(st, S.A, false, n, m, lamd, false, Y, T);           // R  = A Y - Y Lambda
+        ritz_residual(st, S.AT, true, n, m, lamd, true, Yh, T + blk);     // Rh = A^H Yh - Yh Lambda^*
+        for (int i = 0; i < m; ++i) {
+            cplx r = 0.0;
+            for (int j = 0; j < ne; ++j) {
+                const cplx cj = w[j] / (z[j] - lam[i]);
+                coef[(size_t)j * m + i] = cj;
+                coef[(size_t)ne * m + (size_t)j * m + i] = std::conj(cj);
+                r += cj;
+            }
+            rho[i] = r;
+            rho[m + i] = std::conj(r);
+        }
+        replicate<double>(st, blk, T, Bb, ne);
+        replicate<double>(st, blk, T + blk, Bb + ne * blk, ne);
+    } else {
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < ne; ++j) {
+                coef[(size_t)j * m + i] = w[j];
+                coef[(size_t)ne * m + (size_t)j * m + i] = std::conj(w[j]);
+            }
+        replicate<double>(st, blk, Y, Bb, ne);
+        replicate<double>(st, blk, Yh, Bb + ne * blk, ne);
+    }
+    SolveStats s = solve_all(c, S, ne, z, m, Bb, Xb, o);
+    zd* cd = (zd*)S.coef.ensure(sizeof(zd) * coef.size());
+    FH_HIP(hipMemcpyAsync(cd, coef.data(), sizeof(zd) * coef.size(), hipMemcpyHostToDevice, st));
+    zd* rd = nullptr;
+    if (lam) {
+        rd = (zd*)S.rho.p;
+        FH_HIP(hipMemcpyAsync(rd, rho.data(), sizeof(zd) * 2 * m, hipMemcpyHostToDevice, st));
+    }
+    filter_accum(st, ne, n, m, Xb, cd, lam ? Y : nullptr, rd, Q);
+    filter_accum(st, ne, n, m, Xb + ne * blk, cd + (size_t)ne * m, lam ? Yh : nullptr, rd ? rd + m : nullptr, Qh);
+    FH_HIP(hipStreamSynchronize(st));
+    if (rep) {
+        rep->n_solve += 2 * ne;
+        rep->inner_steps = s.steps;
+        rep->inner_relres = s.relres;
+    }
+}
+
+void sparse_apply_A(Ctx& c, Prob& p, int side, int m, const zd* X, zd* Out) {
+    SparseState& S = *p.sp;
+    spmm<double>(c.stream, side ? S.AT : S.A, side == 1, S.n, m, 1, nullptr, -1.0, X, nullptr, Out);
+}
+
+void sparse_shifted_apply(Ctx& c, Prob& p, int side, int nsys, const cplx* shifts, int m, const zd* X, zd* Out) {
+    SparseState& S = *p.sp;
+    std::vector<zd> h(nsys);
+    for (int s = 0; s < nsys; ++s) h[s] = zd{shifts[s].real(), shifts[s].imag()};
+    zd* d = (zd*)S.shifts64.ensure(sizeof(zd) * nsys);
+    FH_HIP(hipMemcpyAsync(d, h.data(), sizeof(zd) * nsys, hipMemcpyHostToDevice, c.stream));
+    FH_HIP(hipStreamSynchronize(c.stream));
+    spmm<double>(c.stream, side ? S.AT : S.A, side == 1, S.n, m, nsys, d, 1.0, X, nullptr, Out);
+}
+
+void sparse_ilu0(Ctx& c, Prob& p, cplx z, zd* lu_out) {
+    SparseState& S = *p.sp;
+    fh_opts o;
+    std::memset(&o, 0, sizeof(o));
+    o.save_factors = 0;
+    ensure_factors(c, S, 1, &z, false, o, nullptr);
+    // values on the M pattern -> A pattern positions (plus diagonal if A has it)
+    std::vector<int> a2m(S.nnzA);
+    FH_HIP(hipMemcpyAsync(a2m.data(), S.a2m, sizeof(int) * S.nnzA, hipMemcpyDeviceToHost, c.stream));
+    FH_HIP(hipStreamSynchronize(c.stream));
+    DBuf ib;
+    int* idx = (int*)ib.ensure(sizeof(int) * S.nnzA);
+    FH_HIP(hipMemcpyAsync(idx, a2m.data(), sizeof(int) * S.nnzA, hipMemcpyHostToDevice, c.stream));
+    gather_vals(c.stream, S.nnzA, true, S.lu64.p, idx, lu_out);
+    FH_HIP(hipStreamSynchronize(c.stream));
+    S.fact_z.clear();   // single-node factors are not a filter node set
+}
+
+void sparse_ilu0_apply(Ctx& c, Prob& p, cplx z, int side, int m, const zd* X, zd* Out) {
+    SparseState& S = *p.sp;
+    fh_opts o;
+    std::memset(&o, 0, sizeof(o));
+    o.save_factors = 0;
+    ensure_factors(c, S, 1, &z, false, o, nullptr);
+    int node = 0;
+    FH_HIP(hipMemcpyAsync(S.node_of.ensure(sizeof(int)), &node, sizeof(int), hipMemcpyHostToDevice, c.stream));
+    FH_HIP(hipMemcpyAsync(S.side_of.ensure(sizeof(int)), &side, sizeof(int), hipMemcpyHostToDevice, c.stream));
+    Batch b;
+    b.nsys = 1;
+    b.nright = side == 0 ? 1 : 0;
+    b.m = m;
+    DBuf xb;
+    zd* xc = (zd*)xb.ensure(sizeof(zd) * (size_t)S.n * m);
+    FH_HIP(hipMemcpyAsync(xc, X, sizeof(zd) * (size_t)S.n * m, hipMemcpyDeviceToDevice, c.stream));
+    apply_P<double>(c, S, b, FH_PC_ILU0, xc, Out, nullptr);
+    FH_HIP(hipStreamSynchronize(c.stream));
+    S.fact_z.clear();
+}
+
+}  // namespace fh

@@ -1,0 +1,160 @@
+"""GPU parity of the sparse (CSR) path against the CPU oracle, through the C ABI:
+operator products, ILU(0) factors and both of its applications, the
+GMRES-based contour filter (FP64 and complex-FP32 + FP64 refinement), and full
+FEAST on convection-diffusion and complex-symmetric operators."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import contour as ct
+from oracle import feast as F
+from oracle import linsolve as L
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+fh = pytest.importorskip("paper_1506_04463_amd")
+
+
+@pytest.fixture(scope="module")
+def handle():
+    return fh.Handle(0)
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _csr(A):
+    return fh.CSR(_cuda(A["rowptr"].astype(np.int32)), _cuda(A["colind"].astype(np.int32)), _cuda(A["val"]), A["n"])
+
+
+def _shift_vals(A, z):
+    val = -np.asarray(A["val"], dtype=np.complex128)
+    for i in range(A["n"]):
+        for p in range(A["rowptr"][i], A["rowptr"][i + 1]):
+            if A["colind"][p] == i:
+                val[p] += z
+    return val
+
+
+PROBS = {
+    "convdiff": lambda: W.convdiff2d_csr(12, 20.0, 10.0),
+    "random_complex": lambda: W.random_sparse_csr(70, 0.08, seed=3, complex_vals=True, diag_shift=8.0),
+    "schrodinger": lambda: W.schrodinger2d_csr(10, L=10.0, nwells=4, seed=2),
+}
+
+
+@pytest.mark.parametrize("name", list(PROBS))
+@pytest.mark.parametrize("m", [1, 5, 64])
+def test_shifted_apply(handle, name, m):
+    A = PROBS[name]()
+    n = A["n"]
+    Ad = W.csr_to_dense(A).astype(np.complex128)
+    prob = fh.Problem(handle, _csr(A))
+    X = np.stack([W.subspace(n, m, 10 + s) for s in range(3)])
+    shifts = np.array([0.5 + 1j, -2.0 + 0.1j, 3.0 - 4j])
+    for side, op in ((0, Ad), (1, Ad.conj().T)):
+        out = fh.shifted_apply(prob, side, shifts, _cuda(X)).cpu().numpy()
+        ref = np.stack([shifts[s] * X[s] - op @ X[s] for s in range(3)])
+        np.testing.assert_allclose(out, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("name", list(PROBS))
+def test_ilu0_factor_matches_oracle(handle, name):
+    A = PROBS[name]()
+    prob = fh.Problem(handle, _csr(A))
+    z = 3.0 + 0.7j if name != "convdiff" else 300.0 + 40.0j
+    lu = fh.ilu0(prob, z).cpu().numpy()
+    ref = L.ilu0(A["rowptr"], A["colind"], _shift_vals(A, z))
+    np.testing.assert_allclose(lu, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("name", list(PROBS))
+@pytest.mark.parametrize("m", [1, 7, 64])
+def test_ilu0_apply_both_sides(handle, name, m):
+    A = PROBS[name]()
+    n = A["n"]
+    prob = fh.Problem(handle, _csr(A))
+    z = 2.0 - 1.5j if name != "convdiff" else 500.0 + 20.0j
+    ref_lu = L.ilu0(A["rowptr"], A["colind"], _shift_vals(A, z))
+    X = W.subspace(n, m, 4)
+    for side, trans in ((0, "N"), (1, "H")):
+        out = fh.ilu0_apply(prob, z, side, _cuda(X)).cpu().numpy()
+        ref = L.ilu0_apply(A["rowptr"], A["colind"], ref_lu, X, trans)
+        np.testing.assert_allclose(out, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
+def _small_convdiff(N=20, m_in=8, m0=16):
+    return W.convdiff2d(N=N, m_in=m_in, m0=m0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_filter_sparse_parity(handle, precision):
+    p = _small_convdiff()
+    A = p.A
+    z, w = ct.ellipse_nodes(p.contour.center, p.contour.a, p.contour.ratio, 0.0, 16)
+    Qo, Qho = F.contour_filter(L.csr_matrix(A), None, z, w, p.Y0, p.Yh0)
+    prob = fh.Problem(handle, _csr(A))
+    opts = fh.default_opts(p.m0, solver=1, precond=2, inner_tol=1e-12, restart=30, max_restarts=400,
+                           precision=precision, mixed_inner_tol=1e-5, max_refine=30)
+    Q, Qh, rep = fh.contour_filter(prob, z, w, _cuda(p.Y0), _cuda(p.Yh0), opts)
+    Q, Qh = Q.cpu().numpy(), Qh.cpu().numpy()
+    # restarted GMRES reaches ~1e-11 here; the parity bound scales with what it reached
+    assert rep["inner_relres"] <= 1e-10
+    Ad = W.csr_to_dense(A)
+    kap = max(np.linalg.cond(zj * np.eye(p.n) - Ad) for zj in z)
+    tol = 10 * kap * max(rep["inner_relres"], 1e-14)
+    assert np.linalg.norm(Q - Qo) / np.linalg.norm(Qo) < tol
+    assert np.linalg.norm(Qh - Qho) / np.linalg.norm(Qho) < tol
+
+
+@pytest.mark.parametrize("precision,precond", [(0, 2), (1, 2), (0, 1)])
+def test_feast_sparse_convdiff_small(handle, precision, precond):
+    p = _small_convdiff(N=24, m_in=10, m0=20)
+    cont = F.Contour(p.contour.center, p.contour.a, p.contour.ratio, 0.0, 16)
+    ref = F.feast(L.csr_matrix(p.A), None, cont, p.Y0, p.Yh0, eps=1e-12, max_iter=30)
+    prob = fh.Problem(handle, _csr(p.A))
+    opts = fh.default_opts(p.m0, solver=1, precond=precond, inner_tol=1e-3, restart=30, max_restarts=2,
+                           precision=precision, mixed_inner_tol=1e-3, max_refine=3, eps=1e-12, max_iter=40)
+    out = fh.feast(prob, p.contour.center, p.contour.a, p.contour.ratio, 0.0, 16, _cuda(p.Y0), _cuda(p.Yh0), opts)
+    assert out["info"] == 0, out["report"]
+    assert len(out["lam"]) == len(ref.lam) == 10
+    alpha = cont.alpha()
+    assert np.max(np.abs(out["lam"] - ref.lam)) < 1e-10 * alpha
+    exact = p.info["lam_sorted"][:10]
+    assert np.max(np.abs(np.sort(out["lam"].real) - exact)) < 1e-10 * alpha
+    X, Xh = out["X"].cpu().numpy(), out["Xh"].cpu().numpy()
+    np.testing.assert_allclose(Xh.conj().T @ X, np.eye(10), atol=1e-10)
+    Ad = W.csr_to_dense(p.A)
+    nA = np.abs(Ad).sum(axis=0).max()
+    lam = out["lam"]
+    rr = np.abs(Ad @ X - X * lam).sum(axis=0) / (nA * np.abs(X).sum(axis=0))
+    rl = np.abs(Ad.T @ Xh - Xh * np.conj(lam)).sum(axis=0) / (nA * np.abs(Xh).sum(axis=0))
+    assert rr.max() <= 1e-10 and rl.max() <= 1e-10
+
+
+def test_feast_complex_symmetric_small(handle):
+    A = W.schrodinger2d_csr(16, L=10.0, nwells=6, seed=4)
+    Ad = W.csr_to_dense(A)
+    ev = sla.eigvals(Ad)
+    # ellipse in the lower half-plane around the eigenvalues nearest a chosen point
+    c = ev[np.argsort(np.abs(ev - (np.median(ev.real[:40]) - 0.5j)))[0]]
+    d = np.sort(np.abs(ev - c))
+    r = 0.5 * (d[7] + d[8])
+    cont = F.Contour(c, r, 1.0, 0.0, 16)
+    Y0, Yh0 = W.subspace(A["n"], 16, 1), W.subspace(A["n"], 16, 2)
+    ref = F.feast(L.csr_matrix(A), None, cont, Y0, Yh0, eps=1e-12, max_iter=40)
+    prob = fh.Problem(handle, _csr(A))
+    opts = fh.default_opts(16, solver=1, precond=2, inner_tol=1e-3, restart=30, max_restarts=2, eps=1e-12,
+                           max_iter=40)
+    out = fh.feast(prob, c, r, 1.0, 0.0, 16, _cuda(Y0), _cuda(Yh0), opts)
+    assert out["info"] == 0 and ref.info == 0
+    assert len(out["lam"]) == len(ref.lam) == 8
+    assert np.max(np.abs(out["lam"] - ref.lam)) < 1e-10 * cont.alpha()
+    X, Xh = out["X"].cpu().numpy(), out["Xh"].cpu().numpy()
+    for i in range(8):          # complex symmetric: Xh parallel to conj(X)
+        x, xh = X[:, i], Xh[:, i]
+        assert abs(np.vdot(np.conj(x), xh)) / (np.linalg.norm(x) * np.linalg.norm(xh)) > 1 - 1e-9

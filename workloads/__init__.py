@@ -218,3 +218,45 @@ def random_sparse_csr(n, density, seed, complex_vals=True, diag_shift=0.0):
             if colind[p] == i:
                 val[p] = val[p] + diag_shift
     return {"n": n, "rowptr": rowptr, "colind": colind, "val": val}
+
+
+# --------------------------------------------------------------------------
+# Complex-symmetric 2D operator (fifth configuration and its small variants)
+# --------------------------------------------------------------------------
+def schrodinger2d_csr(N: int, L: float = 40.0, nwells: int = 50, depth: float = 20.0, sigma: float = 1.0,
+                      eta: float = 5.0, seed: int = 5):
+    """A = -Lap_h + diag(V) - i eta diag(W) on (0, L)^2, Dirichlet, 5-point,
+    h = L/(N+1), index = ix + N*iy.  V = -depth * sum of Gaussian wells (centres
+    area-uniform in [0.1L, 0.9L]^2); W = w(x1) + w(x2) with
+    w(t) = max(0, (|t - L/2| - 0.4L)/(0.1L))^2 (absorbing ramp on the outer 10%).
+    A is complex symmetric (A = A^T)."""
+    rng = np.random.default_rng(seed)
+    h = L / (N + 1)
+    x = (np.arange(N) + 1) * h
+    X1, X2 = np.meshgrid(x, x, indexing="xy")          # X1 varies fastest along a row
+    cen = 0.1 * L + 0.8 * L * rng.random((nwells, 2))
+    V = np.zeros_like(X1)
+    for c1, c2 in cen:
+        V -= depth * np.exp(-((X1 - c1) ** 2 + (X2 - c2) ** 2) / (2 * sigma ** 2))
+    ramp = lambda t: np.maximum(0.0, (np.abs(t - L / 2) - 0.4 * L) / (0.1 * L)) ** 2
+    Wf = ramp(X1) + ramp(X2)
+    diag = 4.0 / h ** 2 + V.ravel() - 1j * eta * Wf.ravel()
+    off = -1.0 / h ** 2
+    n = N * N
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    cols, vals = [], []
+    for iy in range(N):
+        for ix in range(N):
+            r = ix + N * iy
+            if iy > 0:
+                cols.append(r - N); vals.append(off)
+            if ix > 0:
+                cols.append(r - 1); vals.append(off)
+            cols.append(r); vals.append(diag[r])
+            if ix < N - 1:
+                cols.append(r + 1); vals.append(off)
+            if iy < N - 1:
+                cols.append(r + N); vals.append(off)
+            rowptr[r + 1] = len(cols)
+    return {"n": n, "rowptr": rowptr, "colind": np.asarray(cols, dtype=np.int32),
+            "val": np.asarray(vals, dtype=np.complex128), "V": V, "W": Wf}
