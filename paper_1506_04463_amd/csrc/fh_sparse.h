@@ -23,18 +23,31 @@ struct LevelsDev {
     int nlev = 0;
 };
 
+// One triangular sweep in level-packed ELL form: packed row t (level order)
+// is matrix row rows[t]; its off-diagonal entries sit in slots k < K at
+// ell_col[k*n + t] (-1 = empty) with per-node values ell_val[node][k*n + t];
+// a non-unit sweep multiplies by dval[node][t] (the inverse pivot).
+struct SweepDev {
+    const int* lev_ptr = nullptr;   // nlev + 1
+    const int* rows = nullptr;      // n
+    const int* ell_col = nullptr;   // K * n
+    const int* ell_pos = nullptr;   // K * n: position of the value in the LU factor (-1 = empty)
+    const int* dpos = nullptr;      // n: position of the pivot (non-unit sweeps) or null
+    int nlev = 0, K = 0;
+    bool conj = false;              // values enter conjugated (left-side sweeps)
+};
+
 template <typename T>
 struct IluApplyArgs {
     int n = 0, m = 0, cw = 8;
-    long nnzM = 0;
     const int* node_of = nullptr;  // per system
     const int* side_of = nullptr;  // per system
-    const int *rowptr = nullptr, *col = nullptr, *diag = nullptr;      // M pattern
-    const int *rowptrT = nullptr, *colT = nullptr, *diagT = nullptr;   // M^T pattern
-    LevelsDev levL, levU, levUT, levLT;
-    const Cx<T>* lu = nullptr;    // [node][nnzM]
-    const Cx<T>* luT = nullptr;   // [node][nnzM] (values on the M^T pattern)
-    const Cx<T>* dinv = nullptr;  // [node][n]
+    SweepDev fwd[2], bwd[2];       // [side]: side 0 = L then U, side 1 = U^H then L^H
+    const Cx<T>* fval[2] = {nullptr, nullptr};   // [node][K*n]
+    const Cx<T>* fdiag[2] = {nullptr, nullptr};  // [node][n] or null (unit)
+    const Cx<T>* bval[2] = {nullptr, nullptr};
+    const Cx<T>* bdiag[2] = {nullptr, nullptr};
+    const Cx<T>* dinv = nullptr;                 // Jacobi: [node][n] (null: identity)
 };
 
 struct SparseState {
@@ -48,11 +61,14 @@ struct SparseState {
     int2* upd = nullptr;
     long nupd = 0;
     LevelsDev levL, levU, levUT, levLT;
+    SweepDev swL, swU, swUT, swLT;
     std::vector<DBuf*> owned;     // every device array above
     // factor cache
     std::vector<cplx> fact_z;
     int fact_prec = -1;
     DBuf lu64, luT64, dinv64, jd64, lu32, luT32, dinv32, jd32, mvals, zdev;
+    DBuf pk64[6], pk32[6];          // packed sweep values: L, U, Udiag, UT, UTdiag, LT
+    int ilu_cw64 = 4, ilu_cw32 = 4; // column chunk of the sweeps (4: best of 4/8/16 measured at m = 64)
     // batch descriptors and GMRES workspace
     DBuf node_of, side_of, shifts64, shifts32, coef, rho, bufB, bufX, bufR, bufT, b32, x32;
     DBuf V, Z, Hs, cs, sn, g, resid, vscale, kuse, y, h1, h2, hnorm, beta, bnorm, part, bn64, rn64, sc64;
@@ -68,6 +84,7 @@ void spmm(hipStream_t st, const CsrDev& A, bool conj_t, int n, int m, int nsys, 
           const Cx<T>* X, const Cx<T>* Yadd, Cx<T>* Out);
 void form_mvals(hipStream_t st, const SparseState& S, int ne, const zd* z_dev, zd* out);
 void ilu0_factor(hipStream_t st, const SparseState& S, int ne, zd* lu, zd* luT, zd* dinv);
+void pack_sweep_vals(hipStream_t st, const SweepDev& sw, int n, int ne, long nnzM, const zd* lu, zd* ell, zd* diag);
 void to_single(hipStream_t st, long len, const zd* s, cf* d);
 template <typename T>
 void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<T>* Out, const T* scale);

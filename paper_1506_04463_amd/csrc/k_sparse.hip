@@ -178,85 +178,127 @@ void to_single(hipStream_t st, long len, const zd* s, cf* d) {
 }
 
 // ---------------------------------------------------------------------------
+// Packing of the factor values into the level-packed ELL order of a sweep
+// (per node), conjugated for the left-side sweeps; pivots inverted.
+// ---------------------------------------------------------------------------
+__global__ void k_pack_ell(int n, int K, const int* __restrict__ pos, const zd* __restrict__ lu_all, long nnzM,
+                           int conjv, zd* __restrict__ out_all) {
+    const int j = blockIdx.y;
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)K * n) return;
+    const int p = pos[e];
+    zd v = p >= 0 ? lu_all[(long)j * nnzM + p] : czero<double>();
+    out_all[(long)j * K * n + e] = conjv ? conj(v) : v;
+}
+__global__ void k_pack_diag(int n, const int* __restrict__ dpos, const zd* __restrict__ lu_all, long nnzM, int conjv,
+                            zd* __restrict__ out_all) {
+    const int j = blockIdx.y;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    zd v = cdiv(cx(1.0, 0.0), lu_all[(long)j * nnzM + dpos[t]]);
+    out_all[(long)j * n + t] = conjv ? conj(v) : v;
+}
+void pack_sweep_vals(hipStream_t st, const SweepDev& sw, int n, int ne, long nnzM, const zd* lu, zd* ell, zd* diag) {
+    if (sw.K > 0) {
+        dim3 g(ceil_div((size_t)sw.K * n, 256), ne);
+        k_pack_ell<<<g, 256, 0, st>>>(n, sw.K, sw.ell_pos, lu, nnzM, sw.conj ? 1 : 0, ell);
+        FH_LAUNCH_CHECK();
+    }
+    if (sw.dpos && diag) {
+        dim3 g(ceil_div(n, 256), ne);
+        k_pack_diag<<<g, 256, 0, st>>>(n, sw.dpos, lu, nnzM, sw.conj ? 1 : 0, diag);
+        FH_LAUNCH_CHECK();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Preconditioner apply: Out_s = (L U)^{-1} X_s (side 0) or (L U)^{-H} X_s
 // (side 1) with the factors of node(s).  One workgroup per (column chunk,
-// system); rows swept level by level.  If scale != nullptr, the input column
-// c is multiplied by scale[s*m + c] and the scaled value is written back to X.
+// system) sweeps the rows level by level; within a level each thread first
+// issues the loads of up to P items (independent of the level's stores), then
+// stores them.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_ilu_apply(IluApplyArgs<T> a, Cx<T>* __restrict__ X, Cx<T>* __restrict__ Out,
-                                                   const T* __restrict__ scale) {
-    const int s = blockIdx.y;
-    const int c0 = blockIdx.x * a.cw;
-    const int cw = min(a.cw, a.m - c0);
-    const int node = a.node_of[s], side = a.side_of[s];
-    const long base = (long)s * a.n * a.m;
-    Cx<T>* Xs = X + base;
-    Cx<T>* Os = Out + base;
-    const Cx<T>* lu = (side == 0 ? a.lu : a.luT) + (long)node * a.nnzM;
-    const Cx<T>* dv = a.dinv + (long)node * a.n;
-    const int* rp = side == 0 ? a.rowptr : a.rowptrT;
-    const int* cl = side == 0 ? a.col : a.colT;
-    const int* dg = side == 0 ? a.diag : a.diagT;
-    const LevelsDev& F = side == 0 ? a.levL : a.levUT;
-    const LevelsDev& B = side == 0 ? a.levU : a.levLT;
+template <typename T, int P, int KM>
+__device__ __forceinline__ void sweep(const SweepDev& sw, int n, int m, int c0, int cw, const Cx<T>* __restrict__ val,
+                                      const Cx<T>* __restrict__ dval, const Cx<T>* In, Cx<T>* Os) {
     const int tid = threadIdx.x;
-    // forward: unit L (side 0) or U^H (side 1)
-    for (int lev = 0; lev < F.nlev; ++lev) {
-        const int t0 = F.ptr[lev], cnt = (F.ptr[lev + 1] - t0) * cw;
-        for (int e = tid; e < cnt; e += 256) {
-            const int i = F.rows[t0 + e / cw];
-            const int c = c0 + e % cw;
-            Cx<T> acc = Xs[(long)i * a.m + c];
-            if (scale) {
-                acc = scale[(long)s * a.m + c] * acc;
-                Xs[(long)i * a.m + c] = acc;
+    const int K = sw.K;
+    for (int lev = 0; lev < sw.nlev; ++lev) {
+        const int t0 = sw.lev_ptr[lev];
+        const int items = (sw.lev_ptr[lev + 1] - t0) * cw;
+        for (int base = 0; base < items; base += 256 * P) {
+            Cx<T> acc[P];
+            int rowq[P], ccq[P];
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                const int e = base + tid + 256 * q;
+                rowq[q] = -1;
+                if (e < items) {
+                    const int t = t0 + e / cw;
+                    const int cc = c0 + e % cw;
+                    const int row = sw.rows[t];
+                    Cx<T> v = In[(long)row * m + cc];
+#pragma unroll
+                    for (int k = 0; k < KM; ++k) {
+                        if (k < K) {
+                            const int col = sw.ell_col[(long)k * n + t];
+                            if (col >= 0) cfms(v, val[(long)k * n + t], Os[(long)col * m + cc]);
+                        }
+                    }
+                    if (dval) v = dval[t] * v;
+                    acc[q] = v;
+                    rowq[q] = row;
+                    ccq[q] = cc;
+                }
             }
-            const int pd = dg[i];
-            if (side == 0) {
-                for (int p = rp[i]; p < pd; ++p) cfms(acc, lu[p], Os[(long)cl[p] * a.m + c]);
-            } else {
-                for (int p = rp[i]; p < pd; ++p) cfms(acc, conj(lu[p]), Os[(long)cl[p] * a.m + c]);
-                acc = conj(dv[i]) * acc;
-            }
-            Os[(long)i * a.m + c] = acc;
-        }
-        __syncthreads();
-    }
-    // backward: U (side 0) or unit L^H (side 1)
-    for (int lev = 0; lev < B.nlev; ++lev) {
-        const int t0 = B.ptr[lev], cnt = (B.ptr[lev + 1] - t0) * cw;
-        for (int e = tid; e < cnt; e += 256) {
-            const int i = B.rows[t0 + e / cw];
-            const int c = c0 + e % cw;
-            Cx<T> acc = Os[(long)i * a.m + c];
-            const int p1 = rp[i + 1];
-            if (side == 0) {
-                for (int p = dg[i] + 1; p < p1; ++p) cfms(acc, lu[p], Os[(long)cl[p] * a.m + c]);
-                acc = dv[i] * acc;
-            } else {
-                for (int p = dg[i] + 1; p < p1; ++p) cfms(acc, conj(lu[p]), Os[(long)cl[p] * a.m + c]);
-            }
-            Os[(long)i * a.m + c] = acc;
+#pragma unroll
+            for (int q = 0; q < P; ++q)
+                if (rowq[q] >= 0) Os[(long)rowq[q] * m + ccq[q]] = acc[q];
         }
         __syncthreads();
     }
 }
 
+template <typename T, int P, int KM>
+__global__ __launch_bounds__(256) void k_ilu_apply(IluApplyArgs<T> a, const Cx<T>* __restrict__ X, Cx<T>* Out) {
+    const int s = blockIdx.y;
+    const int c0 = blockIdx.x * a.cw;
+    const int cw = min(a.cw, a.m - c0);
+    const int node = a.node_of[s], side = a.side_of[s];
+    const long base = (long)s * a.n * a.m;
+    const Cx<T>* Xs = X + base;
+    Cx<T>* Os = Out + base;
+    const SweepDev& F = a.fwd[side];
+    const SweepDev& B = a.bwd[side];
+    const Cx<T>* fv = a.fval[side] + (long)node * F.K * a.n;
+    const Cx<T>* fd = a.fdiag[side] ? a.fdiag[side] + (long)node * a.n : nullptr;
+    const Cx<T>* bv = a.bval[side] + (long)node * B.K * a.n;
+    const Cx<T>* bd = a.bdiag[side] ? a.bdiag[side] + (long)node * a.n : nullptr;
+    sweep<T, P, KM>(F, a.n, a.m, c0, cw, fv, fd, Xs, Os);
+    sweep<T, P, KM>(B, a.n, a.m, c0, cw, bv, bd, Os, Os);
+}
+
 template <typename T>
 void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<T>* Out, const T* scale) {
     if (nsys <= 0) return;
+    FH_REQUIRE(scale == nullptr, -1, "ilu_apply: input scaling is not supported");
     dim3 grid(ceil_div(a.m, a.cw), nsys);
+    const int K = std::max(std::max(a.fwd[0].K, a.bwd[0].K), std::max(a.fwd[1].K, a.bwd[1].K));
     hipEvent_t ev = prof_begin(st);
-    k_ilu_apply<T><<<grid, 256, 0, st>>>(a, X, Out, scale);
+    if (K <= 2) k_ilu_apply<T, 8, 2><<<grid, 256, 0, st>>>(a, X, Out);
+    else if (K <= 4) k_ilu_apply<T, 8, 4><<<grid, 256, 0, st>>>(a, X, Out);
+    else if (K <= 8) k_ilu_apply<T, 4, 8><<<grid, 256, 0, st>>>(a, X, Out);
+    else if (K <= 32) k_ilu_apply<T, 2, 32><<<grid, 256, 0, st>>>(a, X, Out);
+    else throw Error(-1, "ILU(0) sweeps support at most 32 off-diagonal entries per triangular row");
     FH_LAUNCH_CHECK();
     if (ev) {
         // X read, Out written by the forward sweep, read and rewritten by the
-        // backward sweep; factors (values, pattern, inverse diagonal) once per system
+        // backward sweep; packed factor values and indices once per system
         const double vec = (double)nsys * a.n * a.m * sizeof(Cx<T>);
-        const double fac = (double)a.nnzM * (sizeof(Cx<T>) + 4) + (double)a.n * (sizeof(Cx<T>) + 8);
+        const double fac = (double)a.n * (a.fwd[0].K + a.bwd[0].K) * (sizeof(Cx<T>) + 4) +
+                           (double)a.n * (sizeof(Cx<T>) + 8);
         prof_end(st, ev, std::string("ilu_apply_") + (sizeof(T) == 8 ? "c128" : "c64"), 4 * vec + nsys * fac,
-                 (double)nsys * a.m * 8.0 * a.nnzM);
+                 (double)nsys * a.m * 8.0 * a.n * (a.fwd[0].K + a.bwd[0].K + 1));
     }
 }
 template void ilu_apply<double>(hipStream_t, const IluApplyArgs<double>&, int, zd*, zd*, const double*);
@@ -295,38 +337,18 @@ template void jacobi_apply<float>(hipStream_t, const IluApplyArgs<float>&, int, 
 // ---------------------------------------------------------------------------
 constexpr int ROWS_PER_CHUNK = 256;
 
-// h_i = V_i^H W  (i = 0..kp1-1)
-template <typename T, int KM>
-__global__ __launch_bounds__(256) void k_cgs_dots(int n, int m, int kp1, const Cx<T>* __restrict__ V, long vstride,
-                                                  const Cx<T>* __restrict__ W, double* __restrict__ part, int nchunk) {
-    const int s = blockIdx.y, chunk = blockIdx.x;
-    const int c = threadIdx.x, ty = threadIdx.y, ry = blockDim.y;
-    const long base = (long)s * n * m;
-    const int r0 = chunk * ROWS_PER_CHUNK, r1 = min(n, r0 + ROWS_PER_CHUNK);
-    double acc_re[KM], acc_im[KM];
-#pragma unroll
-    for (int i = 0; i < KM; ++i) { acc_re[i] = 0.0; acc_im[i] = 0.0; }
-    for (int r = r0 + ty; r < r1; r += ry) {
-        const long off = base + (long)r * m + c;
-        const Cx<T> w = W[off];
-#pragma unroll
-        for (int i = 0; i < KM; ++i) {
-            if (i < kp1) {
-                const Cx<T> v = V[i * vstride + off];
-                acc_re[i] += (double)v.re * w.re + (double)v.im * w.im;
-                acc_im[i] += (double)v.re * w.im - (double)v.im * w.re;
-            }
-        }
-    }
-    // reduce over ty through LDS
-    __shared__ double sh[2][256];
-    const int C = gridDim.y * m;
-    const int col = s * m + c;
+template <typename T> struct AccT { using type = double; };
+template <> struct AccT<float> { using type = float; };
+
+// per-chunk partial sums reduced over the ry row groups of the block through LDS
+template <typename A, int KM>
+__device__ __forceinline__ void store_partials(const A* acc_re, const A* acc_im, int kp1, int m, int c, int ty, int ry,
+                                               int chunk, int C, int col, double* part, double (*sh)[256]) {
 #pragma unroll
     for (int i = 0; i < KM; ++i) {
         if (i < kp1) {
-            sh[0][ty * m + c] = acc_re[i];
-            sh[1][ty * m + c] = acc_im[i];
+            sh[0][ty * m + c] = (double)acc_re[i];
+            sh[1][ty * m + c] = (double)acc_im[i];
             __syncthreads();
             if (ty == 0) {
                 double a = sh[0][c], b = sh[1][c];
@@ -339,59 +361,73 @@ __global__ __launch_bounds__(256) void k_cgs_dots(int n, int m, int kp1, const C
     }
 }
 
-// W' = W - sum_i h_i V_i ; then partial dots of V_i^H W' (fused second pass)
+// h_i = V_i^H W  (i = 0..kp1-1)
+template <typename T, int KM>
+__global__ __launch_bounds__(256) void k_cgs_dots(int n, int m, int kp1, const Cx<T>* __restrict__ V, long vstride,
+                                                  const Cx<T>* __restrict__ W, double* __restrict__ part, int nchunk) {
+    using A = typename AccT<T>::type;
+    const int s = blockIdx.y, chunk = blockIdx.x;
+    const int c = threadIdx.x, ty = threadIdx.y, ry = blockDim.y;
+    const long base = (long)s * n * m;
+    const int r0 = chunk * ROWS_PER_CHUNK, r1 = min(n, r0 + ROWS_PER_CHUNK);
+    A acc_re[KM], acc_im[KM];
+#pragma unroll
+    for (int i = 0; i < KM; ++i) { acc_re[i] = A(0); acc_im[i] = A(0); }
+    for (int r = r0 + ty; r < r1; r += ry) {
+        const long off = base + (long)r * m + c;
+        const Cx<T> w = W[off];
+#pragma unroll
+        for (int i = 0; i < KM; ++i) {
+            if (i < kp1) {
+                const Cx<T> v = V[i * vstride + off];
+                acc_re[i] += (A)v.re * (A)w.re + (A)v.im * (A)w.im;
+                acc_im[i] += (A)v.re * (A)w.im - (A)v.im * (A)w.re;
+            }
+        }
+    }
+    __shared__ double sh[2][256];
+    store_partials<A, KM>(acc_re, acc_im, kp1, m, c, ty, ry, chunk, gridDim.y * m, s * m + c, part, sh);
+}
+
+// W' = W - sum_i h_i V_i ; then partial dots V_i^H W' (fused second pass;
+// V_i is re-read from cache rather than held in registers)
 template <typename T, int KM>
 __global__ __launch_bounds__(256) void k_cgs_update_dots(int n, int m, int kp1, const Cx<T>* __restrict__ V,
                                                          long vstride, Cx<T>* __restrict__ W,
                                                          const zd* __restrict__ h, double* __restrict__ part) {
+    using A = typename AccT<T>::type;
     const int s = blockIdx.y, chunk = blockIdx.x;
     const int c = threadIdx.x, ty = threadIdx.y, ry = blockDim.y;
     const long base = (long)s * n * m;
     const int C = gridDim.y * m;
     const int col = s * m + c;
     const int r0 = chunk * ROWS_PER_CHUNK, r1 = min(n, r0 + ROWS_PER_CHUNK);
-    Cx<T> hh[KM];
+    extern __shared__ unsigned char dsm[];
+    Cx<T>* hs = reinterpret_cast<Cx<T>*>(dsm);          // [kp1][m]
+    if (ty == 0)
+        for (int i = 0; i < kp1; ++i) hs[i * m + c] = ccast<T>(h[(long)i * C + col]);
+    __syncthreads();
+    A acc_re[KM], acc_im[KM];
 #pragma unroll
-    for (int i = 0; i < KM; ++i) hh[i] = (i < kp1) ? ccast<T>(h[(long)i * C + col]) : czero<T>();
-    double acc_re[KM], acc_im[KM];
-#pragma unroll
-    for (int i = 0; i < KM; ++i) { acc_re[i] = 0.0; acc_im[i] = 0.0; }
+    for (int i = 0; i < KM; ++i) { acc_re[i] = A(0); acc_im[i] = A(0); }
     for (int r = r0 + ty; r < r1; r += ry) {
         const long off = base + (long)r * m + c;
         Cx<T> w = W[off];
-        Cx<T> vv[KM];
 #pragma unroll
-        for (int i = 0; i < KM; ++i) {
-            if (i < kp1) {
-                vv[i] = V[i * vstride + off];
-                cfms(w, hh[i], vv[i]);
-            }
-        }
+        for (int i = 0; i < KM; ++i)
+            if (i < kp1) cfms(w, hs[i * m + c], V[i * vstride + off]);
         W[off] = w;
 #pragma unroll
         for (int i = 0; i < KM; ++i) {
             if (i < kp1) {
-                acc_re[i] += (double)vv[i].re * w.re + (double)vv[i].im * w.im;
-                acc_im[i] += (double)vv[i].re * w.im - (double)vv[i].im * w.re;
+                const Cx<T> v = V[i * vstride + off];
+                acc_re[i] += (A)v.re * (A)w.re + (A)v.im * (A)w.im;
+                acc_im[i] += (A)v.re * (A)w.im - (A)v.im * (A)w.re;
             }
         }
     }
     __shared__ double sh[2][256];
-#pragma unroll
-    for (int i = 0; i < KM; ++i) {
-        if (i < kp1) {
-            sh[0][ty * m + c] = acc_re[i];
-            sh[1][ty * m + c] = acc_im[i];
-            __syncthreads();
-            if (ty == 0) {
-                double a = sh[0][c], b = sh[1][c];
-                for (int t = 1; t < ry; ++t) { a += sh[0][t * m + c]; b += sh[1][t * m + c]; }
-                part[((long)chunk * KM + i) * 2 * C + col] = a;
-                part[((long)chunk * KM + i) * 2 * C + C + col] = b;
-            }
-            __syncthreads();
-        }
-    }
+    store_partials<A, KM>(acc_re, acc_im, kp1, m, c, ty, ry, chunk, C, col, part, sh);
 }
 
 // W'' = W' - sum_i h_i V_i ; partial ||W''||^2
@@ -405,16 +441,18 @@ __global__ __launch_bounds__(256) void k_cgs_update_norm(int n, int m, int kp1, 
     const int C = gridDim.y * m;
     const int col = s * m + c;
     const int r0 = chunk * ROWS_PER_CHUNK, r1 = min(n, r0 + ROWS_PER_CHUNK);
-    Cx<T> hh[KM];
-#pragma unroll
-    for (int i = 0; i < KM; ++i) hh[i] = (i < kp1) ? ccast<T>(h[(long)i * C + col]) : czero<T>();
+    extern __shared__ unsigned char dsm[];
+    Cx<T>* hs = reinterpret_cast<Cx<T>*>(dsm);          // [kp1][m]
+    if (ty == 0)
+        for (int i = 0; i < kp1; ++i) hs[i * m + c] = ccast<T>(h[(long)i * C + col]);
+    __syncthreads();
     double nn = 0.0;
     for (int r = r0 + ty; r < r1; r += ry) {
         const long off = base + (long)r * m + c;
         Cx<T> w = W[off];
 #pragma unroll
         for (int i = 0; i < KM; ++i)
-            if (i < kp1) cfms(w, hh[i], V[i * vstride + off]);
+            if (i < kp1) cfms(w, hs[i * m + c], V[i * vstride + off]);
         W[off] = w;
         nn += (double)w.re * w.re + (double)w.im * w.im;
     }
@@ -490,13 +528,19 @@ static void cgs_launch(hipStream_t st, int n, int m, int nsys, int kp1, const Cx
     k_reduce_dots<<<rg, 128, 0, st>>>(nchunk, kp1, KM, C, P, h1, 0);
     FH_LAUNCH_CHECK();
     ev = prof_begin(st);
-    k_cgs_update_dots<T, KM><<<grid, blk, 0, st>>>(n, m, kp1, V, vstride, W, h1, P);
+    const size_t hsb = sizeof(Cx<T>) * (size_t)kp1 * m;
+    FH_REQUIRE(hsb <= 96 * 1024, -1, "GMRES restart length x columns per system too large for the LDS staging");
+    if (hsb > 64 * 1024) {
+        FH_HIP(hipFuncSetAttribute((const void*)k_cgs_update_dots<T, KM>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
+        FH_HIP(hipFuncSetAttribute((const void*)k_cgs_update_norm<T, KM>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
+    }
+    k_cgs_update_dots<T, KM><<<grid, blk, hsb, st>>>(n, m, kp1, V, vstride, W, h1, P);
     FH_LAUNCH_CHECK();
     prof_end(st, ev, "cgs_update_dots_" + tag, (kp1 + 2) * vec, 16.0 * kp1 * vec / sizeof(Cx<T>));
     k_reduce_dots<<<rg, 128, 0, st>>>(nchunk, kp1, KM, C, P, h2, 0);
     FH_LAUNCH_CHECK();
     ev = prof_begin(st);
-    k_cgs_update_norm<T, KM><<<grid, blk, 0, st>>>(n, m, kp1, V, vstride, W, h2, P);
+    k_cgs_update_norm<T, KM><<<grid, blk, hsb, st>>>(n, m, kp1, V, vstride, W, h2, P);
     FH_LAUNCH_CHECK();
     prof_end(st, ev, "cgs_update_norm_" + tag, (kp1 + 2) * vec, 8.0 * kp1 * vec / sizeof(Cx<T>));
     k_reduce_norm<<<ceil_div(C, 128), 128, 0, st>>>(nchunk, C, P, hnorm);

@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cstring>
 #include <numeric>
+#include <cstdlib>
 
 #include "fh_sparse.h"
 
@@ -27,6 +28,62 @@ static int* dev_ints(SparseState& S, const std::vector<int>& h, hipStream_t st) 
         FH_HIP(hipStreamSynchronize(st));   // h may be reused or freed by the caller
     }
     return p;
+}
+
+// rows grouped by level (ascending row index within a level)
+static void level_order(const std::vector<int>& lev, int n, std::vector<int>& ptr, std::vector<int>& rows) {
+    int nlev = 0;
+    for (int i = 0; i < n; ++i) nlev = std::max(nlev, lev[i] + 1);
+    ptr.assign(nlev + 1, 0);
+    rows.resize(n);
+    for (int i = 0; i < n; ++i) ptr[lev[i] + 1]++;
+    for (int l = 0; l < nlev; ++l) ptr[l + 1] += ptr[l];
+    std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+    for (int i = 0; i < n; ++i) rows[fill[lev[i]]++] = i;
+}
+
+// Level-packed ELL form of one triangular sweep.  entries(i, cols, pos) lists
+// the off-diagonal entries of row i (column, position of its value in the LU
+// factor on the M pattern); dpos_of(i) is the pivot position or -1 (unit).
+template <typename F, typename D>
+static SweepDev build_sweep(SparseState& S, const std::vector<int>& lev, int n, bool conjv, F entries, D dpos_of,
+                            hipStream_t st) {
+    std::vector<int> ptr, rows;
+    level_order(lev, n, ptr, rows);
+    int K = 0;
+    std::vector<int> cols, pos;
+    for (int i = 0; i < n; ++i) {
+        cols.clear();
+        pos.clear();
+        entries(i, cols, pos);
+        K = std::max(K, (int)cols.size());
+    }
+    std::vector<int> ecol((size_t)K * n, -1), epos((size_t)K * n, -1), dp;
+    bool has_diag = false;
+    for (int t = 0; t < n; ++t) {
+        cols.clear();
+        pos.clear();
+        entries(rows[t], cols, pos);
+        for (size_t k = 0; k < cols.size(); ++k) {
+            ecol[k * n + t] = cols[k];
+            epos[k * n + t] = pos[k];
+        }
+        const int d = dpos_of(rows[t]);
+        if (d >= 0) has_diag = true;
+        dp.push_back(d);
+    }
+    SweepDev sw;
+    sw.lev_ptr = dev_ints(S, ptr, st);
+    sw.rows = dev_ints(S, rows, st);
+    sw.nlev = (int)ptr.size() - 1;
+    sw.K = K;
+    sw.conj = conjv;
+    if (K > 0) {
+        sw.ell_col = dev_ints(S, ecol, st);
+        sw.ell_pos = dev_ints(S, epos, st);
+    }
+    if (has_diag) sw.dpos = dev_ints(S, dp, st);
+    return sw;
 }
 
 static LevelsDev levels_dev(SparseState& S, const std::vector<int>& lev, int n, hipStream_t st) {
@@ -61,6 +118,12 @@ static void transpose_pattern(int n, const std::vector<int>& rp, const std::vect
             tci[q] = i;
             tpos[q] = p;
         }
+}
+
+// column chunk of the ILU sweeps: FH_ILU_CW64 / FH_ILU_CW32 override the defaults
+static void ilu_chunk_defaults(SparseState& S) {
+    if (const char* e = std::getenv("FH_ILU_CW64")) S.ilu_cw64 = std::max(1, std::atoi(e));
+    if (const char* e = std::getenv("FH_ILU_CW32")) S.ilu_cw32 = std::max(1, std::atoi(e));
 }
 
 void sparse_prepare(Ctx& c, Prob& p) {
@@ -131,24 +194,40 @@ void sparse_prepare(Ctx& c, Prob& p) {
         lev[i] = l;
     }
     S->levL = levels_dev(*S, lev, n, st);
+    S->swL = build_sweep(*S, lev, n, false,
+        [&](int i, std::vector<int>& c, std::vector<int>& ps) {
+            for (int q = mrp[i]; q < mdiag[i]; ++q) { c.push_back(mci[q]); ps.push_back(q); } },
+        [&](int) { return -1; }, st);
     for (int i = n - 1; i >= 0; --i) {       // U (backward)
         int l = 0;
         for (int q = mdiag[i] + 1; q < mrp[i + 1]; ++q) l = std::max(l, lev[mci[q]] + 1);
         lev[i] = l;
     }
     S->levU = levels_dev(*S, lev, n, st);
+    S->swU = build_sweep(*S, lev, n, false,
+        [&](int i, std::vector<int>& c, std::vector<int>& ps) {
+            for (int q = mdiag[i] + 1; q < mrp[i + 1]; ++q) { c.push_back(mci[q]); ps.push_back(q); } },
+        [&](int i) { return mdiag[i]; }, st);
     for (int i = 0; i < n; ++i) {            // U^H: lower part of M^T (forward)
         int l = 0;
         for (int q = trp[i]; q < tdiag[i]; ++q) l = std::max(l, lev[tci[q]] + 1);
         lev[i] = l;
     }
     S->levUT = levels_dev(*S, lev, n, st);
+    S->swUT = build_sweep(*S, lev, n, true,
+        [&](int i, std::vector<int>& c, std::vector<int>& ps) {
+            for (int q = trp[i]; q < tdiag[i]; ++q) { c.push_back(tci[q]); ps.push_back(t2m[q]); } },
+        [&](int i) { return mdiag[i]; }, st);
     for (int i = n - 1; i >= 0; --i) {       // L^H: upper part of M^T (backward)
         int l = 0;
         for (int q = tdiag[i] + 1; q < trp[i + 1]; ++q) l = std::max(l, lev[tci[q]] + 1);
         lev[i] = l;
     }
     S->levLT = levels_dev(*S, lev, n, st);
+    S->swLT = build_sweep(*S, lev, n, true,
+        [&](int i, std::vector<int>& c, std::vector<int>& ps) {
+            for (int q = tdiag[i] + 1; q < trp[i + 1]; ++q) { c.push_back(tci[q]); ps.push_back(t2m[q]); } },
+        [&](int) { return -1; }, st);
     S->mrowptr = dev_ints(*S, mrp, st);
     S->mcol = dev_ints(*S, mci, st);
     S->mdiag = dev_ints(*S, mdiag, st);
@@ -189,6 +268,7 @@ void sparse_prepare(Ctx& c, Prob& p) {
     S->AT.val32 = S->atval32.ensure(vb / 2 * std::max<long>(1, nnz));
     cast_vals(st, nnz, cplx_vals, S->AT.val64, (void*)S->AT.val32);
     FH_HIP(hipStreamSynchronize(st));
+    ilu_chunk_defaults(*S);
 }
 
 void sparse_destroy(SparseState* s) { delete s; }
@@ -216,6 +296,14 @@ static void ensure_factors(Ctx& c, SparseState& S, int ne, const cplx* z, bool n
         form_mvals(st, S, ne, zd_, lu);
         jacobi_diag(st, S, ne, lu, jd);      // 1/(z_j - a_ii) from the unfactored values
         ilu0_factor(st, S, ne, lu, luT, dinv);
+        // level-packed values of the four sweeps
+        const SweepDev* sws[4] = {&S.swL, &S.swU, &S.swUT, &S.swLT};
+        const int vi[4] = {0, 1, 3, 5}, di[4] = {-1, 2, 4, -1};
+        for (int q = 0; q < 4; ++q) {
+            zd* ell = (zd*)S.pk64[vi[q]].ensure(sizeof(zd) * std::max<size_t>(1, (size_t)sws[q]->K * n * ne));
+            zd* dg = di[q] >= 0 ? (zd*)S.pk64[di[q]].ensure(sizeof(zd) * (size_t)n * ne) : nullptr;
+            pack_sweep_vals(st, *sws[q], n, ne, nnzM, lu, ell, dg);
+        }
         // zero or non-finite pivots
         std::vector<zd> hdv((size_t)n * ne);
         FH_HIP(hipMemcpyAsync(hdv.data(), dinv, sizeof(zd) * hdv.size(), hipMemcpyDeviceToHost, st));
@@ -237,6 +325,11 @@ static void ensure_factors(Ctx& c, SparseState& S, int ne, const cplx* z, bool n
         to_single(st, nnzM * ne, (const zd*)S.luT64.p, (cf*)S.luT32.ensure(sizeof(cf) * nnzM * ne));
         to_single(st, (long)n * ne, (const zd*)S.dinv64.p, (cf*)S.dinv32.ensure(sizeof(cf) * (size_t)n * ne));
         to_single(st, (long)n * ne, (const zd*)S.jd64.p, (cf*)S.jd32.ensure(sizeof(cf) * (size_t)n * ne));
+        for (int q = 0; q < 6; ++q) {
+            if (!S.pk64[q].p) continue;
+            const size_t cnt = S.pk64[q].bytes / sizeof(zd);
+            to_single(st, (long)cnt, (const zd*)S.pk64[q].p, (cf*)S.pk32[q].ensure(sizeof(cf) * cnt));
+        }
         S.fact_prec = 1;
     }
 }
@@ -244,28 +337,26 @@ static void ensure_factors(Ctx& c, SparseState& S, int ne, const cplx* z, bool n
 template <typename T>
 static IluApplyArgs<T> ilu_args(SparseState& S, int m, int precond) {
     IluApplyArgs<T> a;
+    const bool d = sizeof(T) == sizeof(double);
     a.n = S.n;
     a.m = m;
-    a.cw = sizeof(T) == sizeof(double) ? 8 : 16;
-    a.cw = std::min(a.cw, m);
-    a.nnzM = S.nnzM;
+    a.cw = std::max(1, std::min(d ? S.ilu_cw64 : S.ilu_cw32, m));
     a.node_of = (const int*)S.node_of.p;
     a.side_of = (const int*)S.side_of.p;
-    a.rowptr = S.mrowptr;
-    a.col = S.mcol;
-    a.diag = S.mdiag;
-    a.rowptrT = S.trowptr;
-    a.colT = S.tcol;
-    a.diagT = S.tdiag;
-    a.levL = S.levL;
-    a.levU = S.levU;
-    a.levUT = S.levUT;
-    a.levLT = S.levLT;
-    const bool d = sizeof(T) == sizeof(double);
-    a.lu = (const Cx<T>*)(d ? S.lu64.p : S.lu32.p);
-    a.luT = (const Cx<T>*)(d ? S.luT64.p : S.luT32.p);
+    a.fwd[0] = S.swL;
+    a.bwd[0] = S.swU;
+    a.fwd[1] = S.swUT;
+    a.bwd[1] = S.swLT;
+    DBuf* pk = d ? S.pk64 : S.pk32;
+    a.fval[0] = (const Cx<T>*)pk[0].p;
+    a.fdiag[0] = nullptr;
+    a.bval[0] = (const Cx<T>*)pk[1].p;
+    a.bdiag[0] = (const Cx<T>*)pk[2].p;
+    a.fval[1] = (const Cx<T>*)pk[3].p;
+    a.fdiag[1] = (const Cx<T>*)pk[4].p;
+    a.bval[1] = (const Cx<T>*)pk[5].p;
+    a.bdiag[1] = nullptr;
     if (precond == FH_PC_JACOBI) a.dinv = (const Cx<T>*)(d ? S.jd64.p : S.jd32.p);
-    else a.dinv = (const Cx<T>*)(d ? S.dinv64.p : S.dinv32.p);
     return a;
 }
 
