@@ -11,9 +11,9 @@ A "step" is one full FEAST iteration (contour filter, B_Q, resize and
 B-bi-orthonormalization, Rayleigh-Ritz, residuals).  The fast path (complex
 FP32 inner solves + FP64 refinement) is timed over exactly K steps after W
 warm-up steps; the plain FP64 path is timed the same way for the comparison.
-The subspace is then iterated (untimed) to convergence and the returned
-eigenpairs are checked: eq:res <= 1e-10 and eigenvalues against the closed-form
-spectrum.
+A separate solve from the seeded start to eq:res <= 1e-10 gives the
+time-to-solution and the checked eigenpairs (count, residuals, eigenvalues
+against the closed-form spectrum).
 """
 from __future__ import annotations
 
@@ -37,8 +37,10 @@ def _problem():
 
 
 def _opts(fh, m0, precision, max_iter, eps, resume=0):
+    # GMRES(30), two cycles per solve, residual-form filter; the mixed path runs
+    # one complex-FP32 solve per filter followed by its FP64 residual check
     return fh.default_opts(m0, solver=fh.FH_SOLVER_BGMRES, precond=fh.FH_PC_ILU0, restart=30, max_restarts=2,
-                           inner_tol=1e-3, precision=precision, mixed_inner_tol=1e-3, max_refine=2,
+                           inner_tol=1e-3, precision=precision, mixed_inner_tol=1e-3, max_refine=1,
                            max_iter=max_iter, eps=eps, resume=resume)
 
 
@@ -66,12 +68,17 @@ def run_path(fh, torch, handle, prob, p, precision, steps, warmup, profile=False
     return dt, out, stats
 
 
-def validate(fh, torch, prob, p, out, precision):
-    """Continue (untimed) to convergence; check the eigenpairs."""
+def solve_to_convergence(fh, torch, prob, p, precision):
+    """Untimed for the metric: a fresh solve from the seeded start to eq:res <= 1e-10
+    (time-to-solution), then the returned eigenpairs are checked."""
     c = p.contour
-    Y, Yh, ritz = out["Y"].contiguous(), out["Yh"].contiguous(), out["ritz"]
-    fin = fh.feast(prob, c.center, c.a, c.ratio, c.angle, c.ne, Y, Yh,
-                   _opts(fh, Y.shape[1], precision, 60, 1e-10, resume=1), ritz0=ritz)
+    Y0 = torch.from_numpy(p.Y0).cuda()
+    Yh0 = torch.from_numpy(p.Yh0).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fin = fh.feast(prob, c.center, c.a, c.ratio, c.angle, c.ne, Y0, Yh0, _opts(fh, p.m0, precision, 60, 1e-10))
+    torch.cuda.synchronize()
+    tts = time.perf_counter() - t0
     alpha = abs(c.center) + max(c.a, c.ratio * c.a)
     exact = p.info["lam_sorted"][: p.info["m_in"]]
     lam = np.sort(fin["lam"].real)
@@ -83,7 +90,7 @@ def validate(fh, torch, prob, p, out, precision):
             "max_eq_res": max_res,
             # ||Ax - lam x||_1 / (||A||_1 ||x||_1) = eq:res * alpha / ||A||_1 for B = I
             "max_rel_residual": None if max_res is None else max_res * alpha / normA,
-            "max_dlam_over_alpha": dl, "extra_iters": int(fin["report"]["iters"])}
+            "max_dlam_over_alpha": dl, "iterations": int(fin["report"]["iters"]), "time_to_solution_s": tts}
 
 
 def cpu_baseline(p):
@@ -144,7 +151,7 @@ def main():
         print(f"[bench] fp64: {ms_64:.1f} ms/iteration", file=sys.stderr, flush=True)
     valid = None
     if not args.no_validate:
-        valid = validate(fh, torch, prob, p, out_mx, fh.FH_PREC_MIXED)
+        valid = solve_to_convergence(fh, torch, prob, p, fh.FH_PREC_MIXED)
         print(f"[bench] validation: {valid}", file=sys.stderr, flush=True)
 
     # dominant kernel (largest total time) -> achieved algorithmic bandwidth

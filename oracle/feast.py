@@ -17,7 +17,9 @@ Readings where the paper is silent (each also listed in the design doc):
   so that Wh^H B_U W = I.  Infinite or NaN Ritz values count as outside.
 * Convergence: the m = m_r - m_s smallest residuals among the m_r Ritz pairs
   inside the contour must all be below eps; on exit every inside pair whose
-  residual is below eps is returned (spurious pairs never converge).
+  residual is below eps is returned (spurious pairs never converge).  When the
+  test passes only because of spurious flags (m_s > 0), the exit waits for the
+  next iteration to pass as well with the same number of converged pairs.
 """
 from __future__ import annotations
 
@@ -217,6 +219,7 @@ def feast(A, B, cont: Contour, Y0, Yh0, eps=1e-12, max_iter=50, keep_history=Fal
     Y, Yh = np.array(Y0, dtype=np.complex128), np.array(Yh0, dtype=np.complex128)
     rho_prev = None
     prev_inside = None
+    prev_pass, prev_nconv = False, -1
     hist = []
     for it in range(1, max_iter + 1):
         rec = feast_iteration(A, B, z, w, cont, Y, Yh, rho_prev, factors, eps, counters, it)
@@ -226,6 +229,13 @@ def feast(A, B, cont: Contour, Y0, Yh0, eps=1e-12, max_iter=50, keep_history=Fal
         else:
             m_s = 0
         ok, m = converged(rec["res"], rec["inside"], m_s, eps)
+        # an exit that relies on spurious flags (m_s > 0) must be confirmed by
+        # the next iteration with the same number of converged inside pairs
+        nconv = int(np.count_nonzero(rec["inside"] & (rec["res"] < eps)))
+        passed = ok
+        if ok and m_s > 0 and not (prev_pass and prev_nconv == nconv):
+            ok = False
+        prev_pass, prev_nconv = passed, nconv
         rec["m_s"], rec["m"] = m_s, m
         if keep_history:
             hist.append(rec)

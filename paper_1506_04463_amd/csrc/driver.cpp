@@ -203,7 +203,8 @@ int feast(Ctx& c, Prob& p, const fh_contour& ct, const cplx* zin, const cplx* wi
     std::vector<double> res(m0in), hn(m0in), hd(m0in), hn2(m0in), hd2(m0in);
     int info = FH_NOT_CONVERGED, m_out = 0, it = 0, m_s = 0;
     std::vector<int> sel;
-    bool converged = false;
+    bool converged = false, prev_pass = false;
+    int prev_nconv = -1;
     for (it = 1; it <= o.max_iter; ++it) {
         auto t0 = std::chrono::steady_clock::now();
         // step 1: contour integration
@@ -288,6 +289,14 @@ int feast(Ctx& c, Prob& p, const fh_contour& ct, const cplx* zin, const cplx* wi
         else sel.clear();
         converged = m > 0;
         for (int i : sel) converged = converged && (res[i] < o.eps);
+        // an exit that relies on spurious flags must be confirmed by the next
+        // iteration with the same number of converged inside pairs
+        int nconv = 0;
+        for (int i = 0; i < mt; ++i) nconv += (inside[i] && res[i] < o.eps) ? 1 : 0;
+        const bool passed = converged;
+        if (converged && m_s > 0 && !(prev_pass && prev_nconv == nconv)) converged = false;
+        prev_pass = passed;
+        prev_nconv = nconv;
         mcur = mt;
         if (verbose()) {
             double worst = 0.0;

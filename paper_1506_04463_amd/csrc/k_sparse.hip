@@ -218,44 +218,94 @@ void pack_sweep_vals(hipStream_t st, const SweepDev& sw, int n, int ne, long nnz
 // issues the loads of up to P items (independent of the level's stores), then
 // stores them.
 // ---------------------------------------------------------------------------
+// everything an item needs that does not depend on the sweep's own results
+template <typename T, int KM>
+struct SwItem {
+    int row, cc, t;
+    int col[KM];
+    Cx<T> xin;
+};
+
+template <typename T, int P, int KM>
+__device__ __forceinline__ void load_items(const SweepDev& sw, int n, int m, int c0, int cw, const Cx<T>* __restrict__ val,
+                                           const Cx<T>* __restrict__ dval, const Cx<T>* In, int lev, int base,
+                                           SwItem<T, KM>* it) {
+    const int t0 = sw.lev_ptr[lev];
+    const int items = (sw.lev_ptr[lev + 1] - t0) * cw;
+    const int K = sw.K;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int e = base + threadIdx.x + 256 * q;
+        it[q].row = -1;
+        if (e < items) {
+            const int t = t0 + e / cw;
+            const int cc = c0 + e % cw;
+            const int row = sw.rows[t];
+            it[q].row = row;
+            it[q].cc = cc;
+            it[q].t = t;
+#pragma unroll
+            for (int k = 0; k < KM; ++k) it[q].col[k] = (k < K) ? sw.ell_col[(long)k * n + t] : -1;
+            it[q].xin = In[(long)row * m + cc];
+        }
+    }
+}
+
+// loads of the previous levels' results (and of the factor values, which are
+// independent) for all items first, then the stores
+template <typename T, int P, int KM, typename Between>
+__device__ __forceinline__ void solve_items(const SwItem<T, KM>* it, int n, int m, const Cx<T>* __restrict__ val,
+                                            const Cx<T>* __restrict__ dval, Cx<T>* Os, Between between) {
+    Cx<T> xs[P][KM], vs[P][KM], d[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        d[q] = cx(T(1), T(0));
+#pragma unroll
+        for (int k = 0; k < KM; ++k) { xs[q][k] = czero<T>(); vs[q][k] = czero<T>(); }
+        if (it[q].row >= 0) {
+#pragma unroll
+            for (int k = 0; k < KM; ++k)
+                if (it[q].col[k] >= 0) {
+                    vs[q][k] = val[(long)k * n + it[q].t];
+                    xs[q][k] = Os[(long)it[q].col[k] * m + it[q].cc];
+                }
+            if (dval) d[q] = dval[it[q].t];
+        }
+    }
+    between();
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        if (it[q].row >= 0) {
+            Cx<T> v = it[q].xin;
+#pragma unroll
+            for (int k = 0; k < KM; ++k) cfms(v, vs[q][k], xs[q][k]);
+            Os[(long)it[q].row * m + it[q].cc] = d[q] * v;
+        }
+    }
+}
+
 template <typename T, int P, int KM>
 __device__ __forceinline__ void sweep(const SweepDev& sw, int n, int m, int c0, int cw, const Cx<T>* __restrict__ val,
                                       const Cx<T>* __restrict__ dval, const Cx<T>* In, Cx<T>* Os) {
-    const int tid = threadIdx.x;
-    const int K = sw.K;
+    if (sw.nlev <= 0) return;
+    SwItem<T, KM> cur[P], nxt[P];
+    load_items<T, P, KM>(sw, n, m, c0, cw, val, dval, In, 0, 0, cur);
     for (int lev = 0; lev < sw.nlev; ++lev) {
-        const int t0 = sw.lev_ptr[lev];
-        const int items = (sw.lev_ptr[lev + 1] - t0) * cw;
-        for (int base = 0; base < items; base += 256 * P) {
-            Cx<T> acc[P];
-            int rowq[P], ccq[P];
-#pragma unroll
-            for (int q = 0; q < P; ++q) {
-                const int e = base + tid + 256 * q;
-                rowq[q] = -1;
-                if (e < items) {
-                    const int t = t0 + e / cw;
-                    const int cc = c0 + e % cw;
-                    const int row = sw.rows[t];
-                    Cx<T> v = In[(long)row * m + cc];
-#pragma unroll
-                    for (int k = 0; k < KM; ++k) {
-                        if (k < K) {
-                            const int col = sw.ell_col[(long)k * n + t];
-                            if (col >= 0) cfms(v, val[(long)k * n + t], Os[(long)col * m + cc]);
-                        }
-                    }
-                    if (dval) v = dval[t] * v;
-                    acc[q] = v;
-                    rowq[q] = row;
-                    ccq[q] = cc;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < P; ++q)
-                if (rowq[q] >= 0) Os[(long)rowq[q] * m + ccq[q]] = acc[q];
+        // the current level's loads are issued first, then the prefetch of the
+        // next level's independent data, so waiting on the former does not
+        // wait on the latter (loads retire in issue order)
+        solve_items<T, P, KM>(cur, n, m, val, dval, Os, [&] {
+            if (lev + 1 < sw.nlev) load_items<T, P, KM>(sw, n, m, c0, cw, val, dval, In, lev + 1, 0, nxt);
+        });
+        const int items = (sw.lev_ptr[lev + 1] - sw.lev_ptr[lev]) * cw;
+        for (int base = 256 * P; base < items; base += 256 * P) {     // levels wider than one batch
+            SwItem<T, KM> tmp[P];
+            load_items<T, P, KM>(sw, n, m, c0, cw, val, dval, In, lev, base, tmp);
+            solve_items<T, P, KM>(tmp, n, m, val, dval, Os, [] {});
         }
         __syncthreads();
+#pragma unroll
+        for (int q = 0; q < P; ++q) cur[q] = nxt[q];
     }
 }
 
@@ -285,10 +335,10 @@ void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<
     dim3 grid(ceil_div(a.m, a.cw), nsys);
     const int K = std::max(std::max(a.fwd[0].K, a.bwd[0].K), std::max(a.fwd[1].K, a.bwd[1].K));
     hipEvent_t ev = prof_begin(st);
-    if (K <= 2) k_ilu_apply<T, 8, 2><<<grid, 256, 0, st>>>(a, X, Out);
-    else if (K <= 4) k_ilu_apply<T, 8, 4><<<grid, 256, 0, st>>>(a, X, Out);
-    else if (K <= 8) k_ilu_apply<T, 4, 8><<<grid, 256, 0, st>>>(a, X, Out);
-    else if (K <= 32) k_ilu_apply<T, 2, 32><<<grid, 256, 0, st>>>(a, X, Out);
+    if (K <= 2) k_ilu_apply<T, 4, 2><<<grid, 256, 0, st>>>(a, X, Out);
+    else if (K <= 4) k_ilu_apply<T, 4, 4><<<grid, 256, 0, st>>>(a, X, Out);
+    else if (K <= 8) k_ilu_apply<T, 2, 8><<<grid, 256, 0, st>>>(a, X, Out);
+    else if (K <= 32) k_ilu_apply<T, 1, 32><<<grid, 256, 0, st>>>(a, X, Out);
     else throw Error(-1, "ILU(0) sweeps support at most 32 off-diagonal entries per triangular row");
     FH_LAUNCH_CHECK();
     if (ev) {
