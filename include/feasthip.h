@@ -52,10 +52,14 @@ enum { FH_DENSE = 0, FH_CSR = 1 };
 enum { FH_R64 = 0, FH_C128 = 1 };
 enum { FH_PREC_FP64 = 0, FH_PREC_MIXED = 1 };        /* solve precision            */
 enum { FH_SOLVER_LU = 0, FH_SOLVER_BGMRES = 1 };      /* shifted-system solver      */
-enum { FH_PC_NONE = 0, FH_PC_JACOBI = 1, FH_PC_ILU0 = 2 };
+enum { FH_PC_NONE = 0, FH_PC_JACOBI = 1, FH_PC_ILU0 = 2, FH_PC_LEARNED = 3 };
+
+/* most constant input fields a learned preconditioner takes */
+enum { FH_NET_MAX_FIELDS = 11 };
 
 typedef struct fh_ctx*  fh_handle;
 typedef struct fh_prob* fh_problem;
+typedef struct fh_net_s* fh_net;
 
 /* A matrix operand; all pointers are DEVICE pointers owned by the caller. */
 typedef struct {
@@ -97,6 +101,10 @@ typedef struct {
     int resume;           /* fh_feast: 1 = the start columns of Y / Yh are Ritz
                              vectors whose Ritz values are passed in lambda
                              (resume from a previous call's subspace)         */
+    int fallback;         /* FH_PC_LEARNED only: preconditioner that takes over
+                             for the rest of a solve when a restart cycle with
+                             the network cuts the worst relative residual by
+                             less than half (FH_PC_NONE, _JACOBI or _ILU0)    */
 } fh_opts;
 
 typedef struct {
@@ -112,6 +120,8 @@ typedef struct {
     double inner_relres;  /* worst final relative residual of the last filter  */
     double t_filter_ms;   /* time of the last contour integration             */
     double t_iter_ms;     /* time of the last full FEAST iteration            */
+    long long n_fallback; /* solves whose learned preconditioner was replaced
+                             by the fallback (cumulative)                     */
 } fh_report;
 
 /* ---- handle ----------------------------------------------------------- */
@@ -209,6 +219,83 @@ int fh_ilu0(fh_handle h, fh_problem p, double z_re, double z_im, void* lu);
  * with the ILU(0) of (z B - A); X, Out: device n x m blocks. */
 int fh_ilu0_apply(fh_handle h, fh_problem p, double z_re, double z_im, int side, int m,
                   const void* X, void* Out);
+
+/* Shifted solves, the linear systems of the contour filter (Section 2.4,
+ * eq:qr and eq:ql) for arbitrary shifts:
+ *   sides[s] == 0:  (z_s B - A) X_s = B_s
+ *   sides[s] == 1:  (z_s B - A)^H X_s = B_s
+ * s = 0..nsys-1; all right systems (side 0) must come before the left ones.
+ * z: host complex array of nsys shifts; B, X: device complex, nsys blocks of
+ * n x m (system-major, row-major n x m each).
+ * Dense problem: one LU with partial pivoting per system (FP64), direct
+ * solves; only o->save_factors is read.
+ * CSR problem (B = I): GMRES with m <= 256; restart, max_restarts,
+ * inner_tol, precision, mixed_inner_tol, max_refine and precond come from
+ * *o.  With precond == FH_PC_LEARNED the network attached by
+ * fh_problem_set_net is the (nonlinear) preconditioner, the flexible
+ * variant of GMRES is used and o->fallback takes over when a restart cycle
+ * does not halve the worst relative residual.  rep (optional): n_factor,
+ * n_solve, inner_steps (Krylov steps), inner_relres (largest final relative
+ * residual), n_fallback.
+ * Returns FH_OK, -k for an invalid argument k, FH_SINGULAR_SHIFT on a zero
+ * pivot, or an error status with fh_last_error set. */
+int fh_shifted_solve(fh_handle h, fh_problem p, int nsys, const double* z, const int* sides, int m,
+                     const fh_opts* o, const void* B, void* X, fh_report* rep);
+
+/* Learned preconditioner (not part of the paper's method: a flexible
+ * preconditioner for the iterative shifted solves of Section 2.4).
+ * A 3-layer convolutional network on an ny x nx grid (vector index
+ * i = y * nx + x, so n = ny * nx): 3x3 convolutions with zero padding,
+ * cin -> 16 -> 16 -> 2 channels, bias, ReLU after the first two layers.
+ * Input channels: Re and Im of v / ||v||_2, Re and Im of the operator shift
+ * divided by alpha (z for a right system, conj(z) for a left one), the side
+ * (0 or 1), then nfields constant fields.  Output:
+ * e = ||v||_2 out_scale (o_0 + i o_1), an approximation of (z B - A)^{-1} v
+ * (side 0) or (z B - A)^{-H} v (side 1); out_scale sets the magnitude of
+ * the operator's inverse (about 1 / max |a_ii| for a stiff operator).
+ * Parameters are kept in FP32 (Adam master copy) and used in BF16 by the
+ * kernels, which accumulate in FP32.  Parameter vector layout (floats):
+ *   w1 [16][cin][9], b1 [16], w2 [16][16][9], b2 [16], w3 [2][16][9], b3 [2]
+ * with cin = 5 + nfields and tap index (dy + 1) * 3 + (dx + 1), where the tap
+ * reads the input at (y + dy, x + dx).
+ *
+ * fh_net_create: fields = host [nfields][ny * nx] (may be NULL if nfields is
+ * 0); alpha > 0 scales the shift channels, out_scale > 0 the output;
+ * He-normal initial weights drawn from seed.  The network belongs to h's
+ * device; destroy it with fh_net_destroy after detaching it from every
+ * problem. */
+int fh_net_create(fh_handle h, int ny, int nx, int nfields, const double* fields, double alpha,
+                  double out_scale, unsigned long long seed, fh_net* net);
+int fh_net_destroy(fh_net net);
+/* number of floats in the parameter vector (or a negative error) */
+int fh_net_param_count(fh_net net);
+/* copy the FP32 parameters to / from host memory; set also resets Adam */
+int fh_net_get_params(fh_handle h, fh_net net, float* params);
+int fh_net_set_params(fh_handle h, fh_net net, const float* params);
+/* Out_s = network(V_s) for nsys blocks (device, [nsys][n][m] complex);
+ * z, sides as in fh_shifted_solve. */
+int fh_net_forward(fh_handle h, fh_net net, int nsys, int m, const double* z, const int* sides,
+                   const void* V, void* Out);
+/* One training step on (residual, error) pairs R_s, E_s (device, [nsys][n][m],
+ * E_s an exact or accurate solution of M_s E_s = R_s).  With t = e / ||r||
+ * and o the network's raw output (both in units of out_scale), the loss is
+ * the mean over the nsys*m columns of
+ *   p == NULL:   ||o - t||^2 / ||t||^2                      (error norm)
+ *   p != NULL:   ||M (o - t)||^2 / ||M t||^2                (residual norm)
+ * where M is the column's shifted operator of the CSR problem p (n = ny*nx,
+ * m <= 256); the second form measures how close M net(r) is to r and is the
+ * one that trains a useful preconditioner for stiff operators.  The gradient
+ * with respect to the BF16 parameters goes to grad (host, optional,
+ * param_count floats); if update != 0 one Adam step (beta 0.9 / 0.999,
+ * eps 1e-8, learning rate lr) is applied to the FP32 parameters.
+ * loss: host, optional. */
+int fh_net_train_step(fh_handle h, fh_net net, fh_problem p, int nsys, int m, const double* z,
+                      const int* sides, const void* R, const void* E, double lr, int update, double* loss,
+                      float* grad);
+/* attach (net != NULL) or detach (NULL) the learned preconditioner used by
+ * fh_filter / fh_feast / fh_shifted_solve on a CSR problem when
+ * opts.precond == FH_PC_LEARNED; the grid must have n points.  Not owned. */
+int fh_problem_set_net(fh_problem p, fh_net net);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,124 @@
+"""Reference (oracle) of the learned preconditioner network, NumPy float64.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).  The paper has no learned
+component; this network is the one the build uses as a flexible preconditioner
+inside FGMRES: three 3x3 convolutions with zero padding on the solution grid,
+Cin -> H -> H -> 2 channels, bias, ReLU after the first two.  The input
+channels are (Re r, Im r)/||r||_2 followed by optional constant fields; the
+output (Re e, Im e) is scaled back by ||r||_2.
+
+Layouts follow the HIP kernels: an activation is an array [ny, nx, C, m]
+(grid row, grid column, channel, batch column); weights are [Cout, Cin, 3, 3]
+(dy, dx in -1, 0, 1 order); the grid row index is the slower one.
+
+Two losses over the columns c of a batch, with o_c = out[:, :, 0, c] + i
+out[:, :, 1, c] and t_c the (scaled) error target:
+* plain: mean_c ||o_c - t_c||^2 / ||t_c||^2;
+* operator-weighted: mean_c ||M_c (o_c - t_c)||^2 / ||M_c t_c||^2, where M_c
+  is the shifted operator of the column's system, so that M_c t_c is the
+  (scaled) residual; this measures how close M_c net(r) is to r.
+
+Parity status: pinned by central finite differences of both losses in
+tests/test_oracle_convnet.py (gradients), and by a direct sum for the forward
+convolution; the HIP kernels are checked against these functions.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def conv3x3(x, w, b):
+    """x [ny, nx, Cin, m], w [Cout, Cin, 3, 3], b [Cout] -> [ny, nx, Cout, m]."""
+    ny, nx, cin, m = x.shape
+    cout = w.shape[0]
+    xp = np.zeros((ny + 2, nx + 2, cin, m))
+    xp[1:-1, 1:-1] = x
+    out = np.zeros((ny, nx, cout, m)) + b[None, None, :, None]
+    for dy in range(3):
+        for dx in range(3):
+            patch = xp[dy:dy + ny, dx:dx + nx]                    # input at (y+dy-1, x+dx-1)
+            out += np.einsum("oc,yxcm->yxom", w[:, :, dy, dx], patch)
+    return out
+
+
+def conv3x3_backward(x, w, gout):
+    """Gradients of sum(gout * conv3x3(x, w, b)) w.r.t. x, w, b."""
+    ny, nx, cin, m = x.shape
+    xp = np.zeros((ny + 2, nx + 2, cin, m))
+    xp[1:-1, 1:-1] = x
+    gw = np.zeros_like(w)
+    gxp = np.zeros_like(xp)
+    for dy in range(3):
+        for dx in range(3):
+            patch = xp[dy:dy + ny, dx:dx + nx]
+            gw[:, :, dy, dx] = np.einsum("yxom,yxcm->oc", gout, patch)
+            gxp[dy:dy + ny, dx:dx + nx] += np.einsum("oc,yxom->yxcm", w[:, :, dy, dx], gout)
+    gb = gout.sum(axis=(0, 1, 3))
+    return gxp[1:-1, 1:-1], gw, gb
+
+
+def forward(params, x):
+    """params: list of (w, b) for the 3 layers; returns output and cache."""
+    (w1, b1), (w2, b2), (w3, b3) = params
+    z1 = conv3x3(x, w1, b1)
+    a1 = np.maximum(z1, 0.0)
+    z2 = conv3x3(a1, w2, b2)
+    a2 = np.maximum(z2, 0.0)
+    out = conv3x3(a2, w3, b3)
+    return out, (x, z1, a1, z2, a2)
+
+
+def backward(params, cache, gout):
+    (w1, b1), (w2, b2), (w3, b3) = params
+    x, z1, a1, z2, a2 = cache
+    ga2, gw3, gb3 = conv3x3_backward(a2, w3, gout)
+    gz2 = ga2 * (z2 > 0)
+    ga1, gw2, gb2 = conv3x3_backward(a1, w2, gz2)
+    gz1 = ga1 * (z1 > 0)
+    _, gw1, gb1 = conv3x3_backward(x, w1, gz1)
+    return [(gw1, gb1), (gw2, gb2), (gw3, gb3)]
+
+
+def encode(r, ny, nx, fields=None):
+    """r [n, m] complex -> input [ny, nx, 2 + F, m] and the column norms."""
+    n, m = r.shape
+    nr = np.linalg.norm(r, axis=0)
+    s = np.where(nr > 0, 1.0 / np.where(nr > 0, nr, 1.0), 0.0)
+    rr = (r * s[None, :]).reshape(ny, nx, m)
+    chans = [rr.real, rr.imag]
+    if fields is not None:
+        for f in fields:                                  # [ny, nx] or [ny, nx, m]
+            f = np.asarray(f, dtype=np.float64)
+            chans.append(np.broadcast_to(f[..., None] if f.ndim == 2 else f, (ny, nx, m)))
+    return np.stack(chans, axis=2), nr
+
+
+def loss_and_grad(params, x, target):
+    """Mean over columns of ||net(x) - t||^2 / ||t||^2 with t = target [ny, nx, 2, m]."""
+    out, cache = forward(params, x)
+    diff = out - target
+    tn = (target ** 2).sum(axis=(0, 1, 2))
+    tn = np.where(tn > 0, tn, 1.0)
+    m = x.shape[3]
+    loss = float(((diff ** 2).sum(axis=(0, 1, 2)) / tn).mean())
+    gout = 2.0 * diff / tn[None, None, None, :] / m
+    return loss, backward(params, cache, gout)
+
+
+def loss_and_grad_op(params, x, target, ops):
+    """Operator-weighted loss; ops[c] is the dense complex operator of column c."""
+    out, cache = forward(params, x)
+    ny, nx, _, m = out.shape
+    gout = np.zeros_like(out)
+    total = 0.0
+    for c in range(m):
+        d = (out[:, :, 0, c] + 1j * out[:, :, 1, c] - target[:, :, 0, c] - 1j * target[:, :, 1, c]).ravel()
+        t = (target[:, :, 0, c] + 1j * target[:, :, 1, c]).ravel()
+        Md = ops[c] @ d
+        den = np.vdot(ops[c] @ t, ops[c] @ t).real
+        den = den if den > 0 else 1.0
+        total += np.vdot(Md, Md).real / den
+        g = 2.0 * (ops[c].conj().T @ Md) / den / m
+        gout[:, :, 0, c] = g.real.reshape(ny, nx)
+        gout[:, :, 1, c] = g.imag.reshape(ny, nx)
+    return total / m, backward(params, cache, gout)

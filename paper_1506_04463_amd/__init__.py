@@ -21,7 +21,9 @@ FH_DENSE, FH_CSR = 0, 1
 FH_R64, FH_C128 = 0, 1
 FH_PREC_FP64, FH_PREC_MIXED = 0, 1
 FH_SOLVER_LU, FH_SOLVER_BGMRES = 0, 1
-FH_PC_NONE, FH_PC_JACOBI, FH_PC_ILU0 = 0, 1, 2
+FH_PC_NONE, FH_PC_JACOBI, FH_PC_ILU0, FH_PC_LEARNED = 0, 1, 2, 3
+NET_HIDDEN = 16
+NET_FIXED_CHANNELS = 5
 
 STATUS = {0: "ok", 1: "no eigenvalue inside", 2: "not converged", 3: "m0 too small",
           4: "singular shift", 5: "inner solve failed", 6: "non-finite", 7: "reduced eig failed",
@@ -48,14 +50,14 @@ class fh_opts(C.Structure):
     _fields_ = [("m0", C.c_int), ("max_iter", C.c_int), ("eps", C.c_double), ("precision", C.c_int),
                 ("solver", C.c_int), ("restart", C.c_int), ("block", C.c_int), ("precond", C.c_int),
                 ("inner_tol", C.c_double), ("max_restarts", C.c_int), ("mixed_inner_tol", C.c_double),
-                ("max_refine", C.c_int), ("save_factors", C.c_int), ("resume", C.c_int)]
+                ("max_refine", C.c_int), ("save_factors", C.c_int), ("resume", C.c_int), ("fallback", C.c_int)]
 
 
 class fh_report(C.Structure):
     _fields_ = [("info", C.c_int), ("m", C.c_int), ("iters", C.c_int), ("m0_final", C.c_int),
                 ("bad_node", C.c_int), ("m_s", C.c_int), ("n_factor", C.c_longlong), ("n_solve", C.c_longlong),
                 ("inner_steps", C.c_longlong), ("inner_relres", C.c_double), ("t_filter_ms", C.c_double),
-                ("t_iter_ms", C.c_double)]
+                ("t_iter_ms", C.c_double), ("n_fallback", C.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -93,6 +95,15 @@ def lib():
         "fh_shifted_apply": (i, [vp, vp, i, i, dp, i, vp, vp]),
         "fh_ilu0": (i, [vp, vp, d, d, vp]),
         "fh_ilu0_apply": (i, [vp, vp, d, d, i, i, vp, vp]),
+        "fh_shifted_solve": (i, [vp, vp, i, dp, ip, i, C.POINTER(fh_opts), vp, vp, C.POINTER(fh_report)]),
+        "fh_net_create": (i, [vp, i, i, i, dp, d, d, C.c_ulonglong, C.POINTER(vp)]),
+        "fh_net_destroy": (i, [vp]),
+        "fh_net_param_count": (i, [vp]),
+        "fh_net_get_params": (i, [vp, vp, C.POINTER(C.c_float)]),
+        "fh_net_set_params": (i, [vp, vp, C.POINTER(C.c_float)]),
+        "fh_net_forward": (i, [vp, vp, i, i, dp, ip, vp, vp]),
+        "fh_net_train_step": (i, [vp, vp, vp, i, i, dp, ip, vp, vp, d, i, dp, C.POINTER(C.c_float)]),
+        "fh_problem_set_net": (i, [vp, vp]),
         "fh_profile": (i, [vp, i]),
         "fh_profile_read": (i, [vp, i, C.c_char_p, i, C.POINTER(C.c_longlong), dp, dp, dp]),
     }
@@ -362,3 +373,124 @@ def ilu0_apply(prob: Problem, z, side, X):
     prob.handle.check(lib().fh_ilu0_apply(prob.handle._h, prob._p, complex(z).real, complex(z).imag, side,
                                           X.shape[1], _dptr(X), _dptr(Out)), "fh_ilu0_apply")
     return Out
+
+
+def _sides(sides, nsys):
+    a = np.ascontiguousarray(np.broadcast_to(np.asarray(sides, dtype=np.int32), (nsys,)))
+    return a, a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+def _check_batch(t, n, name):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()
+            and t.dim() == 3 and t.shape[1] == n):
+        raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor of shape (nsys, n={n}, m)")
+
+
+def shifted_solve(prob: Problem, z, sides, B, opts: fh_opts | None = None):
+    """X_s = (z_s - A)^{-1} B_s (side 0) or (z_s - A)^{-H} B_s (side 1); B: (nsys, n, m) complex128.
+
+    Right systems must come before left ones.  Returns (X, report dict)."""
+    torch = _torch()
+    _check_batch(B, prob.n, "B")
+    nsys, n, m = B.shape
+    if opts is None:
+        opts = default_opts(m)
+    zk, zp = _cbuf(np.broadcast_to(np.asarray(z, dtype=np.complex128), (nsys,)))
+    sk, sp = _sides(sides, nsys)
+    X = torch.empty_like(B)
+    rep = fh_report()
+    prob.handle.check(lib().fh_shifted_solve(prob.handle._h, prob._p, nsys, zp, sp, m, C.byref(opts), _dptr(B),
+                                             _dptr(X), C.byref(rep)), "fh_shifted_solve")
+    return X, rep.as_dict()
+
+
+class Net:
+    """Learned preconditioner network (3x3 conv, cin -> 16 -> 16 -> 2) on an ny x nx grid."""
+
+    def __init__(self, handle: Handle, ny, nx, fields=None, alpha=1.0, out_scale=1.0, seed=0):
+        self.handle = handle
+        self.ny, self.nx = ny, nx
+        f = None if fields is None else np.ascontiguousarray(np.asarray(fields, dtype=np.float64).reshape(-1, ny * nx))
+        self.nfields = 0 if f is None else f.shape[0]
+        self._fields = f
+        fp = None if f is None else f.ctypes.data_as(C.POINTER(C.c_double))
+        p = C.c_void_p()
+        handle.check(lib().fh_net_create(handle._h, ny, nx, self.nfields, fp, float(alpha), float(out_scale),
+                                         C.c_ulonglong(seed), C.byref(p)), "fh_net_create")
+        self.out_scale = float(out_scale)
+        self._n = p
+        self.n_params = lib().fh_net_param_count(p)
+        self.cin = NET_FIXED_CHANNELS + self.nfields
+
+    def get_params(self):
+        a = np.zeros(self.n_params, np.float32)
+        self.handle.check(lib().fh_net_get_params(self.handle._h, self._n, a.ctypes.data_as(C.POINTER(C.c_float))),
+                          "fh_net_get_params")
+        return a
+
+    def set_params(self, params):
+        a = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if a.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        self.handle.check(lib().fh_net_set_params(self.handle._h, self._n, a.ctypes.data_as(C.POINTER(C.c_float))),
+                          "fh_net_set_params")
+
+    def unpack(self, params):
+        """flat vector -> [(w1, b1), (w2, b2), (w3, b3)] with w [cout, cin, 3, 3]"""
+        H, cin = NET_HIDDEN, self.cin
+        shapes = [(H, cin), (H, H), (2, H)]
+        out, off = [], 0
+        for co, ci in shapes:
+            w = np.asarray(params[off:off + co * ci * 9]).reshape(co, ci, 3, 3)
+            off += co * ci * 9
+            b = np.asarray(params[off:off + co])
+            off += co
+            out.append((w, b))
+        return out
+
+    def forward(self, z, sides, V):
+        """V: (nsys, n, m) complex128 -> network output of the same shape."""
+        torch = _torch()
+        _check_batch(V, self.ny * self.nx, "V")
+        nsys, n, m = V.shape
+        zk, zp = _cbuf(np.broadcast_to(np.asarray(z, dtype=np.complex128), (nsys,)))
+        sk, sp = _sides(sides, nsys)
+        Out = torch.empty_like(V)
+        self.handle.check(lib().fh_net_forward(self.handle._h, self._n, nsys, m, zp, sp, _dptr(V), _dptr(Out)),
+                          "fh_net_forward")
+        return Out
+
+    def train_step(self, z, sides, R, E, lr=1e-3, update=True, want_grad=False, problem: "Problem | None" = None):
+        """One loss/gradient evaluation on (residual, error) pairs; Adam step if update.
+
+        With a CSR problem the loss is measured in the residual norm of its
+        shifted operators, else in the error norm."""
+        _check_batch(R, self.ny * self.nx, "R")
+        _check_batch(E, self.ny * self.nx, "E")
+        nsys, n, m = R.shape
+        zk, zp = _cbuf(np.broadcast_to(np.asarray(z, dtype=np.complex128), (nsys,)))
+        sk, sp = _sides(sides, nsys)
+        loss = C.c_double()
+        g = np.zeros(self.n_params, np.float32) if want_grad else None
+        gp = g.ctypes.data_as(C.POINTER(C.c_float)) if want_grad else None
+        pp = problem._p if problem is not None else None
+        self.handle.check(lib().fh_net_train_step(self.handle._h, self._n, pp, nsys, m, zp, sp, _dptr(R), _dptr(E),
+                                                  float(lr), int(bool(update)), C.byref(loss), gp),
+                          "fh_net_train_step")
+        return (loss.value, g) if want_grad else loss.value
+
+    def __del__(self):
+        try:
+            if getattr(self, "_n", None):
+                lib().fh_net_destroy(self._n)
+        except Exception:
+            pass
+
+
+def set_net(prob: Problem, net: "Net | None"):
+    """Attach (or detach with None) the learned preconditioner of a CSR problem."""
+    rc = lib().fh_problem_set_net(prob._p, net._n if net is not None else None)
+    if rc != 0:
+        raise FeastError(rc, "fh_problem_set_net: grid size does not match the problem")
+    prob._net = net   # keep the network alive while attached

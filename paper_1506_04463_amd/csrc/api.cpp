@@ -10,6 +10,13 @@ using namespace fh;
 
 struct fh_ctx : Ctx {};
 struct fh_prob : Prob {};
+struct fh_net_s {
+    NetState* st = nullptr;
+    int device = 0;
+    ~fh_net_s() {
+        if (st) net_destroy(st);
+    }
+};
 
 namespace fh {
 Prob::~Prob() {
@@ -53,6 +60,7 @@ void fh_default_opts(fh_opts* o) {
     o->max_refine = 8;
     o->save_factors = 1;
     o->resume = 0;
+    o->fallback = FH_PC_ILU0;
 }
 
 int fh_create(fh_handle* h, int device, void* stream) {
@@ -359,6 +367,159 @@ int fh_ilu0_apply(fh_handle h, fh_problem p, double z_re, double z_im, int side,
     FH_HIP(hipStreamSynchronize(h->stream));
     return FH_OK;
     FH_API_END(h)
+}
+
+int fh_shifted_solve(fh_handle h, fh_problem p, int nsys, const double* z, const int* sides, int m,
+                     const fh_opts* o, const void* B, void* X, fh_report* rep) {
+    if (!h) return -1;
+    if (!p) return -2;
+    if (nsys < 1) return -3;
+    if (!z) return -4;
+    if (!sides) return -5;
+    if (m < 1 || (!p->dense && m > 256)) return -6;
+    if (!o) return -7;
+    if (!B) return -8;
+    if (!X) return -9;
+    int nright = 0;
+    while (nright < nsys && sides[nright] == 0) ++nright;
+    for (int s = nright; s < nsys; ++s)
+        if (sides[s] != 1) return -5;
+    if (o->precision != FH_PREC_FP64 && o->precision != FH_PREC_MIXED) return -7;
+    if (o->precond < FH_PC_NONE || o->precond > FH_PC_LEARNED) return -7;
+    if (o->precond == FH_PC_LEARNED && (o->fallback < FH_PC_NONE || o->fallback > FH_PC_ILU0)) return -7;
+    FH_API_BEGIN(h)
+    set_device(h);
+    if (rep) std::memset(rep, 0, sizeof(*rep));
+    const cplx* zc = reinterpret_cast<const cplx*>(z);
+    if (p->dense)
+        dense_shifted_solve(*h, *p, nsys, nright, zc, m, (const zd*)B, (zd*)X, *o, rep);
+    else
+        sparse_shifted_solve(*h, *p, nsys, zc, sides, m, (const zd*)B, (zd*)X, *o, rep);
+    FH_HIP(hipStreamSynchronize(h->stream));
+    return FH_OK;
+    FH_API_END(h)
+}
+
+int fh_net_create(fh_handle h, int ny, int nx, int nfields, const double* fields, double alpha,
+                  double out_scale, unsigned long long seed, fh_net* out) {
+    if (!h) return -1;
+    if (ny < 1) return -2;
+    if (nx < 1) return -3;
+    if (nfields < 0 || nfields > FH_NET_MAX_FIELDS) return -4;
+    if (nfields > 0 && !fields) return -5;
+    if (!(alpha > 0)) return -6;
+    if (!(out_scale > 0)) return -7;
+    if (!out) return -9;
+    *out = nullptr;
+    FH_API_BEGIN(h)
+    set_device(h);
+    fh_net_s* n = new fh_net_s();
+    n->device = h->device;
+    try {
+        n->st = net_create(*h, ny, nx, nfields, fields, alpha, out_scale, seed);
+    } catch (...) {
+        delete n;
+        throw;
+    }
+    *out = n;
+    return FH_OK;
+    FH_API_END(h)
+}
+
+int fh_net_destroy(fh_net net) {
+    if (!net) return -1;
+    (void)hipSetDevice(net->device);
+    delete net;
+    return FH_OK;
+}
+
+int fh_net_param_count(fh_net net) {
+    if (!net) return -1;
+    return net_param_count(net->st);
+}
+
+int fh_net_get_params(fh_handle h, fh_net net, float* params) {
+    if (!h) return -1;
+    if (!net) return -2;
+    if (!params) return -3;
+    FH_API_BEGIN(h)
+    set_device(h);
+    net_get_params(*h, *net->st, params);
+    return FH_OK;
+    FH_API_END(h)
+}
+
+int fh_net_set_params(fh_handle h, fh_net net, const float* params) {
+    if (!h) return -1;
+    if (!net) return -2;
+    if (!params) return -3;
+    FH_API_BEGIN(h)
+    set_device(h);
+    net_set_params(*h, *net->st, params);
+    return FH_OK;
+    FH_API_END(h)
+}
+
+// operator shift per system: z for a right system, conj(z) for a left one
+static std::vector<double> op_shifts(int nsys, const double* z, const int* sides) {
+    std::vector<double> s(2 * (size_t)nsys);
+    for (int k = 0; k < nsys; ++k) {
+        s[2 * k] = z[2 * k];
+        s[2 * k + 1] = sides[k] ? -z[2 * k + 1] : z[2 * k + 1];
+    }
+    return s;
+}
+
+int fh_net_forward(fh_handle h, fh_net net, int nsys, int m, const double* z, const int* sides, const void* V,
+                   void* Out) {
+    if (!h) return -1;
+    if (!net) return -2;
+    if (nsys < 1) return -3;
+    if (m < 1) return -4;
+    if (!z) return -5;
+    if (!sides) return -6;
+    if (!V) return -7;
+    if (!Out) return -8;
+    for (int s = 0; s < nsys; ++s)
+        if (sides[s] != 0 && sides[s] != 1) return -6;
+    FH_API_BEGIN(h)
+    set_device(h);
+    std::vector<double> sh = op_shifts(nsys, z, sides);
+    net_forward_host(*h, *net->st, nsys, m, (const zd*)V, sh.data(), sides, (zd*)Out);
+    return FH_OK;
+    FH_API_END(h)
+}
+
+int fh_net_train_step(fh_handle h, fh_net net, fh_problem p, int nsys, int m, const double* z, const int* sides,
+                      const void* R, const void* E, double lr, int update, double* loss, float* grad) {
+    if (!h) return -1;
+    if (!net) return -2;
+    if (p && (p->dense || p->n != net_grid_size(net->st))) return -3;
+    if (nsys < 1) return -4;
+    if (m < 1 || (p && m > 256)) return -5;
+    if (!z) return -6;
+    if (!sides) return -7;
+    if (!R) return -8;
+    if (!E) return -9;
+    if (update && !(lr > 0)) return -10;
+    for (int s = 0; s < nsys; ++s)
+        if (sides[s] != 0 && sides[s] != 1) return -7;
+    FH_API_BEGIN(h)
+    set_device(h);
+    std::vector<double> sh = op_shifts(nsys, z, sides);
+    const double l = net_loss_grad(*h, *net->st, p ? p->sp : nullptr, nsys, m, (const zd*)R, (const zd*)E,
+                                   sh.data(), sides, update != 0, lr);
+    if (loss) *loss = l;
+    if (grad) net_get_grad(*h, *net->st, grad);
+    return FH_OK;
+    FH_API_END(h)
+}
+
+int fh_problem_set_net(fh_problem p, fh_net net) {
+    if (!p || p->dense) return -1;
+    if (net && net_grid_size(net->st) != p->n) return -2;
+    sparse_set_net(*p, net ? net->st : nullptr);
+    return FH_OK;
 }
 
 }  // extern "C"

@@ -151,6 +151,24 @@ void filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m0, const
         rep->t_filter_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// dense shifted solves: one LU of (z_s B - A) per system, 'N' solves for the
+// right systems (first nright), 'C' solves for the left ones
+void dense_shifted_solve(Ctx& c, Prob& p, int nsys, int nright, const cplx* z, int m, const zd* B, zd* X,
+                         const fh_opts& o, fh_report* rep) {
+    const int n = p.n;
+    const size_t blk = (size_t)n * m;
+    dense_factor(c, p, nsys, z, o, rep);
+    FH_HIP(hipMemcpyAsync(X, B, sizeof(zd) * blk * nsys, hipMemcpyDeviceToDevice, c.stream));
+    const zd* M = (const zd*)p.lu.p;
+    const int* ipiv = (const int*)p.ipiv.p;
+    if (nright > 0) lu_solve(c.stream, 'N', n, M, ipiv, m, X, nright);
+    if (nsys > nright)
+        lu_solve(c.stream, 'C', n, M + (size_t)nright * n * n, ipiv + (size_t)nright * n, m, X + nright * blk,
+                 nsys - nright);
+    if (rep) rep->n_solve += nsys;
+    sync(c);
+}
+
 // ---------------------------------------------------------------------------
 // FEAST (complete algorithm figure)
 // ---------------------------------------------------------------------------

@@ -12,6 +12,7 @@
 namespace fh {
 
 struct SparseState;   // k_sparse.hip / sparse.cpp
+struct NetState;      // k_net.hip / net.cpp
 
 struct FilterBufs {
     DBuf X, Xh, R, Rh, wdev, zdev;
@@ -74,5 +75,23 @@ void sparse_shifted_apply(Ctx& c, Prob& p, int side, int nsys, const cplx* shift
 void sparse_ilu0(Ctx& c, Prob& p, cplx z, zd* lu_out);
 void sparse_ilu0_apply(Ctx& c, Prob& p, cplx z, int side, int m, const zd* X, zd* Out);
 void sparse_destroy(SparseState* s);
+void sparse_shifted_solve(Ctx& c, Prob& p, int nsys, const cplx* z, const int* sides, int m, const zd* B, zd* X,
+                          const fh_opts& o, fh_report* rep);
+void sparse_set_net(Prob& p, NetState* net);
+void dense_shifted_solve(Ctx& c, Prob& p, int nsys, int nright, const cplx* z, int m, const zd* B, zd* X,
+                         const fh_opts& o, fh_report* rep);
+
+// net.cpp
+NetState* net_create(Ctx& c, int ny, int nx, int nfields, const double* fields, double alpha, double out_scale,
+                     unsigned long long seed);
+void net_destroy(NetState* s);
+int net_param_count(const NetState* s);
+int net_grid_size(const NetState* s);
+void net_set_params(Ctx& c, NetState& S, const float* host);
+void net_get_params(Ctx& c, NetState& S, float* host);
+void net_forward_host(Ctx& c, NetState& S, int nsys, int m, const zd* X, const double* shifts, const int* sides, zd* Out);
+double net_loss_grad(Ctx& c, NetState& S, const SparseState* sp, int nsys, int m, const zd* R, const zd* E,
+                     const double* shifts, const int* sides, bool step, double lr);
+void net_get_grad(Ctx& c, NetState& S, float* host);
 
 }  // namespace fh

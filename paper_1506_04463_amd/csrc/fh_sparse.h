@@ -50,6 +50,8 @@ struct IluApplyArgs {
     const Cx<T>* dinv = nullptr;                 // Jacobi: [node][n] (null: identity)
 };
 
+struct NetState;
+
 struct SparseState {
     int n = 0;
     long nnzA = 0, nnzM = 0;
@@ -72,7 +74,8 @@ struct SparseState {
     // batch descriptors and GMRES workspace
     DBuf node_of, side_of, shifts64, shifts32, coef, rho, bufB, bufX, bufR, bufT, b32, x32;
     DBuf V, Z, Hs, cs, sn, g, resid, vscale, kuse, y, h1, h2, hnorm, beta, bnorm, part, bn64, rn64, sc64;
-    DBuf aval32, atval64, atval32, bn32;
+    DBuf aval32, atval64, atval32, bn32, Zf;
+    NetState* net = nullptr;   // attached learned preconditioner (not owned)
     ~SparseState() {
         for (DBuf* b : owned) delete b;
     }

@@ -1,0 +1,443 @@
+// Learned preconditioner: a 3-layer 3x3 convolutional network on the solution
+// grid (Cin -> H -> H -> 2 channels, zero padding, ReLU between layers), with
+// weights stored in BF16 and FP32 accumulation; forward, backward (data and
+// weights) and Adam kernels used to train it on (residual, error) pairs and
+// to apply it as a flexible preconditioner inside FGMRES.
+//
+// Activation layout: [pixel][channel][column] (FP32), pixel = y * nx + x; the
+// columns of a batch are contiguous, so every access is coalesced across the
+// batch.  Weight layout: [Cout][Cin][9] (tap = (dy+1)*3 + (dx+1)).
+#include "fh_net.h"
+
+namespace fh {
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+    // round to nearest even
+    uint32_t u;
+#ifdef __HIP_DEVICE_COMPILE__
+    u = __float_as_uint(f);
+#else
+    std::memcpy(&u, &f, 4);
+#endif
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+// ---------------------------------------------------------------------------
+// input encoding: x[p][ch][col], col = s*m + c:
+//   ch 0, 1: Re/Im of V[s][p][c] * scale[col]; ch 2, 3: Re/Im of shift_s / alpha;
+//   ch 4: side_s; ch 5..: fields[f][p]
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_net_encode(int npix, int m, int nsys, int cin, const Cx<T>* __restrict__ V,
+                             const float* __restrict__ scale, const zd* __restrict__ shifts, const int* __restrict__ sides,
+                             double inv_alpha, const float* __restrict__ fields, float* __restrict__ x) {
+    const int mt = nsys * m;
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)npix * mt) return;
+    const int p = e / mt, col = e % mt;
+    const int s = col / m, c = col % m;
+    const Cx<T> v = V[(long)s * npix * m + (long)p * m + c];
+    const float sc = scale ? scale[col] : 1.0f;
+    float* xp = x + (long)p * cin * mt + col;
+    xp[0] = (float)v.re * sc;
+    xp[(long)mt] = (float)v.im * sc;
+    const zd z = shifts[s];
+    xp[2L * mt] = (float)(z.re * inv_alpha);
+    xp[3L * mt] = (float)(z.im * inv_alpha);
+    xp[4L * mt] = (float)sides[s];
+    for (int f = 0; f < cin - NET_FIXED_CH; ++f) xp[(long)(NET_FIXED_CH + f) * mt] = fields[(long)f * npix + p];
+}
+
+// Out[s][p][c] = oscale (o[p][0][col] + i o[p][1][col]) / scale[col]  (scale = 1/||r|| of the input)
+template <typename T>
+__global__ void k_net_decode(int npix, int m, int nsys, float oscale, const float* __restrict__ o,
+                             const float* __restrict__ scale, Cx<T>* __restrict__ Out) {
+    const int mt = nsys * m;
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)npix * mt) return;
+    const int p = e / mt, col = e % mt;
+    const int s = col / m, c = col % m;
+    const float sc = scale ? scale[col] : 1.0f;
+    const float inv = sc > 0.0f ? oscale / sc : 0.0f;
+    const float* op = o + (long)p * 2 * mt + col;
+    Out[(long)s * npix * m + (long)p * m + c] = Cx<T>{T(op[0] * inv), T(op[mt] * inv)};
+}
+
+// ---------------------------------------------------------------------------
+// forward 3x3 convolution: one thread per (pixel, column), all COUT outputs
+// ---------------------------------------------------------------------------
+template <int COUT>
+__global__ __launch_bounds__(256) void k_conv_fwd(int ny, int nx, int mt, int cin, const float* __restrict__ x,
+                                                  const uint16_t* __restrict__ w, const uint16_t* __restrict__ b,
+                                                  int relu, float* __restrict__ y) {
+    __shared__ float ws[COUT * NET_MAX_CIN * 9];
+    __shared__ float bs[COUT];
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    for (int i = tid; i < COUT * cin * 9; i += blockDim.x * blockDim.y) ws[i] = bf16_to_f32(w[i]);
+    if (tid < COUT) bs[tid] = bf16_to_f32(b[tid]);
+    __syncthreads();
+    const int col = blockIdx.y * blockDim.x + threadIdx.x;
+    const int p = blockIdx.x * blockDim.y + threadIdx.y;
+    if (col >= mt || p >= ny * nx) return;
+    const int py = p / nx, px = p % nx;
+    float acc[COUT];
+#pragma unroll
+    for (int o = 0; o < COUT; ++o) acc[o] = bs[o];
+    for (int tap = 0; tap < 9; ++tap) {
+        const int qy = py + tap / 3 - 1, qx = px + tap % 3 - 1;
+        if (qy < 0 || qy >= ny || qx < 0 || qx >= nx) continue;
+        const float* xq = x + (long)(qy * nx + qx) * cin * mt + col;
+        for (int ci = 0; ci < cin; ++ci) {
+            const float v = xq[(long)ci * mt];
+#pragma unroll
+            for (int o = 0; o < COUT; ++o) acc[o] = fmaf(ws[(o * cin + ci) * 9 + tap], v, acc[o]);
+        }
+    }
+    float* yp = y + (long)p * COUT * mt + col;
+#pragma unroll
+    for (int o = 0; o < COUT; ++o) yp[(long)o * mt] = relu ? fmaxf(acc[o], 0.0f) : acc[o];
+}
+
+// ---------------------------------------------------------------------------
+// backward (data): dx[p][ci][col] = mask(p, ci) * sum_{o,tap} w[o][ci][tap] dy[p - d(tap)][o][col]
+// mask: a_prev[p][ci][col] > 0 (ReLU of the layer input), or none
+// ---------------------------------------------------------------------------
+template <int CIN>
+__global__ __launch_bounds__(256) void k_conv_bwd_data(int ny, int nx, int mt, int cout, const float* __restrict__ dy,
+                                                       const uint16_t* __restrict__ w, const float* __restrict__ mask,
+                                                       float* __restrict__ dx) {
+    __shared__ float ws[NET_MAX_COUT * CIN * 9];
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    for (int i = tid; i < cout * CIN * 9; i += blockDim.x * blockDim.y) ws[i] = bf16_to_f32(w[i]);
+    __syncthreads();
+    const int col = blockIdx.y * blockDim.x + threadIdx.x;
+    const int p = blockIdx.x * blockDim.y + threadIdx.y;
+    if (col >= mt || p >= ny * nx) return;
+    const int py = p / nx, px = p % nx;
+    float acc[CIN];
+#pragma unroll
+    for (int c = 0; c < CIN; ++c) acc[c] = 0.0f;
+    for (int tap = 0; tap < 9; ++tap) {
+        // output pixel q = p - d feeds input p through tap
+        const int qy = py - (tap / 3 - 1), qx = px - (tap % 3 - 1);
+        if (qy < 0 || qy >= ny || qx < 0 || qx >= nx) continue;
+        const float* dq = dy + (long)(qy * nx + qx) * cout * mt + col;
+        for (int o = 0; o < cout; ++o) {
+            const float g = dq[(long)o * mt];
+#pragma unroll
+            for (int c = 0; c < CIN; ++c) acc[c] = fmaf(ws[(o * CIN + c) * 9 + tap], g, acc[c]);
+        }
+    }
+    float* dxp = dx + (long)p * CIN * mt + col;
+    const float* mp = mask ? mask + (long)p * CIN * mt + col : nullptr;
+#pragma unroll
+    for (int c = 0; c < CIN; ++c) dxp[(long)c * mt] = (mp && !(mp[(long)c * mt] > 0.0f)) ? 0.0f : acc[c];
+}
+
+// ---------------------------------------------------------------------------
+// backward (weights): thread (o, ci) accumulates, for the 9 taps,
+// sum over its pixel slice and all columns of dy[p][o][col] * x[p + d][ci][col];
+// the slice's rows are staged through LDS in 64-column chunks.  Bias gradient
+// by the threads with ci == cin (extra row).  Partials [slice][o][cin+1][9].
+// ---------------------------------------------------------------------------
+constexpr int WG_SLICE = 8;     // pixels per workgroup
+constexpr int WG_COLS = 32;     // columns per LDS chunk
+
+__global__ __launch_bounds__(320) void k_conv_bwd_weight(int ny, int nx, int mt, int cin, int cout,
+                                                         const float* __restrict__ x, const float* __restrict__ dy,
+                                                         float* __restrict__ part) {
+    __shared__ float dys[NET_MAX_COUT][WG_COLS];
+    __shared__ float xs[9][NET_MAX_CIN][WG_COLS];
+    const int tid = threadIdx.x;
+    const int o = tid / (NET_MAX_CIN + 1), ci = tid % (NET_MAX_CIN + 1);
+    const bool active = (tid < NET_WG_THREADS) && (o < cout) && (ci <= cin);
+    const int nth = blockDim.x;
+    float acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = 0.0f;
+    const int npix = ny * nx;
+    const int p0 = blockIdx.x * WG_SLICE;
+    for (int p = p0; p < min(npix, p0 + WG_SLICE); ++p) {
+        const int py = p / nx, px = p % nx;
+        for (int c0 = 0; c0 < mt; c0 += WG_COLS) {
+            const int cw = min(WG_COLS, mt - c0);
+            for (int e = tid; e < cout * WG_COLS; e += nth) {
+                const int oo = e / WG_COLS, cc = e % WG_COLS;
+                dys[oo][cc] = (cc < cw) ? dy[(long)p * cout * mt + (long)oo * mt + c0 + cc] : 0.0f;
+            }
+            for (int e = tid; e < 9 * cin * WG_COLS; e += nth) {
+                const int tap = e / (cin * WG_COLS), rem = e % (cin * WG_COLS);
+                const int cc2 = rem / WG_COLS, cc = rem % WG_COLS;
+                const int qy = py + tap / 3 - 1, qx = px + tap % 3 - 1;
+                float v = 0.0f;
+                if (cc < cw && qy >= 0 && qy < ny && qx >= 0 && qx < nx)
+                    v = x[(long)(qy * nx + qx) * cin * mt + (long)cc2 * mt + c0 + cc];
+                xs[tap][cc2][cc] = v;
+            }
+            __syncthreads();
+            if (active) {
+                for (int cc = 0; cc < cw; ++cc) {
+                    const float g = dys[o][cc];
+                    if (ci < cin) {
+#pragma unroll
+                        for (int t = 0; t < 9; ++t) acc[t] = fmaf(g, xs[t][ci][cc], acc[t]);
+                    } else {
+                        acc[0] += g;       // bias
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (active) {
+        float* pp = part + ((long)blockIdx.x * NET_MAX_COUT * (NET_MAX_CIN + 1) + (long)o * (NET_MAX_CIN + 1) + ci) * 9;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) pp[t] = acc[t];
+    }
+}
+
+// sum the partials of the slices into the gradient (weights [o][ci][9], then bias [o])
+__global__ void k_wgrad_reduce(int nslice, int cin, int cout, const float* __restrict__ part, float* __restrict__ gw,
+                               float* __restrict__ gb) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = (NET_MAX_CIN + 1) * 9;
+    if (e >= cout * (cin + 1) * 9) return;
+    const int o = e / ((cin + 1) * 9), rem = e % ((cin + 1) * 9);
+    const int ci = rem / 9, t = rem % 9;
+    double s = 0.0;
+    for (int k = 0; k < nslice; ++k) s += part[(long)k * NET_MAX_COUT * per + (long)o * per + ci * 9 + t];
+    if (ci < cin) gw[(o * cin + ci) * 9 + t] = (float)s;
+    else if (t == 0) gb[o] = (float)s;
+}
+
+// ---------------------------------------------------------------------------
+// loss: per column sum (out - tgt)^2 / sum tgt^2, gradient 2 (out - tgt) / tn / mt
+// ---------------------------------------------------------------------------
+__global__ void k_loss_cols(int npix, int mt, const float* __restrict__ out, const float* __restrict__ tgt,
+                            double* __restrict__ num, double* __restrict__ den) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= mt) return;
+    double a = 0.0, b = 0.0;
+    for (int p = 0; p < npix; ++p)
+        for (int ch = 0; ch < 2; ++ch) {
+            const float o = out[(long)p * 2 * mt + (long)ch * mt + col];
+            const float t = tgt[(long)p * 2 * mt + (long)ch * mt + col];
+            a += (double)(o - t) * (o - t);
+            b += (double)t * t;
+        }
+    num[col] = a;
+    den[col] = b > 0 ? b : 1.0;
+}
+__global__ void k_loss_grad(int npix, int mt, const float* __restrict__ out, const float* __restrict__ tgt,
+                            const double* __restrict__ den, float* __restrict__ g) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)npix * 2 * mt) return;
+    const int col = e % mt;
+    g[e] = (float)(2.0 * ((double)out[e] - tgt[e]) / den[col] / mt);
+}
+
+// target encoding: t[p][0/1][col] = Re/Im(E[s][p][c]) * scale[col] / oscale
+template <typename T>
+__global__ void k_net_target(int npix, int m, int nsys, float inv_oscale, const Cx<T>* __restrict__ E,
+                             const float* __restrict__ scale, float* __restrict__ t) {
+    const int mt = nsys * m;
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)npix * mt) return;
+    const int p = e / mt, col = e % mt;
+    const int s = col / m, c = col % m;
+    const Cx<T> v = E[(long)s * npix * m + (long)p * m + c];
+    const float sc = (scale ? scale[col] : 1.0f) * inv_oscale;
+    t[(long)p * 2 * mt + col] = (float)v.re * sc;
+    t[(long)p * 2 * mt + mt + col] = (float)v.im * sc;
+}
+
+// operator-weighted loss: D[s][p][c] = (o - t)[p][.][col], Tc[s][p][c] = t[p][.][col] as complex FP64
+__global__ void k_net_pack_diff(int npix, int m, int nsys, const float* __restrict__ o, const float* __restrict__ t,
+                                zd* __restrict__ D, zd* __restrict__ Tc) {
+    const int mt = nsys * m;
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)npix * mt) return;
+    const int p = e / mt, col = e % mt;
+    const int s = col / m, c = col % m;
+    const long i2 = (long)p * 2 * mt + col;
+    const long q = (long)s * npix * m + (long)p * m + c;
+    D[q] = zd{(double)o[i2] - t[i2], (double)o[i2 + mt] - t[i2 + mt]};
+    Tc[q] = zd{(double)t[i2], (double)t[i2 + mt]};
+}
+
+// gout[p][0/1][col] = f[col] * Re/Im G[s][p][c]
+__global__ void k_net_grad_encode(int npix, int m, int nsys, const zd* __restrict__ G, const double* __restrict__ f,
+                                  float* __restrict__ gout) {
+    const int mt = nsys * m;
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)npix * mt) return;
+    const int p = e / mt, col = e % mt;
+    const int s = col / m, c = col % m;
+    const zd g = G[(long)s * npix * m + (long)p * m + c];
+    gout[(long)p * 2 * mt + col] = (float)(f[col] * g.re);
+    gout[(long)p * 2 * mt + mt + col] = (float)(f[col] * g.im);
+}
+
+// Adam on the FP32 master parameters, then the BF16 copy
+__global__ void k_adam(int np, float* __restrict__ w, const float* __restrict__ g, float* __restrict__ mo,
+                       float* __restrict__ ve, uint16_t* __restrict__ wb, float lr, float b1, float b2, float eps, int t) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const float gi = g[i];
+    const float m1 = b1 * mo[i] + (1.0f - b1) * gi;
+    const float v1 = b2 * ve[i] + (1.0f - b2) * gi * gi;
+    mo[i] = m1;
+    ve[i] = v1;
+    const float mh = m1 / (1.0f - powf(b1, (float)t));
+    const float vh = v1 / (1.0f - powf(b2, (float)t));
+    const float wi = w[i] - lr * mh / (sqrtf(vh) + eps);
+    w[i] = wi;
+    wb[i] = f32_to_bf16(wi);
+}
+__global__ void k_to_bf16(int np, const float* __restrict__ w, uint16_t* __restrict__ wb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < np) wb[i] = f32_to_bf16(w[i]);
+}
+
+// per-column 1/||V col|| (0 for a zero column)
+template <typename T>
+__global__ void k_inv_colnorm(int npix, int m, int nsys, const Cx<T>* __restrict__ V, float* __restrict__ sc) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    const int mt = nsys * m;
+    if (col >= mt) return;
+    const int s = col / m, c = col % m;
+    double a = 0.0;
+    for (int p = 0; p < npix; ++p) {
+        const Cx<T> v = V[(long)s * npix * m + (long)p * m + c];
+        a += (double)v.re * v.re + (double)v.im * v.im;
+    }
+    sc[col] = a > 0 ? (float)(1.0 / sqrt(a)) : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+// pixel blocks along x (up to 2^31), column blocks along y
+static dim3 conv_grid(int npix, int mt) { return dim3(ceil_div(npix, 4), ceil_div(mt, 64)); }
+
+template <typename T>
+void net_encode(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* V, const float* scale, const zd* shifts,
+                const int* sides, float* x) {
+    const long tot = (long)N.ny * N.nx * m * nsys;
+    k_net_encode<T><<<ceil_div(tot, 256), 256, 0, st>>>(N.ny * N.nx, m, nsys, N.cin, V, scale, shifts, sides,
+                                                         N.inv_alpha, N.fields, x);
+    FH_LAUNCH_CHECK();
+}
+template <typename T>
+void net_decode(hipStream_t st, const NetDev& N, int m, int nsys, const float* o, const float* scale, Cx<T>* Out) {
+    const long tot = (long)N.ny * N.nx * m * nsys;
+    k_net_decode<T><<<ceil_div(tot, 256), 256, 0, st>>>(N.ny * N.nx, m, nsys, N.oscale, o, scale, Out);
+    FH_LAUNCH_CHECK();
+}
+template <typename T>
+void net_target(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* E, const float* scale, float* t) {
+    const long tot = (long)N.ny * N.nx * m * nsys;
+    k_net_target<T><<<ceil_div(tot, 256), 256, 0, st>>>(N.ny * N.nx, m, nsys, 1.0f / N.oscale, E, scale, t);
+    FH_LAUNCH_CHECK();
+}
+template <typename T>
+void net_inv_colnorm(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* V, float* sc) {
+    k_inv_colnorm<T><<<ceil_div(m * nsys, 64), 64, 0, st>>>(N.ny * N.nx, m, nsys, V, sc);
+    FH_LAUNCH_CHECK();
+}
+template void net_encode<double>(hipStream_t, const NetDev&, int, int, const zd*, const float*, const zd*, const int*, float*);
+template void net_encode<float>(hipStream_t, const NetDev&, int, int, const cf*, const float*, const zd*, const int*, float*);
+template void net_decode<double>(hipStream_t, const NetDev&, int, int, const float*, const float*, zd*);
+template void net_decode<float>(hipStream_t, const NetDev&, int, int, const float*, const float*, cf*);
+template void net_target<double>(hipStream_t, const NetDev&, int, int, const zd*, const float*, float*);
+template void net_inv_colnorm<double>(hipStream_t, const NetDev&, int, int, const zd*, float*);
+template void net_inv_colnorm<float>(hipStream_t, const NetDev&, int, int, const cf*, float*);
+
+void net_forward(hipStream_t st, const NetDev& N, int mt, const float* x, float* a1, float* a2, float* out) {
+    const int npix = N.ny * N.nx;
+    dim3 blk(64, 4), g = conv_grid(npix, mt);
+    hipEvent_t ev = prof_begin(st);
+    k_conv_fwd<NET_HID><<<g, blk, 0, st>>>(N.ny, N.nx, mt, N.cin, x, N.wb + N.off_w1, N.wb + N.off_b1, 1, a1);
+    FH_LAUNCH_CHECK();
+    k_conv_fwd<NET_HID><<<g, blk, 0, st>>>(N.ny, N.nx, mt, NET_HID, a1, N.wb + N.off_w2, N.wb + N.off_b2, 1, a2);
+    FH_LAUNCH_CHECK();
+    k_conv_fwd<2><<<g, blk, 0, st>>>(N.ny, N.nx, mt, NET_HID, a2, N.wb + N.off_w3, N.wb + N.off_b3, 0, out);
+    FH_LAUNCH_CHECK();
+    const double macs = 9.0 * (N.cin * NET_HID + NET_HID * NET_HID + NET_HID * 2) * npix * mt;
+    prof_end(st, ev, "net_forward", 4.0 * npix * mt * (N.cin + 2 * NET_HID + 2) * 2, 2 * macs);
+}
+
+void net_backward(hipStream_t st, const NetDev& N, int mt, const float* x, const float* a1, const float* a2,
+                  const float* gout, float* g2, float* g1, float* grad, DBuf& part) {
+    const int npix = N.ny * N.nx;
+    dim3 blk(64, 4), g = conv_grid(npix, mt);
+    const int nslice = ceil_div(npix, WG_SLICE);
+    float* P = (float*)part.ensure(sizeof(float) * (size_t)nslice * NET_MAX_COUT * (NET_MAX_CIN + 1) * 9);
+    // layer 3: weights, then data through ReLU(a2)
+    k_conv_bwd_weight<<<nslice, 320, 0, st>>>(N.ny, N.nx, mt, NET_HID, 2, a2, gout, P);
+    FH_LAUNCH_CHECK();
+    k_wgrad_reduce<<<ceil_div(2 * (NET_HID + 1) * 9, 128), 128, 0, st>>>(nslice, NET_HID, 2, P, grad + N.off_w3, grad + N.off_b3);
+    FH_LAUNCH_CHECK();
+    k_conv_bwd_data<NET_HID><<<g, blk, 0, st>>>(N.ny, N.nx, mt, 2, gout, N.wb + N.off_w3, a2, g2);
+    FH_LAUNCH_CHECK();
+    // layer 2
+    k_conv_bwd_weight<<<nslice, 320, 0, st>>>(N.ny, N.nx, mt, NET_HID, NET_HID, a1, g2, P);
+    FH_LAUNCH_CHECK();
+    k_wgrad_reduce<<<ceil_div(NET_HID * (NET_HID + 1) * 9, 128), 128, 0, st>>>(nslice, NET_HID, NET_HID, P, grad + N.off_w2,
+                                                                                grad + N.off_b2);
+    FH_LAUNCH_CHECK();
+    k_conv_bwd_data<NET_HID><<<g, blk, 0, st>>>(N.ny, N.nx, mt, NET_HID, g2, N.wb + N.off_w2, a1, g1);
+    FH_LAUNCH_CHECK();
+    // layer 1 (weights only)
+    k_conv_bwd_weight<<<nslice, 320, 0, st>>>(N.ny, N.nx, mt, N.cin, NET_HID, x, g1, P);
+    FH_LAUNCH_CHECK();
+    k_wgrad_reduce<<<ceil_div(NET_HID * (N.cin + 1) * 9, 128), 128, 0, st>>>(nslice, N.cin, NET_HID, P, grad + N.off_w1,
+                                                                              grad + N.off_b1);
+    FH_LAUNCH_CHECK();
+}
+
+double net_loss(hipStream_t st, const NetDev& N, int mt, const float* out, const float* tgt, float* gout, DBuf& scratch) {
+    const int npix = N.ny * N.nx;
+    double* nd = (double*)scratch.ensure(sizeof(double) * 2 * mt);
+    k_loss_cols<<<ceil_div(mt, 64), 64, 0, st>>>(npix, mt, out, tgt, nd, nd + mt);
+    FH_LAUNCH_CHECK();
+    k_loss_grad<<<ceil_div((size_t)npix * 2 * mt, 256), 256, 0, st>>>(npix, mt, out, tgt, nd + mt, gout);
+    FH_LAUNCH_CHECK();
+    std::vector<double> h(2 * mt);
+    FH_HIP(hipMemcpyAsync(h.data(), nd, sizeof(double) * 2 * mt, hipMemcpyDeviceToHost, st));
+    FH_HIP(hipStreamSynchronize(st));
+    double l = 0.0;
+    for (int c = 0; c < mt; ++c) l += h[c] / h[mt + c];
+    return l / mt;
+}
+
+void net_adam(hipStream_t st, NetDev& N, const float* grad, float lr) {
+    N.t += 1;
+    k_adam<<<ceil_div(N.np, 256), 256, 0, st>>>(N.np, N.w, grad, N.mom, N.vel, N.wb, lr, 0.9f, 0.999f, 1e-8f, N.t);
+    FH_LAUNCH_CHECK();
+}
+
+void net_sync_bf16(hipStream_t st, NetDev& N) {
+    k_to_bf16<<<ceil_div(N.np, 256), 256, 0, st>>>(N.np, N.w, N.wb);
+    FH_LAUNCH_CHECK();
+}
+
+void net_pack_diff(hipStream_t st, const NetDev& N, int m, int nsys, const float* o, const float* t, zd* D, zd* Tc) {
+    const long tot = (long)N.ny * N.nx * m * nsys;
+    k_net_pack_diff<<<ceil_div(tot, 256), 256, 0, st>>>(N.ny * N.nx, m, nsys, o, t, D, Tc);
+    FH_LAUNCH_CHECK();
+}
+
+void net_grad_encode(hipStream_t st, const NetDev& N, int m, int nsys, const zd* G, const double* f, float* gout) {
+    const long tot = (long)N.ny * N.nx * m * nsys;
+    k_net_grad_encode<<<ceil_div(tot, 256), 256, 0, st>>>(N.ny * N.nx, m, nsys, G, f, gout);
+    FH_LAUNCH_CHECK();
+}
+
+uint16_t host_f32_to_bf16(float f) { return f32_to_bf16(f); }
+
+}  // namespace fh

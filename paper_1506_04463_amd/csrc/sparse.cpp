@@ -16,6 +16,7 @@
 #include <cstdlib>
 
 #include "fh_sparse.h"
+#include "fh_net.h"
 
 namespace fh {
 
@@ -334,6 +335,12 @@ static void ensure_factors(Ctx& c, SparseState& S, int ne, const cplx* z, bool n
     }
 }
 
+// ILU(0) factors (and the Jacobi diagonal) are needed by the preconditioner or its fallback
+static bool needs_factors(const fh_opts& o) {
+    const int p = o.precond == FH_PC_LEARNED ? o.fallback : o.precond;
+    return p == FH_PC_ILU0 || p == FH_PC_JACOBI;
+}
+
 template <typename T>
 static IluApplyArgs<T> ilu_args(SparseState& S, int m, int precond) {
     IluApplyArgs<T> a;
@@ -377,6 +384,12 @@ static void apply_M(Ctx& c, SparseState& S, const Batch& b, const Cx<T>* shifts,
 
 template <typename T>
 static void apply_P(Ctx& c, SparseState& S, const Batch& b, int precond, Cx<T>* X, Cx<T>* Out, const T* scale) {
+    if (precond == FH_PC_LEARNED) {
+        // operator shift and side of every system (FP64 shifts, set by solve_batch)
+        // Krylov vectors have unit columns (stopped columns are zero and unused)
+        net_apply<T>(c, *S.net, b.nsys, b.m, X, (const zd*)S.shifts64.p, (const int*)S.side_of.p, Out, true);
+        return;
+    }
     IluApplyArgs<T> a = ilu_args<T>(S, b.m, precond);
     if (precond == FH_PC_ILU0) ilu_apply<T>(c.stream, a, b.nsys, X, Out, scale);
     else {
@@ -389,19 +402,28 @@ struct SolveStats {
     long long steps = 0;
     double relres = 0.0;
     int cycles = 0;
+    int fallback = 0;   // 1 if the learned preconditioner was replaced
 };
+
+// a restart cycle with the learned preconditioner must at least halve the
+// worst relative residual, else the fallback preconditioner takes over
+constexpr double LEARNED_STALL = 0.5;
 
 // GMRES(restart), right preconditioned, every column of every system in lockstep.
 // Solves M_s x = b_s; x starts at zero.  bn: device column norms of b (C doubles).
 template <typename T>
 static SolveStats gmres(Ctx& c, SparseState& S, const Batch& b, const Cx<T>* shifts, const Cx<T>* B, Cx<T>* X,
-                        int restart, int max_cycles, double tol, int precond, const double* bn) {
+                        int restart, int max_cycles, double tol, int precond, const double* bn, int fallback) {
     hipStream_t st = c.stream;
     const int n = S.n, m = b.m, C = b.nsys * m, KP = restart + 1;
     const long vstride = (long)b.nsys * n * m;
     SolveStats stats;
     Cx<T>* V = (Cx<T>*)S.V.ensure(sizeof(Cx<T>) * vstride * (restart + 1));
     Cx<T>* Z = (Cx<T>*)S.Z.ensure(sizeof(Cx<T>) * vstride);
+    // a nonlinear (learned) preconditioner needs the flexible variant: keep
+    // every Z_k and update x with them directly
+    const bool flex = (precond == FH_PC_LEARNED);
+    Cx<T>* Zf = flex ? (Cx<T>*)S.Zf.ensure(sizeof(Cx<T>) * vstride * restart) : nullptr;
     zd* Hs = (zd*)S.Hs.ensure(sizeof(zd) * (size_t)restart * KP * C);
     double* cs = (double*)S.cs.ensure(sizeof(double) * (size_t)restart * C);
     zd* sn = (zd*)S.sn.ensure(sizeof(zd) * (size_t)restart * C);
@@ -418,6 +440,7 @@ static SolveStats gmres(Ctx& c, SparseState& S, const Batch& b, const Cx<T>* shi
     std::vector<int> hk(C);
     FH_HIP(hipMemsetAsync(X, 0, sizeof(Cx<T>) * vstride, st));
     FH_HIP(hipMemcpyAsync(hbn.data(), bn, sizeof(double) * C, hipMemcpyDeviceToHost, st));
+    double prev_worst = 0.0;
     for (int cyc = 0; cyc < max_cycles + 1; ++cyc) {
         // r = b - M x into V_0
         if (cyc == 0) FH_HIP(hipMemcpyAsync(V, B, sizeof(Cx<T>) * vstride, hipMemcpyDeviceToDevice, st));
@@ -429,6 +452,11 @@ static SolveStats gmres(Ctx& c, SparseState& S, const Batch& b, const Cx<T>* shi
         for (int k = 0; k < C; ++k) worst = std::max(worst, hbn[k] > 0 ? hb[k] / hbn[k] : 0.0);
         stats.relres = worst;
         if (!(worst > tol) || cyc == max_cycles) break;
+        if (precond == FH_PC_LEARNED && cyc > 0 && !(worst < LEARNED_STALL * prev_worst)) {
+            precond = fallback;            // flexible updates stay valid for any preconditioner
+            stats.fallback = 1;
+        }
+        prev_worst = worst;
         stats.cycles++;
         gmres_start(st, C, KP, restart, beta, bn, tol, g, vscale, kuse);
         scale_inplace<T>(st, n, m, b.nsys, V, vscale);                  // V_0 = r / beta
@@ -436,8 +464,9 @@ static SolveStats gmres(Ctx& c, SparseState& S, const Batch& b, const Cx<T>* shi
         for (int k = 0; k < restart; ++k) {
             Cx<T>* Vk = V + (long)k * vstride;
             Cx<T>* Vk1 = V + (long)(k + 1) * vstride;
-            apply_P<T>(c, S, b, precond, Vk, Z, (const T*)nullptr);     // Z = P^{-1} V_k
-            apply_M<T>(c, S, b, shifts, T(1), Z, nullptr, Vk1);         // W = M Z
+            Cx<T>* Zk = flex ? Zf + (long)k * vstride : Z;
+            apply_P<T>(c, S, b, precond, Vk, Zk, (const T*)nullptr);    // Z = P^{-1} V_k
+            apply_M<T>(c, S, b, shifts, T(1), Zk, nullptr, Vk1);        // W = M Z
             cgs2<T>(st, n, m, b.nsys, k + 1, V, vstride, Vk1, h1, h2, hnorm, S.part);
             givens_step(st, C, k, KP, h1, h2, hnorm, Hs, cs, sn, g, resid, vscale, kuse, bn, tol);
             scale_inplace<T>(st, n, m, b.nsys, Vk1, vscale);            // V_{k+1} = W / h_{k+1,k}
@@ -449,57 +478,63 @@ static SolveStats gmres(Ctx& c, SparseState& S, const Batch& b, const Cx<T>* shi
             for (int q = 0; q < C && !any; ++q) any = hk[q] > k + 1;
             if (!any) break;
         }
-        // x += P^{-1} (V y)
-        gmres_update_prep<T>(st, n, m, b.nsys, kexec, KP, Hs, g, kuse, y, V, vstride, Z);
-        Cx<T>* tmp = V + (long)kexec * vstride;   // free after the cycle
-        apply_P<T>(c, S, b, precond, Z, tmp, (const T*)nullptr);
-        add_same<T>(st, vstride, tmp, X);                               // x += P^{-1} V y
+        if (flex) {
+            // x += Z y
+            gmres_update_prep<T>(st, n, m, b.nsys, kexec, KP, Hs, g, kuse, y, Zf, vstride, Z);
+            add_same<T>(st, vstride, Z, X);
+        } else {
+            // x += P^{-1} (V y)
+            gmres_update_prep<T>(st, n, m, b.nsys, kexec, KP, Hs, g, kuse, y, V, vstride, Z);
+            Cx<T>* tmp = V + (long)kexec * vstride;   // free after the cycle
+            apply_P<T>(c, S, b, precond, Z, tmp, (const T*)nullptr);
+            add_same<T>(st, vstride, tmp, X);                           // x += P^{-1} V y
+        }
     }
     return stats;
 }
 
-// shifts per system (side 1 uses conj(z))
+// operator shifts per system: z for a right system, conj(z) for a left one
 template <typename T>
-static Cx<T>* upload_shifts(Ctx& c, SparseState& S, int ne, const cplx* z) {
-    std::vector<Cx<T>> h(2 * ne);
-    for (int j = 0; j < ne; ++j) {
-        h[j] = Cx<T>{T(z[j].real()), T(z[j].imag())};
-        h[ne + j] = Cx<T>{T(z[j].real()), T(-z[j].imag())};
-    }
+static Cx<T>* upload_op_shifts(Ctx& c, SparseState& S, int nsys, const cplx* zsys, const int* side) {
+    std::vector<Cx<T>> h(nsys);
+    for (int s = 0; s < nsys; ++s) h[s] = Cx<T>{T(zsys[s].real()), T(side[s] ? -zsys[s].imag() : zsys[s].imag())};
     DBuf& d = sizeof(T) == sizeof(double) ? S.shifts64 : S.shifts32;
-    Cx<T>* p = (Cx<T>*)d.ensure(sizeof(Cx<T>) * 2 * ne);
-    FH_HIP(hipMemcpyAsync(p, h.data(), sizeof(Cx<T>) * 2 * ne, hipMemcpyHostToDevice, c.stream));
+    Cx<T>* p = (Cx<T>*)d.ensure(sizeof(Cx<T>) * nsys);
+    FH_HIP(hipMemcpyAsync(p, h.data(), sizeof(Cx<T>) * nsys, hipMemcpyHostToDevice, c.stream));
     FH_HIP(hipStreamSynchronize(c.stream));
     return p;
 }
 
-// Solve all 2 ne systems for the RHS block B64 ([2ne][n][m], FP64) into X64.
-static SolveStats solve_all(Ctx& c, SparseState& S, int ne, const cplx* z, int m, const zd* B64, zd* X64,
-                            const fh_opts& o) {
+// Solve the nsys shifted systems of a batch: system s uses the factors of node
+// node_of[s] with node value zsys[s]; sides: the first nright systems are
+// right systems (z - A) x = b, the others left systems (z - A)^H x = b.
+// B64, X64: [nsys][n][m] FP64.
+static SolveStats solve_batch(Ctx& c, SparseState& S, int nsys, int nright, const int* node_of, const cplx* zsys, int m,
+                              const zd* B64, zd* X64, const fh_opts& o) {
     hipStream_t st = c.stream;
     Batch b;
-    b.nsys = 2 * ne;
-    b.nright = ne;
+    b.nsys = nsys;
+    b.nright = nright;
     b.m = m;
     const int n = S.n, C = b.nsys * m;
     const long len = (long)b.nsys * n * m;
-    std::vector<int> node_of(b.nsys), side_of(b.nsys);
-    for (int s = 0; s < b.nsys; ++s) { node_of[s] = s % ne; side_of[s] = s >= ne; }
-    FH_HIP(hipMemcpyAsync(S.node_of.ensure(sizeof(int) * b.nsys), node_of.data(), sizeof(int) * b.nsys,
+    std::vector<int> side_of(b.nsys);
+    for (int s = 0; s < b.nsys; ++s) side_of[s] = s >= nright;
+    FH_HIP(hipMemcpyAsync(S.node_of.ensure(sizeof(int) * b.nsys), node_of, sizeof(int) * b.nsys,
                           hipMemcpyHostToDevice, st));
     FH_HIP(hipMemcpyAsync(S.side_of.ensure(sizeof(int) * b.nsys), side_of.data(), sizeof(int) * b.nsys,
                           hipMemcpyHostToDevice, st));
     const int precond = o.precond;
+    FH_REQUIRE(precond != FH_PC_LEARNED || S.net, -1, "learned preconditioner requested but no network is attached");
     double* bn = (double*)S.bn64.ensure(sizeof(double) * C);
     colnorms<double>(st, n, m, b.nsys, B64, bn, S.part);
     const int restart = std::max(1, o.restart);
-    if (o.precision == FH_PREC_FP64) {
-        zd* sh = upload_shifts<double>(c, S, ne, z);
-        return gmres<double>(c, S, b, sh, B64, X64, restart, std::max(1, o.max_restarts), o.inner_tol, precond, bn);
-    }
+    zd* sh64 = upload_op_shifts<double>(c, S, nsys, zsys, side_of.data());
+    if (o.precision == FH_PREC_FP64)
+        return gmres<double>(c, S, b, sh64, B64, X64, restart, std::max(1, o.max_restarts), o.inner_tol, precond, bn,
+                             o.fallback);
     // complex FP32 inner solves wrapped in FP64 iterative refinement
-    cf* sh32 = upload_shifts<float>(c, S, ne, z);
-    zd* sh64 = upload_shifts<double>(c, S, ne, z);
+    cf* sh32 = upload_op_shifts<float>(c, S, nsys, zsys, side_of.data());
     zd* R = (zd*)S.bufR.ensure(sizeof(zd) * len);
     cf* b32 = (cf*)S.b32.ensure(sizeof(cf) * len);
     cf* x32 = (cf*)S.x32.ensure(sizeof(cf) * len);
@@ -510,6 +545,7 @@ static SolveStats solve_all(Ctx& c, SparseState& S, int ne, const cplx* z, int m
     FH_HIP(hipMemsetAsync(X64, 0, sizeof(zd) * len, st));
     FH_HIP(hipMemcpyAsync(R, B64, sizeof(zd) * len, hipMemcpyDeviceToDevice, st));
     SolveStats tot;
+    int pc = precond;
     for (int it = 0; it <= std::max(1, o.max_refine); ++it) {
         colnorms<double>(st, n, m, b.nsys, R, rn, S.part);
         FH_HIP(hipMemcpyAsync(hrn.data(), rn, sizeof(double) * C, hipMemcpyDeviceToHost, st));
@@ -524,16 +560,45 @@ static SolveStats solve_all(Ctx& c, SparseState& S, int ne, const cplx* z, int m
         double* ones = (double*)S.bn32.ensure(sizeof(double) * C);     // |b32 columns| = 1 (or 0)
         colnorms<float>(st, n, m, b.nsys, b32, ones, S.part);
         SolveStats s32 = gmres<float>(c, S, b, sh32, b32, x32, restart, std::max(1, o.max_restarts),
-                                      o.mixed_inner_tol, precond, ones);
+                                      o.mixed_inner_tol, pc, ones, o.fallback);
         tot.steps += s32.steps;
+        tot.fallback |= s32.fallback;
+        if (s32.fallback) pc = o.fallback;     // later refinement steps keep the fallback
         tot.cycles += s32.cycles;
         FH_HIP(hipMemcpyAsync(sc, hrn.data(), sizeof(double) * C, hipMemcpyHostToDevice, st));
         axpy_cols<float>(st, n, m, b.nsys, x32, sc, X64);               // x += |r| d
-        // r = b - M x in FP64
-        Batch bb = b;
-        apply_M<double>(c, S, bb, sh64, -1.0, X64, B64, R);
+        apply_M<double>(c, S, b, sh64, -1.0, X64, B64, R);               // r = b - M x in FP64
     }
     return tot;
+}
+
+// all 2 ne systems of the filter: right systems of nodes 0..ne-1, then left ones
+static SolveStats solve_all(Ctx& c, SparseState& S, int ne, const cplx* z, int m, const zd* B64, zd* X64,
+                            const fh_opts& o) {
+    std::vector<int> node_of(2 * ne);
+    std::vector<cplx> zsys(2 * ne);
+    for (int s = 0; s < 2 * ne; ++s) { node_of[s] = s % ne; zsys[s] = z[s % ne]; }
+    return solve_batch(c, S, 2 * ne, ne, node_of.data(), zsys.data(), m, B64, X64, o);
+}
+
+// public: solve (z_s - A) X_s = B_s (right) / (z_s - A)^H X_s = B_s (left) for a
+// batch whose right systems come first; one ILU(0) per system (cached)
+void sparse_shifted_solve(Ctx& c, Prob& p, int nsys, const cplx* z, const int* sides, int m, const zd* B, zd* X,
+                          const fh_opts& o, fh_report* rep) {
+    SparseState& S = *p.sp;
+    int nright = 0;
+    while (nright < nsys && sides[nright] == 0) ++nright;
+    if (needs_factors(o)) ensure_factors(c, S, nsys, z, o.precision == FH_PREC_MIXED, o, rep);
+    std::vector<int> node_of(nsys);
+    for (int s = 0; s < nsys; ++s) node_of[s] = s;
+    SolveStats st = solve_batch(c, S, nsys, nright, node_of.data(), z, m, B, X, o);
+    FH_HIP(hipStreamSynchronize(c.stream));
+    if (rep) {
+        rep->n_fallback += st.fallback ? nsys : 0;
+        rep->n_solve += nsys;
+        rep->inner_steps = st.steps;
+        rep->inner_relres = st.relres;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -546,7 +611,7 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
     hipStream_t st = c.stream;
     const int n = S.n;
     const long blk = (long)n * m;
-    ensure_factors(c, S, ne, z, o.precision == FH_PREC_MIXED, o, rep);
+    if (needs_factors(o)) ensure_factors(c, S, ne, z, o.precision == FH_PREC_MIXED, o, rep);
     zd* Bb = (zd*)S.bufB.ensure(sizeof(zd) * blk * 2 * ne);
     zd* Xb = (zd*)S.bufX.ensure(sizeof(zd) * blk * 2 * ne);
     zd* T = (zd*)S.bufT.ensure(sizeof(zd) * blk * 2);
@@ -592,11 +657,14 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
     filter_accum(st, ne, n, m, Xb + ne * blk, cd + (size_t)ne * m, lam ? Yh : nullptr, rd ? rd + m : nullptr, Qh);
     FH_HIP(hipStreamSynchronize(st));
     if (rep) {
+        rep->n_fallback += s.fallback ? 2 * ne : 0;
         rep->n_solve += 2 * ne;
         rep->inner_steps = s.steps;
         rep->inner_relres = s.relres;
     }
 }
+
+void sparse_set_net(Prob& p, NetState* net) { p.sp->net = net; }
 
 void sparse_apply_A(Ctx& c, Prob& p, int side, int m, const zd* X, zd* Out) {
     SparseState& S = *p.sp;

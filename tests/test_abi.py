@@ -61,3 +61,16 @@ def test_bad_arguments_are_rejected():
     o = fh.fh_opts()
     L.fh_default_opts(C.byref(o))
     assert o.max_iter > 0 and o.eps > 0 and o.restart == 30
+
+
+def test_net_and_solve_arguments_are_rejected():
+    L = fh.lib()
+    assert L.fh_shifted_solve(None, None, 1, None, None, 1, None, None, None, None) == -1
+    assert L.fh_net_create(None, 4, 4, 0, None, 1.0, 1.0, 0, None) == -1
+    assert L.fh_net_destroy(None) == -1
+    assert L.fh_net_param_count(None) == -1
+    assert L.fh_net_get_params(None, None, None) == -1
+    assert L.fh_net_set_params(None, None, None) == -1
+    assert L.fh_net_forward(None, None, 1, 1, None, None, None, None) == -1
+    assert L.fh_net_train_step(None, None, None, 1, 1, None, None, None, None, 1e-3, 1, None, None) == -1
+    assert L.fh_problem_set_net(None, None) == -1

@@ -1,0 +1,101 @@
+"""Pins of the oracle's conv-net reference (the learned preconditioner has no
+counterpart in the paper): a direct summation of the convolution, kernels with
+known action (identity, shift), and central finite differences of the loss."""
+import numpy as np
+
+from oracle import convnet as N
+
+
+def _params(rng, cin, h):
+    shapes = [(h, cin), (h, h), (2, h)]
+    return [(0.3 * rng.standard_normal((o, i, 3, 3)), 0.1 * rng.standard_normal(o)) for o, i in shapes]
+
+
+def test_conv_direct_sum_and_known_kernels():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((5, 6, 3, 2))
+    w = rng.standard_normal((4, 3, 3, 3))
+    b = rng.standard_normal(4)
+    y = N.conv3x3(x, w, b)
+    for (yy, xx, o, m) in [(0, 0, 1, 0), (2, 3, 3, 1), (4, 5, 0, 1)]:
+        s = b[o]
+        for dy in range(3):
+            for dx in range(3):
+                py, px = yy + dy - 1, xx + dx - 1
+                if 0 <= py < 5 and 0 <= px < 6:
+                    s += sum(w[o, c, dy, dx] * x[py, px, c, m] for c in range(3))
+        assert abs(y[yy, xx, o, m] - s) < 1e-12
+    wid = np.zeros((3, 3, 3, 3)); wid[np.arange(3), np.arange(3), 1, 1] = 1.0
+    np.testing.assert_allclose(N.conv3x3(x, wid, np.zeros(3)), x)
+    wsh = np.zeros((1, 1, 3, 3)); wsh[0, 0, 1, 2] = 1.0        # picks the right neighbour
+    xs = x[:, :, :1]
+    ys = N.conv3x3(xs, wsh, np.zeros(1))
+    np.testing.assert_allclose(ys[:, :-1], xs[:, 1:])
+    np.testing.assert_allclose(ys[:, -1], 0.0)
+
+
+def test_gradients_finite_differences():
+    rng = np.random.default_rng(1)
+    params = _params(rng, 4, 5)
+    x = rng.standard_normal((6, 5, 4, 3))
+    t = rng.standard_normal((6, 5, 2, 3))
+    loss, grads = N.loss_and_grad(params, x, t)
+    h = 1e-6
+    for layer, idx in [(0, (2, 1, 0, 2)), (1, (4, 3, 1, 1)), (2, (1, 4, 2, 0)), (0, (0, 0, 1, 1))]:
+        w, b = params[layer]
+        wp = [(p[0].copy(), p[1].copy()) for p in params]
+        wm = [(p[0].copy(), p[1].copy()) for p in params]
+        wp[layer][0][idx] += h
+        wm[layer][0][idx] -= h
+        fd = (N.loss_and_grad(wp, x, t)[0] - N.loss_and_grad(wm, x, t)[0]) / (2 * h)
+        assert abs(fd - grads[layer][0][idx]) < 1e-6 * max(1.0, abs(fd))
+    for layer, o in [(0, 3), (2, 1)]:
+        wp = [(p[0].copy(), p[1].copy()) for p in params]
+        wm = [(p[0].copy(), p[1].copy()) for p in params]
+        wp[layer][1][o] += h
+        wm[layer][1][o] -= h
+        fd = (N.loss_and_grad(wp, x, t)[0] - N.loss_and_grad(wm, x, t)[0]) / (2 * h)
+        assert abs(fd - grads[layer][1][o]) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_encode_normalizes_columns():
+    rng = np.random.default_rng(2)
+    r = rng.standard_normal((12, 3)) + 1j * rng.standard_normal((12, 3))
+    x, nr = N.encode(r, 3, 4, fields=[np.ones((3, 4))])
+    assert x.shape == (3, 4, 3, 3)
+    np.testing.assert_allclose(np.sqrt((x[:, :, :2] ** 2).sum(axis=(0, 1, 2))), 1.0)
+    np.testing.assert_allclose(nr, np.linalg.norm(r, axis=0))
+
+
+def test_operator_loss_gradients_finite_differences_and_special_cases():
+    rng = np.random.default_rng(3)
+    ny, nx, m = 4, 3, 3
+    n = ny * nx
+    params = _params(rng, 4, 5)
+    x = rng.standard_normal((ny, nx, 4, m))
+    t = rng.standard_normal((ny, nx, 2, m))
+    ops = [rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) for _ in range(m)]
+    loss, grads = N.loss_and_grad_op(params, x, t, ops)
+    h = 1e-6
+    for layer, idx in [(0, (2, 1, 0, 2)), (1, (4, 3, 1, 1)), (2, (1, 4, 2, 0))]:
+        wp = [(p[0].copy(), p[1].copy()) for p in params]
+        wm = [(p[0].copy(), p[1].copy()) for p in params]
+        wp[layer][0][idx] += h
+        wm[layer][0][idx] -= h
+        fd = (N.loss_and_grad_op(wp, x, t, ops)[0] - N.loss_and_grad_op(wm, x, t, ops)[0]) / (2 * h)
+        assert abs(fd - grads[layer][0][idx]) < 1e-6 * max(1.0, abs(fd))
+    for layer, o in [(0, 2), (2, 0)]:
+        wp = [(p[0].copy(), p[1].copy()) for p in params]
+        wm = [(p[0].copy(), p[1].copy()) for p in params]
+        wp[layer][1][o] += h
+        wm[layer][1][o] -= h
+        fd = (N.loss_and_grad_op(wp, x, t, ops)[0] - N.loss_and_grad_op(wm, x, t, ops)[0]) / (2 * h)
+        assert abs(fd - grads[layer][1][o]) < 1e-6 * max(1.0, abs(fd))
+    # identity operators reduce it to the plain loss; a scaled operator changes nothing
+    eye = [np.eye(n, dtype=complex)] * m
+    l1, g1 = N.loss_and_grad_op(params, x, t, eye)
+    l0, g0 = N.loss_and_grad(params, x, t)
+    assert abs(l1 - l0) < 1e-12 * l0
+    np.testing.assert_allclose(g1[1][0], g0[1][0], rtol=1e-10, atol=1e-14)
+    l2, _ = N.loss_and_grad_op(params, x, t, [3j * M for M in ops])
+    assert abs(l2 - loss) < 1e-12 * loss
