@@ -175,6 +175,25 @@ int fh_filter(fh_handle h, fh_problem p, int ne, const double* z, const double* 
 int fh_feast(fh_handle h, fh_problem p, const fh_contour* c, const double* z, const double* w,
              const fh_opts* o, void* Y, void* Yh, void* lambda, double* res, fh_report* rep);
 
+/* ---- many dense problems at once (sizes may differ) ---------------------
+ * FEAST on each problem i with its own contour contours[i] and start
+ * subspaces Y[i], Yh[i] (device n_i x m0, in/out exactly as in fh_feast;
+ * lambda[i]: device m0; res[i]: host m0 or NULL; reports[i] optional).  The
+ * contour filters of all problems run together every iteration: one
+ * factorization of (z_j B_i - A_i) per (problem, node), made once for all
+ * problems by grouped launches in which every launch advances every matrix
+ * by one panel, then grouped 'N' and 'C' solves.  With o->precision ==
+ * FH_PREC_MIXED the factors and solves are complex FP32 (GEMM updates on
+ * MFMA, tile autotuned per shape class) inside FP64 iterative refinement of
+ * every right-hand side (o->inner_tol, o->max_refine); otherwise FP64.
+ * Steps 2-5 run per problem.  All problems must be dense; o->m0 <= every n_i;
+ * nodes are generated from the contours (Section 2.4 trapezoidal rule).
+ * Returns FH_OK when every problem converged, else the first other status
+ * (each report holds its own). */
+int fh_feast_batched(fh_handle h, int count, const fh_problem* problems, const fh_contour* contours,
+                     const fh_opts* o, void* const* Y, void* const* Yh, void* const* lambda, double* const* res,
+                     fh_report* reports);
+
 /* ---- kernel timing ---------------------------------------------------------
  * fh_profile(h, 1) resets and enables per-kernel timing with HIP events on
  * the handle's stream (a small overhead per launch); fh_profile_read returns

@@ -96,6 +96,8 @@ def lib():
         "fh_ilu0": (i, [vp, vp, d, d, vp]),
         "fh_ilu0_apply": (i, [vp, vp, d, d, i, i, vp, vp]),
         "fh_shifted_solve": (i, [vp, vp, i, dp, ip, i, C.POINTER(fh_opts), vp, vp, C.POINTER(fh_report)]),
+        "fh_feast_batched": (i, [vp, i, C.POINTER(vp), C.POINTER(fh_contour), C.POINTER(fh_opts), C.POINTER(vp),
+                                 C.POINTER(vp), C.POINTER(vp), C.POINTER(dp), C.POINTER(fh_report)]),
         "fh_net_create": (i, [vp, i, i, i, dp, d, d, C.c_ulonglong, C.POINTER(vp)]),
         "fh_net_destroy": (i, [vp]),
         "fh_net_param_count": (i, [vp]),
@@ -314,6 +316,43 @@ def feast(prob: Problem, center, a, ratio=1.0, angle=0.0, ne=8, Y0=None, Yh0=Non
     m, mt = rep.m, rep.m0_final
     return {"info": rc, "lam": lam[:m].cpu().numpy(), "X": Y[:, :m], "Xh": Yh[:, :m], "res": res[:m],
             "report": rep.as_dict(), "Y": Y[:, :mt], "Yh": Yh[:, :mt], "ritz": lam[:mt], "ritz_res": res[:mt]}
+
+
+def feast_batched(probs, contours, Y0s, Yh0s, opts: fh_opts):
+    """FEAST on many dense problems at once (fh_feast_batched).
+
+    contours: list of (center, a, ratio, angle, ne); Y0s, Yh0s: lists of
+    complex128 CUDA tensors (n_i, m0).  Returns (status, list of dicts as
+    feast())."""
+    torch = _torch()
+    k = len(probs)
+    m0 = opts.m0
+    Ys = [Y.clone() for Y in Y0s]
+    Yhs = [Y.clone() for Y in Yh0s]
+    for i in range(k):
+        _check_block(Ys[i], probs[i].n, "Y0")
+        _check_block(Yhs[i], probs[i].n, "Yh0")
+    lams = [torch.zeros(m0, dtype=torch.complex128, device=Ys[i].device) for i in range(k)]
+    res = [np.zeros(m0) for _ in range(k)]
+    cs = (fh_contour * k)(*[fh_contour(complex(c[0]).real, complex(c[0]).imag, c[1], c[2], c[3], c[4])
+                            for c in contours])
+    vp = C.c_void_p
+    pa = (vp * k)(*[p._p.value for p in probs])
+    ya = (vp * k)(*[Y.data_ptr() for Y in Ys])
+    yha = (vp * k)(*[Y.data_ptr() for Y in Yhs])
+    la = (vp * k)(*[l.data_ptr() for l in lams])
+    ra = (C.POINTER(C.c_double) * k)(*[r.ctypes.data_as(C.POINTER(C.c_double)) for r in res])
+    reps = (fh_report * k)()
+    h = probs[0].handle
+    rc = lib().fh_feast_batched(h._h, k, pa, cs, C.byref(opts), ya, yha, la, ra, reps)
+    if rc < 0 or rc >= 4:
+        h.check(rc, "fh_feast_batched")
+    out = []
+    for i in range(k):
+        m, mt = reps[i].m, reps[i].m0_final
+        out.append({"info": reps[i].info, "lam": lams[i][:m].cpu().numpy(), "X": Ys[i][:, :m], "Xh": Yhs[i][:, :m],
+                    "res": res[i][:m], "report": reps[i].as_dict(), "Y": Ys[i][:, :mt], "Yh": Yhs[i][:, :mt]})
+    return rc, out
 
 
 def reduced_matrix(prob: Problem, Qh, Q):

@@ -22,6 +22,8 @@ namespace fh {
 Prob::~Prob() {
     if (sp) sparse_destroy(sp);
     sp = nullptr;
+    if (dg) dg_destroy(dg);
+    dg = nullptr;
 }
 }  // namespace fh
 
@@ -366,6 +368,42 @@ int fh_ilu0_apply(fh_handle h, fh_problem p, double z_re, double z_im, int side,
     sparse_ilu0_apply(*h, *p, cplx(z_re, z_im), side, m, (const zd*)X, (zd*)Out);
     FH_HIP(hipStreamSynchronize(h->stream));
     return FH_OK;
+    FH_API_END(h)
+}
+
+int fh_feast_batched(fh_handle h, int count, const fh_problem* problems, const fh_contour* contours,
+                     const fh_opts* o, void* const* Y, void* const* Yh, void* const* lambda, double* const* res,
+                     fh_report* reports) {
+    if (!h) return -1;
+    if (count < 1) return -2;
+    if (!problems) return -3;
+    if (!contours) return -4;
+    if (!o || o->m0 < 1 || o->m0 > 1024 || o->max_iter < 1 || !(o->eps > 0)) return -5;
+    if (o->precision != FH_PREC_FP64 && o->precision != FH_PREC_MIXED) return -5;
+    if (!Y) return -6;
+    if (!Yh) return -7;
+    if (!lambda) return -8;
+    for (int i = 0; i < count; ++i) {
+        if (!problems[i] || !problems[i]->dense || o->m0 > problems[i]->n) return -3;
+        const fh_contour& c = contours[i];
+        if (c.ne < 1 || !(c.a > 0) || !(c.ratio > 0)) return -4;
+        if (!Y[i]) return -6;
+        if (!Yh[i]) return -7;
+        if (!lambda[i]) return -8;
+    }
+    FH_API_BEGIN(h)
+    set_device(h);
+    std::vector<Prob*> ps(count);
+    std::vector<zd*> y(count), yh(count), l(count);
+    std::vector<double*> r(count, nullptr);
+    for (int i = 0; i < count; ++i) {
+        ps[i] = problems[i];
+        y[i] = (zd*)Y[i];
+        yh[i] = (zd*)Yh[i];
+        l[i] = (zd*)lambda[i];
+        if (res) r[i] = res[i];
+    }
+    return feast_batched(*h, count, ps.data(), contours, *o, y.data(), yh.data(), l.data(), r.data(), reports);
     FH_API_END(h)
 }
 

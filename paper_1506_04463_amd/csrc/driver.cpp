@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 
+#include "fh_dgroup.h"
 #include "fh_internal.h"
 
 namespace fh {
@@ -123,6 +124,8 @@ void filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m0, const
     auto t0 = std::chrono::steady_clock::now();
     if (!p.dense) {
         sparse_filter(c, p, ne, z, w, m0, Y, Yh, Q, Qh, o, rep, lam);
+    } else if (o.precision == FH_PREC_MIXED) {
+        dense_filter_group(c, p, ne, z, w, m0, Y, Yh, Q, Qh, o, rep);
     } else {
         const int n = p.n;
         const size_t blk = (size_t)n * m0;
@@ -173,63 +176,87 @@ void dense_shifted_solve(Ctx& c, Prob& p, int nsys, int nright, const cplx* z, i
 // FEAST (complete algorithm figure)
 // ---------------------------------------------------------------------------
 
-int feast(Ctx& c, Prob& p, const fh_contour& ct, const cplx* zin, const cplx* win, const fh_opts& o, zd* Yio,
-          zd* Yhio, zd* lambda, double* res_out, fh_report* rep) {
-    const int n = p.n, m0in = o.m0, ne = ct.ne;
+// One FEAST run (complete algorithm figure) as a state machine: the caller
+// fills Q and Qh by the contour filter (step 1) from Ycur / Yhcur, then
+// step() performs steps 2-5; finish() writes the outputs (step 5.d).
+struct FeastRun {
+    Ctx& c;
+    Prob& p;
+    fh_contour ct;
+    fh_opts o;
+    fh_report* rep;
+    FeastBufs& B;
     std::vector<cplx> z, w;
-    if (zin) { z.assign(zin, zin + ne); w.assign(win, win + ne); }
-    else contour_nodes(ct, z, w);
-    const double alpha = std::abs(cplx(ct.c_re, ct.c_im)) + std::max(ct.a, ct.ratio * ct.a);
-    FeastBufs& B = c.sb;
-    const size_t big = (size_t)n * m0in;
-    zd* Ycur = (zd*)B.Ycur.ensure(sizeof(zd) * big);
-    zd* Yhcur = (zd*)B.Yhcur.ensure(sizeof(zd) * big);
-    zd* Q = (zd*)B.Q.ensure(sizeof(zd) * big);
-    zd* Qh = (zd*)B.Qh.ensure(sizeof(zd) * big);
-    zd* U = (zd*)B.U.ensure(sizeof(zd) * big);
-    zd* Uh = (zd*)B.Uh.ensure(sizeof(zd) * big);
-    zd* T1 = (zd*)B.T1.ensure(sizeof(zd) * big);
-    zd* T2 = (zd*)B.T2.ensure(sizeof(zd) * big);
-    const size_t sm = (size_t)m0in * m0in;
-    zd* BQ = (zd*)B.BQ.ensure(sizeof(zd) * sm);
-    zd* S = (zd*)B.S.ensure(sizeof(zd) * sm);
-    zd* Sh = (zd*)B.Sh.ensure(sizeof(zd) * sm);
-    zd* gam = (zd*)B.gam.ensure(sizeof(zd) * m0in);
-    zd* AUr = (zd*)B.AUr.ensure(sizeof(zd) * sm);
-    zd* BUr = (zd*)B.BUr.ensure(sizeof(zd) * sm);
-    zd* lam = (zd*)B.lam.ensure(sizeof(zd) * m0in);
-    zd* W = (zd*)B.W.ensure(sizeof(zd) * sm);
-    zd* Wh = (zd*)B.Wh.ensure(sizeof(zd) * sm);
-    double* num = (double*)B.num.ensure(sizeof(double) * m0in);
-    double* den = (double*)B.den.ensure(sizeof(double) * m0in);
-    double* num2 = (double*)B.num2.ensure(sizeof(double) * m0in);
-    double* den2 = (double*)B.den2.ensure(sizeof(double) * m0in);
-    int* ints = (int*)B.ints.ensure(sizeof(int) * 4);
-    int* perm = (int*)B.perm.ensure(sizeof(int) * m0in);
-
-    // step 0: start subspaces
-    FH_HIP(hipMemcpyAsync(Ycur, Yio, sizeof(zd) * big, hipMemcpyDeviceToDevice, c.stream));
-    FH_HIP(hipMemcpyAsync(Yhcur, Yhio, sizeof(zd) * big, hipMemcpyDeviceToDevice, c.stream));
-
-    int mcur = m0in;
-    std::vector<cplx> rho_prev, hlam(m0in), hbq(sm), rho(m0in);
-    if (o.resume) {
-        // the start columns are Ritz vectors whose values are passed in lambda
-        to_host(c, reinterpret_cast<zd*>(hlam.data()), lambda, m0in);
-    }
-    std::vector<char> inside_prev, inside(m0in);
-    std::vector<double> res(m0in), hn(m0in), hd(m0in), hn2(m0in), hd2(m0in);
-    int info = FH_NOT_CONVERGED, m_out = 0, it = 0, m_s = 0;
+    int n, m0in, ne;
+    double alpha;
+    zd *Ycur, *Yhcur, *Q, *Qh, *U, *Uh, *T1, *T2, *BQ, *S, *Sh, *gam, *AUr, *BUr, *lam, *W, *Wh;
+    double *num, *den, *num2, *den2;
+    int *ints, *perm;
+    int mcur = 0, it = 0, info = FH_NOT_CONVERGED, m_s = 0, prev_nconv = -1;
+    bool converged = false, prev_pass = false, done = false;
+    std::vector<cplx> rho_prev, hlam, hbq, rho;
+    std::vector<char> inside_prev, inside;
+    std::vector<double> res, hn, hd, hn2, hd2;
     std::vector<int> sel;
-    bool converged = false, prev_pass = false;
-    int prev_nconv = -1;
-    for (it = 1; it <= o.max_iter; ++it) {
-        auto t0 = std::chrono::steady_clock::now();
-        // step 1: contour integration
-        // Ritz values of the current columns enable the residual form of the
-        // iterative filter from the second iteration on
-        filter(c, p, ne, z.data(), w.data(), mcur, Ycur, Yhcur, Q, Qh, o, rep,
-               ((it >= 2 || o.resume) && !p.dense) ? hlam.data() : nullptr);
+    std::chrono::steady_clock::time_point t0;
+
+    FeastRun(Ctx& c_, Prob& p_, FeastBufs& bufs, const fh_contour& ct_, const cplx* zin, const cplx* win,
+             const fh_opts& o_, const zd* Yio, const zd* Yhio, const zd* lambda, fh_report* rep_)
+        : c(c_), p(p_), ct(ct_), o(o_), rep(rep_), B(bufs) {
+        n = p.n;
+        m0in = o.m0;
+        ne = ct.ne;
+        if (zin) { z.assign(zin, zin + ne); w.assign(win, win + ne); }
+        else contour_nodes(ct, z, w);
+        alpha = std::abs(cplx(ct.c_re, ct.c_im)) + std::max(ct.a, ct.ratio * ct.a);
+        const size_t big = (size_t)n * m0in, sm = (size_t)m0in * m0in;
+        Ycur = (zd*)B.Ycur.ensure(sizeof(zd) * big);
+        Yhcur = (zd*)B.Yhcur.ensure(sizeof(zd) * big);
+        Q = (zd*)B.Q.ensure(sizeof(zd) * big);
+        Qh = (zd*)B.Qh.ensure(sizeof(zd) * big);
+        U = (zd*)B.U.ensure(sizeof(zd) * big);
+        Uh = (zd*)B.Uh.ensure(sizeof(zd) * big);
+        T1 = (zd*)B.T1.ensure(sizeof(zd) * big);
+        T2 = (zd*)B.T2.ensure(sizeof(zd) * big);
+        BQ = (zd*)B.BQ.ensure(sizeof(zd) * sm);
+        S = (zd*)B.S.ensure(sizeof(zd) * sm);
+        Sh = (zd*)B.Sh.ensure(sizeof(zd) * sm);
+        gam = (zd*)B.gam.ensure(sizeof(zd) * m0in);
+        AUr = (zd*)B.AUr.ensure(sizeof(zd) * sm);
+        BUr = (zd*)B.BUr.ensure(sizeof(zd) * sm);
+        lam = (zd*)B.lam.ensure(sizeof(zd) * m0in);
+        W = (zd*)B.W.ensure(sizeof(zd) * sm);
+        Wh = (zd*)B.Wh.ensure(sizeof(zd) * sm);
+        num = (double*)B.num.ensure(sizeof(double) * m0in);
+        den = (double*)B.den.ensure(sizeof(double) * m0in);
+        num2 = (double*)B.num2.ensure(sizeof(double) * m0in);
+        den2 = (double*)B.den2.ensure(sizeof(double) * m0in);
+        ints = (int*)B.ints.ensure(sizeof(int) * 4);
+        perm = (int*)B.perm.ensure(sizeof(int) * m0in);
+        // step 0: start subspaces
+        FH_HIP(hipMemcpyAsync(Ycur, Yio, sizeof(zd) * big, hipMemcpyDeviceToDevice, c.stream));
+        FH_HIP(hipMemcpyAsync(Yhcur, Yhio, sizeof(zd) * big, hipMemcpyDeviceToDevice, c.stream));
+        mcur = m0in;
+        hlam.assign(m0in, 0.0);
+        hbq.assign(sm, 0.0);
+        rho.assign(m0in, 0.0);
+        inside.assign(m0in, 0);
+        res.assign(m0in, 0.0);
+        hn.assign(m0in, 0.0);
+        hd.assign(m0in, 0.0);
+        hn2.assign(m0in, 0.0);
+        hd2.assign(m0in, 0.0);
+        // resume: the start columns are Ritz vectors whose values are passed in lambda
+        if (o.resume) to_host(c, reinterpret_cast<zd*>(hlam.data()), lambda, m0in);
+    }
+
+    // Ritz values of the current columns (residual form of the iterative
+    // filter from the second iteration on), or nullptr
+    const cplx* filter_lambda() const { return ((it >= 1 || o.resume) && !p.dense) ? hlam.data() : nullptr; }
+
+    // steps 2-5 of iteration it+1 (Q, Qh filled); true when the run is over
+    bool step() {
+        ++it;
         // step 2.a: B_Q = Qh^H B Q
         const zd* BQin = Q;
         if (p.hasB) { apply_B(c, p, 0, mcur, Q, T1); BQin = T1; }
@@ -334,45 +361,152 @@ int feast(Ctx& c, Prob& p, const fh_contour& ct, const cplx* zin, const cplx* wi
             rep->m = (int)sel.size();
             rep->t_iter_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         }
-        if (converged) { info = FH_OK; break; }
+        if (converged) {
+            info = FH_OK;
+            done = true;
+            return true;
+        }
         rho_prev.assign(rho.begin(), rho.begin() + mt);
         inside_prev.assign(inside.begin(), inside.begin() + mt);
-        if (it == o.max_iter) info = (m_r == 0) ? FH_NO_EIG_INSIDE : FH_NOT_CONVERGED;
+        if (it == o.max_iter) {
+            info = (m_r == 0) ? FH_NO_EIG_INSIDE : FH_NOT_CONVERGED;
+            done = true;
+            return true;
+        }
+        return false;
     }
-    if (it > o.max_iter) it = o.max_iter;
+
     // step 5.d: the converged pairs in the first m columns, sorted by (Re, Im).
     // Every inside pair whose residual meets eps is returned (flagged spurious
     // pairs never converge, so this is the spurious-free set).  The remaining
     // Ritz vectors follow in columns m..m0_final-1 so that the whole search
     // subspace can be reused as a start (resume).
-    if (converged) {
+    int finish(zd* Yio, zd* Yhio, zd* lambda, double* res_out) {
+        if (converged) {
+            for (int i = 0; i < mcur; ++i)
+                if (inside[i] && res[i] < o.eps && std::find(sel.begin(), sel.end(), i) == sel.end()) sel.push_back(i);
+        }
+        std::stable_sort(sel.begin(), sel.end(), [&](int a, int b) {
+            if (hlam[a].real() != hlam[b].real()) return hlam[a].real() < hlam[b].real();
+            return hlam[a].imag() < hlam[b].imag();
+        });
+        const int m_out = converged ? (int)sel.size() : 0;
+        std::vector<int> order(sel.begin(), sel.end());
         for (int i = 0; i < mcur; ++i)
-            if (inside[i] && res[i] < o.eps && std::find(sel.begin(), sel.end(), i) == sel.end()) sel.push_back(i);
-    }
-    std::stable_sort(sel.begin(), sel.end(), [&](int a, int b) {
-        if (hlam[a].real() != hlam[b].real()) return hlam[a].real() < hlam[b].real();
-        return hlam[a].imag() < hlam[b].imag();
-    });
-    m_out = converged ? (int)sel.size() : 0;
-    std::vector<int> order(sel.begin(), sel.end());
-    for (int i = 0; i < mcur; ++i)
-        if (std::find(order.begin(), order.end(), i) == order.end()) order.push_back(i);
-    to_dev(c, perm, order.data(), mcur);
-    gather_cols(c.stream, n, mcur, Ycur, mcur, perm, Yio, m0in);
-    gather_cols(c.stream, n, mcur, Yhcur, mcur, perm, Yhio, m0in);
-    {
+            if (std::find(order.begin(), order.end(), i) == order.end()) order.push_back(i);
+        to_dev(c, perm, order.data(), mcur);
+        gather_cols(c.stream, n, mcur, Ycur, mcur, perm, Yio, m0in);
+        gather_cols(c.stream, n, mcur, Yhcur, mcur, perm, Yhio, m0in);
         std::vector<cplx> lo(mcur);
         for (int k = 0; k < mcur; ++k) lo[k] = hlam[order[k]];
         to_dev(c, lambda, reinterpret_cast<const zd*>(lo.data()), mcur);
         if (res_out)
             for (int k = 0; k < mcur; ++k) res_out[k] = res[order[k]];
+        sync(c);
+        if (rep) {
+            rep->m = m_out;
+            rep->info = info;
+        }
+        return info;
     }
-    sync(c);
-    if (rep) {
-        rep->m = m_out;
-        rep->info = info;
+};
+
+int feast(Ctx& c, Prob& p, const fh_contour& ct, const cplx* zin, const cplx* win, const fh_opts& o, zd* Yio,
+          zd* Yhio, zd* lambda, double* res_out, fh_report* rep) {
+    FeastRun r(c, p, c.sb, ct, zin, win, o, Yio, Yhio, lambda, rep);
+    for (;;) {
+        r.t0 = std::chrono::steady_clock::now();
+        // step 1: contour integration
+        filter(c, p, r.ne, r.z.data(), r.w.data(), r.mcur, r.Ycur, r.Yhcur, r.Q, r.Qh, o, rep, r.filter_lambda());
+        if (r.step()) break;
     }
-    return info;
+    return r.finish(Yio, Yhio, lambda, res_out);
+}
+
+// Many dense instances at once: the contour filters of all instances (every
+// node, both sides) run through one grouped engine per iteration, factors
+// computed once for all instances; steps 2-5 run per instance.
+int feast_batched(Ctx& c, int count, Prob* const* probs, const fh_contour* cts, const fh_opts& o, zd* const* Y,
+                  zd* const* Yh, zd* const* lambda, double* const* res, fh_report* reps) {
+    hipStream_t st = c.stream;
+    std::vector<std::unique_ptr<FeastBufs>> bufs;
+    std::vector<std::unique_ptr<FeastRun>> runs;
+    std::vector<Prob*> plist(probs, probs + count);
+    std::vector<std::vector<cplx>> zs;
+    for (int i = 0; i < count; ++i) {
+        bufs.emplace_back(new FeastBufs());
+        if (reps) std::memset(&reps[i], 0, sizeof(fh_report));
+        runs.emplace_back(new FeastRun(c, *probs[i], *bufs[i], cts[i], nullptr, nullptr, o, Y[i], Yh[i], lambda[i],
+                                       reps ? &reps[i] : nullptr));
+        zs.push_back(runs[i]->z);
+    }
+    DenseGroup G;
+    fh_report frep{};
+    dg_build(c, G, plist, zs, o.precision == FH_PREC_MIXED, &frep);
+    std::vector<int> first(count);   // first system of each instance
+    for (int i = 0, s = 0; i < count; ++i) {
+        first[i] = s;
+        s += cts[i].ne;
+    }
+    std::vector<DBuf> wdev(count);
+    for (int i = 0; i < count; ++i) {
+        zd* wd = (zd*)wdev[i].ensure(sizeof(zd) * cts[i].ne);
+        to_dev(c, wd, reinterpret_cast<const zd*>(runs[i]->w.data()), cts[i].ne);
+        if (reps) reps[i].n_factor = cts[i].ne;
+    }
+    for (;;) {
+        std::vector<int> m(G.count, 0);
+        int active = 0;
+        for (int i = 0; i < count; ++i) {
+            if (runs[i]->done) continue;
+            ++active;
+            for (int j = 0; j < cts[i].ne; ++j) m[first[i] + j] = runs[i]->mcur;
+        }
+        if (!active) break;
+        auto t0 = std::chrono::steady_clock::now();
+        dg_layout(c, G, m);
+        // right-hand sides B Y_i and B^H Yh_i, replicated over the nodes of instance i
+        for (int i = 0; i < count; ++i) {
+            FeastRun& r = *runs[i];
+            if (r.done) continue;
+            r.t0 = t0;
+            const long blk = (long)r.n * r.mcur;
+            const long off = G.voff[first[i]];
+            apply_B(c, r.p, 0, r.mcur, r.Ycur, r.T1);
+            replicate<double>(st, blk, r.T1, (zd*)G.Bv.p + off, r.ne);
+            apply_B(c, r.p, 1, r.mcur, r.Yhcur, r.T1);
+            replicate<double>(st, blk, r.T1, (zd*)G.Bhv.p + off, r.ne);
+        }
+        fh_report srep{};
+        dg_solve(c, G, o, &srep);
+        for (int i = 0; i < count; ++i) {
+            FeastRun& r = *runs[i];
+            if (r.done) continue;
+            const long blk = (long)r.n * r.mcur;
+            const long off = G.voff[first[i]];
+            accumulate(st, r.ne, blk, (const zd*)G.Xv.p + off, blk, (const zd*)wdev[i].p, false, r.Q);
+            accumulate(st, r.ne, blk, (const zd*)G.Xhv.p + off, blk, (const zd*)wdev[i].p, true, r.Qh);
+        }
+        sync(c);
+        const double tf = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        for (int i = 0; i < count; ++i) {
+            FeastRun& r = *runs[i];
+            if (r.done) continue;
+            if (reps) {
+                reps[i].n_solve += 2 * r.ne;
+                reps[i].t_filter_ms = tf;
+                reps[i].inner_steps = srep.inner_steps;
+                reps[i].inner_relres = srep.inner_relres;
+            }
+            r.step();
+        }
+    }
+    int worst = FH_OK;
+    for (int i = 0; i < count; ++i) {
+        const int inf = runs[i]->finish(Y[i], Yh[i], lambda[i], res ? res[i] : nullptr);
+        if (inf != FH_OK && worst == FH_OK) worst = inf;
+    }
+    return worst;
 }
 
 }  // namespace fh

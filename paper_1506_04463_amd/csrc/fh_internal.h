@@ -1,6 +1,7 @@
 // Internal state of handles and prepared problems.
 #pragma once
 #include <complex>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -13,6 +14,7 @@ namespace fh {
 
 struct SparseState;   // k_sparse.hip / sparse.cpp
 struct NetState;      // k_net.hip / net.cpp
+struct DenseGroup;    // k_group.hip / dgroup.cpp
 
 struct FilterBufs {
     DBuf X, Xh, R, Rh, wdev, zdev;
@@ -32,6 +34,9 @@ struct Ctx {
     FeastBufs sb;
     bool prof_on = false;
     Prof prof;
+    // autotuned grouped-GEMM tiles per shape class, and their probe scratch
+    std::map<std::string, int> tuned;
+    DBuf tune_scratch;
 };
 
 // makes the handle's profiler current on this thread for the duration of a call
@@ -50,6 +55,8 @@ struct Prob {
     // dense: cached LU of (z_j B - A) for the node set fact_z
     std::vector<std::complex<double>> fact_z;
     DBuf lu, ipiv, info;
+    // dense grouped factors (complex-FP32 path)
+    DenseGroup* dg = nullptr;
     // sparse state (CSR)
     SparseState* sp = nullptr;
     ~Prob();
@@ -78,6 +85,11 @@ void sparse_destroy(SparseState* s);
 void sparse_shifted_solve(Ctx& c, Prob& p, int nsys, const cplx* z, const int* sides, int m, const zd* B, zd* X,
                           const fh_opts& o, fh_report* rep);
 void sparse_set_net(Prob& p, NetState* net);
+void dg_destroy(DenseGroup* g);
+void dense_filter_group(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m0, const zd* Y, const zd* Yh,
+                        zd* Q, zd* Qh, const fh_opts& o, fh_report* rep);
+int feast_batched(Ctx& c, int count, Prob* const* probs, const fh_contour* cts, const fh_opts& o, zd* const* Y,
+                  zd* const* Yh, zd* const* lambda, double* const* res, fh_report* reps);
 void dense_shifted_solve(Ctx& c, Prob& p, int nsys, int nright, const cplx* z, int m, const zd* B, zd* X,
                          const fh_opts& o, fh_report* rep);
 

@@ -1,0 +1,138 @@
+"""The grouped dense engine through the C ABI: the complex-FP32 contour filter
+(LU and solves in complex FP32 with GEMM updates on MFMA, FP64 iterative
+refinement of every solve) against the FP64 oracle, and FEAST on a batch of
+dense generalized problems of different sizes (all filters in shared grouped
+launches) against the oracle, in FP64 and in complex FP32 + refinement."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import contour as ct
+from oracle import feast as F
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+fh = pytest.importorskip("paper_1506_04463_amd")
+
+
+@pytest.fixture(scope="module")
+def handle():
+    return fh.Handle(0)
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _kappa_max(A, B, z):
+    n = A.shape[0]
+    Bm = np.eye(n) if B is None else B
+    return max(np.linalg.cond(zj * Bm - A) for zj in z)
+
+
+@pytest.mark.parametrize("n,m0,ne,gen", [(150, 16, 8, False), (97, 13, 5, True), (33, 7, 3, True),
+                                         (257, 40, 4, False), (1, 1, 4, False), (64, 64, 8, True)])
+def test_mixed_filter_matches_oracle(handle, n, m0, ne, gen):
+    """Refined to inner_tol = 1e-12: the filter output matches the FP64
+    oracle to the conditioning of the shifted systems."""
+    rng = np.random.default_rng(n + 7 * m0)
+    A = np.array([[0.05 + 0.02j]]) if n == 1 else W.dense_prescribed(n=n, n_in=min(6, n // 2), m0=m0, ne=ne,
+                                                                       seed=n).A
+    B = None
+    if gen:
+        B = np.eye(n) + 0.1 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2 * n)
+    z, w = ct.ellipse_nodes(0.1 + 0.1j, 0.25, 0.7, 0.3, ne)
+    Y, Yh = W.subspace(n, m0, 1), W.subspace(n, m0, 2)
+    Qo, Qho = F.contour_filter(A, B, z, w, Y, Yh)
+    prob = fh.Problem(handle, _cuda(A), None if B is None else _cuda(B))
+    o = fh.default_opts(m0, precision=fh.FH_PREC_MIXED, inner_tol=1e-12, max_refine=10)
+    Q, Qh, rep = fh.contour_filter(prob, z, w, _cuda(Y), _cuda(Yh), o)
+    Q, Qh = Q.cpu().numpy(), Qh.cpu().numpy()
+    tol = 1000 * _kappa_max(A, B, z) * np.finfo(float).eps
+    assert np.linalg.norm(Q - Qo) / np.linalg.norm(Qo) < tol
+    assert np.linalg.norm(Qh - Qho) / np.linalg.norm(Qho) < tol
+    # refinement stops at 1e-12 or at the FP64 rounding floor of the residual
+    assert rep["inner_relres"] <= max(1e-12, tol)
+    assert 1 <= rep["inner_steps"] <= 10
+    assert rep["n_factor"] == ne
+
+
+def test_mixed_filter_single_step_is_fp32_accurate(handle):
+    """One refinement step is a plain complex-FP32 solve: its relative
+    residual is at the FP32 level, far above FP64's, which the next steps
+    remove (the per-result error statement of the mixed path)."""
+    p = W.dense_prescribed(n=300, n_in=6, m0=16, seed=4)
+    z, w = ct.ellipse_nodes(p.contour.center, p.contour.a, 1.0, 0.0, 8)
+    prob = fh.Problem(handle, _cuda(p.A))
+    Y, Yh = _cuda(p.Y0[:, :16]), _cuda(p.Yh0[:, :16])
+    _, _, r1 = fh.contour_filter(prob, z, w, Y, Yh, fh.default_opts(16, precision=fh.FH_PREC_MIXED, max_refine=1,
+                                                                     save_factors=0))
+    _, _, r3 = fh.contour_filter(prob, z, w, Y, Yh, fh.default_opts(16, precision=fh.FH_PREC_MIXED, max_refine=4,
+                                                                     inner_tol=1e-13, save_factors=0))
+    assert 1e-9 < r1["inner_relres"] < 1e-2
+    assert r3["inner_relres"] < 1e-12
+
+
+def test_mixed_feast_first_config(handle):
+    """Dense n = 400, 24 eigenvalues: complex-FP32 LU + FP64 refinement gives
+    the FP64 eigenvalues (relative error 1e-10) and residuals."""
+    p = W.dense_prescribed()
+    cont = F.Contour(p.contour.center, p.contour.a, 1.0, 0.0, 8)
+    prob = fh.Problem(handle, _cuda(p.A))
+    out = fh.feast(prob, p.contour.center, p.contour.a, 1.0, 0.0, 8, _cuda(p.Y0), _cuda(p.Yh0),
+                   fh.default_opts(36, eps=1e-12, max_iter=60, precision=fh.FH_PREC_MIXED, inner_tol=1e-12))
+    assert out["info"] == 0 and len(out["lam"]) == 24
+    lam_true = p.info["lam"][:24]
+    lam_true = lam_true[np.lexsort((lam_true.imag, lam_true.real))]
+    assert np.max(np.abs(out["lam"] - lam_true) / np.abs(lam_true)) < 1e-10
+    X = out["X"].cpu().numpy()
+    r = np.linalg.norm(p.A @ X - X * out["lam"][None, :], axis=0) / (np.linalg.norm(p.A, 2) * np.linalg.norm(X, axis=0))
+    assert r.max() < 1e-10
+
+
+def _batch(count, nmin, nmax, seed, m0=12, ne=8):
+    probs = W.gen_dense_batch(count=count, nmin=nmin, nmax=nmax, ne=ne, m0=m0, seed=seed)
+    # a radius holding a few eigenvalues of each instance (the subspace must hold them all)
+    out = []
+    for p in probs:
+        ev = np.linalg.eigvals(np.linalg.solve(p.B, p.A))
+        d = np.sort(np.abs(ev - p.contour.center))
+        r = 0.5 * (d[3] + d[4])
+        out.append((p, r))
+    return out
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_feast_batched_uneven_matches_oracle(handle, prec):
+    batch = _batch(5, 40, 230, seed=11)
+    m0 = 12
+    probs = [fh.Problem(handle, _cuda(p.A), _cuda(p.B)) for p, r in batch]
+    conts = [(p.contour.center, r, 1.0, 0.0, 8) for p, r in batch]
+    o = fh.default_opts(m0, eps=1e-12, max_iter=40, precision=prec, inner_tol=1e-12, max_refine=10)
+    rc, outs = fh.feast_batched(probs, conts, [_cuda(p.Y0) for p, r in batch], [_cuda(p.Yh0) for p, r in batch], o)
+    assert rc == 0
+    for (p, r), out in zip(batch, outs):
+        cont = F.Contour(p.contour.center, r, 1.0, 0.0, 8)
+        ref = F.feast(p.A, p.B, cont, p.Y0, p.Yh0, eps=1e-12, max_iter=40)
+        assert ref.info == 0 and out["info"] == 0
+        assert len(out["lam"]) == len(ref.lam) == 4
+        np.testing.assert_allclose(out["lam"], ref.lam, rtol=1e-10, atol=1e-12)
+        X, Xh = out["X"].cpu().numpy(), out["Xh"].cpu().numpy()
+        np.testing.assert_allclose(Xh.conj().T @ p.B @ X, np.eye(4), atol=1e-9)
+        assert np.all(out["res"] < 1e-12)
+        assert out["report"]["n_factor"] == 8
+
+
+def test_feast_batched_equals_single_runs(handle):
+    """The batch gives each instance what fh_feast gives it alone."""
+    batch = _batch(3, 60, 120, seed=5)
+    m0 = 12
+    probs = [fh.Problem(handle, _cuda(p.A), _cuda(p.B)) for p, r in batch]
+    conts = [(p.contour.center, r, 1.0, 0.0, 8) for p, r in batch]
+    o = fh.default_opts(m0, eps=1e-12, max_iter=40)
+    rc, outs = fh.feast_batched(probs, conts, [_cuda(p.Y0) for p, r in batch], [_cuda(p.Yh0) for p, r in batch], o)
+    for (p, r), pr, out in zip(batch, probs, outs):
+        single = fh.feast(pr, p.contour.center, r, 1.0, 0.0, 8, _cuda(p.Y0), _cuda(p.Yh0), o)
+        assert out["report"]["iters"] == single["report"]["iters"]
+        np.testing.assert_allclose(out["lam"], single["lam"], rtol=1e-12, atol=1e-14)
