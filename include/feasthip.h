@@ -105,6 +105,9 @@ typedef struct {
                              for the rest of a solve when a restart cycle with
                              the network cuts the worst relative residual by
                              less than half (FH_PC_NONE, _JACOBI or _ILU0)    */
+    int graph;            /* dense grouped solves (fh_feast_batched, mixed dense
+                             filter): 1 = capture each solve / refinement step
+                             into a HIP graph once per layout and replay it   */
 } fh_opts;
 
 typedef struct {

@@ -2,6 +2,7 @@
 // the grouped complex-FP32 GEMM.
 #include <algorithm>
 #include <cstring>
+#include <functional>
 
 #include "fh_dgroup.h"
 
@@ -133,6 +134,7 @@ void dg_build(Ctx& c, DenseGroup& G, const std::vector<Prob*>& probs,
             throw Error(FH_SINGULAR_SHIFT, "zero pivot in the LU of (z B - A) of grouped system " + std::to_string(s));
         }
     G.layout_vtot = -1;   // plans point at the factors: rebuild
+    G.drop_graphs();
 }
 
 void dg_layout(Ctx& c, DenseGroup& G, const std::vector<int>& m) {
@@ -172,6 +174,7 @@ void dg_layout(Ctx& c, DenseGroup& G, const std::vector<int>& m) {
     for (int q = 0; q < 4; ++q) same = same && key[q] == G.layout_key[q];
     if (same) return;
     FH_HIP(hipStreamSynchronize(c.stream));   // earlier solves may still read the old plans
+    G.drop_graphs();
     // device layout arrays
     std::vector<int> len(cnt);
     for (int s = 0; s < cnt; ++s) len[s] = G.n[s] * m[s];
@@ -260,8 +263,42 @@ void dense_filter_group(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, i
     FH_HIP(hipStreamSynchronize(st));
 }
 
+// Run body(stream) through a HIP graph: captured on the handle's capture
+// stream the first time (profiling off meanwhile), replayed afterwards, and
+// ordered after / before the work of the handle's stream by events.
+static void run_graph(Ctx& c, hipGraphExec_t& exec, const std::function<void(hipStream_t)>& body) {
+    if (!c.gstream) {
+        FH_HIP(hipStreamCreateWithFlags(&c.gstream, hipStreamNonBlocking));
+        FH_HIP(hipEventCreateWithFlags(&c.gev[0], hipEventDisableTiming));
+        FH_HIP(hipEventCreateWithFlags(&c.gev[1], hipEventDisableTiming));
+    }
+    if (!exec) {
+        Prof* saved = tl_prof();
+        tl_prof() = nullptr;
+        FH_HIP(hipStreamBeginCapture(c.gstream, hipStreamCaptureModeThreadLocal));
+        hipGraph_t g = nullptr;
+        try {
+            body(c.gstream);
+        } catch (...) {
+            (void)hipStreamEndCapture(c.gstream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            tl_prof() = saved;
+            throw;
+        }
+        FH_HIP(hipStreamEndCapture(c.gstream, &g));
+        tl_prof() = saved;
+        const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        FH_HIP(e);
+    }
+    FH_HIP(hipEventRecord(c.gev[0], c.stream));
+    FH_HIP(hipStreamWaitEvent(c.gstream, c.gev[0], 0));
+    FH_HIP(hipGraphLaunch(exec, c.gstream));
+    FH_HIP(hipEventRecord(c.gev[1], c.gstream));
+    FH_HIP(hipStreamWaitEvent(c.stream, c.gev[1], 0));
+}
+
 double dg_solve(Ctx& c, DenseGroup& G, const fh_opts& o, fh_report* rep) {
-    hipStream_t st = c.stream;
     const long tot = G.vtot;
     const int cnt = G.count;
     zd* Bv = (zd*)G.Bv.p;
@@ -270,12 +307,17 @@ double dg_solve(Ctx& c, DenseGroup& G, const fh_opts& o, fh_report* rep) {
     zd* Xhv = (zd*)G.Xhv.p;
     if (rep) rep->n_solve += 2 * cnt;
     if (!G.mixed) {
-        FH_HIP(hipMemcpyAsync(Xv, Bv, sizeof(zd) * tot, hipMemcpyDeviceToDevice, st));
-        FH_HIP(hipMemcpyAsync(Xhv, Bhv, sizeof(zd) * tot, hipMemcpyDeviceToDevice, st));
-        G.sN64.run(st);
-        G.sC64.run(st);
+        auto body = [&](hipStream_t st) {
+            FH_HIP(hipMemcpyAsync(Xv, Bv, sizeof(zd) * tot, hipMemcpyDeviceToDevice, st));
+            FH_HIP(hipMemcpyAsync(Xhv, Bhv, sizeof(zd) * tot, hipMemcpyDeviceToDevice, st));
+            G.sN64.run(st);
+            G.sC64.run(st);
+        };
+        if (o.graph) run_graph(c, G.g_fp64, body);
+        else body(c.stream);
         return 0.0;
     }
+    hipStream_t st0 = c.stream;
     cf* X32 = (cf*)G.X32.p;
     cf* Xh32 = (cf*)G.Xh32.p;
     zd* R = (zd*)G.R.p;
@@ -286,47 +328,34 @@ double dg_solve(Ctx& c, DenseGroup& G, const fh_opts& o, fh_report* rep) {
     const int* dm = (const int*)G.dm.p;
     const int C = cnt * G.mmax;
     double* nrm = (double*)G.nrm.ensure(sizeof(double) * 4 * (size_t)std::max(1, C));
-    // zero shifts for systems whose residual gets its B term from a GEMM
-    std::vector<zd> hz0(cnt), hzc0(cnt);
-    bool anyB = false;
+    // shifts of the residual initialisation R = B - z X: zero for systems whose
+    // B term comes from a GEMM (a problem with B), z / conj(z) otherwise
+    std::vector<zd> hz0(2 * (size_t)cnt);
     for (int s = 0; s < cnt; ++s) {
         const bool b = G.prob[s]->hasB;
-        anyB = anyB || b;
         hz0[s] = b ? zd{0.0, 0.0} : zd{G.z[s].real(), G.z[s].imag()};
-        hzc0[s] = b ? zd{0.0, 0.0} : zd{G.z[s].real(), -G.z[s].imag()};
+        hz0[cnt + s] = b ? zd{0.0, 0.0} : zd{G.z[s].real(), -G.z[s].imag()};
     }
-    const zd* zr = (const zd*)G.dz.p;
-    const zd* zl = (const zd*)G.dzc.p;
-    DBuf zb;
-    if (anyB) {
-        zd* d = (zd*)zb.ensure(sizeof(zd) * 2 * cnt);
-        FH_HIP(hipMemcpy(d, hz0.data(), sizeof(zd) * cnt, hipMemcpyHostToDevice));
-        FH_HIP(hipMemcpy(d + cnt, hzc0.data(), sizeof(zd) * cnt, hipMemcpyHostToDevice));
-        zr = d;
-        zl = d + cnt;
-    }
-    set_colnorm(st, cnt, G.mmax, off, dn, dm, Bv, nrm);
-    set_colnorm(st, cnt, G.mmax, off, dn, dm, Bhv, nrm + C);
+    zd* zr = (zd*)G.zb.ensure(sizeof(zd) * 2 * cnt);
+    const zd* zl = zr + cnt;
+    FH_HIP(hipMemcpyAsync(zr, hz0.data(), sizeof(zd) * 2 * cnt, hipMemcpyHostToDevice, st0));
+    set_colnorm(st0, cnt, G.mmax, off, dn, dm, Bv, nrm);
+    set_colnorm(st0, cnt, G.mmax, off, dn, dm, Bhv, nrm + C);
     std::vector<double> hb(2 * (size_t)C), hr(2 * (size_t)C);
-    FH_HIP(hipMemcpyAsync(hb.data(), nrm, sizeof(double) * 2 * C, hipMemcpyDeviceToHost, st));
-    const zd* rsrc = Bv;
-    const zd* rhsrc = Bhv;
-    double worst = 0.0;
-    const int steps = std::max(1, o.max_refine);
-    for (int it = 0; it < steps; ++it) {
-        // d = LU32^{-1} r in complex FP32, x += d
-        cast<float, double>(st, tot, rsrc, X32);
-        cast<float, double>(st, tot, rhsrc, Xh32);
+    FH_HIP(hipMemcpyAsync(hb.data(), nrm, sizeof(double) * 2 * C, hipMemcpyDeviceToHost, st0));
+    // one refinement step: d = LU32^{-1} r in complex FP32, x += d, r = b - (z B - A) x in FP64
+    auto body = [&](hipStream_t st, bool first) {
+        cast<float, double>(st, tot, first ? Bv : R, X32);
+        cast<float, double>(st, tot, first ? Bhv : Rh, Xh32);
         G.sN32.run(st);
         G.sC32.run(st);
-        if (it == 0) {
+        if (first) {
             cast<double, float>(st, tot, X32, Xv);
             cast<double, float>(st, tot, Xh32, Xhv);
         } else {
             add_cast(st, tot, X32, Xv);
             add_cast(st, tot, Xh32, Xhv);
         }
-        // r = b - (z B - A) x in FP64
         set_resid_init(st, cnt, G.maxlen, off, len, zr, Bv, Xv, R);
         set_resid_init(st, cnt, G.maxlen, off, len, zl, Bhv, Xhv, Rh);
         G.resBN.run(st);
@@ -335,8 +364,15 @@ double dg_solve(Ctx& c, DenseGroup& G, const fh_opts& o, fh_report* rep) {
         G.resC.run(st);
         set_colnorm(st, cnt, G.mmax, off, dn, dm, R, nrm + 2 * C);
         set_colnorm(st, cnt, G.mmax, off, dn, dm, Rh, nrm + 3 * C);
-        FH_HIP(hipMemcpyAsync(hr.data(), nrm + 2 * C, sizeof(double) * 2 * C, hipMemcpyDeviceToHost, st));
-        FH_HIP(hipStreamSynchronize(st));
+    };
+    double worst = 0.0;
+    const int steps = std::max(1, o.max_refine);
+    for (int it = 0; it < steps; ++it) {
+        const bool first = (it == 0);
+        if (o.graph) run_graph(c, first ? G.g_first : G.g_next, [&](hipStream_t st) { body(st, first); });
+        else body(st0, first);
+        FH_HIP(hipMemcpyAsync(hr.data(), nrm + 2 * C, sizeof(double) * 2 * C, hipMemcpyDeviceToHost, st0));
+        FH_HIP(hipStreamSynchronize(st0));
         const double prev = worst;
         worst = 0.0;
         for (int q = 0; q < 2 * C; ++q) worst = std::max(worst, hb[q] > 0 ? hr[q] / hb[q] : 0.0);
@@ -344,8 +380,6 @@ double dg_solve(Ctx& c, DenseGroup& G, const fh_opts& o, fh_report* rep) {
         if (!(worst > o.inner_tol)) break;
         // stop at the FP64 rounding floor: a step that does not halve the residual
         if (it > 0 && !(worst < 0.5 * prev)) break;
-        rsrc = R;
-        rhsrc = Rh;
     }
     if (rep) rep->inner_relres = worst;
     return worst;

@@ -32,6 +32,17 @@ struct DenseGroup {
     GroupPlan<float> sN32, sC32;
     const void* layout_key[4] = {nullptr, nullptr, nullptr, nullptr};
     long layout_vtot = -1;
+    // captured launch sequences (valid for the current layout)
+    hipGraphExec_t g_fp64 = nullptr, g_first = nullptr, g_next = nullptr;
+    DBuf zb;                        // shifts of the residual initialisation
+    void drop_graphs() {
+        for (hipGraphExec_t* g : {&g_fp64, &g_first, &g_next})
+            if (*g) {
+                (void)hipGraphExecDestroy(*g);
+                *g = nullptr;
+            }
+    }
+    ~DenseGroup() { drop_graphs(); }
 };
 
 // Form and factor (z_s B_p - A_p) for the nodes zs[p] of every problem p.

@@ -37,6 +37,14 @@ struct Ctx {
     // autotuned grouped-GEMM tiles per shape class, and their probe scratch
     std::map<std::string, int> tuned;
     DBuf tune_scratch;
+    // stream and events for HIP-graph capture and replay (created on first use)
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    ~Ctx() {
+        if (gev[0]) (void)hipEventDestroy(gev[0]);
+        if (gev[1]) (void)hipEventDestroy(gev[1]);
+        if (gstream) (void)hipStreamDestroy(gstream);
+    }
 };
 
 // makes the handle's profiler current on this thread for the duration of a call
