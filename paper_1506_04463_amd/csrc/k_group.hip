@@ -343,18 +343,30 @@ __global__ void k_set_resid_init(const long* __restrict__ off, const int* __rest
     R[q] = r;
 }
 
-// out[s * mmax + c] = || column c of block s ||_2  (block s: n[s] x m[s], ld m[s])
-__global__ void k_set_colnorm(const long* __restrict__ off, const int* __restrict__ n, const int* __restrict__ m,
-                              int mmax, const zd* __restrict__ V, double* __restrict__ out) {
-    const int s = blockIdx.x;
-    for (int c = threadIdx.x; c < mmax; c += blockDim.x) {
+// out[s * mmax + c] = || column c of block s ||_2  (block s: n[s] x m[s], ld m[s]);
+// one workgroup per block: column c is summed by the threads t with
+// t % w == c over row strides of 256 / w (w = columns per pass), then reduced in LDS
+__global__ __launch_bounds__(256) void k_set_colnorm(const long* __restrict__ off, const int* __restrict__ n,
+                                                     const int* __restrict__ m, int mmax, const zd* __restrict__ V,
+                                                     double* __restrict__ out) {
+    __shared__ double red[256];
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const int ms = m[s], ns = n[s];
+    const zd* v = V + off[s];
+    for (int c0 = 0; c0 < mmax; c0 += 64) {
+        const int w = 64;                       // columns per pass
+        const int c = c0 + (tid % w), g = tid / w, ng = 256 / w;
         double a = 0.0;
-        if (c < m[s]) {
-            const zd* v = V + off[s] + c;
-            const int ms = m[s];
-            for (int i = 0; i < n[s]; ++i) a += abs2(v[(long)i * ms]);
+        if (c < ms)
+            for (int i = g; i < ns; i += ng) a += abs2(v[(long)i * ms + c]);
+        red[tid] = a;
+        __syncthreads();
+        if (g == 0 && c < mmax) {
+            double t = 0.0;
+            for (int q = 0; q < ng; ++q) t += red[q * w + (tid % w)];
+            out[(long)s * mmax + c] = sqrt(t);
         }
-        out[(long)s * mmax + c] = sqrt(a);
+        __syncthreads();
     }
 }
 
