@@ -33,7 +33,11 @@ struct SweepDev {
     const int* ell_col = nullptr;   // K * n
     const int* ell_pos = nullptr;   // K * n: position of the value in the LU factor (-1 = empty)
     const int* dpos = nullptr;      // n: position of the pivot (non-unit sweeps) or null
+    const int* ell_slot = nullptr;  // K * n: position of the dependency within the previous level (-1: none)
     int nlev = 0, K = 0;
+    int wmax = 0;                   // widest level (rows)
+    bool adjacent = false;          // every dependency lies in the level just before
+    bool pad_ = false;
     bool conj = false;              // values enter conjugated (left-side sweeps)
 };
 
@@ -70,7 +74,7 @@ struct SparseState {
     int fact_prec = -1;
     DBuf lu64, luT64, dinv64, jd64, lu32, luT32, dinv32, jd32, mvals, zdev;
     DBuf pk64[6], pk32[6];          // packed sweep values: L, U, Udiag, UT, UTdiag, LT
-    int ilu_cw64 = 4, ilu_cw32 = 4; // column chunk of the sweeps (4: best of 4/8/16 measured at m = 64)
+    int ilu_cw64 = 4, ilu_cw32 = 8;  // columns per workgroup of the ILU sweeps (measured best at m = 64)
     // batch descriptors and GMRES workspace
     DBuf node_of, side_of, shifts64, shifts32, coef, rho, bufB, bufX, bufR, bufT, b32, x32;
     DBuf V, Z, Hs, cs, sn, g, resid, vscale, kuse, y, h1, h2, hnorm, beta, bnorm, part, bn64, rn64, sc64;

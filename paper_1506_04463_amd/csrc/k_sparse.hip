@@ -218,12 +218,16 @@ void pack_sweep_vals(hipStream_t st, const SweepDev& sw, int n, int ne, long nnz
 // issues the loads of up to P items (independent of the level's stores), then
 // stores them.
 // ---------------------------------------------------------------------------
-// everything an item needs that does not depend on the sweep's own results
+// everything an item needs that does not depend on the sweep's own results:
+// its row, column, ELL slot, dependency columns, input value, and the factor
+// values and pivot (all prefetched one level ahead, so only the loads of the
+// previous levels' results are waited on inside a level)
 template <typename T, int KM>
 struct SwItem {
-    int row, cc, t;
+    int row, cc;
     int col[KM];
-    Cx<T> xin;
+    Cx<T> xin, d;
+    Cx<T> v[KM];
 };
 
 template <typename T, int P, int KM>
@@ -243,33 +247,31 @@ __device__ __forceinline__ void load_items(const SweepDev& sw, int n, int m, int
             const int row = sw.rows[t];
             it[q].row = row;
             it[q].cc = cc;
-            it[q].t = t;
 #pragma unroll
-            for (int k = 0; k < KM; ++k) it[q].col[k] = (k < K) ? sw.ell_col[(long)k * n + t] : -1;
+            for (int k = 0; k < KM; ++k) {
+                const bool on = k < K;
+                it[q].col[k] = on ? sw.ell_col[(long)k * n + t] : -1;
+                it[q].v[k] = on ? val[(long)k * n + t] : czero<T>();
+            }
+            it[q].d = dval ? dval[t] : cx(T(1), T(0));
             it[q].xin = In[(long)row * m + cc];
         }
     }
 }
 
-// loads of the previous levels' results (and of the factor values, which are
-// independent) for all items first, then the stores
+// loads of the previous levels' results for all items first, then the
+// caller's prefetch of the next level, then the stores
 template <typename T, int P, int KM, typename Between>
-__device__ __forceinline__ void solve_items(const SwItem<T, KM>* it, int n, int m, const Cx<T>* __restrict__ val,
-                                            const Cx<T>* __restrict__ dval, Cx<T>* Os, Between between) {
-    Cx<T> xs[P][KM], vs[P][KM], d[P];
+__device__ __forceinline__ void solve_items(const SwItem<T, KM>* it, int n, int m, Cx<T>* Os, Between between) {
+    Cx<T> xs[P][KM];
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-        d[q] = cx(T(1), T(0));
 #pragma unroll
-        for (int k = 0; k < KM; ++k) { xs[q][k] = czero<T>(); vs[q][k] = czero<T>(); }
+        for (int k = 0; k < KM; ++k) xs[q][k] = czero<T>();
         if (it[q].row >= 0) {
 #pragma unroll
             for (int k = 0; k < KM; ++k)
-                if (it[q].col[k] >= 0) {
-                    vs[q][k] = val[(long)k * n + it[q].t];
-                    xs[q][k] = Os[(long)it[q].col[k] * m + it[q].cc];
-                }
-            if (dval) d[q] = dval[it[q].t];
+                if (it[q].col[k] >= 0) xs[q][k] = Os[(long)it[q].col[k] * m + it[q].cc];
         }
     }
     between();
@@ -278,8 +280,8 @@ __device__ __forceinline__ void solve_items(const SwItem<T, KM>* it, int n, int 
         if (it[q].row >= 0) {
             Cx<T> v = it[q].xin;
 #pragma unroll
-            for (int k = 0; k < KM; ++k) cfms(v, vs[q][k], xs[q][k]);
-            Os[(long)it[q].row * m + it[q].cc] = d[q] * v;
+            for (int k = 0; k < KM; ++k) cfms(v, it[q].v[k], xs[q][k]);
+            Os[(long)it[q].row * m + it[q].cc] = it[q].d * v;
         }
     }
 }
@@ -294,19 +296,246 @@ __device__ __forceinline__ void sweep(const SweepDev& sw, int n, int m, int c0, 
         // the current level's loads are issued first, then the prefetch of the
         // next level's independent data, so waiting on the former does not
         // wait on the latter (loads retire in issue order)
-        solve_items<T, P, KM>(cur, n, m, val, dval, Os, [&] {
+        solve_items<T, P, KM>(cur, n, m, Os, [&] {
             if (lev + 1 < sw.nlev) load_items<T, P, KM>(sw, n, m, c0, cw, val, dval, In, lev + 1, 0, nxt);
         });
         const int items = (sw.lev_ptr[lev + 1] - sw.lev_ptr[lev]) * cw;
         for (int base = 256 * P; base < items; base += 256 * P) {     // levels wider than one batch
             SwItem<T, KM> tmp[P];
             load_items<T, P, KM>(sw, n, m, c0, cw, val, dval, In, lev, base, tmp);
-            solve_items<T, P, KM>(tmp, n, m, val, dval, Os, [] {});
+            solve_items<T, P, KM>(tmp, n, m, Os, [] {});
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < P; ++q) cur[q] = nxt[q];
     }
+}
+
+// Deeper pipeline for narrow sweeps (KM <= 4): the level pointers are read
+// three levels ahead, the t-indexed data (row, dependency columns, factor
+// values, pivot) two levels ahead, the input value (which needs the row) one
+// level ahead, so that inside a level only the loads of the previous levels'
+// results are waited on and no chain of dependent memory loads remains.
+template <typename T, int KM>
+struct SwA {
+    int row, cc;
+    int col[KM];
+    Cx<T> v[KM];
+    Cx<T> d;
+};
+
+template <typename T, int P, int KM>
+__device__ __forceinline__ void load_a(const SweepDev& sw, int n, int c0, int cw, const Cx<T>* __restrict__ val,
+                                       const Cx<T>* __restrict__ dval, int t0, int t1, SwA<T, KM>* a) {
+    const int items = (t1 - t0) * cw;
+    const int K = sw.K;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        a[q].row = -1;
+        if (e < items) {
+            const int t = t0 + e / cw;
+            a[q].row = sw.rows[t];
+            a[q].cc = c0 + e % cw;
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                const bool on = k < K;
+                a[q].col[k] = on ? sw.ell_col[(long)k * n + t] : -1;
+                a[q].v[k] = on ? val[(long)k * n + t] : czero<T>();
+            }
+            a[q].d = dval ? dval[t] : cx(T(1), T(0));
+        }
+    }
+}
+
+template <typename T, int P, int KM>
+__device__ __forceinline__ void sweep_deep(const SweepDev& sw, int n, int m, int c0, int cw,
+                                           const Cx<T>* __restrict__ val, const Cx<T>* __restrict__ dval,
+                                           const Cx<T>* In, Cx<T>* Os) {
+    const int nlev = sw.nlev;
+    if (nlev <= 0) return;
+    auto LP = [&](int l) { return sw.lev_ptr[l <= nlev ? l : nlev]; };
+    int p0 = LP(0), p1 = LP(1), p2 = LP(2), p3 = LP(3);
+    SwA<T, KM> a0[P], a1[P], a2[P];
+    Cx<T> x0[P], x1[P];
+    load_a<T, P, KM>(sw, n, c0, cw, val, dval, p0, p1, a0);
+    load_a<T, P, KM>(sw, n, c0, cw, val, dval, p1, p2, a1);
+#pragma unroll
+    for (int q = 0; q < P; ++q) x0[q] = a0[q].row >= 0 ? In[(long)a0[q].row * m + a0[q].cc] : czero<T>();
+    for (int lev = 0; lev < nlev; ++lev) {
+        const int p4 = LP(lev + 4);
+        // results of the previous levels this level depends on
+        Cx<T> xs[P][KM];
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+#pragma unroll
+            for (int k = 0; k < KM; ++k)
+                xs[q][k] = (a0[q].row >= 0 && a0[q].col[k] >= 0) ? Os[(long)a0[q].col[k] * m + a0[q].cc]
+                                                                 : czero<T>();
+        // prefetch: inputs of level lev+1, t-indexed data of level lev+2
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+            x1[q] = (lev + 1 < nlev && a1[q].row >= 0) ? In[(long)a1[q].row * m + a1[q].cc] : czero<T>();
+        if (lev + 2 < nlev) load_a<T, P, KM>(sw, n, c0, cw, val, dval, p2, p3, a2);
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            if (a0[q].row >= 0) {
+                Cx<T> v = x0[q];
+#pragma unroll
+                for (int k = 0; k < KM; ++k) cfms(v, a0[q].v[k], xs[q][k]);
+                Os[(long)a0[q].row * m + a0[q].cc] = a0[q].d * v;
+            }
+        }
+        const int items = (p1 - p0) * cw;
+        for (int base = 256 * P; base < items; base += 256 * P) {     // levels wider than one batch
+            SwItem<T, KM> tmp[P];
+            load_items<T, P, KM>(sw, n, m, c0, cw, val, dval, In, lev, base, tmp);
+            solve_items<T, P, KM>(tmp, n, m, Os, [] {});
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            a0[q] = a1[q];
+            a1[q] = a2[q];
+            x0[q] = x1[q];
+        }
+        p0 = p1;
+        p1 = p2;
+        p2 = p3;
+        p3 = p4;
+    }
+}
+
+// Sweep whose dependencies all lie in the previous level (true for the
+// natural-order ILU(0) of a 5-point stencil: anti-diagonal levels): the last
+// two levels' results for the workgroup's columns live in an LDS ring, so a
+// level waits only on LDS and its barrier on LDS traffic; the results still
+// go to global memory, which nothing inside the sweep reads back.
+template <typename T, int KM>
+struct SwL {
+    int row, cc, pos;
+    bool act;
+    int slot[KM];
+    Cx<T> v[KM];
+    Cx<T> d;
+};
+
+// Prefetch of the t-indexed data of a level.  Branch-free and without any
+// arithmetic on the loaded values (which would make the compiler wait for
+// them here): every load uses a clamped, valid index; masks are applied
+// where the values are used.
+template <typename T, int P, int KM>
+__device__ __forceinline__ void load_l(const SweepDev& sw, int n, int c0, int cw, const Cx<T>* __restrict__ val,
+                                       const Cx<T>* __restrict__ dval, int t0, int t1, int base, SwL<T, KM>* a) {
+    const int items = (t1 - t0) * cw;
+    const int K = sw.K;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int e0 = base + threadIdx.x + 256 * q;
+        const bool act = e0 < items;
+        const int e = act ? e0 : 0;
+        const int t = min(t0 + e / cw, n - 1);      // t0 may be n past the last level
+        a[q].row = sw.rows[t];
+        a[q].act = act;
+        a[q].cc = e % cw;
+        a[q].pos = t - t0;
+        if (K > 0) {                                 // uniform
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                const int kk = k < K ? k : 0;
+                a[q].slot[k] = sw.ell_slot[(long)kk * n + t];
+                a[q].v[k] = val[(long)kk * n + t];
+            }
+        }
+        a[q].d = dval ? dval[t] : cx(T(1), T(0));
+    }
+}
+
+// wait for this workgroup's LDS traffic only, then barrier
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+template <typename T, int P, int KM>
+__device__ __forceinline__ void sweep_lds(const SweepDev& sw, int n, int m, int c0, int cw,
+                                          const Cx<T>* __restrict__ val, const Cx<T>* __restrict__ dval,
+                                          const Cx<T>* In, Cx<T>* Os, Cx<T>* ring, int ring_stride) {
+    const int nlev = sw.nlev;
+    if (nlev <= 0) return;
+    auto LP = [&](int l) { return sw.lev_ptr[l <= nlev ? l : nlev]; };
+    int p0 = LP(0), p1 = LP(1), p2 = LP(2), p3 = LP(3);
+    SwL<T, KM> a0[P], a1[P], a2[P];
+    Cx<T> x0[P], x1[P];
+    load_l<T, P, KM>(sw, n, c0, cw, val, dval, p0, p1, 0, a0);
+    load_l<T, P, KM>(sw, n, c0, cw, val, dval, p1, p2, 0, a1);
+#pragma unroll
+    for (int q = 0; q < P; ++q) x0[q] = In[(long)a0[q].row * m + c0 + a0[q].cc];
+    for (int lev = 0; lev < nlev; ++lev) {
+        const int p4 = LP(lev + 4);
+        const Cx<T>* prev = ring + (long)((lev + 1) & 1) * ring_stride;
+        Cx<T>* cur = ring + (long)(lev & 1) * ring_stride;
+        // prefetch: inputs of level lev+1, t-indexed data of level lev+2
+#pragma unroll
+        for (int q = 0; q < P; ++q) x1[q] = In[(long)a1[q].row * m + c0 + a1[q].cc];
+        load_l<T, P, KM>(sw, n, c0, cw, val, dval, p2, p3, 0, a2);
+        const int items = (p1 - p0) * cw;
+        for (int base = 0; base < items; base += 256 * P) {
+            SwL<T, KM> b[P];
+            Cx<T> xb[P];
+            if (base == 0) {
+#pragma unroll
+                for (int q = 0; q < P; ++q) { b[q] = a0[q]; xb[q] = x0[q]; }
+            } else {                                   // levels wider than one batch
+                load_l<T, P, KM>(sw, n, c0, cw, val, dval, p0, p1, base, b);
+#pragma unroll
+                for (int q = 0; q < P; ++q) xb[q] = In[(long)b[q].row * m + c0 + b[q].cc];
+            }
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                if (b[q].act) {
+                    Cx<T> v = xb[q];
+#pragma unroll
+                    for (int k = 0; k < KM; ++k) {
+                        const int sl = b[q].slot[k];
+                        if (k < sw.K && sl >= 0) cfms(v, b[q].v[k], prev[sl * cw + b[q].cc]);
+                    }
+                    v = b[q].d * v;
+                    cur[b[q].pos * cw + b[q].cc] = v;
+                    Os[(long)b[q].row * m + c0 + b[q].cc] = v;
+                }
+            }
+        }
+        lds_barrier();
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            a0[q] = a1[q];
+            a1[q] = a2[q];
+            x0[q] = x1[q];
+        }
+        p0 = p1;
+        p1 = p2;
+        p2 = p3;
+        p3 = p4;
+    }
+}
+
+template <typename T, int P, int KM>
+__global__ __launch_bounds__(256) void k_ilu_apply_lds(IluApplyArgs<T> a, const Cx<T>* __restrict__ X, Cx<T>* Out,
+                                                       int ring_stride) {
+    extern __shared__ unsigned char dsm[];
+    Cx<T>* ring = reinterpret_cast<Cx<T>*>(dsm);      // [2][wmax][cw]
+    const int s = blockIdx.y;
+    const int c0 = blockIdx.x * a.cw;
+    const int cw = min(a.cw, a.m - c0);
+    const int node = a.node_of[s], side = a.side_of[s];
+    const long base = (long)s * a.n * a.m;
+    const SweepDev& F = a.fwd[side];
+    const SweepDev& B = a.bwd[side];
+    const Cx<T>* fv = a.fval[side] + (long)node * F.K * a.n;
+    const Cx<T>* fd = a.fdiag[side] ? a.fdiag[side] + (long)node * a.n : nullptr;
+    const Cx<T>* bv = a.bval[side] + (long)node * B.K * a.n;
+    const Cx<T>* bd = a.bdiag[side] ? a.bdiag[side] + (long)node * a.n : nullptr;
+    sweep_lds<T, P, KM>(F, a.n, a.m, c0, cw, fv, fd, X + base, Out + base, ring, ring_stride);
+    __syncthreads();       // the backward sweep reads the forward results from global memory
+    sweep_lds<T, P, KM>(B, a.n, a.m, c0, cw, bv, bd, Out + base, Out + base, ring, ring_stride);
 }
 
 template <typename T, int P, int KM>
@@ -324,8 +553,13 @@ __global__ __launch_bounds__(256) void k_ilu_apply(IluApplyArgs<T> a, const Cx<T
     const Cx<T>* fd = a.fdiag[side] ? a.fdiag[side] + (long)node * a.n : nullptr;
     const Cx<T>* bv = a.bval[side] + (long)node * B.K * a.n;
     const Cx<T>* bd = a.bdiag[side] ? a.bdiag[side] + (long)node * a.n : nullptr;
-    sweep<T, P, KM>(F, a.n, a.m, c0, cw, fv, fd, Xs, Os);
-    sweep<T, P, KM>(B, a.n, a.m, c0, cw, bv, bd, Os, Os);
+    if constexpr (KM <= 4) {
+        sweep_deep<T, P, KM>(F, a.n, a.m, c0, cw, fv, fd, Xs, Os);
+        sweep_deep<T, P, KM>(B, a.n, a.m, c0, cw, bv, bd, Os, Os);
+    } else {
+        sweep<T, P, KM>(F, a.n, a.m, c0, cw, fv, fd, Xs, Os);
+        sweep<T, P, KM>(B, a.n, a.m, c0, cw, bv, bd, Os, Os);
+    }
 }
 
 template <typename T>
@@ -335,7 +569,18 @@ void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<
     dim3 grid(ceil_div(a.m, a.cw), nsys);
     const int K = std::max(std::max(a.fwd[0].K, a.bwd[0].K), std::max(a.fwd[1].K, a.bwd[1].K));
     hipEvent_t ev = prof_begin(st);
-    if (K <= 2) k_ilu_apply<T, 4, 2><<<grid, 256, 0, st>>>(a, X, Out);
+    bool lds = K <= 4;
+    int wmax = 0;
+    for (int sd = 0; sd < 2; ++sd) {
+        lds = lds && a.fwd[sd].adjacent && a.bwd[sd].adjacent;
+        wmax = std::max(wmax, std::max(a.fwd[sd].wmax, a.bwd[sd].wmax));
+    }
+    const size_t ring_bytes = 2 * sizeof(Cx<T>) * (size_t)wmax * a.cw;
+    if (lds && ring_bytes <= 48 * 1024) {
+        const int stride = wmax * a.cw;
+        if (K <= 2) k_ilu_apply_lds<T, 4, 2><<<grid, 256, ring_bytes, st>>>(a, X, Out, stride);
+        else k_ilu_apply_lds<T, 4, 4><<<grid, 256, ring_bytes, st>>>(a, X, Out, stride);
+    } else if (K <= 2) k_ilu_apply<T, 4, 2><<<grid, 256, 0, st>>>(a, X, Out);
     else if (K <= 4) k_ilu_apply<T, 4, 4><<<grid, 256, 0, st>>>(a, X, Out);
     else if (K <= 8) k_ilu_apply<T, 2, 8><<<grid, 256, 0, st>>>(a, X, Out);
     else if (K <= 32) k_ilu_apply<T, 1, 32><<<grid, 256, 0, st>>>(a, X, Out);

@@ -79,9 +79,27 @@ static SweepDev build_sweep(SparseState& S, const std::vector<int>& lev, int n, 
     sw.nlev = (int)ptr.size() - 1;
     sw.K = K;
     sw.conj = conjv;
+    // dependencies as positions within the previous level (for the LDS ring of
+    // the sweep kernel), when every dependency lies in the level just before
+    std::vector<int> pos_in_level(n);
+    for (int l = 0; l < sw.nlev; ++l) {
+        sw.wmax = std::max(sw.wmax, ptr[l + 1] - ptr[l]);
+        for (int t = ptr[l]; t < ptr[l + 1]; ++t) pos_in_level[rows[t]] = t - ptr[l];
+    }
+    std::vector<int> eslot((size_t)K * n, -1);
+    bool adjacent = true;
+    for (int t = 0; t < n; ++t)
+        for (int k = 0; k < K; ++k) {
+            const int c = ecol[(size_t)k * n + t];
+            if (c < 0) continue;
+            if (lev[rows[t]] - lev[c] != 1) adjacent = false;
+            eslot[(size_t)k * n + t] = pos_in_level[c];
+        }
+    sw.adjacent = adjacent;
     if (K > 0) {
         sw.ell_col = dev_ints(S, ecol, st);
         sw.ell_pos = dev_ints(S, epos, st);
+        sw.ell_slot = dev_ints(S, eslot, st);
     }
     if (has_diag) sw.dpos = dev_ints(S, dp, st);
     return sw;
