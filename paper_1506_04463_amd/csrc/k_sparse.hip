@@ -709,9 +709,12 @@ __global__ __launch_bounds__(256) void k_cgs_update_dots(int n, int m, int kp1, 
     const int col = s * m + c;
     const int r0 = chunk * ROWS_PER_CHUNK, r1 = min(n, r0 + ROWS_PER_CHUNK);
     extern __shared__ unsigned char dsm[];
-    Cx<T>* hs = reinterpret_cast<Cx<T>*>(dsm);          // [kp1][m]
-    if (ty == 0)
+    Cx<T>* hs = reinterpret_cast<Cx<T>*>(dsm);          // [kp1][m] ([KM][m], zero-padded, for REGS)
+    if (ty == 0) {
         for (int i = 0; i < kp1; ++i) hs[i * m + c] = ccast<T>(h[(long)i * C + col]);
+        if constexpr (REGS)
+            for (int i = kp1; i < KM; ++i) hs[i * m + c] = czero<T>();
+    }
     __syncthreads();
     A acc_re[KM], acc_im[KM];
 #pragma unroll
@@ -720,11 +723,13 @@ __global__ __launch_bounds__(256) void k_cgs_update_dots(int n, int m, int kp1, 
         const long off = base + (long)r * m + c;
         Cx<T> w = W[off];
         if constexpr (REGS) {
+            // unconditional arithmetic (zero coefficients and values past kp1)
+            // keeps the loads free of branches
             Cx<T> vv[KM];
 #pragma unroll
             for (int i = 0; i < KM; ++i) {
                 vv[i] = (i < kp1) ? V[i * vstride + off] : czero<T>();
-                if (i < kp1) cfms(w, hs[i * m + c], vv[i]);
+                cfms(w, hs[i * m + c], vv[i]);
             }
             W[off] = w;
 #pragma unroll
@@ -870,11 +875,13 @@ static void cgs_launch(hipStream_t st, int n, int m, int nsys, int kp1, const Cx
     ev = prof_begin(st);
     const size_t hsb = sizeof(Cx<T>) * (size_t)kp1 * m;
     FH_REQUIRE(hsb <= 96 * 1024, -1, "GMRES restart length x columns per system too large for the LDS staging");
+    constexpr bool REGS = (sizeof(T) == 4 && KM <= 32) || (sizeof(T) == 8 && KM <= 16);
+    const size_t hsb_ud = REGS ? sizeof(Cx<T>) * (size_t)KM * m : hsb;   // zero-padded coefficients
     if (hsb > 64 * 1024) {
         FH_HIP(hipFuncSetAttribute((const void*)k_cgs_update_dots<T, KM>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
         FH_HIP(hipFuncSetAttribute((const void*)k_cgs_update_norm<T, KM>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
     }
-    k_cgs_update_dots<T, KM><<<grid, blk, hsb, st>>>(n, m, kp1, V, vstride, W, h1, P);
+    k_cgs_update_dots<T, KM><<<grid, blk, hsb_ud, st>>>(n, m, kp1, V, vstride, W, h1, P);
     FH_LAUNCH_CHECK();
     prof_end(st, ev, "cgs_update_dots_" + tag, (kp1 + 2) * vec, 16.0 * kp1 * vec / sizeof(Cx<T>));
     k_reduce_dots<<<rg, 128, 0, st>>>(nchunk, kp1, KM, C, P, h2, 0);
