@@ -44,6 +44,19 @@ def _opts(fh, m0, precision, max_iter, eps, resume=0):
                            max_iter=max_iter, eps=eps, resume=resume)
 
 
+def _traffic(kernel):
+    """HBM bytes per launch of `kernel` measured with rocprofv3 counters
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), from
+    profiles/hbm_traffic.json; None when not measured for this kernel."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
 def run_path(fh, torch, handle, prob, p, precision, steps, warmup, profile=False):
     """W warm-up iterations from the seeded start, then exactly K timed ones."""
     c = p.contour
@@ -195,6 +208,20 @@ def dense_batch(args):
     print(json.dumps(line))
 
 
+def copy_calibration():
+    """A plain device copy of a known size (1 GiB read, 1 GiB written), run
+    three times: the reference for scaling the FETCH_SIZE / WRITE_SIZE
+    counters of rocprofv3 into HBM bytes."""
+    import torch
+    nbytes = 1 << 30
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,8 +230,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-validate", action="store_true")
-    ap.add_argument("--workload", default="convdiff", choices=["convdiff", "dense-batch"],
-                    help="convdiff: the headline sparse workload (default); dense-batch: 64 dense problems")
+    ap.add_argument("--workload", default="convdiff", choices=["convdiff", "dense-batch", "copy-calibration"],
+                    help="convdiff: the headline sparse workload (default); dense-batch: 64 dense problems; "
+                         "copy-calibration: a 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--count", type=int, default=64, help="dense-batch: number of problems")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -213,6 +241,9 @@ def main():
         sys.exit(2)
     if args.workload == "dense-batch":
         dense_batch(args)
+        return
+    if args.workload == "copy-calibration":
+        copy_calibration()
         return
     import torch
     import paper_1506_04463_amd as fh
@@ -245,7 +276,7 @@ def main():
     avg_ms = st["ms"] / st["count"]
     achieved = st["bytes"] / (st["ms"] * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS, "traffic": None, "avg_ms": avg_ms, "launches": st["count"],
+            "frac": achieved / PEAK_HBM_GBS, "traffic": _traffic(name), "avg_ms": avg_ms, "launches": st["count"],
             "bytes_per_launch": st["bytes"] / st["count"],
             "share_of_step": st["ms"] / (args.steps * ms_mx)}
     kernels = {k: {"ms_total": v["ms"], "count": v["count"], "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}

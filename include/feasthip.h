@@ -108,6 +108,9 @@ typedef struct {
     int graph;            /* dense grouped solves (fh_feast_batched, mixed dense
                              filter): 1 = capture each solve / refinement step
                              into a HIP graph once per layout and replay it   */
+    int orth;             /* GMRES orthogonalization: 0 = classical Gram-Schmidt
+                             with reorthogonalization (two projections),
+                             1 = one projection (one pass over the basis less) */
 } fh_opts;
 
 typedef struct {

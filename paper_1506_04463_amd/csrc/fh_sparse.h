@@ -99,7 +99,7 @@ template <typename T>
 void jacobi_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<T>* Out, const T* scale);
 template <typename T>
 void cgs2(hipStream_t st, int n, int m, int nsys, int kp1, const Cx<T>* V, long vstride, Cx<T>* W, zd* h1, zd* h2,
-          double* hnorm, DBuf& part);
+          double* hnorm, DBuf& part, int passes);
 template <typename T>
 void colnorms(hipStream_t st, int n, int m, int nsys, const Cx<T>* X, double* out, DBuf& part);
 void givens_step(hipStream_t st, int C, int k, int KP, const zd* h1, const zd* h2, const double* hnorm, zd* Hs,

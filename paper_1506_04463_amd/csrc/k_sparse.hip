@@ -857,7 +857,7 @@ __global__ void k_reduce_norm(int nchunk, int C, const double* __restrict__ part
 
 template <typename T, int KM>
 static void cgs_launch(hipStream_t st, int n, int m, int nsys, int kp1, const Cx<T>* V, long vstride, Cx<T>* W,
-                       zd* h1, zd* h2, double* hnorm, DBuf& part) {
+                       zd* h1, zd* h2, double* hnorm, DBuf& part, int passes) {
     const int ry = std::max(1, 256 / m);
     const int nchunk = ceil_div(n, ROWS_PER_CHUNK);
     const int C = nsys * m;
@@ -881,13 +881,20 @@ static void cgs_launch(hipStream_t st, int n, int m, int nsys, int kp1, const Cx
         FH_HIP(hipFuncSetAttribute((const void*)k_cgs_update_dots<T, KM>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
         FH_HIP(hipFuncSetAttribute((const void*)k_cgs_update_norm<T, KM>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
     }
-    k_cgs_update_dots<T, KM><<<grid, blk, hsb_ud, st>>>(n, m, kp1, V, vstride, W, h1, P);
-    FH_LAUNCH_CHECK();
-    prof_end(st, ev, "cgs_update_dots_" + tag, (kp1 + 2) * vec, 16.0 * kp1 * vec / sizeof(Cx<T>));
-    k_reduce_dots<<<rg, 128, 0, st>>>(nchunk, kp1, KM, C, P, h2, 0);
-    FH_LAUNCH_CHECK();
-    ev = prof_begin(st);
-    k_cgs_update_norm<T, KM><<<grid, blk, hsb, st>>>(n, m, kp1, V, vstride, W, h2, P);
+    const zd* hlast = h1;
+    if (passes >= 2) {
+        k_cgs_update_dots<T, KM><<<grid, blk, hsb_ud, st>>>(n, m, kp1, V, vstride, W, h1, P);
+        FH_LAUNCH_CHECK();
+        prof_end(st, ev, "cgs_update_dots_" + tag, (kp1 + 2) * vec, 16.0 * kp1 * vec / sizeof(Cx<T>));
+        k_reduce_dots<<<rg, 128, 0, st>>>(nchunk, kp1, KM, C, P, h2, 0);
+        FH_LAUNCH_CHECK();
+        ev = prof_begin(st);
+        hlast = h2;
+    } else {
+        // one projection (classical Gram-Schmidt without the second pass): h2 = 0
+        FH_HIP(hipMemsetAsync(h2, 0, sizeof(zd) * (size_t)kp1 * C, st));
+    }
+    k_cgs_update_norm<T, KM><<<grid, blk, hsb, st>>>(n, m, kp1, V, vstride, W, hlast, P);
     FH_LAUNCH_CHECK();
     prof_end(st, ev, "cgs_update_norm_" + tag, (kp1 + 2) * vec, 8.0 * kp1 * vec / sizeof(Cx<T>));
     k_reduce_norm<<<ceil_div(C, 128), 128, 0, st>>>(nchunk, C, P, hnorm);
@@ -896,17 +903,17 @@ static void cgs_launch(hipStream_t st, int n, int m, int nsys, int kp1, const Cx
 
 template <typename T>
 void cgs2(hipStream_t st, int n, int m, int nsys, int kp1, const Cx<T>* V, long vstride, Cx<T>* W, zd* h1, zd* h2,
-          double* hnorm, DBuf& part) {
+          double* hnorm, DBuf& part, int passes) {
     FH_REQUIRE(m >= 1 && m <= 256, -1, "GMRES column count per system must be in [1, 256]");
-    if (kp1 <= 4) cgs_launch<T, 4>(st, n, m, nsys, kp1, V, vstride, W, h1, h2, hnorm, part);
-    else if (kp1 <= 8) cgs_launch<T, 8>(st, n, m, nsys, kp1, V, vstride, W, h1, h2, hnorm, part);
-    else if (kp1 <= 16) cgs_launch<T, 16>(st, n, m, nsys, kp1, V, vstride, W, h1, h2, hnorm, part);
-    else if (kp1 <= 32) cgs_launch<T, 32>(st, n, m, nsys, kp1, V, vstride, W, h1, h2, hnorm, part);
-    else if (kp1 <= 64) cgs_launch<T, 64>(st, n, m, nsys, kp1, V, vstride, W, h1, h2, hnorm, part);
+    if (kp1 <= 4) cgs_launch<T, 4>(st, n, m, nsys, kp1, V, vstride, W, h1, h2, hnorm, part, passes);
+    else if (kp1 <= 8) cgs_launch<T, 8>(st, n, m, nsys, kp1, V, vstride, W, h1, h2, hnorm, part, passes);
+    else if (kp1 <= 16) cgs_launch<T, 16>(st, n, m, nsys, kp1, V, vstride, W, h1, h2, hnorm, part, passes);
+    else if (kp1 <= 32) cgs_launch<T, 32>(st, n, m, nsys, kp1, V, vstride, W, h1, h2, hnorm, part, passes);
+    else if (kp1 <= 64) cgs_launch<T, 64>(st, n, m, nsys, kp1, V, vstride, W, h1, h2, hnorm, part, passes);
     else throw Error(-1, "GMRES restart length above 63 is not supported");
 }
-template void cgs2<double>(hipStream_t, int, int, int, int, const zd*, long, zd*, zd*, zd*, double*, DBuf&);
-template void cgs2<float>(hipStream_t, int, int, int, int, const cf*, long, cf*, zd*, zd*, double*, DBuf&);
+template void cgs2<double>(hipStream_t, int, int, int, int, const zd*, long, zd*, zd*, zd*, double*, DBuf&, int);
+template void cgs2<float>(hipStream_t, int, int, int, int, const cf*, long, cf*, zd*, zd*, double*, DBuf&, int);
 
 template <typename T>
 void colnorms(hipStream_t st, int n, int m, int nsys, const Cx<T>* X, double* out, DBuf& part) {

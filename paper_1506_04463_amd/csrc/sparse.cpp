@@ -431,7 +431,8 @@ constexpr double LEARNED_STALL = 0.5;
 // Solves M_s x = b_s; x starts at zero.  bn: device column norms of b (C doubles).
 template <typename T>
 static SolveStats gmres(Ctx& c, SparseState& S, const Batch& b, const Cx<T>* shifts, const Cx<T>* B, Cx<T>* X,
-                        int restart, int max_cycles, double tol, int precond, const double* bn, int fallback) {
+                        int restart, int max_cycles, double tol, int precond, const double* bn, int fallback,
+                        int orth_passes) {
     hipStream_t st = c.stream;
     const int n = S.n, m = b.m, C = b.nsys * m, KP = restart + 1;
     const long vstride = (long)b.nsys * n * m;
@@ -485,7 +486,7 @@ static SolveStats gmres(Ctx& c, SparseState& S, const Batch& b, const Cx<T>* shi
             Cx<T>* Zk = flex ? Zf + (long)k * vstride : Z;
             apply_P<T>(c, S, b, precond, Vk, Zk, (const T*)nullptr);    // Z = P^{-1} V_k
             apply_M<T>(c, S, b, shifts, T(1), Zk, nullptr, Vk1);        // W = M Z
-            cgs2<T>(st, n, m, b.nsys, k + 1, V, vstride, Vk1, h1, h2, hnorm, S.part);
+            cgs2<T>(st, n, m, b.nsys, k + 1, V, vstride, Vk1, h1, h2, hnorm, S.part, orth_passes);
             givens_step(st, C, k, KP, h1, h2, hnorm, Hs, cs, sn, g, resid, vscale, kuse, bn, tol);
             scale_inplace<T>(st, n, m, b.nsys, Vk1, vscale);            // V_{k+1} = W / h_{k+1,k}
             kexec = k + 1;
@@ -550,7 +551,7 @@ static SolveStats solve_batch(Ctx& c, SparseState& S, int nsys, int nright, cons
     zd* sh64 = upload_op_shifts<double>(c, S, nsys, zsys, side_of.data());
     if (o.precision == FH_PREC_FP64)
         return gmres<double>(c, S, b, sh64, B64, X64, restart, std::max(1, o.max_restarts), o.inner_tol, precond, bn,
-                             o.fallback);
+                             o.fallback, o.orth == 1 ? 1 : 2);
     // complex FP32 inner solves wrapped in FP64 iterative refinement
     cf* sh32 = upload_op_shifts<float>(c, S, nsys, zsys, side_of.data());
     zd* R = (zd*)S.bufR.ensure(sizeof(zd) * len);
@@ -578,7 +579,7 @@ static SolveStats solve_batch(Ctx& c, SparseState& S, int nsys, int nright, cons
         double* ones = (double*)S.bn32.ensure(sizeof(double) * C);     // |b32 columns| = 1 (or 0)
         colnorms<float>(st, n, m, b.nsys, b32, ones, S.part);
         SolveStats s32 = gmres<float>(c, S, b, sh32, b32, x32, restart, std::max(1, o.max_restarts),
-                                      o.mixed_inner_tol, pc, ones, o.fallback);
+                                      o.mixed_inner_tol, pc, ones, o.fallback, o.orth == 1 ? 1 : 2);
         tot.steps += s32.steps;
         tot.fallback |= s32.fallback;
         if (s32.fallback) pc = o.fallback;     // later refinement steps keep the fallback
