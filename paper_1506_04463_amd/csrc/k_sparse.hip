@@ -424,14 +424,14 @@ struct SwL {
 // arithmetic on the loaded values (which would make the compiler wait for
 // them here): every load uses a clamped, valid index; masks are applied
 // where the values are used.
-template <typename T, int P, int KM>
+template <typename T, int P, int KM, int NT>
 __device__ __forceinline__ void load_l(const SweepDev& sw, int n, int c0, int cw, const Cx<T>* __restrict__ val,
                                        const Cx<T>* __restrict__ dval, int t0, int t1, int base, SwL<T, KM>* a) {
     const int items = (t1 - t0) * cw;
     const int K = sw.K;
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-        const int e0 = base + threadIdx.x + 256 * q;
+        const int e0 = base + threadIdx.x + NT * q;
         const bool act = e0 < items;
         const int e = act ? e0 : 0;
         const int t = min(t0 + e / cw, n - 1);      // t0 may be n past the last level
@@ -454,7 +454,7 @@ __device__ __forceinline__ void load_l(const SweepDev& sw, int n, int c0, int cw
 // wait for this workgroup's LDS traffic only, then barrier
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-template <typename T, int P, int KM>
+template <typename T, int P, int KM, int NT>
 __device__ __forceinline__ void sweep_lds(const SweepDev& sw, int n, int m, int c0, int cw,
                                           const Cx<T>* __restrict__ val, const Cx<T>* __restrict__ dval,
                                           const Cx<T>* In, Cx<T>* Os, Cx<T>* ring, int ring_stride) {
@@ -464,8 +464,8 @@ __device__ __forceinline__ void sweep_lds(const SweepDev& sw, int n, int m, int 
     int p0 = LP(0), p1 = LP(1), p2 = LP(2), p3 = LP(3);
     SwL<T, KM> a0[P], a1[P], a2[P];
     Cx<T> x0[P], x1[P];
-    load_l<T, P, KM>(sw, n, c0, cw, val, dval, p0, p1, 0, a0);
-    load_l<T, P, KM>(sw, n, c0, cw, val, dval, p1, p2, 0, a1);
+    load_l<T, P, KM, NT>(sw, n, c0, cw, val, dval, p0, p1, 0, a0);
+    load_l<T, P, KM, NT>(sw, n, c0, cw, val, dval, p1, p2, 0, a1);
 #pragma unroll
     for (int q = 0; q < P; ++q) x0[q] = In[(long)a0[q].row * m + c0 + a0[q].cc];
     for (int lev = 0; lev < nlev; ++lev) {
@@ -475,16 +475,16 @@ __device__ __forceinline__ void sweep_lds(const SweepDev& sw, int n, int m, int 
         // prefetch: inputs of level lev+1, t-indexed data of level lev+2
 #pragma unroll
         for (int q = 0; q < P; ++q) x1[q] = In[(long)a1[q].row * m + c0 + a1[q].cc];
-        load_l<T, P, KM>(sw, n, c0, cw, val, dval, p2, p3, 0, a2);
+        load_l<T, P, KM, NT>(sw, n, c0, cw, val, dval, p2, p3, 0, a2);
         const int items = (p1 - p0) * cw;
-        for (int base = 0; base < items; base += 256 * P) {
+        for (int base = 0; base < items; base += NT * P) {
             SwL<T, KM> b[P];
             Cx<T> xb[P];
             if (base == 0) {
 #pragma unroll
                 for (int q = 0; q < P; ++q) { b[q] = a0[q]; xb[q] = x0[q]; }
             } else {                                   // levels wider than one batch
-                load_l<T, P, KM>(sw, n, c0, cw, val, dval, p0, p1, base, b);
+                load_l<T, P, KM, NT>(sw, n, c0, cw, val, dval, p0, p1, base, b);
 #pragma unroll
                 for (int q = 0; q < P; ++q) xb[q] = In[(long)b[q].row * m + c0 + b[q].cc];
             }
@@ -517,9 +517,9 @@ __device__ __forceinline__ void sweep_lds(const SweepDev& sw, int n, int m, int 
     }
 }
 
-template <typename T, int P, int KM>
-__global__ __launch_bounds__(256) void k_ilu_apply_lds(IluApplyArgs<T> a, const Cx<T>* __restrict__ X, Cx<T>* Out,
-                                                       int ring_stride) {
+template <typename T, int P, int KM, int NT>
+__global__ __launch_bounds__(NT) void k_ilu_apply_lds(IluApplyArgs<T> a, const Cx<T>* __restrict__ X, Cx<T>* Out,
+                                                      int ring_stride) {
     extern __shared__ unsigned char dsm[];
     Cx<T>* ring = reinterpret_cast<Cx<T>*>(dsm);      // [2][wmax][cw]
     const int s = blockIdx.y;
@@ -533,9 +533,9 @@ __global__ __launch_bounds__(256) void k_ilu_apply_lds(IluApplyArgs<T> a, const 
     const Cx<T>* fd = a.fdiag[side] ? a.fdiag[side] + (long)node * a.n : nullptr;
     const Cx<T>* bv = a.bval[side] + (long)node * B.K * a.n;
     const Cx<T>* bd = a.bdiag[side] ? a.bdiag[side] + (long)node * a.n : nullptr;
-    sweep_lds<T, P, KM>(F, a.n, a.m, c0, cw, fv, fd, X + base, Out + base, ring, ring_stride);
+    sweep_lds<T, P, KM, NT>(F, a.n, a.m, c0, cw, fv, fd, X + base, Out + base, ring, ring_stride);
     __syncthreads();       // the backward sweep reads the forward results from global memory
-    sweep_lds<T, P, KM>(B, a.n, a.m, c0, cw, bv, bd, Out + base, Out + base, ring, ring_stride);
+    sweep_lds<T, P, KM, NT>(B, a.n, a.m, c0, cw, bv, bd, Out + base, Out + base, ring, ring_stride);
 }
 
 template <typename T, int P, int KM>
@@ -577,9 +577,18 @@ void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<
     }
     const size_t ring_bytes = 2 * sizeof(Cx<T>) * (size_t)wmax * a.cw;
     if (lds && ring_bytes <= 48 * 1024) {
+        // one batch per level when possible (a second batch would not be prefetched):
+        // 512 threads when a level holds more than 256 x 4 items
         const int stride = wmax * a.cw;
-        if (K <= 2) k_ilu_apply_lds<T, 4, 2><<<grid, 256, ring_bytes, st>>>(a, X, Out, stride);
-        else k_ilu_apply_lds<T, 4, 4><<<grid, 256, ring_bytes, st>>>(a, X, Out, stride);
+        const bool wide = (long)wmax * a.cw > 256 * 4;
+        const size_t sh = ring_bytes;
+        if (K <= 2) {
+            if (wide) k_ilu_apply_lds<T, 4, 2, 512><<<grid, 512, sh, st>>>(a, X, Out, stride);
+            else k_ilu_apply_lds<T, 4, 2, 256><<<grid, 256, sh, st>>>(a, X, Out, stride);
+        } else {
+            if (wide) k_ilu_apply_lds<T, 4, 4, 512><<<grid, 512, sh, st>>>(a, X, Out, stride);
+            else k_ilu_apply_lds<T, 4, 4, 256><<<grid, 256, sh, st>>>(a, X, Out, stride);
+        }
     } else if (K <= 2) k_ilu_apply<T, 4, 2><<<grid, 256, 0, st>>>(a, X, Out);
     else if (K <= 4) k_ilu_apply<T, 4, 4><<<grid, 256, 0, st>>>(a, X, Out);
     else if (K <= 8) k_ilu_apply<T, 2, 8><<<grid, 256, 0, st>>>(a, X, Out);
