@@ -269,9 +269,10 @@ int fh_shifted_solve(fh_handle h, fh_problem p, int nsys, const double* z, const
 
 /* Learned preconditioner (not part of the paper's method: a flexible
  * preconditioner for the iterative shifted solves of Section 2.4).
- * A 3-layer convolutional network on an ny x nx grid (vector index
- * i = y * nx + x, so n = ny * nx): 3x3 convolutions with zero padding,
- * cin -> 16 -> 16 -> 2 channels, bias, ReLU after the first two layers.
+ * A 3-layer convolutional network on an nz x ny x nx grid (vector index
+ * i = (z * ny + y) * nx + x, so n = nz * ny * nx): 3x3 convolutions (nz = 1)
+ * or 3x3x3 convolutions (nz > 1) with zero padding, cin -> 16 -> 16 -> 2
+ * channels, bias, ReLU after the first two layers.
  * Input channels: Re and Im of v / ||v||_2, Re and Im of the operator shift
  * divided by alpha (z for a right system, conj(z) for a left one), the side
  * (0 or 1), then nfields constant fields.  Output:
@@ -279,17 +280,17 @@ int fh_shifted_solve(fh_handle h, fh_problem p, int nsys, const double* z, const
  * (side 0) or (z B - A)^{-H} v (side 1); out_scale sets the magnitude of
  * the operator's inverse (about 1 / max |a_ii| for a stiff operator).
  * Parameters are kept in FP32 (Adam master copy) and used in BF16 by the
- * kernels, which accumulate in FP32.  Parameter vector layout (floats):
- *   w1 [16][cin][9], b1 [16], w2 [16][16][9], b2 [16], w3 [2][16][9], b3 [2]
- * with cin = 5 + nfields and tap index (dy + 1) * 3 + (dx + 1), where the tap
- * reads the input at (y + dy, x + dx).
+ * kernels, which accumulate in FP32.  Parameter vector layout (floats), with
+ * T = 9 (nz = 1) or 27 taps:
+ *   w1 [16][cin][T], b1 [16], w2 [16][16][T], b2 [16], w3 [2][16][T], b3 [2]
+ * with cin = 5 + nfields and tap index (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)
+ * (dz = 0 when nz = 1), where the tap reads the input at (z+dz, y+dy, x+dx).
  *
- * fh_net_create: fields = host [nfields][ny * nx] (may be NULL if nfields is
- * 0); alpha > 0 scales the shift channels, out_scale > 0 the output;
- * He-normal initial weights drawn from seed.  The network belongs to h's
- * device; destroy it with fh_net_destroy after detaching it from every
- * problem. */
-int fh_net_create(fh_handle h, int ny, int nx, int nfields, const double* fields, double alpha,
+ * fh_net_create: fields = host [nfields][n] (may be NULL if nfields is 0);
+ * alpha > 0 scales the shift channels, out_scale > 0 the output; He-normal
+ * initial weights drawn from seed.  The network belongs to h's device;
+ * destroy it with fh_net_destroy after detaching it from every problem. */
+int fh_net_create(fh_handle h, int nz, int ny, int nx, int nfields, const double* fields, double alpha,
                   double out_scale, unsigned long long seed, fh_net* net);
 int fh_net_destroy(fh_net net);
 /* number of floats in the parameter vector (or a negative error) */
@@ -297,6 +298,9 @@ int fh_net_param_count(fh_net net);
 /* copy the FP32 parameters to / from host memory; set also resets Adam */
 int fh_net_get_params(fh_handle h, fh_net net, float* params);
 int fh_net_set_params(fh_handle h, fh_net net, const float* params);
+/* replace the constant input fields (host [nfields][n], as at creation), e.g.
+ * to train one network on the operators of several coefficient fields */
+int fh_net_set_fields(fh_handle h, fh_net net, const double* fields);
 /* Out_s = network(V_s) for nsys blocks (device, [nsys][n][m] complex);
  * z, sides as in fh_shifted_solve. */
 int fh_net_forward(fh_handle h, fh_net net, int nsys, int m, const double* z, const int* sides,

@@ -8,8 +8,10 @@ channels are (Re r, Im r)/||r||_2 followed by optional constant fields; the
 output (Re e, Im e) is scaled back by ||r||_2.
 
 Layouts follow the HIP kernels: an activation is an array [ny, nx, C, m]
-(grid row, grid column, channel, batch column); weights are [Cout, Cin, 3, 3]
-(dy, dx in -1, 0, 1 order); the grid row index is the slower one.
+(grid row, grid column, channel, batch column) on a 2D grid, or
+[nz, ny, nx, C, m] on a 3D grid; weights are [Cout, Cin, 3, 3] or
+[Cout, Cin, 3, 3, 3] (offsets -1, 0, 1 in each axis, slowest axis first).
+The same functions serve both: the number of spatial axes is x.ndim - 2.
 
 Two losses over the columns c of a batch, with o_c = out[:, :, 0, c] + i
 out[:, :, 1, c] and t_c the (scaled) error target:
@@ -24,37 +26,43 @@ convolution; the HIP kernels are checked against these functions.
 """
 from __future__ import annotations
 
+import itertools
+
 import numpy as np
 
 
+def _offsets(d):
+    return itertools.product(range(3), repeat=d)
+
+
 def conv3x3(x, w, b):
-    """x [ny, nx, Cin, m], w [Cout, Cin, 3, 3], b [Cout] -> [ny, nx, Cout, m]."""
-    ny, nx, cin, m = x.shape
+    """x [*S, Cin, m], w [Cout, Cin, 3 (x d)], b [Cout] -> [*S, Cout, m]; zero padding."""
+    d = x.ndim - 2
+    S = x.shape[:d]
     cout = w.shape[0]
-    xp = np.zeros((ny + 2, nx + 2, cin, m))
-    xp[1:-1, 1:-1] = x
-    out = np.zeros((ny, nx, cout, m)) + b[None, None, :, None]
-    for dy in range(3):
-        for dx in range(3):
-            patch = xp[dy:dy + ny, dx:dx + nx]                    # input at (y+dy-1, x+dx-1)
-            out += np.einsum("oc,yxcm->yxom", w[:, :, dy, dx], patch)
+    xp = np.pad(x, [(1, 1)] * d + [(0, 0), (0, 0)])
+    out = np.zeros(S + (cout, x.shape[-1])) + b[(None,) * d + (slice(None), None)]
+    for off in _offsets(d):
+        patch = xp[tuple(slice(o, o + n) for o, n in zip(off, S))]    # input at (s + off - 1)
+        out += np.einsum("oc,...cm->...om", w[(slice(None), slice(None)) + off], patch)
     return out
 
 
 def conv3x3_backward(x, w, gout):
     """Gradients of sum(gout * conv3x3(x, w, b)) w.r.t. x, w, b."""
-    ny, nx, cin, m = x.shape
-    xp = np.zeros((ny + 2, nx + 2, cin, m))
-    xp[1:-1, 1:-1] = x
+    d = x.ndim - 2
+    S = x.shape[:d]
+    xp = np.pad(x, [(1, 1)] * d + [(0, 0), (0, 0)])
     gw = np.zeros_like(w)
     gxp = np.zeros_like(xp)
-    for dy in range(3):
-        for dx in range(3):
-            patch = xp[dy:dy + ny, dx:dx + nx]
-            gw[:, :, dy, dx] = np.einsum("yxom,yxcm->oc", gout, patch)
-            gxp[dy:dy + ny, dx:dx + nx] += np.einsum("oc,yxom->yxcm", w[:, :, dy, dx], gout)
-    gb = gout.sum(axis=(0, 1, 3))
-    return gxp[1:-1, 1:-1], gw, gb
+    for off in _offsets(d):
+        sl = tuple(slice(o, o + n) for o, n in zip(off, S))
+        patch = xp[sl]
+        gw[(slice(None), slice(None)) + off] = np.einsum("pom,pcm->oc", gout.reshape(-1, *gout.shape[-2:]),
+                                                         patch.reshape(-1, *patch.shape[-2:]))
+        gxp[sl] += np.einsum("oc,...om->...cm", w[(slice(None), slice(None)) + off], gout)
+    gb = gout.sum(axis=tuple(range(d)) + (d + 1,))
+    return gxp[tuple(slice(1, -1) for _ in range(d))], gw, gb
 
 
 def forward(params, x):
@@ -79,46 +87,49 @@ def backward(params, cache, gout):
     return [(gw1, gb1), (gw2, gb2), (gw3, gb3)]
 
 
-def encode(r, ny, nx, fields=None):
-    """r [n, m] complex -> input [ny, nx, 2 + F, m] and the column norms."""
+def encode(r, ny, nx, fields=None, nz=None):
+    """r [n, m] complex -> input [(nz,) ny, nx, 2 + F, m] and the column norms."""
     n, m = r.shape
+    S = (ny, nx) if nz is None else (nz, ny, nx)
     nr = np.linalg.norm(r, axis=0)
     s = np.where(nr > 0, 1.0 / np.where(nr > 0, nr, 1.0), 0.0)
-    rr = (r * s[None, :]).reshape(ny, nx, m)
+    rr = (r * s[None, :]).reshape(S + (m,))
     chans = [rr.real, rr.imag]
     if fields is not None:
-        for f in fields:                                  # [ny, nx] or [ny, nx, m]
+        for f in fields:                                  # S or S + (m,)
             f = np.asarray(f, dtype=np.float64)
-            chans.append(np.broadcast_to(f[..., None] if f.ndim == 2 else f, (ny, nx, m)))
-    return np.stack(chans, axis=2), nr
+            chans.append(np.broadcast_to(f[..., None] if f.ndim == len(S) else f, S + (m,)))
+    return np.stack(chans, axis=len(S)), nr
 
 
 def loss_and_grad(params, x, target):
-    """Mean over columns of ||net(x) - t||^2 / ||t||^2 with t = target [ny, nx, 2, m]."""
+    """Mean over columns of ||net(x) - t||^2 / ||t||^2 with t = target [*S, 2, m]."""
     out, cache = forward(params, x)
     diff = out - target
-    tn = (target ** 2).sum(axis=(0, 1, 2))
+    ax = tuple(range(x.ndim - 1))
+    tn = (target ** 2).sum(axis=ax)
     tn = np.where(tn > 0, tn, 1.0)
-    m = x.shape[3]
-    loss = float(((diff ** 2).sum(axis=(0, 1, 2)) / tn).mean())
-    gout = 2.0 * diff / tn[None, None, None, :] / m
+    m = x.shape[-1]
+    loss = float(((diff ** 2).sum(axis=ax) / tn).mean())
+    gout = 2.0 * diff / tn / m
     return loss, backward(params, cache, gout)
 
 
 def loss_and_grad_op(params, x, target, ops):
     """Operator-weighted loss; ops[c] is the dense complex operator of column c."""
     out, cache = forward(params, x)
-    ny, nx, _, m = out.shape
+    S = out.shape[:-2]
+    m = out.shape[-1]
     gout = np.zeros_like(out)
     total = 0.0
     for c in range(m):
-        d = (out[:, :, 0, c] + 1j * out[:, :, 1, c] - target[:, :, 0, c] - 1j * target[:, :, 1, c]).ravel()
-        t = (target[:, :, 0, c] + 1j * target[:, :, 1, c]).ravel()
+        d = (out[..., 0, c] + 1j * out[..., 1, c] - target[..., 0, c] - 1j * target[..., 1, c]).ravel()
+        t = (target[..., 0, c] + 1j * target[..., 1, c]).ravel()
         Md = ops[c] @ d
         den = np.vdot(ops[c] @ t, ops[c] @ t).real
         den = den if den > 0 else 1.0
         total += np.vdot(Md, Md).real / den
         g = 2.0 * (ops[c].conj().T @ Md) / den / m
-        gout[:, :, 0, c] = g.real.reshape(ny, nx)
-        gout[:, :, 1, c] = g.imag.reshape(ny, nx)
+        gout[..., 0, c] = g.real.reshape(S)
+        gout[..., 1, c] = g.imag.reshape(S)
     return total / m, backward(params, cache, gout)

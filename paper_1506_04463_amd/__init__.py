@@ -99,12 +99,13 @@ def lib():
         "fh_shifted_solve": (i, [vp, vp, i, dp, ip, i, C.POINTER(fh_opts), vp, vp, C.POINTER(fh_report)]),
         "fh_feast_batched": (i, [vp, i, C.POINTER(vp), C.POINTER(fh_contour), C.POINTER(fh_opts), C.POINTER(vp),
                                  C.POINTER(vp), C.POINTER(vp), C.POINTER(dp), C.POINTER(fh_report)]),
-        "fh_net_create": (i, [vp, i, i, i, dp, d, d, C.c_ulonglong, C.POINTER(vp)]),
+        "fh_net_create": (i, [vp, i, i, i, i, dp, d, d, C.c_ulonglong, C.POINTER(vp)]),
         "fh_net_destroy": (i, [vp]),
         "fh_net_param_count": (i, [vp]),
         "fh_net_get_params": (i, [vp, vp, C.POINTER(C.c_float)]),
         "fh_net_set_params": (i, [vp, vp, C.POINTER(C.c_float)]),
         "fh_net_forward": (i, [vp, vp, i, i, dp, ip, vp, vp]),
+        "fh_net_set_fields": (i, [vp, vp, dp]),
         "fh_net_train_step": (i, [vp, vp, vp, i, i, dp, ip, vp, vp, d, i, dp, C.POINTER(C.c_float)]),
         "fh_problem_set_net": (i, [vp, vp]),
         "fh_profile": (i, [vp, i]),
@@ -446,17 +447,19 @@ def shifted_solve(prob: Problem, z, sides, B, opts: fh_opts | None = None):
 
 
 class Net:
-    """Learned preconditioner network (3x3 conv, cin -> 16 -> 16 -> 2) on an ny x nx grid."""
+    """Learned preconditioner network (3x3 or 3x3x3 conv, cin -> 16 -> 16 -> 2) on an
+    (nz x) ny x nx grid."""
 
-    def __init__(self, handle: Handle, ny, nx, fields=None, alpha=1.0, out_scale=1.0, seed=0):
+    def __init__(self, handle: Handle, ny, nx, fields=None, alpha=1.0, out_scale=1.0, seed=0, nz=1):
         self.handle = handle
-        self.ny, self.nx = ny, nx
-        f = None if fields is None else np.ascontiguousarray(np.asarray(fields, dtype=np.float64).reshape(-1, ny * nx))
+        self.nz, self.ny, self.nx = nz, ny, nx
+        self.npix = nz * ny * nx
+        f = None if fields is None else np.ascontiguousarray(np.asarray(fields, dtype=np.float64).reshape(-1, self.npix))
         self.nfields = 0 if f is None else f.shape[0]
         self._fields = f
         fp = None if f is None else f.ctypes.data_as(C.POINTER(C.c_double))
         p = C.c_void_p()
-        handle.check(lib().fh_net_create(handle._h, ny, nx, self.nfields, fp, float(alpha), float(out_scale),
+        handle.check(lib().fh_net_create(handle._h, nz, ny, nx, self.nfields, fp, float(alpha), float(out_scale),
                                          C.c_ulonglong(seed), C.byref(p)), "fh_net_create")
         self.out_scale = float(out_scale)
         self._n = p
@@ -477,22 +480,33 @@ class Net:
                           "fh_net_set_params")
 
     def unpack(self, params):
-        """flat vector -> [(w1, b1), (w2, b2), (w3, b3)] with w [cout, cin, 3, 3]"""
+        """flat vector -> [(w1, b1), (w2, b2), (w3, b3)] with w [cout, cin, 3, 3(, 3)]"""
         H, cin = NET_HIDDEN, self.cin
+        k = (3, 3) if self.nz == 1 else (3, 3, 3)
+        T = int(np.prod(k))
         shapes = [(H, cin), (H, H), (2, H)]
         out, off = [], 0
         for co, ci in shapes:
-            w = np.asarray(params[off:off + co * ci * 9]).reshape(co, ci, 3, 3)
-            off += co * ci * 9
+            w = np.asarray(params[off:off + co * ci * T]).reshape((co, ci) + k)
+            off += co * ci * T
             b = np.asarray(params[off:off + co])
             off += co
             out.append((w, b))
         return out
 
+    def set_fields(self, fields):
+        """Replace the constant input fields ([nfields, n] or [nfields, *grid])."""
+        f = np.ascontiguousarray(np.asarray(fields, dtype=np.float64).reshape(-1, self.npix))
+        if f.shape[0] != self.nfields:
+            raise ValueError(f"expected {self.nfields} fields")
+        self._fields = f
+        self.handle.check(lib().fh_net_set_fields(self.handle._h, self._n, f.ctypes.data_as(C.POINTER(C.c_double))),
+                          "fh_net_set_fields")
+
     def forward(self, z, sides, V):
         """V: (nsys, n, m) complex128 -> network output of the same shape."""
         torch = _torch()
-        _check_batch(V, self.ny * self.nx, "V")
+        _check_batch(V, self.npix, "V")
         nsys, n, m = V.shape
         zk, zp = _cbuf(np.broadcast_to(np.asarray(z, dtype=np.complex128), (nsys,)))
         sk, sp = _sides(sides, nsys)
@@ -506,8 +520,8 @@ class Net:
 
         With a CSR problem the loss is measured in the residual norm of its
         shifted operators, else in the error norm."""
-        _check_batch(R, self.ny * self.nx, "R")
-        _check_batch(E, self.ny * self.nx, "E")
+        _check_batch(R, self.npix, "R")
+        _check_batch(E, self.npix, "E")
         nsys, n, m = R.shape
         zk, zp = _cbuf(np.broadcast_to(np.asarray(z, dtype=np.complex128), (nsys,)))
         sk, sp = _sides(sides, nsys)

@@ -440,23 +440,24 @@ int fh_shifted_solve(fh_handle h, fh_problem p, int nsys, const double* z, const
     FH_API_END(h)
 }
 
-int fh_net_create(fh_handle h, int ny, int nx, int nfields, const double* fields, double alpha,
+int fh_net_create(fh_handle h, int nz, int ny, int nx, int nfields, const double* fields, double alpha,
                   double out_scale, unsigned long long seed, fh_net* out) {
     if (!h) return -1;
-    if (ny < 1) return -2;
-    if (nx < 1) return -3;
-    if (nfields < 0 || nfields > FH_NET_MAX_FIELDS) return -4;
-    if (nfields > 0 && !fields) return -5;
-    if (!(alpha > 0)) return -6;
-    if (!(out_scale > 0)) return -7;
-    if (!out) return -9;
+    if (nz < 1) return -2;
+    if (ny < 1) return -3;
+    if (nx < 1) return -4;
+    if (nfields < 0 || nfields > FH_NET_MAX_FIELDS) return -5;
+    if (nfields > 0 && !fields) return -6;
+    if (!(alpha > 0)) return -7;
+    if (!(out_scale > 0)) return -8;
+    if (!out) return -10;
     *out = nullptr;
     FH_API_BEGIN(h)
     set_device(h);
     fh_net_s* n = new fh_net_s();
     n->device = h->device;
     try {
-        n->st = net_create(*h, ny, nx, nfields, fields, alpha, out_scale, seed);
+        n->st = net_create(*h, nz, ny, nx, nfields, fields, alpha, out_scale, seed);
     } catch (...) {
         delete n;
         throw;
@@ -508,6 +509,17 @@ static std::vector<double> op_shifts(int nsys, const double* z, const int* sides
         s[2 * k + 1] = sides[k] ? -z[2 * k + 1] : z[2 * k + 1];
     }
     return s;
+}
+
+int fh_net_set_fields(fh_handle h, fh_net net, const double* fields) {
+    if (!h) return -1;
+    if (!net) return -2;
+    if (!fields && net_field_count(net->st) > 0) return -3;
+    FH_API_BEGIN(h)
+    set_device(h);
+    if (net_field_count(net->st) > 0) net_set_fields(*h, *net->st, fields);
+    return FH_OK;
+    FH_API_END(h)
 }
 
 int fh_net_forward(fh_handle h, fh_net net, int nsys, int m, const double* z, const int* sides, const void* V,

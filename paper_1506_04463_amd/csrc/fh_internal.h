@@ -102,12 +102,14 @@ void dense_shifted_solve(Ctx& c, Prob& p, int nsys, int nright, const cplx* z, i
                          const fh_opts& o, fh_report* rep);
 
 // net.cpp
-NetState* net_create(Ctx& c, int ny, int nx, int nfields, const double* fields, double alpha, double out_scale,
-                     unsigned long long seed);
+NetState* net_create(Ctx& c, int nz, int ny, int nx, int nfields, const double* fields, double alpha,
+                     double out_scale, unsigned long long seed);
 void net_destroy(NetState* s);
 int net_param_count(const NetState* s);
 int net_grid_size(const NetState* s);
 void net_set_params(Ctx& c, NetState& S, const float* host);
+void net_set_fields(Ctx& c, NetState& S, const double* fields);
+int net_field_count(const NetState* s);
 void net_get_params(Ctx& c, NetState& S, float* host);
 void net_forward_host(Ctx& c, NetState& S, int nsys, int m, const zd* X, const double* shifts, const int* sides, zd* Out);
 double net_loss_grad(Ctx& c, NetState& S, const SparseState* sp, int nsys, int m, const zd* R, const zd* E,

@@ -15,7 +15,8 @@ constexpr int NET_WG_THREADS = NET_MAX_COUT * (NET_MAX_CIN + 1);   // 272
 
 // device view of the network (pointers into NetState buffers)
 struct NetDev {
-    int ny = 0, nx = 0, cin = NET_FIXED_CH, np = 0, t = 0;
+    int nz = 1, ny = 0, nx = 0, cin = NET_FIXED_CH, np = 0, t = 0;
+    int taps = 9;                // 9 (2D grid, nz = 1) or 27 (3D grid)
     double inv_alpha = 1.0;
     float oscale = 1.0f;         // output scale: e = ||r|| oscale (o_0 + i o_1)
     int off_w1 = 0, off_b1 = 0, off_w2 = 0, off_b2 = 0, off_w3 = 0, off_b3 = 0;
@@ -24,6 +25,7 @@ struct NetDev {
     float* mom = nullptr;        // Adam first moment
     float* vel = nullptr;        // Adam second moment
     const float* fields = nullptr;   // [nfields][npix]
+    __host__ __device__ int npix() const { return nz * ny * nx; }
 };
 
 template <typename T>

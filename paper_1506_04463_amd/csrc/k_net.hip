@@ -4,9 +4,10 @@
 // weights) and Adam kernels used to train it on (residual, error) pairs and
 // to apply it as a flexible preconditioner inside FGMRES.
 //
-// Activation layout: [pixel][channel][column] (FP32), pixel = y * nx + x; the
-// columns of a batch are contiguous, so every access is coalesced across the
-// batch.  Weight layout: [Cout][Cin][9] (tap = (dy+1)*3 + (dx+1)).
+// Activation layout: [pixel][channel][column] (FP32), pixel = (z * ny + y) * nx + x;
+// the columns of a batch are contiguous, so every access is coalesced across
+// the batch.  Weight layout: [Cout][Cin][TAPS], TAPS = 9 on a 2D grid (tap =
+// (dy+1)*3 + (dx+1)) or 27 on a 3D grid (tap = (dz+1)*9 + (dy+1)*3 + (dx+1)).
 #include "fh_net.h"
 
 namespace fh {
@@ -24,6 +25,14 @@ __host__ __device__ inline uint16_t f32_to_bf16(float f) {
     const uint32_t lsb = (u >> 16) & 1u;
     u += 0x7fffu + lsb;
     return (uint16_t)(u >> 16);
+}
+
+// offsets of a tap along z, y, x
+template <int TAPS>
+__device__ __forceinline__ void tap_off(int tap, int& dz, int& dy, int& dx) {
+    dz = TAPS == 27 ? tap / 9 - 1 : 0;
+    dy = (tap % 9) / 3 - 1;
+    dx = tap % 3 - 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -70,31 +79,33 @@ __global__ void k_net_decode(int npix, int m, int nsys, float oscale, const floa
 // ---------------------------------------------------------------------------
 // forward 3x3 convolution: one thread per (pixel, column), all COUT outputs
 // ---------------------------------------------------------------------------
-template <int COUT>
-__global__ __launch_bounds__(256) void k_conv_fwd(int ny, int nx, int mt, int cin, const float* __restrict__ x,
+template <int COUT, int TAPS>
+__global__ __launch_bounds__(256) void k_conv_fwd(int nz, int ny, int nx, int mt, int cin, const float* __restrict__ x,
                                                   const uint16_t* __restrict__ w, const uint16_t* __restrict__ b,
                                                   int relu, float* __restrict__ y) {
-    __shared__ float ws[COUT * NET_MAX_CIN * 9];
+    __shared__ float ws[COUT * NET_MAX_CIN * TAPS];
     __shared__ float bs[COUT];
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-    for (int i = tid; i < COUT * cin * 9; i += blockDim.x * blockDim.y) ws[i] = bf16_to_f32(w[i]);
+    for (int i = tid; i < COUT * cin * TAPS; i += blockDim.x * blockDim.y) ws[i] = bf16_to_f32(w[i]);
     if (tid < COUT) bs[tid] = bf16_to_f32(b[tid]);
     __syncthreads();
     const int col = blockIdx.y * blockDim.x + threadIdx.x;
     const int p = blockIdx.x * blockDim.y + threadIdx.y;
-    if (col >= mt || p >= ny * nx) return;
-    const int py = p / nx, px = p % nx;
+    if (col >= mt || p >= nz * ny * nx) return;
+    const int px = p % nx, py = (p / nx) % ny, pz = p / (nx * ny);
     float acc[COUT];
 #pragma unroll
     for (int o = 0; o < COUT; ++o) acc[o] = bs[o];
-    for (int tap = 0; tap < 9; ++tap) {
-        const int qy = py + tap / 3 - 1, qx = px + tap % 3 - 1;
-        if (qy < 0 || qy >= ny || qx < 0 || qx >= nx) continue;
-        const float* xq = x + (long)(qy * nx + qx) * cin * mt + col;
+    for (int tap = 0; tap < TAPS; ++tap) {
+        int dz, dy, dx;
+        tap_off<TAPS>(tap, dz, dy, dx);
+        const int qz = pz + dz, qy = py + dy, qx = px + dx;
+        if (qz < 0 || qz >= nz || qy < 0 || qy >= ny || qx < 0 || qx >= nx) continue;
+        const float* xq = x + (long)((qz * ny + qy) * nx + qx) * cin * mt + col;
         for (int ci = 0; ci < cin; ++ci) {
             const float v = xq[(long)ci * mt];
 #pragma unroll
-            for (int o = 0; o < COUT; ++o) acc[o] = fmaf(ws[(o * cin + ci) * 9 + tap], v, acc[o]);
+            for (int o = 0; o < COUT; ++o) acc[o] = fmaf(ws[(o * cin + ci) * TAPS + tap], v, acc[o]);
         }
     }
     float* yp = y + (long)p * COUT * mt + col;
@@ -106,30 +117,32 @@ __global__ __launch_bounds__(256) void k_conv_fwd(int ny, int nx, int mt, int ci
 // backward (data): dx[p][ci][col] = mask(p, ci) * sum_{o,tap} w[o][ci][tap] dy[p - d(tap)][o][col]
 // mask: a_prev[p][ci][col] > 0 (ReLU of the layer input), or none
 // ---------------------------------------------------------------------------
-template <int CIN>
-__global__ __launch_bounds__(256) void k_conv_bwd_data(int ny, int nx, int mt, int cout, const float* __restrict__ dy,
-                                                       const uint16_t* __restrict__ w, const float* __restrict__ mask,
-                                                       float* __restrict__ dx) {
-    __shared__ float ws[NET_MAX_COUT * CIN * 9];
+template <int CIN, int TAPS>
+__global__ __launch_bounds__(256) void k_conv_bwd_data(int nz, int ny, int nx, int mt, int cout,
+                                                       const float* __restrict__ dy, const uint16_t* __restrict__ w,
+                                                       const float* __restrict__ mask, float* __restrict__ dx) {
+    __shared__ float ws[NET_MAX_COUT * CIN * TAPS];
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-    for (int i = tid; i < cout * CIN * 9; i += blockDim.x * blockDim.y) ws[i] = bf16_to_f32(w[i]);
+    for (int i = tid; i < cout * CIN * TAPS; i += blockDim.x * blockDim.y) ws[i] = bf16_to_f32(w[i]);
     __syncthreads();
     const int col = blockIdx.y * blockDim.x + threadIdx.x;
     const int p = blockIdx.x * blockDim.y + threadIdx.y;
-    if (col >= mt || p >= ny * nx) return;
-    const int py = p / nx, px = p % nx;
+    if (col >= mt || p >= nz * ny * nx) return;
+    const int px = p % nx, py = (p / nx) % ny, pz = p / (nx * ny);
     float acc[CIN];
 #pragma unroll
     for (int c = 0; c < CIN; ++c) acc[c] = 0.0f;
-    for (int tap = 0; tap < 9; ++tap) {
+    for (int tap = 0; tap < TAPS; ++tap) {
         // output pixel q = p - d feeds input p through tap
-        const int qy = py - (tap / 3 - 1), qx = px - (tap % 3 - 1);
-        if (qy < 0 || qy >= ny || qx < 0 || qx >= nx) continue;
-        const float* dq = dy + (long)(qy * nx + qx) * cout * mt + col;
+        int ddz, ddy, ddx;
+        tap_off<TAPS>(tap, ddz, ddy, ddx);
+        const int qz = pz - ddz, qy = py - ddy, qx = px - ddx;
+        if (qz < 0 || qz >= nz || qy < 0 || qy >= ny || qx < 0 || qx >= nx) continue;
+        const float* dq = dy + (long)((qz * ny + qy) * nx + qx) * cout * mt + col;
         for (int o = 0; o < cout; ++o) {
             const float g = dq[(long)o * mt];
 #pragma unroll
-            for (int c = 0; c < CIN; ++c) acc[c] = fmaf(ws[(o * CIN + c) * 9 + tap], g, acc[c]);
+            for (int c = 0; c < CIN; ++c) acc[c] = fmaf(ws[(o * CIN + c) * TAPS + tap], g, acc[c]);
         }
     }
     float* dxp = dx + (long)p * CIN * mt + col;
@@ -145,37 +158,40 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(int ny, int nx, int mt, i
 // by the threads with ci == cin (extra row).  Partials [slice][o][cin+1][9].
 // ---------------------------------------------------------------------------
 constexpr int WG_SLICE = 8;     // pixels per workgroup
-constexpr int WG_COLS = 32;     // columns per LDS chunk
 
-__global__ __launch_bounds__(320) void k_conv_bwd_weight(int ny, int nx, int mt, int cin, int cout,
+template <int TAPS>
+__global__ __launch_bounds__(320) void k_conv_bwd_weight(int nz, int ny, int nx, int mt, int cin, int cout,
                                                          const float* __restrict__ x, const float* __restrict__ dy,
                                                          float* __restrict__ part) {
-    __shared__ float dys[NET_MAX_COUT][WG_COLS];
-    __shared__ float xs[9][NET_MAX_CIN][WG_COLS];
+    constexpr int WGC = TAPS == 27 ? 16 : 32;    // columns per LDS chunk
+    __shared__ float dys[NET_MAX_COUT][WGC];
+    __shared__ float xs[TAPS][NET_MAX_CIN][WGC];
     const int tid = threadIdx.x;
     const int o = tid / (NET_MAX_CIN + 1), ci = tid % (NET_MAX_CIN + 1);
     const bool active = (tid < NET_WG_THREADS) && (o < cout) && (ci <= cin);
     const int nth = blockDim.x;
-    float acc[9];
+    float acc[TAPS];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) acc[t] = 0.0f;
-    const int npix = ny * nx;
+    for (int t = 0; t < TAPS; ++t) acc[t] = 0.0f;
+    const int npix = nz * ny * nx;
     const int p0 = blockIdx.x * WG_SLICE;
     for (int p = p0; p < min(npix, p0 + WG_SLICE); ++p) {
-        const int py = p / nx, px = p % nx;
-        for (int c0 = 0; c0 < mt; c0 += WG_COLS) {
-            const int cw = min(WG_COLS, mt - c0);
-            for (int e = tid; e < cout * WG_COLS; e += nth) {
-                const int oo = e / WG_COLS, cc = e % WG_COLS;
+        const int px = p % nx, py = (p / nx) % ny, pz = p / (nx * ny);
+        for (int c0 = 0; c0 < mt; c0 += WGC) {
+            const int cw = min(WGC, mt - c0);
+            for (int e = tid; e < cout * WGC; e += nth) {
+                const int oo = e / WGC, cc = e % WGC;
                 dys[oo][cc] = (cc < cw) ? dy[(long)p * cout * mt + (long)oo * mt + c0 + cc] : 0.0f;
             }
-            for (int e = tid; e < 9 * cin * WG_COLS; e += nth) {
-                const int tap = e / (cin * WG_COLS), rem = e % (cin * WG_COLS);
-                const int cc2 = rem / WG_COLS, cc = rem % WG_COLS;
-                const int qy = py + tap / 3 - 1, qx = px + tap % 3 - 1;
+            for (int e = tid; e < TAPS * cin * WGC; e += nth) {
+                const int tap = e / (cin * WGC), rem = e % (cin * WGC);
+                const int cc2 = rem / WGC, cc = rem % WGC;
+                int dz, dyy, dx;
+                tap_off<TAPS>(tap, dz, dyy, dx);
+                const int qz = pz + dz, qy = py + dyy, qx = px + dx;
                 float v = 0.0f;
-                if (cc < cw && qy >= 0 && qy < ny && qx >= 0 && qx < nx)
-                    v = x[(long)(qy * nx + qx) * cin * mt + (long)cc2 * mt + c0 + cc];
+                if (cc < cw && qz >= 0 && qz < nz && qy >= 0 && qy < ny && qx >= 0 && qx < nx)
+                    v = x[(long)((qz * ny + qy) * nx + qx) * cin * mt + (long)cc2 * mt + c0 + cc];
                 xs[tap][cc2][cc] = v;
             }
             __syncthreads();
@@ -184,7 +200,7 @@ __global__ __launch_bounds__(320) void k_conv_bwd_weight(int ny, int nx, int mt,
                     const float g = dys[o][cc];
                     if (ci < cin) {
 #pragma unroll
-                        for (int t = 0; t < 9; ++t) acc[t] = fmaf(g, xs[t][ci][cc], acc[t]);
+                        for (int t = 0; t < TAPS; ++t) acc[t] = fmaf(g, xs[t][ci][cc], acc[t]);
                     } else {
                         acc[0] += g;       // bias
                     }
@@ -194,23 +210,23 @@ __global__ __launch_bounds__(320) void k_conv_bwd_weight(int ny, int nx, int mt,
         }
     }
     if (active) {
-        float* pp = part + ((long)blockIdx.x * NET_MAX_COUT * (NET_MAX_CIN + 1) + (long)o * (NET_MAX_CIN + 1) + ci) * 9;
+        float* pp = part + ((long)blockIdx.x * NET_MAX_COUT * (NET_MAX_CIN + 1) + (long)o * (NET_MAX_CIN + 1) + ci) * TAPS;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) pp[t] = acc[t];
+        for (int t = 0; t < TAPS; ++t) pp[t] = acc[t];
     }
 }
 
-// sum the partials of the slices into the gradient (weights [o][ci][9], then bias [o])
-__global__ void k_wgrad_reduce(int nslice, int cin, int cout, const float* __restrict__ part, float* __restrict__ gw,
-                               float* __restrict__ gb) {
+// sum the partials of the slices into the gradient (weights [o][ci][TAPS], then bias [o])
+__global__ void k_wgrad_reduce(int nslice, int cin, int cout, int taps, const float* __restrict__ part,
+                               float* __restrict__ gw, float* __restrict__ gb) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    const int per = (NET_MAX_CIN + 1) * 9;
-    if (e >= cout * (cin + 1) * 9) return;
-    const int o = e / ((cin + 1) * 9), rem = e % ((cin + 1) * 9);
-    const int ci = rem / 9, t = rem % 9;
+    const int per = (NET_MAX_CIN + 1) * taps;
+    if (e >= cout * (cin + 1) * taps) return;
+    const int o = e / ((cin + 1) * taps), rem = e % ((cin + 1) * taps);
+    const int ci = rem / taps, t = rem % taps;
     double s = 0.0;
-    for (int k = 0; k < nslice; ++k) s += part[(long)k * NET_MAX_COUT * per + (long)o * per + ci * 9 + t];
-    if (ci < cin) gw[(o * cin + ci) * 9 + t] = (float)s;
+    for (int k = 0; k < nslice; ++k) s += part[(long)k * NET_MAX_COUT * per + (long)o * per + ci * taps + t];
+    if (ci < cin) gw[(o * cin + ci) * taps + t] = (float)s;
     else if (t == 0) gb[o] = (float)s;
 }
 
@@ -327,26 +343,26 @@ static dim3 conv_grid(int npix, int mt) { return dim3(ceil_div(npix, 4), ceil_di
 template <typename T>
 void net_encode(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* V, const float* scale, const zd* shifts,
                 const int* sides, float* x) {
-    const long tot = (long)N.ny * N.nx * m * nsys;
-    k_net_encode<T><<<ceil_div(tot, 256), 256, 0, st>>>(N.ny * N.nx, m, nsys, N.cin, V, scale, shifts, sides,
+    const long tot = (long)N.npix() * m * nsys;
+    k_net_encode<T><<<ceil_div(tot, 256), 256, 0, st>>>(N.npix(), m, nsys, N.cin, V, scale, shifts, sides,
                                                          N.inv_alpha, N.fields, x);
     FH_LAUNCH_CHECK();
 }
 template <typename T>
 void net_decode(hipStream_t st, const NetDev& N, int m, int nsys, const float* o, const float* scale, Cx<T>* Out) {
-    const long tot = (long)N.ny * N.nx * m * nsys;
-    k_net_decode<T><<<ceil_div(tot, 256), 256, 0, st>>>(N.ny * N.nx, m, nsys, N.oscale, o, scale, Out);
+    const long tot = (long)N.npix() * m * nsys;
+    k_net_decode<T><<<ceil_div(tot, 256), 256, 0, st>>>(N.npix(), m, nsys, N.oscale, o, scale, Out);
     FH_LAUNCH_CHECK();
 }
 template <typename T>
 void net_target(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* E, const float* scale, float* t) {
-    const long tot = (long)N.ny * N.nx * m * nsys;
-    k_net_target<T><<<ceil_div(tot, 256), 256, 0, st>>>(N.ny * N.nx, m, nsys, 1.0f / N.oscale, E, scale, t);
+    const long tot = (long)N.npix() * m * nsys;
+    k_net_target<T><<<ceil_div(tot, 256), 256, 0, st>>>(N.npix(), m, nsys, 1.0f / N.oscale, E, scale, t);
     FH_LAUNCH_CHECK();
 }
 template <typename T>
 void net_inv_colnorm(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* V, float* sc) {
-    k_inv_colnorm<T><<<ceil_div(m * nsys, 64), 64, 0, st>>>(N.ny * N.nx, m, nsys, V, sc);
+    k_inv_colnorm<T><<<ceil_div(m * nsys, 64), 64, 0, st>>>(N.npix(), m, nsys, V, sc);
     FH_LAUNCH_CHECK();
 }
 template void net_encode<double>(hipStream_t, const NetDev&, int, int, const zd*, const float*, const zd*, const int*, float*);
@@ -357,51 +373,70 @@ template void net_target<double>(hipStream_t, const NetDev&, int, int, const zd*
 template void net_inv_colnorm<double>(hipStream_t, const NetDev&, int, int, const zd*, float*);
 template void net_inv_colnorm<float>(hipStream_t, const NetDev&, int, int, const cf*, float*);
 
-void net_forward(hipStream_t st, const NetDev& N, int mt, const float* x, float* a1, float* a2, float* out) {
-    const int npix = N.ny * N.nx;
+template <int TAPS>
+static void forward_t(hipStream_t st, const NetDev& N, int mt, const float* x, float* a1, float* a2, float* out) {
+    const int npix = N.npix();
     dim3 blk(64, 4), g = conv_grid(npix, mt);
+    k_conv_fwd<NET_HID, TAPS><<<g, blk, 0, st>>>(N.nz, N.ny, N.nx, mt, N.cin, x, N.wb + N.off_w1, N.wb + N.off_b1, 1, a1);
+    FH_LAUNCH_CHECK();
+    k_conv_fwd<NET_HID, TAPS><<<g, blk, 0, st>>>(N.nz, N.ny, N.nx, mt, NET_HID, a1, N.wb + N.off_w2, N.wb + N.off_b2, 1,
+                                                 a2);
+    FH_LAUNCH_CHECK();
+    k_conv_fwd<2, TAPS><<<g, blk, 0, st>>>(N.nz, N.ny, N.nx, mt, NET_HID, a2, N.wb + N.off_w3, N.wb + N.off_b3, 0, out);
+    FH_LAUNCH_CHECK();
+}
+
+void net_forward(hipStream_t st, const NetDev& N, int mt, const float* x, float* a1, float* a2, float* out) {
+    const int npix = N.npix();
     hipEvent_t ev = prof_begin(st);
-    k_conv_fwd<NET_HID><<<g, blk, 0, st>>>(N.ny, N.nx, mt, N.cin, x, N.wb + N.off_w1, N.wb + N.off_b1, 1, a1);
-    FH_LAUNCH_CHECK();
-    k_conv_fwd<NET_HID><<<g, blk, 0, st>>>(N.ny, N.nx, mt, NET_HID, a1, N.wb + N.off_w2, N.wb + N.off_b2, 1, a2);
-    FH_LAUNCH_CHECK();
-    k_conv_fwd<2><<<g, blk, 0, st>>>(N.ny, N.nx, mt, NET_HID, a2, N.wb + N.off_w3, N.wb + N.off_b3, 0, out);
-    FH_LAUNCH_CHECK();
-    const double macs = 9.0 * (N.cin * NET_HID + NET_HID * NET_HID + NET_HID * 2) * npix * mt;
+    if (N.taps == 27) forward_t<27>(st, N, mt, x, a1, a2, out);
+    else forward_t<9>(st, N, mt, x, a1, a2, out);
+    const double macs = (double)N.taps * (N.cin * NET_HID + NET_HID * NET_HID + NET_HID * 2) * npix * mt;
     prof_end(st, ev, "net_forward", 4.0 * npix * mt * (N.cin + 2 * NET_HID + 2) * 2, 2 * macs);
+}
+
+template <int TAPS>
+static void backward_t(hipStream_t st, const NetDev& N, int mt, const float* x, const float* a1, const float* a2,
+                       const float* gout, float* g2, float* g1, float* grad, float* P, int nslice) {
+    dim3 blk(64, 4), g = conv_grid(N.npix(), mt);
+    const int T = TAPS;
+    // layer 3: weights, then data through ReLU(a2)
+    k_conv_bwd_weight<TAPS><<<nslice, 320, 0, st>>>(N.nz, N.ny, N.nx, mt, NET_HID, 2, a2, gout, P);
+    FH_LAUNCH_CHECK();
+    k_wgrad_reduce<<<ceil_div(2 * (NET_HID + 1) * T, 128), 128, 0, st>>>(nslice, NET_HID, 2, T, P, grad + N.off_w3,
+                                                                           grad + N.off_b3);
+    FH_LAUNCH_CHECK();
+    k_conv_bwd_data<NET_HID, TAPS><<<g, blk, 0, st>>>(N.nz, N.ny, N.nx, mt, 2, gout, N.wb + N.off_w3, a2, g2);
+    FH_LAUNCH_CHECK();
+    // layer 2
+    k_conv_bwd_weight<TAPS><<<nslice, 320, 0, st>>>(N.nz, N.ny, N.nx, mt, NET_HID, NET_HID, a1, g2, P);
+    FH_LAUNCH_CHECK();
+    k_wgrad_reduce<<<ceil_div(NET_HID * (NET_HID + 1) * T, 128), 128, 0, st>>>(nslice, NET_HID, NET_HID, T, P,
+                                                                                 grad + N.off_w2, grad + N.off_b2);
+    FH_LAUNCH_CHECK();
+    k_conv_bwd_data<NET_HID, TAPS><<<g, blk, 0, st>>>(N.nz, N.ny, N.nx, mt, NET_HID, g2, N.wb + N.off_w2, a1, g1);
+    FH_LAUNCH_CHECK();
+    // layer 1 (weights only)
+    k_conv_bwd_weight<TAPS><<<nslice, 320, 0, st>>>(N.nz, N.ny, N.nx, mt, N.cin, NET_HID, x, g1, P);
+    FH_LAUNCH_CHECK();
+    k_wgrad_reduce<<<ceil_div(NET_HID * (N.cin + 1) * T, 128), 128, 0, st>>>(nslice, N.cin, NET_HID, T, P,
+                                                                               grad + N.off_w1, grad + N.off_b1);
+    FH_LAUNCH_CHECK();
 }
 
 void net_backward(hipStream_t st, const NetDev& N, int mt, const float* x, const float* a1, const float* a2,
                   const float* gout, float* g2, float* g1, float* grad, DBuf& part) {
-    const int npix = N.ny * N.nx;
-    dim3 blk(64, 4), g = conv_grid(npix, mt);
-    const int nslice = ceil_div(npix, WG_SLICE);
-    float* P = (float*)part.ensure(sizeof(float) * (size_t)nslice * NET_MAX_COUT * (NET_MAX_CIN + 1) * 9);
-    // layer 3: weights, then data through ReLU(a2)
-    k_conv_bwd_weight<<<nslice, 320, 0, st>>>(N.ny, N.nx, mt, NET_HID, 2, a2, gout, P);
-    FH_LAUNCH_CHECK();
-    k_wgrad_reduce<<<ceil_div(2 * (NET_HID + 1) * 9, 128), 128, 0, st>>>(nslice, NET_HID, 2, P, grad + N.off_w3, grad + N.off_b3);
-    FH_LAUNCH_CHECK();
-    k_conv_bwd_data<NET_HID><<<g, blk, 0, st>>>(N.ny, N.nx, mt, 2, gout, N.wb + N.off_w3, a2, g2);
-    FH_LAUNCH_CHECK();
-    // layer 2
-    k_conv_bwd_weight<<<nslice, 320, 0, st>>>(N.ny, N.nx, mt, NET_HID, NET_HID, a1, g2, P);
-    FH_LAUNCH_CHECK();
-    k_wgrad_reduce<<<ceil_div(NET_HID * (NET_HID + 1) * 9, 128), 128, 0, st>>>(nslice, NET_HID, NET_HID, P, grad + N.off_w2,
-                                                                                grad + N.off_b2);
-    FH_LAUNCH_CHECK();
-    k_conv_bwd_data<NET_HID><<<g, blk, 0, st>>>(N.ny, N.nx, mt, NET_HID, g2, N.wb + N.off_w2, a1, g1);
-    FH_LAUNCH_CHECK();
-    // layer 1 (weights only)
-    k_conv_bwd_weight<<<nslice, 320, 0, st>>>(N.ny, N.nx, mt, N.cin, NET_HID, x, g1, P);
-    FH_LAUNCH_CHECK();
-    k_wgrad_reduce<<<ceil_div(NET_HID * (N.cin + 1) * 9, 128), 128, 0, st>>>(nslice, N.cin, NET_HID, P, grad + N.off_w1,
-                                                                              grad + N.off_b1);
-    FH_LAUNCH_CHECK();
+    const int nslice = ceil_div(N.npix(), WG_SLICE);
+    float* P = (float*)part.ensure(sizeof(float) * (size_t)nslice * NET_MAX_COUT * (NET_MAX_CIN + 1) * N.taps);
+    hipEvent_t ev = prof_begin(st);
+    if (N.taps == 27) backward_t<27>(st, N, mt, x, a1, a2, gout, g2, g1, grad, P, nslice);
+    else backward_t<9>(st, N, mt, x, a1, a2, gout, g2, g1, grad, P, nslice);
+    const double macs = (double)N.taps * (N.cin * NET_HID + NET_HID * NET_HID + NET_HID * 2) * N.npix() * mt;
+    prof_end(st, ev, "net_backward", 0.0, 4 * macs);
 }
 
 double net_loss(hipStream_t st, const NetDev& N, int mt, const float* out, const float* tgt, float* gout, DBuf& scratch) {
-    const int npix = N.ny * N.nx;
+    const int npix = N.npix();
     double* nd = (double*)scratch.ensure(sizeof(double) * 2 * mt);
     k_loss_cols<<<ceil_div(mt, 64), 64, 0, st>>>(npix, mt, out, tgt, nd, nd + mt);
     FH_LAUNCH_CHECK();
@@ -427,14 +462,14 @@ void net_sync_bf16(hipStream_t st, NetDev& N) {
 }
 
 void net_pack_diff(hipStream_t st, const NetDev& N, int m, int nsys, const float* o, const float* t, zd* D, zd* Tc) {
-    const long tot = (long)N.ny * N.nx * m * nsys;
-    k_net_pack_diff<<<ceil_div(tot, 256), 256, 0, st>>>(N.ny * N.nx, m, nsys, o, t, D, Tc);
+    const long tot = (long)N.npix() * m * nsys;
+    k_net_pack_diff<<<ceil_div(tot, 256), 256, 0, st>>>(N.npix(), m, nsys, o, t, D, Tc);
     FH_LAUNCH_CHECK();
 }
 
 void net_grad_encode(hipStream_t st, const NetDev& N, int m, int nsys, const zd* G, const double* f, float* gout) {
-    const long tot = (long)N.ny * N.nx * m * nsys;
-    k_net_grad_encode<<<ceil_div(tot, 256), 256, 0, st>>>(N.ny * N.nx, m, nsys, G, f, gout);
+    const long tot = (long)N.npix() * m * nsys;
+    k_net_grad_encode<<<ceil_div(tot, 256), 256, 0, st>>>(N.npix(), m, nsys, G, f, gout);
     FH_LAUNCH_CHECK();
 }
 

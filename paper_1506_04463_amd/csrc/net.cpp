@@ -10,24 +10,27 @@
 namespace fh {
 
 static void layout(NetDev& d) {
+    const int T = d.taps;
     int off = 0;
-    d.off_w1 = off; off += NET_HID * d.cin * 9;
+    d.off_w1 = off; off += NET_HID * d.cin * T;
     d.off_b1 = off; off += NET_HID;
-    d.off_w2 = off; off += NET_HID * NET_HID * 9;
+    d.off_w2 = off; off += NET_HID * NET_HID * T;
     d.off_b2 = off; off += NET_HID;
-    d.off_w3 = off; off += 2 * NET_HID * 9;
+    d.off_w3 = off; off += 2 * NET_HID * T;
     d.off_b3 = off; off += 2;
     d.np = off;
 }
 
-NetState* net_create(Ctx& c, int ny, int nx, int nfields, const double* fields, double alpha, double out_scale,
-                     unsigned long long seed) {
-    FH_REQUIRE(ny > 0 && nx > 0, -2, "network grid must be positive");
+NetState* net_create(Ctx& c, int nz, int ny, int nx, int nfields, const double* fields, double alpha,
+                     double out_scale, unsigned long long seed) {
+    FH_REQUIRE(nz > 0 && ny > 0 && nx > 0, -2, "network grid must be positive");
     FH_REQUIRE(nfields >= 0 && NET_FIXED_CH + nfields <= NET_MAX_CIN, -4, "too many input fields");
     NetState* S = new NetState();
     NetDev& d = S->d;
+    d.nz = nz;
     d.ny = ny;
     d.nx = nx;
+    d.taps = nz > 1 ? 27 : 9;
     d.cin = NET_FIXED_CH + nfields;
     d.inv_alpha = alpha > 0 ? 1.0 / alpha : 1.0;
     d.oscale = out_scale > 0 ? (float)out_scale : 1.0f;
@@ -40,9 +43,10 @@ NetState* net_create(Ctx& c, int ny, int nx, int nfields, const double* fields, 
         const double s = gain * std::sqrt(2.0 / fan_in);
         for (int i = 0; i < cnt; ++i) w[off + i] = (float)(s * nd(rng));
     };
-    fill(d.off_w1, NET_HID * d.cin * 9, d.cin * 9, 1.0);
-    fill(d.off_w2, NET_HID * NET_HID * 9, NET_HID * 9, 1.0);
-    fill(d.off_w3, 2 * NET_HID * 9, NET_HID * 9, 0.1);
+    const int T = d.taps;
+    fill(d.off_w1, NET_HID * d.cin * T, d.cin * T, 1.0);
+    fill(d.off_w2, NET_HID * NET_HID * T, NET_HID * T, 1.0);
+    fill(d.off_w3, 2 * NET_HID * T, NET_HID * T, 0.1);
     d.w = (float*)S->w.ensure(sizeof(float) * d.np);
     d.wb = (uint16_t*)S->wb.ensure(sizeof(uint16_t) * d.np);
     d.mom = (float*)S->mom.ensure(sizeof(float) * d.np);
@@ -51,7 +55,7 @@ NetState* net_create(Ctx& c, int ny, int nx, int nfields, const double* fields, 
     FH_HIP(hipMemcpyAsync(d.w, w.data(), sizeof(float) * d.np, hipMemcpyHostToDevice, c.stream));
     FH_HIP(hipMemsetAsync(d.mom, 0, sizeof(float) * d.np, c.stream));
     FH_HIP(hipMemsetAsync(d.vel, 0, sizeof(float) * d.np, c.stream));
-    const int npix = ny * nx;
+    const int npix = nz * ny * nx;
     std::vector<float> hf((size_t)std::max(1, nfields) * npix, 0.0f);
     for (size_t i = 0; i < (size_t)nfields * npix; ++i) hf[i] = (float)fields[i];
     d.fields = (const float*)S->fields.ensure(sizeof(float) * hf.size());
@@ -59,6 +63,15 @@ NetState* net_create(Ctx& c, int ny, int nx, int nfields, const double* fields, 
     net_sync_bf16(c.stream, d);
     FH_HIP(hipStreamSynchronize(c.stream));
     return S;
+}
+
+void net_set_fields(Ctx& c, NetState& S, const double* fields) {
+    const int nf = S.d.cin - NET_FIXED_CH;
+    const long npix = S.d.npix();
+    std::vector<float> hf((size_t)std::max(1, nf) * npix, 0.0f);
+    for (size_t i = 0; i < (size_t)nf * npix; ++i) hf[i] = (float)fields[i];
+    FH_HIP(hipMemcpyAsync((void*)S.d.fields, hf.data(), sizeof(float) * hf.size(), hipMemcpyHostToDevice, c.stream));
+    FH_HIP(hipStreamSynchronize(c.stream));
 }
 
 void net_set_params(Ctx& c, NetState& S, const float* host) {
@@ -92,7 +105,7 @@ static void upload_sys(Ctx& c, NetState& S, int nsys, const double* shifts, cons
 template <typename T>
 void net_apply(Ctx& c, NetState& S, int nsys, int m, const Cx<T>* V, const zd* shifts_dev, const int* sides_dev,
                Cx<T>* Out, bool unit_columns) {
-    const long npix = (long)S.d.ny * S.d.nx;
+    const long npix = (long)S.d.npix();
     const int mt = nsys * m;
     ensure_acts(S, npix, mt);
     float* sc = nullptr;
@@ -171,7 +184,7 @@ static double op_loss_grad(Ctx& c, NetState& S, const SparseState& sp, int nsys,
 double net_loss_grad(Ctx& c, NetState& S, const SparseState* sp, int nsys, int m, const zd* R, const zd* E,
                      const double* shifts, const int* sides, bool step, double lr) {
     upload_sys(c, S, nsys, shifts, sides);
-    const long npix = (long)S.d.ny * S.d.nx;
+    const long npix = (long)S.d.npix();
     const int mt = nsys * m;
     ensure_acts(S, npix, mt);
     float* sc = (float*)S.scale.ensure(sizeof(float) * mt);
@@ -194,7 +207,8 @@ double net_loss_grad(Ctx& c, NetState& S, const SparseState* sp, int nsys, int m
 
 void net_destroy(NetState* s) { delete s; }
 int net_param_count(const NetState* s) { return s->d.np; }
-int net_grid_size(const NetState* s) { return s->d.ny * s->d.nx; }
+int net_field_count(const NetState* s) { return s->d.cin - NET_FIXED_CH; }
+int net_grid_size(const NetState* s) { return s->d.npix(); }
 void net_get_grad(Ctx& c, NetState& S, float* host) {
     FH_HIP(hipMemcpyAsync(host, S.grad.p, sizeof(float) * S.d.np, hipMemcpyDeviceToHost, c.stream));
     FH_HIP(hipStreamSynchronize(c.stream));

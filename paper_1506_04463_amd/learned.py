@@ -99,6 +99,25 @@ def train(net: Net, data, epochs=50, lr=1e-3, batch_systems=8, seed=0, problem: 
     return hist
 
 
+def train_fields(net: Net, sets, epochs=50, lr=1e-3, batch_systems=8, seed=0):
+    """Train one network on several operators that differ by a coefficient
+    field: sets is a list of (fields, problem, data); every epoch visits the
+    sets in turn, switching the network's input fields.  Returns the mean
+    loss of each epoch (residual-norm loss of each set's operator)."""
+    rng = np.random.default_rng(seed)
+    hist = []
+    for ep in range(epochs):
+        tot, cnt = 0.0, 0
+        for k in rng.permutation(len(sets)):
+            fields, prob, data = sets[k]
+            net.set_fields(fields)
+            h = train(net, data, epochs=1, lr=lr, batch_systems=batch_systems, seed=seed * 1000 + ep, problem=prob)
+            tot += h[0] * data["R"].shape[0]
+            cnt += data["R"].shape[0]
+        hist.append(tot / cnt)
+    return hist
+
+
 def evaluate(prob: Problem, z, m=4, seed=1, tol=1e-8, restart=30, max_restarts=10, precision=FH_PREC_FP64,
              fallback=FH_PC_NONE, sides=None):
     """Each preconditioner (none, the attached network in FGMRES, ILU(0)) on

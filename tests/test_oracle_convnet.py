@@ -99,3 +99,40 @@ def test_operator_loss_gradients_finite_differences_and_special_cases():
     np.testing.assert_allclose(g1[1][0], g0[1][0], rtol=1e-10, atol=1e-14)
     l2, _ = N.loss_and_grad_op(params, x, t, [3j * M for M in ops])
     assert abs(l2 - loss) < 1e-12 * loss
+
+
+def test_conv3d_direct_sum_and_gradients():
+    """The 3D case of the same functions: a direct sum of the 27 taps and
+    central finite differences of the loss."""
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((3, 4, 5, 2, 2))
+    w = rng.standard_normal((3, 2, 3, 3, 3))
+    b = rng.standard_normal(3)
+    y = N.conv3x3(x, w, b)
+    for (zz, yy, xx, o, m) in [(0, 0, 0, 1, 0), (1, 2, 3, 2, 1), (2, 3, 4, 0, 1)]:
+        s = b[o]
+        for dz in range(3):
+            for dy in range(3):
+                for dx in range(3):
+                    pz, py, px = zz + dz - 1, yy + dy - 1, xx + dx - 1
+                    if 0 <= pz < 3 and 0 <= py < 4 and 0 <= px < 5:
+                        s += sum(w[o, c, dz, dy, dx] * x[pz, py, px, c, m] for c in range(2))
+        assert abs(y[zz, yy, xx, o, m] - s) < 1e-12
+    # 2D functions are the 3D ones on a single plane with only the middle taps
+    w2 = rng.standard_normal((3, 2, 3, 3))
+    w3 = np.zeros((3, 2, 3, 3, 3)); w3[:, :, 1] = w2
+    x2 = rng.standard_normal((4, 5, 2, 2))
+    np.testing.assert_allclose(N.conv3x3(x2[None], w3, b)[0], N.conv3x3(x2, w2, b), atol=1e-12)
+    shapes = [(4, 3), (4, 4), (2, 4)]
+    params = [(0.3 * rng.standard_normal((o, i, 3, 3, 3)), 0.1 * rng.standard_normal(o)) for o, i in shapes]
+    x = rng.standard_normal((3, 3, 4, 3, 2))
+    t = rng.standard_normal((3, 3, 4, 2, 2))
+    loss, grads = N.loss_and_grad(params, x, t)
+    h = 1e-6
+    for layer, idx in [(0, (1, 2, 0, 1, 2)), (1, (3, 0, 2, 2, 1)), (2, (1, 3, 1, 0, 0))]:
+        wp = [(p[0].copy(), p[1].copy()) for p in params]
+        wm = [(p[0].copy(), p[1].copy()) for p in params]
+        wp[layer][0][idx] += h
+        wm[layer][0][idx] -= h
+        fd = (N.loss_and_grad(wp, x, t)[0] - N.loss_and_grad(wm, x, t)[0]) / (2 * h)
+        assert abs(fd - grads[layer][0][idx]) < 1e-6 * max(1.0, abs(fd))

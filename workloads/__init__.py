@@ -187,6 +187,60 @@ def gen_dense_batch(count=64, nmin=256, nmax=2048, ne=8, m0=32, radius=0.3, seed
 # --------------------------------------------------------------------------
 # Small helpers for tests
 # --------------------------------------------------------------------------
+# --------------------------------------------------------------------------
+# 3D convection-diffusion-reaction with a smooth random convection field
+# (fourth configuration)
+# --------------------------------------------------------------------------
+def smooth_field3d(N: int, seed: int, vmax: float = 30.0, modes: int = 3) -> np.ndarray:
+    """Three components [3, N, N, N] (axes z, y, x) of a sum of low Fourier
+    modes with Gaussian amplitudes and random phases, scaled to max |v| = vmax."""
+    rng = np.random.default_rng(seed)
+    g = (np.arange(N) + 1.0) / (N + 1)
+    Z, Yg, X = np.meshgrid(g, g, g, indexing="ij")
+    v = np.zeros((3, N, N, N))
+    for d in range(3):
+        for kz in range(1, modes + 1):
+            for ky in range(1, modes + 1):
+                for kx in range(1, modes + 1):
+                    a = rng.standard_normal() / (kz * kz + ky * ky + kx * kx)
+                    pz, py, px = rng.uniform(0, 2 * math.pi, 3)
+                    v[d] += a * np.sin(kz * math.pi * Z + pz) * np.sin(ky * math.pi * Yg + py) * \
+                        np.sin(kx * math.pi * X + px)
+    mag = np.sqrt((v ** 2).sum(axis=0)).max()
+    return v * (vmax / mag)
+
+
+def convdiff3d_csr(N: int, v: np.ndarray, c: float = 5.0):
+    """CSR of -Lap(u) + v(x).grad(u) + c u, 7-point central differences on the
+    N^3 interior grid of the unit cube (Dirichlet), h = 1/(N+1),
+    index = x + N*(y + N*z); v: [3, N, N, N] as from smooth_field3d (z, y, x)."""
+    import scipy.sparse as sp
+    h = 1.0 / (N + 1)
+    n = N ** 3
+    idx = np.arange(n).reshape(N, N, N)          # [z, y, x]
+    rows, cols, vals = [idx.ravel()], [idx.ravel()], [np.full(n, 6.0 / h ** 2 + c)]
+    # component d of v acts along axis d of [z, y, x]
+    for axis, comp in ((2, 2), (1, 1), (0, 0)):   # x, y, z
+        vd = v[comp]
+        for sgn in (-1, 1):
+            src = [slice(None)] * 3
+            dst = [slice(None)] * 3
+            if sgn < 0:
+                src[axis], dst[axis] = slice(1, None), slice(0, -1)
+            else:
+                src[axis], dst[axis] = slice(0, -1), slice(1, None)
+            r = idx[tuple(src)].ravel()
+            cc = idx[tuple(dst)].ravel()
+            coef = -1.0 / h ** 2 + sgn * vd[tuple(src)].ravel() / (2 * h)
+            rows.append(r)
+            cols.append(cc)
+            vals.append(coef)
+    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+    A.sort_indices()
+    return {"n": n, "rowptr": A.indptr.astype(np.int32), "colind": A.indices.astype(np.int32),
+            "val": A.data.astype(np.float64)}
+
+
 def csr_to_dense(A) -> np.ndarray:
     n = A["n"]
     D = np.zeros((n, n), dtype=np.result_type(A["val"].dtype, np.float64))
