@@ -34,6 +34,7 @@ PEAK_HBM_GBS = 8000.0
 # 2e-9 (FP64 and complex FP32 alike); 1e-9 is a residual
 # ||Ax - lam x|| / (||A|| ||x||) of about 1.4e-12
 EPS_ITER = 1e-9
+EPS_DENSE = 1e-10   # dense batch: the residual level the throughput metric is stated at
 
 
 def _problem():
@@ -138,12 +139,13 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 
 
 def dense_batch(args):
-    """Third configuration: 64 dense generalized problems (A = G/sqrt(n),
+    """Dense batch: 64 dense generalized problems (A = G/sqrt(n),
     B = I + 0.1 G'/sqrt(n)), n_i uniform in [256, 2048], Ne = 8, m0 = 32,
     circles whose radius is scaled with 1/sqrt(n_i) (about 23 eigenvalues
     inside each).  Fast path: one batched FEAST run (grouped complex-FP32 LU on
-    MFMA + FP64 refinement, HIP-graph replay); plain path: FP64 FEAST one
-    instance at a time.  Both to eq:res <= 1e-12 from the seeded starts."""
+    MFMA + FP64 refinement, HIP-graph replay, steps 2-5 of all instances in
+    lockstep); plain path: FP64 FEAST one instance at a time.  Both to
+    eq:res <= 1e-10 from the seeded starts."""
     import torch
     import workloads as W
     import paper_1506_04463_amd as fh
@@ -158,7 +160,7 @@ def dense_batch(args):
     ns = [p.n for p in ps]
     print(f"[bench] dense batch: {count} problems, n in [{min(ns)}, {max(ns)}], Ne=8, m0=32", file=sys.stderr,
           flush=True)
-    o = fh.default_opts(32, eps=1e-12, max_iter=40, precision=fh.FH_PREC_MIXED, inner_tol=1e-12, max_refine=6,
+    o = fh.default_opts(32, eps=EPS_DENSE, max_iter=60, precision=fh.FH_PREC_MIXED, inner_tol=1e-12, max_refine=6,
                         graph=1)
     # warm-up on a small batch (autotuner, code objects)
     fh.feast_batched(probs[:2], conts[:2], Y0[:2], Yh0[:2], o)
@@ -177,7 +179,7 @@ def dense_batch(args):
     rhs = sum(2 * 8 * 32 * it for it in iters)
     plain = None
     if not args.no_fp64:
-        o64 = fh.default_opts(32, eps=1e-12, max_iter=40)
+        o64 = fh.default_opts(32, eps=EPS_DENSE, max_iter=60)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         lam64 = []
@@ -187,9 +189,10 @@ def dense_batch(args):
             lam64.append(r["lam"])
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
-        dl = max(float(np.max(np.abs(a["lam"] - b) / np.abs(b))) if len(b) and len(a["lam"]) == len(b) else
-                 float("inf") for a, b in zip(outs, lam64))
-        plain = {"seconds": t_plain, "max_rel_dlam_vs_fast": dl}
+        same = [len(a["lam"]) == len(b) and len(b) > 0 for a, b in zip(outs, lam64)]
+        dl = max([float(np.max(np.abs(np.sort_complex(a["lam"]) - np.sort_complex(b)) / np.abs(np.sort_complex(b))))
+                  for a, b, ok in zip(outs, lam64, same) if ok] or [float("inf")])
+        plain = {"seconds": t_plain, "max_rel_dlam_vs_fast": dl, "instances_same_count": int(sum(same))}
         print(f"[bench] plain FP64 one at a time: {t_plain:.2f} s, max |dlam|/|lam| {dl:.2e}", file=sys.stderr,
               flush=True)
     mf = {k: v for k, v in stats.items() if k.startswith("ggemm_c64")}
@@ -202,7 +205,7 @@ def dense_batch(args):
                 "launches": st["count"], "flops_per_launch": st["flops"] / st["count"]}
     kernels = {k: {"ms_total": v["ms"], "count": v["count"]}
                for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])[:8]}
-    line = {"metric": "dense batch: time to solution and shifted-solve RHS/s at eq:res <= 1e-12",
+    line = {"metric": "dense batch: time to solution and shifted-solve RHS/s at eq:res <= 1e-10",
             "value": rhs / t_fast, "unit": "RHS/s", "n_gpus": 1, "steps": 1, "warmup": 1,
             "ms_per_step": 1000.0 * t_fast, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "c64 LU/solves + c128 refinement/Rayleigh-Ritz", "data": "synthetic",
@@ -210,6 +213,48 @@ def dense_batch(args):
             "seconds_fast": t_fast, "status": rc, "iterations": [min(iters), max(iters)], "eigenpairs": sum(ms),
             "plain_fp64": plain, "speedup_vs_fp64": None if plain is None else plain["seconds"] / t_fast,
             "roofline": roof, "kernels": kernels}
+    print(json.dumps(line))
+
+
+def learned3d(args):
+    """Fourth configuration's operator (64^3 convection-diffusion-reaction,
+    seeded smooth convection field |v| <= 30, reaction 5): cost of one
+    application of the 3x3x3 network (8 input channels: residual, shift,
+    side, the three field components) to a block of columns, against one
+    ILU(0) apply and one SpMM of the same block, complex FP32, kernel times
+    from the library's HIP-event profiler."""
+    import torch
+    import workloads as W
+    import paper_1506_04463_amd as fh
+    N, m = 64, args.columns
+    v = W.smooth_field3d(N, 1)
+    A = W.convdiff3d_csr(N, v)
+    h = fh.Handle(0)
+    prob = fh.Problem(h, fh.CSR(torch.from_numpy(A["rowptr"]).cuda(), torch.from_numpy(A["colind"]).cuda(),
+                                torch.from_numpy(A["val"]).cuda(), A["n"]))
+    hh = 1.0 / (N + 1)
+    net = fh.Net(h, N, N, fields=v.reshape(3, -1) / 30.0, alpha=300.0, out_scale=hh * hh / 6.0, seed=1, nz=N)
+    fh.set_net(prob, net)
+    z = np.array([80.0 + 40.0j, 80.0 + 40.0j])
+    B = torch.randn((2, A["n"], m), dtype=torch.complex128, device="cuda")
+    res = {}
+    for name, pc in (("learned", fh.FH_PC_LEARNED), ("ilu0", fh.FH_PC_ILU0)):
+        o = fh.default_opts(m, precond=pc, restart=4, max_restarts=1, inner_tol=1e-300, precision=fh.FH_PREC_MIXED,
+                            mixed_inner_tol=1e-300, max_refine=1, fallback=fh.FH_PC_NONE, save_factors=1)
+        fh.shifted_solve(prob, z, [0, 1], B, o)          # warm-up (factors, code objects)
+        h.profile(True)
+        fh.shifted_solve(prob, z, [0, 1], B, o)
+        st = h.profile_stats()
+        h.profile(False)
+        res[name] = {k: {"ms_avg": v_["ms"] / v_["count"], "count": v_["count"],
+                         "TFLOPs": v_["flops"] / (v_["ms"] * 1e-3) / 1e12 if v_["flops"] else None}
+                     for k, v_ in st.items() if k.startswith(("net_", "ilu_apply", "spmm"))}
+    cols = 2 * m
+    fw = res["learned"].get("net_forward")
+    line = {"metric": "learned preconditioner apply cost, 64^3 grid", "columns_per_apply": cols,
+            "gflop_per_column": None if fw is None else fw["TFLOPs"] * fw["ms_avg"] * 1e-3 * 1e12 / cols / 1e9,
+            "net_forward": fw, "ilu_apply": res["ilu0"].get("ilu_apply_c64"), "spmm": res["ilu0"].get("spmm_c64"),
+            "peak_fp32_vector_tflops": 157.3}
     print(json.dumps(line))
 
 
@@ -235,7 +280,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-validate", action="store_true")
-    ap.add_argument("--workload", default="convdiff", choices=["convdiff", "dense-batch", "copy-calibration"],
+    ap.add_argument("--columns", type=int, default=128, help="learned3d: columns per system")
+    ap.add_argument("--workload", default="convdiff", choices=["convdiff", "dense-batch", "copy-calibration",
+                                                              "learned3d"],
                     help="convdiff: the headline sparse workload (default); dense-batch: 64 dense problems; "
                          "copy-calibration: a 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--count", type=int, default=64, help="dense-batch: number of problems")
@@ -249,6 +296,9 @@ def main():
         return
     if args.workload == "copy-calibration":
         copy_calibration()
+        return
+    if args.workload == "learned3d":
+        learned3d(args)
         return
     import torch
     import paper_1506_04463_amd as fh

@@ -254,15 +254,32 @@ struct FeastRun {
     // filter from the second iteration on), or nullptr
     const cplx* filter_lambda() const { return ((it >= 1 || o.resume) && !p.dense) ? hlam.data() : nullptr; }
 
-    // steps 2-5 of iteration it+1 (Q, Qh filled); true when the run is over
-    bool step() {
+    // Steps 2-5 of iteration it+1 (Q, Qh filled), in phases so that many runs
+    // can share one launch of each small eigensolver: GPU work is enqueued by
+    // the launch_* / phase_bq calls, host decisions read results in read_* /
+    // decide.  step() runs them for this run alone.
+    DBuf eigw;
+    int mt = 0;
+
+    EigJob job_biortho() {
+        return EigJob{mcur, 1e-16, BQ, nullptr, gam, S, Sh, ints, ints + 1,
+                      (zd*)eigw.ensure(eig_work_size(m0in))};
+    }
+    EigJob job_reduced() {
+        return EigJob{mt, 0.0, AUr, BUr, lam, W, Wh, ints + 2, nullptr, (zd*)eigw.ensure(eig_work_size(m0in))};
+    }
+
+    // step 2.a: B_Q = Qh^H B Q
+    void phase_bq() {
         ++it;
-        // step 2.a: B_Q = Qh^H B Q
         const zd* BQin = Q;
         if (p.hasB) { apply_B(c, p, 0, mcur, Q, T1); BQin = T1; }
         gemm_hn_tall(c.stream, n, mcur, mcur, Qh, mcur, BQin, mcur, BQ, mcur, c.partial);
+    }
+
+    // after steps 3.a-3.c (eig_biortho): spurious test (2.b), resize count
+    void read_bq() {
         to_host(c, hbq.data(), BQ, (size_t)mcur * mcur);
-        // step 2.b: spurious detection from the second iteration
         m_s = 0;
         if (it >= 2) {
             for (int i = 0; i < mcur; ++i) {
@@ -272,37 +289,40 @@ struct FeastRun {
                 if (flag && inside_prev[i]) ++m_s;
             }
         }
-        // steps 3.a-3.c on the GPU: eig of B_Q, sort, resize, scaled factors
-        eig_biortho(c.stream, mcur, BQ, 1e-16, gam, S, Sh, ints, ints + 1, c.eig_work);
         int hi[2];
         to_host(c, hi, ints, 2);
         if (hi[1] != 0) throw Error(FH_EIG_FAILED, "eigendecomposition of B_Q failed (code " + std::to_string(hi[1]) + ")");
-        const int mt = hi[0];
+        mt = hi[0];
         FH_REQUIRE(mt >= 1 && mt <= mcur, FH_EIG_FAILED, "resize produced an empty subspace");
-        // step 3.d: U = Q S, Uh = Qh Sh (n x mt)
+    }
+
+    // step 3.d and 4.a
+    void launch_rr() {
         gemm<double>(c.stream, 'N', 'N', n, mt, mcur, cx(1.0, 0.0), Q, mcur, 0, S, mcur, 0, czero<double>(), U,
                      mt, 0, 1);
         gemm<double>(c.stream, 'N', 'N', n, mt, mcur, cx(1.0, 0.0), Qh, mcur, 0, Sh, mcur, 0, czero<double>(), Uh,
                      mt, 0, 1);
-        // step 4.a: A_U = Uh^H A U, B_U = Uh^H B U
         apply_A(c, p, 0, mt, U, T1);
         gemm_hn_tall(c.stream, n, mt, mt, Uh, mt, T1, mt, AUr, mt, c.partial);
         const zd* BUin = U;
         if (p.hasB) { apply_B(c, p, 0, mt, U, T2); BUin = T2; }
         gemm_hn_tall(c.stream, n, mt, mt, Uh, mt, BUin, mt, BUr, mt, c.partial);
-        // step 4.b: reduced eigenproblem
-        eig_reduced(c.stream, mt, AUr, BUr, lam, W, Wh, ints + 2, c.eig_work);
+    }
+
+    // after step 4.b (eig_reduced): Ritz values, step 4.c
+    void read_lam() {
         int e4 = 0;
         to_host(c, &e4, ints + 2, 1);
         if (e4 != 0) throw Error(FH_EIG_FAILED, "reduced eigenproblem failed (code " + std::to_string(e4) + ")");
         to_host(c, reinterpret_cast<zd*>(hlam.data()), lam, mt);
-        // step 4.c
         for (int i = 0; i < mt; ++i) rho[i] = rational(ne, z.data(), w.data(), hlam[i]);
-        // step 4.d: Y = U W, Yh = Uh Wh
+    }
+
+    // step 4.d and the products of step 5.b
+    void launch_ritz() {
         gemm<double>(c.stream, 'N', 'N', n, mt, mt, cx(1.0, 0.0), U, mt, 0, W, mt, 0, czero<double>(), Ycur, mt, 0, 1);
         gemm<double>(c.stream, 'N', 'N', n, mt, mt, cx(1.0, 0.0), Uh, mt, 0, Wh, mt, 0, czero<double>(), Yhcur, mt, 0,
                      1);
-        // step 5.b: residuals eq:res
         apply_A(c, p, 0, mt, Ycur, T1);
         const zd* BY = Ycur;
         if (p.hasB) { apply_B(c, p, 0, mt, Ycur, T2); BY = T2; }
@@ -311,6 +331,10 @@ struct FeastRun {
         const zd* BhYh = Yhcur;
         if (p.hasB) { apply_B(c, p, 1, mt, Yhcur, T2); BhYh = T2; }
         res_colnorms(c.stream, n, mt, T1, BhYh, mt, lam, true, num2, den2, c.partial2);
+    }
+
+    // steps 5.a-5.c; true when the run is over
+    bool decide() {
         to_host(c, hn.data(), num, mt);
         to_host(c, hd.data(), den, mt);
         to_host(c, hn2.data(), num2, mt);
@@ -374,6 +398,19 @@ struct FeastRun {
             return true;
         }
         return false;
+    }
+
+    bool step() {
+        phase_bq();
+        const EigJob jb = job_biortho();
+        eig_biortho(c.stream, jb.m, jb.in1, jb.eta, jb.out0, jb.out1, jb.out2, jb.i0, jb.i1, eigw);
+        read_bq();
+        launch_rr();
+        const EigJob jr = job_reduced();
+        eig_reduced(c.stream, jr.m, jr.in1, jr.in2, jr.out0, jr.out1, jr.out2, jr.i0, eigw);
+        read_lam();
+        launch_ritz();
+        return decide();
     }
 
     // step 5.d: the converged pairs in the first m columns, sorted by (Re, Im).
@@ -441,6 +478,7 @@ int feast_batched(Ctx& c, int count, Prob* const* probs, const fh_contour* cts, 
         zs.push_back(runs[i]->z);
     }
     DenseGroup G;
+    DBuf jobbuf;
     fh_report frep{};
     dg_build(c, G, plist, zs, o.precision == FH_PREC_MIXED, &frep);
     std::vector<int> first(count);   // first system of each instance
@@ -489,6 +527,7 @@ int feast_batched(Ctx& c, int count, Prob* const* probs, const fh_contour* cts, 
         }
         sync(c);
         const double tf = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        std::vector<FeastRun*> act;
         for (int i = 0; i < count; ++i) {
             FeastRun& r = *runs[i];
             if (r.done) continue;
@@ -498,8 +537,24 @@ int feast_batched(Ctx& c, int count, Prob* const* probs, const fh_contour* cts, 
                 reps[i].inner_steps = srep.inner_steps;
                 reps[i].inner_relres = srep.inner_relres;
             }
-            r.step();
+            act.push_back(&r);
         }
+        // steps 2-5 of all active runs in lockstep: one launch of each small
+        // eigensolver for all of them, host decisions between
+        std::vector<EigJob> jobs(act.size());
+        EigJob* dj = (EigJob*)jobbuf.ensure(sizeof(EigJob) * std::max<size_t>(1, act.size()));
+        for (FeastRun* r : act) r->phase_bq();
+        for (size_t k = 0; k < act.size(); ++k) jobs[k] = act[k]->job_biortho();
+        to_dev(c, dj, jobs.data(), jobs.size());
+        eig_biortho_batched(st, (int)act.size(), dj);
+        for (FeastRun* r : act) r->read_bq();
+        for (FeastRun* r : act) r->launch_rr();
+        for (size_t k = 0; k < act.size(); ++k) jobs[k] = act[k]->job_reduced();
+        to_dev(c, dj, jobs.data(), jobs.size());
+        eig_reduced_batched(st, (int)act.size(), dj);
+        for (FeastRun* r : act) r->read_lam();
+        for (FeastRun* r : act) r->launch_ritz();
+        for (FeastRun* r : act) r->decide();
     }
     int worst = FH_OK;
     for (int i = 0; i < count; ++i) {

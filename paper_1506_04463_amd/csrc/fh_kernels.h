@@ -51,6 +51,24 @@ void lu_factor(hipStream_t st, int n, zd* M, int batch, int* ipiv, int* info, DB
 void lu_solve(hipStream_t st, char op, int n, const zd* M, const int* ipiv, int m, zd* X, int batch);
 
 // ----------------------------- k_eig.hip -----------------------------------
+// one small eigenproblem of a batched launch (fields used by each kernel:
+// biortho: m, in1 = B_Q, eta, out0 = gamma, out1 = S, out2 = Sh, i0 = m0t, i1 = info;
+// reduced: m, in1 = A_U, in2 = B_U, out0 = lambda, out1 = W, out2 = Wh, i0 = info)
+struct EigJob {
+    int m;
+    double eta;
+    const zd* in1;
+    const zd* in2;
+    zd* out0;
+    zd* out1;
+    zd* out2;
+    int* i0;
+    int* i1;
+    zd* work;      // eig_work_size(m) bytes
+};
+size_t eig_work_size(int m);
+void eig_biortho_batched(hipStream_t st, int count, const EigJob* jobs_dev);
+void eig_reduced_batched(hipStream_t st, int count, const EigJob* jobs_dev);
 // Steps 3.a-3.c (see fh_biortho_factors); work: device scratch
 void eig_biortho(hipStream_t st, int m, const zd* BQ, double eta, zd* gamma, zd* S, zd* Sh, int* m0t,
                  int* info, DBuf& work);

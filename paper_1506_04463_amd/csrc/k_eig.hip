@@ -248,12 +248,9 @@ __device__ void eig_core(int m, zd* H, zd* Z, zd* X, zd* V, zd* v, double* red, 
     schur_vectors(m, H, Z, X, V, red);
 }
 
-__global__ __launch_bounds__(ENT) void k_eig_biortho(int m, const zd* __restrict__ BQ, double eta, zd* __restrict__ gamma,
-                                                     zd* __restrict__ S, zd* __restrict__ Sh, int* __restrict__ m0t,
-                                                     int* __restrict__ info, zd* __restrict__ work) {
-    __shared__ double red[ENT];
-    __shared__ int redi[ENT];
-    __shared__ int sorder[1024];
+__device__ void biortho_body(int m, const zd* __restrict__ BQ, double eta, zd* __restrict__ gamma,
+                             zd* __restrict__ S, zd* __restrict__ Sh, int* __restrict__ m0t, int* __restrict__ info,
+                             zd* __restrict__ work, double* red, int* redi, int* sorder) {
     const int tid = threadIdx.x;
     const size_t mm = (size_t)m * m;
     zd *H = work, *Z = H + mm, *X = Z + mm, *V = X + mm, *Aug = V + mm, *v = Aug + 3 * mm, *f = v + m;
@@ -304,11 +301,9 @@ __global__ __launch_bounds__(ENT) void k_eig_biortho(int m, const zd* __restrict
     }
 }
 
-__global__ __launch_bounds__(ENT) void k_eig_reduced(int m, const zd* __restrict__ AU, const zd* __restrict__ BU,
-                                                     zd* __restrict__ lam, zd* __restrict__ W, zd* __restrict__ Wh,
-                                                     int* __restrict__ info, zd* __restrict__ work) {
-    __shared__ double red[ENT];
-    __shared__ int redi[ENT];
+__device__ void reduced_body(int m, const zd* __restrict__ AU, const zd* __restrict__ BU, zd* __restrict__ lam,
+                             zd* __restrict__ W, zd* __restrict__ Wh, int* __restrict__ info, zd* __restrict__ work,
+                             double* red, int* redi) {
     const int tid = threadIdx.x;
     const size_t mm = (size_t)m * m;
     zd *H = work, *Z = H + mm, *X = Z + mm, *V = X + mm, *Aug = V + mm, *v = Aug + 3 * mm, *f = v + m;
@@ -351,6 +346,41 @@ __global__ __launch_bounds__(ENT) void k_eig_reduced(int m, const zd* __restrict
     }
 }
 
+__global__ __launch_bounds__(ENT) void k_eig_biortho(int m, const zd* __restrict__ BQ, double eta, zd* __restrict__ gamma,
+                                                     zd* __restrict__ S, zd* __restrict__ Sh, int* __restrict__ m0t,
+                                                     int* __restrict__ info, zd* __restrict__ work) {
+    __shared__ double red[ENT];
+    __shared__ int redi[ENT];
+    __shared__ int sorder[1024];
+    biortho_body(m, BQ, eta, gamma, S, Sh, m0t, info, work, red, redi, sorder);
+}
+
+__global__ __launch_bounds__(ENT) void k_eig_reduced(int m, const zd* __restrict__ AU, const zd* __restrict__ BU,
+                                                     zd* __restrict__ lam, zd* __restrict__ W, zd* __restrict__ Wh,
+                                                     int* __restrict__ info, zd* __restrict__ work) {
+    __shared__ double red[ENT];
+    __shared__ int redi[ENT];
+    reduced_body(m, AU, BU, lam, W, Wh, info, work, red, redi);
+}
+
+// batched: one workgroup per problem of the list
+__global__ __launch_bounds__(ENT) void k_eig_biortho_b(const EigJob* __restrict__ jobs) {
+    __shared__ double red[ENT];
+    __shared__ int redi[ENT];
+    __shared__ int sorder[1024];
+    const EigJob j = jobs[blockIdx.x];
+    biortho_body(j.m, j.in1, j.eta, j.out0, j.out1, j.out2, j.i0, j.i1, j.work, red, redi, sorder);
+}
+
+__global__ __launch_bounds__(ENT) void k_eig_reduced_b(const EigJob* __restrict__ jobs) {
+    __shared__ double red[ENT];
+    __shared__ int redi[ENT];
+    const EigJob j = jobs[blockIdx.x];
+    reduced_body(j.m, j.in1, j.in2, j.out0, j.out1, j.out2, j.i0, j.work, red, redi);
+}
+
+size_t eig_work_size(int m) { return sizeof(zd) * eig_work_elems(m); }
+
 void eig_biortho(hipStream_t st, int m, const zd* BQ, double eta, zd* gamma, zd* S, zd* Sh, int* m0t, int* info,
                  DBuf& work) {
     FH_REQUIRE(m >= 1 && m <= 1024, -2, "eig_biortho: m out of range");
@@ -358,11 +388,20 @@ void eig_biortho(hipStream_t st, int m, const zd* BQ, double eta, zd* gamma, zd*
     k_eig_biortho<<<1, ENT, 0, st>>>(m, BQ, eta, gamma, S, Sh, m0t, info, w);
     FH_LAUNCH_CHECK();
 }
-
 void eig_reduced(hipStream_t st, int m, const zd* AU, const zd* BU, zd* lam, zd* W, zd* Wh, int* info, DBuf& work) {
     FH_REQUIRE(m >= 1 && m <= 1024, -2, "eig_reduced: m out of range");
     zd* w = (zd*)work.ensure(sizeof(zd) * eig_work_elems(m));
     k_eig_reduced<<<1, ENT, 0, st>>>(m, AU, BU, lam, W, Wh, info, w);
+    FH_LAUNCH_CHECK();
+}
+void eig_biortho_batched(hipStream_t st, int count, const EigJob* jobs_dev) {
+    if (count <= 0) return;
+    k_eig_biortho_b<<<count, ENT, 0, st>>>(jobs_dev);
+    FH_LAUNCH_CHECK();
+}
+void eig_reduced_batched(hipStream_t st, int count, const EigJob* jobs_dev) {
+    if (count <= 0) return;
+    k_eig_reduced_b<<<count, ENT, 0, st>>>(jobs_dev);
     FH_LAUNCH_CHECK();
 }
 
