@@ -35,6 +35,7 @@ PEAK_HBM_GBS = 8000.0
 # ||Ax - lam x|| / (||A|| ||x||) of about 1.4e-12
 EPS_ITER = 1e-9
 EPS_DENSE = 1e-10   # dense batch: the residual level the throughput metric is stated at
+ORTH = 2            # GMRES orthogonalization (fh_opts.orth), set by --orth
 
 
 def _problem():
@@ -44,10 +45,12 @@ def _problem():
 
 def _opts(fh, m0, precision, max_iter, eps, resume=0):
     # GMRES(30), two cycles per solve, residual-form filter; the mixed path runs
-    # one complex-FP32 solve per filter followed by its FP64 residual check
+    # one complex-FP32 solve per filter followed by its FP64 residual check.
+    # orth = 2 (delayed reorthogonalization) acts on the complex-FP32 solves
+    # only; FP64 solves keep classical Gram-Schmidt with reorthogonalization.
     return fh.default_opts(m0, solver=fh.FH_SOLVER_BGMRES, precond=fh.FH_PC_ILU0, restart=30, max_restarts=2,
                            inner_tol=1e-3, precision=precision, mixed_inner_tol=1e-3, max_refine=1,
-                           max_iter=max_iter, eps=eps, resume=resume)
+                           max_iter=max_iter, eps=eps, resume=resume, orth=ORTH)
 
 
 def _traffic(kernel):
@@ -286,7 +289,12 @@ def main():
                     help="convdiff: the headline sparse workload (default); dense-batch: 64 dense problems; "
                          "copy-calibration: a 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--count", type=int, default=64, help="dense-batch: number of problems")
+    ap.add_argument("--orth", type=int, default=2, choices=[0, 1, 2],
+                    help="GMRES orthogonalization: 0 CGS2, 1 one projection, 2 delayed reorthogonalization "
+                         "(complex-FP32 solves; FP64 solves use CGS2)")
     args = ap.parse_args()
+    global ORTH
+    ORTH = args.orth
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of the "
               "contour filter is described in DESIGN.md and not built", file=sys.stderr)
@@ -358,7 +366,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "convdiff2d 256x256 (n=65536, nnz=326656), Pe 20 along (1,0.5), ellipse around 41 "
                                "eigenvalues, Ne=16, m0=64, GMRES(30)x2 + ILU(0), c64 + FP64 refinement",
-                   "rhs_per_iteration": rhs},
+                   "rhs_per_iteration": rhs,
+                   "orthogonalization": {0: "CGS2", 1: "CGS", 2: "DCGS2 (c64 solves)"}[ORTH]},
         "rhs_per_s": rhs * 1000.0 / ms_mx,
         "plain_fp64": plain,
         "speedup_vs_fp64": None if plain is None else plain["ms_per_step"] / ms_mx,

@@ -110,7 +110,12 @@ typedef struct {
                              into a HIP graph once per layout and replay it   */
     int orth;             /* GMRES orthogonalization: 0 = classical Gram-Schmidt
                              with reorthogonalization (two projections),
-                             1 = one projection (one pass over the basis less) */
+                             1 = one projection (one pass over the basis less),
+                             2 = delayed reorthogonalization (the second
+                             projection of each vector shares the next step's
+                             pass: two passes over the basis per step instead
+                             of three); 2 applies to complex-FP32 solves with
+                             restart <= 31, other solves use 0 */
 } fh_opts;
 
 typedef struct {

@@ -78,6 +78,7 @@ struct SparseState {
     // batch descriptors and GMRES workspace
     DBuf node_of, side_of, shifts64, shifts32, coef, rho, bufB, bufX, bufR, bufT, b32, x32;
     DBuf V, Z, Hs, cs, sn, g, resid, vscale, kuse, y, h1, h2, hnorm, beta, bnorm, part, bn64, rn64, sc64;
+    DBuf Hraw, htent, tau, dcoef, scv, scw, dots;   // DCGS2
     DBuf aval32, atval64, atval32, bn32, Zf;
     NetState* net = nullptr;   // attached learned preconditioner (not owned)
     ~SparseState() {
@@ -100,6 +101,25 @@ void jacobi_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, 
 template <typename T>
 void cgs2(hipStream_t st, int n, int m, int nsys, int kp1, const Cx<T>* V, long vstride, Cx<T>* W, zd* h1, zd* h2,
           double* hnorm, DBuf& part, int passes);
+// Device state of the delayed-reorthogonalization Arnoldi step (DCGS2): the
+// GMRES arrays it updates (Hs rotated, cs, sn, g, resid, vscale, kuse, bnorm)
+// and its own (Hraw unrotated columns [restart][KP][C], htent [KP][C], tau,
+// coef [2 KP][C], scv, scw, D reduced dots [2 KM + 3][C], part partials).
+struct DcgsState {
+    int KP = 0;
+    zd *Hs = nullptr, *sn = nullptr, *g = nullptr, *Hraw = nullptr, *htent = nullptr, *coef = nullptr, *D = nullptr;
+    double *cs = nullptr, *resid = nullptr, *vscale = nullptr, *tau = nullptr, *scv = nullptr, *scw = nullptr;
+    const double* bnorm = nullptr;
+    int* kuse = nullptr;
+    DBuf* part = nullptr;
+};
+// Step k of DCGS2 Arnoldi (complex FP32 basis, k <= 32): W = A z_k holds the
+// new vector on entry; V_k is reorthogonalized in place and W becomes the
+// tentative V_{k+1}; Hessenberg column k - 1 is finalized and rotated.
+// final != 0 (W = nullptr): only finalize column k - 1.
+template <typename T>
+void dcgs_step(hipStream_t st, int n, int m, int nsys, int k, Cx<T>* V, long vstride, Cx<T>* W, const DcgsState& d,
+               int flex, int final, double tol);
 template <typename T>
 void colnorms(hipStream_t st, int n, int m, int nsys, const Cx<T>* X, double* out, DBuf& part);
 void givens_step(hipStream_t st, int C, int k, int KP, const zd* h1, const zd* h2, const double* hnorm, zd* Hs,

@@ -946,16 +946,15 @@ template void colnorms<float>(hipStream_t, int, int, int, const cf*, double*, DB
 // State layout: Hs[(k * KP + i) * C + col] (column k of R), cs/sn[k * C + col],
 // g[i * C + col].
 // ---------------------------------------------------------------------------
-__global__ void k_givens(int C, int k, int KP, const zd* __restrict__ h1, const zd* __restrict__ h2,
-                         const double* __restrict__ hnorm, zd* __restrict__ Hs, double* __restrict__ cs,
-                         zd* __restrict__ sn, zd* __restrict__ g, double* __restrict__ resid, double* __restrict__ vscale,
-                         int* __restrict__ kuse, const double* __restrict__ bnorm, double tol) {
-    const int col = blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= C) return;
-    if (kuse[col] <= k) { vscale[col] = 0.0; return; }   // stopped earlier: keep its state
+// Givens update of Hessenberg column k of GMRES column `col`: Hs column k
+// holds the new entries 0..k (not yet rotated), hn >= 0 is the subdiagonal
+// entry h_{k+1,k}.  Applies the previous rotations, forms the new one, updates
+// g and the residual estimate, and stops the column (kuse = k + 1) on
+// convergence or breakdown.
+__device__ void givens_col(int C, int k, int KP, int col, double hn, zd* __restrict__ Hs, double* __restrict__ cs,
+                           zd* __restrict__ sn, zd* __restrict__ g, double* __restrict__ resid,
+                           double* __restrict__ vscale, int* __restrict__ kuse, double bn, double tol) {
     zd* hc = Hs + (long)k * KP * C;
-    for (int i = 0; i <= k; ++i) hc[(long)i * C + col] = h1[(long)i * C + col] + h2[(long)i * C + col];
-    const double hn = hnorm[col];
     // previous rotations
     for (int i = 0; i < k; ++i) {
         const double c = cs[(long)i * C + col];
@@ -990,11 +989,304 @@ __global__ void k_givens(int C, int k, int KP, const zd* __restrict__ h1, const 
     const double res = cabs(gk1);
     resid[col] = res;
     // columns stop growing their basis after convergence or breakdown
-    const double bn = bnorm[col];
     const bool stop = !(res > tol * bn && hn > 1e-300 * (ax + hn) && r.re == r.re);
     if (stop) kuse[col] = k + 1;
     vscale[col] = (hn > 0.0 && kuse[col] > k + 1) ? 1.0 / hn : 0.0;
 }
+
+__global__ void k_givens(int C, int k, int KP, const zd* __restrict__ h1, const zd* __restrict__ h2,
+                         const double* __restrict__ hnorm, zd* __restrict__ Hs, double* __restrict__ cs,
+                         zd* __restrict__ sn, zd* __restrict__ g, double* __restrict__ resid, double* __restrict__ vscale,
+                         int* __restrict__ kuse, const double* __restrict__ bnorm, double tol) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= C) return;
+    if (kuse[col] <= k) { vscale[col] = 0.0; return; }   // stopped earlier: keep its state
+    zd* hc = Hs + (long)k * KP * C;
+    for (int i = 0; i <= k; ++i) hc[(long)i * C + col] = h1[(long)i * C + col] + h2[(long)i * C + col];
+    givens_col(C, k, KP, col, hnorm[col], Hs, cs, sn, g, resid, vscale, kuse, bnorm[col], tol);
+}
+
+// ---------------------------------------------------------------------------
+// Delayed classical Gram-Schmidt with reorthogonalization (DCGS2) for the
+// column-batched Arnoldi process: the second projection of the vector made at
+// step k - 1 is deferred to step k, where its dot products share the pass
+// over the basis with the first projection of the new vector.  Per step: one
+// pass of dot products (reads V_0..V_k and W) and one update pass (reads them
+// again, writes V_k and W), instead of three passes; the normalization is
+// folded into the update.
+//
+// State entering step k >= 1 (per column): V_0..V_{k-1} orthonormal, V_k a
+// tentative vector (once projected, scaled to about unit norm), the tentative
+// Hessenberg column k - 1 (htent) and the scale tau with which the once
+// projected vector t_k = tau V_k entered.  Dots of the pass:
+//   s_i = V_i^H V_k, c_i = V_i^H W (i < k), alpha = V_k^H V_k, beta = V_k^H W,
+//   omega = W^H W.
+// With nu^2 = alpha - |s|^2 the reorthogonalized vector is
+// (V_k - V s) / nu, the final column k - 1 is htent + tau s with subdiagonal
+// tau nu, d = (c, (beta - s^H c) / nu) are the coefficients of W against the
+// final V_0..V_k, and the new tentative vector is (W - V d) / rho with
+// rho^2 = omega - |d|^2.  Its Hessenberg column: for the fixed (linear)
+// preconditioner W was built from the tentative V_k, so the column is
+// (d - H s) / nu with H the final columns 0..k-1 and tau = rho / nu; for the
+// flexible variant W = A z_k belongs to z_k as it is, the column is d and
+// tau = rho.
+// ---------------------------------------------------------------------------
+constexpr int DCGS_ROWS_PER_CHUNK = 1024;
+
+template <typename T, int KM>
+__global__ __launch_bounds__(256) void k_dcgs_dots(int n, int m, int k, const Cx<T>* __restrict__ V, long vstride,
+                                                   const Cx<T>* __restrict__ W, double* __restrict__ part) {
+    using A = typename AccT<T>::type;
+    constexpr int NE = 2 * KM + 3;
+    const int s = blockIdx.y, chunk = blockIdx.x;
+    const int c = threadIdx.x, ty = threadIdx.y, ry = blockDim.y;
+    const long base = (long)s * n * m;
+    const int C = gridDim.y * m;
+    const int col = s * m + c;
+    const int r0 = chunk * DCGS_ROWS_PER_CHUNK, r1 = min(n, r0 + DCGS_ROWS_PER_CHUNK);
+    const bool hw = W != nullptr;
+    A sre[KM], sim[KM], cre[KM], cim[KM];
+#pragma unroll
+    for (int i = 0; i < KM; ++i) { sre[i] = A(0); sim[i] = A(0); cre[i] = A(0); cim[i] = A(0); }
+    A al = A(0), bre = A(0), bim = A(0), om = A(0);
+    const Cx<T>* Vk = V + (long)k * vstride;
+    for (int r = r0 + ty; r < r1; r += ry) {
+        const long off = base + (long)r * m + c;
+        const Cx<T> x = Vk[off];
+        const Cx<T> w = hw ? W[off] : czero<T>();
+        Cx<T> vv[KM];
+#pragma unroll
+        for (int i = 0; i < KM; ++i) vv[i] = (i < k) ? V[i * vstride + off] : czero<T>();
+#pragma unroll
+        for (int i = 0; i < KM; ++i) {
+            sre[i] += (A)vv[i].re * (A)x.re + (A)vv[i].im * (A)x.im;
+            sim[i] += (A)vv[i].re * (A)x.im - (A)vv[i].im * (A)x.re;
+            cre[i] += (A)vv[i].re * (A)w.re + (A)vv[i].im * (A)w.im;
+            cim[i] += (A)vv[i].re * (A)w.im - (A)vv[i].im * (A)w.re;
+        }
+        al += (A)x.re * (A)x.re + (A)x.im * (A)x.im;
+        bre += (A)x.re * (A)w.re + (A)x.im * (A)w.im;
+        bim += (A)x.re * (A)w.im - (A)x.im * (A)w.re;
+        om += (A)w.re * (A)w.re + (A)w.im * (A)w.im;
+    }
+    // block reduction over the ry row groups, 8 entries per round; entry j of
+    // the compact output order: s_0..s_{k-1}, c_0..c_{k-1}, alpha, beta, omega
+    __shared__ double sh[8][2][256];
+    const int t = ty * m + c;
+#pragma unroll
+    for (int g0 = 0; g0 < NE; g0 += 8) {
+        // skip rounds whose entries are all unused (uniform over the block)
+        bool any = false;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int slot = g0 + e;
+            if (slot < NE) any = any || (slot < KM ? slot < k : (slot < 2 * KM ? slot - KM < k : true));
+        }
+        if (!any) continue;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int slot = g0 + e;
+            double re = 0.0, im = 0.0;
+            if (slot < KM) { re = sre[slot < KM ? slot : 0]; im = sim[slot < KM ? slot : 0]; }
+            else if (slot < 2 * KM) { const int i = slot - KM; re = cre[i < KM && i >= 0 ? i : 0]; im = cim[i < KM && i >= 0 ? i : 0]; }
+            else if (slot == 2 * KM) re = al;
+            else if (slot == 2 * KM + 1) { re = bre; im = bim; }
+            else if (slot == 2 * KM + 2) re = om;
+            sh[e][0][t] = re;
+            sh[e][1][t] = im;
+        }
+        __syncthreads();
+        if (ty == 0) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int slot = g0 + e;
+                int j = -1;
+                if (slot < KM) j = slot < k ? slot : -1;
+                else if (slot < 2 * KM) j = (slot - KM < k) ? k + (slot - KM) : -1;
+                else if (slot < NE) j = 2 * k + (slot - 2 * KM);
+                if (j >= 0) {
+                    double a = sh[e][0][c], b = sh[e][1][c];
+                    for (int q = 1; q < ry; ++q) { a += sh[e][0][q * m + c]; b += sh[e][1][q * m + c]; }
+                    part[((long)chunk * NE + j) * 2 * C + col] = a;
+                    part[((long)chunk * NE + j) * 2 * C + C + col] = b;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Per-column scalars of DCGS2 step k (one thread per column).  D: reduced dots
+// in the compact order.  Writes the update coefficients (coef rows [0, k): s,
+// rows [KP, KP + k]: d), the scales scv = 1/nu (V_k) and scw = 1/rho (W), the
+// final Hessenberg column k - 1 (Hraw unrotated; Hs then rotated by
+// givens_col) and the tentative column k.  final != 0: only finalize column
+// k - 1 (W absent).  Columns that have stopped get zero coefficients and
+// scales, so their vectors become zero.
+__global__ void k_dcgs_coef(int C, int k, int KP, int flex, int final, double floor_rel, const zd* __restrict__ D,
+                            zd* __restrict__ Hraw, zd* __restrict__ Hs, double* __restrict__ cs, zd* __restrict__ sn,
+                            zd* __restrict__ g, double* __restrict__ resid, double* __restrict__ vscale,
+                            int* __restrict__ kuse, const double* __restrict__ bnorm, double tol,
+                            zd* __restrict__ htent, double* __restrict__ tau, zd* __restrict__ coef,
+                            double* __restrict__ scv, double* __restrict__ scw) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= C) return;
+    auto dv = [&](int j) { return D[(long)j * C + col]; };
+    auto zero_out = [&]() {
+        for (int i = 0; i < k; ++i) coef[(long)i * C + col] = czero<double>();
+        for (int i = 0; i <= k; ++i) coef[(long)(KP + i) * C + col] = czero<double>();
+        scv[col] = 0.0;
+        scw[col] = 0.0;
+    };
+    double nu = 1.0;
+    if (k >= 1) {
+        if (kuse[col] <= k - 1) { if (!final) zero_out(); return; }   // stopped earlier
+        double s2 = 0.0;
+        for (int i = 0; i < k; ++i) s2 += abs2(dv(i));
+        const double alpha = dv(2 * k).re;
+        const double nu2 = alpha - s2;
+        nu = nu2 > floor_rel * alpha ? sqrt(nu2) : sqrt(floor_rel * alpha);
+        if (!(nu > 0.0)) nu = 1.0;                                     // zero vector (breakdown)
+        // final column k - 1: htent + tau s, subdiagonal tau nu
+        const double tp = tau[col];
+        zd* hr = Hraw + (long)(k - 1) * KP * C;
+        zd* hc = Hs + (long)(k - 1) * KP * C;
+        for (int i = 0; i < k; ++i) {
+            zd v = htent[(long)i * C + col];
+            cfma(v, cx(tp, 0.0), dv(i));
+            hr[(long)i * C + col] = v;
+            hc[(long)i * C + col] = v;
+        }
+        const double hn = tp * nu;
+        hr[(long)k * C + col] = cx(hn, 0.0);
+        givens_col(C, k - 1, KP, col, hn, Hs, cs, sn, g, resid, vscale, kuse, bnorm[col], tol);
+        if (final) return;
+        if (kuse[col] <= k) { zero_out(); return; }                    // converged at column k - 1
+    } else if (kuse[col] <= 0) {
+        zero_out();
+        return;
+    }
+    // coefficients of W against the final V_0..V_k
+    const int o = (k >= 1) ? k : 0;
+    zd dk = (k >= 1) ? dv(2 * k + 1) : dv(1);
+    for (int i = 0; i < k; ++i) {
+        const zd ci = dv(o + i);
+        dk = dk - conj(dv(i)) * ci;
+        coef[(long)i * C + col] = dv(i);                 // s_i
+        coef[(long)(KP + i) * C + col] = ci;             // d_i = c_i
+    }
+    dk = cx(dk.re / nu, dk.im / nu);
+    coef[(long)(KP + k) * C + col] = dk;
+    const double omega = (k >= 1) ? dv(2 * k + 2).re : dv(2).re;
+    double d2 = abs2(dk);
+    for (int i = 0; i < k; ++i) d2 += abs2(dv(o + i));
+    const double rho2 = omega - d2;
+    const double rho = rho2 > floor_rel * omega ? sqrt(rho2) : sqrt(floor_rel * omega);
+    // tentative column k
+    for (int l = 0; l <= k; ++l) {
+        zd dl = (l < k) ? dv(o + l) : dk;
+        if (!flex) {
+            zd u = czero<double>();
+            for (int i = (l > 0 ? l - 1 : 0); i < k; ++i) cfma(u, Hraw[((long)i * KP + l) * C + col], dv(i));
+            dl = cx((dl.re - u.re) / nu, (dl.im - u.im) / nu);
+        }
+        htent[(long)l * C + col] = dl;
+    }
+    tau[col] = flex ? rho : rho / nu;
+    scv[col] = 1.0 / nu;
+    scw[col] = rho > 0.0 ? 1.0 / rho : 0.0;
+}
+
+// V_k <- (V_k - sum_{i<k} s_i V_i) scv ;  W <- (W - sum_{i<k} d_i V_i - d_k V_k) scw
+template <typename T, int KM>
+__global__ __launch_bounds__(256) void k_dcgs_update(int n, int m, int k, Cx<T>* __restrict__ V, long vstride,
+                                                     Cx<T>* __restrict__ W, const zd* __restrict__ coef, int KP,
+                                                     const double* __restrict__ scv, const double* __restrict__ scw) {
+    const int s = blockIdx.y, chunk = blockIdx.x;
+    const int c = threadIdx.x, ty = threadIdx.y, ry = blockDim.y;
+    const long base = (long)s * n * m;
+    const int C = gridDim.y * m;
+    const int col = s * m + c;
+    const int r0 = chunk * ROWS_PER_CHUNK, r1 = min(n, r0 + ROWS_PER_CHUNK);
+    extern __shared__ unsigned char dsm[];
+    Cx<T>* hs = reinterpret_cast<Cx<T>*>(dsm);          // [KM][m] s (zero-padded)
+    Cx<T>* hd = hs + KM * m;                            // [KM][m] d (zero-padded)
+    if (ty == 0) {
+        for (int i = 0; i < KM; ++i) {
+            hs[i * m + c] = (i < k) ? ccast<T>(coef[(long)i * C + col]) : czero<T>();
+            hd[i * m + c] = (i < k) ? ccast<T>(coef[(long)(KP + i) * C + col]) : czero<T>();
+        }
+    }
+    __syncthreads();
+    const Cx<T> dk = ccast<T>(coef[(long)(KP + k) * C + col]);
+    const T sv = (T)scv[col], sw = (T)scw[col];
+    Cx<T>* Vk = V + (long)k * vstride;
+    for (int r = r0 + ty; r < r1; r += ry) {
+        const long off = base + (long)r * m + c;
+        Cx<T> x = Vk[off];
+        Cx<T> w = W[off];
+        Cx<T> vv[KM];
+#pragma unroll
+        for (int i = 0; i < KM; ++i) vv[i] = (i < k) ? V[i * vstride + off] : czero<T>();
+#pragma unroll
+        for (int i = 0; i < KM; ++i) {
+            cfms(x, hs[i * m + c], vv[i]);
+            cfms(w, hd[i * m + c], vv[i]);
+        }
+        x.re *= sv;
+        x.im *= sv;
+        cfms(w, dk, x);
+        w.re *= sw;
+        w.im *= sw;
+        if (k > 0) Vk[off] = x;
+        W[off] = w;
+    }
+}
+
+template <typename T, int KM>
+static void dcgs_launch(hipStream_t st, int n, int m, int nsys, int k, Cx<T>* V, long vstride, Cx<T>* W,
+                        const DcgsState& d, int flex, int final, double tol) {
+    const int ry = std::max(1, 256 / m);
+    const int C = nsys * m;
+    constexpr int NE = 2 * KM + 3;
+    const int nchunk_d = ceil_div(n, DCGS_ROWS_PER_CHUNK);
+    double* P = (double*)d.part->ensure(sizeof(double) * (size_t)nchunk_d * NE * 2 * C);
+    dim3 blk(m, ry);
+    const double vec = (double)nsys * n * m * sizeof(Cx<T>);
+    const std::string tag = std::string(sizeof(T) == 8 ? "c128" : "c64") + "_k" + std::to_string(KM);
+    const int ne = 2 * k + 3;
+    hipEvent_t ev = prof_begin(st);
+    k_dcgs_dots<T, KM><<<dim3(nchunk_d, nsys), blk, 0, st>>>(n, m, k, V, vstride, W, P);
+    FH_LAUNCH_CHECK();
+    prof_end(st, ev, "dcgs_dots_" + tag, (k + (W ? 2 : 1)) * vec, 8.0 * (2 * k + 3) * vec / sizeof(Cx<T>));
+    k_reduce_dots<<<dim3(ceil_div(C, 128), ne), 128, 0, st>>>(nchunk_d, ne, NE, C, P, d.D, 0);
+    FH_LAUNCH_CHECK();
+    const double floor_rel = sizeof(T) == 4 ? 1e-7 : 1e-15;
+    k_dcgs_coef<<<ceil_div(C, 128), 128, 0, st>>>(C, k, d.KP, flex, final, floor_rel, d.D, d.Hraw, d.Hs, d.cs, d.sn,
+                                                   d.g, d.resid, d.vscale, d.kuse, d.bnorm, tol, d.htent, d.tau, d.coef,
+                                                   d.scv, d.scw);
+    FH_LAUNCH_CHECK();
+    if (final) return;
+    const int nchunk = ceil_div(n, ROWS_PER_CHUNK);
+    const size_t lds = 2 * sizeof(Cx<T>) * (size_t)KM * m;
+    FH_REQUIRE(lds <= 64 * 1024, -1, "DCGS2: restart length x columns per system too large for the LDS staging");
+    ev = prof_begin(st);
+    k_dcgs_update<T, KM><<<dim3(nchunk, nsys), blk, lds, st>>>(n, m, k, V, vstride, W, d.coef, d.KP, d.scv, d.scw);
+    FH_LAUNCH_CHECK();
+    prof_end(st, ev, "dcgs_update_" + tag, (k + 2 + (k > 0 ? 2 : 1)) * vec, 16.0 * (k + 1) * vec / sizeof(Cx<T>));
+}
+
+template <typename T>
+void dcgs_step(hipStream_t st, int n, int m, int nsys, int k, Cx<T>* V, long vstride, Cx<T>* W, const DcgsState& d,
+               int flex, int final, double tol) {
+    FH_REQUIRE(m >= 1 && m <= 256, -1, "GMRES column count per system must be in [1, 256]");
+    if (k <= 4) dcgs_launch<T, 4>(st, n, m, nsys, k, V, vstride, W, d, flex, final, tol);
+    else if (k <= 8) dcgs_launch<T, 8>(st, n, m, nsys, k, V, vstride, W, d, flex, final, tol);
+    else if (k <= 16) dcgs_launch<T, 16>(st, n, m, nsys, k, V, vstride, W, d, flex, final, tol);
+    else if (k <= 32) dcgs_launch<T, 32>(st, n, m, nsys, k, V, vstride, W, d, flex, final, tol);
+    else throw Error(-1, "DCGS2: restart length above 32 is not supported");
+}
+template void dcgs_step<float>(hipStream_t, int, int, int, int, cf*, long, cf*, const DcgsState&, int, int, double);
 
 // y = R^{-1} g (first kuse[col] steps), per column
 __global__ void k_gmres_trisolve(int C, int k, int KP, const zd* __restrict__ Hs, const zd* __restrict__ g,

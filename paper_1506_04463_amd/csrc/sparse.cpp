@@ -457,6 +457,28 @@ static SolveStats gmres(Ctx& c, SparseState& S, const Batch& b, const Cx<T>* shi
     double* beta = (double*)S.beta.ensure(sizeof(double) * C);
     std::vector<double> hb(C), hbn(C);
     std::vector<int> hk(C);
+    // delayed reorthogonalization: complex FP32 bases up to 32 steps
+    const bool delayed = orth_passes == 3 && sizeof(T) == 4 && restart <= 31;
+    DcgsState dstate;
+    if (delayed) {
+        dstate.KP = KP;
+        dstate.Hs = Hs;
+        dstate.sn = sn;
+        dstate.g = g;
+        dstate.cs = cs;
+        dstate.resid = resid;
+        dstate.vscale = vscale;
+        dstate.kuse = kuse;
+        dstate.bnorm = bn;
+        dstate.Hraw = (zd*)S.Hraw.ensure(sizeof(zd) * (size_t)restart * KP * C);
+        dstate.htent = (zd*)S.htent.ensure(sizeof(zd) * (size_t)KP * C);
+        dstate.tau = (double*)S.tau.ensure(sizeof(double) * C);
+        dstate.coef = (zd*)S.dcoef.ensure(sizeof(zd) * (size_t)2 * KP * C);
+        dstate.scv = (double*)S.scv.ensure(sizeof(double) * C);
+        dstate.scw = (double*)S.scw.ensure(sizeof(double) * C);
+        dstate.D = (zd*)S.dots.ensure(sizeof(zd) * (size_t)(2 * 32 + 3) * C);
+        dstate.part = &S.part;
+    }
     FH_HIP(hipMemsetAsync(X, 0, sizeof(Cx<T>) * vstride, st));
     FH_HIP(hipMemcpyAsync(hbn.data(), bn, sizeof(double) * C, hipMemcpyDeviceToHost, st));
     double prev_worst = 0.0;
@@ -468,7 +490,15 @@ static SolveStats gmres(Ctx& c, SparseState& S, const Batch& b, const Cx<T>* shi
         FH_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * C, hipMemcpyDeviceToHost, st));
         FH_HIP(hipStreamSynchronize(st));
         double worst = 0.0;
-        for (int k = 0; k < C; ++k) worst = std::max(worst, hbn[k] > 0 ? hb[k] / hbn[k] : 0.0);
+        for (int k = 0; k < C; ++k) {
+            // an overflow in the operator or the preconditioner (e.g. an
+            // unstable incomplete factorization in complex FP32) must not pass
+            // for convergence
+            if (!std::isfinite(hb[k]))
+                throw Error(FH_NONFINITE, "non-finite residual in the Krylov solve (system " +
+                                              std::to_string(k / m) + "): the operator or preconditioner overflowed");
+            worst = std::max(worst, hbn[k] > 0 ? hb[k] / hbn[k] : 0.0);
+        }
         stats.relres = worst;
         if (!(worst > tol) || cyc == max_cycles) break;
         if (precond == FH_PC_LEARNED && cyc > 0 && !(worst < LEARNED_STALL * prev_worst)) {
@@ -486,16 +516,30 @@ static SolveStats gmres(Ctx& c, SparseState& S, const Batch& b, const Cx<T>* shi
             Cx<T>* Zk = flex ? Zf + (long)k * vstride : Z;
             apply_P<T>(c, S, b, precond, Vk, Zk, (const T*)nullptr);    // Z = P^{-1} V_k
             apply_M<T>(c, S, b, shifts, T(1), Zk, nullptr, Vk1);        // W = M Z
-            cgs2<T>(st, n, m, b.nsys, k + 1, V, vstride, Vk1, h1, h2, hnorm, S.part, orth_passes);
-            givens_step(st, C, k, KP, h1, h2, hnorm, Hs, cs, sn, g, resid, vscale, kuse, bn, tol);
-            scale_inplace<T>(st, n, m, b.nsys, Vk1, vscale);            // V_{k+1} = W / h_{k+1,k}
             kexec = k + 1;
             stats.steps++;
+            if (delayed) {
+                // V_k reorthogonalized, W -> tentative V_{k+1}, column k - 1 final
+                dcgs_step<T>(st, n, m, b.nsys, k, V, vstride, Vk1, dstate, flex ? 1 : 0, 0, tol);
+            } else {
+                cgs2<T>(st, n, m, b.nsys, k + 1, V, vstride, Vk1, h1, h2, hnorm, S.part, orth_passes);
+                givens_step(st, C, k, KP, h1, h2, hnorm, Hs, cs, sn, g, resid, vscale, kuse, bn, tol);
+                scale_inplace<T>(st, n, m, b.nsys, Vk1, vscale);        // V_{k+1} = W / h_{k+1,k}
+            }
             FH_HIP(hipMemcpyAsync(hk.data(), kuse, sizeof(int) * C, hipMemcpyDeviceToHost, st));
             FH_HIP(hipStreamSynchronize(st));
+            // delayed: the columns known to have stopped are those of column k - 1
+            const int need = delayed ? k : k + 1;
             bool any = false;
-            for (int q = 0; q < C && !any; ++q) any = hk[q] > k + 1;
+            for (int q = 0; q < C && !any; ++q) any = hk[q] > need;
             if (!any) break;
+        }
+        if (delayed) {
+            // the last column is still tentative: finalize it (dots of the
+            // tentative V_kexec only) where a column still runs
+            bool any = false;
+            for (int q = 0; q < C && !any; ++q) any = hk[q] >= kexec;
+            if (any) dcgs_step<T>(st, n, m, b.nsys, kexec, V, vstride, (Cx<T>*)nullptr, dstate, flex ? 1 : 0, 1, tol);
         }
         if (flex) {
             // x += Z y
@@ -551,7 +595,7 @@ static SolveStats solve_batch(Ctx& c, SparseState& S, int nsys, int nright, cons
     zd* sh64 = upload_op_shifts<double>(c, S, nsys, zsys, side_of.data());
     if (o.precision == FH_PREC_FP64)
         return gmres<double>(c, S, b, sh64, B64, X64, restart, std::max(1, o.max_restarts), o.inner_tol, precond, bn,
-                             o.fallback, o.orth == 1 ? 1 : 2);
+                             o.fallback, o.orth == 1 ? 1 : (o.orth == 2 ? 3 : 2));
     // complex FP32 inner solves wrapped in FP64 iterative refinement
     cf* sh32 = upload_op_shifts<float>(c, S, nsys, zsys, side_of.data());
     zd* R = (zd*)S.bufR.ensure(sizeof(zd) * len);
@@ -579,7 +623,7 @@ static SolveStats solve_batch(Ctx& c, SparseState& S, int nsys, int nright, cons
         double* ones = (double*)S.bn32.ensure(sizeof(double) * C);     // |b32 columns| = 1 (or 0)
         colnorms<float>(st, n, m, b.nsys, b32, ones, S.part);
         SolveStats s32 = gmres<float>(c, S, b, sh32, b32, x32, restart, std::max(1, o.max_restarts),
-                                      o.mixed_inner_tol, pc, ones, o.fallback, o.orth == 1 ? 1 : 2);
+                                      o.mixed_inner_tol, pc, ones, o.fallback, o.orth == 1 ? 1 : (o.orth == 2 ? 3 : 2));
         tot.steps += s32.steps;
         tot.fallback |= s32.fallback;
         if (s32.fallback) pc = o.fallback;     // later refinement steps keep the fallback

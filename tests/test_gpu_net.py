@@ -183,9 +183,10 @@ def test_fgmres_with_untrained_net_falls_back_and_meets_tolerance(handle):
     z = np.array([zc[2], zc[3], zc[2]])          # nodes where ILU(0)-GMRES(30) converges
     sides = [0, 0, 1]
     B = np.stack([W.subspace(n, 6, 40 + s) for s in range(3)])
-    for prec in (fh.FH_PREC_FP64, fh.FH_PREC_MIXED):
+    # orth = 2: delayed reorthogonalization in the flexible complex-FP32 solves
+    for prec, orth in ((fh.FH_PREC_FP64, 0), (fh.FH_PREC_MIXED, 0), (fh.FH_PREC_MIXED, 2)):
         o = fh.default_opts(6, precond=fh.FH_PC_LEARNED, fallback=fh.FH_PC_ILU0, restart=30, max_restarts=60,
-                            inner_tol=1e-10, precision=prec, mixed_inner_tol=1e-4, max_refine=12)
+                            inner_tol=1e-10, precision=prec, mixed_inner_tol=1e-4, max_refine=12, orth=orth)
         X, rep = fh.shifted_solve(prob, z, sides, _cuda(B), o)
         X = X.cpu().numpy()
         for s in range(3):

@@ -91,15 +91,15 @@ def _small_convdiff(N=20, m_in=8, m0=16):
     return W.convdiff2d(N=N, m_in=m_in, m0=m0)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_filter_sparse_parity(handle, precision):
+@pytest.mark.parametrize("precision,orth", [(0, 0), (1, 0), (1, 2)])
+def test_filter_sparse_parity(handle, precision, orth):
     p = _small_convdiff()
     A = p.A
     z, w = ct.ellipse_nodes(p.contour.center, p.contour.a, p.contour.ratio, 0.0, 16)
     Qo, Qho = F.contour_filter(L.csr_matrix(A), None, z, w, p.Y0, p.Yh0)
     prob = fh.Problem(handle, _csr(A))
     opts = fh.default_opts(p.m0, solver=1, precond=2, inner_tol=1e-12, restart=30, max_restarts=400,
-                           precision=precision, mixed_inner_tol=1e-5, max_refine=30)
+                           precision=precision, mixed_inner_tol=1e-5, max_refine=30, orth=orth)
     Q, Qh, rep = fh.contour_filter(prob, z, w, _cuda(p.Y0), _cuda(p.Yh0), opts)
     Q, Qh = Q.cpu().numpy(), Qh.cpu().numpy()
     # restarted GMRES reaches ~1e-11 here; the parity bound scales with what it reached
@@ -111,8 +111,8 @@ def test_filter_sparse_parity(handle, precision):
     assert np.linalg.norm(Qh - Qho) / np.linalg.norm(Qho) < tol
 
 
-@pytest.mark.parametrize("precision,precond", [(0, 2), (1, 2)])
-def test_feast_sparse_convdiff_small(handle, precision, precond):
+@pytest.mark.parametrize("precision,precond,orth", [(0, 2, 0), (1, 2, 0), (1, 2, 2)])
+def test_feast_sparse_convdiff_small(handle, precision, precond, orth):
     p = _small_convdiff(N=24, m_in=10, m0=20)
     cont = F.Contour(p.contour.center, p.contour.a, p.contour.ratio, 0.0, 16)
     ref = F.feast(L.csr_matrix(p.A), None, cont, p.Y0, p.Yh0, eps=1e-12, max_iter=30)
@@ -120,7 +120,8 @@ def test_feast_sparse_convdiff_small(handle, precision, precond):
     # Jacobi is a much weaker preconditioner: give its GMRES more cycles
     cycles = 2 if precond == 2 else 8
     opts = fh.default_opts(p.m0, solver=1, precond=precond, inner_tol=1e-3, restart=30, max_restarts=cycles,
-                           precision=precision, mixed_inner_tol=1e-3, max_refine=3, eps=1e-12, max_iter=60)
+                           precision=precision, mixed_inner_tol=1e-3, max_refine=3, eps=1e-12, max_iter=60,
+                           orth=orth)
     out = fh.feast(prob, p.contour.center, p.contour.a, p.contour.ratio, 0.0, 16, _cuda(p.Y0), _cuda(p.Yh0), opts)
     assert out["info"] == 0, out["report"]
     assert len(out["lam"]) == len(ref.lam) == 10
@@ -180,3 +181,60 @@ def test_feast_complex_symmetric_small(handle):
     for i in range(8):          # complex symmetric: Xh parallel to conj(X)
         x, xh = X[:, i], Xh[:, i]
         assert abs(np.vdot(np.conj(x), xh)) / (np.linalg.norm(x) * np.linalg.norm(xh)) > 1 - 1e-9
+
+
+@pytest.mark.parametrize("restart", [30, 20])
+def test_delayed_reorthogonalization_matches_cgs2(handle, restart):
+    """GMRES with delayed reorthogonalization (opts.orth = 2: the second
+    projection of each Krylov vector shares the next step's pass) in the
+    complex-FP32 inner solves reaches the same solutions as classical
+    Gram-Schmidt with reorthogonalization, in about as many Krylov steps, over
+    many restart cycles and refinement steps with columns that stop at
+    different steps.  The inner tolerance 1e-2 sits well above the complex-FP32
+    floor of these solves (about 1e-4 at these interior nodes), where step
+    counts would only measure rounding noise."""
+    N = 20
+    A = W.convdiff2d_csr(N, 20.0, 10.0)
+    n = A["n"]
+    Ad = W.csr_to_dense(A).astype(np.complex128)
+    lam = np.sort(np.linalg.eigvals(Ad).real)
+    prob = fh.Problem(handle, _csr(A))
+    zc, _ = fh.contour_nodes(0.5 * (lam[0] + lam[40]), 0.5 * (lam[40] - lam[0]), 0.3, 0.0, 8)
+    z = np.array([zc[2], zc[3], zc[2], zc[3]])   # nodes where complex-FP32 ILU(0) stays finite
+    sides = [0, 0, 1, 1]
+    B = np.stack([W.subspace(n, 8, 60 + s) for s in range(4)])
+    steps = {}
+    for orth in (0, 2):
+        o = fh.default_opts(8, precond=2, restart=restart, max_restarts=400, inner_tol=1e-10,
+                            precision=fh.FH_PREC_MIXED, mixed_inner_tol=1e-2, max_refine=60, orth=orth)
+        X, rep = fh.shifted_solve(prob, z, sides, _cuda(B), o)
+        X = X.cpu().numpy()
+        for s in range(4):
+            M = z[s] * np.eye(n) - Ad
+            if sides[s]:
+                M = M.conj().T
+            rr = np.linalg.norm(B[s] - M @ X[s], axis=0) / np.linalg.norm(B[s], axis=0)
+            assert rr.max() < 1e-9, (orth, s, rr.max())
+            ref = np.linalg.solve(M, B[s])
+            kap = np.linalg.cond(M)
+            assert np.linalg.norm(X[s] - ref) / np.linalg.norm(ref) < 10 * kap * 1e-10
+        steps[orth] = rep["inner_steps"]
+    assert 0.75 * steps[0] <= steps[2] <= 1.35 * steps[0], steps
+
+
+def test_overflowing_preconditioner_is_reported(handle):
+    """At a node where the complex-FP32 ILU(0) of this convection-dominated
+    operator overflows, the solve reports FH_NONFINITE instead of returning
+    non-finite values as a solution."""
+    N = 20
+    A = W.convdiff2d_csr(N, 20.0, 10.0)
+    n = A["n"]
+    lam = np.sort(np.linalg.eigvals(W.csr_to_dense(A)).real)
+    prob = fh.Problem(handle, _csr(A))
+    zc, _ = fh.contour_nodes(0.5 * (lam[0] + lam[40]), 0.5 * (lam[40] - lam[0]), 0.3, 0.0, 8)
+    B = W.subspace(n, 8, 60)[None]
+    o = fh.default_opts(8, precond=2, restart=30, max_restarts=400, inner_tol=1e-10, precision=fh.FH_PREC_MIXED,
+                        mixed_inner_tol=1e-4, max_refine=40)
+    with pytest.raises(fh.FeastError) as e:
+        fh.shifted_solve(prob, [zc[0]], [0], _cuda(B), o)
+    assert e.value.code == 6
