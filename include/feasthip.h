@@ -250,6 +250,14 @@ int fh_ilu0(fh_handle h, fh_problem p, double z_re, double z_im, void* lu);
 int fh_ilu0_apply(fh_handle h, fh_problem p, double z_re, double z_im, int side, int m,
                   const void* X, void* Out);
 
+/* The same apply in complex FP32, as the mixed-precision Krylov solves use
+ * it: the ILU(0) is computed in FP64 and its factors are rounded to FP32;
+ * X, Out: device complex-FP32 (interleaved float pairs) n x m blocks.
+ * Returns FH_OK, -k for an invalid argument k, FH_SINGULAR_SHIFT on a zero
+ * pivot. */
+int fh_ilu0_apply_c64(fh_handle h, fh_problem p, double z_re, double z_im, int side, int m,
+                      const void* X, void* Out);
+
 /* Shifted solves, the linear systems of the contour filter (Section 2.4,
  * eq:qr and eq:ql) for arbitrary shifts:
  *   sides[s] == 0:  (z_s B - A) X_s = B_s

@@ -96,6 +96,7 @@ def lib():
         "fh_shifted_apply": (i, [vp, vp, i, i, dp, i, vp, vp]),
         "fh_ilu0": (i, [vp, vp, d, d, vp]),
         "fh_ilu0_apply": (i, [vp, vp, d, d, i, i, vp, vp]),
+        "fh_ilu0_apply_c64": (i, [vp, vp, d, d, i, i, vp, vp]),
         "fh_shifted_solve": (i, [vp, vp, i, dp, ip, i, C.POINTER(fh_opts), vp, vp, C.POINTER(fh_report)]),
         "fh_feast_batched": (i, [vp, i, C.POINTER(vp), C.POINTER(fh_contour), C.POINTER(fh_opts), C.POINTER(vp),
                                  C.POINTER(vp), C.POINTER(vp), C.POINTER(dp), C.POINTER(fh_report)]),
@@ -409,8 +410,17 @@ def ilu0(prob: Problem, z):
 
 
 def ilu0_apply(prob: Problem, z, side, X):
+    """(LU)^{-1} X (side 0) or (LU)^{-H} X (side 1) with the ILU(0) of (z - A);
+    X: complex128 (n, m) CUDA tensor, or complex64 for the complex-FP32 apply."""
     torch = _torch()
     Out = torch.empty_like(X)
+    if X.dtype == torch.complex64:
+        if not (X.is_cuda and X.is_contiguous() and X.dim() == 2 and X.shape[0] == prob.n):
+            raise ValueError(f"X must be a contiguous ({prob.n}, m) complex64 CUDA tensor")
+        prob.handle.check(lib().fh_ilu0_apply_c64(prob.handle._h, prob._p, complex(z).real, complex(z).imag, side,
+                                                  X.shape[1], C.c_void_p(X.data_ptr()), C.c_void_p(Out.data_ptr())),
+                          "fh_ilu0_apply_c64")
+        return Out
     prob.handle.check(lib().fh_ilu0_apply(prob.handle._h, prob._p, complex(z).real, complex(z).imag, side,
                                           X.shape[1], _dptr(X), _dptr(Out)), "fh_ilu0_apply")
     return Out

@@ -373,6 +373,22 @@ int fh_ilu0_apply(fh_handle h, fh_problem p, double z_re, double z_im, int side,
     FH_API_END(h)
 }
 
+int fh_ilu0_apply_c64(fh_handle h, fh_problem p, double z_re, double z_im, int side, int m, const void* X,
+                      void* Out) {
+    if (!h) return -1;
+    if (!p || p->dense) return -2;
+    if (side != 0 && side != 1) return -5;
+    if (m < 1) return -6;
+    if (!X) return -7;
+    if (!Out) return -8;
+    FH_API_BEGIN(h)
+    set_device(h);
+    sparse_ilu0_apply32(*h, *p, cplx(z_re, z_im), side, m, (const cf*)X, (cf*)Out);
+    FH_HIP(hipStreamSynchronize(h->stream));
+    return FH_OK;
+    FH_API_END(h)
+}
+
 int fh_feast_batched(fh_handle h, int count, const fh_problem* problems, const fh_contour* contours,
                      const fh_opts* o, void* const* Y, void* const* Yh, void* const* lambda, double* const* res,
                      fh_report* reports) {

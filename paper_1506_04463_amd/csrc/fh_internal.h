@@ -89,6 +89,7 @@ void sparse_apply_A(Ctx& c, Prob& p, int side, int m, const zd* X, zd* Out);
 void sparse_shifted_apply(Ctx& c, Prob& p, int side, int nsys, const cplx* shifts, int m, const zd* X, zd* Out);
 void sparse_ilu0(Ctx& c, Prob& p, cplx z, zd* lu_out);
 void sparse_ilu0_apply(Ctx& c, Prob& p, cplx z, int side, int m, const zd* X, zd* Out);
+void sparse_ilu0_apply32(Ctx& c, Prob& p, cplx z, int side, int m, const cf* X, cf* Out);
 void sparse_destroy(SparseState* s);
 void sparse_shifted_solve(Ctx& c, Prob& p, int nsys, const cplx* z, const int* sides, int m, const zd* B, zd* X,
                           const fh_opts& o, fh_report* rep);

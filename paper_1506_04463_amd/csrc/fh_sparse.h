@@ -14,6 +14,7 @@ struct CsrDev {
     const void* val32 = nullptr;
     bool complex_vals = false;
     long nnz = 0;
+    int maxrow = 0;   // longest row (entries)
     template <typename T> const void* val() const { return sizeof(T) == sizeof(double) ? val64 : val32; }
 };
 

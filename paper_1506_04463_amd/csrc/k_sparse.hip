@@ -49,6 +49,88 @@ __global__ void k_spmm(int n, int m, const int* __restrict__ rowptr, const int* 
     Out[base + (long)r * m + c] = res;
 }
 
+// Same product for rows of at most SL entries (m >= 16 columns per system):
+// the block first stages its rows' entries in LDS as a padded SL-slot table
+// (empty slots point at the row itself with weight zero), then every thread
+// issues the gathers of its RPT rows together, so that a wave keeps RPT x SL
+// independent loads in flight instead of walking one row's chain of
+// dependent loads (row pointer, column index, then the gathered value).
+// block (m, ry), grid (ceil(n / (ry RPT)), nsys); rows r0 + ty + j ry.
+template <typename T, typename TA, bool CONJ, int SL, int RPT>
+__global__ __launch_bounds__(256) void k_spmm_rows(int n, int m, const int* __restrict__ rowptr,
+                                                   const int* __restrict__ col, const TA* __restrict__ val,
+                                                   const Cx<T>* __restrict__ shifts, T alpha,
+                                                   const Cx<T>* __restrict__ X, const Cx<T>* __restrict__ Yadd,
+                                                   Cx<T>* __restrict__ Out) {
+    constexpr int MAXR = 16 * RPT;                    // ry <= 16 (m >= 16)
+    __shared__ int s_col[MAXR * SL];
+    __shared__ TA s_val[MAXR * SL];
+    const int c = threadIdx.x, ty = threadIdx.y, ry = blockDim.y;
+    const int rows = ry * RPT;
+    const int r0 = blockIdx.x * rows;
+    const int s = blockIdx.y;
+    const int tid = ty * m + c, nt = m * ry;
+    for (int idx = tid; idx < rows * SL; idx += nt) {
+        const int rl = idx / SL, q = idx - rl * SL;
+        const int r = r0 + rl;
+        int cc = 0;
+        TA vv{};
+        if (r < n) {
+            const int p = rowptr[r] + q;
+            cc = r;
+            if (p < rowptr[r + 1]) { cc = col[p]; vv = val[p]; }
+        }
+        s_col[idx] = cc;
+        s_val[idx] = vv;
+    }
+    __syncthreads();
+    const long base = (long)s * n * m;
+    const Cx<T>* Xs = X + base;
+    Cx<T> xv[RPT][SL];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int rl = ty + j * ry;
+#pragma unroll
+        for (int q = 0; q < SL; ++q) xv[j][q] = Xs[(long)s_col[rl * SL + q] * m + c];
+    }
+    const Cx<T> sh = shifts ? shifts[s] : czero<T>();
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int rl = ty + j * ry;
+        const int r = r0 + rl;
+        Cx<T> acc = czero<T>();
+#pragma unroll
+        for (int q = 0; q < SL; ++q) mac_val(acc, s_val[rl * SL + q], xv[j][q], CONJ);
+        if (r < n) {
+            Cx<T> res = shifts ? sh * Xs[(long)r * m + c] : czero<T>();
+            res = alpha * (res - acc);
+            if (Yadd) res = res + Yadd[base + (long)r * m + c];
+            Out[base + (long)r * m + c] = res;
+        }
+    }
+}
+
+template <typename T, typename TA, bool CONJ, int SL, int RPT>
+static void spmm_rows_launch(hipStream_t st, int n, int m, int nsys, const CsrDev& A, const TA* v,
+                             const Cx<T>* shifts, T alpha, const Cx<T>* X, const Cx<T>* Yadd, Cx<T>* Out) {
+    const int ry = 256 / m;
+    dim3 blk(m, ry), grid(ceil_div(n, ry * RPT), nsys);
+    k_spmm_rows<T, TA, CONJ, SL, RPT><<<grid, blk, 0, st>>>(n, m, A.rowptr, A.col, v, shifts, alpha, X, Yadd, Out);
+}
+
+template <typename T, typename TA, bool CONJ>
+static bool spmm_rows(hipStream_t st, int n, int m, int nsys, const CsrDev& A, const TA* v, const Cx<T>* shifts,
+                      T alpha, const Cx<T>* X, const Cx<T>* Yadd, Cx<T>* Out) {
+    // whole warps of columns, at most 16 row groups per block
+    if (m < 16 || m > 256 || 256 % m != 0 || A.maxrow < 1) return false;
+    if (A.maxrow <= 5) spmm_rows_launch<T, TA, CONJ, 5, 4>(st, n, m, nsys, A, v, shifts, alpha, X, Yadd, Out);
+    else if (A.maxrow <= 8) spmm_rows_launch<T, TA, CONJ, 8, 4>(st, n, m, nsys, A, v, shifts, alpha, X, Yadd, Out);
+    else if (A.maxrow <= 16) spmm_rows_launch<T, TA, CONJ, 16, 2>(st, n, m, nsys, A, v, shifts, alpha, X, Yadd, Out);
+    else if (A.maxrow <= 32) spmm_rows_launch<T, TA, CONJ, 32, 1>(st, n, m, nsys, A, v, shifts, alpha, X, Yadd, Out);
+    else return false;
+    return true;
+}
+
 template <typename T>
 void spmm(hipStream_t st, const CsrDev& A, bool conj_t, int n, int m, int nsys, const Cx<T>* shifts, T alpha,
           const Cx<T>* X, const Cx<T>* Yadd, Cx<T>* Out) {
@@ -58,11 +140,17 @@ void spmm(hipStream_t st, const CsrDev& A, bool conj_t, int n, int m, int nsys, 
     hipEvent_t ev = prof_begin(st);
     if (A.complex_vals) {
         const Cx<T>* v = (const Cx<T>*)A.val<T>();
-        if (conj_t) k_spmm<T, Cx<T>, true><<<grid, blk, 0, st>>>(n, m, A.rowptr, A.col, v, shifts, alpha, X, Yadd, Out);
-        else k_spmm<T, Cx<T>, false><<<grid, blk, 0, st>>>(n, m, A.rowptr, A.col, v, shifts, alpha, X, Yadd, Out);
+        if (conj_t) {
+            if (!spmm_rows<T, Cx<T>, true>(st, n, m, nsys, A, v, shifts, alpha, X, Yadd, Out))
+                k_spmm<T, Cx<T>, true><<<grid, blk, 0, st>>>(n, m, A.rowptr, A.col, v, shifts, alpha, X, Yadd, Out);
+        } else {
+            if (!spmm_rows<T, Cx<T>, false>(st, n, m, nsys, A, v, shifts, alpha, X, Yadd, Out))
+                k_spmm<T, Cx<T>, false><<<grid, blk, 0, st>>>(n, m, A.rowptr, A.col, v, shifts, alpha, X, Yadd, Out);
+        }
     } else {
         const T* v = (const T*)A.val<T>();
-        k_spmm<T, T, false><<<grid, blk, 0, st>>>(n, m, A.rowptr, A.col, v, shifts, alpha, X, Yadd, Out);
+        if (!spmm_rows<T, T, false>(st, n, m, nsys, A, v, shifts, alpha, X, Yadd, Out))
+            k_spmm<T, T, false><<<grid, blk, 0, st>>>(n, m, A.rowptr, A.col, v, shifts, alpha, X, Yadd, Out);
     }
     FH_LAUNCH_CHECK();
     if (ev) {

@@ -274,11 +274,13 @@ void sparse_prepare(Ctx& c, Prob& p) {
     S->A.complex_vals = cplx_vals;
     S->A.nnz = nnz;
     S->AT.nnz = nnz;
+    for (int i = 0; i < n; ++i) S->A.maxrow = std::max(S->A.maxrow, rp[i + 1] - rp[i]);
     S->A.val32 = S->aval32.ensure(vb / 2 * std::max<long>(1, nnz));
     cast_vals(st, nnz, cplx_vals, p.A.val, (void*)S->A.val32);
     std::vector<int> atrp, atci, at2a;
     transpose_pattern(n, rp, ci, atrp, atci, at2a);
     S->AT.rowptr = dev_ints(*S, atrp, st);
+    for (int i = 0; i < n; ++i) S->AT.maxrow = std::max(S->AT.maxrow, atrp[i + 1] - atrp[i]);
     S->AT.col = dev_ints(*S, atci, st);
     int* at2a_d = dev_ints(*S, at2a, st);
     S->AT.complex_vals = cplx_vals;
@@ -760,6 +762,27 @@ void sparse_ilu0(Ctx& c, Prob& p, cplx z, zd* lu_out) {
     gather_vals(c.stream, S.nnzA, true, S.lu64.p, idx, lu_out);
     FH_HIP(hipStreamSynchronize(c.stream));
     S.fact_z.clear();   // single-node factors are not a filter node set
+}
+
+void sparse_ilu0_apply32(Ctx& c, Prob& p, cplx z, int side, int m, const cf* X, cf* Out) {
+    SparseState& S = *p.sp;
+    fh_opts o;
+    std::memset(&o, 0, sizeof(o));
+    o.save_factors = 0;
+    ensure_factors(c, S, 1, &z, true, o, nullptr);
+    int node = 0;
+    FH_HIP(hipMemcpyAsync(S.node_of.ensure(sizeof(int)), &node, sizeof(int), hipMemcpyHostToDevice, c.stream));
+    FH_HIP(hipMemcpyAsync(S.side_of.ensure(sizeof(int)), &side, sizeof(int), hipMemcpyHostToDevice, c.stream));
+    Batch b;
+    b.nsys = 1;
+    b.nright = side == 0 ? 1 : 0;
+    b.m = m;
+    DBuf xb;
+    cf* xc = (cf*)xb.ensure(sizeof(cf) * (size_t)S.n * m);
+    FH_HIP(hipMemcpyAsync(xc, X, sizeof(cf) * (size_t)S.n * m, hipMemcpyDeviceToDevice, c.stream));
+    apply_P<float>(c, S, b, FH_PC_ILU0, xc, Out, nullptr);
+    FH_HIP(hipStreamSynchronize(c.stream));
+    S.fact_z.clear();
 }
 
 void sparse_ilu0_apply(Ctx& c, Prob& p, cplx z, int side, int m, const zd* X, zd* Out) {

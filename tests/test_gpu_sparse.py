@@ -48,7 +48,7 @@ PROBS = {
 
 
 @pytest.mark.parametrize("name", list(PROBS))
-@pytest.mark.parametrize("m", [1, 5, 64])
+@pytest.mark.parametrize("m", [1, 5, 16, 64])
 def test_shifted_apply(handle, name, m):
     A = PROBS[name]()
     n = A["n"]
@@ -85,6 +85,54 @@ def test_ilu0_apply_both_sides(handle, name, m):
         out = fh.ilu0_apply(prob, z, side, _cuda(X)).cpu().numpy()
         ref = L.ilu0_apply(A["rowptr"], A["colind"], ref_lu, X, trans)
         np.testing.assert_allclose(out, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("name", list(PROBS))
+@pytest.mark.parametrize("m", [1, 7, 64])
+def test_ilu0_apply_c64_both_sides(handle, name, m):
+    """The complex-FP32 apply (the one the mixed-precision solves use) against
+    the oracle's FP64 apply, to FP32 accuracy."""
+    A = PROBS[name]()
+    n = A["n"]
+    prob = fh.Problem(handle, _csr(A))
+    z = 2.0 - 1.5j if name != "convdiff" else 500.0 + 20.0j
+    ref_lu = L.ilu0(A["rowptr"], A["colind"], _shift_vals(A, z))
+    X = W.subspace(n, m, 5)
+    for side, trans in ((0, "N"), (1, "H")):
+        out = fh.ilu0_apply(prob, z, side, _cuda(X.astype(np.complex64))).cpu().numpy()
+        ref = L.ilu0_apply(A["rowptr"], A["colind"], ref_lu, X.astype(np.complex64).astype(np.complex128), trans)
+        np.testing.assert_allclose(out, ref, rtol=0, atol=2e-5 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("m", [5, 64])
+def test_ilu0_apply_c64_many_levels(handle, m):
+    """160 x 160 grid: 319 dependent levels per sweep (not a multiple of the
+    sweep's four-level unrolling), levels up to 160 rows wide (1,280 items per
+    workgroup at 8 columns).  Checked by the defining property L U y = x with
+    the oracle's factors, and against the complex-FP64 apply."""
+    N = 160
+    A = W.convdiff2d_csr(N, 20.0, 10.0)
+    n = A["n"]
+    prob = fh.Problem(handle, _csr(A))
+    z = 300.0 + 40.0j
+    lu = L.ilu0(A["rowptr"], A["colind"], _shift_vals(A, z))
+    rp, ci = A["rowptr"], A["colind"]
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    low = ci < rows
+    Lm = sp.csr_matrix((lu[low], (rows[low], ci[low])), shape=(n, n)) + sp.identity(n, format="csr")
+    Um = sp.csr_matrix((lu[~low], (rows[~low], ci[~low])), shape=(n, n))
+    X = W.subspace(n, m, 9).astype(np.complex64)
+    Xd = _cuda(X)
+    for side in (0, 1):
+        y = fh.ilu0_apply(prob, z, side, Xd).cpu().numpy().astype(np.complex128)
+        if side == 0:
+            r = Lm @ (Um @ y) - X
+        else:
+            r = Um.conj().T @ (Lm.conj().T @ y) - X
+        nrm = np.abs(X).max() + (abs(Lm) @ (abs(Um) @ np.abs(y))).max()
+        assert np.abs(r).max() < 1e-5 * nrm, (side, np.abs(r).max() / nrm)
+        y64 = fh.ilu0_apply(prob, z, side, _cuda(X.astype(np.complex128))).cpu().numpy()
+        assert np.abs(y - y64).max() < 1e-4 * np.abs(y64).max()
 
 
 def _small_convdiff(N=20, m_in=8, m0=16):
