@@ -189,7 +189,7 @@ struct FeastRun {
     std::vector<cplx> z, w;
     int n, m0in, ne;
     double alpha;
-    zd *Ycur, *Yhcur, *Q, *Qh, *U, *Uh, *T1, *T2, *BQ, *S, *Sh, *gam, *AUr, *BUr, *lam, *W, *Wh;
+    zd *Ycur, *Yhcur, *Q, *Qh, *U, *Uh, *T1, *T2, *T3, *T4, *BQ, *S, *Sh, *gam, *AUr, *BUr, *lam, *W, *Wh;
     double *num, *den, *num2, *den2;
     int *ints, *perm;
     int mcur = 0, it = 0, info = FH_NOT_CONVERGED, m_s = 0, prev_nconv = -1;
@@ -218,6 +218,8 @@ struct FeastRun {
         Uh = (zd*)B.Uh.ensure(sizeof(zd) * big);
         T1 = (zd*)B.T1.ensure(sizeof(zd) * big);
         T2 = (zd*)B.T2.ensure(sizeof(zd) * big);
+        T3 = (zd*)B.T3.ensure(sizeof(zd) * big);
+        T4 = (zd*)B.T4.ensure(sizeof(zd) * big);
         BQ = (zd*)B.BQ.ensure(sizeof(zd) * sm);
         S = (zd*)B.S.ensure(sizeof(zd) * sm);
         Sh = (zd*)B.Sh.ensure(sizeof(zd) * sm);
@@ -296,17 +298,53 @@ struct FeastRun {
         FH_REQUIRE(mt >= 1 && mt <= mcur, FH_EIG_FAILED, "resize produced an empty subspace");
     }
 
-    // step 3.d and 4.a
-    void launch_rr() {
-        gemm<double>(c.stream, 'N', 'N', n, mt, mcur, cx(1.0, 0.0), Q, mcur, 0, S, mcur, 0, czero<double>(), U,
-                     mt, 0, 1);
-        gemm<double>(c.stream, 'N', 'N', n, mt, mcur, cx(1.0, 0.0), Qh, mcur, 0, Sh, mcur, 0, czero<double>(), Uh,
-                     mt, 0, 1);
-        apply_A(c, p, 0, mt, U, T1);
+    // Products of steps 3-5.  The batched driver sets gN / gC: dense products
+    // are then appended to these lists (op(A) = A, resp. A^H) and launched by
+    // it as one grouped GEMM over all runs; otherwise they launch here.
+    std::vector<GItem<double>>* gN = nullptr;
+    std::vector<GItem<double>>* gC = nullptr;
+    // C (M x N, ld ldc) = op(A) B, op 'N' or 'C', row-major
+    void prod(char op, int M, int N, int K, const zd* A, long lda, const zd* B, long ldb, zd* C, long ldc) {
+        std::vector<GItem<double>>* sink = op == 'C' ? gC : gN;
+        if (sink) {
+            sink->push_back(GItem<double>{A, B, C, M, N, K, (int)lda, (int)ldb, (int)ldc, 0, 0, cx(1.0, 0.0), 0});
+            return;
+        }
+        gemm<double>(c.stream, op, 'N', M, N, K, cx(1.0, 0.0), A, lda, 0, B, ldb, 0, czero<double>(), C, ldc, 0, 1);
+    }
+    // op(A) X or op(B) X of this run's problem (side 1: conjugate transpose)
+    void prod_A(int side, int m, const zd* X, zd* Out) {
+        if (!p.dense) { apply_A(c, p, side, m, X, Out); return; }
+        prod(side ? 'C' : 'N', n, m, n, (const zd*)p.A.val, p.A.ld, X, m, Out, m);
+    }
+    // returns the operand that holds op(B) X (X itself when B = I)
+    const zd* prod_B(int side, int m, const zd* X, zd* Out) {
+        if (!p.hasB) return X;
+        if (!p.dense) { apply_B(c, p, side, m, X, Out); return Out; }
+        prod(side ? 'C' : 'N', n, m, n, (const zd*)p.B.val, p.B.ld, X, m, Out, m);
+        return Out;
+    }
+
+    // step 3.d: U = Q S, Uh = Qh Sh
+    void launch_rr_a() {
+        prod('N', n, mt, mcur, Q, mcur, S, mcur, U, mt);        // S, Sh: mcur x mcur (first mt columns used)
+        prod('N', n, mt, mcur, Qh, mcur, Sh, mcur, Uh, mt);
+    }
+    // step 4.a, products with the operators
+    const zd* BUin = nullptr;
+    void launch_rr_b() {
+        prod_A(0, mt, U, T1);
+        BUin = prod_B(0, mt, U, T2);
+    }
+    // step 4.a: A_U = Uh^H A U, B_U = Uh^H B U
+    void launch_rr_c() {
         gemm_hn_tall(c.stream, n, mt, mt, Uh, mt, T1, mt, AUr, mt, c.partial);
-        const zd* BUin = U;
-        if (p.hasB) { apply_B(c, p, 0, mt, U, T2); BUin = T2; }
         gemm_hn_tall(c.stream, n, mt, mt, Uh, mt, BUin, mt, BUr, mt, c.partial);
+    }
+    void launch_rr() {
+        launch_rr_a();
+        launch_rr_b();
+        launch_rr_c();
     }
 
     // after step 4.b (eig_reduced): Ritz values, step 4.c
@@ -318,19 +356,28 @@ struct FeastRun {
         for (int i = 0; i < mt; ++i) rho[i] = rational(ne, z.data(), w.data(), hlam[i]);
     }
 
-    // step 4.d and the products of step 5.b
-    void launch_ritz() {
-        gemm<double>(c.stream, 'N', 'N', n, mt, mt, cx(1.0, 0.0), U, mt, 0, W, mt, 0, czero<double>(), Ycur, mt, 0, 1);
-        gemm<double>(c.stream, 'N', 'N', n, mt, mt, cx(1.0, 0.0), Uh, mt, 0, Wh, mt, 0, czero<double>(), Yhcur, mt, 0,
-                     1);
-        apply_A(c, p, 0, mt, Ycur, T1);
-        const zd* BY = Ycur;
-        if (p.hasB) { apply_B(c, p, 0, mt, Ycur, T2); BY = T2; }
+    // step 4.d: Y = U W, Yh = Uh Wh
+    void launch_ritz_a() {
+        prod('N', n, mt, mt, U, mt, W, mt, Ycur, mt);
+        prod('N', n, mt, mt, Uh, mt, Wh, mt, Yhcur, mt);
+    }
+    // products of step 5.b: A Y, B Y, A^H Yh, B^H Yh
+    const zd *BY = nullptr, *BhYh = nullptr;
+    void launch_ritz_b() {
+        prod_A(0, mt, Ycur, T1);
+        BY = prod_B(0, mt, Ycur, T2);
+        prod_A(1, mt, Yhcur, T3);
+        BhYh = prod_B(1, mt, Yhcur, T4);
+    }
+    // step 5.b: residual norms of the right and left pairs
+    void launch_ritz_c() {
         res_colnorms(c.stream, n, mt, T1, BY, mt, lam, false, num, den, c.partial);
-        apply_A(c, p, 1, mt, Yhcur, T1);
-        const zd* BhYh = Yhcur;
-        if (p.hasB) { apply_B(c, p, 1, mt, Yhcur, T2); BhYh = T2; }
-        res_colnorms(c.stream, n, mt, T1, BhYh, mt, lam, true, num2, den2, c.partial2);
+        res_colnorms(c.stream, n, mt, T3, BhYh, mt, lam, true, num2, den2, c.partial2);
+    }
+    void launch_ritz() {
+        launch_ritz_a();
+        launch_ritz_b();
+        launch_ritz_c();
     }
 
     // steps 5.a-5.c; true when the run is over
@@ -479,6 +526,8 @@ int feast_batched(Ctx& c, int count, Prob* const* probs, const fh_contour* cts, 
     }
     DenseGroup G;
     DBuf jobbuf;
+    std::vector<GItem<double>> gn, gc;
+    GroupPlan<double> gp[8];
     fh_report frep{};
     dg_build(c, G, plist, zs, o.precision == FH_PREC_MIXED, &frep);
     std::vector<int> first(count);   // first system of each instance
@@ -548,12 +597,28 @@ int feast_batched(Ctx& c, int count, Prob* const* probs, const fh_contour* cts, 
         to_dev(c, dj, jobs.data(), jobs.size());
         eig_biortho_batched(st, (int)act.size(), dj);
         for (FeastRun* r : act) r->read_bq();
-        for (FeastRun* r : act) r->launch_rr();
+        // the products of steps 3-5 of all runs as grouped GEMMs, one launch
+        // per dependent stage (each plan's work list is used once per iteration)
+        auto grouped = [&](GroupPlan<double>& pn, GroupPlan<double>& pc) {
+            if (!gn.empty()) { group_gemm_plan(pn, false, gn, GTILE_64); pn.run(st); gn.clear(); }
+            if (!gc.empty()) { group_gemm_plan(pc, true, gc, GTILE_64); pc.run(st); gc.clear(); }
+        };
+        for (FeastRun* r : act) { r->gN = &gn; r->gC = &gc; }
+        for (FeastRun* r : act) r->launch_rr_a();
+        grouped(gp[0], gp[1]);
+        for (FeastRun* r : act) r->launch_rr_b();
+        grouped(gp[2], gp[3]);
+        for (FeastRun* r : act) r->launch_rr_c();
         for (size_t k = 0; k < act.size(); ++k) jobs[k] = act[k]->job_reduced();
         to_dev(c, dj, jobs.data(), jobs.size());
         eig_reduced_batched(st, (int)act.size(), dj);
         for (FeastRun* r : act) r->read_lam();
-        for (FeastRun* r : act) r->launch_ritz();
+        for (FeastRun* r : act) r->launch_ritz_a();
+        grouped(gp[4], gp[5]);
+        for (FeastRun* r : act) r->launch_ritz_b();
+        grouped(gp[6], gp[7]);
+        for (FeastRun* r : act) r->launch_ritz_c();
+        for (FeastRun* r : act) { r->gN = nullptr; r->gC = nullptr; }
         for (FeastRun* r : act) r->decide();
     }
     int worst = FH_OK;

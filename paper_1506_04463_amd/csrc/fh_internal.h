@@ -20,8 +20,8 @@ struct FilterBufs {
     DBuf X, Xh, R, Rh, wdev, zdev;
 };
 struct FeastBufs {
-    DBuf Ycur, Yhcur, Q, Qh, U, Uh, T1, T2, BQ, S, Sh, gam, AUr, BUr, lam, W, Wh, num, den, num2, den2, ints,
-        perm;
+    DBuf Ycur, Yhcur, Q, Qh, U, Uh, T1, T2, T3, T4, BQ, S, Sh, gam, AUr, BUr, lam, W, Wh, num, den, num2, den2,
+        ints, perm;
 };
 
 struct Ctx {
