@@ -206,7 +206,8 @@ def dense_batch(args):
         roof = {"bound": "mfma", "kernel": name, "achieved": tf, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "frac": tf / PEAK_FP32_MFMA_TFLOPS, "traffic": None, "avg_ms": st["ms"] / st["count"],
                 "launches": st["count"], "flops_per_launch": st["flops"] / st["count"]}
-    kernels = {k: {"ms_total": v["ms"], "count": v["count"]}
+    kernels = {k: {"ms_total": v["ms"], "count": v["count"],
+                   "TFLOPs": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v.get("flops") else None}
                for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])[:8]}
     line = {"metric": "dense batch: time to solution and shifted-solve RHS/s at eq:res <= 1e-10",
             "value": rhs / t_fast, "unit": "RHS/s", "n_gpus": 1, "steps": 1, "warmup": 1,

@@ -117,6 +117,22 @@ void dg_build(Ctx& c, DenseGroup& G, const std::vector<Prob*>& probs,
         group_lu_plan<float>(lu, cnt, mp.data(), G.n.data(), pv.data(), iv.data(), G.tile_lu);
         lu.run(st);
         G.M64.release();   // the FP64 matrices are not kept: residuals use A and B
+        // inverses of the complex-FP32 factorizations: LU X = I, n right-hand sides
+        cf* inv = (cf*)G.Inv32.ensure(sizeof(cf) * mt);
+        FH_HIP(hipMemsetAsync(inv, 0, sizeof(cf) * mt, st));
+        long* doffm = (long*)G.doff.ensure(sizeof(long) * cnt);
+        int* dnm = (int*)G.dn.ensure(sizeof(int) * cnt);
+        FH_HIP(hipMemcpyAsync(doffm, G.moff.data(), sizeof(long) * cnt, hipMemcpyHostToDevice, st));
+        FH_HIP(hipMemcpyAsync(dnm, G.n.data(), sizeof(int) * cnt, hipMemcpyHostToDevice, st));
+        set_identity(st, cnt, nmax, doffm, dnm, inv);
+        std::vector<cf*> xp(cnt);
+        for (int s = 0; s < cnt; ++s) xp[s] = inv + G.moff[s];
+        GroupPlan<float> sol;
+        group_solve_plan<float>(sol, 'N', cnt, mp.data(), G.n.data(), pv.data(), xp.data(), G.n.data(), G.tile_lu);
+        sol.run(st);
+        FH_HIP(hipStreamSynchronize(st));       // the layout arrays are rewritten by dg_layout
+        G.layout_vtot = -1;
+        G.M32.release();
     } else {
         std::vector<zd*> mp(cnt);
         for (int s = 0; s < cnt; ++s) mp[s] = M64 + G.moff[s];
@@ -163,15 +179,20 @@ void dg_layout(Ctx& c, DenseGroup& G, const std::vector<int>& m) {
     cf* Xh32 = nullptr;
     zd* R = nullptr;
     zd* Rh = nullptr;
+    cf* T32 = nullptr;
+    cf* Th32 = nullptr;
     if (G.mixed) {
         X32 = (cf*)G.X32.ensure(sizeof(cf) * std::max<long>(1, tot));
         Xh32 = (cf*)G.Xh32.ensure(sizeof(cf) * std::max<long>(1, tot));
+        T32 = (cf*)G.T32.ensure(sizeof(cf) * std::max<long>(1, tot));
+        Th32 = (cf*)G.Th32.ensure(sizeof(cf) * std::max<long>(1, tot));
         R = (zd*)G.R.ensure(vb);
         Rh = (zd*)G.Rh.ensure(vb);
     }
-    const void* key[4] = {Xv, Xhv, G.mixed ? (const void*)X32 : nullptr, G.mixed ? (const void*)R : nullptr};
+    const void* key[5] = {Xv, Xhv, G.mixed ? (const void*)X32 : nullptr, G.mixed ? (const void*)R : nullptr,
+                          G.mixed ? (const void*)T32 : nullptr};
     bool same = G.layout_vtot == tot && same_m;
-    for (int q = 0; q < 4; ++q) same = same && key[q] == G.layout_key[q];
+    for (int q = 0; q < 5; ++q) same = same && key[q] == G.layout_key[q];
     if (same) return;
     FH_HIP(hipStreamSynchronize(c.stream));   // earlier solves may still read the old plans
     G.drop_graphs();
@@ -196,17 +217,20 @@ void dg_layout(Ctx& c, DenseGroup& G, const std::vector<int>& m) {
     } else {
         int nmax = 0;
         for (int v : G.n) nmax = std::max(nmax, v);
-        G.tile_solve = autotune_tile(c, nmax, std::max(1, mmax), GNB, std::min(cnt, 8));
-        std::vector<cf*> mp(cnt), xr(cnt), xl(cnt);
+        G.tile_solve = autotune_tile(c, nmax, std::max(1, mmax), nmax, std::min(cnt, 8));
+        // solves: X32 = M^{-1} T32 (right), Xh32 = M^{-H} Th32 (left)
+        std::vector<GItem<float>> gr, gl;
         for (int s = 0; s < cnt; ++s) {
-            mp[s] = (cf*)G.M32.p + G.moff[s];
-            xr[s] = X32 + G.voff[s];
-            xl[s] = Xh32 + G.voff[s];
+            if (m[s] <= 0) continue;
+            const int n = G.n[s];
+            const cf* inv = (const cf*)G.Inv32.p + G.moff[s];
+            gr.push_back(GItem<float>{inv, T32 + G.voff[s], X32 + G.voff[s], n, m[s], n, n, m[s], m[s], 0, 0,
+                                      cx(1.0f, 0.0f), 0});
+            gl.push_back(GItem<float>{inv, Th32 + G.voff[s], Xh32 + G.voff[s], n, m[s], n, n, m[s], m[s], 0, 0,
+                                      cx(1.0f, 0.0f), 0});
         }
-        group_solve_plan<float>(G.sN32, 'N', cnt, mp.data(), G.n.data(), pv.data(), xr.data(), m.data(),
-                                G.tile_solve);
-        group_solve_plan<float>(G.sC32, 'C', cnt, mp.data(), G.n.data(), pv.data(), xl.data(), m.data(),
-                                G.tile_solve);
+        group_gemm_plan<float>(G.sN32, false, gr, G.tile_solve);
+        group_gemm_plan<float>(G.sC32, true, gl, G.tile_solve);
         // FP64 residual products: R_s += A X_s, Rh_s += A^H Xh_s, and the B terms
         std::vector<GItem<double>> iN, iC, bN, bC;
         for (int s = 0; s < cnt; ++s) {
@@ -232,7 +256,7 @@ void dg_layout(Ctx& c, DenseGroup& G, const std::vector<int>& m) {
         group_gemm_plan<double>(G.resBN, false, bN, GTILE_64);
         group_gemm_plan<double>(G.resBC, true, bC, GTILE_64);
     }
-    for (int q = 0; q < 4; ++q) G.layout_key[q] = key[q];
+    for (int q = 0; q < 5; ++q) G.layout_key[q] = key[q];
     G.layout_vtot = tot;
 }
 
@@ -320,6 +344,8 @@ double dg_solve(Ctx& c, DenseGroup& G, const fh_opts& o, fh_report* rep) {
     hipStream_t st0 = c.stream;
     cf* X32 = (cf*)G.X32.p;
     cf* Xh32 = (cf*)G.Xh32.p;
+    cf* T32 = (cf*)G.T32.p;
+    cf* Th32 = (cf*)G.Th32.p;
     zd* R = (zd*)G.R.p;
     zd* Rh = (zd*)G.Rh.p;
     const long* off = (const long*)G.doff.p;
@@ -345,8 +371,8 @@ double dg_solve(Ctx& c, DenseGroup& G, const fh_opts& o, fh_report* rep) {
     FH_HIP(hipMemcpyAsync(hb.data(), nrm, sizeof(double) * 2 * C, hipMemcpyDeviceToHost, st0));
     // one refinement step: d = LU32^{-1} r in complex FP32, x += d, r = b - (z B - A) x in FP64
     auto body = [&](hipStream_t st, bool first) {
-        cast<float, double>(st, tot, first ? Bv : R, X32);
-        cast<float, double>(st, tot, first ? Bhv : Rh, Xh32);
+        cast<float, double>(st, tot, first ? Bv : R, T32);
+        cast<float, double>(st, tot, first ? Bhv : Rh, Th32);
         G.sN32.run(st);
         G.sC32.run(st);
         if (first) {

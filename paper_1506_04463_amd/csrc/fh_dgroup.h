@@ -1,8 +1,12 @@
 // Dense shifted systems (z_s B - A) of one or many problems solved together
 // with the grouped kernels (Section 2.4: one factorization per node, reused
 // for the right and the left solves): FP64 LU and direct solves, or a
-// complex-FP32 LU (GEMM updates on MFMA) with complex-FP32 solves inside FP64
-// iterative refinement of every right-hand side.
+// complex-FP32 LU (GEMM updates on MFMA) inside FP64 iterative refinement of
+// every right-hand side.  In the complex-FP32 case the inverse of each
+// factorization is formed once (LU X = I, grouped solves with n right-hand
+// sides), so that every refinement step's solve is one grouped MFMA GEMM
+// (d = M^{-1} r, d = M^{-H} r on the left) instead of a chain of dependent
+// triangular-block launches; the FP64 residuals keep the refinement exact.
 #pragma once
 #include <complex>
 
@@ -19,7 +23,7 @@ struct DenseGroup {
     std::vector<std::complex<double>> z;
     int tile_lu = GTILE_64, tile_solve = GTILE_32;
     // factors
-    DBuf M64, M32, ipiv, info, dz, dzc;
+    DBuf M64, M32, Inv32, ipiv, info, dz, dzc;
     std::vector<size_t> moff;       // element offset of each matrix
     std::vector<size_t> poff;       // pivot offset of each matrix
     // right-hand-side layout: block s is n[s] x m[s] (ld m[s]) at voff[s]
@@ -27,10 +31,10 @@ struct DenseGroup {
     std::vector<long> voff;
     long vtot = 0;
     int mmax = 0, maxlen = 0;
-    DBuf Bv, Bhv, Xv, Xhv, X32, Xh32, R, Rh, doff, dlen, dn, dm, nrm;
+    DBuf Bv, Bhv, Xv, Xhv, X32, Xh32, T32, Th32, R, Rh, doff, dlen, dn, dm, nrm;
     GroupPlan<double> sN64, sC64, resN, resC, resBN, resBC;
     GroupPlan<float> sN32, sC32;
-    const void* layout_key[4] = {nullptr, nullptr, nullptr, nullptr};
+    const void* layout_key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     long layout_vtot = -1;
     // captured launch sequences (valid for the current layout)
     hipGraphExec_t g_fp64 = nullptr, g_first = nullptr, g_next = nullptr;

@@ -76,5 +76,8 @@ void set_resid_init(hipStream_t st, int count, int maxlen, const long* off, cons
 void set_colnorm(hipStream_t st, int count, int mmax, const long* off, const int* n, const int* m, const zd* V,
                  double* out);
 void add_cast(hipStream_t st, long len, const cf* x, zd* y);
+// X_s = identity for the count blocks (n[s] x n[s] at element offset off[s],
+// device arrays); X must be zero on entry
+void set_identity(hipStream_t st, int count, int nmax, const long* off, const int* n, cf* X);
 
 }  // namespace fh

@@ -387,6 +387,19 @@ void set_colnorm(hipStream_t st, int count, int mmax, const long* off, const int
     k_set_colnorm<<<count, 256, 0, st>>>(off, n, m, mmax, V, out);
     FH_LAUNCH_CHECK();
 }
+// X_s = I (n_s x n_s at element offset off[s]); X must be zero on entry
+__global__ void k_set_identity(const long* __restrict__ off, const int* __restrict__ n, cf* __restrict__ X) {
+    const int s = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ns = n[s];
+    if (i < ns) X[off[s] + (long)i * ns + i] = cf{1.0f, 0.0f};
+}
+void set_identity(hipStream_t st, int count, int nmax, const long* off, const int* n, cf* X) {
+    if (count <= 0 || nmax <= 0) return;
+    k_set_identity<<<dim3(ceil_div(nmax, 256), count), 256, 0, st>>>(off, n, X);
+    FH_LAUNCH_CHECK();
+}
+
 void add_cast(hipStream_t st, long len, const cf* x, zd* y) {
     if (len <= 0) return;
     k_add_cast<<<ceil_div(len, 256), 256, 0, st>>>(len, x, y);
