@@ -115,7 +115,8 @@ typedef struct {
                              projection of each vector shares the next step's
                              pass: two passes over the basis per step instead
                              of three); 2 applies to complex-FP32 solves with
-                             restart <= 31, other solves use 0 */
+                             restart <= 31 and at most 128 columns per
+                             system, other solves use 0 */
 } fh_opts;
 
 typedef struct {

@@ -114,6 +114,144 @@ __global__ __launch_bounds__(256) void k_conv_fwd(int nz, int ny, int nx, int mt
 }
 
 // ---------------------------------------------------------------------------
+// 16-channel convolutions on MFMA (v_mfma_f32_16x16x16_bf16).  Per pixel the
+// [16 channels][16 columns] output block is a sum over taps of a 16 x 16 BF16
+// weight block times the neighbour's [16 channels][16 columns] input block.
+// Lane l of a wave supplies A[l % 16][4 (l / 16) + j] and B[4 (l / 16) + j][l % 16]
+// (j = 0..3) and receives D[4 (l / 16) + v][l % 16] (v = 0..3).  The weights are
+// BF16 already; each FP32 input enters as two BF16 terms, x = hi + lo to
+// 2^-17 relative, so that the result keeps FP32-level accuracy; the
+// accumulation is FP32.  A wave computes 16 columns of PPW consecutive pixels
+// with all taps' weight blocks held in registers.
+// ---------------------------------------------------------------------------
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+constexpr int MFMA_PPW = 8;    // pixels per wave
+
+__device__ __forceinline__ void split_bf16(float v, short& hi, short& lo) {
+    const uint16_t h = f32_to_bf16(v);
+    hi = (short)h;
+    lo = (short)f32_to_bf16(v - bf16_to_f32(h));
+}
+
+// y[p][co][col] = act(b[co] + sum_{tap, ci} w[co][ci][tap] x[p + d(tap)][ci][col]), 16 outputs, cin <= 16
+template <int TAPS>
+__global__ __launch_bounds__(256) void k_conv16_fwd_mfma(int nz, int ny, int nx, int mt, int cin,
+                                                         const float* __restrict__ x, const uint16_t* __restrict__ w,
+                                                         const uint16_t* __restrict__ b, int relu,
+                                                         float* __restrict__ y) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int col = blockIdx.y * 16 + i16;
+    const bool colok = col < mt;
+    const int npix = nz * ny * nx;
+    bf16x4_t wa[TAPS];
+#pragma unroll
+    for (int tap = 0; tap < TAPS; ++tap)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int ci = 4 * kq + j;
+            wa[tap][j] = ci < cin ? (short)w[(i16 * cin + ci) * TAPS + tap] : (short)0;
+        }
+    float bias[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) bias[v] = bf16_to_f32(b[4 * kq + v]);
+    const int p0 = (blockIdx.x * 4 + wave) * MFMA_PPW;
+    for (int pp = 0; pp < MFMA_PPW; ++pp) {
+        const int p = p0 + pp;
+        if (p >= npix) break;                       // uniform over the wave
+        const int px = p % nx, py = (p / nx) % ny, pz = p / (nx * ny);
+        f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int tap = 0; tap < TAPS; ++tap) {
+            int dz, dy, dx;
+            tap_off<TAPS>(tap, dz, dy, dx);
+            const int qz = pz + dz, qy = py + dy, qx = px + dx;
+            if (qz < 0 || qz >= nz || qy < 0 || qy >= ny || qx < 0 || qx >= nx) continue;   // uniform
+            const float* xq = x + (long)((qz * ny + qy) * nx + qx) * cin * mt;
+            bf16x4_t hi, lo;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int ci = 4 * kq + j;
+                const float v = (ci < cin && colok) ? xq[(long)ci * mt + col] : 0.0f;
+                short h, l;
+                split_bf16(v, h, l);
+                hi[j] = h;
+                lo[j] = l;
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[tap], hi, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[tap], lo, acc, 0, 0, 0);
+        }
+        if (colok) {
+            float* yp = y + (long)p * 16 * mt + col;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float o = acc[v] + bias[v];
+                yp[(long)(4 * kq + v) * mt] = relu ? fmaxf(o, 0.0f) : o;
+            }
+        }
+    }
+}
+
+// dx[p][ci][col] = mask(p, ci) * sum_{co, tap} w[co][ci][tap] dy[p - d(tap)][co][col], 16 inputs and
+// 16 outputs; mask: a_prev[p][ci][col] > 0 (ReLU of the layer input), or none
+template <int TAPS>
+__global__ __launch_bounds__(256) void k_conv16_bwd_data_mfma(int nz, int ny, int nx, int mt,
+                                                              const float* __restrict__ dy,
+                                                              const uint16_t* __restrict__ w,
+                                                              const float* __restrict__ mask, float* __restrict__ dx) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int col = blockIdx.y * 16 + i16;
+    const bool colok = col < mt;
+    const int npix = nz * ny * nx;
+    // A[i = ci][k = co] = w[co][ci][tap]
+    bf16x4_t wa[TAPS];
+#pragma unroll
+    for (int tap = 0; tap < TAPS; ++tap)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) wa[tap][j] = (short)w[((4 * kq + j) * 16 + i16) * TAPS + tap];
+    const int p0 = (blockIdx.x * 4 + wave) * MFMA_PPW;
+    for (int pp = 0; pp < MFMA_PPW; ++pp) {
+        const int p = p0 + pp;
+        if (p >= npix) break;                       // uniform over the wave
+        const int px = p % nx, py = (p / nx) % ny, pz = p / (nx * ny);
+        f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int tap = 0; tap < TAPS; ++tap) {
+            // output pixel q = p - d feeds input p through tap
+            int dz, ddy, ddx;
+            tap_off<TAPS>(tap, dz, ddy, ddx);
+            const int qz = pz - dz, qy = py - ddy, qx = px - ddx;
+            if (qz < 0 || qz >= nz || qy < 0 || qy >= ny || qx < 0 || qx >= nx) continue;   // uniform
+            const float* gq = dy + (long)((qz * ny + qy) * nx + qx) * 16 * mt;
+            bf16x4_t hi, lo;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float v = colok ? gq[(long)(4 * kq + j) * mt + col] : 0.0f;
+                short h, l;
+                split_bf16(v, h, l);
+                hi[j] = h;
+                lo[j] = l;
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[tap], hi, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[tap], lo, acc, 0, 0, 0);
+        }
+        if (colok) {
+            float* dxp = dx + (long)p * 16 * mt + col;
+            const float* mp = mask ? mask + (long)p * 16 * mt + col : nullptr;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const long o = (long)(4 * kq + v) * mt;
+                dxp[o] = (mp && !(mp[o] > 0.0f)) ? 0.0f : acc[v];
+            }
+        }
+    }
+}
+
+static dim3 mfma_grid(int npix, int mt) { return dim3(ceil_div(npix, 4 * MFMA_PPW), ceil_div(mt, 16)); }
+
+// ---------------------------------------------------------------------------
 // backward (data): dx[p][ci][col] = mask(p, ci) * sum_{o,tap} w[o][ci][tap] dy[p - d(tap)][o][col]
 // mask: a_prev[p][ci][col] > 0 (ReLU of the layer input), or none
 // ---------------------------------------------------------------------------
@@ -376,11 +514,12 @@ template void net_inv_colnorm<float>(hipStream_t, const NetDev&, int, int, const
 template <int TAPS>
 static void forward_t(hipStream_t st, const NetDev& N, int mt, const float* x, float* a1, float* a2, float* out) {
     const int npix = N.npix();
-    dim3 blk(64, 4), g = conv_grid(npix, mt);
-    k_conv_fwd<NET_HID, TAPS><<<g, blk, 0, st>>>(N.nz, N.ny, N.nx, mt, N.cin, x, N.wb + N.off_w1, N.wb + N.off_b1, 1, a1);
+    dim3 blk(64, 4), g = conv_grid(npix, mt), gm = mfma_grid(npix, mt);
+    static_assert(NET_HID == 16 && NET_MAX_CIN <= 16, "the MFMA convolutions are 16-channel blocks");
+    k_conv16_fwd_mfma<TAPS><<<gm, 256, 0, st>>>(N.nz, N.ny, N.nx, mt, N.cin, x, N.wb + N.off_w1, N.wb + N.off_b1, 1, a1);
     FH_LAUNCH_CHECK();
-    k_conv_fwd<NET_HID, TAPS><<<g, blk, 0, st>>>(N.nz, N.ny, N.nx, mt, NET_HID, a1, N.wb + N.off_w2, N.wb + N.off_b2, 1,
-                                                 a2);
+    k_conv16_fwd_mfma<TAPS><<<gm, 256, 0, st>>>(N.nz, N.ny, N.nx, mt, NET_HID, a1, N.wb + N.off_w2, N.wb + N.off_b2, 1,
+                                                a2);
     FH_LAUNCH_CHECK();
     k_conv_fwd<2, TAPS><<<g, blk, 0, st>>>(N.nz, N.ny, N.nx, mt, NET_HID, a2, N.wb + N.off_w3, N.wb + N.off_b3, 0, out);
     FH_LAUNCH_CHECK();
@@ -414,7 +553,8 @@ static void backward_t(hipStream_t st, const NetDev& N, int mt, const float* x, 
     k_wgrad_reduce<<<ceil_div(NET_HID * (NET_HID + 1) * T, 128), 128, 0, st>>>(nslice, NET_HID, NET_HID, T, P,
                                                                                  grad + N.off_w2, grad + N.off_b2);
     FH_LAUNCH_CHECK();
-    k_conv_bwd_data<NET_HID, TAPS><<<g, blk, 0, st>>>(N.nz, N.ny, N.nx, mt, NET_HID, g2, N.wb + N.off_w2, a1, g1);
+    k_conv16_bwd_data_mfma<TAPS><<<mfma_grid(N.npix(), mt), 256, 0, st>>>(N.nz, N.ny, N.nx, mt, g2, N.wb + N.off_w2, a1,
+                                                                           g1);
     FH_LAUNCH_CHECK();
     // layer 1 (weights only)
     k_conv_bwd_weight<TAPS><<<nslice, 320, 0, st>>>(N.nz, N.ny, N.nx, mt, N.cin, NET_HID, x, g1, P);

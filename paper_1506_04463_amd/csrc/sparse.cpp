@@ -459,8 +459,11 @@ static SolveStats gmres(Ctx& c, SparseState& S, const Batch& b, const Cx<T>* shi
     double* beta = (double*)S.beta.ensure(sizeof(double) * C);
     std::vector<double> hb(C), hbn(C);
     std::vector<int> hk(C);
-    // delayed reorthogonalization: complex FP32 bases up to 32 steps
-    const bool delayed = orth_passes == 3 && sizeof(T) == 4 && restart <= 31;
+    // delayed reorthogonalization: complex FP32 bases up to 32 steps and 128
+    // columns per system (the update pass stages 2 x 32 x m coefficients in
+    // LDS); otherwise classical Gram-Schmidt with reorthogonalization
+    const bool delayed = orth_passes == 3 && sizeof(T) == 4 && restart <= 31 && m <= 128;
+    if (orth_passes == 3 && !delayed) orth_passes = 2;
     DcgsState dstate;
     if (delayed) {
         dstate.KP = KP;
