@@ -117,6 +117,13 @@ typedef struct {
                              of three); 2 applies to complex-FP32 solves with
                              restart <= 31 and at most 128 columns per
                              system, other solves use 0 */
+    int batch_nodes;      /* sparse filter: quadrature nodes whose right and
+                             left systems are solved together (their Krylov
+                             bases live in device memory at once); 0 = as many
+                             as fit in half of the device memory.  The filter
+                             sums the chunks' contributions, so the result
+                             does not depend on it beyond rounding and the
+                             inner tolerances */
 } fh_opts;
 
 typedef struct {

@@ -65,6 +65,7 @@ void fh_default_opts(fh_opts* o) {
     o->fallback = FH_PC_ILU0;
     o->graph = 0;
     o->orth = 0;
+    o->batch_nodes = 0;
 }
 
 int fh_create(fh_handle* h, int device, void* stream) {

@@ -45,6 +45,7 @@ struct GOp {
     int mcols;          // solves: largest right-hand-side column count of the list
     double flops = 0.0; // GEMM: algorithmic flops (8 M N K per complex product)
     double bytes = 0.0; // GEMM: algorithmic bytes (A, B read, C read and written once)
+    int narrow = 0;     // FP64 GEMM: 128 x 32 tiles (every item has at most 32 columns)
 };
 
 // GEMM tile used by the grouped MFMA kernel (chosen by the autotuner)

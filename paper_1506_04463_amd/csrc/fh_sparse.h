@@ -136,7 +136,9 @@ template <typename T>
 void scale_cols_cast(hipStream_t st, int n, int m, int nsys, const zd* X, const double* sc, Cx<T>* Out);
 template <typename T>
 void axpy_cols(hipStream_t st, int n, int m, int nsys, const Cx<T>* Z, const double* sc, zd* X);
-void filter_accum(hipStream_t st, int ne, int n, int m, const zd* E, const zd* coef, const zd* Y, const zd* rho, zd* Q);
+// Q = (add ? Q : 0) + Y diag(rho) (when Y) + sum_j E_j diag(coef_j)
+void filter_accum(hipStream_t st, int ne, int n, int m, const zd* E, const zd* coef, const zd* Y, const zd* rho, zd* Q,
+                  bool add);
 void ritz_residual(hipStream_t st, const CsrDev& A, bool conj_t, int n, int m, const zd* lam, bool conj_lam,
                    const zd* X, zd* Out);
 void jacobi_diag(hipStream_t st, const SparseState& S, int ne, const zd* mvals, zd* jd);

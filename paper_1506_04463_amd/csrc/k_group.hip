@@ -183,33 +183,40 @@ __device__ __forceinline__ int find_item(const GItem<T>* __restrict__ items, int
     return lo;
 }
 
-// vector-FMA version (any T): 64 x 64 tile, 4 x 4 complex micro-tile per thread
-template <typename T, bool CA>
+// vector-FMA version (any T): (16 RA) x (16 RB) tile, RA x RB complex
+// micro-tile per thread (64 x 64 in general; 128 x 32 when every item of the
+// launch has at most 32 columns, so that no FMA works on padding)
+template <typename T, bool CA, int RA, int RB>
 __global__ __launch_bounds__(256) void k_ggemm_fma(const GItem<T>* __restrict__ items, int nitems) {
+    constexpr int TM = 16 * RA, TN = 16 * RB;
     const int t = blockIdx.x;
     const GItem<T> it = items[find_item(items, nitems, t)];
     const int tl = t - it.tile0;
-    const int m0 = (tl / it.tiles_n) * 64, n0 = (tl % it.tiles_n) * 64;
+    const int m0 = (tl / it.tiles_n) * TM, n0 = (tl % it.tiles_n) * TN;
     constexpr int KT = 16;
-    __shared__ Cx<T> As[KT][64 + 1];
-    __shared__ Cx<T> Bs[KT][64 + 1];
+    __shared__ Cx<T> As[KT][TM + 1];
+    __shared__ Cx<T> Bs[KT][TN + 1];
     const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-    Cx<T> acc[4][4];
+    Cx<T> acc[RA][RB];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < RA; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = czero<T>();
+        for (int b = 0; b < RB; ++b) acc[a][b] = czero<T>();
     for (int k0 = 0; k0 < it.K; k0 += KT) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < RA; ++q) {
             const int e = tid + 256 * q;
             int i, kk;
-            if (!CA) { i = e / KT; kk = e % KT; } else { kk = e / 64; i = e % 64; }
+            if (!CA) { i = e / KT; kk = e % KT; } else { kk = e / TM; i = e % TM; }
             const int gi = m0 + i, gk = k0 + kk;
             Cx<T> v = czero<T>();
             if (gi < it.M && gk < it.K) v = CA ? conj(it.A[(long)gk * it.lda + gi]) : it.A[(long)gi * it.lda + gk];
             As[kk][i] = v;
-            const int kb = e / 64, j = e % 64;
+        }
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int e = tid + 256 * q;
+            const int kb = e / TN, j = e % TN;
             Cx<T> u = czero<T>();
             if (n0 + j < it.N && k0 + kb < it.K) u = it.B[(long)(k0 + kb) * it.ldb + n0 + j];
             Bs[kb][j] = u;
@@ -217,24 +224,24 @@ __global__ __launch_bounds__(256) void k_ggemm_fma(const GItem<T>* __restrict__ 
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < KT; ++kk) {
-            Cx<T> av[4], bv[4];
+            Cx<T> av[RA], bv[RB];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = As[kk][ty + 16 * a];
+            for (int a = 0; a < RA; ++a) av[a] = As[kk][ty + 16 * a];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][tx + 16 * b];
+            for (int b = 0; b < RB; ++b) bv[b] = Bs[kk][tx + 16 * b];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < RA; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) cfma(acc[a][b], av[a], bv[b]);
+                for (int b = 0; b < RB; ++b) cfma(acc[a][b], av[a], bv[b]);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < RA; ++a) {
         const int gi = m0 + ty + 16 * a;
         if (gi >= it.M) continue;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < RB; ++b) {
             const int gj = n0 + tx + 16 * b;
             if (gj >= it.N) continue;
             Cx<T>& c = it.C[(long)gi * it.ldc + gj];
@@ -417,8 +424,14 @@ static void launch_gemm(hipStream_t st, const GOp& op, const void* list, int til
 template <>
 void launch_gemm<double>(hipStream_t st, const GOp& op, const void* list, int) {
     const GItem<double>* it = (const GItem<double>*)list;
-    if (op.kind == GOP_GEMM_N) k_ggemm_fma<double, false><<<op.tiles, 256, 0, st>>>(it, op.count);
-    else k_ggemm_fma<double, true><<<op.tiles, 256, 0, st>>>(it, op.count);
+    const bool c = op.kind == GOP_GEMM_C;
+    if (op.narrow) {
+        if (c) k_ggemm_fma<double, true, 8, 2><<<op.tiles, 256, 0, st>>>(it, op.count);
+        else k_ggemm_fma<double, false, 8, 2><<<op.tiles, 256, 0, st>>>(it, op.count);
+    } else {
+        if (c) k_ggemm_fma<double, true, 4, 4><<<op.tiles, 256, 0, st>>>(it, op.count);
+        else k_ggemm_fma<double, false, 4, 4><<<op.tiles, 256, 0, st>>>(it, op.count);
+    }
     FH_LAUNCH_CHECK();
 }
 
@@ -497,18 +510,24 @@ void finish(GroupPlan<T>& plan, Builder& b) {
 
 template <typename T>
 void add_gemm(GroupPlan<T>& plan, Builder& bld, bool conjA, std::vector<GItem<T>>& items, int tile) {
-    const int ts = (std::is_same<T, float>::value) ? tile_of(tile) : 64;
+    // FP64 (vector FMA): 128 x 32 tiles when no item has more than 32 columns
+    bool narrow = !std::is_same<T, float>::value;
+    for (const GItem<T>& it : items)
+        if (it.M > 0 && it.N > 32) narrow = false;
+    const int tm = (std::is_same<T, float>::value) ? tile_of(tile) : (narrow ? 128 : 64);
+    const int tn = (std::is_same<T, float>::value) ? tile_of(tile) : (narrow ? 32 : 64);
     std::vector<GItem<T>> keep;
     int tiles = 0;
     for (GItem<T> it : items) {
         if (it.M <= 0 || it.N <= 0) continue;
-        it.tiles_n = (int)ceil_div(it.N, ts);
+        it.tiles_n = (int)ceil_div(it.N, tn);
         it.tile0 = tiles;
-        tiles += (int)ceil_div(it.M, ts) * it.tiles_n;
+        tiles += (int)ceil_div(it.M, tm) * it.tiles_n;
         keep.push_back(it);
     }
     if (keep.empty()) return;
     GOp op{};
+    op.narrow = narrow ? 1 : 0;
     for (const auto& it : keep) {
         op.flops += 8.0 * it.M * it.N * it.K;
         op.bytes += (double)sizeof(Cx<T>) * ((double)it.M * it.K + (double)it.K * it.N + 2.0 * it.M * it.N);

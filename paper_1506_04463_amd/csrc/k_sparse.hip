@@ -1504,17 +1504,18 @@ template void axpy_cols<float>(hipStream_t, int, int, int, const cf*, const doub
 // coef: [ne][m] complex; E: [ne][n][m] (system-major slice of one side)
 // ---------------------------------------------------------------------------
 __global__ void k_filter_accum(int ne, int n, int m, const zd* __restrict__ E, const zd* __restrict__ coef,
-                               const zd* __restrict__ Y, const zd* __restrict__ rho, zd* __restrict__ Q) {
+                               const zd* __restrict__ Y, const zd* __restrict__ rho, int add, zd* __restrict__ Q) {
     long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long)n * m) return;
     const int c = e % m;
-    zd acc = czero<double>();
-    if (Y) acc = rho[c] * Y[e];
+    zd acc = add ? Q[e] : czero<double>();
+    if (Y) cfma(acc, rho[c], Y[e]);
     for (int j = 0; j < ne; ++j) cfma(acc, coef[(long)j * m + c], E[(long)j * n * m + e]);
     Q[e] = acc;
 }
-void filter_accum(hipStream_t st, int ne, int n, int m, const zd* E, const zd* coef, const zd* Y, const zd* rho, zd* Q) {
-    k_filter_accum<<<ceil_div((size_t)n * m, 256), 256, 0, st>>>(ne, n, m, E, coef, Y, rho, Q);
+void filter_accum(hipStream_t st, int ne, int n, int m, const zd* E, const zd* coef, const zd* Y, const zd* rho, zd* Q,
+                  bool add) {
+    k_filter_accum<<<ceil_div((size_t)n * m, 256), 256, 0, st>>>(ne, n, m, E, coef, Y, rho, add ? 1 : 0, Q);
     FH_LAUNCH_CHECK();
 }
 

@@ -672,6 +672,25 @@ void sparse_shifted_solve(Ctx& c, Prob& p, int nsys, const cplx* z, const int* s
 // ---------------------------------------------------------------------------
 // contour filter on a CSR problem (B = I)
 // ---------------------------------------------------------------------------
+// Nodes per batch of the sparse filter: opts.batch_nodes, or as many as fit in
+// half of the device memory with the workspace of one system (right or left)
+// estimated as its Krylov basis, flexible directions, work copies and the
+// filter's right-hand side and solution blocks.
+static int filter_chunk(const SparseState& S, int ne, int m, const fh_opts& o) {
+    if (o.batch_nodes > 0) return std::min(ne, o.batch_nodes);
+    const double elems = (double)S.n * m;
+    const int restart = std::max(1, o.restart);
+    const bool flex = o.precond == FH_PC_LEARNED;
+    const double b = o.precision == FH_PREC_MIXED ? 8.0 : 16.0;       // bytes of a Krylov entry
+    double per_sys = elems * (b * (restart + 2 + (flex ? restart : 0)) + 2 * 16.0);
+    if (o.precision == FH_PREC_MIXED) per_sys += elems * (16.0 + 2 * 8.0);   // FP64 residual, FP32 rhs / solution
+    size_t freeb = 0, total = 0;
+    FH_HIP(hipMemGetInfo(&freeb, &total));
+    const double budget = 0.5 * (double)total;
+    const int g = (int)std::floor(budget / (2.0 * per_sys));
+    return std::max(1, std::min(ne, g));
+}
+
 void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m, const zd* Y, const zd* Yh, zd* Q,
                    zd* Qh, const fh_opts& o, fh_report* rep, const cplx* lam) {
     FH_REQUIRE(m >= 1 && m <= 256, -6, "sparse filter: m0 must be in [1, 256]");
@@ -680,10 +699,12 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
     const int n = S.n;
     const long blk = (long)n * m;
     if (needs_factors(o)) ensure_factors(c, S, ne, z, o.precision == FH_PREC_MIXED, o, rep);
-    zd* Bb = (zd*)S.bufB.ensure(sizeof(zd) * blk * 2 * ne);
-    zd* Xb = (zd*)S.bufX.ensure(sizeof(zd) * blk * 2 * ne);
+    const int g = filter_chunk(S, ne, m, o);
+    zd* Bb = (zd*)S.bufB.ensure(sizeof(zd) * blk * 2 * g);
+    zd* Xb = (zd*)S.bufX.ensure(sizeof(zd) * blk * 2 * g);
     zd* T = (zd*)S.bufT.ensure(sizeof(zd) * blk * 2);
     zd* lamd = nullptr;
+    // coef[side][j][i]: weight of column i of E_j (right: w_j or w_j / (z_j - lam_i); left: conjugates)
     std::vector<cplx> coef(2 * (size_t)ne * m), rho(2 * (size_t)m);
     if (lam) {
         zd* ld = (zd*)S.rho.ensure(sizeof(zd) * 3 * m);
@@ -702,18 +723,13 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
             rho[i] = r;
             rho[m + i] = std::conj(r);
         }
-        replicate<double>(st, blk, T, Bb, ne);
-        replicate<double>(st, blk, T + blk, Bb + ne * blk, ne);
     } else {
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < ne; ++j) {
                 coef[(size_t)j * m + i] = w[j];
                 coef[(size_t)ne * m + (size_t)j * m + i] = std::conj(w[j]);
             }
-        replicate<double>(st, blk, Y, Bb, ne);
-        replicate<double>(st, blk, Yh, Bb + ne * blk, ne);
     }
-    SolveStats s = solve_all(c, S, ne, z, m, Bb, Xb, o);
     zd* cd = (zd*)S.coef.ensure(sizeof(zd) * coef.size());
     FH_HIP(hipMemcpyAsync(cd, coef.data(), sizeof(zd) * coef.size(), hipMemcpyHostToDevice, st));
     zd* rd = nullptr;
@@ -721,8 +737,28 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
         rd = (zd*)S.rho.p;
         FH_HIP(hipMemcpyAsync(rd, rho.data(), sizeof(zd) * 2 * m, hipMemcpyHostToDevice, st));
     }
-    filter_accum(st, ne, n, m, Xb, cd, lam ? Y : nullptr, rd, Q);
-    filter_accum(st, ne, n, m, Xb + ne * blk, cd + (size_t)ne * m, lam ? Yh : nullptr, rd ? rd + m : nullptr, Qh);
+    const zd* Rr = lam ? T : Y;            // right-hand sides: residuals (or Y), replicated per node
+    const zd* Rl = lam ? T + blk : Yh;
+    SolveStats s;
+    // nodes [j0, j1) at a time: their right and left systems in one batch
+    for (int j0 = 0; j0 < ne; j0 += g) {
+        const int j1 = std::min(ne, j0 + g), gc = j1 - j0;
+        replicate<double>(st, blk, Rr, Bb, gc);
+        replicate<double>(st, blk, Rl, Bb + gc * blk, gc);
+        std::vector<int> node_of(2 * gc);
+        std::vector<cplx> zsys(2 * gc);
+        for (int q = 0; q < 2 * gc; ++q) { node_of[q] = j0 + q % gc; zsys[q] = z[j0 + q % gc]; }
+        const SolveStats sc = solve_batch(c, S, 2 * gc, gc, node_of.data(), zsys.data(), m, Bb, Xb, o);
+        s.steps += sc.steps;
+        s.cycles += sc.cycles;
+        s.relres = std::max(s.relres, sc.relres);
+        s.fallback |= sc.fallback;
+        const bool first = j0 == 0;
+        filter_accum(st, gc, n, m, Xb, cd + (size_t)j0 * m, (lam && first) ? Y : nullptr, first ? rd : nullptr, Q,
+                     !first);
+        filter_accum(st, gc, n, m, Xb + gc * blk, cd + (size_t)(ne + j0) * m, (lam && first) ? Yh : nullptr,
+                     (first && rd) ? rd + m : nullptr, Qh, !first);
+    }
     FH_HIP(hipStreamSynchronize(st));
     if (rep) {
         rep->n_fallback += s.fallback ? 2 * ne : 0;

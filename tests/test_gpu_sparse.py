@@ -139,15 +139,18 @@ def _small_convdiff(N=20, m_in=8, m0=16):
     return W.convdiff2d(N=N, m_in=m_in, m0=m0)
 
 
-@pytest.mark.parametrize("precision,orth", [(0, 0), (1, 0), (1, 2)])
-def test_filter_sparse_parity(handle, precision, orth):
+@pytest.mark.parametrize("precision,orth,batch_nodes", [(0, 0, 0), (1, 0, 0), (1, 2, 0), (0, 0, 3), (1, 2, 5)])
+def test_filter_sparse_parity(handle, precision, orth, batch_nodes):
+    """batch_nodes = 3 / 5: the 16 nodes are solved in chunks (16 = 5 x 3 + 1,
+    3 x 5 + 1) whose contributions are summed."""
     p = _small_convdiff()
     A = p.A
     z, w = ct.ellipse_nodes(p.contour.center, p.contour.a, p.contour.ratio, 0.0, 16)
     Qo, Qho = F.contour_filter(L.csr_matrix(A), None, z, w, p.Y0, p.Yh0)
     prob = fh.Problem(handle, _csr(A))
     opts = fh.default_opts(p.m0, solver=1, precond=2, inner_tol=1e-12, restart=30, max_restarts=400,
-                           precision=precision, mixed_inner_tol=1e-5, max_refine=30, orth=orth)
+                           precision=precision, mixed_inner_tol=1e-5, max_refine=30, orth=orth,
+                           batch_nodes=batch_nodes)
     Q, Qh, rep = fh.contour_filter(prob, z, w, _cuda(p.Y0), _cuda(p.Yh0), opts)
     Q, Qh = Q.cpu().numpy(), Qh.cpu().numpy()
     # restarted GMRES reaches ~1e-11 here; the parity bound scales with what it reached
@@ -159,8 +162,8 @@ def test_filter_sparse_parity(handle, precision, orth):
     assert np.linalg.norm(Qh - Qho) / np.linalg.norm(Qho) < tol
 
 
-@pytest.mark.parametrize("precision,precond,orth", [(0, 2, 0), (1, 2, 0), (1, 2, 2)])
-def test_feast_sparse_convdiff_small(handle, precision, precond, orth):
+@pytest.mark.parametrize("precision,precond,orth,batch_nodes", [(0, 2, 0, 0), (1, 2, 0, 0), (1, 2, 2, 0), (1, 2, 2, 6)])
+def test_feast_sparse_convdiff_small(handle, precision, precond, orth, batch_nodes):
     p = _small_convdiff(N=24, m_in=10, m0=20)
     cont = F.Contour(p.contour.center, p.contour.a, p.contour.ratio, 0.0, 16)
     ref = F.feast(L.csr_matrix(p.A), None, cont, p.Y0, p.Yh0, eps=1e-12, max_iter=30)
@@ -169,7 +172,7 @@ def test_feast_sparse_convdiff_small(handle, precision, precond, orth):
     cycles = 2 if precond == 2 else 8
     opts = fh.default_opts(p.m0, solver=1, precond=precond, inner_tol=1e-3, restart=30, max_restarts=cycles,
                            precision=precision, mixed_inner_tol=1e-3, max_refine=3, eps=1e-12, max_iter=60,
-                           orth=orth)
+                           orth=orth, batch_nodes=batch_nodes)
     out = fh.feast(prob, p.contour.center, p.contour.a, p.contour.ratio, 0.0, 16, _cuda(p.Y0), _cuda(p.Yh0), opts)
     assert out["info"] == 0, out["report"]
     assert len(out["lam"]) == len(ref.lam) == 10
