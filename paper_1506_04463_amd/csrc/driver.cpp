@@ -272,33 +272,7 @@ struct FeastRun {
     }
 
     // step 2.a: B_Q = Qh^H B Q
-    void phase_bq() {
-        ++it;
-        const zd* BQin = Q;
-        if (p.hasB) { apply_B(c, p, 0, mcur, Q, T1); BQin = T1; }
-        gemm_hn_tall(c.stream, n, mcur, mcur, Qh, mcur, BQin, mcur, BQ, mcur, c.partial);
-    }
-
-    // after steps 3.a-3.c (eig_biortho): spurious test (2.b), resize count
-    void read_bq() {
-        to_host(c, hbq.data(), BQ, (size_t)mcur * mcur);
-        m_s = 0;
-        if (it >= 2) {
-            for (int i = 0; i < mcur; ++i) {
-                const cplx r2 = rho_prev[i] * rho_prev[i];
-                const double rel = std::abs(r2 - hbq[(size_t)i * mcur + i]) / std::abs(r2);
-                const bool flag = !(rel < 0.1);
-                if (flag && inside_prev[i]) ++m_s;
-            }
-        }
-        int hi[2];
-        to_host(c, hi, ints, 2);
-        if (hi[1] != 0) throw Error(FH_EIG_FAILED, "eigendecomposition of B_Q failed (code " + std::to_string(hi[1]) + ")");
-        mt = hi[0];
-        FH_REQUIRE(mt >= 1 && mt <= mcur, FH_EIG_FAILED, "resize produced an empty subspace");
-    }
-
-    // Products of steps 3-5.  The batched driver sets gN / gC: dense products
+    // Products of steps 2-5.  The batched driver sets gN / gC: dense products
     // are then appended to these lists (op(A) = A, resp. A^H) and launched by
     // it as one grouped GEMM over all runs; otherwise they launch here.
     std::vector<GItem<double>>* gN = nullptr;
@@ -323,6 +297,36 @@ struct FeastRun {
         if (!p.dense) { apply_B(c, p, side, m, X, Out); return Out; }
         prod(side ? 'C' : 'N', n, m, n, (const zd*)p.B.val, p.B.ld, X, m, Out, m);
         return Out;
+    }
+
+    const zd* BQin = nullptr;
+    void phase_bq_a() {   // B Q
+        ++it;
+        BQin = prod_B(0, mcur, Q, T1);
+    }
+    void phase_bq_b() { gemm_hn_tall(c.stream, n, mcur, mcur, Qh, mcur, BQin, mcur, BQ, mcur, c.partial); }
+    void phase_bq() {
+        phase_bq_a();
+        phase_bq_b();
+    }
+
+    // after steps 3.a-3.c (eig_biortho): spurious test (2.b), resize count
+    void read_bq() {
+        to_host(c, hbq.data(), BQ, (size_t)mcur * mcur);
+        m_s = 0;
+        if (it >= 2) {
+            for (int i = 0; i < mcur; ++i) {
+                const cplx r2 = rho_prev[i] * rho_prev[i];
+                const double rel = std::abs(r2 - hbq[(size_t)i * mcur + i]) / std::abs(r2);
+                const bool flag = !(rel < 0.1);
+                if (flag && inside_prev[i]) ++m_s;
+            }
+        }
+        int hi[2];
+        to_host(c, hi, ints, 2);
+        if (hi[1] != 0) throw Error(FH_EIG_FAILED, "eigendecomposition of B_Q failed (code " + std::to_string(hi[1]) + ")");
+        mt = hi[0];
+        FH_REQUIRE(mt >= 1 && mt <= mcur, FH_EIG_FAILED, "resize produced an empty subspace");
     }
 
     // step 3.d: U = Q S, Uh = Qh Sh
@@ -526,8 +530,15 @@ int feast_batched(Ctx& c, int count, Prob* const* probs, const fh_contour* cts, 
     }
     DenseGroup G;
     DBuf jobbuf;
+    // the dense products of steps 1-5 of all runs as grouped GEMMs, one launch
+    // per dependent stage (each plan's work list is used once per iteration)
     std::vector<GItem<double>> gn, gc;
-    GroupPlan<double> gp[8];
+    GroupPlan<double> gp[12];
+    auto grouped = [&](GroupPlan<double>& pn, GroupPlan<double>& pc) {
+        if (!gn.empty()) { group_gemm_plan(pn, false, gn, GTILE_64); pn.run(st); gn.clear(); }
+        if (!gc.empty()) { group_gemm_plan(pc, true, gc, GTILE_64); pc.run(st); gc.clear(); }
+    };
+    std::vector<const zd*> bys(count), bhys(count);
     fh_report frep{};
     dg_build(c, G, plist, zs, o.precision == FH_PREC_MIXED, &frep);
     std::vector<int> first(count);   // first system of each instance
@@ -557,12 +568,20 @@ int feast_batched(Ctx& c, int count, Prob* const* probs, const fh_contour* cts, 
             FeastRun& r = *runs[i];
             if (r.done) continue;
             r.t0 = t0;
+            r.gN = &gn;
+            r.gC = &gc;
+            bys[i] = r.prod_B(0, r.mcur, r.Ycur, r.T1);
+            bhys[i] = r.prod_B(1, r.mcur, r.Yhcur, r.T2);
+            r.gN = r.gC = nullptr;
+        }
+        grouped(gp[8], gp[9]);
+        for (int i = 0; i < count; ++i) {
+            FeastRun& r = *runs[i];
+            if (r.done) continue;
             const long blk = (long)r.n * r.mcur;
             const long off = G.voff[first[i]];
-            apply_B(c, r.p, 0, r.mcur, r.Ycur, r.T1);
-            replicate<double>(st, blk, r.T1, (zd*)G.Bv.p + off, r.ne);
-            apply_B(c, r.p, 1, r.mcur, r.Yhcur, r.T1);
-            replicate<double>(st, blk, r.T1, (zd*)G.Bhv.p + off, r.ne);
+            replicate<double>(st, blk, bys[i], (zd*)G.Bv.p + off, r.ne);
+            replicate<double>(st, blk, bhys[i], (zd*)G.Bhv.p + off, r.ne);
         }
         fh_report srep{};
         dg_solve(c, G, o, &srep);
@@ -592,18 +611,14 @@ int feast_batched(Ctx& c, int count, Prob* const* probs, const fh_contour* cts, 
         // eigensolver for all of them, host decisions between
         std::vector<EigJob> jobs(act.size());
         EigJob* dj = (EigJob*)jobbuf.ensure(sizeof(EigJob) * std::max<size_t>(1, act.size()));
-        for (FeastRun* r : act) r->phase_bq();
+        for (FeastRun* r : act) { r->gN = &gn; r->gC = &gc; }
+        for (FeastRun* r : act) r->phase_bq_a();
+        grouped(gp[10], gp[11]);
+        for (FeastRun* r : act) r->phase_bq_b();
         for (size_t k = 0; k < act.size(); ++k) jobs[k] = act[k]->job_biortho();
         to_dev(c, dj, jobs.data(), jobs.size());
         eig_biortho_batched(st, (int)act.size(), dj);
         for (FeastRun* r : act) r->read_bq();
-        // the products of steps 3-5 of all runs as grouped GEMMs, one launch
-        // per dependent stage (each plan's work list is used once per iteration)
-        auto grouped = [&](GroupPlan<double>& pn, GroupPlan<double>& pc) {
-            if (!gn.empty()) { group_gemm_plan(pn, false, gn, GTILE_64); pn.run(st); gn.clear(); }
-            if (!gc.empty()) { group_gemm_plan(pc, true, gc, GTILE_64); pc.run(st); gc.clear(); }
-        };
-        for (FeastRun* r : act) { r->gN = &gn; r->gC = &gc; }
         for (FeastRun* r : act) r->launch_rr_a();
         grouped(gp[0], gp[1]);
         for (FeastRun* r : act) r->launch_rr_b();
