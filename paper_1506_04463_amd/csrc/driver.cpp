@@ -617,7 +617,9 @@ int feast_batched(Ctx& c, int count, Prob* const* probs, const fh_contour* cts, 
         for (FeastRun* r : act) r->phase_bq_b();
         for (size_t k = 0; k < act.size(); ++k) jobs[k] = act[k]->job_biortho();
         to_dev(c, dj, jobs.data(), jobs.size());
-        eig_biortho_batched(st, (int)act.size(), dj);
+        int mmax = 1;
+        for (const EigJob& jj : jobs) mmax = std::max(mmax, jj.m);
+        eig_biortho_batched(st, (int)act.size(), dj, mmax);
         for (FeastRun* r : act) r->read_bq();
         for (FeastRun* r : act) r->launch_rr_a();
         grouped(gp[0], gp[1]);
@@ -626,7 +628,9 @@ int feast_batched(Ctx& c, int count, Prob* const* probs, const fh_contour* cts, 
         for (FeastRun* r : act) r->launch_rr_c();
         for (size_t k = 0; k < act.size(); ++k) jobs[k] = act[k]->job_reduced();
         to_dev(c, dj, jobs.data(), jobs.size());
-        eig_reduced_batched(st, (int)act.size(), dj);
+        mmax = 1;
+        for (const EigJob& jj : jobs) mmax = std::max(mmax, jj.m);
+        eig_reduced_batched(st, (int)act.size(), dj, mmax);
         for (FeastRun* r : act) r->read_lam();
         for (FeastRun* r : act) r->launch_ritz_a();
         grouped(gp[4], gp[5]);

@@ -67,8 +67,8 @@ struct EigJob {
     zd* work;      // eig_work_size(m) bytes
 };
 size_t eig_work_size(int m);
-void eig_biortho_batched(hipStream_t st, int count, const EigJob* jobs_dev);
-void eig_reduced_batched(hipStream_t st, int count, const EigJob* jobs_dev);
+void eig_biortho_batched(hipStream_t st, int count, const EigJob* jobs_dev, int mmax);
+void eig_reduced_batched(hipStream_t st, int count, const EigJob* jobs_dev, int mmax);
 // Steps 3.a-3.c (see fh_biortho_factors); work: device scratch
 void eig_biortho(hipStream_t st, int m, const zd* BQ, double eta, zd* gamma, zd* S, zd* Sh, int* m0t,
                  int* info, DBuf& work);

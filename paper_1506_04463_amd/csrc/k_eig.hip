@@ -90,18 +90,24 @@ __device__ int schur_qr(int m, zd* H, zd* Z) {
     const int tid = threadIdx.x;
     const double ulp = DBL_EPSILON, smlnum = DBL_MIN * (double(m) / DBL_EPSILON);
     int ihi = m - 1, its = 0, total = 0;
+    __shared__ int lsh;
     while (ihi >= 1) {
-        int l = 0;
-        for (int kk = ihi; kk >= 1; --kk) {
+        // largest kk <= ihi with a negligible subdiagonal entry (0 if none):
+        // every thread tests its own entries and one LDS maximum combines them
+        // (a serial scan down from ihi costs one memory latency per entry)
+        if (tid == 0) lsh = 0;
+        __syncthreads();
+        for (int kk = 1 + tid; kk <= ihi; kk += ENT) {
             const double sub = cabs1(H[(long)kk * m + kk - 1]);
             double tst = cabs1(H[(long)(kk - 1) * m + kk - 1]) + cabs1(H[(long)kk * m + kk]);
             if (tst == 0.0) {
                 if (kk - 2 >= 0) tst += fabs(H[(long)(kk - 1) * m + kk - 2].re);
                 if (kk + 1 <= ihi) tst += fabs(H[(long)(kk + 1) * m + kk].re);
             }
-            if (sub <= fmax(ulp * tst, smlnum)) { l = kk; break; }
+            if (sub <= fmax(ulp * tst, smlnum)) atomicMax(&lsh, kk);
         }
         __syncthreads();
+        const int l = lsh;
         if (l > 0 && tid == 0) H[(long)l * m + l - 1] = czero<double>();
         __syncthreads();
         if (l == ihi) { --ihi; its = 0; continue; }
@@ -238,12 +244,31 @@ __device__ int gauss_jordan(int m, int w, zd* Aug, zd* f, double* red, int* redi
 // Work layout (complex): H, Z, X, V, Vi (m*m each), Aug (m*3m), v, f (m each)
 static size_t eig_work_elems(int m) { return (size_t)m * m * 8 + 2 * (size_t)m + 64; }
 
+// H and Z of the reduction and the QR iteration live in LDS when m <= 64
+// (dynamic shared memory of 2 m^2 entries): every one of the QR iteration's
+// dependent Givens steps then waits on LDS, not on global memory.
+constexpr int EIG_LDS_M = 64;
+
 __device__ void eig_core(int m, zd* H, zd* Z, zd* X, zd* V, zd* v, double* red, int* info) {
     const int tid = threadIdx.x;
-    for (int e = tid; e < m * m; e += ENT) Z[e] = (e / m == e % m) ? cx(1.0, 0.0) : czero<double>();
+    extern __shared__ unsigned char eig_dsm[];
+    const bool lds = m <= EIG_LDS_M;
+    zd* Hw = lds ? (zd*)eig_dsm : H;
+    zd* Zw = lds ? (zd*)eig_dsm + (size_t)m * m : Z;
+    for (int e = tid; e < m * m; e += ENT) {
+        Zw[e] = (e / m == e % m) ? cx(1.0, 0.0) : czero<double>();
+        if (lds) Hw[e] = H[e];
+    }
     __syncthreads();
-    hessenberg(m, H, Z, v, red);
-    int bad = schur_qr(m, H, Z);
+    hessenberg(m, Hw, Zw, v, red);
+    int bad = schur_qr(m, Hw, Zw);
+    if (lds) {
+        for (int e = tid; e < m * m; e += ENT) {
+            H[e] = Hw[e];
+            Z[e] = Zw[e];
+        }
+        __syncthreads();
+    }
     if (bad && tid == 0) *info = 1;
     schur_vectors(m, H, Z, X, V, red);
 }
@@ -381,27 +406,42 @@ __global__ __launch_bounds__(ENT) void k_eig_reduced_b(const EigJob* __restrict_
 
 size_t eig_work_size(int m) { return sizeof(zd) * eig_work_elems(m); }
 
+// dynamic LDS of the eigensolver kernels for problems up to size mmax
+static size_t eig_lds_bytes(int mmax) {
+    static bool attr = false;
+    if (!attr) {
+        const int b = (int)(2 * sizeof(zd) * EIG_LDS_M * EIG_LDS_M);   // 128 KiB of the 160 KiB per workgroup
+        FH_HIP(hipFuncSetAttribute((const void*)k_eig_biortho, hipFuncAttributeMaxDynamicSharedMemorySize, b));
+        FH_HIP(hipFuncSetAttribute((const void*)k_eig_reduced, hipFuncAttributeMaxDynamicSharedMemorySize, b));
+        FH_HIP(hipFuncSetAttribute((const void*)k_eig_biortho_b, hipFuncAttributeMaxDynamicSharedMemorySize, b));
+        FH_HIP(hipFuncSetAttribute((const void*)k_eig_reduced_b, hipFuncAttributeMaxDynamicSharedMemorySize, b));
+        attr = true;
+    }
+    const int mm = std::min(mmax, EIG_LDS_M);
+    return 2 * sizeof(zd) * (size_t)mm * mm;
+}
+
 void eig_biortho(hipStream_t st, int m, const zd* BQ, double eta, zd* gamma, zd* S, zd* Sh, int* m0t, int* info,
                  DBuf& work) {
     FH_REQUIRE(m >= 1 && m <= 1024, -2, "eig_biortho: m out of range");
     zd* w = (zd*)work.ensure(sizeof(zd) * eig_work_elems(m));
-    k_eig_biortho<<<1, ENT, 0, st>>>(m, BQ, eta, gamma, S, Sh, m0t, info, w);
+    k_eig_biortho<<<1, ENT, eig_lds_bytes(m), st>>>(m, BQ, eta, gamma, S, Sh, m0t, info, w);
     FH_LAUNCH_CHECK();
 }
 void eig_reduced(hipStream_t st, int m, const zd* AU, const zd* BU, zd* lam, zd* W, zd* Wh, int* info, DBuf& work) {
     FH_REQUIRE(m >= 1 && m <= 1024, -2, "eig_reduced: m out of range");
     zd* w = (zd*)work.ensure(sizeof(zd) * eig_work_elems(m));
-    k_eig_reduced<<<1, ENT, 0, st>>>(m, AU, BU, lam, W, Wh, info, w);
+    k_eig_reduced<<<1, ENT, eig_lds_bytes(m), st>>>(m, AU, BU, lam, W, Wh, info, w);
     FH_LAUNCH_CHECK();
 }
-void eig_biortho_batched(hipStream_t st, int count, const EigJob* jobs_dev) {
+void eig_biortho_batched(hipStream_t st, int count, const EigJob* jobs_dev, int mmax) {
     if (count <= 0) return;
-    k_eig_biortho_b<<<count, ENT, 0, st>>>(jobs_dev);
+    k_eig_biortho_b<<<count, ENT, eig_lds_bytes(mmax), st>>>(jobs_dev);
     FH_LAUNCH_CHECK();
 }
-void eig_reduced_batched(hipStream_t st, int count, const EigJob* jobs_dev) {
+void eig_reduced_batched(hipStream_t st, int count, const EigJob* jobs_dev, int mmax) {
     if (count <= 0) return;
-    k_eig_reduced_b<<<count, ENT, 0, st>>>(jobs_dev);
+    k_eig_reduced_b<<<count, ENT, eig_lds_bytes(mmax), st>>>(jobs_dev);
     FH_LAUNCH_CHECK();
 }
 
