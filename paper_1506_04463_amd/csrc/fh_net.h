@@ -37,9 +37,11 @@ template <typename T>
 void net_target(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* E, const float* scale, float* t);
 template <typename T>
 void net_inv_colnorm(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* V, float* sc);
-void net_forward(hipStream_t st, const NetDev& N, int mt, const float* x, float* a1, float* a2, float* out);
+// s1, s2: split (BF16 hi / lo) workspaces of 2 x npix x 16 x mt entries each
+void net_forward(hipStream_t st, const NetDev& N, int mt, const float* x, float* a1, float* a2, float* out,
+                 uint16_t* s1, uint16_t* s2);
 void net_backward(hipStream_t st, const NetDev& N, int mt, const float* x, const float* a1, const float* a2,
-                  const float* gout, float* g2, float* g1, float* grad, DBuf& part);
+                  const float* gout, float* g2, float* g1, float* grad, DBuf& part, uint16_t* s1);
 double net_loss(hipStream_t st, const NetDev& N, int mt, const float* out, const float* tgt, float* gout, DBuf& scratch);
 void net_adam(hipStream_t st, NetDev& N, const float* grad, float lr);
 void net_pack_diff(hipStream_t st, const NetDev& N, int m, int nsys, const float* o, const float* t, zd* D, zd* Tc);
@@ -51,6 +53,7 @@ struct NetState {
     NetDev d;
     DBuf w, wb, mom, vel, fields, grad;
     DBuf x, a1, a2, out, tgt, g1, g2, gout, scale, shifts, sides, part, lossbuf;
+    DBuf s1, s2;   // BF16 hi / lo splits of the MFMA layers' inputs
     DBuf opD, opT, opMD, opMT, opG, opsh, opn, opf;   // operator-weighted loss
 };
 

@@ -121,8 +121,11 @@ __global__ __launch_bounds__(256) void k_conv_fwd(int nz, int ny, int nx, int mt
 // (j = 0..3) and receives D[4 (l / 16) + v][l % 16] (v = 0..3).  The weights are
 // BF16 already; each FP32 input enters as two BF16 terms, x = hi + lo to
 // 2^-17 relative, so that the result keeps FP32-level accuracy; the
-// accumulation is FP32.  A wave computes 16 columns of PPW consecutive pixels
-// with all taps' weight blocks held in registers.
+// accumulation is FP32.  The inputs are split once, into "split" arrays of
+// layout [pixel][channel / 4][column][4] (hi and lo arrays of 16 channels), so
+// that a lane's B operand is one 8-byte load and no tap repeats the split.
+// A wave computes 16 columns of MFMA_PPW consecutive pixels with all taps'
+// weight blocks held in registers.
 // ---------------------------------------------------------------------------
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
@@ -134,122 +137,144 @@ __device__ __forceinline__ void split_bf16(float v, short& hi, short& lo) {
     lo = (short)f32_to_bf16(v - bf16_to_f32(h));
 }
 
-// y[p][co][col] = act(b[co] + sum_{tap, ci} w[co][ci][tap] x[p + d(tap)][ci][col]), 16 outputs, cin <= 16
-template <int TAPS>
-__global__ __launch_bounds__(256) void k_conv16_fwd_mfma(int nz, int ny, int nx, int mt, int cin,
-                                                         const float* __restrict__ x, const uint16_t* __restrict__ w,
-                                                         const uint16_t* __restrict__ b, int relu,
-                                                         float* __restrict__ y) {
+// split arrays of x[p][ci][col] (cin <= 16 channels, zero padded to 16):
+// hi/lo[((p * 4 + cq) * mt + col) * 4 + j] for ci = 4 cq + j
+__global__ void k_split16(long npix, int mt, int cin, const float* __restrict__ x, bf16x4_t* __restrict__ hi,
+                          bf16x4_t* __restrict__ lo) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;   // (p, cq, col)
+    if (e >= npix * 4 * mt) return;
+    const int col = (int)(e % mt);
+    const long pq = e / mt;
+    const int cq = (int)(pq % 4);
+    const long p = pq / 4;
+    bf16x4_t h, l;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int ci = 4 * cq + j;
+        const float v = ci < cin ? x[(p * cin + ci) * mt + col] : 0.0f;
+        short a, b;
+        split_bf16(v, a, b);
+        h[j] = a;
+        l[j] = b;
+    }
+    hi[e] = h;
+    lo[e] = l;
+}
+
+// One kernel for both directions.  Forward: y[p][co][col] = act(b[co] +
+// sum_{tap, ci} w[co][ci][tap] x[p + d(tap)][ci][col]), 16 outputs, cin <= 16,
+// and the split of y when yhi != null.  Backward (BWD): dx[p][ci][col] =
+// mask(p, ci) sum_{co, tap} w[co][ci][tap] dy[p - d(tap)][co][col] (16 and 16
+// channels; mask: a_prev > 0, or none).  A wave computes MFMA_PPW consecutive
+// pixels of one grid row (x fastest) for 16 columns; for each (dz, dy) plane
+// it loads the MFMA_PPW + 2 input blocks of the row window once and uses each
+// for up to three taps and three output pixels (a neighbour outside the grid
+// contributes a zero operand).
+template <int TAPS, bool BWD>
+__global__ __launch_bounds__(256) void k_conv16_mfma(int nz, int ny, int nx, int mt, int cin,
+                                                     const bf16x4_t* __restrict__ xhi, const bf16x4_t* __restrict__ xlo,
+                                                     const uint16_t* __restrict__ w, const uint16_t* __restrict__ b,
+                                                     int relu, const float* __restrict__ mask, float* __restrict__ y,
+                                                     bf16x4_t* __restrict__ yhi, bf16x4_t* __restrict__ ylo) {
+    constexpr int PP = MFMA_PPW, WIN = MFMA_PPW + 2;
+    constexpr int NPL = TAPS == 27 ? 9 : 3;          // (dz, dy) planes
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i16 = lane & 15, kq = lane >> 4;
     const int col = blockIdx.y * 16 + i16;
     const bool colok = col < mt;
-    const int npix = nz * ny * nx;
+    const int segs = (nx + PP - 1) / PP;
+    const long task = (long)blockIdx.x * 4 + wave;   // (z, y, segment)
+    if (task >= (long)nz * ny * segs) return;        // uniform over the wave; no barrier below
+    const int seg = (int)(task % segs);
+    const int py = (int)((task / segs) % ny), pz = (int)(task / ((long)segs * ny));
+    const int px0 = seg * PP;
     bf16x4_t wa[TAPS];
 #pragma unroll
     for (int tap = 0; tap < TAPS; ++tap)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int ci = 4 * kq + j;
-            wa[tap][j] = ci < cin ? (short)w[(i16 * cin + ci) * TAPS + tap] : (short)0;
-        }
-    float bias[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) bias[v] = bf16_to_f32(b[4 * kq + v]);
-    const int p0 = (blockIdx.x * 4 + wave) * MFMA_PPW;
-    for (int pp = 0; pp < MFMA_PPW; ++pp) {
-        const int p = p0 + pp;
-        if (p >= npix) break;                       // uniform over the wave
-        const int px = p % nx, py = (p / nx) % ny, pz = p / (nx * ny);
-        f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int tap = 0; tap < TAPS; ++tap) {
-            int dz, dy, dx;
-            tap_off<TAPS>(tap, dz, dy, dx);
-            const int qz = pz + dz, qy = py + dy, qx = px + dx;
-            if (qz < 0 || qz >= nz || qy < 0 || qy >= ny || qx < 0 || qx >= nx) continue;   // uniform
-            const float* xq = x + (long)((qz * ny + qy) * nx + qx) * cin * mt;
-            bf16x4_t hi, lo;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            if (!BWD) {
                 const int ci = 4 * kq + j;
-                const float v = (ci < cin && colok) ? xq[(long)ci * mt + col] : 0.0f;
-                short h, l;
-                split_bf16(v, h, l);
-                hi[j] = h;
-                lo[j] = l;
+                wa[tap][j] = ci < cin ? (short)w[(i16 * cin + ci) * TAPS + tap] : (short)0;
+            } else {
+                wa[tap][j] = (short)w[((4 * kq + j) * 16 + i16) * TAPS + tap];   // A[ci][co]
             }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[tap], hi, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[tap], lo, acc, 0, 0, 0);
         }
-        if (colok) {
-            float* yp = y + (long)p * 16 * mt + col;
+    const bf16x4_t zero4 = {0, 0, 0, 0};
+    f32x4_t acc[PP];
+#pragma unroll
+    for (int i = 0; i < PP; ++i) acc[i] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    const int sg = BWD ? -1 : 1;
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl) {
+        const int dz = TAPS == 27 ? pl / 3 - 1 : 0, dy = pl % 3 - 1;
+        const int qz = pz + sg * dz, qy = py + sg * dy;
+        const bool plane = qz >= 0 && qz < nz && qy >= 0 && qy < ny && colok;
+        const long rowbase = plane ? (long)(qz * ny + qy) * nx : 0;
+        bf16x4_t hi[WIN], lo[WIN];
+#pragma unroll
+        for (int u = 0; u < WIN; ++u) {
+            const int qx = px0 - 1 + u;
+            const bool in = plane && qx >= 0 && qx < nx;
+            const long e = ((in ? rowbase + qx : 0L) * 4 + kq) * mt + (colok ? col : 0);
+            const bf16x4_t hl = xhi[e], ll = xlo[e];
+            hi[u] = in ? hl : zero4;
+            lo[u] = in ? ll : zero4;
+        }
+#pragma unroll
+        for (int i = 0; i < PP; ++i)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int tap = (TAPS == 27 ? (dz + 1) * 9 : 0) + (dy + 1) * 3 + (dx + 1);
+                const int u = i + 1 + sg * dx;
+                acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[tap], hi[u], acc[i], 0, 0, 0);
+                acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[tap], lo[u], acc[i], 0, 0, 0);
+            }
+    }
+    if (!colok) return;
+    float bias[4];
+    if (!BWD) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bias[v] = bf16_to_f32(b[4 * kq + v]);
+    }
+#pragma unroll
+    for (int i = 0; i < PP; ++i) {
+        const int px = px0 + i;
+        if (px >= nx) break;
+        const long p = (long)(pz * ny + py) * nx + px;
+        float* yp = y + p * 16 * mt + col;
+        if (!BWD) {
+            bf16x4_t h, l;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const float o = acc[v] + bias[v];
-                yp[(long)(4 * kq + v) * mt] = relu ? fmaxf(o, 0.0f) : o;
+                float o = acc[i][v] + bias[v];
+                if (relu) o = fmaxf(o, 0.0f);
+                yp[(long)(4 * kq + v) * mt] = o;
+                short a, c;
+                split_bf16(o, a, c);
+                h[v] = a;
+                l[v] = c;
             }
-        }
-    }
-}
-
-// dx[p][ci][col] = mask(p, ci) * sum_{co, tap} w[co][ci][tap] dy[p - d(tap)][co][col], 16 inputs and
-// 16 outputs; mask: a_prev[p][ci][col] > 0 (ReLU of the layer input), or none
-template <int TAPS>
-__global__ __launch_bounds__(256) void k_conv16_bwd_data_mfma(int nz, int ny, int nx, int mt,
-                                                              const float* __restrict__ dy,
-                                                              const uint16_t* __restrict__ w,
-                                                              const float* __restrict__ mask, float* __restrict__ dx) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i16 = lane & 15, kq = lane >> 4;
-    const int col = blockIdx.y * 16 + i16;
-    const bool colok = col < mt;
-    const int npix = nz * ny * nx;
-    // A[i = ci][k = co] = w[co][ci][tap]
-    bf16x4_t wa[TAPS];
-#pragma unroll
-    for (int tap = 0; tap < TAPS; ++tap)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) wa[tap][j] = (short)w[((4 * kq + j) * 16 + i16) * TAPS + tap];
-    const int p0 = (blockIdx.x * 4 + wave) * MFMA_PPW;
-    for (int pp = 0; pp < MFMA_PPW; ++pp) {
-        const int p = p0 + pp;
-        if (p >= npix) break;                       // uniform over the wave
-        const int px = p % nx, py = (p / nx) % ny, pz = p / (nx * ny);
-        f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int tap = 0; tap < TAPS; ++tap) {
-            // output pixel q = p - d feeds input p through tap
-            int dz, ddy, ddx;
-            tap_off<TAPS>(tap, dz, ddy, ddx);
-            const int qz = pz - dz, qy = py - ddy, qx = px - ddx;
-            if (qz < 0 || qz >= nz || qy < 0 || qy >= ny || qx < 0 || qx >= nx) continue;   // uniform
-            const float* gq = dy + (long)((qz * ny + qy) * nx + qx) * 16 * mt;
-            bf16x4_t hi, lo;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float v = colok ? gq[(long)(4 * kq + j) * mt + col] : 0.0f;
-                short h, l;
-                split_bf16(v, h, l);
-                hi[j] = h;
-                lo[j] = l;
+            if (yhi) {
+                const long e = (p * 4 + kq) * mt + col;
+                yhi[e] = h;
+                ylo[e] = l;
             }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[tap], hi, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[tap], lo, acc, 0, 0, 0);
-        }
-        if (colok) {
-            float* dxp = dx + (long)p * 16 * mt + col;
-            const float* mp = mask ? mask + (long)p * 16 * mt + col : nullptr;
+        } else {
+            const float* mp = mask ? mask + p * 16 * mt + col : nullptr;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const long o = (long)(4 * kq + v) * mt;
-                dxp[o] = (mp && !(mp[o] > 0.0f)) ? 0.0f : acc[v];
+                yp[o] = (mp && !(mp[o] > 0.0f)) ? 0.0f : acc[i][v];
             }
         }
     }
 }
 
-static dim3 mfma_grid(int npix, int mt) { return dim3(ceil_div(npix, 4 * MFMA_PPW), ceil_div(mt, 16)); }
+static dim3 mfma_grid(const NetDev& N, int mt) {
+    const long tasks = (long)N.nz * N.ny * ceil_div(N.nx, MFMA_PPW);
+    return dim3((unsigned)ceil_div(tasks, 4), ceil_div(mt, 16));
+}
 
 // ---------------------------------------------------------------------------
 // backward (data): dx[p][ci][col] = mask(p, ci) * sum_{o,tap} w[o][ci][tap] dy[p - d(tap)][o][col]
@@ -512,31 +537,41 @@ template void net_inv_colnorm<double>(hipStream_t, const NetDev&, int, int, cons
 template void net_inv_colnorm<float>(hipStream_t, const NetDev&, int, int, const cf*, float*);
 
 template <int TAPS>
-static void forward_t(hipStream_t st, const NetDev& N, int mt, const float* x, float* a1, float* a2, float* out) {
+static void forward_t(hipStream_t st, const NetDev& N, int mt, const float* x, float* a1, float* a2, float* out,
+                      uint16_t* s1, uint16_t* s2) {
     const int npix = N.npix();
-    dim3 blk(64, 4), g = conv_grid(npix, mt), gm = mfma_grid(npix, mt);
+    dim3 blk(64, 4), g = conv_grid(npix, mt), gm = mfma_grid(N, mt);
     static_assert(NET_HID == 16 && NET_MAX_CIN <= 16, "the MFMA convolutions are 16-channel blocks");
-    k_conv16_fwd_mfma<TAPS><<<gm, 256, 0, st>>>(N.nz, N.ny, N.nx, mt, N.cin, x, N.wb + N.off_w1, N.wb + N.off_b1, 1, a1);
+    const long half = (long)npix * 16 * mt;      // bf16 entries of one split array
+    bf16x4_t* x_hi = (bf16x4_t*)s1;
+    bf16x4_t* x_lo = (bf16x4_t*)(s1 + half);
+    bf16x4_t* a_hi = (bf16x4_t*)s2;
+    bf16x4_t* a_lo = (bf16x4_t*)(s2 + half);
+    k_split16<<<ceil_div((size_t)npix * 4 * mt, 256), 256, 0, st>>>(npix, mt, N.cin, x, x_hi, x_lo);
     FH_LAUNCH_CHECK();
-    k_conv16_fwd_mfma<TAPS><<<gm, 256, 0, st>>>(N.nz, N.ny, N.nx, mt, NET_HID, a1, N.wb + N.off_w2, N.wb + N.off_b2, 1,
-                                                a2);
+    k_conv16_mfma<TAPS, false><<<gm, 256, 0, st>>>(N.nz, N.ny, N.nx, mt, N.cin, x_hi, x_lo, N.wb + N.off_w1,
+                                                   N.wb + N.off_b1, 1, nullptr, a1, a_hi, a_lo);
+    FH_LAUNCH_CHECK();
+    k_conv16_mfma<TAPS, false><<<gm, 256, 0, st>>>(N.nz, N.ny, N.nx, mt, NET_HID, a_hi, a_lo, N.wb + N.off_w2,
+                                                   N.wb + N.off_b2, 1, nullptr, a2, nullptr, nullptr);
     FH_LAUNCH_CHECK();
     k_conv_fwd<2, TAPS><<<g, blk, 0, st>>>(N.nz, N.ny, N.nx, mt, NET_HID, a2, N.wb + N.off_w3, N.wb + N.off_b3, 0, out);
     FH_LAUNCH_CHECK();
 }
 
-void net_forward(hipStream_t st, const NetDev& N, int mt, const float* x, float* a1, float* a2, float* out) {
+void net_forward(hipStream_t st, const NetDev& N, int mt, const float* x, float* a1, float* a2, float* out,
+                 uint16_t* s1, uint16_t* s2) {
     const int npix = N.npix();
     hipEvent_t ev = prof_begin(st);
-    if (N.taps == 27) forward_t<27>(st, N, mt, x, a1, a2, out);
-    else forward_t<9>(st, N, mt, x, a1, a2, out);
+    if (N.taps == 27) forward_t<27>(st, N, mt, x, a1, a2, out, s1, s2);
+    else forward_t<9>(st, N, mt, x, a1, a2, out, s1, s2);
     const double macs = (double)N.taps * (N.cin * NET_HID + NET_HID * NET_HID + NET_HID * 2) * npix * mt;
     prof_end(st, ev, "net_forward", 4.0 * npix * mt * (N.cin + 2 * NET_HID + 2) * 2, 2 * macs);
 }
 
 template <int TAPS>
 static void backward_t(hipStream_t st, const NetDev& N, int mt, const float* x, const float* a1, const float* a2,
-                       const float* gout, float* g2, float* g1, float* grad, float* P, int nslice) {
+                       const float* gout, float* g2, float* g1, float* grad, float* P, int nslice, uint16_t* s1) {
     dim3 blk(64, 4), g = conv_grid(N.npix(), mt);
     const int T = TAPS;
     // layer 3: weights, then data through ReLU(a2)
@@ -553,8 +588,16 @@ static void backward_t(hipStream_t st, const NetDev& N, int mt, const float* x, 
     k_wgrad_reduce<<<ceil_div(NET_HID * (NET_HID + 1) * T, 128), 128, 0, st>>>(nslice, NET_HID, NET_HID, T, P,
                                                                                  grad + N.off_w2, grad + N.off_b2);
     FH_LAUNCH_CHECK();
-    k_conv16_bwd_data_mfma<TAPS><<<mfma_grid(N.npix(), mt), 256, 0, st>>>(N.nz, N.ny, N.nx, mt, g2, N.wb + N.off_w2, a1,
-                                                                           g1);
+    {
+        const long half = (long)N.npix() * 16 * mt;
+        bf16x4_t* g_hi = (bf16x4_t*)s1;
+        bf16x4_t* g_lo = (bf16x4_t*)(s1 + half);
+        k_split16<<<ceil_div((size_t)N.npix() * 4 * mt, 256), 256, 0, st>>>(N.npix(), mt, NET_HID, g2, g_hi, g_lo);
+        FH_LAUNCH_CHECK();
+        k_conv16_mfma<TAPS, true><<<mfma_grid(N, mt), 256, 0, st>>>(N.nz, N.ny, N.nx, mt, NET_HID, g_hi, g_lo,
+                                                                     N.wb + N.off_w2, nullptr, 0, a1, g1, nullptr,
+                                                                     nullptr);
+    }
     FH_LAUNCH_CHECK();
     // layer 1 (weights only)
     k_conv_bwd_weight<TAPS><<<nslice, 320, 0, st>>>(N.nz, N.ny, N.nx, mt, N.cin, NET_HID, x, g1, P);
@@ -565,12 +608,12 @@ static void backward_t(hipStream_t st, const NetDev& N, int mt, const float* x, 
 }
 
 void net_backward(hipStream_t st, const NetDev& N, int mt, const float* x, const float* a1, const float* a2,
-                  const float* gout, float* g2, float* g1, float* grad, DBuf& part) {
+                  const float* gout, float* g2, float* g1, float* grad, DBuf& part, uint16_t* s1) {
     const int nslice = ceil_div(N.npix(), WG_SLICE);
     float* P = (float*)part.ensure(sizeof(float) * (size_t)nslice * NET_MAX_COUT * (NET_MAX_CIN + 1) * N.taps);
     hipEvent_t ev = prof_begin(st);
-    if (N.taps == 27) backward_t<27>(st, N, mt, x, a1, a2, gout, g2, g1, grad, P, nslice);
-    else backward_t<9>(st, N, mt, x, a1, a2, gout, g2, g1, grad, P, nslice);
+    if (N.taps == 27) backward_t<27>(st, N, mt, x, a1, a2, gout, g2, g1, grad, P, nslice, s1);
+    else backward_t<9>(st, N, mt, x, a1, a2, gout, g2, g1, grad, P, nslice, s1);
     const double macs = (double)N.taps * (N.cin * NET_HID + NET_HID * NET_HID + NET_HID * 2) * N.npix() * mt;
     prof_end(st, ev, "net_backward", 0.0, 4 * macs);
 }

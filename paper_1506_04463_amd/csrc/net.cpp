@@ -94,6 +94,8 @@ static void ensure_acts(NetState& S, long npix, int mt) {
     S.a1.ensure(sizeof(float) * npix * NET_HID * mt);
     S.a2.ensure(sizeof(float) * npix * NET_HID * mt);
     S.out.ensure(sizeof(float) * npix * 2 * mt);
+    S.s1.ensure(sizeof(uint16_t) * 2 * npix * 16 * mt);
+    S.s2.ensure(sizeof(uint16_t) * 2 * npix * 16 * mt);
 }
 
 static void upload_sys(Ctx& c, NetState& S, int nsys, const double* shifts, const int* sides) {
@@ -114,7 +116,8 @@ void net_apply(Ctx& c, NetState& S, int nsys, int m, const Cx<T>* V, const zd* s
         net_inv_colnorm<T>(c.stream, S.d, m, nsys, V, sc);
     }
     net_encode<T>(c.stream, S.d, m, nsys, V, sc, shifts_dev, sides_dev, (float*)S.x.p);
-    net_forward(c.stream, S.d, mt, (const float*)S.x.p, (float*)S.a1.p, (float*)S.a2.p, (float*)S.out.p);
+    net_forward(c.stream, S.d, mt, (const float*)S.x.p, (float*)S.a1.p, (float*)S.a2.p, (float*)S.out.p,
+                (uint16_t*)S.s1.p, (uint16_t*)S.s2.p);
     net_decode<T>(c.stream, S.d, m, nsys, (const float*)S.out.p, sc, Out);
 }
 template void net_apply<double>(Ctx&, NetState&, int, int, const zd*, const zd*, const int*, zd*, bool);
@@ -192,14 +195,15 @@ double net_loss_grad(Ctx& c, NetState& S, const SparseState* sp, int nsys, int m
     net_encode<double>(c.stream, S.d, m, nsys, R, sc, (const zd*)S.shifts.p, (const int*)S.sides.p, (float*)S.x.p);
     float* tgt = (float*)S.tgt.ensure(sizeof(float) * npix * 2 * mt);
     net_target<double>(c.stream, S.d, m, nsys, E, sc, tgt);
-    net_forward(c.stream, S.d, mt, (const float*)S.x.p, (float*)S.a1.p, (float*)S.a2.p, (float*)S.out.p);
+    net_forward(c.stream, S.d, mt, (const float*)S.x.p, (float*)S.a1.p, (float*)S.a2.p, (float*)S.out.p,
+                (uint16_t*)S.s1.p, (uint16_t*)S.s2.p);
     float* gout = (float*)S.gout.ensure(sizeof(float) * npix * 2 * mt);
     const double loss = sp ? op_loss_grad(c, S, *sp, nsys, m, shifts, sides, (const float*)S.out.p, tgt, gout)
                            : net_loss(c.stream, S.d, mt, (const float*)S.out.p, tgt, gout, S.lossbuf);
     float* g2 = (float*)S.g2.ensure(sizeof(float) * npix * NET_HID * mt);
     float* g1 = (float*)S.g1.ensure(sizeof(float) * npix * NET_HID * mt);
     net_backward(c.stream, S.d, mt, (const float*)S.x.p, (const float*)S.a1.p, (const float*)S.a2.p, gout, g2, g1,
-                 (float*)S.grad.p, S.part);
+                 (float*)S.grad.p, S.part, (uint16_t*)S.s1.p);
     if (step) net_adam(c.stream, S.d, (const float*)S.grad.p, (float)lr);
     FH_HIP(hipStreamSynchronize(c.stream));
     return loss;
