@@ -622,7 +622,10 @@ __global__ __launch_bounds__(NT) void k_ilu_apply_lds(IluApplyArgs<T> a, const C
     const Cx<T>* bv = a.bval[side] + (long)node * B.K * a.n;
     const Cx<T>* bd = a.bdiag[side] ? a.bdiag[side] + (long)node * a.n : nullptr;
     sweep_lds<T, P, KM, NT>(F, a.n, a.m, c0, cw, fv, fd, X + base, Out + base, ring, ring_stride);
-    __syncthreads();       // the backward sweep reads the forward results from global memory
+    // The backward sweep starts with the rows other waves stored last in the
+    // forward sweep: a fence (waits for those stores) before the barrier.
+    __threadfence();
+    __syncthreads();
     sweep_lds<T, P, KM, NT>(B, a.n, a.m, c0, cw, bv, bd, Out + base, Out + base, ring, ring_stride);
 }
 

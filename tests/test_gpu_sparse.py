@@ -135,6 +135,21 @@ def test_ilu0_apply_c64_many_levels(handle, m):
         assert np.abs(y - y64).max() < 1e-4 * np.abs(y64).max()
 
 
+@pytest.mark.parametrize("N,m", [(24, 20), (160, 64)])
+def test_ilu0_apply_c64_repeatable(handle, N, m):
+    """The same apply, repeated, gives the same result: the sweeps' level
+    ordering leaves no read of a value before it is written (a race would
+    show as run-to-run differences far above rounding)."""
+    A = W.convdiff2d_csr(N, 20.0, 10.0)
+    prob = fh.Problem(handle, _csr(A))
+    X = _cuda(W.subspace(A["n"], m, 11).astype(np.complex64))
+    for side in (0, 1):
+        ys = [fh.ilu0_apply(prob, 300.0 + 40.0j, side, X).cpu().numpy() for _ in range(6)]
+        scale = np.abs(ys[0]).max()
+        for y in ys[1:]:
+            assert np.abs(y - ys[0]).max() <= 1e-6 * scale, (side, np.abs(y - ys[0]).max() / scale)
+
+
 def _small_convdiff(N=20, m_in=8, m0=16):
     return W.convdiff2d(N=N, m_in=m_in, m0=m0)
 
