@@ -144,7 +144,7 @@ def test_feast_dense_prescribed_against_truth():
     ev = ev[cont.inside(ev)]
     ev = ev[np.lexsort((ev.imag, ev.real))]
     assert np.max(np.abs(ev - r.lam)) < 1e-10 * cont.alpha()
-    # eigen-residual in the spec form, right and left, 1-norms
+    # eigen-residual ||Ax - lam x||_1 / (||A||_1 ||x||_1), right and left
     nA = np.abs(p.A).sum(axis=0).max()
     rr = np.abs(p.A @ r.X - r.X * r.lam).sum(axis=0) / (nA * np.abs(r.X).sum(axis=0))
     rl = np.abs(p.A.conj().T @ r.Xh - r.Xh * np.conj(r.lam)).sum(axis=0) / (nA * np.abs(r.Xh).sum(axis=0))
