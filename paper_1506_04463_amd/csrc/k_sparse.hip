@@ -605,6 +605,188 @@ __device__ __forceinline__ void sweep_lds(const SweepDev& sw, int n, int m, int 
     }
 }
 
+// Sweep with a deeper prefetch for levels that fit one batch (at most NT
+// rows and P * NT / cw items per level, at least one off-diagonal slot per
+// sweep).  A level's time is the latency it waits for, so every load a level
+// uses is issued three levels earlier, the row indices (on which the input
+// addresses depend) six levels earlier.  The factor data of a row (its
+// dependency slots, values and pivot) are loaded once per row, by the thread
+// of that row, and passed to the level's other threads through a two-level
+// LDS ring: per thread one row's worth of registers instead of one per item,
+// which keeps the four prefetch slots within the register file.  Nothing in
+// the loop branches on a thread's data (the compiler then counts the loads in
+// flight exactly):
+//  * the loop is unrolled by four, so each slot keeps its registers;
+//  * prefetches past the last level repeat the last level (in bounds, unused);
+//  * a thread whose item (or row) lies past the end of a narrower level
+//    repeats the level's last one: same inputs, same value, same address;
+//  * absent dependencies (slot < 0) contribute a selected zero;
+//  * the level pointers are read through the scalar cache.
+template <typename T, int P, int KM>
+struct SwPipe {
+    int row[P];          // row indices of a level (loaded six levels ahead)
+    Cx<T> x[P];          // inputs of a level (three levels ahead)
+    int off[P];          // element offsets of those inputs / outputs
+    int fslot[KM];       // one row's factor data (four levels ahead)
+    Cx<T> fv[KM];
+    Cx<T> fd;
+};
+
+template <typename T, int P, int KM, int NT>
+__device__ __forceinline__ void sweep_pipe(const SweepDev& sw, int n, int m, int c0, int cw,
+                                           const Cx<T>* __restrict__ val, const Cx<T>* __restrict__ dval,
+                                           const Cx<T>* In, Cx<T>* Os, Cx<T>* ring, int ring_stride,
+                                           int* fslot_l, Cx<T>* fv_l, Cx<T>* fd_l, int wmax) {
+    const int nlev = sw.nlev;
+    if (nlev <= 0) return;
+    using CI = const __attribute__((address_space(4))) int;
+    CI* lp = (CI*)sw.lev_ptr;
+    const int K = sw.K;
+    const bool hasd = dval != nullptr;
+    const Cx<T>* dsrc = hasd ? dval : val;         // unit sweeps load (and ignore) a valid entry
+    const int tid = threadIdx.x;
+    int ediv[P], emod[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int e0 = tid + NT * q;
+        ediv[q] = e0 / cw;
+        emod[q] = e0 % cw;
+    }
+    // level position of item q (or, for q < 0, of this thread's row) of level l, clamped
+    auto pos_of = [&](int l, int r) {
+        const int L = min(l, nlev - 1);
+        const int t0 = lp[L], rows = lp[L + 1] - t0;
+        return min(t0 + min(r, rows - 1), n - 1);
+    };
+    auto load_row = [&](int l, SwPipe<T, P, KM>& s) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) s.row[q] = sw.rows[pos_of(l, ediv[q])];
+    };
+    auto load_x = [&](SwPipe<T, P, KM>& s) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            s.off[q] = s.row[q] * m + c0 + emod[q];
+            s.x[q] = In[s.off[q]];
+        }
+    };
+    auto load_fac = [&](int l, SwPipe<T, P, KM>& s) {
+        const int t = pos_of(l, tid);
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            const int kk = k < K ? k : 0;
+            s.fslot[k] = sw.ell_slot[(long)kk * n + t];
+            s.fv[k] = val[(long)kk * n + t];
+        }
+        s.fd = dsrc[t];
+    };
+    // factor data of one level into LDS ring slot b (rows past the level's end repeat its last row)
+    auto put_fac = [&](const SwPipe<T, P, KM>& s, int b) {
+        if (tid < wmax) {
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                fslot_l[(b * wmax + tid) * KM + k] = s.fslot[k];
+                fv_l[(b * wmax + tid) * KM + k] = s.fv[k];
+            }
+            fd_l[b * wmax + tid] = s.fd;
+        }
+    };
+    // Slot of level L: L mod 4 for each kind of data (row indices live from
+    // level L-6 to L-3, inputs from L-3 to L, factor data from L-4 to L-1).
+    // At level l, with a, b, c, d the slots of l .. l+3: inputs of level l+3
+    // (rows in d), factor data of level l+1 (in b) to LDS, rows of level l+6
+    // (slot c), factor data of level l+4 (slot a), then level l from a and
+    // LDS.  Every wait is for loads issued three levels earlier.
+    auto level = [&](int l, SwPipe<T, P, KM>& a, SwPipe<T, P, KM>& b, SwPipe<T, P, KM>& c,
+                     SwPipe<T, P, KM>& d) {
+        load_x(d);
+        put_fac(b, (l + 1) & 1);
+        load_row(l + 6, c);
+        load_fac(l + 4, a);
+        const int rows = lp[l + 1] - lp[l];
+        const Cx<T>* prev = ring + (long)((l + 1) & 1) * ring_stride;
+        Cx<T>* cur = ring + (long)(l & 1) * ring_stride;
+        const int fb = (l & 1) * wmax;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int pos = min(ediv[q], rows - 1);
+            Cx<T> v = a.x[q];
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                const int sl = fslot_l[(fb + pos) * KM + k];
+                const bool dep = k < K && sl >= 0;
+                const Cx<T> pv = prev[(dep ? sl : 0) * cw + emod[q]];
+                cfms(v, fv_l[(fb + pos) * KM + k], dep ? pv : czero<T>());
+            }
+            if (hasd) v = fd_l[fb + pos] * v;
+            cur[pos * cw + emod[q]] = v;
+            Os[a.off[q]] = v;
+        }
+        lds_barrier();
+    };
+    SwPipe<T, P, KM> s0, s1, s2, s3;
+    // The loads of levels 0-5 in the order the loop issues them (as if levels
+    // -6 to -1 ran): at the loop entry the compiler merges this order with the
+    // loop's own, and waits by the one with fewer loads issued since
+    // (scheduling barriers keep that order).
+    load_row(0, s0);
+    load_row(1, s1);
+    load_row(2, s2);
+    load_fac(0, s0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_x(s0);
+    load_row(3, s3);
+    load_fac(1, s1);
+    __builtin_amdgcn_sched_barrier(0);
+    load_x(s1);
+    load_row(4, s0);
+    load_fac(2, s2);
+    __builtin_amdgcn_sched_barrier(0);
+    load_x(s2);
+    put_fac(s0, 0);
+    load_row(5, s1);
+    load_fac(3, s3);
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+    for (int l = 0; l < nlev; l += 4) {
+        level(l, s0, s1, s2, s3);
+        if (l + 1 >= nlev) break;
+        level(l + 1, s1, s2, s3, s0);
+        if (l + 2 >= nlev) break;
+        level(l + 2, s2, s3, s0, s1);
+        if (l + 3 >= nlev) break;
+        level(l + 3, s3, s0, s1, s2);
+    }
+}
+
+template <typename T, int P, int KM, int NT>
+__global__ __launch_bounds__(NT) void k_ilu_apply_pipe(IluApplyArgs<T> a, const Cx<T>* __restrict__ X, Cx<T>* Out,
+                                                       int ring_stride, int wmax) {
+    extern __shared__ unsigned char dsm[];
+    Cx<T>* ring = reinterpret_cast<Cx<T>*>(dsm);                 // [2][wmax][cw]
+    Cx<T>* fv_l = ring + 2 * ring_stride;                         // [2][wmax][KM]
+    Cx<T>* fd_l = fv_l + 2 * wmax * KM;                           // [2][wmax]
+    int* fslot_l = reinterpret_cast<int*>(fd_l + 2 * wmax);       // [2][wmax][KM]
+    const int s = blockIdx.y;
+    const int c0 = blockIdx.x * a.cw;
+    const int cw = min(a.cw, a.m - c0);
+    const int node = a.node_of[s], side = a.side_of[s];
+    const long base = (long)s * a.n * a.m;
+    const SweepDev& F = a.fwd[side];
+    const SweepDev& B = a.bwd[side];
+    const Cx<T>* fv = a.fval[side] + (long)node * F.K * a.n;
+    const Cx<T>* fd = a.fdiag[side] ? a.fdiag[side] + (long)node * a.n : nullptr;
+    const Cx<T>* bv = a.bval[side] + (long)node * B.K * a.n;
+    const Cx<T>* bd = a.bdiag[side] ? a.bdiag[side] + (long)node * a.n : nullptr;
+    sweep_pipe<T, P, KM, NT>(F, a.n, a.m, c0, cw, fv, fd, X + base, Out + base, ring, ring_stride, fslot_l, fv_l,
+                             fd_l, wmax);
+    // the backward sweep starts with the rows other waves stored last in the
+    // forward sweep, whose stores the sweep loop leaves in flight
+    __threadfence();
+    __syncthreads();
+    sweep_pipe<T, P, KM, NT>(B, a.n, a.m, c0, cw, bv, bd, Out + base, Out + base, ring, ring_stride, fslot_l, fv_l,
+                             fd_l, wmax);
+}
+
 template <typename T, int P, int KM, int NT>
 __global__ __launch_bounds__(NT) void k_ilu_apply_lds(IluApplyArgs<T> a, const Cx<T>* __restrict__ X, Cx<T>* Out,
                                                       int ring_stride) {
@@ -661,13 +843,28 @@ void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<
     const int K = std::max(std::max(a.fwd[0].K, a.bwd[0].K), std::max(a.fwd[1].K, a.bwd[1].K));
     hipEvent_t ev = prof_begin(st);
     bool lds = K <= 4;
-    int wmax = 0;
+    int wmax = 0, kmin = K;
     for (int sd = 0; sd < 2; ++sd) {
         lds = lds && a.fwd[sd].adjacent && a.bwd[sd].adjacent;
         wmax = std::max(wmax, std::max(a.fwd[sd].wmax, a.bwd[sd].wmax));
+        kmin = std::min(kmin, std::min(a.fwd[sd].K, a.bwd[sd].K));
     }
     const size_t ring_bytes = 2 * sizeof(Cx<T>) * (size_t)wmax * a.cw;
-    if (lds && ring_bytes <= 48 * 1024) {
+    const size_t fac_bytes = 2 * (size_t)wmax * (2 * sizeof(Cx<T>) + sizeof(Cx<T>) + 2 * sizeof(int));
+    // complex FP32, at most two off-diagonal slots, levels of at most 512 rows
+    // and 2,048 items: the pipelined sweep
+    const bool pipe = lds && sizeof(T) == 4 && K <= 2 && kmin >= 1 && wmax <= 512 && (long)wmax * a.cw <= 2048 &&
+                      (long)a.n * a.m < (1L << 31) && ring_bytes + fac_bytes <= 64 * 1024;
+    if (pipe) {
+        if constexpr (sizeof(T) == 4) {
+            const int stride = wmax * a.cw;
+            const size_t sh = ring_bytes + fac_bytes;
+            if (wmax > 256 || (long)wmax * a.cw > 1024)
+                k_ilu_apply_pipe<T, 4, 2, 512><<<grid, 512, sh, st>>>(a, X, Out, stride, wmax);
+            else
+                k_ilu_apply_pipe<T, 4, 2, 256><<<grid, 256, sh, st>>>(a, X, Out, stride, wmax);
+        }
+    } else if (lds && ring_bytes <= 48 * 1024) {
         // one batch per level when possible (a second batch would not be prefetched):
         // 512 threads when a level holds more than 256 x 4 items
         const int stride = wmax * a.cw;
