@@ -264,6 +264,90 @@ def learned3d(args):
     print(json.dumps(line))
 
 
+def csym(args):
+    """Complex-symmetric 2D operator A = -Lap_h + V - i eta W (256 x 256 grid,
+    n = 65,536, A = A^T; 50 Gaussian wells, absorbing ramp), circle around the
+    40 lowest eigenvalues (well-bound states, located once on the CPU with
+    scipy's shift-invert ARPACK), Ne = 16, m0 = 64, mixed path.  FEAST with
+    the left subspace taken as the conjugate of the right one (opts.sym = 1:
+    Ne solves per iteration) against the general algorithm (2 Ne solves):
+    both solved to eq:res <= 1e-9 from the same seeded start (eigenvalues
+    compared), and iterations 2..K+1 (K <= 2) of that start timed.""" 
+    import scipy.sparse as sps
+    import scipy.sparse.linalg as spla
+    import torch
+    import workloads as W
+    import paper_1506_04463_amd as fh
+    A = W.schrodinger2d_csr(256)
+    n = A["n"]
+    Asp = sps.csr_matrix((A["val"], A["colind"], A["rowptr"]), shape=(n, n))
+    # the 48 lowest eigenvalues (nearest a point below the spectrum); the circle
+    # spans the 40 lowest, where the shifted systems are nearly definite
+    ev = spla.eigs(Asp, k=48, sigma=-60.0, return_eigenvectors=False, tol=1e-10)
+    ev = ev[np.argsort(ev.real)]
+    c = 0.5 * (ev[0].real + ev[39].real)
+    r = 0.5 * (abs(ev[39] - c) + abs(ev[40] - c))
+    target = complex(c)
+    h = fh.Handle(0)
+    prob = fh.Problem(h, fh.CSR(torch.from_numpy(A["rowptr"]).cuda(), torch.from_numpy(A["colind"]).cuda(),
+                                torch.from_numpy(A["val"]).cuda(), n))
+    m0, ne = 64, 16
+    Y0 = torch.from_numpy(W.subspace(n, m0, 7)).cuda()
+    Yh0 = torch.conj(Y0).resolve_conj().contiguous()
+    print(f"[bench] csym: n={n} circle {target:.4f} r={r:.4g}, {int(np.sum(np.abs(ev - target) < r))} of the 48 "
+          f"lowest eigenvalues inside", 
+          file=sys.stderr, flush=True)
+
+    def opts(sym, max_iter, eps, resume=0):
+        o = _opts(fh, m0, fh.FH_PREC_MIXED, max_iter, eps, resume)
+        o.sym = sym
+        return o
+
+    # time to solution from the seeded start first; then iterations 2..K+1 of
+    # the same start timed (the general path's eigendecomposition of B_Q fails
+    # from its 4th-5th iteration on this problem, an open issue: it is
+    # reported, and the timed iterations stay before it)
+    K = max(1, min(args.steps, 2))
+    res = {}
+    for sym in (1, 0):
+        r_ = {"solves_per_iteration": ne * (1 if sym else 2)}
+        try:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fin = fh.feast(prob, target, r, 1.0, 0.0, ne, Y0, Yh0, opts(sym, 60, EPS_ITER))
+            torch.cuda.synchronize()
+            r_.update({"converged": fin["info"] == 0, "iterations": int(fin["report"]["iters"]),
+                       "m": int(len(fin["lam"])), "time_to_solution_s": time.perf_counter() - t0,
+                       "lam": np.sort_complex(fin["lam"])})
+        except fh.FeastError as e:
+            r_.update({"converged": False, "error": str(e), "lam": np.zeros(0, complex)})
+        out = fh.feast(prob, target, r, 1.0, 0.0, ne, Y0, Yh0, opts(sym, 1, 1e-300))
+        Y, Yh, ritz = out["Y"].contiguous(), out["Yh"].contiguous(), out["ritz"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fh.feast(prob, target, r, 1.0, 0.0, ne, Y, Yh, opts(sym, K, 1e-300, 1), ritz0=ritz)
+        torch.cuda.synchronize()
+        r_["ms_per_iteration"] = 1000.0 * (time.perf_counter() - t0) / K
+        res[sym] = r_
+        print(f"[bench] csym sym={sym}: {r_['ms_per_iteration']:.1f} ms/iteration; to eq:res <= {EPS_ITER:g}: "
+              + (f"{r_['time_to_solution_s']:.2f} s, {r_['iterations']} iterations, m = {r_['m']}"
+                 if "error" not in r_ else r_["error"]), file=sys.stderr, flush=True)
+    la, lb = res[1].pop("lam"), res[0].pop("lam")
+    same = len(la) == len(lb) and len(la) > 0
+    dl = float(np.max(np.abs(la - lb)) / (abs(target) + r)) if same else None
+    line = {"metric": "FEAST iterations/s, complex symmetric (left subspace = conj(right)) vs general",
+            "value": 1000.0 / res[1]["ms_per_iteration"], "unit": "FEAST iterations/s", "n_gpus": 1,
+            "steps": K, "warmup": 1, "ms_per_step": res[1]["ms_per_iteration"],
+            "higher_is_better": True, "dtype": "c64 inner solves + c128 refinement/Rayleigh-Ritz",
+            "data": "synthetic",
+            "config": {"workload": "complex-symmetric Schroedinger-type 256x256 (n=65536), Ne=16, m0=64, "
+                                   "GMRES(30)x2 + ILU(0), c64 + FP64 refinement"},
+            "sym": res[1], "general": res[0],
+            "speedup_per_iteration": res[0]["ms_per_iteration"] / res[1]["ms_per_iteration"],
+            "same_eigenvalue_count": same, "max_dlam_over_alpha": dl}
+    print(json.dumps(line))
+
+
 def copy_calibration():
     """A plain device copy of a known size (1 GiB read, 1 GiB written), run
     three times: the reference for scaling the FETCH_SIZE / WRITE_SIZE
@@ -288,7 +372,7 @@ def main():
     ap.add_argument("--no-validate", action="store_true")
     ap.add_argument("--columns", type=int, default=128, help="learned3d: columns per system")
     ap.add_argument("--workload", default="convdiff", choices=["convdiff", "dense-batch", "copy-calibration",
-                                                              "learned3d"],
+                                                              "learned3d", "csym"],
                     help="convdiff: the headline sparse workload (default); dense-batch: 64 dense problems; "
                          "copy-calibration: a 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--count", type=int, default=64, help="dense-batch: number of problems")
@@ -310,6 +394,9 @@ def main():
         return
     if args.workload == "learned3d":
         learned3d(args)
+        return
+    if args.workload == "csym":
+        csym(args)
         return
     import torch
     import paper_1506_04463_amd as fh

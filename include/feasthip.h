@@ -124,6 +124,15 @@ typedef struct {
                              sums the chunks' contributions, so the result
                              does not depend on it beyond rounding and the
                              inner tolerances */
+    int sym;              /* sparse problems: 1 = complex symmetric (A = A^T).
+                             The left eigenvectors are then the conjugates of
+                             the right ones, so the filter takes Qh = conj(Q)
+                             and solves only the n_e right systems instead of
+                             2 n_e (paper, reduced-workload cases, complex
+                             symmetric; Table tab:solve); Yh is not read by
+                             the filter.  The call returns -2 if A is not
+                             symmetric.  0 = general.  Dense problems ignore
+                             it */
 } fh_opts;
 
 typedef struct {

@@ -51,7 +51,8 @@ class fh_opts(C.Structure):
                 ("solver", C.c_int), ("restart", C.c_int), ("block", C.c_int), ("precond", C.c_int),
                 ("inner_tol", C.c_double), ("max_restarts", C.c_int), ("mixed_inner_tol", C.c_double),
                 ("max_refine", C.c_int), ("save_factors", C.c_int), ("resume", C.c_int), ("fallback", C.c_int),
-                ("graph", C.c_int), ("orth", C.c_int), ("batch_nodes", C.c_int)]
+                ("graph", C.c_int), ("orth", C.c_int), ("batch_nodes", C.c_int),
+                ("sym", C.c_int)]
 
 
 class fh_report(C.Structure):

@@ -66,6 +66,7 @@ void fh_default_opts(fh_opts* o) {
     o->graph = 0;
     o->orth = 0;
     o->batch_nodes = 0;
+    o->sym = 0;
 }
 
 int fh_create(fh_handle* h, int device, void* stream) {

@@ -29,6 +29,9 @@ void accumulate(hipStream_t st, int ne, long len, const zd* X, long strideX, con
 template <typename T>
 void replicate(hipStream_t st, long len, const Cx<T>* src, Cx<T>* dst, int copies);
 
+// dst = conj(src), elementwise
+void conj_copy(hipStream_t st, long len, const zd* src, zd* dst);
+
 // cast between complex precisions
 template <typename D, typename S>
 void cast(hipStream_t st, long len, const Cx<S>* src, Cx<D>* dst);

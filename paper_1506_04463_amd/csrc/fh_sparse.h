@@ -60,6 +60,7 @@ struct NetState;
 struct SparseState {
     int n = 0;
     long nnzA = 0, nnzM = 0;
+    bool csym = false;            // A = A^T (pattern and values)
     CsrDev A, AT;
     // M = A + diagonal pattern and its transpose
     int *mrowptr = nullptr, *mcol = nullptr, *mdiag = nullptr, *a2m = nullptr;

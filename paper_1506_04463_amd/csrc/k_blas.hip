@@ -213,6 +213,19 @@ void replicate(hipStream_t st, long len, const Cx<T>* src, Cx<T>* dst, int copie
 template void replicate<double>(hipStream_t, long, const zd*, zd*, int);
 template void replicate<float>(hipStream_t, long, const cf*, cf*, int);
 
+// dst = conj(src), elementwise
+__global__ void k_conj_copy(long len, const zd* __restrict__ src, zd* __restrict__ dst) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= len) return;
+    const zd v = src[e];
+    dst[e] = zd{v.re, -v.im};
+}
+void conj_copy(hipStream_t st, long len, const zd* src, zd* dst) {
+    if (len <= 0) return;
+    k_conj_copy<<<ceil_div(len, 256), 256, 0, st>>>(len, src, dst);
+    FH_LAUNCH_CHECK();
+}
+
 template <typename D, typename S>
 __global__ void k_cast(long len, const Cx<S>* __restrict__ src, Cx<D>* __restrict__ dst) {
     long e = (long)blockIdx.x * blockDim.x + threadIdx.x;

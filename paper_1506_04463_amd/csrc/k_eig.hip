@@ -89,7 +89,7 @@ __device__ __forceinline__ void givens(zd x, zd y, double& c, zd& s, zd& r) {
 __device__ int schur_qr(int m, zd* H, zd* Z) {
     const int tid = threadIdx.x;
     const double ulp = DBL_EPSILON, smlnum = DBL_MIN * (double(m) / DBL_EPSILON);
-    int ihi = m - 1, its = 0, total = 0;
+    int ihi = m - 1, its = 0;
     __shared__ int lsh;
     while (ihi >= 1) {
         // largest kk <= ihi with a negligible subdiagonal entry (0 if none):
@@ -111,11 +111,13 @@ __device__ int schur_qr(int m, zd* H, zd* Z) {
         if (l > 0 && tid == 0) H[(long)l * m + l - 1] = czero<double>();
         __syncthreads();
         if (l == ihi) { --ihi; its = 0; continue; }
-        // shift
+        // shift: Wilkinson's, or every 10 iterations without a deflation an
+        // exceptional one, alternating between the top and the bottom of the
+        // active block (the schedule of LAPACK's complex QR iteration)
         zd mu;
-        if (its == 10) {
+        if (its > 0 && its % 20 == 10) {
             mu = H[(long)l * m + l] + cx(0.75 * fabs(H[(long)(l + 1) * m + l].re), 0.0);
-        } else if (its == 20) {
+        } else if (its > 0 && its % 20 == 0) {
             mu = H[(long)ihi * m + ihi] + cx(0.75 * fabs(H[(long)ihi * m + ihi - 1].re), 0.0);
         } else {
             const zd a = H[(long)(ihi - 1) * m + ihi - 1], b = H[(long)(ihi - 1) * m + ihi];
@@ -153,8 +155,7 @@ __device__ int schur_qr(int m, zd* H, zd* Z) {
             }
             __syncthreads();
         }
-        ++its;
-        if (++total > 30 * m) return 1;
+        if (++its > 30 * max(10, m)) return 1;   // per deflation, as LAPACK's ITMAX
     }
     __syncthreads();
     return 0;

@@ -758,6 +758,18 @@ __device__ __forceinline__ void sweep_pipe(const SweepDev& sw, int n, int m, int
     }
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  The
+// column blocks of one system share the factor data, and neighbouring blocks
+// share the 128-byte lines of the vectors: this mapping gives consecutive
+// blocks of a system consecutive workgroups of the same XCD.  Returns the
+// (system, column block) of this workgroup.
+__device__ __forceinline__ int2 xcd_block() {
+    int lin = blockIdx.x + blockIdx.y * gridDim.x;
+    const int G = gridDim.x * gridDim.y;
+    if (G % 8 == 0) lin = (lin % 8) * (G / 8) + lin / 8;
+    return make_int2(lin / gridDim.x, lin % gridDim.x);
+}
+
 template <typename T, int P, int KM, int NT>
 __global__ __launch_bounds__(NT) void k_ilu_apply_pipe(IluApplyArgs<T> a, const Cx<T>* __restrict__ X, Cx<T>* Out,
                                                        int ring_stride, int wmax) {
@@ -766,8 +778,9 @@ __global__ __launch_bounds__(NT) void k_ilu_apply_pipe(IluApplyArgs<T> a, const 
     Cx<T>* fv_l = ring + 2 * ring_stride;                         // [2][wmax][KM]
     Cx<T>* fd_l = fv_l + 2 * wmax * KM;                           // [2][wmax]
     int* fslot_l = reinterpret_cast<int*>(fd_l + 2 * wmax);       // [2][wmax][KM]
-    const int s = blockIdx.y;
-    const int c0 = blockIdx.x * a.cw;
+    const int2 sb = xcd_block();
+    const int s = sb.x;
+    const int c0 = sb.y * a.cw;
     const int cw = min(a.cw, a.m - c0);
     const int node = a.node_of[s], side = a.side_of[s];
     const long base = (long)s * a.n * a.m;
@@ -792,8 +805,9 @@ __global__ __launch_bounds__(NT) void k_ilu_apply_lds(IluApplyArgs<T> a, const C
                                                       int ring_stride) {
     extern __shared__ unsigned char dsm[];
     Cx<T>* ring = reinterpret_cast<Cx<T>*>(dsm);      // [2][wmax][cw]
-    const int s = blockIdx.y;
-    const int c0 = blockIdx.x * a.cw;
+    const int2 sb = xcd_block();
+    const int s = sb.x;
+    const int c0 = sb.y * a.cw;
     const int cw = min(a.cw, a.m - c0);
     const int node = a.node_of[s], side = a.side_of[s];
     const long base = (long)s * a.n * a.m;

@@ -288,6 +288,18 @@ void sparse_prepare(Ctx& c, Prob& p) {
     gather_vals(st, nnz, cplx_vals, p.A.val, at2a_d, (void*)S->AT.val64);
     S->AT.val32 = S->atval32.ensure(vb / 2 * std::max<long>(1, nnz));
     cast_vals(st, nnz, cplx_vals, S->AT.val64, (void*)S->AT.val32);
+    // complex symmetric (A = A^T): the transposed pattern is the pattern and
+    // every value equals its transposed partner (checked exactly)
+    S->csym = atrp == rp && atci == ci;
+    if (S->csym && nnz > 0) {
+        std::vector<double> hv(nnz * (cplx_vals ? 2 : 1));
+        FH_HIP(hipMemcpyAsync(hv.data(), p.A.val, vb * nnz, hipMemcpyDeviceToHost, st));
+        FH_HIP(hipStreamSynchronize(st));
+        const int w = cplx_vals ? 2 : 1;
+        for (long q = 0; q < nnz && S->csym; ++q)
+            for (int k = 0; k < w; ++k)
+                if (hv[(size_t)q * w + k] != hv[(size_t)at2a[q] * w + k]) S->csym = false;
+    }
     FH_HIP(hipStreamSynchronize(st));
     ilu_chunk_defaults(*S);
 }
@@ -687,7 +699,7 @@ static int filter_chunk(const SparseState& S, int ne, int m, const fh_opts& o) {
     size_t freeb = 0, total = 0;
     FH_HIP(hipMemGetInfo(&freeb, &total));
     const double budget = 0.5 * (double)total;
-    const int g = (int)std::floor(budget / (2.0 * per_sys));
+    const int g = (int)std::floor(budget / ((o.sym ? 1.0 : 2.0) * per_sys));
     return std::max(1, std::min(ne, g));
 }
 
@@ -695,6 +707,11 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
                    zd* Qh, const fh_opts& o, fh_report* rep, const cplx* lam) {
     FH_REQUIRE(m >= 1 && m <= 256, -6, "sparse filter: m0 must be in [1, 256]");
     SparseState& S = *p.sp;
+    // complex symmetric problems: the left subspace is the conjugate of the
+    // right one (section on reduced workloads, complex symmetric case), so
+    // only the right systems are solved
+    const bool sym = o.sym == 1;
+    FH_REQUIRE(!sym || S.csym, -2, "opts.sym = 1 needs a complex symmetric matrix (A = A^T)");
     hipStream_t st = c.stream;
     const int n = S.n;
     const long blk = (long)n * m;
@@ -711,7 +728,7 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
         lamd = ld + 2 * m;
         FH_HIP(hipMemcpyAsync(lamd, lam, sizeof(zd) * m, hipMemcpyHostToDevice, st));
         ritz_residual(st, S.A, false, n, m, lamd, false, Y, T);           // R  = A Y - Y Lambda
-        ritz_residual(st, S.AT, true, n, m, lamd, true, Yh, T + blk);     // Rh = A^H Yh - Yh Lambda^*
+        if (!sym) ritz_residual(st, S.AT, true, n, m, lamd, true, Yh, T + blk);   // Rh = A^H Yh - Yh Lambda^*
         for (int i = 0; i < m; ++i) {
             cplx r = 0.0;
             for (int j = 0; j < ne; ++j) {
@@ -741,14 +758,15 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
     const zd* Rl = lam ? T + blk : Yh;
     SolveStats s;
     // nodes [j0, j1) at a time: their right and left systems in one batch
+    const int sides = sym ? 1 : 2;
     for (int j0 = 0; j0 < ne; j0 += g) {
         const int j1 = std::min(ne, j0 + g), gc = j1 - j0;
         replicate<double>(st, blk, Rr, Bb, gc);
-        replicate<double>(st, blk, Rl, Bb + gc * blk, gc);
-        std::vector<int> node_of(2 * gc);
-        std::vector<cplx> zsys(2 * gc);
-        for (int q = 0; q < 2 * gc; ++q) { node_of[q] = j0 + q % gc; zsys[q] = z[j0 + q % gc]; }
-        const SolveStats sc = solve_batch(c, S, 2 * gc, gc, node_of.data(), zsys.data(), m, Bb, Xb, o);
+        if (!sym) replicate<double>(st, blk, Rl, Bb + gc * blk, gc);
+        std::vector<int> node_of(sides * gc);
+        std::vector<cplx> zsys(sides * gc);
+        for (int q = 0; q < sides * gc; ++q) { node_of[q] = j0 + q % gc; zsys[q] = z[j0 + q % gc]; }
+        const SolveStats sc = solve_batch(c, S, sides * gc, gc, node_of.data(), zsys.data(), m, Bb, Xb, o);
         s.steps += sc.steps;
         s.cycles += sc.cycles;
         s.relres = std::max(s.relres, sc.relres);
@@ -756,13 +774,15 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
         const bool first = j0 == 0;
         filter_accum(st, gc, n, m, Xb, cd + (size_t)j0 * m, (lam && first) ? Y : nullptr, first ? rd : nullptr, Q,
                      !first);
-        filter_accum(st, gc, n, m, Xb + gc * blk, cd + (size_t)(ne + j0) * m, (lam && first) ? Yh : nullptr,
-                     (first && rd) ? rd + m : nullptr, Qh, !first);
+        if (!sym)
+            filter_accum(st, gc, n, m, Xb + gc * blk, cd + (size_t)(ne + j0) * m, (lam && first) ? Yh : nullptr,
+                         (first && rd) ? rd + m : nullptr, Qh, !first);
     }
+    if (sym) conj_copy(st, blk, Q, Qh);                                   // Qh = conj(Q)
     FH_HIP(hipStreamSynchronize(st));
     if (rep) {
-        rep->n_fallback += s.fallback ? 2 * ne : 0;
-        rep->n_solve += 2 * ne;
+        rep->n_fallback += s.fallback ? sides * ne : 0;
+        rep->n_solve += sides * ne;
         rep->inner_steps = s.steps;
         rep->inner_relres = s.relres;
     }

@@ -225,7 +225,11 @@ def test_filter_unpreconditioned_and_jacobi(handle, precond):
     assert np.linalg.norm(Qh.cpu().numpy() - Qho) / np.linalg.norm(Qho) < tol
 
 
-def test_feast_complex_symmetric_small(handle):
+@pytest.mark.parametrize("sym", [0, 1])
+def test_feast_complex_symmetric_small(handle, sym):
+    """sym = 1: the left subspace is taken as the conjugate of the right one
+    and only the right systems are solved (half the solves of sym = 0), with
+    the same eigenpairs."""
     A = W.schrodinger2d_csr(16, L=10.0, nwells=6, seed=4)
     Ad = W.csr_to_dense(A)
     ev = sla.eigvals(Ad)
@@ -238,15 +242,56 @@ def test_feast_complex_symmetric_small(handle):
     ref = F.feast(L.csr_matrix(A), None, cont, Y0, Yh0, eps=1e-12, max_iter=40)
     prob = fh.Problem(handle, _csr(A))
     opts = fh.default_opts(16, solver=1, precond=2, inner_tol=1e-3, restart=30, max_restarts=2, eps=1e-12,
-                           max_iter=40)
+                           max_iter=40, sym=sym)
     out = fh.feast(prob, c, r, 1.0, 0.0, 16, _cuda(Y0), _cuda(Yh0), opts)
     assert out["info"] == 0 and ref.info == 0
+    assert out["report"]["n_solve"] == out["report"]["iters"] * 16 * (1 if sym else 2)
     assert len(out["lam"]) == len(ref.lam) == 8
     assert np.max(np.abs(out["lam"] - ref.lam)) < 1e-10 * cont.alpha()
     X, Xh = out["X"].cpu().numpy(), out["Xh"].cpu().numpy()
     for i in range(8):          # complex symmetric: Xh parallel to conj(X)
         x, xh = X[:, i], Xh[:, i]
         assert abs(np.vdot(np.conj(x), xh)) / (np.linalg.norm(x) * np.linalg.norm(xh)) > 1 - 1e-9
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_filter_sparse_sym_parity(handle, precision):
+    """Complex symmetric A with Yh = conj(Y): the filter with opts.sym = 1
+    (right systems only, Qh = conj(Q)) against the oracle's filter, which
+    solves the left systems too."""
+    A = W.schrodinger2d_csr(12, L=10.0, nwells=5, seed=3)
+    n = A["n"]
+    ev = sla.eigvals(W.csr_to_dense(A))
+    c = ev[np.argsort(np.abs(ev - (np.median(ev.real[:30]) - 0.5j)))[0]]
+    r = 0.5 * np.sort(np.abs(ev - c))[6:8].sum()
+    z, w = ct.ellipse_nodes(c, r, 1.0, 0.0, 12)
+    Y = W.subspace(n, 10, 21)
+    Yh = np.conj(Y)
+    Qo, Qho = F.contour_filter(L.csr_matrix(A), None, z, w, Y, Yh)
+    prob = fh.Problem(handle, _csr(A))
+    opts = fh.default_opts(10, solver=1, precond=2, inner_tol=1e-12, restart=30, max_restarts=400,
+                           precision=precision, mixed_inner_tol=1e-5, max_refine=30, sym=1)
+    Q, Qh, rep = fh.contour_filter(prob, z, w, _cuda(Y), _cuda(Yh), opts)
+    Q, Qh = Q.cpu().numpy(), Qh.cpu().numpy()
+    assert rep["n_solve"] == 12
+    assert rep["inner_relres"] <= 1e-10
+    Ad = W.csr_to_dense(A)
+    kap = max(np.linalg.cond(zj * np.eye(n) - Ad) for zj in z)
+    tol = 10 * kap * max(rep["inner_relres"], 1e-14)
+    assert np.linalg.norm(Q - Qo) / np.linalg.norm(Qo) < tol
+    assert np.linalg.norm(Qh - Qho) / np.linalg.norm(Qho) < tol
+    assert np.array_equal(Qh, np.conj(Q))
+
+
+def test_sym_rejects_nonsymmetric_matrix(handle):
+    """opts.sym = 1 on a matrix with A != A^T is an error (-2, the problem)."""
+    p = _small_convdiff(N=12, m_in=4, m0=8)
+    prob = fh.Problem(handle, _csr(p.A))
+    z, w = ct.ellipse_nodes(p.contour.center, p.contour.a, p.contour.ratio, 0.0, 8)
+    opts = fh.default_opts(p.m0, solver=1, precond=2, sym=1)
+    with pytest.raises(fh.FeastError) as e:
+        fh.contour_filter(prob, z, w, _cuda(p.Y0), _cuda(p.Yh0), opts)
+    assert e.value.code == -2
 
 
 @pytest.mark.parametrize("restart", [30, 20])

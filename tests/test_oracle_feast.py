@@ -248,3 +248,28 @@ def test_convergence_rate_prediction():
     assert len(idx) >= 3
     obs = np.exp(np.polyfit(idx, np.log(worst[idx]), 1)[0])
     assert abs(np.log(obs / rate)) < np.log(1.6), (obs, rate)
+
+
+def test_complex_symmetric_left_filter_is_conjugate():
+    """Complex symmetric A (A = A^T): the left eigenvectors are the conjugates
+    of the right ones, and with Yh = conj(Y) the left filter equals the
+    conjugate of the right filter (the reduced-workload case of the paper
+    that lets the left solves be skipped).  Checked with the oracle's own left
+    solves, against scipy's left eigenvectors."""
+    A = W.schrodinger2d_csr(8, L=8.0, nwells=3, seed=1)
+    Asp = L.csr_matrix(A)
+    assert abs(Asp - Asp.T).max() == 0
+    Ad = W.csr_to_dense(A)
+    lam, vl, vr = sla.eig(Ad, left=True, right=True)
+    for i in range(0, A["n"], 7):
+        x, xh = vr[:, i], vl[:, i]
+        assert abs(np.vdot(np.conj(x), xh)) / (np.linalg.norm(x) * np.linalg.norm(xh)) > 1 - 1e-10
+    c = lam[np.argsort(np.abs(lam - np.median(lam)))[0]]
+    r = 0.5 * np.sort(np.abs(lam - c))[5:7].sum()
+    z, w = ct.ellipse_nodes(c, r, 1.0, 0.0, 8)
+    Y = W.subspace(A["n"], 8, 3)
+    Q, Qh = F.contour_filter(Asp, None, z, w, Y, np.conj(Y))
+    assert np.linalg.norm(Qh - np.conj(Q)) <= 1e-12 * np.linalg.norm(Q)
+    # a general left block breaks the identity (the check has teeth)
+    Q2, Qh2 = F.contour_filter(Asp, None, z, w, Y, W.subspace(A["n"], 8, 4))
+    assert np.linalg.norm(Qh2 - np.conj(Q2)) > 1e-3 * np.linalg.norm(Q2)
