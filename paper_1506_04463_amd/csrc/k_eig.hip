@@ -90,7 +90,7 @@ __device__ int schur_qr(int m, zd* H, zd* Z) {
     const int tid = threadIdx.x;
     const double ulp = DBL_EPSILON, smlnum = DBL_MIN * (double(m) / DBL_EPSILON);
     int ihi = m - 1, its = 0;
-    __shared__ int lsh;
+    __shared__ int lsh, lst;
     while (ihi >= 1) {
         // largest kk <= ihi with a negligible subdiagonal entry (0 if none):
         // every thread tests its own entries and one LDS maximum combines them
@@ -127,14 +127,31 @@ __device__ int schur_qr(int m, zd* H, zd* Z) {
             const zd mu1 = t2 + disc, mu2 = t2 - disc;
             mu = (cabs(mu1 - d) <= cabs(mu2 - d)) ? mu1 : mu2;
         }
-        for (int k = l; k < ihi; ++k) {
+        // start row, as in LAPACK's complex QR: the lowest ks in (l, ihi) where
+        // a sweep begun with the shift at row ks leaves H[ks][ks-1] negligible
+        // (its fill-in is dropped).  On a graded H — B_Q once the filter has
+        // suppressed part of the subspace — the sweep then stays in the small
+        // trailing block instead of mixing rounding errors of the large block
+        // into it, which would keep it from ever deflating.
+        if (tid == 0) lst = l;
+        __syncthreads();
+        for (int M = l + 1 + tid; M < ihi; M += ENT) {
+            const zd h11 = H[(long)M * m + M], h22 = H[(long)(M + 1) * m + M + 1];
+            const double a11 = cabs1(h11 - mu), a21 = cabs1(H[(long)(M + 1) * m + M]);
+            const double sc = a11 + a21;                      // > 0: H[M+1][M] did not deflate
+            const double h10 = cabs1(H[(long)M * m + M - 1]);
+            if (h10 * (a21 / sc) <= ulp * ((a11 / sc) * (cabs1(h11) + cabs1(h22)))) atomicMax(&lst, M);
+        }
+        __syncthreads();
+        const int ks = lst;
+        for (int k = ks; k < ihi; ++k) {
             zd x, y;
-            if (k == l) { x = H[(long)l * m + l] - mu; y = H[(long)(l + 1) * m + l]; }
+            if (k == ks) { x = H[(long)ks * m + ks] - mu; y = H[(long)(ks + 1) * m + ks]; }
             else { x = H[(long)k * m + k - 1]; y = H[(long)(k + 1) * m + k - 1]; }
             double c; zd s, r;
             givens(x, y, c, s, r);
             __syncthreads();
-            const int j0 = (k == l) ? l : k - 1;
+            const int j0 = (k == ks) ? ks : k - 1;
             for (int j = j0 + tid; j < m; j += ENT) {
                 const zd h1 = H[(long)k * m + j], h2 = H[(long)(k + 1) * m + j];
                 zd n1 = c * h1; cfma(n1, s, h2);
@@ -143,7 +160,10 @@ __device__ int schur_qr(int m, zd* H, zd* Z) {
                 H[(long)(k + 1) * m + j] = n2;
             }
             __syncthreads();
-            if (k > l && tid == 0) { H[(long)k * m + k - 1] = r; H[(long)(k + 1) * m + k - 1] = czero<double>(); }
+            if (tid == 0) {
+                if (k > ks) { H[(long)k * m + k - 1] = r; H[(long)(k + 1) * m + k - 1] = czero<double>(); }
+                else if (ks > l) H[(long)ks * m + ks - 1] = c * H[(long)ks * m + ks - 1];   // fill-in below: dropped
+            }
             const int iend = min(k + 2, ihi);
             for (int i = tid; i < (iend + 1) + m; i += ENT) {
                 zd* R = (i <= iend) ? (H + (long)i * m) : (Z + (long)(i - iend - 1) * m);

@@ -191,3 +191,26 @@ def test_bad_shapes_rejected(handle):
     import ctypes as C
     rc = fh.lib().fh_filter(handle._h, prob._p, 4, None, None, 0, None, None, None, None, None, None)
     assert rc == -4
+
+
+def test_biortho_factors_graded_bq(handle):
+    """B_Q of a subspace whose last 24 of 64 directions are suppressed to
+    1e-9..1e-14 of the others (what the contour filter does to the directions
+    beyond m when m0 is much larger): 40 eigenvalues of order one and 24 at
+    or below rounding level.  The eigendecomposition succeeds, the resize
+    keeps the 40, and the kept factors bi-orthonormalize B_Q."""
+    rng = np.random.default_rng(5)
+    n, m, k = 400, 64, 40
+    scale = np.ones(m)
+    scale[k:] = 10.0 ** -rng.uniform(9.0, 14.0, m - k)
+    Q = W.subspace(n, m, 31) * scale
+    Qh = W.subspace(n, m, 32) * scale
+    BQ = Qh.conj().T @ Q
+    g = np.sort(np.abs(np.linalg.eigvals(BQ)))[::-1]
+    assert g[k - 1] > 1e-3 * g[0] and g[k] < 1e-14 * g[0]
+    gam, S, Sh, mt = fh.biortho_factors(handle, _cuda(BQ), 1e-12)
+    assert mt == k
+    gam = gam.cpu().numpy()
+    np.testing.assert_allclose(np.abs(gam[:k]), g[:k], rtol=1e-9)
+    S, Sh = S.cpu().numpy()[:, :mt], Sh.cpu().numpy()[:, :mt]
+    np.testing.assert_allclose(Sh.conj().T @ BQ @ S, np.eye(mt), atol=1e-9)

@@ -283,6 +283,29 @@ def test_filter_sparse_sym_parity(handle, precision):
     assert np.array_equal(Qh, np.conj(Q))
 
 
+def test_feast_general_full_size_graded_bq(handle):
+    """Regression: the general algorithm on the complex-symmetric operator at
+    full size (256 x 256 grid), circle around its 40 lowest eigenvalues,
+    m0 = 64, left start block conj(Y0).  From the 5th iteration the filter has
+    suppressed the 24 spare directions to rounding level and B_Q is graded;
+    the QR iteration that diagonalizes it must start each sweep below a
+    negligible subdiagonal pair (else it exhausts its budget: status 7)."""
+    import scipy.sparse.linalg as spla
+    A = W.schrodinger2d_csr(256)
+    n = A["n"]
+    ev = spla.eigs(sp.csr_matrix((A["val"], A["colind"], A["rowptr"]), shape=(n, n)), k=48, sigma=-60.0,
+                   return_eigenvectors=False, tol=1e-10)
+    ev = ev[np.argsort(ev.real)]
+    c = 0.5 * (ev[0].real + ev[39].real)
+    r = 0.5 * (abs(ev[39] - c) + abs(ev[40] - c))
+    prob = fh.Problem(handle, _csr(A))
+    Y0 = W.subspace(n, 64, 7)
+    opts = fh.default_opts(64, solver=1, precond=2, restart=30, max_restarts=2, inner_tol=1e-3, precision=1,
+                           mixed_inner_tol=1e-3, max_refine=1, orth=2, max_iter=6, eps=1e-300)
+    out = fh.feast(prob, c, r, 1.0, 0.0, 16, _cuda(Y0), _cuda(np.conj(Y0)), opts)
+    assert out["info"] == 2 and out["report"]["iters"] == 6
+
+
 def test_sym_rejects_nonsymmetric_matrix(handle):
     """opts.sym = 1 on a matrix with A != A^T is an error (-2, the problem)."""
     p = _small_convdiff(N=12, m_in=4, m0=8)
