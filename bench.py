@@ -332,6 +332,17 @@ def csym(args):
         print(f"[bench] csym sym={sym}: {r_['ms_per_iteration']:.1f} ms/iteration; to eq:res <= {EPS_ITER:g}: "
               + (f"{r_['time_to_solution_s']:.2f} s, {r_['iterations']} iterations, m = {r_['m']}"
                  if "error" not in r_ else r_["error"]), file=sys.stderr, flush=True)
+    # eigenvalue-count estimate: 64 Rademacher probes, right solves only
+    zc, wc = fh.contour_nodes(target, r, 1.0, 0.0, ne)
+    V = torch.from_numpy(np.random.default_rng(13).choice([-1.0, 1.0], size=(n, m0)).astype(np.complex128)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    est, _ = fh.count_estimate(prob, zc, wc, V, opts(0, 1, EPS_ITER))
+    torch.cuda.synchronize()
+    count = {"estimate": est.real, "estimate_imag": est.imag, "probes": m0, "seconds": time.perf_counter() - t0,
+             "eigenvalues_found": res[1].get("m")}
+    print(f"[bench] csym count estimate: {est.real:.2f} (found {count['eigenvalues_found']}), "
+          f"{count['seconds']:.2f} s", file=sys.stderr, flush=True)
     la, lb = res[1].pop("lam"), res[0].pop("lam")
     same = len(la) == len(lb) and len(la) > 0
     dl = float(np.max(np.abs(la - lb)) / (abs(target) + r)) if same else None
@@ -344,7 +355,7 @@ def csym(args):
                                    "GMRES(30)x2 + ILU(0), c64 + FP64 refinement"},
             "sym": res[1], "general": res[0],
             "speedup_per_iteration": res[0]["ms_per_iteration"] / res[1]["ms_per_iteration"],
-            "same_eigenvalue_count": same, "max_dlam_over_alpha": dl}
+            "same_eigenvalue_count": same, "max_dlam_over_alpha": dl, "count_estimate": count}
     print(json.dumps(line))
 
 

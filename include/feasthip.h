@@ -233,6 +233,17 @@ int fh_profile_read(fh_handle h, int idx, char* name, int namelen, long long* co
 
 /* ---- components (exposed for parity tests of single steps) -------------- */
 
+/* Stochastic estimate of the number of eigenvalues inside the contour (the
+ * eigenvalue-count estimator the paper's section on the FEAST v3.0 software
+ * cites): the filter applied to p probe vectors, Q = sum_j w_j (z_j B - A)^{-1} B V
+ * (right solves only), and est = (1/p) trace(V^H Q) = (1/p) sum_k v_k^H Q e_k,
+ * which estimates trace(rho_a) = sum_i rho_a(lambda_i).  V: device n x p
+ * row-major complex (the probes: the caller draws them, e.g. Rademacher or
+ * Gaussian entries; V = I with p = n gives the exact trace).  1 <= p <= 256.
+ * est: host double[2] (real, imaginary part).  Returns FH_OK or -k. */
+int fh_count_estimate(fh_handle h, fh_problem p, int ne, const double* z, const double* w, int nprobe,
+                      const void* V, const fh_opts* o, double* est, fh_report* rep);
+
 /* Step 2.a: BQ (m x m, device, row-major) = Qh^H B Q. */
 int fh_reduced_matrix(fh_handle h, fh_problem p, int m, const void* Qh, const void* Q, void* BQ);
 

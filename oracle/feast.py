@@ -72,6 +72,17 @@ def contour_filter(A, B, z, w, Y, Yh, factors=None, counters=None):
     return Q, Qh
 
 
+def count_estimate(A, B, z, w, V):
+    """Stochastic estimate of the number of eigenvalues inside the contour
+    (the estimator FEAST v3.0 ships, cited in the paper's section on the
+    software): the trace of the filter rho_a(B^{-1}A) = sum_j w_j (z_j B - A)^{-1} B,
+    whose eigenvalues are rho_a(lambda_i) (about 1 inside, 0 outside),
+    estimated with the probe block V (n x p): (1/p) trace(V^H rho_a V).
+    Returns a complex number."""
+    Q, _ = contour_filter(A, B, z, w, V, V)
+    return np.trace(V.conj().T @ Q) / V.shape[1]
+
+
 # --------------------------------------------------------------------------
 # Steps 2-5 for one iteration
 # --------------------------------------------------------------------------

@@ -93,6 +93,7 @@ def lib():
                          C.POINTER(fh_report)]),
         "fh_reduced_matrix": (i, [vp, vp, i, vp, vp, vp]),
         "fh_biortho_factors": (i, [vp, i, vp, d, vp, vp, vp, ip]),
+        "fh_count_estimate": (i, [vp, vp, i, dp, dp, i, vp, vp, dp, vp]),
         "fh_reduced_eig": (i, [vp, i, vp, vp, vp, vp, vp]),
         "fh_shifted_apply": (i, [vp, vp, i, i, dp, i, vp, vp]),
         "fh_ilu0": (i, [vp, vp, d, d, vp]),
@@ -287,6 +288,23 @@ def contour_filter(prob: Problem, z, w, Y, Yh, opts: fh_opts | None = None):
                          C.byref(opts) if opts is not None else None, C.byref(rep))
     prob.handle.check(rc, "fh_filter")
     return Q, Qh, rep.as_dict()
+
+
+def count_estimate(prob: Problem, z, w, V, opts: fh_opts | None = None):
+    """Stochastic estimate of the number of eigenvalues inside the contour:
+    (1/p) trace(V^H Q) with Q the filter applied to the probe block V (n x p,
+    complex128 CUDA).  Returns (estimate as a complex number, report)."""
+    n = prob.n
+    _check_block(V, n, "V")
+    zk, zp = _cbuf(z)
+    wk, wp = _cbuf(w)
+    est = np.zeros(2)
+    rep = fh_report()
+    rc = lib().fh_count_estimate(prob.handle._h, prob._p, len(zk), zp, wp, V.shape[1], _dptr(V),
+                                 C.byref(opts) if opts is not None else None,
+                                 est.ctypes.data_as(C.POINTER(C.c_double)), C.byref(rep))
+    prob.handle.check(rc, "fh_count_estimate")
+    return complex(est[0], est[1]), rep.as_dict()
 
 
 def feast(prob: Problem, center, a, ratio=1.0, angle=0.0, ne=8, Y0=None, Yh0=None, opts: fh_opts | None = None,

@@ -254,6 +254,51 @@ int fh_feast(fh_handle h, fh_problem p, const fh_contour* c, const double* z, co
     FH_API_END(h)
 }
 
+int fh_count_estimate(fh_handle h, fh_problem p, int ne, const double* z, const double* w, int nprobe,
+                      const void* V, const fh_opts* o, double* est, fh_report* rep) {
+    if (!h) return -1;
+    if (!p) return -2;
+    if (ne < 1) return -3;
+    if (!z) return -4;
+    if (!w) return -5;
+    if (nprobe < 1 || nprobe > 256 || nprobe > p->n) return -6;
+    if (!V) return -7;
+    if (!est) return -9;
+    fh_opts def;
+    fh_default_opts(&def);
+    def.m0 = nprobe;
+    if (!o) { o = &def; if (!p->dense) def.solver = FH_SOLVER_BGMRES; }
+    FH_API_BEGIN(h)
+    set_device(h);
+    fh_report local{};
+    fh_report* r = rep ? rep : &local;
+    std::memset(r, 0, sizeof(*r));
+    const size_t blk = (size_t)p->n * nprobe;
+    DBuf qb, hb, cb;
+    zd* Q = (zd*)qb.ensure(sizeof(zd) * blk);
+    // sparse problems: right solves only (no left block); dense: the filter's
+    // left half runs on the probes too and is discarded
+    zd* Qh = p->dense ? (zd*)hb.ensure(sizeof(zd) * blk) : nullptr;
+    const zd* Yh = p->dense ? (const zd*)V : nullptr;
+    filter(*h, *p, ne, reinterpret_cast<const cplx*>(z), reinterpret_cast<const cplx*>(w), nprobe, (const zd*)V, Yh,
+           Q, Qh, *o, r);
+    zd* C = (zd*)cb.ensure(sizeof(zd) * (size_t)nprobe * nprobe);
+    gemm_hn_tall(h->stream, p->n, nprobe, nprobe, (const zd*)V, nprobe, Q, nprobe, C, nprobe, h->partial);
+    std::vector<zd> hc((size_t)nprobe * nprobe);
+    FH_HIP(hipMemcpyAsync(hc.data(), C, sizeof(zd) * hc.size(), hipMemcpyDeviceToHost, h->stream));
+    FH_HIP(hipStreamSynchronize(h->stream));
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < nprobe; ++k) {
+        re += hc[(size_t)k * nprobe + k].re;
+        im += hc[(size_t)k * nprobe + k].im;
+    }
+    est[0] = re / nprobe;
+    est[1] = im / nprobe;
+    r->info = FH_OK;
+    return FH_OK;
+    FH_API_END(h)
+}
+
 int fh_reduced_matrix(fh_handle h, fh_problem p, int m, const void* Qh, const void* Q, void* BQ) {
     if (!h) return -1;
     if (!p) return -2;

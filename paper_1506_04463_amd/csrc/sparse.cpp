@@ -712,6 +712,9 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
     // only the right systems are solved
     const bool sym = o.sym == 1;
     FH_REQUIRE(!sym || S.csym, -2, "opts.sym = 1 needs a complex symmetric matrix (A = A^T)");
+    // right systems only: complex symmetric problems, and callers without a
+    // left block (the eigenvalue-count estimate)
+    const bool right_only = sym || Yh == nullptr;
     hipStream_t st = c.stream;
     const int n = S.n;
     const long blk = (long)n * m;
@@ -728,7 +731,7 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
         lamd = ld + 2 * m;
         FH_HIP(hipMemcpyAsync(lamd, lam, sizeof(zd) * m, hipMemcpyHostToDevice, st));
         ritz_residual(st, S.A, false, n, m, lamd, false, Y, T);           // R  = A Y - Y Lambda
-        if (!sym) ritz_residual(st, S.AT, true, n, m, lamd, true, Yh, T + blk);   // Rh = A^H Yh - Yh Lambda^*
+        if (!right_only) ritz_residual(st, S.AT, true, n, m, lamd, true, Yh, T + blk);   // Rh = A^H Yh - Yh Lambda^*
         for (int i = 0; i < m; ++i) {
             cplx r = 0.0;
             for (int j = 0; j < ne; ++j) {
@@ -758,11 +761,11 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
     const zd* Rl = lam ? T + blk : Yh;
     SolveStats s;
     // nodes [j0, j1) at a time: their right and left systems in one batch
-    const int sides = sym ? 1 : 2;
+    const int sides = right_only ? 1 : 2;
     for (int j0 = 0; j0 < ne; j0 += g) {
         const int j1 = std::min(ne, j0 + g), gc = j1 - j0;
         replicate<double>(st, blk, Rr, Bb, gc);
-        if (!sym) replicate<double>(st, blk, Rl, Bb + gc * blk, gc);
+        if (!right_only) replicate<double>(st, blk, Rl, Bb + gc * blk, gc);
         std::vector<int> node_of(sides * gc);
         std::vector<cplx> zsys(sides * gc);
         for (int q = 0; q < sides * gc; ++q) { node_of[q] = j0 + q % gc; zsys[q] = z[j0 + q % gc]; }
@@ -774,11 +777,11 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
         const bool first = j0 == 0;
         filter_accum(st, gc, n, m, Xb, cd + (size_t)j0 * m, (lam && first) ? Y : nullptr, first ? rd : nullptr, Q,
                      !first);
-        if (!sym)
+        if (!right_only)
             filter_accum(st, gc, n, m, Xb + gc * blk, cd + (size_t)(ne + j0) * m, (lam && first) ? Yh : nullptr,
                          (first && rd) ? rd + m : nullptr, Qh, !first);
     }
-    if (sym) conj_copy(st, blk, Q, Qh);                                   // Qh = conj(Q)
+    if (sym && Qh) conj_copy(st, blk, Q, Qh);                             // Qh = conj(Q)
     FH_HIP(hipStreamSynchronize(st));
     if (rep) {
         rep->n_fallback += s.fallback ? sides * ne : 0;

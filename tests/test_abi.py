@@ -67,6 +67,7 @@ def test_net_and_solve_arguments_are_rejected():
     L = fh.lib()
     assert L.fh_shifted_solve(None, None, 1, None, None, 1, None, None, None, None) == -1
     assert L.fh_ilu0_apply_c64(None, None, 0.0, 0.0, 0, 1, None, None) == -1
+    assert L.fh_count_estimate(None, None, 8, None, None, 4, None, None, None, None) == -1
     assert L.fh_net_create(None, 1, 4, 4, 0, None, 1.0, 1.0, 0, None) == -1
     assert L.fh_net_destroy(None) == -1
     assert L.fh_net_param_count(None) == -1

@@ -214,3 +214,15 @@ def test_biortho_factors_graded_bq(handle):
     np.testing.assert_allclose(np.abs(gam[:k]), g[:k], rtol=1e-9)
     S, Sh = S.cpu().numpy()[:, :mt], Sh.cpu().numpy()[:, :mt]
     np.testing.assert_allclose(Sh.conj().T @ BQ @ S, np.eye(mt), atol=1e-9)
+
+
+def test_count_estimate_dense_exact_trace(handle):
+    """Dense problem, identity probes (p = n): the estimate is trace(rho_a) / n,
+    the closed-form filter summed over the prescribed eigenvalues."""
+    p = W.dense_prescribed(n=96, n_in=7, center=0.1 + 0.1j, radius=0.25, m0=12, seed=4)
+    c, r, ne = p.contour.center, p.contour.a, 16
+    z, w = ct.ellipse_nodes(c, r, 1.0, 0.0, ne)
+    exact = np.sum(1.0 / (1.0 + ((p.info["lam"] - c) / r) ** ne))
+    prob = fh.Problem(handle, _cuda(p.A))
+    est, rep = fh.count_estimate(prob, z, w, _cuda(np.eye(p.n, dtype=np.complex128)))
+    assert abs(est * p.n - exact) < 1e-9 * p.n

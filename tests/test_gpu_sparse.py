@@ -306,6 +306,48 @@ def test_feast_general_full_size_graded_bq(handle):
     assert out["info"] == 2 and out["report"]["iters"] == 6
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_count_estimate_sparse_parity(handle, precision):
+    """Eigenvalue-count estimate (right solves only) against the oracle's with
+    the same Rademacher probes.  On this strongly non-normal operator the
+    estimator's spread is huge (64 probes: about -757 for 8 eigenvalues), so
+    only parity is checked; the bound scales with the probes' products."""
+    p = _small_convdiff()
+    z, w = ct.ellipse_nodes(p.contour.center, p.contour.a, p.contour.ratio, 0.0, 16)
+    rng = np.random.default_rng(2)
+    V = rng.choice([-1.0, 1.0], size=(p.n, 64)).astype(np.complex128)
+    ref = F.count_estimate(L.csr_matrix(p.A), None, z, w, V)
+    Qo, _ = F.contour_filter(L.csr_matrix(p.A), None, z, w, V, V)
+    scale = np.sum(np.abs(np.conj(V) * Qo)) / V.shape[1]
+    prob = fh.Problem(handle, _csr(p.A))
+    opts = fh.default_opts(64, solver=1, precond=2, inner_tol=1e-12, restart=30, max_restarts=400,
+                           precision=precision, mixed_inner_tol=1e-5, max_refine=30)
+    est, rep = fh.count_estimate(prob, z, w, _cuda(V), opts)
+    assert rep["n_solve"] == 16
+    Ad = W.csr_to_dense(p.A)
+    kap = max(np.linalg.cond(zj * np.eye(p.n) - Ad) for zj in z)
+    assert abs(est - ref) < 10 * kap * max(rep["inner_relres"], 1e-14) * scale
+
+
+def test_count_estimate_complex_symmetric(handle):
+    """On a near-normal (complex-symmetric) operator 64 probes land near the
+    count: exact trace 8.003 (8 eigenvalues inside), oracle estimate 7.77."""
+    A = W.schrodinger2d_csr(16, L=10.0, nwells=6, seed=4)
+    ev = sla.eigvals(W.csr_to_dense(A))
+    c = ev[np.argsort(np.abs(ev - (np.median(ev.real[:40]) - 0.5j)))[0]]
+    d = np.sort(np.abs(ev - c))
+    r = 0.5 * (d[7] + d[8])
+    z, w = ct.ellipse_nodes(c, r, 1.0, 0.0, 16)
+    rng = np.random.default_rng(2)
+    V = rng.choice([-1.0, 1.0], size=(A["n"], 64)).astype(np.complex128)
+    ref = F.count_estimate(L.csr_matrix(A), None, z, w, V)
+    prob = fh.Problem(handle, _csr(A))
+    opts = fh.default_opts(64, solver=1, precond=2, inner_tol=1e-12, restart=30, max_restarts=400)
+    est, rep = fh.count_estimate(prob, z, w, _cuda(V), opts)
+    assert abs(est - ref) < 1e-8 * abs(ref)
+    assert abs(est - 8.0) < 1.0
+
+
 def test_sym_rejects_nonsymmetric_matrix(handle):
     """opts.sym = 1 on a matrix with A != A^T is an error (-2, the problem)."""
     p = _small_convdiff(N=12, m_in=4, m0=8)

@@ -273,3 +273,23 @@ def test_complex_symmetric_left_filter_is_conjugate():
     # a general left block breaks the identity (the check has teeth)
     Q2, Qh2 = F.contour_filter(Asp, None, z, w, Y, W.subspace(A["n"], 8, 4))
     assert np.linalg.norm(Qh2 - np.conj(Q2)) > 1e-3 * np.linalg.norm(Q2)
+
+
+def test_count_estimate_exact_trace_and_probes():
+    """The eigenvalue-count estimator: with the identity as probe block (p = n)
+    it is exactly trace(rho_a) / n, and for the trapezoid circle rho_a has the
+    closed form 1 / (1 + ((lambda - c) / r)^Ne), summed over the prescribed
+    eigenvalues; with 400 Rademacher probes it lands near that trace (the
+    estimator's spread here is well below 1)."""
+    p = W.dense_prescribed(n=160, n_in=9, center=0.1 + 0.1j, radius=0.25, m0=12, seed=3)
+    c, r, ne = p.contour.center, p.contour.a, 16
+    z, w = ct.ellipse_nodes(c, r, 1.0, 0.0, ne)
+    lam = p.info["lam"]
+    exact = np.sum(1.0 / (1.0 + ((lam - c) / r) ** ne))
+    assert 6.0 < exact.real < 12.0          # 9 inside, partly weighted near the circle
+    est = F.count_estimate(p.A, None, z, w, np.eye(p.n, dtype=np.complex128)) * p.n
+    assert abs(est - exact) < 1e-9 * p.n
+    rng = np.random.default_rng(11)
+    V = rng.choice([-1.0, 1.0], size=(p.n, 400)).astype(np.complex128)
+    est_r = F.count_estimate(p.A, None, z, w, V)
+    assert abs(est_r - exact) < 1.5
