@@ -74,13 +74,21 @@ typedef struct {
 } fh_mat;
 
 /* Search contour: ellipse z(t) = c + e^{i angle} (a cos t + i ratio*a sin t).
- * Paper Section 2.1 (complex midpoint, radius, axis ratio, rotation angle). */
+ * Paper Section 2.1 (complex midpoint, radius, axis ratio, rotation angle).
+ * Or, with nv >= 3, a polygon (the paper's custom contours, e.g. the squares
+ * of its multi-contour experiment): vertices verts (host, nv complex values,
+ * either orientation, not self-intersecting), ne / nv trapezoid intervals on
+ * each side (ne a multiple of nv; 16 nodes = 4 per side of a square), the
+ * inside test (step 5.a) point-in-polygon, alpha of eq:res |g| + max_k
+ * |v_k - g| with g the mean of the vertices; c_re .. angle are then unused. */
 typedef struct {
     double c_re, c_im;    /* centre lambda_mid                                */
     double a;             /* horizontal semi-axis (radius for a circle)       */
     double ratio;         /* vertical / horizontal semi-axis (1 = circle)     */
     double angle;         /* rotation in radians                              */
     int ne;               /* number of quadrature nodes                       */
+    int nv;               /* polygon: number of vertices (0 = the ellipse)    */
+    const double* verts;  /* polygon: nv complex vertices (re, im pairs)      */
 } fh_contour;
 
 typedef struct {

@@ -56,3 +56,57 @@ def inside_ellipse(lam, center, a, ratio=1.0, angle=0.0):
 def alpha(center, a, ratio=1.0):
     """Scale of eq:res: |lambda_mid| + r for a circle; |c| + max semi-axis here."""
     return abs(complex(center)) + max(a, ratio * a)
+
+
+# --------------------------------------------------------------------------
+# Polygon contours (the paper's custom contours, e.g. the squares of its
+# multi-contour experiment with 4 trapezoidal intervals per side)
+# --------------------------------------------------------------------------
+def _ccw(verts):
+    """Vertices in counterclockwise order (shoelace signed area)."""
+    v = np.asarray(verts, dtype=np.complex128).reshape(-1)
+    area2 = np.sum(v.real * np.roll(v, -1).imag - np.roll(v, -1).real * v.imag)
+    return v if area2 >= 0 else v[::-1].copy()
+
+
+def polygon_nodes(verts, ne):
+    """Composite trapezoid rule for (1/2 pi i) \oint f(z) dz along the polygon,
+    ne / nv intervals per side, nodes at the interval ends.  On side k from
+    v_k to v_{k+1} with step h_k = (v_{k+1} - v_k) / p the interval ends are
+    v_k + q h_k (q = 0 .. p-1; q = p is the next side's first node); an
+    interior end gets h_k / (2 pi i), a vertex (h_{k-1} + h_k) / (2 (2 pi i))."""
+    v = _ccw(verts)
+    nv = len(v)
+    assert ne % nv == 0 and ne >= nv
+    per = ne // nv
+    z, w = [], []
+    for k in range(nv):
+        h = (v[(k + 1) % nv] - v[k]) / per
+        hprev = (v[k] - v[k - 1]) / per
+        for q in range(per):
+            z.append(v[k] + q * h)
+            w.append(((hprev + h) / 2 if q == 0 else h) / (2j * np.pi))
+    return np.array(z, dtype=np.complex128), np.array(w, dtype=np.complex128)
+
+
+def inside_polygon(lam, verts):
+    """Strict inside test by the winding number of the closed polygon around
+    lam (sum of the signed angles its sides subtend); non-finite: outside."""
+    lam = np.atleast_1d(np.asarray(lam, dtype=np.complex128))
+    v = np.asarray(verts, dtype=np.complex128).reshape(-1)
+    out = np.zeros(lam.shape, dtype=bool)
+    for i, x in enumerate(lam):
+        if not (np.isfinite(x.real) and np.isfinite(x.imag)):
+            continue
+        a = v - x
+        b = np.roll(v, -1) - x
+        wind = np.sum(np.angle(b / a)) / (2 * np.pi)
+        out[i] = abs(round(wind)) == 1
+    return out
+
+
+def polygon_alpha(verts):
+    """Scale of eq:res for a polygon: |g| + max_k |v_k - g|, g the mean vertex."""
+    v = np.asarray(verts, dtype=np.complex128).reshape(-1)
+    g = v.mean()
+    return abs(g) + np.max(np.abs(v - g))

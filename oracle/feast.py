@@ -162,6 +162,23 @@ class Contour:
         return ct.alpha(self.center, self.a, self.ratio)
 
 
+@dataclass
+class PolygonContour:
+    """A polygon search contour (custom contour): vertices, ne nodes (ne / nv
+    trapezoid intervals per side)."""
+    verts: np.ndarray
+    ne: int = 16
+
+    def nodes(self):
+        return ct.polygon_nodes(self.verts, self.ne)
+
+    def inside(self, lam):
+        return ct.inside_polygon(lam, self.verts)
+
+    def alpha(self):
+        return ct.polygon_alpha(self.verts)
+
+
 def feast_iteration(A, B, z, w, cont: Contour, Y, Yh, rho_prev=None, factors=None, eps=1e-12,
                     counters=None, it=1):
     """One pass of steps 1-5 from the current subspaces (Y, Yh)."""

@@ -43,7 +43,18 @@ class fh_mat(C.Structure):
 
 class fh_contour(C.Structure):
     _fields_ = [("c_re", C.c_double), ("c_im", C.c_double), ("a", C.c_double), ("ratio", C.c_double),
-                ("angle", C.c_double), ("ne", C.c_int)]
+                ("angle", C.c_double), ("ne", C.c_int), ("nv", C.c_int), ("verts", C.c_void_p)]
+
+
+def _polygon(c: "fh_contour", polygon):
+    """Set the polygon fields of c; returns the vertex buffer (keep it alive
+    for the call)."""
+    if polygon is None:
+        return None
+    v = np.ascontiguousarray(np.asarray(polygon, dtype=np.complex128).reshape(-1))
+    c.nv = len(v)
+    c.verts = v.ctypes.data_as(C.c_void_p)
+    return v
 
 
 class fh_opts(C.Structure):
@@ -250,8 +261,11 @@ def default_opts(m0, **kw) -> fh_opts:
     return o
 
 
-def contour_nodes(center, a, ratio=1.0, angle=0.0, ne=8):
+def contour_nodes(center, a, ratio=1.0, angle=0.0, ne=8, polygon=None):
+    """Nodes and weights of the ellipse, or of the polygon with the vertices
+    `polygon` (ne / len(polygon) trapezoid intervals per side)."""
     c = fh_contour(complex(center).real, complex(center).imag, a, ratio, angle, ne)
+    keep = _polygon(c, polygon)
     z = np.zeros(ne, np.complex128)
     w = np.zeros(ne, np.complex128)
     rc = lib().fh_contour_nodes(C.byref(c), z.ctypes.data_as(C.POINTER(C.c_double)),
@@ -308,10 +322,11 @@ def count_estimate(prob: Problem, z, w, V, opts: fh_opts | None = None):
 
 
 def feast(prob: Problem, center, a, ratio=1.0, angle=0.0, ne=8, Y0=None, Yh0=None, opts: fh_opts | None = None,
-          z=None, w=None, ritz0=None):
+          z=None, w=None, ritz0=None, polygon=None):
     """Non-Hermitian FEAST; returns dict(info, lam, X, Xh, res, report, and the
     whole final subspace Y, Yh, ritz, ritz_res).  ritz0 (with opts.resume = 1):
-    Ritz values of the start columns."""
+    Ritz values of the start columns.  polygon: complex vertices of a polygon
+    contour (then center .. angle are unused)."""
     torch = _torch()
     n = prob.n
     _check_block(Y0, n, "Y0")
@@ -326,6 +341,7 @@ def feast(prob: Problem, center, a, ratio=1.0, angle=0.0, ne=8, Y0=None, Yh0=Non
         lam.copy_(ritz0.reshape(-1)[:m0] if isinstance(ritz0, torch.Tensor) else torch.from_numpy(np.asarray(ritz0)))
     res = np.zeros(m0)
     c = fh_contour(complex(center).real, complex(center).imag, a, ratio, angle, ne)
+    keep = _polygon(c, polygon)
     zp = wp = None
     if z is not None:
         zk, zp = _cbuf(z)

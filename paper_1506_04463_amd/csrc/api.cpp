@@ -124,11 +124,19 @@ int fh_set_stream(fh_handle h, void* stream) {
 
 const char* fh_last_error(fh_handle h) { return h ? h->err.c_str() : "null handle"; }
 
+// an ellipse with positive axes, or a polygon of nv >= 3 vertices whose node
+// count is a positive multiple of nv
+static bool contour_ok(const fh_contour& c) {
+    if (c.ne < 1) return false;
+    if (c.nv == 0) return c.a > 0 && c.ratio > 0;
+    return c.nv >= 3 && c.verts != nullptr && c.ne % c.nv == 0;
+}
+
 int fh_contour_nodes(const fh_contour* c, double* z, double* w) {
     if (!c) return -1;
     if (!z) return -2;
     if (!w) return -3;
-    if (c->ne < 1 || !(c->a > 0) || !(c->ratio > 0)) return -1;
+    if (!contour_ok(*c)) return -1;
     std::vector<cplx> zz, ww;
     contour_nodes(*c, zz, ww);
     std::memcpy(z, zz.data(), sizeof(cplx) * c->ne);
@@ -235,7 +243,7 @@ int fh_feast(fh_handle h, fh_problem p, const fh_contour* c, const double* z, co
              void* Y, void* Yh, void* lambda, double* res, fh_report* rep) {
     if (!h) return -1;
     if (!p) return -2;
-    if (!c || c->ne < 1 || !(c->a > 0) || !(c->ratio > 0)) return -3;
+    if (!c || !contour_ok(*c)) return -3;
     if ((z == nullptr) != (w == nullptr)) return -4;
     if (!o) return -6;
     if (o->m0 < 1 || o->m0 > p->n || o->m0 > 1024 || o->max_iter < 1 || !(o->eps > 0)) return -6;
@@ -451,7 +459,7 @@ int fh_feast_batched(fh_handle h, int count, const fh_problem* problems, const f
     for (int i = 0; i < count; ++i) {
         if (!problems[i] || !problems[i]->dense || o->m0 > problems[i]->n) return -3;
         const fh_contour& c = contours[i];
-        if (c.ne < 1 || !(c.a > 0) || !(c.ratio > 0)) return -4;
+        if (!contour_ok(c)) return -4;
         if (!Y[i]) return -6;
         if (!Yh[i]) return -7;
         if (!lambda[i]) return -8;

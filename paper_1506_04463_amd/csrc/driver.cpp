@@ -19,7 +19,13 @@ static const double PI = 3.14159265358979323846;
 
 // Trapezoidal rule on z(t) = c + e^{i phi}(a cos t + i b sin t), t_j = 2 pi (j - 1/2)/ne,
 // w_j = z'(t_j)/(i ne)  (Sections 1 and 2.1; eq:rational)
+static void polygon_nodes(const fh_contour& ct, std::vector<cplx>& z, std::vector<cplx>& w);
+
 void contour_nodes(const fh_contour& ct, std::vector<cplx>& z, std::vector<cplx>& w) {
+    if (ct.nv >= 3) {
+        polygon_nodes(ct, z, w);
+        return;
+    }
     const int ne = ct.ne;
     z.resize(ne);
     w.resize(ne);
@@ -33,8 +39,61 @@ void contour_nodes(const fh_contour& ct, std::vector<cplx>& z, std::vector<cplx>
     }
 }
 
+// polygon: composite trapezoid rule on each side (ne / nv intervals), nodes
+// at the interval ends; the weight of a node is (h_prev + h_next) / (2 * 2 pi i)
+// with h the complex interval steps beside it, counterclockwise orientation
+static void polygon_nodes(const fh_contour& ct, std::vector<cplx>& z, std::vector<cplx>& w) {
+    const int nv = ct.nv, per = ct.ne / nv;
+    std::vector<cplx> v(nv);
+    double area2 = 0.0;
+    for (int k = 0; k < nv; ++k) v[k] = cplx(ct.verts[2 * k], ct.verts[2 * k + 1]);
+    for (int k = 0; k < nv; ++k) {
+        const cplx a = v[k], b = v[(k + 1) % nv];
+        area2 += a.real() * b.imag() - b.real() * a.imag();
+    }
+    if (area2 < 0.0) std::reverse(v.begin(), v.end());
+    const cplx twopii(0.0, 2.0 * PI);
+    z.clear();
+    w.clear();
+    for (int k = 0; k < nv; ++k) {
+        const cplx h = (v[(k + 1) % nv] - v[k]) / double(per);
+        const cplx hp = (v[k] - v[(k + nv - 1) % nv]) / double(per);
+        for (int q = 0; q < per; ++q) {
+            z.push_back(v[k] + double(q) * h);
+            w.push_back((q == 0 ? 0.5 * (hp + h) : h) / twopii);
+        }
+    }
+}
+
+static cplx polygon_centroid(const fh_contour& ct) {
+    cplx g = 0.0;
+    for (int k = 0; k < ct.nv; ++k) g += cplx(ct.verts[2 * k], ct.verts[2 * k + 1]);
+    return g / double(ct.nv);
+}
+
+double contour_alpha(const fh_contour& ct) {
+    if (ct.nv >= 3) {
+        const cplx g = polygon_centroid(ct);
+        double r = 0.0;
+        for (int k = 0; k < ct.nv; ++k) r = std::max(r, std::abs(cplx(ct.verts[2 * k], ct.verts[2 * k + 1]) - g));
+        return std::abs(g) + r;
+    }
+    return std::abs(cplx(ct.c_re, ct.c_im)) + std::max(ct.a, ct.ratio * ct.a);
+}
+
 static bool inside_contour(const fh_contour& ct, cplx lam) {
     if (!std::isfinite(lam.real()) || !std::isfinite(lam.imag())) return false;
+    if (ct.nv >= 3) {                                 // even-odd ray casting along +Re
+        bool in = false;
+        for (int k = 0, l = ct.nv - 1; k < ct.nv; l = k++) {
+            const double xk = ct.verts[2 * k], yk = ct.verts[2 * k + 1];
+            const double xl = ct.verts[2 * l], yl = ct.verts[2 * l + 1];
+            if ((yk > lam.imag()) != (yl > lam.imag()) &&
+                lam.real() < xk + (lam.imag() - yk) * (xl - xk) / (yl - yk))
+                in = !in;
+        }
+        return in;
+    }
     const cplx u = (lam - cplx(ct.c_re, ct.c_im)) * std::polar(1.0, -ct.angle);
     const double a = ct.a, b = ct.ratio * ct.a;
     const double q = (u.real() / a) * (u.real() / a) + (u.imag() / b) * (u.imag() / b);
@@ -208,7 +267,7 @@ struct FeastRun {
         ne = ct.ne;
         if (zin) { z.assign(zin, zin + ne); w.assign(win, win + ne); }
         else contour_nodes(ct, z, w);
-        alpha = std::abs(cplx(ct.c_re, ct.c_im)) + std::max(ct.a, ct.ratio * ct.a);
+        alpha = contour_alpha(ct);
         const size_t big = (size_t)n * m0in, sm = (size_t)m0in * m0in;
         Ycur = (zd*)B.Ycur.ensure(sizeof(zd) * big);
         Yhcur = (zd*)B.Yhcur.ensure(sizeof(zd) * big);

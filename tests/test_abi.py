@@ -15,7 +15,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "feasthip.h")).read()
+    with open(os.path.join(ROOT, "include", "feasthip.h")) as f:
+        src = f.read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(fh_[a-z0-9_]+)\s*\(", src)))
 
@@ -76,3 +77,18 @@ def test_net_and_solve_arguments_are_rejected():
     assert L.fh_net_forward(None, None, 1, 1, None, None, None, None) == -1
     assert L.fh_net_train_step(None, None, None, 1, 1, None, None, None, None, 1e-3, 1, None, None) == -1
     assert L.fh_problem_set_net(None, None) == -1
+
+
+@pytest.mark.parametrize("verts,ne", [(np.array([-1 - 1j, 1 - 1j, 1 + 1j, -1 + 1j]), 16),
+                                      (np.array([0, 2, 2 + 1j, 1 + 1j, 1 + 2j, 2j]), 18)])
+def test_polygon_nodes_match_oracle(verts, ne):
+    """Polygon contours (both orientations): the library's nodes and weights
+    equal the oracle's; a node count that is not a multiple of the vertex
+    count is rejected."""
+    for v in (verts, verts[::-1]):
+        z, w = fh.contour_nodes(0.0, 1.0, 1.0, 0.0, ne, polygon=v)
+        zo, wo = ct.polygon_nodes(v, ne)
+        np.testing.assert_allclose(z, zo, atol=1e-15)
+        np.testing.assert_allclose(w, wo, atol=1e-16)
+    with pytest.raises(fh.FeastError):
+        fh.contour_nodes(0.0, 1.0, 1.0, 0.0, ne + 1, polygon=verts)

@@ -226,3 +226,25 @@ def test_count_estimate_dense_exact_trace(handle):
     prob = fh.Problem(handle, _cuda(p.A))
     est, rep = fh.count_estimate(prob, z, w, _cuda(np.eye(p.n, dtype=np.complex128)))
     assert abs(est * p.n - exact) < 1e-9 * p.n
+
+
+def test_feast_polygon_contour_matches_oracle(handle):
+    """FEAST with a square contour (4 trapezoid intervals per side, 16 nodes,
+    as in the paper's multi-contour experiment): the polygon's nodes, inside
+    test and alpha, against the oracle with the same polygon."""
+    p = W.dense_prescribed(n=200, n_in=12, center=0.1 + 0.1j, radius=0.25, m0=24, seed=7)
+    # half-side in the widest gap of the eigenvalues' max-norm distance from the
+    # centre (ratio 1.17): 7 inside, none within a few percent of the edges
+    c, h = 0.1 + 0.1j, 0.1832
+    sq = np.array([c - h - 1j * h, c + h - 1j * h, c + h + 1j * h, c - h + 1j * h])
+    cont = F.PolygonContour(sq, 16)
+    ref = F.feast(p.A, None, cont, p.Y0, p.Yh0, eps=1e-12, max_iter=40)
+    prob = fh.Problem(handle, _cuda(p.A))
+    opts = fh.default_opts(24, eps=1e-12, max_iter=40)
+    out = fh.feast(prob, 0.0, 1.0, 1.0, 0.0, 16, _cuda(p.Y0), _cuda(p.Yh0), opts, polygon=sq)
+    assert out["info"] == 0 and ref.info == 0
+    inside = ct.inside_polygon(p.info["lam"], sq)
+    assert len(out["lam"]) == len(ref.lam) == int(inside.sum()) > 0
+    lam = np.sort_complex(out["lam"])
+    np.testing.assert_allclose(lam, np.sort_complex(ref.lam), atol=1e-10 * cont.alpha())
+    np.testing.assert_allclose(lam, np.sort_complex(p.info["lam"][inside]), atol=1e-9 * cont.alpha())

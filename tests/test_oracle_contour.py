@@ -97,3 +97,54 @@ def test_inside_and_alpha():
     assert not ct.inside_ellipse(0.9, 0.0, 1.0, 0.3, math.pi / 2)
     assert ct.alpha(0.1 + 0.1j, 0.25) == pytest.approx(abs(0.1 + 0.1j) + 0.25)
     assert ct.alpha(3.0, 2.0, 2.0) == pytest.approx(3.0 + 4.0)
+
+
+SQUARE = np.array([-1 - 1j, 1 - 1j, 1 + 1j, -1 + 1j])
+LSHAPE = np.array([0, 2, 2 + 1j, 1 + 1j, 1 + 2j, 2j])          # non-convex, counterclockwise
+
+
+@pytest.mark.parametrize("verts,per", [(SQUARE, 4), (LSHAPE, 5), (np.exp(2j * np.pi * np.arange(5) / 5), 3)])
+def test_polygon_trapezoid_exact_for_linear_integrands(verts, per):
+    """The trapezoid rule is exact for z^0 and z^1 on every side, so the
+    closed-contour integrals of 1 and z vanish to rounding."""
+    z, w = ct.polygon_nodes(verts, per * len(verts))
+    assert abs(np.sum(w)) < 1e-15 * len(z)
+    assert abs(np.sum(w * z)) < 1e-15 * len(z)
+
+
+def test_polygon_filter_converges_second_order():
+    """rho_a at an interior point tends to 1, at an exterior one to 0, with
+    the trapezoid rule's O(h^2) error (the paper's square has 4 intervals per
+    side: 16 nodes)."""
+    errs = []
+    for per in (4, 8, 16, 32):
+        z, w = ct.polygon_nodes(SQUARE, 4 * per)
+        errs.append(abs(ct.rational(z, w, np.array([0.2 + 0.1j]))[0] - 1.0))
+        assert abs(ct.rational(z, w, np.array([2.5 - 0.3j]))[0]) < 0.1
+    assert errs[0] < 0.1
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 3.0 < e0 / e1 < 5.0
+
+
+def test_polygon_orientation_and_inside():
+    """Clockwise vertices give the same rule; the inside test agrees with the
+    filter of a fine rule (|rho| > 1/2 inside) on random points away from the
+    boundary, for a convex and a non-convex polygon."""
+    z1, w1 = ct.polygon_nodes(LSHAPE, 30)
+    z2, w2 = ct.polygon_nodes(LSHAPE[::-1], 30)
+    lam = np.array([0.5 + 0.5j, 1.5 + 1.5j, 3.0 + 0j])
+    np.testing.assert_allclose(ct.rational(z1, w1, lam), ct.rational(z2, w2, lam), atol=1e-14)
+    rng = np.random.default_rng(4)
+    for verts in (SQUARE, LSHAPE):
+        zf, wf = ct.polygon_nodes(verts, 400 * len(verts))
+        pts = (rng.uniform(-1.5, 2.5, 400) + 1j * rng.uniform(-1.5, 2.5, 400))
+        v = np.asarray(verts)
+        # distance to the boundary: keep points at least 0.05 from every side
+        def dist(x):
+            a, b = v, np.roll(v, -1)
+            t = np.clip(((x - a) * np.conj(b - a)).real / np.abs(b - a) ** 2, 0, 1)
+            return np.min(np.abs(a + t * (b - a) - x))
+        pts = np.array([x for x in pts if dist(x) > 0.05])
+        inside = ct.inside_polygon(pts, verts)
+        assert np.array_equal(inside, np.abs(ct.rational(zf, wf, pts)) > 0.5)
+        assert 0 < inside.sum() < len(pts)
