@@ -359,7 +359,8 @@ def feast(prob: Problem, center, a, ratio=1.0, angle=0.0, ne=8, Y0=None, Yh0=Non
 def feast_batched(probs, contours, Y0s, Yh0s, opts: fh_opts):
     """FEAST on many dense problems at once (fh_feast_batched).
 
-    contours: list of (center, a, ratio, angle, ne); Y0s, Yh0s: lists of
+    contours: list of (center, a, ratio, angle, ne[, polygon vertices]) (the
+    same problem may appear with several contours); Y0s, Yh0s: lists of
     complex128 CUDA tensors (n_i, m0).  Returns (status, list of dicts as
     feast())."""
     torch = _torch()
@@ -374,6 +375,7 @@ def feast_batched(probs, contours, Y0s, Yh0s, opts: fh_opts):
     res = [np.zeros(m0) for _ in range(k)]
     cs = (fh_contour * k)(*[fh_contour(complex(c[0]).real, complex(c[0]).imag, c[1], c[2], c[3], c[4])
                             for c in contours])
+    keep = [_polygon(cs[i], c[5] if len(c) > 5 else None) for i, c in enumerate(contours)]
     vp = C.c_void_p
     pa = (vp * k)(*[p._p.value for p in probs])
     ya = (vp * k)(*[Y.data_ptr() for Y in Ys])
@@ -389,7 +391,8 @@ def feast_batched(probs, contours, Y0s, Yh0s, opts: fh_opts):
     for i in range(k):
         m, mt = reps[i].m, reps[i].m0_final
         out.append({"info": reps[i].info, "lam": lams[i][:m].cpu().numpy(), "X": Ys[i][:, :m], "Xh": Yhs[i][:, :m],
-                    "res": res[i][:m], "report": reps[i].as_dict(), "Y": Ys[i][:, :mt], "Yh": Yhs[i][:, :mt]})
+                    "res": res[i][:m], "report": reps[i].as_dict(), "Y": Ys[i][:, :mt], "Yh": Yhs[i][:, :mt],
+                    "ritz": lams[i][:mt], "ritz_res": res[i][:mt]})
     return rc, out
 
 

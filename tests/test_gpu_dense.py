@@ -248,3 +248,43 @@ def test_feast_polygon_contour_matches_oracle(handle):
     lam = np.sort_complex(out["lam"])
     np.testing.assert_allclose(lam, np.sort_complex(ref.lam), atol=1e-10 * cont.alpha())
     np.testing.assert_allclose(lam, np.sort_complex(p.info["lam"][inside]), atol=1e-9 * cont.alpha())
+
+
+def _gap(d, lo, hi):
+    """Size in the widest relative gap of the sorted distances d within [lo, hi]."""
+    d = np.sort(d)
+    best = None
+    for a, b in zip(d[:-1], d[1:]):
+        if lo <= a and b <= hi and (best is None or b / a > best[0]):
+            best = (b / a, np.sqrt(a * b))
+    return best[1]
+
+
+def test_feast_batched_multi_contour_one_matrix(handle):
+    """Multi-contour partition of one matrix (the paper's contour-grid
+    experiment in small): two squares (16 nodes, 4 per side) and two circles
+    (16 nodes) over one 600 x 600 matrix with eigenvalues in the unit disk,
+    all in one batched call; each contour returns exactly the prescribed
+    eigenvalues it contains."""
+    p = W.dense_prescribed(n=600, n_in=20, center=0.0, radius=0.3, m0=32, seed=9)
+    lam = p.info["lam"]
+    conts, truth = [], []
+    for c in (-0.1j, 0.6 + 0.1j):                                  # squares
+        h = _gap(np.maximum(np.abs((lam - c).real), np.abs((lam - c).imag)), 0.08, 0.16)
+        sq = np.array([c - h - 1j * h, c + h - 1j * h, c + h + 1j * h, c - h + 1j * h])
+        conts.append((0.0, 1.0, 1.0, 0.0, 16, sq))
+        truth.append(lam[ct.inside_polygon(lam, sq)])
+    for c in (-0.45 + 0.4j, 0.4 - 0.45j):                         # circles
+        r = _gap(np.abs(lam - c), 0.08, 0.18)
+        conts.append((c, r, 1.0, 0.0, 16))
+        truth.append(lam[np.abs(lam - c) < r])
+    assert all(0 < len(t) <= 16 for t in truth)
+    prob = fh.Problem(handle, _cuda(p.A))
+    opts = fh.default_opts(32, eps=1e-12, max_iter=40)
+    Y0s = [_cuda(W.subspace(p.n, 32, 700 + i)) for i in range(4)]
+    Yh0s = [_cuda(W.subspace(p.n, 32, 710 + i)) for i in range(4)]
+    rc, outs = fh.feast_batched([prob] * 4, conts, Y0s, Yh0s, opts)
+    assert rc == 0
+    for out, t in zip(outs, truth):
+        assert out["info"] == 0 and len(out["lam"]) == len(t)
+        np.testing.assert_allclose(np.sort_complex(out["lam"]), np.sort_complex(t), atol=1e-9)

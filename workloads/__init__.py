@@ -94,6 +94,18 @@ def dense_prescribed(n=400, n_in=24, center=0.1 + 0.1j, radius=0.25, ne=8, m0=36
                    info={"lam": lam, "V": V, "n_in": n_in})
 
 
+def dense_unit_disk(n=4000, seed=12):
+    """A = V diag(lam) V^{-1}, lam area-uniform in the unit disk, V Gaussian with
+    unit columns (the matrix of the paper's multi-contour experiment: a dense
+    matrix whose eigenvalues all lie in the unit disk).  Returns (A, lam)."""
+    rng = np.random.default_rng(seed)
+    V = _cgauss(rng, (n, n))
+    V /= np.linalg.norm(V, axis=0, keepdims=True)
+    lam = _area_uniform_disk(rng, n, 0.0, 1.0)
+    A = np.linalg.solve(V.T, (V * lam[None, :]).T).T
+    return np.ascontiguousarray(A), lam
+
+
 # --------------------------------------------------------------------------
 # 2D convection-diffusion, 5-point central differences (second configuration)
 # --------------------------------------------------------------------------
