@@ -70,8 +70,9 @@ def _ccw(verts):
 
 
 def polygon_nodes(verts, ne):
-    """Composite trapezoid rule for (1/2 pi i) \oint f(z) dz along the polygon,
-    ne / nv intervals per side, nodes at the interval ends.  On side k from
+    """Composite trapezoid rule for (1/2 pi i) times the closed integral of
+    f(z) dz along the polygon, ne / nv intervals per side, nodes at the
+    interval ends.  On side k from
     v_k to v_{k+1} with step h_k = (v_{k+1} - v_k) / p the interval ends are
     v_k + q h_k (q = 0 .. p-1; q = p is the next side's first node); an
     interior end gets h_k / (2 pi i), a vertex (h_{k-1} + h_k) / (2 (2 pi i))."""
