@@ -257,11 +257,14 @@ def feast(A, B, cont: Contour, Y0, Yh0, eps=1e-12, max_iter=50, keep_history=Fal
         else:
             m_s = 0
         ok, m = converged(rec["res"], rec["inside"], m_s, eps)
-        # an exit that relies on spurious flags (m_s > 0) must be confirmed by
-        # the next iteration with the same number of converged inside pairs
+        # an exit that relies on spurious flags (m_s > 0 and some inside pair
+        # above eps) must be confirmed by the next iteration with the same
+        # number of converged inside pairs; when every inside pair meets eps
+        # the flags exclude nothing and the exit is immediate
         nconv = int(np.count_nonzero(rec["inside"] & (rec["res"] < eps)))
+        all_in = nconv > 0 and nconv == int(np.count_nonzero(rec["inside"]))
         passed = ok
-        if ok and m_s > 0 and not (prev_pass and prev_nconv == nconv):
+        if ok and m_s > 0 and not all_in and not (prev_pass and prev_nconv == nconv):
             ok = False
         prev_pass, prev_nconv = passed, nconv
         rec["m_s"], rec["m"] = m_s, m

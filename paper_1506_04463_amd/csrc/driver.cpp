@@ -468,12 +468,15 @@ struct FeastRun {
         else sel.clear();
         converged = m > 0;
         for (int i : sel) converged = converged && (res[i] < o.eps);
-        // an exit that relies on spurious flags must be confirmed by the next
-        // iteration with the same number of converged inside pairs
+        // an exit that relies on spurious flags (some inside pair above eps,
+        // passed over as flagged) must be confirmed by the next iteration with
+        // the same number of converged inside pairs; when every inside pair
+        // meets eps the flags exclude nothing and the exit is immediate
         int nconv = 0;
         for (int i = 0; i < mt; ++i) nconv += (inside[i] && res[i] < o.eps) ? 1 : 0;
+        const bool all_in = m_r > 0 && nconv == m_r;
         const bool passed = converged;
-        if (converged && m_s > 0 && !(prev_pass && prev_nconv == nconv)) converged = false;
+        if (converged && m_s > 0 && !all_in && !(prev_pass && prev_nconv == nconv)) converged = false;
         prev_pass = passed;
         prev_nconv = nconv;
         mcur = mt;
