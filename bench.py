@@ -367,9 +367,13 @@ def contour_grid(args):
     all twelve contours in one batched call (complex-FP32 grouped LU on MFMA
     + FP64 refinement, factorizations kept) against three iterations of FP64
     FEAST with direct solves one contour at a time; the Ritz values are
-    matched against the prescribed eigenvalues.  (At this eigenvalue density
-    the exit rule is not met within 40 iterations: Ritz values on the
-    contours flip between inside and outside.)
+    matched against the prescribed eigenvalues.  The work per iteration is
+    timed rather than the time to convergence: with nodes this close to the
+    eigenvalues of a non-normal matrix the complex-FP32 factors are too
+    ill-conditioned for the refinement to take eq:res of every inside pair
+    below 1e-7 (the batched run stops at its iteration limit on all twelve
+    contours, also with the solves refined to 1e-10), while FP64 FEAST meets
+    eps = 1e-7 on nine of the twelve within 4-8 iterations.
     Sizes: half-side 0.13 / radius 0.17 (about 85 / 115 eigenvalues), each
     moved within +-10 % into the widest gap of the eigenvalue distances so
     that no eigenvalue sits on a contour."""
@@ -408,7 +412,7 @@ def contour_grid(args):
     k = len(conts)
     Y0s = [torch.from_numpy(W.subspace(n, m0, 900 + i)).cuda() for i in range(k)]
     Yh0s = [torch.from_numpy(W.subspace(n, m0, 950 + i)).cuda() for i in range(k)]
-    K = 3        # timed iterations (the exit rule is not met at this density: see below)
+    K = 3        # timed iterations (the mixed path does not reach eps here: see above)
     o = fh.default_opts(m0, precision=fh.FH_PREC_MIXED, eps=1e-300, max_iter=K, inner_tol=EPS_DENSE,
                         max_refine=6, graph=1)
     # warm-up: one iteration of one contour (autotuner, code objects)
