@@ -139,6 +139,34 @@ def test_feast_batched_equals_single_runs(handle):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_feast_batched_one_matrix_distinct_contours_equal_single(handle, prec):
+    """One matrix under three distinct circles (15, 16 and 17 prescribed
+    eigenvalues inside, so the instances keep subspaces of different sizes
+    after the first resize): each instance of the batch takes the iterations
+    and finds the eigenvalues that fh_feast finds for its contour alone, and
+    these are the prescribed ones."""
+    n, m0 = 300, 28
+    A, lam = W.dense_unit_disk(n, 3)
+    conts = [(-0.4 + 0.3j, 0.2107, 1.0, 0.0, 16), (0.35 + 0.0j, 0.2568, 1.0, 0.0, 16),
+             (0.0 - 0.45j, 0.2396, 1.0, 0.0, 16)]
+    prob = fh.Problem(handle, _cuda(A))
+    Y0s = [_cuda(W.subspace(n, m0, 40 + i)) for i in range(3)]
+    Yh0s = [_cuda(W.subspace(n, m0, 60 + i)) for i in range(3)]
+    o = fh.default_opts(m0, eps=1e-10, max_iter=30, precision=prec, inner_tol=1e-12, max_refine=10)
+    rc, outs = fh.feast_batched([prob] * 3, conts, Y0s, Yh0s, o)
+    assert rc == 0
+    for i, (c, out) in enumerate(zip(conts, outs)):
+        single = fh.feast(prob, *c, Y0s[i], Yh0s[i], o)
+        assert single["info"] == 0 and out["info"] == 0
+        assert out["report"]["iters"] == single["report"]["iters"]
+        truth = np.sort_complex(lam[np.abs(lam - c[0]) < c[1]])
+        assert len(truth) == 15 + i and len(out["lam"]) == len(truth)
+        got = np.sort_complex(out["lam"])
+        np.testing.assert_allclose(got, np.sort_complex(single["lam"]), rtol=0, atol=1e-11)
+        np.testing.assert_allclose(got, truth, rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_graph_replays_match_eager(handle, prec):
     """The captured solve / refinement steps replayed over a whole batched
     FEAST run (one replay per iteration and step, eager work in between)
