@@ -499,7 +499,7 @@ def main():
     ORTH = args.orth
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of the "
-              "contour filter is described in DESIGN.md and not built", file=sys.stderr)
+              "contour filter (one node group per GPU) is a design only and not built", file=sys.stderr)
         sys.exit(2)
     if args.workload == "dense-batch":
         dense_batch(args)

@@ -4,7 +4,7 @@ Follows the paper's complete algorithm figure (steps 0-5) and Sections 2.2-2.7.
 complex128 throughout.  ``A`` is a dense ndarray or a scipy.sparse matrix; ``B``
 is None (identity), a dense ndarray or a scipy.sparse matrix.
 
-Readings where the paper is silent (each also listed in the design doc):
+Readings where the paper is silent:
 * V are the right eigenvectors of B_Q and Vh = V^{-H}, so B_Q = V Gamma Vh^H.
 * Gamma^{-1/2} is the principal square root; Gamma^{-H/2} = conj(Gamma^{-1/2}).
 * Sorting by decreasing |gamma| is stable (ties keep the original order).
@@ -19,7 +19,8 @@ Readings where the paper is silent (each also listed in the design doc):
   inside the contour must all be below eps; on exit every inside pair whose
   residual is below eps is returned (spurious pairs never converge).  When the
   test passes only because of spurious flags (m_s > 0), the exit waits for the
-  next iteration to pass as well with the same number of converged pairs.
+  next iteration to pass as well with the same number of converged pairs,
+  unless every inside pair already meets eps (the flags then exclude nothing).
 """
 from __future__ import annotations
 
