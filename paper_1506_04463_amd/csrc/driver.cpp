@@ -369,6 +369,30 @@ struct FeastRun {
         phase_bq_b();
     }
 
+    // The shifted QR iteration on B_Q ran out of its iteration budget (code 1).
+    // Its convergence depends on the order of the basis vectors, not only on
+    // the spectrum: run it once more on the reversed order J B_Q J (J the
+    // exchange matrix; same eigenvalues, eigenvectors J v), then reverse the
+    // rows of S and Sh so that they refer to the columns of Q and Qh again.
+    // AUr is free at this point of the iteration (steps 3.e-3.f fill it).
+    void retry_bq_reversed(int* hi) {
+        const int m = mcur;
+        std::vector<cplx> rb((size_t)m * m);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) rb[(size_t)i * m + j] = hbq[(size_t)(m - 1 - i) * m + (m - 1 - j)];
+        to_dev(c, AUr, reinterpret_cast<const zd*>(rb.data()), rb.size());
+        eig_biortho(c.stream, m, AUr, 1e-16, gam, S, Sh, ints, ints + 1, eigw);
+        to_host(c, hi, ints, 2);
+        if (hi[1] != 0) return;
+        for (zd* M : {S, Sh}) {
+            to_host(c, rb.data(), M, rb.size());
+            for (int i = 0; i < m / 2; ++i)
+                std::swap_ranges(rb.begin() + (size_t)i * m, rb.begin() + (size_t)(i + 1) * m,
+                                 rb.begin() + (size_t)(m - 1 - i) * m);
+            to_dev(c, M, reinterpret_cast<const zd*>(rb.data()), rb.size());
+        }
+    }
+
     // after steps 3.a-3.c (eig_biortho): spurious test (2.b), resize count
     void read_bq() {
         to_host(c, hbq.data(), BQ, (size_t)mcur * mcur);
@@ -383,6 +407,7 @@ struct FeastRun {
         }
         int hi[2];
         to_host(c, hi, ints, 2);
+        if (hi[1] == 1) retry_bq_reversed(hi);
         if (hi[1] != 0) throw Error(FH_EIG_FAILED, "eigendecomposition of B_Q failed (code " + std::to_string(hi[1]) + ")");
         mt = hi[0];
         FH_REQUIRE(mt >= 1 && mt <= mcur, FH_EIG_FAILED, "resize produced an empty subspace");
