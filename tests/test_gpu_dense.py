@@ -288,3 +288,30 @@ def test_feast_batched_multi_contour_one_matrix(handle):
     for out, t in zip(outs, truth):
         assert out["info"] == 0 and len(out["lam"]) == len(t)
         np.testing.assert_allclose(np.sort_complex(out["lam"]), np.sort_complex(t), atol=1e-9)
+
+
+def test_feast_fp64_bq_qr_retry_unit_disk_circle(handle):
+    """A case whose B_Q made the shifted QR iteration exhaust its budget at
+    iteration 6 (status 7) before the reversed-order retry: the 4000 x 4000
+    matrix with eigenvalues area-uniform in the unit disk, the circle at
+    0.5 - 0.3i with its radius in the widest eigenvalue gap near 0.17
+    (156 eigenvalues inside), m0 = 200, Ne = 16, FP64 direct solves.  FEAST
+    now meets eps = 1e-7 and returns exactly the prescribed eigenvalues."""
+    n, m0 = 4000, 200
+    A, lam = W.dense_unit_disk(n, 12)
+    c = 0.5 - 0.3j
+    d = np.sort(np.abs(lam - c))
+    best = None
+    for a, b in zip(d[:-1], d[1:]):
+        if 0.9 * 0.17 <= a and b <= 1.1 * 0.17 and (best is None or b / a > best[0]):
+            best = (b / a, np.sqrt(a * b))
+    r = best[1]
+    truth = np.sort_complex(lam[np.abs(lam - c) < r])
+    assert len(truth) == 156
+    prob = fh.Problem(handle, _cuda(A))
+    o = fh.default_opts(m0, precision=fh.FH_PREC_FP64, eps=1e-7, max_iter=40)
+    out = fh.feast(prob, c, r, 1.0, 0.0, 16, _cuda(W.subspace(n, m0, 911)), _cuda(W.subspace(n, m0, 961)), o)
+    assert out["info"] == 0
+    got = np.sort_complex(out["lam"])
+    assert len(got) == len(truth)
+    np.testing.assert_allclose(got, truth, rtol=0, atol=1e-9)
