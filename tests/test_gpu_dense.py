@@ -260,12 +260,14 @@ def _gap(d, lo, hi):
     return best[1]
 
 
-def test_feast_batched_multi_contour_one_matrix(handle):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_feast_batched_multi_contour_one_matrix(handle, prec):
     """Multi-contour partition of one matrix (the paper's contour-grid
     experiment in small): two squares (16 nodes, 4 per side) and two circles
     (16 nodes) over one 600 x 600 matrix with eigenvalues in the unit disk,
-    all in one batched call; each contour returns exactly the prescribed
-    eigenvalues it contains."""
+    all in one batched call, with FP64 solves (eps 1e-12) or complex-FP32
+    solves with FP64 refinement (eps 1e-10); each contour returns exactly
+    the prescribed eigenvalues it contains."""
     p = W.dense_prescribed(n=600, n_in=20, center=0.0, radius=0.3, m0=32, seed=9)
     lam = p.info["lam"]
     conts, truth = [], []
@@ -280,7 +282,11 @@ def test_feast_batched_multi_contour_one_matrix(handle):
         truth.append(lam[np.abs(lam - c) < r])
     assert all(0 < len(t) <= 16 for t in truth)
     prob = fh.Problem(handle, _cuda(p.A))
-    opts = fh.default_opts(32, eps=1e-12, max_iter=40)
+    if prec == 0:
+        opts = fh.default_opts(32, eps=1e-12, max_iter=40)
+    else:
+        opts = fh.default_opts(32, eps=1e-10, max_iter=40, precision=fh.FH_PREC_MIXED, inner_tol=1e-12,
+                               max_refine=10)
     Y0s = [_cuda(W.subspace(p.n, 32, 700 + i)) for i in range(4)]
     Yh0s = [_cuda(W.subspace(p.n, 32, 710 + i)) for i in range(4)]
     rc, outs = fh.feast_batched([prob] * 4, conts, Y0s, Yh0s, opts)
