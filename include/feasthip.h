@@ -18,9 +18,10 @@
  *                  or complex (FH_C128).
  * ownership        every buffer passed in belongs to the caller and is never
  *                  freed by the library; input matrices are never modified.
- *                  The library allocates its own workspace (device memory) in
- *                  the handle and in prepared problems, and frees it in
- *                  fh_destroy / fh_problem_destroy.
+ *                  Workspace (device memory) lives in the handle and in
+ *                  prepared problems and is freed in fh_destroy /
+ *                  fh_problem_destroy; it comes from the allocator given to
+ *                  fh_create (see fh_allocator), else from hipMalloc.
  * streams          all GPU work of a handle runs on the handle's stream; calls
  *                  return after that work has completed.  A handle is not
  *                  thread-safe.
@@ -141,6 +142,16 @@ typedef struct {
                              the filter.  The call returns -2 if A is not
                              symmetric.  0 = general.  Dense problems ignore
                              it */
+    int confirm;          /* exit rule.  0 (default) = the paper's steps 5.c /
+                             5.d: with m_r Ritz values inside and m_s flagged
+                             spurious, converged when the m = m_r - m_s
+                             smallest inside residuals are below eps, and
+                             exactly those m pairs are returned.  1 = a
+                             stricter exit that is not in the paper: when the
+                             test passes only because flagged pairs were
+                             passed over, the next iteration must pass with
+                             the same number of converged inside pairs, and
+                             every inside pair below eps is returned */
 } fh_opts;
 
 typedef struct {
@@ -160,8 +171,30 @@ typedef struct {
                              by the fallback (cumulative)                     */
 } fh_report;
 
-/* ---- handle ----------------------------------------------------------- */
-int         fh_create(fh_handle* h, int device, void* hip_stream);
+/* ---- handle -----------------------------------------------------------
+ * Device-memory provider.  alloc(bytes, stream, user) returns device memory
+ * of at least `bytes` bytes on the handle's device, usable in stream order on
+ * `stream` (the handle's stream at the time of the request), or NULL when it
+ * cannot (the call then fails with FH_HIP_ERROR).  free(ptr, bytes, stream,
+ * user) gives back a block with the size and stream of its alloc; the
+ * library waits for the device before it frees a block.  Blocks are requested
+ * inside the library's calls (workspace grows to the largest problem seen and
+ * is kept) and freed when a workspace grows, in fh_problem_destroy,
+ * fh_net_destroy and fh_destroy, which may run after fh_destroy of the
+ * handle that made the request: the callbacks must stay valid until the
+ * last of them.  A binding can route both to its framework's caching
+ * allocator (the Python binding uses torch's). */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* stream, void* user);
+    void (*free)(void* ptr, size_t bytes, void* stream, void* user);
+    void* user;
+} fh_allocator;
+
+/* h: out; device: HIP device index (-2 if out of range); hip_stream: the
+ * stream every call of the handle runs on (a hipStream_t, NULL = the null
+ * stream); alloc: NULL = hipMalloc / hipFree, else both callbacks must be set
+ * (-4 otherwise); the struct is copied. */
+int         fh_create(fh_handle* h, int device, void* hip_stream, const fh_allocator* alloc);
 int         fh_destroy(fh_handle h);
 int         fh_set_stream(fh_handle h, void* hip_stream);
 const char* fh_last_error(fh_handle h);

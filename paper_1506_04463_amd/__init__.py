@@ -63,7 +63,7 @@ class fh_opts(C.Structure):
                 ("inner_tol", C.c_double), ("max_restarts", C.c_int), ("mixed_inner_tol", C.c_double),
                 ("max_refine", C.c_int), ("save_factors", C.c_int), ("resume", C.c_int), ("fallback", C.c_int),
                 ("graph", C.c_int), ("orth", C.c_int), ("batch_nodes", C.c_int),
-                ("sym", C.c_int)]
+                ("sym", C.c_int), ("confirm", C.c_int)]
 
 
 class fh_report(C.Structure):
@@ -75,6 +75,51 @@ class fh_report(C.Structure):
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
+class fh_allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
+
+
+# torch's caching allocator as the library's device-memory source.  The
+# callbacks are module globals so that they outlive every handle; user carries
+# the device index.  After interpreter shutdown has begun nothing is freed
+# through them (the process is ending; torch may already be gone).
+_shutting_down = False
+
+
+def _on_exit():
+    global _shutting_down
+    _shutting_down = True
+
+
+import atexit as _atexit  # noqa: E402
+
+_atexit.register(_on_exit)
+
+
+def _torch_alloc(nbytes, stream, user):
+    try:
+        torch = _torch()
+        return torch.cuda.caching_allocator_alloc(int(nbytes), int(user or 0), int(stream or 0))
+    except Exception:
+        return None
+
+
+def _torch_free(ptr, nbytes, stream, user):
+    if _shutting_down or not ptr:
+        return
+    try:
+        _torch().cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+_TORCH_ALLOC = _ALLOC_FN(_torch_alloc)
+_TORCH_FREE = _FREE_FN(_torch_free)
 
 _lib = None
 
@@ -90,7 +135,7 @@ def lib():
     L = C.CDLL(LIB_PATH)
     vp, i, d, dp, ip = C.c_void_p, C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int)
     sig = {
-        "fh_create": (i, [C.POINTER(vp), i, vp]),
+        "fh_create": (i, [C.POINTER(vp), i, vp, C.POINTER(fh_allocator)]),
         "fh_destroy": (i, [vp]),
         "fh_set_stream": (i, [vp, vp]),
         "fh_last_error": (C.c_char_p, [vp]),
@@ -156,17 +201,27 @@ def _check_block(t, n, name):
 
 
 class Handle:
-    """Library handle bound to one device and (by default) torch's current stream."""
+    """Library handle bound to one device and (by default) torch's current stream.
 
-    def __init__(self, device=0, stream=None):
+    allocator="torch" (default): the library's workspace comes from torch's
+    caching allocator (it shows in torch.cuda.memory_allocated and is reused
+    by torch after it is freed); allocator=None: the library calls hipMalloc."""
+
+    def __init__(self, device=0, stream=None, allocator="torch"):
         torch = _torch()
         L = lib()
         self.device = device
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
+        if allocator not in ("torch", None):
+            raise ValueError("allocator must be 'torch' or None")
+        al = None
+        if allocator == "torch":
+            al = fh_allocator(_TORCH_ALLOC, _TORCH_FREE, C.c_void_p(device))
+        self.allocator = allocator
         h = C.c_void_p()
-        rc = L.fh_create(C.byref(h), device, C.c_void_p(stream.cuda_stream))
+        rc = L.fh_create(C.byref(h), device, C.c_void_p(stream.cuda_stream), C.byref(al) if al is not None else None)
         if rc != 0:
             raise FeastError(rc, "fh_create")
         self._h = h
@@ -195,7 +250,7 @@ class Handle:
 
     def __del__(self):
         try:
-            if getattr(self, "_h", None):
+            if getattr(self, "_h", None) and not _shutting_down:
                 lib().fh_destroy(self._h)
         except Exception:
             pass
@@ -244,7 +299,7 @@ class Problem:
 
     def __del__(self):
         try:
-            if getattr(self, "_p", None):
+            if getattr(self, "_p", None) and not _shutting_down:
                 lib().fh_problem_destroy(self._p)
         except Exception:
             pass
@@ -584,7 +639,7 @@ class Net:
 
     def __del__(self):
         try:
-            if getattr(self, "_n", None):
+            if getattr(self, "_n", None) and not _shutting_down:
                 lib().fh_net_destroy(self._n)
         except Exception:
             pass

@@ -67,17 +67,25 @@ void fh_default_opts(fh_opts* o) {
     o->orth = 0;
     o->batch_nodes = 0;
     o->sym = 0;
+    o->confirm = 0;
 }
 
-int fh_create(fh_handle* h, int device, void* stream) {
+int fh_create(fh_handle* h, int device, void* stream, const fh_allocator* alloc) {
     if (!h) return -1;
     *h = nullptr;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return FH_HIP_ERROR;
     if (device < 0 || device >= ndev) return -2;
+    if (alloc && (!alloc->alloc || !alloc->free)) return -4;
     fh_ctx* c = new fh_ctx();
     c->device = device;
     c->stream = (hipStream_t)stream;
+    if (alloc) {
+        c->mem = std::make_shared<MemSource>();
+        c->mem->alloc = alloc->alloc;
+        c->mem->free = alloc->free;
+        c->mem->user = alloc->user;
+    }
     *h = c;
     return FH_OK;
 }

@@ -493,17 +493,20 @@ struct FeastRun {
         else sel.clear();
         converged = m > 0;
         for (int i : sel) converged = converged && (res[i] < o.eps);
-        // an exit that relies on spurious flags (some inside pair above eps,
-        // passed over as flagged) must be confirmed by the next iteration with
-        // the same number of converged inside pairs; when every inside pair
-        // meets eps the flags exclude nothing and the exit is immediate
-        int nconv = 0;
-        for (int i = 0; i < mt; ++i) nconv += (inside[i] && res[i] < o.eps) ? 1 : 0;
-        const bool all_in = m_r > 0 && nconv == m_r;
-        const bool passed = converged;
-        if (converged && m_s > 0 && !all_in && !(prev_pass && prev_nconv == nconv)) converged = false;
-        prev_pass = passed;
-        prev_nconv = nconv;
+        if (o.confirm) {
+            // optional stricter exit (not the paper's rule): an exit that relies
+            // on spurious flags (some inside pair above eps, passed over as
+            // flagged) must be confirmed by the next iteration with the same
+            // number of converged inside pairs; when every inside pair meets
+            // eps the flags exclude nothing and the exit is immediate
+            int nconv = 0;
+            for (int i = 0; i < mt; ++i) nconv += (inside[i] && res[i] < o.eps) ? 1 : 0;
+            const bool all_in = m_r > 0 && nconv == m_r;
+            const bool passed = converged;
+            if (converged && m_s > 0 && !all_in && !(prev_pass && prev_nconv == nconv)) converged = false;
+            prev_pass = passed;
+            prev_nconv = nconv;
+        }
         mcur = mt;
         if (verbose()) {
             double worst = 0.0;
@@ -551,13 +554,13 @@ struct FeastRun {
         return decide();
     }
 
-    // step 5.d: the converged pairs in the first m columns, sorted by (Re, Im).
-    // Every inside pair whose residual meets eps is returned (flagged spurious
-    // pairs never converge, so this is the spurious-free set).  The remaining
-    // Ritz vectors follow in columns m..m0_final-1 so that the whole search
-    // subspace can be reused as a start (resume).
+    // step 5.d: the m = m_r - m_s converged pairs of step 5.c (the m smallest
+    // inside residuals) in the first m columns, sorted by (Re, Im).  With
+    // opts.confirm every inside pair whose residual meets eps is returned.
+    // The remaining Ritz vectors follow in columns m..m0_final-1 so that the
+    // whole search subspace can be reused as a start (resume).
     int finish(zd* Yio, zd* Yhio, zd* lambda, double* res_out) {
-        if (converged) {
+        if (converged && o.confirm) {
             for (int i = 0; i < mcur; ++i)
                 if (inside[i] && res[i] < o.eps && std::find(sel.begin(), sel.end(), i) == sel.end()) sel.push_back(i);
         }

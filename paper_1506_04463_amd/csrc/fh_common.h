@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <cstdio>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -95,25 +96,74 @@ struct Error : std::runtime_error {
     } while (0)
 
 // ---------------------------------------------------------------------------
+// device-memory source of a handle: the caller's allocator callbacks (e.g.
+// torch's caching allocator) or, without them, hipMalloc / hipFree.  Every
+// entry point makes its handle's source current on the calling thread
+// (MemScope); a DBuf allocates from the current source and keeps a reference
+// to it for the free, so a buffer may outlive the call (and the handle) that
+// allocated it.
+// ---------------------------------------------------------------------------
+struct MemSource {
+    void* (*alloc)(size_t bytes, void* stream, void* user) = nullptr;
+    void (*free)(void* ptr, size_t bytes, void* stream, void* user) = nullptr;
+    void* user = nullptr;
+    void* stream = nullptr;   // the handle's stream (updated at every call)
+};
+using MemSourceP = std::shared_ptr<MemSource>;
+inline MemSourceP& tl_mem() {
+    static thread_local MemSourceP m;
+    return m;
+}
+struct MemScope {
+    MemSourceP prev;
+    MemScope(const MemSourceP& m, void* stream) : prev(tl_mem()) {
+        if (m) m->stream = stream;
+        tl_mem() = m;
+    }
+    ~MemScope() { tl_mem() = prev; }
+};
+
+// ---------------------------------------------------------------------------
 // device buffer (grow-only)
 // ---------------------------------------------------------------------------
 struct DBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    MemSourceP src;           // the source p came from (null: hipMalloc)
+    void* st = nullptr;       // stream passed to the source's alloc
     DBuf() = default;
     DBuf(const DBuf&) = delete;
     DBuf& operator=(const DBuf&) = delete;
     ~DBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (src && src->free) {
+                // hipFree waits for the device; a caller's allocator may hand the
+                // block out again at once, so wait for work still using it
+                (void)hipDeviceSynchronize();
+                src->free(p, bytes, st, src->user);
+            } else {
+                (void)hipFree(p);
+            }
+        }
         p = nullptr;
         bytes = 0;
+        src.reset();
+        st = nullptr;
     }
     void* ensure(size_t b) {
         if (b <= bytes && p) return p;
         release();
         if (b == 0) b = 256;
-        FH_HIP(hipMalloc(&p, b));
+        const MemSourceP& m = tl_mem();
+        if (m && m->alloc) {
+            p = m->alloc(b, m->stream, m->user);
+            if (!p) throw Error(100, "device allocator returned no memory for " + std::to_string(b) + " bytes");
+            src = m;
+            st = m->stream;
+        } else {
+            FH_HIP(hipMalloc(&p, b));
+        }
         bytes = b;
         return p;
     }

@@ -28,6 +28,7 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    MemSourceP mem;   // caller's allocator (null: hipMalloc / hipFree)
     // scratch shared by the steps of one call
     DBuf eig_work, partial, partial2, small_i;
     FilterBufs fb;
@@ -47,9 +48,11 @@ struct Ctx {
     }
 };
 
-// makes the handle's profiler current on this thread for the duration of a call
+// makes the handle's profiler and memory source current on this thread for
+// the duration of a call
 struct ProfScope {
-    ProfScope(Ctx& c) { tl_prof() = c.prof_on ? &c.prof : nullptr; }
+    MemScope mem;
+    ProfScope(Ctx& c) : mem(c.mem, (void*)c.stream) { tl_prof() = c.prof_on ? &c.prof : nullptr; }
     ~ProfScope() { tl_prof() = nullptr; }
 };
 

@@ -321,3 +321,48 @@ def test_feast_fp64_bq_qr_retry_unit_disk_circle(handle):
     got = np.sort_complex(out["lam"])
     assert len(got) == len(truth)
     np.testing.assert_allclose(got, truth, rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("seed,n,n_in,m0", [(1, 120, 6, 24), (9, 150, 8, 30)])
+def test_feast_exit_with_spurious_flags_matches_oracle(handle, seed, n, n_in, m0):
+    """Steps 5.c / 5.d with m_s > 0 at the exit iteration (the subspace is
+    four times the eigenvalue count, so spurious Ritz values sit inside the
+    circle): the library takes the same exit as the oracle -- same iteration,
+    same m_s, the same m = m_r - m_s pairs."""
+    p = W.dense_prescribed(n=n, n_in=n_in, center=0.1 + 0.1j, radius=0.25, ne=8, m0=m0, seed=seed)
+    cont = F.Contour(p.contour.center, p.contour.a, 1.0, 0.0, 8)
+    ref = F.feast(p.A, None, cont, p.Y0, p.Yh0, eps=1e-12, max_iter=60)
+    assert ref.info == 0 and ref.history[-1]["m_s"] > 0
+    prob = fh.Problem(handle, _cuda(p.A))
+    out = fh.feast(prob, p.contour.center, p.contour.a, 1.0, 0.0, 8, _cuda(p.Y0), _cuda(p.Yh0),
+                   fh.default_opts(m0, eps=1e-12, max_iter=60))
+    rep = out["report"]
+    assert rep["iters"] == ref.iters
+    assert rep["m_s"] == ref.history[-1]["m_s"]
+    _compare_feast(p, p.A, None, out, ref, cont)
+
+
+def test_feast_confirm_option_returns_every_converged_pair(handle):
+    """opts.confirm = 1 (not the paper's rule): on this start the paper's exit
+    passes over one true eigenpair flagged as spurious and returns 5 of the 6
+    eigenvalues inside; the confirmed exit returns all 6 (the prescribed
+    ones), and the literal exit's 5 are among them."""
+    p = W.dense_prescribed(n=120, n_in=6, center=0.1 + 0.1j, radius=0.25, ne=8, m0=24, seed=13)
+    cont = F.Contour(p.contour.center, p.contour.a, 1.0, 0.0, 8)
+    ref = F.feast(p.A, None, cont, p.Y0, p.Yh0, eps=1e-12, max_iter=60)
+    assert ref.info == 0 and len(ref.lam) == 5
+    prob = fh.Problem(handle, _cuda(p.A))
+    lit = fh.feast(prob, p.contour.center, p.contour.a, 1.0, 0.0, 8, _cuda(p.Y0), _cuda(p.Yh0),
+                   fh.default_opts(24, eps=1e-12, max_iter=60))
+    assert lit["info"] == 0 and len(lit["lam"]) == 5
+    assert np.max(np.abs(lit["lam"] - ref.lam)) < 1e-10 * cont.alpha()
+    con = fh.feast(prob, p.contour.center, p.contour.a, 1.0, 0.0, 8, _cuda(p.Y0), _cuda(p.Yh0),
+                   fh.default_opts(24, eps=1e-12, max_iter=60, confirm=1))
+    assert con["info"] == 0 and len(con["lam"]) == 6
+    assert con["report"]["iters"] >= lit["report"]["iters"]
+    lam_true = p.info["lam"][:6]
+    lam_true = lam_true[np.lexsort((lam_true.imag, lam_true.real))]
+    assert np.max(np.abs(con["lam"] - lam_true)) < 1e-10 * cont.alpha()
+    assert np.max(np.abs(lit["lam"][:, None] - con["lam"][None, :]).min(axis=1)) < 1e-10 * cont.alpha()
+    X, Xh = con["X"].cpu().numpy(), con["Xh"].cpu().numpy()
+    assert np.max(np.abs(Xh.conj().T @ X - np.eye(6))) < 1e-10

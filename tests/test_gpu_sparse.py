@@ -177,8 +177,16 @@ def test_filter_sparse_parity(handle, precision, orth, batch_nodes):
     assert np.linalg.norm(Qh - Qho) / np.linalg.norm(Qho) < tol
 
 
-@pytest.mark.parametrize("precision,precond,orth,batch_nodes", [(0, 2, 0, 0), (1, 2, 0, 0), (1, 2, 2, 0), (1, 2, 2, 6)])
+@pytest.mark.parametrize("precision,precond,orth,batch_nodes",
+                         [(0, 2, 0, 0), (1, 2, 0, 0), (1, 2, 2, 0), (1, 2, 2, 6), (0, 1, 0, 0), (0, 2, 2, 0)])
 def test_feast_sparse_convdiff_small(handle, precision, precond, orth, batch_nodes):
+    """FEAST with iterative inner solves (inner tolerance 1e-3) against the
+    oracle's direct-solve FEAST and the closed-form spectrum.  The exit
+    threshold is eq:res <= 1e-11: with inexact inner solves eq:res levels off
+    between 1e-13 and 2e-11 on this grid, so 1e-12 would be met only at a
+    favourable iteration; the spec residual gate below stays 1e-10.
+    (0, 1, ...): Jacobi instead of ILU(0); (0, 2, 2, 0): delayed
+    reorthogonalization in FP64."""
     p = _small_convdiff(N=24, m_in=10, m0=20)
     cont = F.Contour(p.contour.center, p.contour.a, p.contour.ratio, 0.0, 16)
     ref = F.feast(L.csr_matrix(p.A), None, cont, p.Y0, p.Yh0, eps=1e-12, max_iter=30)
@@ -186,7 +194,7 @@ def test_feast_sparse_convdiff_small(handle, precision, precond, orth, batch_nod
     # Jacobi is a much weaker preconditioner: give its GMRES more cycles
     cycles = 2 if precond == 2 else 8
     opts = fh.default_opts(p.m0, solver=1, precond=precond, inner_tol=1e-3, restart=30, max_restarts=cycles,
-                           precision=precision, mixed_inner_tol=1e-3, max_refine=3, eps=1e-12, max_iter=60,
+                           precision=precision, mixed_inner_tol=1e-3, max_refine=3, eps=1e-11, max_iter=60,
                            orth=orth, batch_nodes=batch_nodes)
     out = fh.feast(prob, p.contour.center, p.contour.a, p.contour.ratio, 0.0, 16, _cuda(p.Y0), _cuda(p.Yh0), opts)
     assert out["info"] == 0, out["report"]

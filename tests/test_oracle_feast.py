@@ -293,3 +293,115 @@ def test_count_estimate_exact_trace_and_probes():
     V = rng.choice([-1.0, 1.0], size=(p.n, 400)).astype(np.complex128)
     est_r = F.count_estimate(p.A, None, z, w, V)
     assert abs(est_r - exact) < 1.5
+
+
+# --------------------------------------------------------------------------
+# eq:res, alpha, the output gauge and the exit test of steps 5.c / 5.d
+# --------------------------------------------------------------------------
+def test_residuals_hand_computed_3x3():
+    """eq:res on a 3 x 3 generalized pencil worked out by hand.  A has one
+    complex entry so that A vs A^H and lambda vs conj(lambda) give different
+    numbers; B = diag(1, 2, 1); alpha = 2 (circle centre 1, radius 1).
+    Column 0: y = yh = (1, 1, 0), lambda = 1 + i:
+      A y - lambda B y = (1, 1 - 2i, 0)          -> (1 + sqrt 5) / (2 * 3)
+      A^H yh - conj(lambda) B^H yh = (1 + i, 1 + i, 0) -> 2 sqrt 2 / (2 * 3)
+    Column 1: y = (0, 0, 1), yh = (1, 1, 0), lambda = 1:
+      right residual 0, left (1, 1 - i, 0)        -> (1 + sqrt 2) / (2 * 3)
+    The max of the two sides is eq:res (both sides must be converged)."""
+    A = np.array([[2, 1j, 0], [0, 3, 0], [0, 0, 1]], dtype=np.complex128)
+    B = np.diag([1.0, 2.0, 1.0]).astype(np.complex128)
+    Y = np.array([[1, 0], [1, 0], [0, 1]], dtype=np.complex128)
+    Yh = np.array([[1, 1], [1, 1], [0, 0]], dtype=np.complex128)
+    lam = np.array([1 + 1j, 1.0 + 0j])
+    alpha = ct.alpha(1.0, 1.0, 1.0)
+    assert alpha == 2.0
+    res = F.residuals(A, B, Y, Yh, lam, alpha)
+    r0 = max((1 + np.sqrt(5)) / 6, 2 * np.sqrt(2) / 6)
+    r1 = (1 + np.sqrt(2)) / 6
+    np.testing.assert_allclose(res, [r0, r1], rtol=1e-14)
+    # alpha divides: another alpha scales eq:res by its inverse
+    np.testing.assert_allclose(F.residuals(A, B, Y, Yh, lam, 7.0), [r0 * 2 / 7, r1 * 2 / 7], rtol=1e-14)
+
+
+def test_alpha_circle_and_ellipse():
+    """alpha of eq:res is |lambda_mid| + r for a circle; for an ellipse the
+    larger semi-axis takes the place of r (either one may be the larger)."""
+    assert ct.alpha(3 + 4j, 1.0, 1.0) == 6.0
+    assert ct.alpha(3 + 4j, 1.0, 2.0) == 7.0        # vertical semi-axis 2
+    assert ct.alpha(3 + 4j, 2.0, 0.5) == 7.0        # horizontal semi-axis 2
+    assert ct.alpha(-2.0, 0.5, 0.3) == 2.5
+
+
+def test_polygon_alpha_square_and_rectangle():
+    """Polygon alpha = |g| + max_k |v_k - g|, g the mean vertex: for the
+    square of half-side s centred at g the farthest vertex is at s sqrt 2."""
+    g, s = 0.5 + 0.3j, 0.13
+    sq = g + s * np.array([-1 - 1j, 1 - 1j, 1 + 1j, -1 + 1j])
+    assert abs(ct.polygon_alpha(sq) - (abs(g) + s * np.sqrt(2))) < 1e-15
+    assert abs(ct.polygon_alpha(sq[::-1]) - (abs(g) + s * np.sqrt(2))) < 1e-15
+    rect = np.array([0, 4, 4 + 2j, 2j])               # g = 2 + i, corners at sqrt 5
+    assert abs(ct.polygon_alpha(rect) - 2 * np.sqrt(5)) < 1e-15
+
+
+def test_gauge_normalize_defining_properties():
+    """Output gauge of step 5.d: unit 2-norm, the largest-modulus entry (lowest
+    index on ties) real positive, xh^H B x = 1, each vector a multiple of the
+    input one."""
+    rng = np.random.default_rng(5)
+    n, m = 12, 4
+    X = rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m))
+    Xh = rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m))
+    X[3, 2] = X[7, 2] = 9.0 * np.exp(0.7j)          # a tie: index 3 wins
+    B = np.eye(n) + 0.1 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    Xn, Xhn = F.gauge_normalize(X, Xh, B)
+    for i in range(m):
+        x, xh = Xn[:, i], Xhn[:, i]
+        assert abs(np.linalg.norm(x) - 1) < 1e-14
+        k = int(np.argmax(np.abs(x)))
+        assert abs(x[k].imag) < 1e-15 and x[k].real > 0
+        assert abs(np.vdot(xh, B @ x) - 1) < 1e-13
+        # the same directions
+        assert abs(abs(np.vdot(X[:, i], x)) - np.linalg.norm(X[:, i])) < 1e-12
+        assert abs(abs(np.vdot(Xh[:, i], xh)) - np.linalg.norm(Xh[:, i]) * np.linalg.norm(xh)) < 1e-10
+    assert int(np.argmax(np.abs(Xn[:, 2]))) == 3 and abs(Xn[3, 2].imag) < 1e-15
+
+
+def test_exit_test_synthetic_histories():
+    """Steps 5.c / 5.d on synthetic residuals and flags: m = m_r - m_s, the m
+    smallest inside residuals decide, exactly those m pairs are returned."""
+    inside = np.array([True, True, True, False, True])
+    res = np.array([1e-13, 1e-5, 1e-14, 1e-20, 3e-13])
+    # no spurious flag: the m = 4 inside residuals include 1e-5 -> not converged
+    ok, m, sel = F.exit_test(res, inside, 0, 1e-12)
+    assert (ok, m) == (False, 4) and sel.tolist() == [2, 0, 4, 1]
+    # one flagged pair: the m = 3 smallest (1e-14, 1e-13, 3e-13) decide
+    ok, m, sel = F.exit_test(res, inside, 1, 1e-12)
+    assert (ok, m) == (True, 3) and sel.tolist() == [2, 0, 4]
+    # an outside pair never counts, however small its residual
+    assert 3 not in sel
+    # a tighter eps fails on the third of them
+    assert F.exit_test(res, inside, 1, 2e-13)[0] is False
+    # m_s >= m_r: nothing to converge
+    ok, m, sel = F.exit_test(res, inside, 4, 1.0)
+    assert ok is False and m == 0 and len(sel) == 0
+    # no pair inside
+    assert F.exit_test(res, np.zeros(5, bool), 0, 1.0)[:2] == (False, 0)
+    # ties keep the Ritz order
+    ok, m, sel = F.exit_test(np.array([1e-14, 1e-14, 1e-14]), np.ones(3, bool), 1, 1e-12)
+    assert ok and sel.tolist() == [0, 1]
+
+
+def test_feast_returns_exactly_the_exit_pairs():
+    """The whole loop wires step 5.c to 5.d: the pairs returned are exactly the
+    m of the last history record, i.e. the m smallest inside residuals, all
+    below eps, and m = m_r - m_s."""
+    p = W.dense_prescribed(n=120, n_in=7, center=0.1 + 0.1j, radius=0.25, ne=8, m0=14, seed=23)
+    cont = F.Contour(p.contour.center, p.contour.a, 1.0, 0.0, 8)
+    r = F.feast(p.A, None, cont, p.Y0, p.Yh0, eps=1e-12, max_iter=60)
+    assert r.info == 0
+    h = r.history[-1]
+    m_r = int(np.count_nonzero(h["inside"]))
+    assert h["m"] == m_r - h["m_s"] == len(r.lam)
+    want = np.sort(h["res"][h["inside"]])[: h["m"]]
+    np.testing.assert_array_equal(np.sort(r.res), want)
+    assert np.all(r.res < 1e-12)
