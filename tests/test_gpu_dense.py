@@ -244,10 +244,18 @@ def test_feast_polygon_contour_matches_oracle(handle):
     out = fh.feast(prob, 0.0, 1.0, 1.0, 0.0, 16, _cuda(p.Y0), _cuda(p.Yh0), opts, polygon=sq)
     assert out["info"] == 0 and ref.info == 0
     inside = ct.inside_polygon(p.info["lam"], sq)
-    assert len(out["lam"]) == len(ref.lam) == int(inside.sum()) > 0
+    truth = np.sort_complex(p.info["lam"][inside])
+    # the paper's exit (steps 5.c / 5.d): the same iteration and pairs as the oracle
+    assert out["report"]["iters"] == ref.iters
+    assert 0 < len(out["lam"]) == len(ref.lam) <= len(truth)
     lam = np.sort_complex(out["lam"])
     np.testing.assert_allclose(lam, np.sort_complex(ref.lam), atol=1e-10 * cont.alpha())
-    np.testing.assert_allclose(lam, np.sort_complex(p.info["lam"][inside]), atol=1e-9 * cont.alpha())
+    assert np.max(np.abs(lam[:, None] - truth[None, :]).min(axis=1)) < 1e-9 * cont.alpha()
+    # the confirmed exit (opts.confirm) returns every prescribed eigenvalue inside
+    out = fh.feast(prob, 0.0, 1.0, 1.0, 0.0, 16, _cuda(p.Y0), _cuda(p.Yh0),
+                   fh.default_opts(24, eps=1e-12, max_iter=40, confirm=1), polygon=sq)
+    assert out["info"] == 0 and len(out["lam"]) == len(truth) > 0
+    np.testing.assert_allclose(np.sort_complex(out["lam"]), truth, atol=1e-9 * cont.alpha())
 
 
 def _gap(d, lo, hi):
@@ -267,7 +275,7 @@ def test_feast_batched_multi_contour_one_matrix(handle, prec):
     (16 nodes) over one 600 x 600 matrix with eigenvalues in the unit disk,
     all in one batched call, with FP64 solves (eps 1e-12) or complex-FP32
     solves with FP64 refinement (eps 1e-10); each contour returns exactly
-    the prescribed eigenvalues it contains."""
+    the prescribed eigenvalues it contains (confirmed exit, opts.confirm)."""
     p = W.dense_prescribed(n=600, n_in=20, center=0.0, radius=0.3, m0=32, seed=9)
     lam = p.info["lam"]
     conts, truth = [], []
@@ -283,10 +291,10 @@ def test_feast_batched_multi_contour_one_matrix(handle, prec):
     assert all(0 < len(t) <= 16 for t in truth)
     prob = fh.Problem(handle, _cuda(p.A))
     if prec == 0:
-        opts = fh.default_opts(32, eps=1e-12, max_iter=40)
+        opts = fh.default_opts(32, eps=1e-12, max_iter=40, confirm=1)
     else:
         opts = fh.default_opts(32, eps=1e-10, max_iter=40, precision=fh.FH_PREC_MIXED, inner_tol=1e-12,
-                               max_refine=10)
+                               max_refine=10, confirm=1)
     Y0s = [_cuda(W.subspace(p.n, 32, 700 + i)) for i in range(4)]
     Yh0s = [_cuda(W.subspace(p.n, 32, 710 + i)) for i in range(4)]
     rc, outs = fh.feast_batched([prob] * 4, conts, Y0s, Yh0s, opts)
@@ -302,7 +310,8 @@ def test_feast_fp64_bq_qr_retry_unit_disk_circle(handle):
     matrix with eigenvalues area-uniform in the unit disk, the circle at
     0.5 - 0.3i with its radius in the widest eigenvalue gap near 0.17
     (156 eigenvalues inside), m0 = 200, Ne = 16, FP64 direct solves.  FEAST
-    now meets eps = 1e-7 and returns exactly the prescribed eigenvalues."""
+    now meets eps = 1e-7 and returns exactly the prescribed eigenvalues
+    (confirmed exit, opts.confirm)."""
     n, m0 = 4000, 200
     A, lam = W.dense_unit_disk(n, 12)
     c = 0.5 - 0.3j
@@ -315,7 +324,7 @@ def test_feast_fp64_bq_qr_retry_unit_disk_circle(handle):
     truth = np.sort_complex(lam[np.abs(lam - c) < r])
     assert len(truth) == 156
     prob = fh.Problem(handle, _cuda(A))
-    o = fh.default_opts(m0, precision=fh.FH_PREC_FP64, eps=1e-7, max_iter=40)
+    o = fh.default_opts(m0, precision=fh.FH_PREC_FP64, eps=1e-7, max_iter=40, confirm=1)
     out = fh.feast(prob, c, r, 1.0, 0.0, 16, _cuda(W.subspace(n, m0, 911)), _cuda(W.subspace(n, m0, 961)), o)
     assert out["info"] == 0
     got = np.sort_complex(out["lam"])

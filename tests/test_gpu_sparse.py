@@ -237,7 +237,10 @@ def test_filter_unpreconditioned_and_jacobi(handle, precond):
 def test_feast_complex_symmetric_small(handle, sym):
     """sym = 1: the left subspace is taken as the conjugate of the right one
     and only the right systems are solved (half the solves of sym = 0), with
-    the same eigenpairs."""
+    the same eigenpairs.  Its B_Q (and so its spurious flags) differ from the
+    oracle's, which filters the given left block: with the paper's exit it can
+    stop while pairs are still flagged, so it runs with the confirmed exit
+    (opts.confirm)."""
     A = W.schrodinger2d_csr(16, L=10.0, nwells=6, seed=4)
     Ad = W.csr_to_dense(A)
     ev = sla.eigvals(Ad)
@@ -250,7 +253,7 @@ def test_feast_complex_symmetric_small(handle, sym):
     ref = F.feast(L.csr_matrix(A), None, cont, Y0, Yh0, eps=1e-12, max_iter=40)
     prob = fh.Problem(handle, _csr(A))
     opts = fh.default_opts(16, solver=1, precond=2, inner_tol=1e-3, restart=30, max_restarts=2, eps=1e-12,
-                           max_iter=40, sym=sym)
+                           max_iter=40, sym=sym, confirm=sym)
     out = fh.feast(prob, c, r, 1.0, 0.0, 16, _cuda(Y0), _cuda(Yh0), opts)
     assert out["info"] == 0 and ref.info == 0
     assert out["report"]["n_solve"] == out["report"]["iters"] * 16 * (1 if sym else 2)

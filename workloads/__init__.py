@@ -289,40 +289,49 @@ def random_sparse_csr(n, density, seed, complex_vals=True, diag_shift=0.0):
 # --------------------------------------------------------------------------
 # Complex-symmetric 2D operator (fifth configuration and its small variants)
 # --------------------------------------------------------------------------
-def schrodinger2d_csr(N: int, L: float = 40.0, nwells: int = 50, depth: float = 20.0, sigma: float = 1.0,
-                      eta: float = 5.0, seed: int = 5):
-    """A = -Lap_h + diag(V) - i eta diag(W) on (0, L)^2, Dirichlet, 5-point,
-    h = L/(N+1), index = ix + N*iy.  V = -depth * sum of Gaussian wells (centres
-    area-uniform in [0.1L, 0.9L]^2); W = w(x1) + w(x2) with
-    w(t) = max(0, (|t - L/2| - 0.4L)/(0.1L))^2 (absorbing ramp on the outer 10%).
-    A is complex symmetric (A = A^T)."""
+def schrodinger2d_fields(N: int, L: float = 40.0, nwells: int = 50, depth: float = 20.0, sigma: float = 1.0,
+                         seed: int = 5):
+    """Potential V and absorbing profile W on the N x N interior grid of
+    (0, L)^2 (h = L/(N+1), row iy holds x1 = (ix+1) h): V = -depth * sum of
+    Gaussian wells (width sigma, centres area-uniform in [0.1L, 0.9L]^2),
+    W = w(x1) + w(x2) with w(t) = max(0, (|t - L/2| - 0.4L)/(0.1L))^2."""
     rng = np.random.default_rng(seed)
     h = L / (N + 1)
     x = (np.arange(N) + 1) * h
-    X1, X2 = np.meshgrid(x, x, indexing="xy")          # X1 varies fastest along a row
     cen = 0.1 * L + 0.8 * L * rng.random((nwells, 2))
-    V = np.zeros_like(X1)
+    V = np.zeros((N, N))
     for c1, c2 in cen:
-        V -= depth * np.exp(-((X1 - c1) ** 2 + (X2 - c2) ** 2) / (2 * sigma ** 2))
-    ramp = lambda t: np.maximum(0.0, (np.abs(t - L / 2) - 0.4 * L) / (0.1 * L)) ** 2
-    Wf = ramp(X1) + ramp(X2)
+        g1 = np.exp(-((x - c1) ** 2) / (2 * sigma ** 2))
+        g2 = np.exp(-((x - c2) ** 2) / (2 * sigma ** 2))
+        V -= depth * np.outer(g2, g1)                  # [iy, ix]
+    ramp = np.maximum(0.0, (np.abs(x - L / 2) - 0.4 * L) / (0.1 * L)) ** 2
+    Wf = ramp[None, :] + ramp[:, None]
+    return V, Wf, h
+
+
+def schrodinger2d_csr(N: int, L: float = 40.0, nwells: int = 50, depth: float = 20.0, sigma: float = 1.0,
+                      eta: float = 5.0, seed: int = 5):
+    """A = -Lap_h + diag(V) - i eta diag(W) on (0, L)^2, Dirichlet, 5-point,
+    h = L/(N+1), index = ix + N*iy, columns sorted within each row
+    (r - N, r - 1, r, r + 1, r + N).  V, W as in schrodinger2d_fields.
+    A is complex symmetric (A = A^T)."""
+    V, Wf, h = schrodinger2d_fields(N, L, nwells, depth, sigma, seed)
+    n = N * N
     diag = 4.0 / h ** 2 + V.ravel() - 1j * eta * Wf.ravel()
     off = -1.0 / h ** 2
-    n = N * N
-    rowptr = np.zeros(n + 1, dtype=np.int32)
-    cols, vals = [], []
-    for iy in range(N):
-        for ix in range(N):
-            r = ix + N * iy
-            if iy > 0:
-                cols.append(r - N); vals.append(off)
-            if ix > 0:
-                cols.append(r - 1); vals.append(off)
-            cols.append(r); vals.append(diag[r])
-            if ix < N - 1:
-                cols.append(r + 1); vals.append(off)
-            if iy < N - 1:
-                cols.append(r + N); vals.append(off)
-            rowptr[r + 1] = len(cols)
-    return {"n": n, "rowptr": rowptr, "colind": np.asarray(cols, dtype=np.int32),
-            "val": np.asarray(vals, dtype=np.complex128), "V": V, "W": Wf}
+    idx = np.arange(n, dtype=np.int64).reshape(N, N)        # [iy, ix]
+    ix = np.tile(np.arange(N), N)
+    iy = np.repeat(np.arange(N), N)
+    # per-row entry slots in column order: south, west, centre, east, north
+    has = np.stack([iy > 0, ix > 0, np.ones(n, bool), ix < N - 1, iy < N - 1], axis=1)
+    colv = np.stack([np.arange(n) - N, np.arange(n) - 1, np.arange(n), np.arange(n) + 1, np.arange(n) + N], axis=1)
+    valv = np.empty((n, 5), dtype=np.complex128)
+    valv[:, :] = off
+    valv[:, 2] = diag
+    cnt = has.sum(axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    rowptr[1:] = np.cumsum(cnt)
+    colind = colv[has].astype(np.int32)
+    val = valv[has]
+    del idx
+    return {"n": n, "rowptr": rowptr.astype(np.int32), "colind": colind, "val": val, "V": V, "W": Wf}
