@@ -288,6 +288,23 @@ int fh_count_estimate(fh_handle h, fh_problem p, int ne, const double* z, const 
 /* Step 2.a: BQ (m x m, device, row-major) = Qh^H B Q. */
 int fh_reduced_matrix(fh_handle h, fh_problem p, int m, const void* Qh, const void* Q, void* BQ);
 
+/* Allocation-free variant of fh_reduced_matrix, for callers that cannot
+ * allocate device memory during the call: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same operands and
+ * result (BQ = Qh^H B Q, m x m, device, row-major); it calls no hipMalloc,
+ * hipFree or allocator callback.  Its workspace (the split-K partial sums,
+ * and B Q when the problem has a B matrix) is a static device array of
+ * FH_NOALLOC_SCRATCH_BYTES per device, held from library load until the
+ * process ends, whose device address fh_create resolves once per device.
+ * Limits: m*m*16 bytes (plus n*m*16 with a B matrix) must fit in it,
+ * else -3 and fh_last_error says why.  Every call on one device shares that
+ * array and overwrites it (nothing in it has to start at zero); calls that
+ * overlap on one device, e.g. from two streams or threads, race.  When the
+ * partial sums of fh_reduced_matrix's split fit, the split and so the result
+ * are the same; otherwise a coarser split changes only the summation order. */
+#define FH_NOALLOC_SCRATCH_BYTES (32u << 20)
+int fh_reduced_matrix_noalloc(fh_handle h, fh_problem p, int m, const void* Qh, const void* Q, void* BQ);
+
 /* Steps 3.a-3.c on the GPU: B_Q = V Gamma Vh^H, sort by decreasing |gamma|
  * (stable), count m0t = #{|gamma_i| >= eta max|gamma|}, and return the
  * bi-orthonormalizing factors S = V[:, :m0t] Gamma^{-1/2} and

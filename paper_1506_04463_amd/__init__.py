@@ -148,6 +148,7 @@ def lib():
         "fh_feast": (i, [vp, vp, C.POINTER(fh_contour), dp, dp, C.POINTER(fh_opts), vp, vp, vp, dp,
                          C.POINTER(fh_report)]),
         "fh_reduced_matrix": (i, [vp, vp, i, vp, vp, vp]),
+        "fh_reduced_matrix_noalloc": (i, [vp, vp, i, vp, vp, vp]),
         "fh_biortho_factors": (i, [vp, i, vp, d, vp, vp, vp, ip]),
         "fh_count_estimate": (i, [vp, vp, i, dp, dp, i, vp, vp, dp, vp]),
         "fh_reduced_eig": (i, [vp, i, vp, vp, vp, vp, vp]),
@@ -457,6 +458,17 @@ def reduced_matrix(prob: Problem, Qh, Q):
     BQ = torch.empty((m, m), dtype=torch.complex128, device=Q.device)
     prob.handle.check(lib().fh_reduced_matrix(prob.handle._h, prob._p, m, _dptr(Qh), _dptr(Q), _dptr(BQ)),
                       "fh_reduced_matrix")
+    return BQ
+
+
+def reduced_matrix_noalloc(prob: Problem, Qh, Q, BQ):
+    """fh_reduced_matrix_noalloc: BQ (m x m complex128, caller's) = Qh^H B Q
+    with the library's static device scratch (no allocation in the call)."""
+    m = Q.shape[1]
+    if BQ.shape != (m, m) or not BQ.is_contiguous():
+        raise ValueError("BQ must be a contiguous (m, m) tensor")
+    prob.handle.check(lib().fh_reduced_matrix_noalloc(prob.handle._h, prob._p, m, _dptr(Qh), _dptr(Q), _dptr(BQ)),
+                      "fh_reduced_matrix_noalloc")
     return BQ
 
 

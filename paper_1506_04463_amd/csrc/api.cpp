@@ -1,8 +1,10 @@
 // extern "C" entry points of include/feasthip.h: argument checks, error
 // capture, dispatch to the driver.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <iterator>
+#include <mutex>
 
 #include "fh_internal.h"
 
@@ -43,6 +45,38 @@ Prob::~Prob() {
 
 static void set_device(Ctx* c) { FH_HIP(hipSetDevice(c->device)); }
 
+// ---------------------------------------------------------------------------
+// Device scratch of the allocation-free entry point (fh_reduced_matrix_noalloc):
+// one static array per device, resolved to its device address once per device
+// in fh_create.  Host code uses only the resolved addresses, never the array's
+// name.
+// ---------------------------------------------------------------------------
+static constexpr size_t kScratchBytes = size_t(FH_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static int resolve_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return FH_HIP_ERROR;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return FH_OK;
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return FH_HIP_ERROR;
+    if (hipSetDevice(device) != hipSuccess) return FH_HIP_ERROR;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess || ptr == nullptr) return FH_HIP_ERROR;
+    g_scratch_ptr[device] = ptr;
+    return FH_OK;
+}
+
+static void* scratch_of(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return (device >= 0 && device < kMaxDevices) ? g_scratch_ptr[device] : nullptr;
+}
+
 extern "C" {
 
 void fh_default_opts(fh_opts* o) {
@@ -77,6 +111,7 @@ int fh_create(fh_handle* h, int device, void* stream, const fh_allocator* alloc)
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return FH_HIP_ERROR;
     if (device < 0 || device >= ndev) return -2;
     if (alloc && (!alloc->alloc || !alloc->free)) return -4;
+    if (resolve_scratch(device) != FH_OK) return FH_HIP_ERROR;
     fh_ctx* c = new fh_ctx();
     c->device = device;
     c->stream = (hipStream_t)stream;
@@ -335,6 +370,46 @@ int fh_reduced_matrix(fh_handle h, fh_problem p, int m, const void* Qh, const vo
     FH_HIP(hipStreamSynchronize(h->stream));
     return FH_OK;
     FH_API_END(h)
+}
+
+int fh_reduced_matrix_noalloc(fh_handle h, fh_problem p, int m, const void* Qh, const void* Q, void* BQ) {
+    if (!h) return -1;
+    if (!p) return -2;
+    if (m < 1) return -3;
+    if (!Qh) return -4;
+    if (!Q) return -5;
+    if (!BQ) return -6;
+    const size_t part_min = sizeof(zd) * (size_t)m * m;         // one partial m x m block
+    const size_t bq_tmp = p->hasB ? sizeof(zd) * (size_t)p->n * m : 0;   // B Q
+    if (bq_tmp + part_min > kScratchBytes) {
+        h->err = "fh_reduced_matrix_noalloc: needs " + std::to_string(bq_tmp + part_min) +
+                 " bytes of scratch (m^2 * 16, plus n * m * 16 with a B matrix), more than its " +
+                 std::to_string(kScratchBytes);
+        return -3;
+    }
+    try {
+        FH_HIP(hipSetDevice(h->device));
+        unsigned char* base = (unsigned char*)scratch_of(h->device);
+        FH_REQUIRE(base != nullptr, FH_HIP_ERROR, "fh_reduced_matrix_noalloc: scratch not resolved for this device");
+        const zd* Bq = (const zd*)Q;
+        if (p->hasB) {
+            zd* t = (zd*)base;
+            apply_B(*h, *p, 0, m, (const zd*)Q, t);
+            Bq = t;
+        }
+        const size_t off = (bq_tmp + 255) / 256 * 256;
+        const bool ok = gemm_hn_tall_into(h->stream, p->n, m, m, (const zd*)Qh, m, Bq, m, (zd*)BQ, m, base + off,
+                                          kScratchBytes - off);
+        FH_REQUIRE(ok, -3, "fh_reduced_matrix_noalloc: m too large for the scratch");
+        FH_HIP(hipStreamSynchronize(h->stream));
+        return FH_OK;
+    } catch (const fh::Error& e) {
+        h->err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        h->err = e.what();
+        return FH_HIP_ERROR;
+    }
 }
 
 int fh_biortho_factors(fh_handle h, int m, const void* BQ, double eta, void* gamma, void* S, void* Sh, int* m0t) {

@@ -15,6 +15,12 @@ void gemm(hipStream_t st, char opA, char opB, int M, int N, int K, Cx<T> alpha, 
 // reduced in a fixed order (deterministic).
 void gemm_hn_tall(hipStream_t st, int n, int p, int q, const zd* X, long ldx, const zd* Y, long ldy, zd* C,
                   long ldc, DBuf& partial);
+// The same product with the partial sums in caller-provided device memory of
+// cap bytes (nothing allocated).  The split over n is the one gemm_hn_tall
+// uses when its partials fit in cap, else a coarser one.  Returns false (and
+// launches nothing) when not even one p x q partial fits.
+bool gemm_hn_tall_into(hipStream_t st, int n, int p, int q, const zd* X, long ldx, const zd* Y, long ldy, zd* C,
+                       long ldc, void* part, size_t cap);
 
 // Column 1-norms for eq:res: num_c = sum_i |AY_ic - lam_c BY_ic|,
 // den_c = sum_i |BY_ic| over an n x m block (ld).  lam: device, m.

@@ -107,19 +107,47 @@ __global__ void k_reduce_parts(int parts, int p, int q, const zd* __restrict__ P
     C[(long)(e / q) * ldc + (e % q)] = s;
 }
 
-void gemm_hn_tall(hipStream_t st, int n, int p, int q, const zd* X, long ldx, const zd* Y, long ldy, zd* C,
-                  long ldc, DBuf& partial) {
-    if (p <= 0 || q <= 0) return;
-    int chunk = 256;
-    int parts = ceil_div(n, chunk);
-    if (parts > 1024) { chunk = ceil_div(n, 1024); chunk = (chunk + 15) / 16 * 16; parts = ceil_div(n, chunk); }
-    zd* P = (zd*)partial.ensure(sizeof(zd) * (size_t)parts * p * q);
+// split of the n rows into `parts` chunks of `chunk` rows (multiple of 16 when
+// coarsened) with at most max_parts parts
+static void tall_split(int n, int max_parts, int& chunk, int& parts) {
+    chunk = 256;
+    parts = ceil_div(n, chunk);
+    if (parts > max_parts) {
+        chunk = ceil_div(n, max_parts);
+        chunk = (chunk + 15) / 16 * 16;
+        parts = ceil_div(n, chunk);
+    }
+}
+
+static void tall_launch(hipStream_t st, int n, int p, int q, const zd* X, long ldx, const zd* Y, long ldy, zd* C,
+                        long ldc, zd* P, int chunk, int parts) {
     dim3 grid(ceil_div(q, GT), ceil_div(p, GT), parts);
     k_gemm<double, true, false><<<grid, 256, 0, st>>>(p, q, n, cx(1.0, 0.0), X, ldx, (long)chunk * ldx, Y, ldy,
                                                        (long)chunk * ldy, czero<double>(), P, q, (long)p * q, chunk);
     FH_LAUNCH_CHECK();
     k_reduce_parts<<<ceil_div((size_t)p * q, 256), 256, 0, st>>>(parts, p, q, P, C, ldc);
     FH_LAUNCH_CHECK();
+}
+
+bool gemm_hn_tall_into(hipStream_t st, int n, int p, int q, const zd* X, long ldx, const zd* Y, long ldy, zd* C,
+                       long ldc, void* part, size_t cap) {
+    if (p <= 0 || q <= 0) return true;
+    const size_t per = sizeof(zd) * (size_t)p * q;
+    const size_t fit = cap / per;
+    if (fit < 1) return false;
+    int chunk, parts;
+    tall_split(n, (int)std::min<size_t>(fit, 1024), chunk, parts);
+    tall_launch(st, n, p, q, X, ldx, Y, ldy, C, ldc, (zd*)part, chunk, parts);
+    return true;
+}
+
+void gemm_hn_tall(hipStream_t st, int n, int p, int q, const zd* X, long ldx, const zd* Y, long ldy, zd* C,
+                  long ldc, DBuf& partial) {
+    if (p <= 0 || q <= 0) return;
+    int chunk, parts;
+    tall_split(n, 1024, chunk, parts);
+    zd* P = (zd*)partial.ensure(sizeof(zd) * (size_t)parts * p * q);
+    tall_launch(st, n, p, q, X, ldx, Y, ldy, C, ldc, P, chunk, parts);
 }
 
 // ---------------------------------------------------------------------------
