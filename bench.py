@@ -1,19 +1,22 @@
 """Benchmark: non-Hermitian FEAST iterations per second on one MI355X.
 
-Workload: 2D convection-diffusion, 5-point central differences on a 256 x 256
-grid (n = 65,536, real CSR), Peclet 20 along (1, 0.5), B = I; ellipse
-(ratio 0.3) around the 41 lowest eigenvalues; Ne = 16 trapezoidal nodes,
-m0 = 64.  Shifted systems: column-batched GMRES(30) + ILU(0) on all
-2 x 16 x 64 = 2,048 right-hand sides at once, with the residual form of the
-filter from the second iteration on.
+Headline workload (default, the largest configuration): the complex-symmetric
+2D operator A = -Lap_h + V - 5i W on a 1024 x 1024 grid (n = 1,048,576;
+50 Gaussian wells of depth 20, absorbing ramp on the outer 10 %, B = I),
+ellipse centred in the lower half-plane around its 121 lowest eigenvalues,
+Ne = 24 trapezoidal nodes, m0 = 160.  Shifted systems: column-batched
+GMRES(30) x 2 cycles + ILU(0) with delayed reorthogonalization on the
+24 x 160 right-hand sides of a filter (the left block is conj(Y) D: complex
+symmetric), residual form of the filter from the second iteration on.
 
 A "step" is one full FEAST iteration (contour filter, B_Q, resize and
 B-bi-orthonormalization, Rayleigh-Ritz, residuals).  The fast path (complex
-FP32 inner solves + FP64 refinement) is timed over exactly K steps after W
-warm-up steps; the plain FP64 path is timed the same way for the comparison.
-A separate solve from the seeded start to eq:res <= 1e-10 gives the
-time-to-solution and the checked eigenpairs (count, residuals, eigenvalues
-against the closed-form spectrum).
+FP32 Krylov solves, FP64 residual form and Rayleigh-Ritz) is timed over
+exactly K steps after W warm-up steps, then continued to eq:res <= 1e-9 and
+its eigenpairs checked against reference eigenvalues; the plain FP64 path
+(the same solver in complex128) is timed for the comparison.  The 2D
+convection-diffusion workload (256 x 256) and the others stay available with
+--workload.
 """
 from __future__ import annotations
 
@@ -477,19 +480,254 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
 
 
+# --------------------------------------------------------------------------
+# headline workload: the complex-symmetric 2D operator on the 1024 x 1024 grid
+# --------------------------------------------------------------------------
+C5_GOLDEN = os.path.join(ROOT, "tests", "golden", "schrodinger2d_N1024_lowest.json")
+
+
+def _c5_eigs(path):
+    if path.endswith(".npy"):
+        return np.load(path)
+    with open(path) as f:
+        d = json.load(f)
+    return np.array([complex(a, b) for a, b in d["eigenvalues"]])
+
+
+def _c5_opts(fh, m0, precision, max_iter, eps, resume=0, precond=None):
+    # GMRES(30), two cycles per solve, residual-form filter (the FP64
+    # eigen-residual R = A Y - Y Lambda is the right-hand side of every filter
+    # from the second FEAST iteration on, so the outer FEAST iteration refines
+    # the complex-FP32 solves in FP64); one FP64 residual check per solve
+    # (max_refine = 1: no inner correction step); delayed reorthogonalization
+    # (DCGS2) on both precisions; right solves only with the left block
+    # conj(Y) D (complex symmetric, opts.sym = 1) on both precisions
+    return fh.default_opts(m0, solver=fh.FH_SOLVER_BGMRES, precond=fh.FH_PC_ILU0 if precond is None else precond,
+                           restart=30, max_restarts=2, inner_tol=1e-3, precision=precision, mixed_inner_tol=1e-3,
+                           max_refine=1, max_iter=max_iter, eps=eps, resume=resume, orth=2, sym=1)
+
+
+def _c5_cpu_baseline(p, sample_cols=8):
+    """The oracle on the host cores: one worker process per quadrature node
+    (as many as there are cores, at most Ne), each factorizing (z_j - A) with
+    SuperLU and solving a sample of right-hand-side columns with the oracle's
+    direct solve; scaled to a FEAST iteration's filter (Ne nodes, m0 right
+    solves each -- the same right-solves-only work as the GPU path)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    ne, m0 = p.contour.ne, p.m0
+    cores = min(ne, max(1, len(os.sched_getaffinity(0))), int(os.environ.get("OMP_NUM_THREADS", "64")))
+    z = _c5_nodes(p)
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=cores, mp_context=ctx) as ex:
+        futs = [ex.submit(_c5_cpu_node, p.info["N"], complex(z[j]), sample_cols) for j in range(cores)]
+        res = [f.result() for f in futs]
+    wall = time.perf_counter() - t0
+    t_fact = max(r[0] for r in res)
+    t_col = max(r[1] for r in res) / sample_cols
+    per_node = t_fact + t_col * m0
+    rounds = -(-ne // cores)
+    t_iter = rounds * per_node
+    return {"value": 1.0 / t_iter, "unit": "FEAST iterations/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} nodes in parallel processes (one per core): SuperLU factorization of z_j - A "
+                      f"({t_fact:.1f} s) and {sample_cols} right-hand-side columns ({t_col:.2f} s each), "
+                      f"{wall:.1f} s wall; scaled to {ne} nodes x {m0} columns ({rounds} rounds of "
+                      f"{per_node:.1f} s), the filter only"}
+
+
+def _c5_nodes(p):
+    from oracle import contour as ct
+    c = p.contour
+    z, _ = ct.ellipse_nodes(c.center, c.a, c.ratio, c.angle, c.ne)
+    return z
+
+
+def _c5_cpu_node(N, zj, cols):
+    import workloads as W
+    from threadpoolctl import threadpool_limits
+    from oracle import linsolve as L
+    with threadpool_limits(limits=1):
+        A = L.csr_matrix(W.schrodinger2d_csr(N))
+        t0 = time.perf_counter()
+        F = L.DirectFactor(L.shifted(A, None, zj))
+        t1 = time.perf_counter()
+        F.solve(W.subspace(A.shape[0], cols, 77), "N")
+        t2 = time.perf_counter()
+    return t1 - t0, t2 - t1
+
+
+def schrodinger(args):
+    """Headline workload: A = -Lap_h + V - 5i W on the 1024 x 1024 grid
+    (n = 1,048,576, complex symmetric), ellipse centred in the lower
+    half-plane around its 121 lowest eigenvalues, Ne = 24, m0 = 160.  The fast
+    path (complex-FP32 GMRES(30) x 2 + ILU(0), FP64 residual form) and the
+    plain FP64 path (the same solver in complex128) are timed per FEAST
+    iteration; the fast run then continues to eq:res <= 1e-9 and its
+    eigenpairs are checked against the reference eigenvalues (ARPACK
+    shift-invert, tests/golden) and for X^H X = I, Xh = conj(X) and the
+    spec residual."""
+    import torch
+    import workloads as W
+    import paper_1506_04463_amd as fh
+
+    N = args.grid
+    eigs = _c5_eigs(args.eigs or C5_GOLDEN)
+    p = W.schrodinger2d(N=N, eigs=eigs, m0=160, ne=24)
+    c = p.contour
+    A = p.A
+    handle = fh.Handle(0)
+    prob = fh.Problem(handle, fh.CSR(torch.from_numpy(A["rowptr"]).cuda(), torch.from_numpy(A["colind"]).cuda(),
+                                     torch.from_numpy(A["val"]).cuda(), p.n))
+    alpha = abs(c.center) + max(c.a, c.ratio * c.a)
+    print(f"[bench] {p.name}: n={p.n} nnz={len(A['colind'])} ellipse c={c.center:.4f} a={c.a:.4f} ratio={c.ratio} "
+          f"({p.info['m_in']} reference eigenvalues inside) Ne={c.ne} m0={p.m0}", file=sys.stderr, flush=True)
+    ne = c.ne
+
+    def feast(Y, Yh, o, ritz=None):
+        return fh.feast(prob, c.center, c.a, c.ratio, c.angle, ne, Y, Yh, o, ritz0=ritz)
+
+    Y0 = torch.from_numpy(p.Y0).cuda()
+    Yh0 = torch.from_numpy(p.Yh0).cuda()
+    # fast path: warm-up iterations, K timed ones, then on to convergence
+    t_all = time.perf_counter()
+    out = feast(Y0, Yh0, _c5_opts(fh, p.m0, fh.FH_PREC_MIXED, args.warmup, 1e-300))
+    done_it = out["report"]["iters"]
+    print(f"[bench] fast path: {done_it} warm-up iteration(s), {time.perf_counter() - t_all:.1f} s", file=sys.stderr,
+          flush=True)
+    Y, Yh, ritz = out["Y"].contiguous(), out["Yh"].contiguous(), out["ritz"]
+    handle.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = feast(Y, Yh, _c5_opts(fh, Y.shape[1], fh.FH_PREC_MIXED, args.steps, 1e-300, 1), ritz)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = handle.profile_stats()
+    handle.profile(False)
+    ms_mx = 1000.0 * dt / args.steps
+    rep_mx = out["report"]
+    done_it += rep_mx["iters"]
+    print(f"[bench] fast path: {ms_mx:.1f} ms per FEAST iteration ({args.steps} timed)", file=sys.stderr, flush=True)
+    valid = None
+    if not args.no_validate:
+        Y, Yh, ritz = out["Y"].contiguous(), out["Yh"].contiguous(), out["ritz"]
+        t1 = time.perf_counter()
+        fin = feast(Y, Yh, _c5_opts(fh, Y.shape[1], fh.FH_PREC_MIXED, args.max_iter, EPS_ITER, 1), ritz)
+        torch.cuda.synchronize()
+        valid = _c5_validate(fh, torch, prob, p, fin, eigs, alpha)
+        valid["iterations"] = done_it + fin["report"]["iters"]
+        valid["time_to_solution_s"] = time.perf_counter() - t_all
+        print(f"[bench] validation: {json.dumps(valid)}", file=sys.stderr, flush=True)
+    del Y, Yh
+    plain = None
+    if not args.no_fp64:
+        torch.cuda.empty_cache()
+        K64 = max(1, args.fp64_steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o64 = feast(Y0, Yh0, _c5_opts(fh, p.m0, fh.FH_PREC_FP64, K64, 1e-300))
+        torch.cuda.synchronize()
+        dt64 = time.perf_counter() - t0
+        last = o64["report"]["t_iter_ms"]
+        plain = {"ms_per_step": last, "ms_mean_incl_first": 1000.0 * dt64 / K64, "steps": K64,
+                 "value": 1000.0 / last}
+        print(f"[bench] plain FP64: {last:.1f} ms for its last iteration ({1000.0 * dt64 / K64:.1f} ms mean over "
+              f"{K64} incl. set-up)", file=sys.stderr, flush=True)
+    dom = max(stats.items(), key=lambda kv: kv[1]["ms"])
+    name, st = dom
+    achieved = st["bytes"] / (st["ms"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": _traffic(name), "avg_ms": st["ms"] / st["count"],
+            "launches": st["count"], "bytes_per_launch": st["bytes"] / st["count"],
+            "share_of_step": st["ms"] / (args.steps * ms_mx)}
+    kernels = {k: {"ms_total": v["ms"], "count": v["count"], "share": v["ms"] / (args.steps * ms_mx),
+                   "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["bytes"] else None,
+                   "frac_hbm": (v["bytes"] / (v["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS) if v["bytes"] else None}
+               for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])[:10]}
+    cpu = None if args.no_cpu else _c5_cpu_baseline(p)
+    rhs = ne * p.m0
+    line = {
+        "metric": "FEAST iterations/sec & shifted-solve RHS/s at residual <=1e-10 vs plain FP64",
+        "value": 1000.0 / ms_mx, "unit": "FEAST iterations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_mx, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64 (Krylov solves) + f64/c128 (residual form, Rayleigh-Ritz)",
+        "data": "synthetic",
+        "config": {"workload": f"complex-symmetric -Lap+V-5iW {N}x{N} (n={p.n}, nnz={len(A['colind'])}), "
+                               f"50 wells, ellipse in the lower half-plane around {p.info['m_in']} eigenvalues, "
+                               f"Ne={ne}, m0={p.m0}",
+                   "solver": "GMRES(30) x 2 cycles + ILU(0), DCGS2, right solves only (sym), residual form",
+                   "rhs_per_iteration": rhs},
+        "rhs_per_s": rhs * 1000.0 / ms_mx,
+        "rhs_solve": f"{ne} x {p.m0} right-hand sides per iteration, each 2 GMRES(30) cycles; worst relative "
+                     f"residual of the last timed filter {rep_mx['inner_relres']:.2e} (the FEAST exit, "
+                     f"eq:res <= {EPS_ITER:g}, is what the eigenpairs are held to)",
+        "plain_fp64": plain,
+        "speedup_vs_fp64": None if plain is None else plain["ms_per_step"] / ms_mx,
+        "validity": valid, "roofline": roof, "kernels": kernels, "cpu_baseline": cpu}
+    print(json.dumps(line))
+
+
+def _c5_validate(fh, torch, prob, p, fin, eigs, alpha):
+    """Returned eigenpairs against the reference eigenvalues inside the
+    contour (count and complex distance), X^H X = I, Xh parallel to conj(X)
+    and the spec residual ||A x - lam x||_1 / (||A||_1 ||x||_1) of both
+    sides, with A x from the library's sparse product."""
+    c = p.contour
+    u = (eigs - c.center) * np.exp(-1j * c.angle)
+    ref_in = eigs[(u.real / c.a) ** 2 + (u.imag / (c.ratio * c.a)) ** 2 < 1.0]
+    lam = fin["lam"]
+    m = len(lam)
+    out = {"converged": fin["info"] == 0, "m": m, "m_reference_inside": int(len(ref_in)),
+           "m_s": fin["report"]["m_s"]}
+    if m == 0:
+        return out
+    d = np.abs(lam[:, None] - ref_in[None, :]).min(axis=1)
+    out["max_dlam_over_alpha"] = float(d.max() / alpha)
+    X, Xh = fin["X"], fin["Xh"]
+    G = (Xh.conj().T @ X).cpu().numpy()
+    out["max_abs_XhX_minus_I"] = float(np.max(np.abs(G - np.eye(m))))
+    cosang = (torch.abs((torch.conj(X) * torch.conj(Xh)).sum(0)) /
+              (torch.linalg.vector_norm(X, dim=0) * torch.linalg.vector_norm(Xh, dim=0))).cpu().numpy()
+    out["min_cos_Xh_conjX"] = float(cosang.min())
+    A = p.A
+    normA = float(np.max(np.bincount(A["colind"], weights=np.abs(A["val"]), minlength=A["n"])))
+    worst = 0.0
+    for side, V, lv in ((0, X, lam), (1, Xh, np.conj(lam))):
+        for k0 in range(0, m, 32):
+            k1 = min(m, k0 + 32)
+            blk = V[:, k0:k1].contiguous()
+            AX = -fh.shifted_apply(prob, side, np.zeros(1), blk.unsqueeze(0))[0]        # A x (or A^H x)
+            lt = torch.from_numpy(np.ascontiguousarray(lv[k0:k1])).to(blk.device)
+            r = torch.abs(AX - blk * lt[None, :]).sum(0) / (normA * torch.abs(blk).sum(0))
+            worst = max(worst, float(r.max()))
+    out["max_rel_residual"] = worst
+    out["max_eq_res"] = float(np.max(fin["res"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=16)
-    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=None, help="timed FEAST iterations (default: 2 on the headline "
+                                                              "workload, 16 on convdiff)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed warm-up iterations (default 1 / 4)")
+    ap.add_argument("--fp64-steps", type=int, default=2, help="headline workload: plain FP64 iterations (the last "
+                                                               "one's time is reported)")
+    ap.add_argument("--max-iter", type=int, default=30, help="headline workload: iteration limit of the "
+                                                             "validation run")
+    ap.add_argument("--grid", type=int, default=1024, help="headline workload: grid points per side")
+    ap.add_argument("--eigs", default=None, help="headline workload: reference eigenvalues (.npy or the golden "
+                                                 "JSON; default the 1024 x 1024 one)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-validate", action="store_true")
     ap.add_argument("--columns", type=int, default=128, help="learned3d: columns per system")
-    ap.add_argument("--workload", default="convdiff", choices=["convdiff", "dense-batch", "copy-calibration",
-                                                              "learned3d", "csym", "contour-grid"],
-                    help="convdiff: the headline sparse workload (default); dense-batch: 64 dense problems; "
-                         "copy-calibration: a 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--workload", default="schrodinger",
+                    choices=["schrodinger", "convdiff", "dense-batch", "copy-calibration", "learned3d", "csym",
+                             "contour-grid"],
+                    help="schrodinger: the headline workload, complex-symmetric 1024 x 1024 (default); convdiff: "
+                         "2D convection-diffusion 256 x 256; dense-batch: 64 dense problems; copy-calibration: a "
+                         "1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--count", type=int, default=64, help="dense-batch: number of problems")
     ap.add_argument("--orth", type=int, default=2, choices=[0, 1, 2],
                     help="GMRES orthogonalization: 0 CGS2, 1 one projection, 2 delayed reorthogonalization "
@@ -497,6 +735,10 @@ def main():
     args = ap.parse_args()
     global ORTH
     ORTH = args.orth
+    if args.steps is None:
+        args.steps = 2 if args.workload == "schrodinger" else 16
+    if args.warmup is None:
+        args.warmup = 1 if args.workload == "schrodinger" else 4
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of the "
               "contour filter (one node group per GPU) is a design only and not built", file=sys.stderr)
@@ -515,6 +757,9 @@ def main():
         return
     if args.workload == "contour-grid":
         contour_grid(args)
+        return
+    if args.workload == "schrodinger":
+        schrodinger(args)
         return
     import torch
     import paper_1506_04463_amd as fh

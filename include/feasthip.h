@@ -123,9 +123,9 @@ typedef struct {
                              2 = delayed reorthogonalization (the second
                              projection of each vector shares the next step's
                              pass: two passes over the basis per step instead
-                             of three); 2 applies to complex-FP32 solves with
-                             restart <= 31 and at most 128 columns per
-                             system, other solves use 0 */
+                             of three); 2 applies when restart <= 31 (FP64
+                             and complex-FP32 solves alike), longer cycles
+                             use 0 */
     int batch_nodes;      /* sparse filter: quadrature nodes whose right and
                              left systems are solved together (their Krylov
                              bases live in device memory at once); 0 = as many
@@ -135,13 +135,16 @@ typedef struct {
                              inner tolerances */
     int sym;              /* sparse problems: 1 = complex symmetric (A = A^T).
                              The left eigenvectors are then the conjugates of
-                             the right ones, so the filter takes Qh = conj(Q)
-                             and solves only the n_e right systems instead of
-                             2 n_e (paper, reduced-workload cases, complex
-                             symmetric; Table tab:solve); Yh is not read by
-                             the filter.  The call returns -2 if A is not
-                             symmetric.  0 = general.  Dense problems ignore
-                             it */
+                             the right ones, so the filter solves only the
+                             n_e right systems instead of 2 n_e (paper,
+                             reduced-workload cases, complex symmetric; Table
+                             tab:solve) and takes for the left block
+                             Qh = conj(Q) D, D = diag(conj(1 / (y_i^T y_i))):
+                             the left filter of conj(Y) D, the left block
+                             with yh_i^H y_i = 1 that FEAST's left Ritz
+                             vectors have; Yh is not read by the filter.  The
+                             call returns -2 if A is not symmetric.
+                             0 = general.  Dense problems ignore it */
     int confirm;          /* exit rule.  0 (default) = the paper's steps 5.c /
                              5.d: with m_r Ritz values inside and m_s flagged
                              spurious, converged when the m = m_r - m_s

@@ -37,6 +37,9 @@ void replicate(hipStream_t st, long len, const Cx<T>* src, Cx<T>* dst, int copie
 
 // dst = conj(src), elementwise
 void conj_copy(hipStream_t st, long len, const zd* src, zd* dst);
+// Qh = conj(Q) diag(conj(1 / s)), s_c = sum_r Y[r][c]^2 (n x m row-major blocks):
+// the filter of the left block conj(Y) D that satisfies yh_c^H y_c = 1
+void conj_copy_bilin(hipStream_t st, int n, int m, const zd* Y, const zd* Q, zd* Qh, DBuf& part);
 
 // cast between complex precisions
 template <typename D, typename S>

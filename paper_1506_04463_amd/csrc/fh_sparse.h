@@ -115,7 +115,7 @@ struct DcgsState {
     int* kuse = nullptr;
     DBuf* part = nullptr;
 };
-// Step k of DCGS2 Arnoldi (complex FP32 basis, k <= 32): W = A z_k holds the
+// Step k of DCGS2 Arnoldi (complex FP32 or FP64 basis, k <= 32): W = A z_k holds the
 // new vector on entry; V_k is reorthogonalized in place and W becomes the
 // tentative V_{k+1}; Hessenberg column k - 1 is finalized and rotated.
 // final != 0 (W = nullptr): only finalize column k - 1.

@@ -254,6 +254,49 @@ void conj_copy(hipStream_t st, long len, const zd* src, zd* dst) {
     FH_LAUNCH_CHECK();
 }
 
+// Left block of a complex symmetric filter: Qh = conj(Q) D with
+// D = diag(conj(1 / s_c)), s_c = sum_r Y[r][c]^2 (bilinear, no conjugate).
+// Partial sums of s per chunk of rows, one thread per column
+__global__ void k_bilin_partial(int n, int m, const zd* __restrict__ Y, int rows, zd* __restrict__ part) {
+    const int c = threadIdx.x, ch = blockIdx.x;
+    if (c >= m) return;
+    const int r0 = ch * rows, r1 = min(n, r0 + rows);
+    zd s = czero<double>();
+    for (int r = r0; r < r1; ++r) {
+        const zd y = Y[(long)r * m + c];
+        cfma(s, y, y);
+    }
+    part[(long)ch * m + c] = s;
+}
+__global__ void k_bilin_scale(int nch, int m, const zd* __restrict__ part, const zd* __restrict__ Y0, zd* __restrict__ d) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    zd s = czero<double>();
+    for (int ch = 0; ch < nch; ++ch) s = s + part[(long)ch * m + c];
+    const double a = cabs(s);
+    // a quasi-null column (y^T y = 0) keeps the plain conjugate
+    d[c] = (a > 0.0 && std::isfinite(a)) ? conj(cdiv(cx(1.0, 0.0), s)) : cx(1.0, 0.0);
+}
+__global__ void k_conj_copy_cols(long len, int m, const zd* __restrict__ src, const zd* __restrict__ d,
+                                 zd* __restrict__ dst) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= len) return;
+    dst[e] = conj(src[e]) * d[e % m];
+}
+void conj_copy_bilin(hipStream_t st, int n, int m, const zd* Y, const zd* Q, zd* Qh, DBuf& part) {
+    if (n <= 0 || m <= 0) return;
+    const int rows = 256, nch = ceil_div(n, rows);
+    zd* P = (zd*)part.ensure(sizeof(zd) * ((size_t)nch * m + m));
+    zd* d = P + (size_t)nch * m;
+    k_bilin_partial<<<nch, ((m + 63) / 64) * 64, 0, st>>>(n, m, Y, rows, P);
+    FH_LAUNCH_CHECK();
+    k_bilin_scale<<<ceil_div(m, 64), 64, 0, st>>>(nch, m, P, Y, d);
+    FH_LAUNCH_CHECK();
+    const long len = (long)n * m;
+    k_conj_copy_cols<<<ceil_div(len, 256), 256, 0, st>>>(len, m, Q, d, Qh);
+    FH_LAUNCH_CHECK();
+}
+
 template <typename D, typename S>
 __global__ void k_cast(long len, const Cx<S>* __restrict__ src, Cx<D>* __restrict__ dst) {
     long e = (long)blockIdx.x * blockDim.x + threadIdx.x;

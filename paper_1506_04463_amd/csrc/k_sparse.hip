@@ -49,27 +49,31 @@ __global__ void k_spmm(int n, int m, const int* __restrict__ rowptr, const int* 
     Out[base + (long)r * m + c] = res;
 }
 
-// Same product for rows of at most SL entries (m >= 16 columns per system):
+// Same product for rows of at most SL entries (column blocks of >= 16 columns):
 // the block first stages its rows' entries in LDS as a padded SL-slot table
 // (empty slots point at the row itself with weight zero), then every thread
 // issues the gathers of its RPT rows together, so that a wave keeps RPT x SL
 // independent loads in flight instead of walking one row's chain of
 // dependent loads (row pointer, column index, then the gathered value).
-// block (m, ry), grid (ceil(n / (ry RPT)), nsys); rows r0 + ty + j ry.
+// A workgroup covers cb of the m columns of a system (blockIdx.y = system *
+// ncb + column block; the last block may be partial) and ry * RPT rows:
+// block (cb, ry), grid (ceil(n / (ry RPT)), nsys * ncb); rows r0 + ty + j ry.
 template <typename T, typename TA, bool CONJ, int SL, int RPT>
-__global__ __launch_bounds__(256) void k_spmm_rows(int n, int m, const int* __restrict__ rowptr,
+__global__ __launch_bounds__(256) void k_spmm_rows(int n, int m, int cb, int ncb, const int* __restrict__ rowptr,
                                                    const int* __restrict__ col, const TA* __restrict__ val,
                                                    const Cx<T>* __restrict__ shifts, T alpha,
                                                    const Cx<T>* __restrict__ X, const Cx<T>* __restrict__ Yadd,
                                                    Cx<T>* __restrict__ Out) {
-    constexpr int MAXR = 16 * RPT;                    // ry <= 16 (m >= 16)
+    constexpr int MAXR = 16 * RPT;                    // ry <= 16 (cb >= 16)
     __shared__ int s_col[MAXR * SL];
     __shared__ TA s_val[MAXR * SL];
-    const int c = threadIdx.x, ty = threadIdx.y, ry = blockDim.y;
+    const int tx = threadIdx.x, ty = threadIdx.y, ry = blockDim.y;
     const int rows = ry * RPT;
     const int r0 = blockIdx.x * rows;
-    const int s = blockIdx.y;
-    const int tid = ty * m + c, nt = m * ry;
+    const int s = blockIdx.y / ncb;
+    const int c = (blockIdx.y % ncb) * cb + tx;
+    const bool act = c < m;
+    const int tid = ty * cb + tx, nt = cb * ry;
     for (int idx = tid; idx < rows * SL; idx += nt) {
         const int rl = idx / SL, q = idx - rl * SL;
         const int r = r0 + rl;
@@ -84,6 +88,7 @@ __global__ __launch_bounds__(256) void k_spmm_rows(int n, int m, const int* __re
         s_val[idx] = vv;
     }
     __syncthreads();
+    if (!act) return;
     const long base = (long)s * n * m;
     const Cx<T>* Xs = X + base;
     Cx<T> xv[RPT][SL];
@@ -110,19 +115,31 @@ __global__ __launch_bounds__(256) void k_spmm_rows(int n, int m, const int* __re
     }
 }
 
+// column block of k_spmm_rows: all m columns when they divide 256 (one or
+// more rows per wave), else the largest of 64, 32, 16 that divides m, else 32
+// with a partial last block
+static int spmm_colblock(int m) {
+    if (m <= 256 && 256 % m == 0) return m;
+    for (int cb : {64, 32, 16})
+        if (m % cb == 0) return cb;
+    return 32;
+}
+
 template <typename T, typename TA, bool CONJ, int SL, int RPT>
 static void spmm_rows_launch(hipStream_t st, int n, int m, int nsys, const CsrDev& A, const TA* v,
                              const Cx<T>* shifts, T alpha, const Cx<T>* X, const Cx<T>* Yadd, Cx<T>* Out) {
-    const int ry = 256 / m;
-    dim3 blk(m, ry), grid(ceil_div(n, ry * RPT), nsys);
-    k_spmm_rows<T, TA, CONJ, SL, RPT><<<grid, blk, 0, st>>>(n, m, A.rowptr, A.col, v, shifts, alpha, X, Yadd, Out);
+    const int cb = spmm_colblock(m), ncb = ceil_div(m, cb);
+    const int ry = 256 / cb;
+    dim3 blk(cb, ry), grid(ceil_div(n, ry * RPT), nsys * ncb);
+    k_spmm_rows<T, TA, CONJ, SL, RPT><<<grid, blk, 0, st>>>(n, m, cb, ncb, A.rowptr, A.col, v, shifts, alpha, X, Yadd,
+                                                            Out);
 }
 
 template <typename T, typename TA, bool CONJ>
 static bool spmm_rows(hipStream_t st, int n, int m, int nsys, const CsrDev& A, const TA* v, const Cx<T>* shifts,
                       T alpha, const Cx<T>* X, const Cx<T>* Yadd, Cx<T>* Out) {
-    // whole warps of columns, at most 16 row groups per block
-    if (m < 16 || m > 256 || 256 % m != 0 || A.maxrow < 1) return false;
+    // column blocks of at least 16 columns: at most 16 row groups per block
+    if (m < 16 || m > 256 || A.maxrow < 1) return false;
     if (A.maxrow <= 5) spmm_rows_launch<T, TA, CONJ, 5, 4>(st, n, m, nsys, A, v, shifts, alpha, X, Yadd, Out);
     else if (A.maxrow <= 8) spmm_rows_launch<T, TA, CONJ, 8, 4>(st, n, m, nsys, A, v, shifts, alpha, X, Yadd, Out);
     else if (A.maxrow <= 16) spmm_rows_launch<T, TA, CONJ, 16, 2>(st, n, m, nsys, A, v, shifts, alpha, X, Yadd, Out);
@@ -622,17 +639,18 @@ __device__ __forceinline__ void sweep_lds(const SweepDev& sw, int n, int m, int 
 //    repeats the level's last one: same inputs, same value, same address;
 //  * absent dependencies (slot < 0) contribute a selected zero;
 //  * the level pointers are read through the scalar cache.
-template <typename T, int P, int KM>
+template <typename T, int P, int KM, int FR>
 struct SwPipe {
     int row[P];          // row indices of a level (loaded six levels ahead)
     Cx<T> x[P];          // inputs of a level (three levels ahead)
     int off[P];          // element offsets of those inputs / outputs
-    int fslot[KM];       // one row's factor data (four levels ahead)
-    Cx<T> fv[KM];
-    Cx<T> fd;
+    int fslot[FR][KM];   // factor data of FR rows (four levels ahead)
+    Cx<T> fv[FR][KM];
+    Cx<T> fd[FR];
 };
 
-template <typename T, int P, int KM, int NT>
+// FR: level rows whose factor data each thread loads (levels of up to NT * FR rows)
+template <typename T, int P, int KM, int NT, int FR>
 __device__ __forceinline__ void sweep_pipe(const SweepDev& sw, int n, int m, int c0, int cw,
                                            const Cx<T>* __restrict__ val, const Cx<T>* __restrict__ dval,
                                            const Cx<T>* In, Cx<T>* Os, Cx<T>* ring, int ring_stride,
@@ -658,36 +676,44 @@ __device__ __forceinline__ void sweep_pipe(const SweepDev& sw, int n, int m, int
         const int t0 = lp[L], rows = lp[L + 1] - t0;
         return min(t0 + min(r, rows - 1), n - 1);
     };
-    auto load_row = [&](int l, SwPipe<T, P, KM>& s) {
+    using SP = SwPipe<T, P, KM, FR>;
+    auto load_row = [&](int l, SP& s) {
 #pragma unroll
         for (int q = 0; q < P; ++q) s.row[q] = sw.rows[pos_of(l, ediv[q])];
     };
-    auto load_x = [&](SwPipe<T, P, KM>& s) {
+    auto load_x = [&](SP& s) {
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             s.off[q] = s.row[q] * m + c0 + emod[q];
             s.x[q] = In[s.off[q]];
         }
     };
-    auto load_fac = [&](int l, SwPipe<T, P, KM>& s) {
-        const int t = pos_of(l, tid);
+    auto load_fac = [&](int l, SP& s) {
 #pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            const int kk = k < K ? k : 0;
-            s.fslot[k] = sw.ell_slot[(long)kk * n + t];
-            s.fv[k] = val[(long)kk * n + t];
-        }
-        s.fd = dsrc[t];
-    };
-    // factor data of one level into LDS ring slot b (rows past the level's end repeat its last row)
-    auto put_fac = [&](const SwPipe<T, P, KM>& s, int b) {
-        if (tid < wmax) {
+        for (int f = 0; f < FR; ++f) {
+            const int t = pos_of(l, tid + f * NT);
 #pragma unroll
             for (int k = 0; k < KM; ++k) {
-                fslot_l[(b * wmax + tid) * KM + k] = s.fslot[k];
-                fv_l[(b * wmax + tid) * KM + k] = s.fv[k];
+                const int kk = k < K ? k : 0;
+                s.fslot[f][k] = sw.ell_slot[(long)kk * n + t];
+                s.fv[f][k] = val[(long)kk * n + t];
             }
-            fd_l[b * wmax + tid] = s.fd;
+            s.fd[f] = dsrc[t];
+        }
+    };
+    // factor data of one level into LDS ring slot b (rows past the level's end repeat its last row)
+    auto put_fac = [&](const SP& s, int b) {
+#pragma unroll
+        for (int f = 0; f < FR; ++f) {
+            const int r = tid + f * NT;
+            if (r < wmax) {
+#pragma unroll
+                for (int k = 0; k < KM; ++k) {
+                    fslot_l[(b * wmax + r) * KM + k] = s.fslot[f][k];
+                    fv_l[(b * wmax + r) * KM + k] = s.fv[f][k];
+                }
+                fd_l[b * wmax + r] = s.fd[f];
+            }
         }
     };
     // Slot of level L: L mod 4 for each kind of data (row indices live from
@@ -696,8 +722,7 @@ __device__ __forceinline__ void sweep_pipe(const SweepDev& sw, int n, int m, int
     // (rows in d), factor data of level l+1 (in b) to LDS, rows of level l+6
     // (slot c), factor data of level l+4 (slot a), then level l from a and
     // LDS.  Every wait is for loads issued three levels earlier.
-    auto level = [&](int l, SwPipe<T, P, KM>& a, SwPipe<T, P, KM>& b, SwPipe<T, P, KM>& c,
-                     SwPipe<T, P, KM>& d) {
+    auto level = [&](int l, SP& a, SP& b, SP& c, SP& d) {
         load_x(d);
         put_fac(b, (l + 1) & 1);
         load_row(l + 6, c);
@@ -723,7 +748,7 @@ __device__ __forceinline__ void sweep_pipe(const SweepDev& sw, int n, int m, int
         }
         lds_barrier();
     };
-    SwPipe<T, P, KM> s0, s1, s2, s3;
+    SP s0, s1, s2, s3;
     // The loads of levels 0-5 in the order the loop issues them (as if levels
     // -6 to -1 ran): at the loop entry the compiler merges this order with the
     // loop's own, and waits by the one with fewer loads issued since
@@ -770,7 +795,7 @@ __device__ __forceinline__ int2 xcd_block() {
     return make_int2(lin / gridDim.x, lin % gridDim.x);
 }
 
-template <typename T, int P, int KM, int NT>
+template <typename T, int P, int KM, int NT, int FR>
 __global__ __launch_bounds__(NT) void k_ilu_apply_pipe(IluApplyArgs<T> a, const Cx<T>* __restrict__ X, Cx<T>* Out,
                                                        int ring_stride, int wmax) {
     extern __shared__ unsigned char dsm[];
@@ -790,14 +815,14 @@ __global__ __launch_bounds__(NT) void k_ilu_apply_pipe(IluApplyArgs<T> a, const 
     const Cx<T>* fd = a.fdiag[side] ? a.fdiag[side] + (long)node * a.n : nullptr;
     const Cx<T>* bv = a.bval[side] + (long)node * B.K * a.n;
     const Cx<T>* bd = a.bdiag[side] ? a.bdiag[side] + (long)node * a.n : nullptr;
-    sweep_pipe<T, P, KM, NT>(F, a.n, a.m, c0, cw, fv, fd, X + base, Out + base, ring, ring_stride, fslot_l, fv_l,
-                             fd_l, wmax);
+    sweep_pipe<T, P, KM, NT, FR>(F, a.n, a.m, c0, cw, fv, fd, X + base, Out + base, ring, ring_stride, fslot_l, fv_l,
+                                 fd_l, wmax);
     // the backward sweep starts with the rows other waves stored last in the
     // forward sweep, whose stores the sweep loop leaves in flight
     __threadfence();
     __syncthreads();
-    sweep_pipe<T, P, KM, NT>(B, a.n, a.m, c0, cw, bv, bd, Out + base, Out + base, ring, ring_stride, fslot_l, fv_l,
-                             fd_l, wmax);
+    sweep_pipe<T, P, KM, NT, FR>(B, a.n, a.m, c0, cw, bv, bd, Out + base, Out + base, ring, ring_stride, fslot_l, fv_l,
+                                 fd_l, wmax);
 }
 
 template <typename T, int P, int KM, int NT>
@@ -865,18 +890,31 @@ void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<
     }
     const size_t ring_bytes = 2 * sizeof(Cx<T>) * (size_t)wmax * a.cw;
     const size_t fac_bytes = 2 * (size_t)wmax * (2 * sizeof(Cx<T>) + sizeof(Cx<T>) + 2 * sizeof(int));
-    // complex FP32, at most two off-diagonal slots, levels of at most 512 rows
-    // and 2,048 items: the pipelined sweep
-    const bool pipe = lds && sizeof(T) == 4 && K <= 2 && kmin >= 1 && wmax <= 512 && (long)wmax * a.cw <= 2048 &&
-                      (long)a.n * a.m < (1L << 31) && ring_bytes + fac_bytes <= 64 * 1024;
+    // complex FP32, at most two off-diagonal slots, levels of at most 1,024
+    // rows and 2,048 items, LDS within the device's per-workgroup limit: the
+    // pipelined sweep (levels above 512 rows: two rows of factor data per
+    // thread, and more than the default 64 KB of LDS)
+    static int lds_max = -1;
+    if (lds_max < 0) {
+        int dev = 0, v = 0;
+        FH_HIP(hipGetDevice(&dev));
+        FH_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        lds_max = v;
+    }
+    const size_t sh = ring_bytes + fac_bytes;
+    const bool pipe = lds && sizeof(T) == 4 && K <= 2 && kmin >= 1 && wmax <= 1024 && (long)wmax * a.cw <= 2048 &&
+                      (long)a.n * a.m < (1L << 31) && sh <= (size_t)lds_max;
     if (pipe) {
         if constexpr (sizeof(T) == 4) {
             const int stride = wmax * a.cw;
-            const size_t sh = ring_bytes + fac_bytes;
-            if (wmax > 256 || (long)wmax * a.cw > 1024)
-                k_ilu_apply_pipe<T, 4, 2, 512><<<grid, 512, sh, st>>>(a, X, Out, stride, wmax);
-            else
-                k_ilu_apply_pipe<T, 4, 2, 256><<<grid, 256, sh, st>>>(a, X, Out, stride, wmax);
+            auto go = [&](auto kern, int nt) {
+                if (sh > 64 * 1024)
+                    FH_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+                kern<<<grid, nt, sh, st>>>(a, X, Out, stride, wmax);
+            };
+            if (wmax > 512) go(k_ilu_apply_pipe<T, 4, 2, 512, 2>, 512);
+            else if (wmax > 256 || (long)wmax * a.cw > 1024) go(k_ilu_apply_pipe<T, 4, 2, 512, 1>, 512);
+            else go(k_ilu_apply_pipe<T, 4, 2, 256, 1>, 256);
         }
     } else if (lds && ring_bytes <= 48 * 1024) {
         // one batch per level when possible (a second batch would not be prefetched):
@@ -1352,31 +1390,45 @@ __global__ void k_givens(int C, int k, int KP, const zd* __restrict__ h1, const 
 // tau = rho.
 // ---------------------------------------------------------------------------
 constexpr int DCGS_ROWS_PER_CHUNK = 1024;
+// slots per chunk in the partial-dot buffer: s_0..s_{k-1}, c_0..c_{k-1},
+// alpha, beta, omega for k <= 32
+constexpr int DCGS_SLOTS = 2 * 32 + 3;
 
+// A workgroup covers cb consecutive columns (of the m of a system; blockIdx.y
+// = system * ncb + column block) and ry row groups; a thread owns one column.
+// The launch handles basis vectors i0 .. i0 + KM - 1 (those below k), and
+// alpha, beta, omega when extras != 0, so a pass over k vectors may be split
+// into launches of KM vectors each (FP64: 16, to keep the accumulators in
+// registers).
 template <typename T, int KM>
-__global__ __launch_bounds__(256) void k_dcgs_dots(int n, int m, int k, const Cx<T>* __restrict__ V, long vstride,
+__global__ __launch_bounds__(256) void k_dcgs_dots(int n, int m, int cb, int ncb, int k, int i0, int extras,
+                                                   const Cx<T>* __restrict__ V, long vstride,
                                                    const Cx<T>* __restrict__ W, double* __restrict__ part) {
     using A = typename AccT<T>::type;
     constexpr int NE = 2 * KM + 3;
-    const int s = blockIdx.y, chunk = blockIdx.x;
-    const int c = threadIdx.x, ty = threadIdx.y, ry = blockDim.y;
+    const int s = blockIdx.y / ncb, cblk = blockIdx.y % ncb, chunk = blockIdx.x;
+    const int tx = threadIdx.x, ty = threadIdx.y, ry = blockDim.y;
+    const int c = cblk * cb + tx;
+    const bool act = c < m;
     const long base = (long)s * n * m;
-    const int C = gridDim.y * m;
+    const int C = (gridDim.y / ncb) * m;
     const int col = s * m + c;
-    const int r0 = chunk * DCGS_ROWS_PER_CHUNK, r1 = min(n, r0 + DCGS_ROWS_PER_CHUNK);
+    const int r0 = chunk * DCGS_ROWS_PER_CHUNK, r1 = act ? min(n, r0 + DCGS_ROWS_PER_CHUNK) : r0;
     const bool hw = W != nullptr;
+    const int kl = min(KM, k - i0);             // basis vectors of this launch
     A sre[KM], sim[KM], cre[KM], cim[KM];
 #pragma unroll
     for (int i = 0; i < KM; ++i) { sre[i] = A(0); sim[i] = A(0); cre[i] = A(0); cim[i] = A(0); }
     A al = A(0), bre = A(0), bim = A(0), om = A(0);
     const Cx<T>* Vk = V + (long)k * vstride;
+    const Cx<T>* Vb = V + (long)i0 * vstride;
     for (int r = r0 + ty; r < r1; r += ry) {
         const long off = base + (long)r * m + c;
         const Cx<T> x = Vk[off];
         const Cx<T> w = hw ? W[off] : czero<T>();
         Cx<T> vv[KM];
 #pragma unroll
-        for (int i = 0; i < KM; ++i) vv[i] = (i < k) ? ld_basis(V + i * vstride + off) : czero<T>();
+        for (int i = 0; i < KM; ++i) vv[i] = (i < kl) ? ld_basis(Vb + i * vstride + off) : czero<T>();
 #pragma unroll
         for (int i = 0; i < KM; ++i) {
             sre[i] += (A)vv[i].re * (A)x.re + (A)vv[i].im * (A)x.im;
@@ -1384,15 +1436,17 @@ __global__ __launch_bounds__(256) void k_dcgs_dots(int n, int m, int k, const Cx
             cre[i] += (A)vv[i].re * (A)w.re + (A)vv[i].im * (A)w.im;
             cim[i] += (A)vv[i].re * (A)w.im - (A)vv[i].im * (A)w.re;
         }
-        al += (A)x.re * (A)x.re + (A)x.im * (A)x.im;
-        bre += (A)x.re * (A)w.re + (A)x.im * (A)w.im;
-        bim += (A)x.re * (A)w.im - (A)x.im * (A)w.re;
-        om += (A)w.re * (A)w.re + (A)w.im * (A)w.im;
+        if (extras) {
+            al += (A)x.re * (A)x.re + (A)x.im * (A)x.im;
+            bre += (A)x.re * (A)w.re + (A)x.im * (A)w.im;
+            bim += (A)x.re * (A)w.im - (A)x.im * (A)w.re;
+            om += (A)w.re * (A)w.re + (A)w.im * (A)w.im;
+        }
     }
     // block reduction over the ry row groups, 8 entries per round; entry j of
     // the compact output order: s_0..s_{k-1}, c_0..c_{k-1}, alpha, beta, omega
     __shared__ double sh[8][2][256];
-    const int t = ty * m + c;
+    const int t = ty * cb + tx;
 #pragma unroll
     for (int g0 = 0; g0 < NE; g0 += 8) {
         // skip rounds whose entries are all unused (uniform over the block)
@@ -1400,7 +1454,7 @@ __global__ __launch_bounds__(256) void k_dcgs_dots(int n, int m, int k, const Cx
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int slot = g0 + e;
-            if (slot < NE) any = any || (slot < KM ? slot < k : (slot < 2 * KM ? slot - KM < k : true));
+            if (slot < NE) any = any || (slot < KM ? slot < kl : (slot < 2 * KM ? slot - KM < kl : extras != 0));
         }
         if (!any) continue;
 #pragma unroll
@@ -1416,19 +1470,19 @@ __global__ __launch_bounds__(256) void k_dcgs_dots(int n, int m, int k, const Cx
             sh[e][1][t] = im;
         }
         __syncthreads();
-        if (ty == 0) {
+        if (ty == 0 && act) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int slot = g0 + e;
                 int j = -1;
-                if (slot < KM) j = slot < k ? slot : -1;
-                else if (slot < 2 * KM) j = (slot - KM < k) ? k + (slot - KM) : -1;
-                else if (slot < NE) j = 2 * k + (slot - 2 * KM);
+                if (slot < KM) j = slot < kl ? i0 + slot : -1;
+                else if (slot < 2 * KM) j = (slot - KM < kl) ? k + i0 + (slot - KM) : -1;
+                else if (slot < NE) j = extras ? 2 * k + (slot - 2 * KM) : -1;
                 if (j >= 0) {
-                    double a = sh[e][0][c], b = sh[e][1][c];
-                    for (int q = 1; q < ry; ++q) { a += sh[e][0][q * m + c]; b += sh[e][1][q * m + c]; }
-                    part[((long)chunk * NE + j) * 2 * C + col] = a;
-                    part[((long)chunk * NE + j) * 2 * C + C + col] = b;
+                    double a = sh[e][0][tx], b = sh[e][1][tx];
+                    for (int q = 1; q < ry; ++q) { a += sh[e][0][q * cb + tx]; b += sh[e][1][q * cb + tx]; }
+                    part[((long)chunk * DCGS_SLOTS + j) * 2 * C + col] = a;
+                    part[((long)chunk * DCGS_SLOTS + j) * 2 * C + C + col] = b;
                 }
             }
         }
@@ -1518,26 +1572,31 @@ __global__ void k_dcgs_coef(int C, int k, int KP, int flex, int final, double fl
 }
 
 // V_k <- (V_k - sum_{i<k} s_i V_i) scv ;  W <- (W - sum_{i<k} d_i V_i - d_k V_k) scw
+// (workgroups over column blocks as in k_dcgs_dots)
 template <typename T, int KM>
-__global__ __launch_bounds__(256) void k_dcgs_update(int n, int m, int k, Cx<T>* __restrict__ V, long vstride,
-                                                     Cx<T>* __restrict__ W, const zd* __restrict__ coef, int KP,
+__global__ __launch_bounds__(256) void k_dcgs_update(int n, int m, int cb, int ncb, int k, Cx<T>* __restrict__ V,
+                                                     long vstride, Cx<T>* __restrict__ W,
+                                                     const zd* __restrict__ coef, int KP,
                                                      const double* __restrict__ scv, const double* __restrict__ scw) {
-    const int s = blockIdx.y, chunk = blockIdx.x;
-    const int c = threadIdx.x, ty = threadIdx.y, ry = blockDim.y;
+    const int s = blockIdx.y / ncb, cblk = blockIdx.y % ncb, chunk = blockIdx.x;
+    const int tx = threadIdx.x, ty = threadIdx.y, ry = blockDim.y;
+    const int c = cblk * cb + tx;
+    const bool act = c < m;
     const long base = (long)s * n * m;
-    const int C = gridDim.y * m;
+    const int C = (gridDim.y / ncb) * m;
     const int col = s * m + c;
-    const int r0 = chunk * ROWS_PER_CHUNK, r1 = min(n, r0 + ROWS_PER_CHUNK);
+    const int r0 = chunk * ROWS_PER_CHUNK, r1 = act ? min(n, r0 + ROWS_PER_CHUNK) : r0;
     extern __shared__ unsigned char dsm[];
-    Cx<T>* hs = reinterpret_cast<Cx<T>*>(dsm);          // [KM][m] s (zero-padded)
-    Cx<T>* hd = hs + KM * m;                            // [KM][m] d (zero-padded)
+    Cx<T>* hs = reinterpret_cast<Cx<T>*>(dsm);          // [KM][cb] s (zero-padded)
+    Cx<T>* hd = hs + KM * cb;                           // [KM][cb] d (zero-padded)
     if (ty == 0) {
         for (int i = 0; i < KM; ++i) {
-            hs[i * m + c] = (i < k) ? ccast<T>(coef[(long)i * C + col]) : czero<T>();
-            hd[i * m + c] = (i < k) ? ccast<T>(coef[(long)(KP + i) * C + col]) : czero<T>();
+            hs[i * cb + tx] = (act && i < k) ? ccast<T>(coef[(long)i * C + col]) : czero<T>();
+            hd[i * cb + tx] = (act && i < k) ? ccast<T>(coef[(long)(KP + i) * C + col]) : czero<T>();
         }
     }
     __syncthreads();
+    if (!act) return;
     const Cx<T> dk = ccast<T>(coef[(long)(KP + k) * C + col]);
     const T sv = (T)scv[col], sw = (T)scw[col];
     Cx<T>* Vk = V + (long)k * vstride;
@@ -1545,13 +1604,19 @@ __global__ __launch_bounds__(256) void k_dcgs_update(int n, int m, int k, Cx<T>*
         const long off = base + (long)r * m + c;
         Cx<T> x = Vk[off];
         Cx<T> w = W[off];
-        Cx<T> vv[KM];
+        // basis values in groups (FP64: 16 at a time, to stay within the
+        // register file; FP32: all at once)
+        constexpr int G = (sizeof(T) == 8 && KM > 16) ? 16 : KM;
+#pragma unroll 1
+        for (int g0 = 0; g0 < KM; g0 += G) {
+            Cx<T> vv[G];
 #pragma unroll
-        for (int i = 0; i < KM; ++i) vv[i] = (i < k) ? ld_basis(V + i * vstride + off) : czero<T>();
+            for (int i = 0; i < G; ++i) vv[i] = (g0 + i < k) ? ld_basis(V + (g0 + i) * vstride + off) : czero<T>();
 #pragma unroll
-        for (int i = 0; i < KM; ++i) {
-            cfms(x, hs[i * m + c], vv[i]);
-            cfms(w, hd[i * m + c], vv[i]);
+            for (int i = 0; i < G; ++i) {
+                cfms(x, hs[(g0 + i) * cb + tx], vv[i]);
+                cfms(w, hd[(g0 + i) * cb + tx], vv[i]);
+            }
         }
         x.re *= sv;
         x.im *= sv;
@@ -1563,23 +1628,39 @@ __global__ __launch_bounds__(256) void k_dcgs_update(int n, int m, int k, Cx<T>*
     }
 }
 
+// column block of the DCGS2 kernels: all m columns when m <= 64, else 64 or 32
+// columns (the last block of a system may be partial)
+static int dcgs_colblock(int m) {
+    if (m <= 64) return m;
+    return (m % 64 == 0) ? 64 : ((m % 32 == 0) ? 32 : 64);
+}
+
 template <typename T, int KM>
 static void dcgs_launch(hipStream_t st, int n, int m, int nsys, int k, Cx<T>* V, long vstride, Cx<T>* W,
                         const DcgsState& d, int flex, int final, double tol) {
-    const int ry = std::max(1, 256 / m);
+    const int cb = dcgs_colblock(m), ncb = ceil_div(m, cb);
+    const int ry = std::max(1, 256 / cb);
     const int C = nsys * m;
-    constexpr int NE = 2 * KM + 3;
     const int nchunk_d = ceil_div(n, DCGS_ROWS_PER_CHUNK);
-    double* P = (double*)d.part->ensure(sizeof(double) * (size_t)nchunk_d * NE * 2 * C);
-    dim3 blk(m, ry);
+    double* P = (double*)d.part->ensure(sizeof(double) * (size_t)nchunk_d * DCGS_SLOTS * 2 * C);
+    dim3 blk(cb, ry);
     const double vec = (double)nsys * n * m * sizeof(Cx<T>);
     const std::string tag = std::string(sizeof(T) == 8 ? "c128" : "c64") + "_k" + std::to_string(KM);
     const int ne = 2 * k + 3;
-    hipEvent_t ev = prof_begin(st);
-    k_dcgs_dots<T, KM><<<dim3(nchunk_d, nsys), blk, 0, st>>>(n, m, k, V, vstride, W, P);
-    FH_LAUNCH_CHECK();
-    prof_end(st, ev, "dcgs_dots_" + tag, (k + (W ? 2 : 1)) * vec, 8.0 * (2 * k + 3) * vec / sizeof(Cx<T>));
-    k_reduce_dots<<<dim3(ceil_div(C, 128), ne), 128, 0, st>>>(nchunk_d, ne, NE, C, P, d.D, 0);
+    // dots: FP64 accumulators for more than 16 vectors do not fit in
+    // registers, so the pass is split into launches of 16 vectors (the block
+    // vectors V_k and W are read once per launch)
+    constexpr int KD = (sizeof(T) == 8 && KM > 16) ? 16 : KM;
+    const int nl = std::max(1, (int)ceil_div(k, KD));
+    for (int l = 0; l < nl; ++l) {
+        const int i0 = l * KD, kl = std::max(0, std::min(KD, k - i0));
+        hipEvent_t ev = prof_begin(st);
+        k_dcgs_dots<T, KD><<<dim3(nchunk_d, nsys * ncb), blk, 0, st>>>(n, m, cb, ncb, k, i0, l == 0 ? 1 : 0, V,
+                                                                        vstride, W, P);
+        FH_LAUNCH_CHECK();
+        prof_end(st, ev, "dcgs_dots_" + tag, (kl + (W ? 2 : 1)) * vec, 8.0 * (2 * kl + (l == 0 ? 3 : 0)) * vec / sizeof(Cx<T>));
+    }
+    k_reduce_dots<<<dim3(ceil_div(C, 128), ne), 128, 0, st>>>(nchunk_d, ne, DCGS_SLOTS, C, P, d.D, 0);
     FH_LAUNCH_CHECK();
     const double floor_rel = sizeof(T) == 4 ? 1e-7 : 1e-15;
     k_dcgs_coef<<<ceil_div(C, 128), 128, 0, st>>>(C, k, d.KP, flex, final, floor_rel, d.D, d.Hraw, d.Hs, d.cs, d.sn,
@@ -1588,10 +1669,11 @@ static void dcgs_launch(hipStream_t st, int n, int m, int nsys, int k, Cx<T>* V,
     FH_LAUNCH_CHECK();
     if (final) return;
     const int nchunk = ceil_div(n, ROWS_PER_CHUNK);
-    const size_t lds = 2 * sizeof(Cx<T>) * (size_t)KM * m;
-    FH_REQUIRE(lds <= 64 * 1024, -1, "DCGS2: restart length x columns per system too large for the LDS staging");
-    ev = prof_begin(st);
-    k_dcgs_update<T, KM><<<dim3(nchunk, nsys), blk, lds, st>>>(n, m, k, V, vstride, W, d.coef, d.KP, d.scv, d.scw);
+    const size_t lds = 2 * sizeof(Cx<T>) * (size_t)KM * cb;
+    FH_REQUIRE(lds <= 64 * 1024, -1, "DCGS2: restart length x column block too large for the LDS staging");
+    hipEvent_t ev = prof_begin(st);
+    k_dcgs_update<T, KM><<<dim3(nchunk, nsys * ncb), blk, lds, st>>>(n, m, cb, ncb, k, V, vstride, W, d.coef, d.KP,
+                                                                       d.scv, d.scw);
     FH_LAUNCH_CHECK();
     prof_end(st, ev, "dcgs_update_" + tag, (k + 2 + (k > 0 ? 2 : 1)) * vec, 16.0 * (k + 1) * vec / sizeof(Cx<T>));
 }
@@ -1607,6 +1689,7 @@ void dcgs_step(hipStream_t st, int n, int m, int nsys, int k, Cx<T>* V, long vst
     else throw Error(-1, "DCGS2: restart length above 32 is not supported");
 }
 template void dcgs_step<float>(hipStream_t, int, int, int, int, cf*, long, cf*, const DcgsState&, int, int, double);
+template void dcgs_step<double>(hipStream_t, int, int, int, int, zd*, long, zd*, const DcgsState&, int, int, double);
 
 // y = R^{-1} g (first kuse[col] steps), per column
 __global__ void k_gmres_trisolve(int C, int k, int KP, const zd* __restrict__ Hs, const zd* __restrict__ g,

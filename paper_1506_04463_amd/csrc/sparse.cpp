@@ -380,6 +380,12 @@ static IluApplyArgs<T> ilu_args(SparseState& S, int m, int precond) {
     a.n = S.n;
     a.m = m;
     a.cw = std::max(1, std::min(d ? S.ilu_cw64 : S.ilu_cw32, m));
+    // wide levels (a 1,024-point grid diagonal): fewer columns per workgroup,
+    // so that one level of the complex-FP32 sweep stays within 2,048 items
+    if (!d) {
+        const int wmax = std::max(std::max(S.swL.wmax, S.swU.wmax), std::max(S.swUT.wmax, S.swLT.wmax));
+        if (wmax > 0) a.cw = std::max(1, std::min(a.cw, 2048 / wmax));
+    }
     a.node_of = (const int*)S.node_of.p;
     a.side_of = (const int*)S.side_of.p;
     a.fwd[0] = S.swL;
@@ -471,10 +477,9 @@ static SolveStats gmres(Ctx& c, SparseState& S, const Batch& b, const Cx<T>* shi
     double* beta = (double*)S.beta.ensure(sizeof(double) * C);
     std::vector<double> hb(C), hbn(C);
     std::vector<int> hk(C);
-    // delayed reorthogonalization: complex FP32 bases up to 32 steps and 128
-    // columns per system (the update pass stages 2 x 32 x m coefficients in
-    // LDS); otherwise classical Gram-Schmidt with reorthogonalization
-    const bool delayed = orth_passes == 3 && sizeof(T) == 4 && restart <= 31 && m <= 128;
+    // delayed reorthogonalization: bases of up to 32 vectors (restart <= 31);
+    // longer cycles use classical Gram-Schmidt with reorthogonalization
+    const bool delayed = orth_passes == 3 && restart <= 31;
     if (orth_passes == 3 && !delayed) orth_passes = 2;
     DcgsState dstate;
     if (delayed) {
@@ -781,7 +786,10 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
             filter_accum(st, gc, n, m, Xb + gc * blk, cd + (size_t)(ne + j0) * m, (lam && first) ? Yh : nullptr,
                          (first && rd) ? rd + m : nullptr, Qh, !first);
     }
-    if (sym && Qh) conj_copy(st, blk, Q, Qh);                             // Qh = conj(Q)
+    // complex symmetric: the left block is taken as conj(Y) D with
+    // D = diag(conj(1 / (y_c^T y_c))), the scaling with yh_c^H y_c = 1 that
+    // FEAST's left Ritz vectors have; its filter is conj(Q) D
+    if (sym && Qh) conj_copy_bilin(st, n, m, Y, Q, Qh, c.partial2);
     FH_HIP(hipStreamSynchronize(st));
     if (rep) {
         rep->n_fallback += s.fallback ? sides * ne : 0;

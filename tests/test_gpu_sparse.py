@@ -104,13 +104,14 @@ def test_ilu0_apply_c64_both_sides(handle, name, m):
         np.testing.assert_allclose(out, ref, rtol=0, atol=2e-5 * np.abs(ref).max())
 
 
-@pytest.mark.parametrize("m", [5, 64])
-def test_ilu0_apply_c64_many_levels(handle, m):
+@pytest.mark.parametrize("N,m", [(160, 5), (160, 64), (600, 16)])
+def test_ilu0_apply_c64_many_levels(handle, N, m):
     """160 x 160 grid: 319 dependent levels per sweep (not a multiple of the
     sweep's four-level unrolling), levels up to 160 rows wide (1,280 items per
-    workgroup at 8 columns).  Checked by the defining property L U y = x with
+    workgroup at 8 columns); 600 x 600: levels of up to 600 rows, wider than
+    the 512-thread workgroup (two rows of factor data per thread, three
+    columns per workgroup).  Checked by the defining property L U y = x with
     the oracle's factors, and against the complex-FP64 apply."""
-    N = 160
     A = W.convdiff2d_csr(N, 20.0, 10.0)
     n = A["n"]
     prob = fh.Problem(handle, _csr(A))
@@ -135,7 +136,7 @@ def test_ilu0_apply_c64_many_levels(handle, m):
         assert np.abs(y - y64).max() < 1e-4 * np.abs(y64).max()
 
 
-@pytest.mark.parametrize("N,m", [(24, 20), (160, 64)])
+@pytest.mark.parametrize("N,m", [(24, 20), (160, 64), (1024, 160)])
 def test_ilu0_apply_c64_repeatable(handle, N, m):
     """The same apply, repeated, gives the same result: the sweeps' level
     ordering leaves no read of a value before it is written (a race would
@@ -148,6 +149,10 @@ def test_ilu0_apply_c64_repeatable(handle, N, m):
         scale = np.abs(ys[0]).max()
         for y in ys[1:]:
             assert np.abs(y - ys[0]).max() <= 1e-6 * scale, (side, np.abs(y - ys[0]).max() / scale)
+        if N >= 1024:
+            # levels of 1,024 rows: the complex-FP32 sweep against the FP64 one
+            y64 = fh.ilu0_apply(prob, 300.0 + 40.0j, side, X.to(torch.complex128)).cpu().numpy()
+            assert np.abs(ys[0] - y64).max() < 1e-4 * np.abs(y64).max()
 
 
 def _small_convdiff(N=20, m_in=8, m0=16):
@@ -267,9 +272,9 @@ def test_feast_complex_symmetric_small(handle, sym):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_filter_sparse_sym_parity(handle, precision):
-    """Complex symmetric A with Yh = conj(Y): the filter with opts.sym = 1
-    (right systems only, Qh = conj(Q)) against the oracle's filter, which
-    solves the left systems too."""
+    """Complex symmetric A: the filter with opts.sym = 1 (right systems only,
+    Qh = conj(Q) D with D = diag(conj(1 / y_i^T y_i))) against the oracle's
+    filter of the left block conj(Y) D, which solves the left systems."""
     A = W.schrodinger2d_csr(12, L=10.0, nwells=5, seed=3)
     n = A["n"]
     ev = sla.eigvals(W.csr_to_dense(A))
@@ -277,7 +282,8 @@ def test_filter_sparse_sym_parity(handle, precision):
     r = 0.5 * np.sort(np.abs(ev - c))[6:8].sum()
     z, w = ct.ellipse_nodes(c, r, 1.0, 0.0, 12)
     Y = W.subspace(n, 10, 21)
-    Yh = np.conj(Y)
+    D = np.conj(1.0 / np.sum(Y * Y, axis=0))
+    Yh = np.conj(Y) * D[None, :]
     Qo, Qho = F.contour_filter(L.csr_matrix(A), None, z, w, Y, Yh)
     prob = fh.Problem(handle, _csr(A))
     opts = fh.default_opts(10, solver=1, precond=2, inner_tol=1e-12, restart=30, max_restarts=400,
@@ -291,7 +297,7 @@ def test_filter_sparse_sym_parity(handle, precision):
     tol = 10 * kap * max(rep["inner_relres"], 1e-14)
     assert np.linalg.norm(Q - Qo) / np.linalg.norm(Qo) < tol
     assert np.linalg.norm(Qh - Qho) / np.linalg.norm(Qho) < tol
-    assert np.array_equal(Qh, np.conj(Q))
+    np.testing.assert_allclose(Qh, np.conj(Q) * D[None, :], rtol=1e-14, atol=0)
 
 
 def test_feast_general_full_size_graded_bq(handle):

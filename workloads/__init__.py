@@ -335,3 +335,42 @@ def schrodinger2d_csr(N: int, L: float = 40.0, nwells: int = 50, depth: float = 
     val = valv[has]
     del idx
     return {"n": n, "rowptr": rowptr.astype(np.int32), "colind": colind, "val": val, "V": V, "W": Wf}
+
+
+def schrodinger2d_contour(eigs, m_target=120, ratio=0.5, window=12, left_margin=1.0):
+    """Ellipse of the complex-symmetric workload from its lowest eigenvalues
+    (eigs: the eigenvalues nearest a shift below the spectrum, any order; all
+    lie in Im <= 0 because W >= 0).  The ellipse holds the j lowest
+    eigenvalues (by real part), j within m_target +- window where the gap
+    Re(lam_{j+1}) - Re(lam_j) is widest; it crosses the real axis at
+    Re(lam_1) - left_margin and at the middle of that gap, has axis ratio
+    `ratio`, and its centre lies in the lower half-plane at a quarter of the
+    vertical semi-axis below the real axis.  Returns (Contour, j)."""
+    ev = np.asarray(eigs, dtype=np.complex128)
+    re = np.sort(ev.real)
+    lo, hi = max(1, m_target - window), min(len(re) - 1, m_target + window)
+    j = max(range(lo, hi + 1), key=lambda q: re[q] - re[q - 1])
+    left = re[0] - left_margin
+    right = 0.5 * (re[j - 1] + re[j])
+    hw = 0.5 * (right - left)
+    delta = 0.25 * ratio * hw
+    a = math.sqrt(hw * hw + (delta / ratio) ** 2)
+    return Contour(center=complex(0.5 * (left + right), -delta), a=a, ratio=ratio, angle=0.0), j
+
+
+def schrodinger2d(N=1024, eigs=None, m_target=120, ne=24, m0=160, ratio=0.5, seed=5, **op) -> Problem:
+    """Complex-symmetric 2D workload (fifth configuration): the operator of
+    schrodinger2d_csr(N, seed=seed, **op), the ellipse of
+    schrodinger2d_contour around about m_target of its lowest eigenvalues
+    (eigs: reference eigenvalues nearest a shift below the spectrum), Ne
+    nodes, m0 columns; Y0 complex Gaussian, Yh0 = conj(Y0) (the left
+    eigenvectors of a complex symmetric matrix are the conjugates of the
+    right ones)."""
+    A = schrodinger2d_csr(N, seed=seed, **op)
+    cont, j = schrodinger2d_contour(eigs, m_target=m_target, ratio=ratio)
+    cont.ne = ne
+    n = A["n"]
+    Y0 = subspace(n, m0, seed * 100 + 1)
+    return Problem(name=f"schrodinger2d_N{N}", n=n, A=A, B=None, contour=cont, m0=m0, Y0=Y0,
+                   Yh0=np.ascontiguousarray(np.conj(Y0)),
+                   info={"m_in": j, "eigs": np.asarray(eigs), "N": N})
