@@ -4,7 +4,7 @@ near -40) of the complex-symmetric Schroedinger-type operator on the
 1024 x 1024 grid (workloads.schrodinger2d_csr(1024): domain (0, 40)^2, 50
 Gaussian wells of depth 20, absorbing ramp on the outer 10 %, eta = 5),
 computed by the oracle's ARPACK shift-invert reference (oracle/reference.py).
-They place the contour of that workload (its 121 lowest lie inside) and
+They place the contour of that workload (its 116 lowest lie inside) and
 certify the eigenvalues FEAST finds there.  About half an hour of CPU.
 
     python tests/golden/make_schrodinger_reference.py
