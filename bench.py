@@ -56,11 +56,13 @@ def _opts(fh, m0, precision, max_iter, eps, resume=0):
                            max_iter=max_iter, eps=eps, resume=resume, orth=ORTH)
 
 
-def _traffic(kernel):
+def _traffic(kernel, workload="convdiff256"):
     """HBM bytes per launch of `kernel` measured with rocprofv3 counters
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), from
-    profiles/hbm_traffic.json; None when not measured for this kernel."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size) on the
+    given workload, from profiles/hbm_traffic_<workload>.json; None when not
+    measured for this kernel.  The counters are taken in their own runs; a
+    kernel changed since then needs them taken again."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -591,15 +593,18 @@ def schrodinger(args):
     Yh0 = torch.from_numpy(p.Yh0).cuda()
     # fast path: warm-up iterations, K timed ones, then on to convergence
     t_all = time.perf_counter()
-    out = feast(Y0, Yh0, _c5_opts(fh, p.m0, fh.FH_PREC_MIXED, args.warmup, 1e-300))
-    done_it = out["report"]["iters"]
-    print(f"[bench] fast path: {done_it} warm-up iteration(s), {time.perf_counter() - t_all:.1f} s", file=sys.stderr,
-          flush=True)
-    Y, Yh, ritz = out["Y"].contiguous(), out["Yh"].contiguous(), out["ritz"]
+    done_it, resume = 0, 0
+    Y, Yh, ritz = Y0, Yh0, None
+    if args.warmup > 0:
+        out = feast(Y0, Yh0, _c5_opts(fh, p.m0, fh.FH_PREC_MIXED, args.warmup, 1e-300))
+        done_it = out["report"]["iters"]
+        print(f"[bench] fast path: {done_it} warm-up iteration(s), {time.perf_counter() - t_all:.1f} s",
+              file=sys.stderr, flush=True)
+        Y, Yh, ritz, resume = out["Y"].contiguous(), out["Yh"].contiguous(), out["ritz"], 1
     handle.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = feast(Y, Yh, _c5_opts(fh, Y.shape[1], fh.FH_PREC_MIXED, args.steps, 1e-300, 1), ritz)
+    out = feast(Y, Yh, _c5_opts(fh, Y.shape[1], fh.FH_PREC_MIXED, args.steps, 1e-300, resume), ritz)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     stats = handle.profile_stats()
@@ -626,11 +631,13 @@ def schrodinger(args):
         torch.cuda.empty_cache()
         # the same iterations as the fast path: W warm-up, then K timed
         K64 = args.steps if args.fp64_steps is None else max(1, args.fp64_steps)
-        o64 = feast(Y0, Yh0, _c5_opts(fh, p.m0, fh.FH_PREC_FP64, args.warmup, 1e-300))
-        Y6, Yh6, r6 = o64["Y"].contiguous(), o64["Yh"].contiguous(), o64["ritz"]
+        Y6, Yh6, r6, res6 = Y0, Yh0, None, 0
+        if args.warmup > 0:
+            o64 = feast(Y0, Yh0, _c5_opts(fh, p.m0, fh.FH_PREC_FP64, args.warmup, 1e-300))
+            Y6, Yh6, r6, res6 = o64["Y"].contiguous(), o64["Yh"].contiguous(), o64["ritz"], 1
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        o64 = feast(Y6, Yh6, _c5_opts(fh, Y6.shape[1], fh.FH_PREC_FP64, K64, 1e-300, 1), r6)
+        o64 = feast(Y6, Yh6, _c5_opts(fh, Y6.shape[1], fh.FH_PREC_FP64, K64, 1e-300, res6), r6)
         torch.cuda.synchronize()
         dt64 = time.perf_counter() - t0
         del Y6, Yh6
@@ -643,7 +650,9 @@ def schrodinger(args):
     name, st = dom
     achieved = st["bytes"] / (st["ms"] * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS, "traffic": _traffic(name), "avg_ms": st["ms"] / st["count"],
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": _traffic(name, f"schrodinger{N}") if N == 1024 else None,
+            "avg_ms": st["ms"] / st["count"],
             "launches": st["count"], "bytes_per_launch": st["bytes"] / st["count"],
             "share_of_step": st["ms"] / (args.steps * ms_mx)}
     kernels = {k: {"ms_total": v["ms"], "count": v["count"], "share": v["ms"] / (args.steps * ms_mx),
