@@ -720,6 +720,111 @@ def _c5_validate(fh, torch, prob, p, fin, eigs, alpha):
     return out
 
 
+# --------------------------------------------------------------------------
+# fourth configuration: 3D convection-diffusion-reaction with the learned
+# preconditioner inside FEAST
+# --------------------------------------------------------------------------
+C4_TRAIN_FIELDS = range(4001, 4033)
+
+
+def convdiff3d_learned(args):
+    """-Lap u + v.grad u + 5u on the 64^3 grid (n = 262,144) with the
+    held-out convection field (seed 4000), ellipse around its lowest ~64
+    eigenvalues, Ne = 16, m0 = 96.  A 3x3x3 network (8 inputs: residual,
+    shift, side, the field v/30; 16 / 16 / 2 channels) is trained on the GPU on
+    (residual, error) pairs harvested from plain GMRES on the operators of 32
+    other seeded fields (4001-4032), then used as the flexible preconditioner
+    of FGMRES(30) x 2 inside FEAST (ILU(0) fallback).  FEAST is run to
+    eq:res <= 1e-9 with each preconditioner -- learned, ILU(0), Jacobi, none --
+    and the iterations, time per iteration, time to solution and eigenvalues
+    (against the reference, tests/golden) are reported; the unpreconditioned
+    FP64 solve of fresh systems with known solutions judges the network's
+    error."""
+    import torch
+    import workloads as W
+    import paper_1506_04463_amd as fh
+    from paper_1506_04463_amd import learned
+
+    N = args.grid3d
+    eigs = _c5_eigs(args.eigs or os.path.join(ROOT, "tests", "golden", f"convdiff3d_N{N}_lowest.json"))
+    p = W.convdiff3d(N=N, field_seed=4000, eigs=eigs, m_target=64, ne=16, m0=96)
+    c = p.contour
+    h = fh.Handle(0)
+
+    def csr(A):
+        return fh.CSR(torch.from_numpy(A["rowptr"]).cuda(), torch.from_numpy(A["colind"]).cuda(),
+                      torch.from_numpy(A["val"]).cuda(), A["n"])
+
+    prob = fh.Problem(h, csr(p.A))
+    alpha = abs(c.center) + max(c.a, c.ratio * c.a)
+    hh = 1.0 / (N + 1)
+    z, _ = fh.contour_nodes(c.center, c.a, c.ratio, 0.0, c.ne)
+    print(f"[bench] {p.name}: n={p.n} ellipse c={c.center:.3f} a={c.a:.3f} ratio={c.ratio:.3f} "
+          f"({p.info['m_in']} reference eigenvalues inside) Ne={c.ne} m0={p.m0}", file=sys.stderr, flush=True)
+    # --- training on the other fields
+    t0 = time.perf_counter()
+    net = fh.Net(h, N, N, fields=p.info["field"].reshape(3, -1) / 30.0, alpha=float(c.a), out_scale=hh * hh / 6.0,
+                 seed=5, nz=N)
+    nfields = args.train_fields
+    sets = []
+    for k, seed in enumerate(list(C4_TRAIN_FIELDS)[:nfields]):
+        v = W.smooth_field3d(N, seed)
+        pk = fh.Problem(h, csr(W.convdiff3d_csr(N, v)))
+        # four nodes per field (rotating), two columns, iterates after 0, 2, 5 steps
+        zk = z[[(k + 4 * q) % c.ne for q in range(4)]]
+        sets.append((v.reshape(3, -1) / 30.0, pk, learned.harvest(pk, zk, m=2, seed=seed, steps=(0, 2, 5))))
+    t_h = time.perf_counter() - t0
+    hist = learned.train_fields(net, sets, epochs=args.epochs, lr=2e-3, batch_systems=8, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del sets
+    net.set_fields(p.info["field"].reshape(3, -1) / 30.0)
+    fh.set_net(prob, net)
+    print(f"[bench] network trained on {nfields} fields: harvest {t_h:.1f} s, total {t_train:.1f} s, loss "
+          f"{hist[0]:.3f} -> {hist[-1]:.3f}", file=sys.stderr, flush=True)
+    judge = learned.evaluate(prob, z[:4], m=4, seed=98, tol=1e-8, restart=30, max_restarts=4,
+                             fallback=fh.FH_PC_ILU0)
+    print(f"[bench] fixed Krylov budget on fresh systems (unpreconditioned FP64 as the judge): {judge}",
+          file=sys.stderr, flush=True)
+    # --- FEAST with each preconditioner
+    Y0 = torch.from_numpy(p.Y0).cuda()
+    Yh0 = torch.from_numpy(p.Yh0).cuda()
+    runs = {}
+    u = (eigs - c.center)
+    ref_in = eigs[(u.real / c.a) ** 2 + (u.imag / (c.ratio * c.a)) ** 2 < 1.0]
+    for name, pc in (("learned", fh.FH_PC_LEARNED), ("ilu0", fh.FH_PC_ILU0), ("jacobi", fh.FH_PC_JACOBI),
+                     ("none", fh.FH_PC_NONE)):
+        o = fh.default_opts(p.m0, solver=fh.FH_SOLVER_BGMRES, precond=pc, restart=30, max_restarts=2,
+                            inner_tol=1e-3, precision=fh.FH_PREC_MIXED, mixed_inner_tol=1e-3, max_refine=1,
+                            max_iter=args.max_iter, eps=EPS_ITER, orth=2, fallback=fh.FH_PC_ILU0, confirm=1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        try:
+            out = fh.feast(prob, c.center, c.a, c.ratio, 0.0, c.ne, Y0, Yh0, o)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            lam = out["lam"]
+            d = float(np.abs(lam[:, None] - ref_in[None, :]).min(axis=1).max() / alpha) if len(lam) else None
+            r = {"info": out["info"], "iterations": out["report"]["iters"], "seconds": dt,
+                 "s_per_iteration": dt / max(1, out["report"]["iters"]), "m": int(len(lam)),
+                 "m_reference_inside": int(len(ref_in)), "max_dlam_over_alpha": d,
+                 "fallback_solves": out["report"]["n_fallback"], "last_inner_relres": out["report"]["inner_relres"]}
+        except fh.FeastError as e:
+            r = {"error": str(e), "seconds": time.perf_counter() - t1}
+        runs[name] = r
+        print(f"[bench] FEAST with {name}: {json.dumps(r)}", file=sys.stderr, flush=True)
+    line = {"metric": "FEAST time to solution (eq:res <= 1e-9) with the learned preconditioner vs ILU(0), "
+                      "Jacobi, none", "unit": "s", "higher_is_better": False, "n_gpus": 1,
+            "value": runs["learned"].get("seconds"), "dtype": "c64 Krylov solves, BF16 network weights",
+            "data": "synthetic",
+            "config": {"workload": f"3D convection-diffusion-reaction {N}^3 (n={p.n}), held-out field, "
+                                   f"{p.info['m_in']} eigenvalues, Ne=16, m0=96, FGMRES(30) x 2"},
+            "training": {"fields": nfields, "epochs": args.epochs, "seconds": t_train, "loss_first": hist[0],
+                         "loss_last": hist[-1]},
+            "fixed_budget_judge": judge, "feast": runs}
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -731,6 +836,9 @@ def main():
     ap.add_argument("--max-iter", type=int, default=30, help="headline workload: iteration limit of the "
                                                              "validation run")
     ap.add_argument("--grid", type=int, default=1024, help="headline workload: grid points per side")
+    ap.add_argument("--grid3d", type=int, default=64, help="convdiff3d: grid points per side")
+    ap.add_argument("--train-fields", type=int, default=32, help="convdiff3d: training convection fields")
+    ap.add_argument("--epochs", type=int, default=20, help="convdiff3d: training epochs")
     ap.add_argument("--eigs", default=None, help="headline workload: reference eigenvalues (.npy or the golden "
                                                  "JSON; default the 1024 x 1024 one)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
@@ -739,7 +847,7 @@ def main():
     ap.add_argument("--columns", type=int, default=128, help="learned3d: columns per system")
     ap.add_argument("--workload", default="schrodinger",
                     choices=["schrodinger", "convdiff", "dense-batch", "copy-calibration", "learned3d", "csym",
-                             "contour-grid"],
+                             "contour-grid", "convdiff3d"],
                     help="schrodinger: the headline workload, complex-symmetric 1024 x 1024 (default); convdiff: "
                          "2D convection-diffusion 256 x 256; dense-batch: 64 dense problems; copy-calibration: a "
                          "1 GiB device copy (reference for the HBM byte counters)")
@@ -775,6 +883,9 @@ def main():
         return
     if args.workload == "schrodinger":
         schrodinger(args)
+        return
+    if args.workload == "convdiff3d":
+        convdiff3d_learned(args)
         return
     import torch
     import paper_1506_04463_amd as fh

@@ -20,14 +20,27 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 
-def nearest_eigenvalues(A, k, sigma, tol=1e-12):
+def nearest_eigenvalues(A, k, sigma, tol=1e-12, ordering="MMD_AT_PLUS_A"):
     """The k eigenvalues of the CSR operator A (dict with n, rowptr, colind,
-    val) nearest sigma, sorted by (Re, Im)."""
+    val) nearest sigma, sorted by (Re, Im).  A real matrix with a real shift
+    is factorized in real arithmetic (the real and imaginary parts of each
+    right-hand side are solved separately).  ordering: SuperLU's column
+    ordering (minimum degree on A^T + A suits 2D grids; COLAMD 3D ones)."""
     n = A["n"]
-    M = sp.csr_matrix((A["val"], A["colind"], A["rowptr"]), shape=(n, n)).tocsc()
-    shifted = (M - sigma * sp.identity(n, format="csc", dtype=M.dtype)).tocsc()
-    lu = spla.splu(shifted, permc_spec="MMD_AT_PLUS_A")
-    dtype = np.result_type(M.dtype, np.complex128)
-    op = spla.LinearOperator((n, n), matvec=lambda x: lu.solve(np.asarray(x, dtype=dtype)), dtype=dtype)
-    vals = spla.eigs(M.astype(dtype), k=k, sigma=sigma, OPinv=op, which="LM", return_eigenvectors=False, tol=tol)
+    val = np.asarray(A["val"])
+    real = not np.iscomplexobj(val) and complex(sigma).imag == 0.0
+    dt = np.float64 if real else np.complex128
+    Mf = sp.csr_matrix((val.astype(dt), A["colind"], A["rowptr"]), shape=(n, n)).tocsc()
+    shifted = (Mf - (complex(sigma).real if real else sigma) * sp.identity(n, format="csc", dtype=dt)).tocsc()
+    lu = spla.splu(shifted, permc_spec=ordering)
+
+    def solve(x):
+        x = np.asarray(x, dtype=np.complex128)
+        if real:
+            return lu.solve(np.ascontiguousarray(x.real)) + 1j * lu.solve(np.ascontiguousarray(x.imag))
+        return lu.solve(x)
+
+    op = spla.LinearOperator((n, n), matvec=solve, dtype=np.complex128)
+    M = Mf.astype(np.complex128)
+    vals = spla.eigs(M, k=k, sigma=sigma, OPinv=op, which="LM", return_eigenvectors=False, tol=tol)
     return vals[np.lexsort((vals.imag, vals.real))]

@@ -374,3 +374,53 @@ def schrodinger2d(N=1024, eigs=None, m_target=120, ne=24, m0=160, ratio=0.5, see
     return Problem(name=f"schrodinger2d_N{N}", n=n, A=A, B=None, contour=cont, m0=m0, Y0=Y0,
                    Yh0=np.ascontiguousarray(np.conj(Y0)),
                    info={"m_in": j, "eigs": np.asarray(eigs), "N": N})
+
+
+def lowest_contour(eigs, m_target, ratio=0.3, window=8, left_margin_frac=0.02):
+    """Ellipse around the eigenvalues of smallest real part (eigs: the
+    eigenvalues nearest a shift below the spectrum).  Sorted by real part,
+    the j lowest (j within m_target +- window where the gap
+    Re(lam_{j+1}) - Re(lam_j) is widest) fix the ellipse: centred on the real
+    axis, crossing it just left of Re(lam_1) (by left_margin_frac of the
+    span) and at the middle of that gap; the vertical semi-axis is `ratio`
+    times the horizontal one, widened where one of those j eigenvalues would
+    fall outside.  Returns (Contour, number of the given eigenvalues inside);
+    raises if the ellipse reaches beyond the disc the given eigenvalues cover
+    (the count would then be incomplete)."""
+    ev = np.asarray(eigs, dtype=np.complex128)
+    ev = ev[np.argsort(ev.real, kind="stable")]
+    re = ev.real
+    lo, hi = max(1, m_target - window), min(len(re) - 1, m_target + window)
+    j = max(range(lo, hi + 1), key=lambda q: re[q] - re[q - 1])
+    right = 0.5 * (re[j - 1] + re[j])
+    left = re[0] - left_margin_frac * (right - re[0])
+    c = 0.5 * (left + right)
+    a = 0.5 * (right - left)
+    b = ratio * a
+    for x in ev[:j]:
+        u = (x.real - c) / a
+        if abs(u) < 1:
+            b = max(b, 1.1 * abs(x.imag) / math.sqrt(1 - u * u))
+    inside = int(np.count_nonzero(((ev.real - c) / a) ** 2 + (ev.imag / b) ** 2 < 1.0))
+    covered = np.abs(ev).max()
+    reach = max(abs(c - a), abs(c + a), math.hypot(c, b))
+    if reach >= covered:
+        raise ValueError(f"the ellipse reaches |z| = {reach:.4g}, beyond the {covered:.4g} the reference covers")
+    return Contour(center=complex(c, 0.0), a=float(a), ratio=float(b / a), angle=0.0), inside
+
+
+def convdiff3d(N=64, field_seed=4000, eigs=None, m_target=64, ne=16, m0=96, seed=4) -> Problem:
+    """3D convection-diffusion-reaction workload (fourth configuration):
+    -Lap u + v.grad u + 5 u on the N^3 interior grid of the unit cube, 7-point
+    central differences, v = smooth_field3d(N, field_seed) (|v| <= 30); the
+    ellipse of lowest_contour around about m_target of its lowest eigenvalues
+    (eigs: reference eigenvalues nearest a shift below the spectrum); Ne
+    nodes, m0 columns, complex Gaussian start blocks."""
+    v = smooth_field3d(N, field_seed)
+    A = convdiff3d_csr(N, v)
+    cont, j = lowest_contour(eigs, m_target)
+    cont.ne = ne
+    n = A["n"]
+    return Problem(name=f"convdiff3d_N{N}", n=n, A=A, B=None, contour=cont, m0=m0,
+                   Y0=subspace(n, m0, seed * 100 + 1), Yh0=subspace(n, m0, seed * 100 + 2),
+                   info={"m_in": j, "eigs": np.asarray(eigs), "N": N, "field": v})
