@@ -44,3 +44,10 @@ def nearest_eigenvalues(A, k, sigma, tol=1e-12, ordering="MMD_AT_PLUS_A"):
     M = Mf.astype(np.complex128)
     vals = spla.eigs(M, k=k, sigma=sigma, OPinv=op, which="LM", return_eigenvectors=False, tol=tol)
     return vals[np.lexsort((vals.imag, vals.real))]
+
+
+def dense_generalized_eigenvalues(A, B=None):
+    """All eigenvalues of the dense pencil (A, B) (B None: identity) by LAPACK's
+    QZ (scipy.linalg.eigvals), the brute-force reference for dense problems."""
+    import scipy.linalg as sla
+    return sla.eigvals(A, B) if B is not None else sla.eigvals(A)
