@@ -761,8 +761,11 @@ def convdiff3d_learned(args):
     z, _ = fh.contour_nodes(c.center, c.a, c.ratio, 0.0, c.ne)
     print(f"[bench] {p.name}: n={p.n} ellipse c={c.center:.3f} a={c.a:.3f} ratio={c.ratio:.3f} "
           f"({p.info['m_in']} reference eigenvalues inside) Ne={c.ne} m0={p.m0}", file=sys.stderr, flush=True)
+    want = [x.strip() for x in args.preconds.split(",") if x.strip()]
     # --- training on the other fields
     t0 = time.perf_counter()
+    if "learned" not in want:
+        args.train_fields = 0
     net = fh.Net(h, N, N, fields=p.info["field"].reshape(3, -1) / 30.0, alpha=float(c.a), out_scale=hh * hh / 6.0,
                  seed=5, nz=N)
     nfields = args.train_fields
@@ -773,8 +776,13 @@ def convdiff3d_learned(args):
         # four nodes per field (rotating), two columns, iterates after 0, 2, 5 steps
         zk = z[[(k + 4 * q) % c.ne for q in range(4)]]
         sets.append((v.reshape(3, -1) / 30.0, pk, learned.harvest(pk, zk, m=2, seed=seed, steps=(0, 2, 5))))
+        print(f"[bench] harvested field {seed} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
     t_h = time.perf_counter() - t0
-    hist = learned.train_fields(net, sets, epochs=args.epochs, lr=2e-3, batch_systems=8, seed=0)
+    hist = [float("nan")]
+    for ep in range(args.epochs if nfields else 0):
+        hist += learned.train_fields(net, sets, epochs=1, lr=2e-3, batch_systems=8, seed=ep)
+        print(f"[bench] epoch {ep + 1}: loss {hist[-1]:.4f} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
+              flush=True)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del sets
@@ -782,8 +790,8 @@ def convdiff3d_learned(args):
     fh.set_net(prob, net)
     print(f"[bench] network trained on {nfields} fields: harvest {t_h:.1f} s, total {t_train:.1f} s, loss "
           f"{hist[0]:.3f} -> {hist[-1]:.3f}", file=sys.stderr, flush=True)
-    judge = learned.evaluate(prob, z[:4], m=4, seed=98, tol=1e-8, restart=30, max_restarts=4,
-                             fallback=fh.FH_PC_ILU0)
+    judge = None if not nfields else learned.evaluate(prob, z[:4], m=4, seed=98, tol=1e-8, restart=30,
+                                                      max_restarts=4, fallback=fh.FH_PC_ILU0)
     print(f"[bench] fixed Krylov budget on fresh systems (unpreconditioned FP64 as the judge): {judge}",
           file=sys.stderr, flush=True)
     # --- FEAST with each preconditioner
@@ -794,6 +802,8 @@ def convdiff3d_learned(args):
     ref_in = eigs[(u.real / c.a) ** 2 + (u.imag / (c.ratio * c.a)) ** 2 < 1.0]
     for name, pc in (("learned", fh.FH_PC_LEARNED), ("ilu0", fh.FH_PC_ILU0), ("jacobi", fh.FH_PC_JACOBI),
                      ("none", fh.FH_PC_NONE)):
+        if name not in want:
+            continue
         o = fh.default_opts(p.m0, solver=fh.FH_SOLVER_BGMRES, precond=pc, restart=30, max_restarts=2,
                             inner_tol=1e-3, precision=fh.FH_PREC_MIXED, mixed_inner_tol=1e-3, max_refine=1,
                             max_iter=args.max_iter, eps=EPS_ITER, orth=2, fallback=fh.FH_PC_ILU0, confirm=1)
@@ -815,7 +825,7 @@ def convdiff3d_learned(args):
         print(f"[bench] FEAST with {name}: {json.dumps(r)}", file=sys.stderr, flush=True)
     line = {"metric": "FEAST time to solution (eq:res <= 1e-9) with the learned preconditioner vs ILU(0), "
                       "Jacobi, none", "unit": "s", "higher_is_better": False, "n_gpus": 1,
-            "value": runs["learned"].get("seconds"), "dtype": "c64 Krylov solves, BF16 network weights",
+            "value": runs.get("learned", {}).get("seconds"), "dtype": "c64 Krylov solves, BF16 network weights",
             "data": "synthetic",
             "config": {"workload": f"3D convection-diffusion-reaction {N}^3 (n={p.n}), held-out field, "
                                    f"{p.info['m_in']} eigenvalues, Ne=16, m0=96, FGMRES(30) x 2"},
@@ -839,6 +849,7 @@ def main():
     ap.add_argument("--grid3d", type=int, default=64, help="convdiff3d: grid points per side")
     ap.add_argument("--train-fields", type=int, default=32, help="convdiff3d: training convection fields")
     ap.add_argument("--epochs", type=int, default=20, help="convdiff3d: training epochs")
+    ap.add_argument("--preconds", default="learned,ilu0,jacobi,none", help="convdiff3d: preconditioners to run")
     ap.add_argument("--eigs", default=None, help="headline workload: reference eigenvalues (.npy or the golden "
                                                  "JSON; default the 1024 x 1024 one)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")

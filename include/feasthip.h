@@ -155,6 +155,17 @@ typedef struct {
                              passed over, the next iteration must pass with
                              the same number of converged inside pairs, and
                              every inside pair below eps is returned */
+    int conj_pairs;       /* sparse problems with real A (FH_R64): 1 (default)
+                             = when the nodes are symmetric about the real
+                             axis (each lower node the conjugate of an upper
+                             one, with the conjugate weight), factorize only
+                             the upper and real-axis nodes and solve a lower
+                             node's systems as its partner's with conjugated
+                             right-hand sides (paper, reduced-workload cases,
+                             real non-symmetric with a contour symmetric about
+                             the real axis: n_e/2 factorizations; Table
+                             tab:solve).  The solves stay 2 n_e: the start
+                             block is complex.  0 = factorize every node */
 } fh_opts;
 
 typedef struct {

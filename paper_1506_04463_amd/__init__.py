@@ -63,7 +63,7 @@ class fh_opts(C.Structure):
                 ("inner_tol", C.c_double), ("max_restarts", C.c_int), ("mixed_inner_tol", C.c_double),
                 ("max_refine", C.c_int), ("save_factors", C.c_int), ("resume", C.c_int), ("fallback", C.c_int),
                 ("graph", C.c_int), ("orth", C.c_int), ("batch_nodes", C.c_int),
-                ("sym", C.c_int), ("confirm", C.c_int)]
+                ("sym", C.c_int), ("confirm", C.c_int), ("conj_pairs", C.c_int)]
 
 
 class fh_report(C.Structure):

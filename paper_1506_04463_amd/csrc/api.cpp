@@ -102,6 +102,7 @@ void fh_default_opts(fh_opts* o) {
     o->batch_nodes = 0;
     o->sym = 0;
     o->confirm = 0;
+    o->conj_pairs = 1;
 }
 
 int fh_create(fh_handle* h, int device, void* stream, const fh_allocator* alloc) {

@@ -408,7 +408,19 @@ struct FeastRun {
         int hi[2];
         to_host(c, hi, ints, 2);
         if (hi[1] == 1) retry_bq_reversed(hi);
-        if (hi[1] != 0) throw Error(FH_EIG_FAILED, "eigendecomposition of B_Q failed (code " + std::to_string(hi[1]) + ")");
+        if (hi[1] != 0) {
+            // diagnostics: FH_DUMP_BQ=<path> writes the matrix whose
+            // eigendecomposition failed (m, then m x m complex row-major)
+            if (const char* path = std::getenv("FH_DUMP_BQ")) {
+                if (FILE* f = std::fopen(path, "wb")) {
+                    const int mm = mcur;
+                    std::fwrite(&mm, sizeof(int), 1, f);
+                    std::fwrite(hbq.data(), sizeof(cplx), (size_t)mcur * mcur, f);
+                    std::fclose(f);
+                }
+            }
+            throw Error(FH_EIG_FAILED, "eigendecomposition of B_Q failed (code " + std::to_string(hi[1]) + ")");
+        }
         mt = hi[0];
         FH_REQUIRE(mt >= 1 && mt <= mcur, FH_EIG_FAILED, "resize produced an empty subspace");
     }

@@ -30,13 +30,15 @@ struct NetDev {
 
 template <typename T>
 void net_encode(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* V, const float* scale, const zd* shifts,
-                const int* sides, float* x);
+                const int* sides, float* x, int ld = 0, int c0 = 0);
 template <typename T>
-void net_decode(hipStream_t st, const NetDev& N, int m, int nsys, const float* o, const float* scale, Cx<T>* Out);
+void net_decode(hipStream_t st, const NetDev& N, int m, int nsys, const float* o, const float* scale, Cx<T>* Out,
+                int ld = 0, int c0 = 0);
 template <typename T>
 void net_target(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* E, const float* scale, float* t);
 template <typename T>
-void net_inv_colnorm(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* V, float* sc);
+void net_inv_colnorm(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* V, float* sc, int ld = 0,
+                     int c0 = 0);
 // s1, s2: split (BF16 hi / lo) workspaces of 2 x npix x 16 x mt entries each
 void net_forward(hipStream_t st, const NetDev& N, int mt, const float* x, float* a1, float* a2, float* out,
                  uint16_t* s1, uint16_t* s2);

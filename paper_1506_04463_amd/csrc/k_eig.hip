@@ -85,12 +85,40 @@ __device__ __forceinline__ void givens(zd x, zd y, double& c, zd& s, zd& r) {
 }
 
 // Shifted QR on an upper Hessenberg H to the Schur form T (in H), Z <- Z G^H.
-// Returns 0 on success, 1 if the iteration budget is exhausted.
-__device__ int schur_qr(int m, zd* H, zd* Z) {
+// Returns 0 on success, 1 if the iteration budget is exhausted.  loose: the
+// stagnation fallback below deflates at sqrt(ulp) ||H|| after 5 max(10, m)
+// sweeps (B_Q), else at ulp ||H|| after 10 max(10, m) (reduced eigenproblem).
+__device__ int schur_qr(int m, zd* H, zd* Z, bool loose) {
     const int tid = threadIdx.x;
     const double ulp = DBL_EPSILON, smlnum = DBL_MIN * (double(m) / DBL_EPSILON);
     int ihi = m - 1, its = 0;
     __shared__ int lsh, lst;
+    // Frobenius norm of H (kept by every unitary similarity of the iteration):
+    // after a number of sweeps without a deflation a subdiagonal entry below
+    // tol ||H|| counts as negligible too.  The local test stalls for good on
+    // a tight cluster: B_Q near convergence holds dozens of eigenvalues
+    // rho_a^2 = 1 to within 1e-8 (the converged pairs), where the Wilkinson
+    // shift cannot separate the trailing entry from its neighbours (seen
+    // stuck at |h| = 1e-11 for 2,880 sweeps on the 64^3 workload).  B_Q's
+    // decomposition only resizes and bi-orthonormalizes the subspace, and
+    // the reduced eigenproblem restores Wh^H B_U W = I exactly, so deflating
+    // at sqrt(ulp) ||H|| there costs no accuracy in the result; the reduced
+    // eigenproblem itself keeps ulp ||H||.
+    __shared__ double hred[ENT];
+    {
+        double a = 0.0;
+        for (int e = tid; e < m * m; e += ENT) a += abs2(H[e]);
+        hred[tid] = a;
+        __syncthreads();
+        for (int s2 = ENT / 2; s2 > 0; s2 >>= 1) {
+            if (tid < s2) hred[tid] += hred[tid + s2];
+            __syncthreads();
+        }
+    }
+    const double hnorm = sqrt(hred[0]);
+    const int stall = (loose ? 5 : 10) * max(10, m);
+    const double stol = (loose ? sqrt(ulp) : ulp) * hnorm;
+    __syncthreads();
     while (ihi >= 1) {
         // largest kk <= ihi with a negligible subdiagonal entry (0 if none):
         // every thread tests its own entries and one LDS maximum combines them
@@ -104,7 +132,8 @@ __device__ int schur_qr(int m, zd* H, zd* Z) {
                 if (kk - 2 >= 0) tst += fabs(H[(long)(kk - 1) * m + kk - 2].re);
                 if (kk + 1 <= ihi) tst += fabs(H[(long)(kk + 1) * m + kk].re);
             }
-            if (sub <= fmax(ulp * tst, smlnum)) atomicMax(&lsh, kk);
+            if (sub <= fmax(ulp * tst, smlnum) || (its > stall && sub <= stol))
+                atomicMax(&lsh, kk);
         }
         __syncthreads();
         const int l = lsh;
@@ -270,7 +299,7 @@ static size_t eig_work_elems(int m) { return (size_t)m * m * 8 + 2 * (size_t)m +
 // dependent Givens steps then waits on LDS, not on global memory.
 constexpr int EIG_LDS_M = 64;
 
-__device__ void eig_core(int m, zd* H, zd* Z, zd* X, zd* V, zd* v, double* red, int* info) {
+__device__ void eig_core(int m, zd* H, zd* Z, zd* X, zd* V, zd* v, double* red, int* info, bool loose) {
     const int tid = threadIdx.x;
     extern __shared__ unsigned char eig_dsm[];
     const bool lds = m <= EIG_LDS_M;
@@ -282,7 +311,7 @@ __device__ void eig_core(int m, zd* H, zd* Z, zd* X, zd* V, zd* v, double* red, 
     }
     __syncthreads();
     hessenberg(m, Hw, Zw, v, red);
-    int bad = schur_qr(m, Hw, Zw);
+    int bad = schur_qr(m, Hw, Zw, loose);
     if (lds) {
         for (int e = tid; e < m * m; e += ENT) {
             H[e] = Hw[e];
@@ -303,7 +332,7 @@ __device__ void biortho_body(int m, const zd* __restrict__ BQ, double eta, zd* _
     if (tid == 0) *info = 0;
     for (size_t e = tid; e < mm; e += ENT) H[e] = BQ[e];
     __syncthreads();
-    eig_core(m, H, Z, X, V, v, red, info);
+    eig_core(m, H, Z, X, V, v, red, info, true);
     // gamma (unsorted) = diag(T)
     // V^{-1} by Gauss-Jordan on [V | I]
     for (int e = tid; e < 2 * m * m; e += ENT) {
@@ -369,7 +398,7 @@ __device__ void reduced_body(int m, const zd* __restrict__ AU, const zd* __restr
     if (bad && tid == 0) *info = 2;
     for (int e = tid; e < (int)mm; e += ENT) H[e] = Aug[(long)(e / m) * w3 + m + (e % m)];
     __syncthreads();
-    eig_core(m, H, Z, X, V, v, red, info);
+    eig_core(m, H, Z, X, V, v, red, info, false);
     for (int i = tid; i < m; i += ENT) lam[i] = H[(long)i * m + i];
     for (size_t e = tid; e < mm; e += ENT) W[e] = V[e];
     // keep B_U^{-1} (right third of Aug) in X

@@ -40,8 +40,9 @@ __device__ __forceinline__ void tap_off(int tap, int& dz, int& dy, int& dx) {
 //   ch 0, 1: Re/Im of V[s][p][c] * scale[col]; ch 2, 3: Re/Im of shift_s / alpha;
 //   ch 4: side_s; ch 5..: fields[f][p]
 // ---------------------------------------------------------------------------
+// V rows of ld entries (ld >= m): column c of the window is entry c0 + c
 template <typename T>
-__global__ void k_net_encode(int npix, int m, int nsys, int cin, const Cx<T>* __restrict__ V,
+__global__ void k_net_encode(int npix, int m, int nsys, int cin, const Cx<T>* __restrict__ V, int ld, int c0,
                              const float* __restrict__ scale, const zd* __restrict__ shifts, const int* __restrict__ sides,
                              double inv_alpha, const float* __restrict__ fields, float* __restrict__ x) {
     const int mt = nsys * m;
@@ -49,7 +50,7 @@ __global__ void k_net_encode(int npix, int m, int nsys, int cin, const Cx<T>* __
     if (e >= (long)npix * mt) return;
     const int p = e / mt, col = e % mt;
     const int s = col / m, c = col % m;
-    const Cx<T> v = V[(long)s * npix * m + (long)p * m + c];
+    const Cx<T> v = V[(long)s * npix * ld + (long)p * ld + c0 + c];
     const float sc = scale ? scale[col] : 1.0f;
     float* xp = x + (long)p * cin * mt + col;
     xp[0] = (float)v.re * sc;
@@ -64,7 +65,7 @@ __global__ void k_net_encode(int npix, int m, int nsys, int cin, const Cx<T>* __
 // Out[s][p][c] = oscale (o[p][0][col] + i o[p][1][col]) / scale[col]  (scale = 1/||r|| of the input)
 template <typename T>
 __global__ void k_net_decode(int npix, int m, int nsys, float oscale, const float* __restrict__ o,
-                             const float* __restrict__ scale, Cx<T>* __restrict__ Out) {
+                             const float* __restrict__ scale, Cx<T>* __restrict__ Out, int ld, int c0) {
     const int mt = nsys * m;
     long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long)npix * mt) return;
@@ -73,7 +74,7 @@ __global__ void k_net_decode(int npix, int m, int nsys, float oscale, const floa
     const float sc = scale ? scale[col] : 1.0f;
     const float inv = sc > 0.0f ? oscale / sc : 0.0f;
     const float* op = o + (long)p * 2 * mt + col;
-    Out[(long)s * npix * m + (long)p * m + c] = Cx<T>{T(op[0] * inv), T(op[mt] * inv)};
+    Out[(long)s * npix * ld + (long)p * ld + c0 + c] = Cx<T>{T(op[0] * inv), T(op[mt] * inv)};
 }
 
 // ---------------------------------------------------------------------------
@@ -484,14 +485,15 @@ __global__ void k_to_bf16(int np, const float* __restrict__ w, uint16_t* __restr
 
 // per-column 1/||V col|| (0 for a zero column)
 template <typename T>
-__global__ void k_inv_colnorm(int npix, int m, int nsys, const Cx<T>* __restrict__ V, float* __restrict__ sc) {
+__global__ void k_inv_colnorm(int npix, int m, int nsys, const Cx<T>* __restrict__ V, int ld, int c0,
+                              float* __restrict__ sc) {
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
     const int mt = nsys * m;
     if (col >= mt) return;
     const int s = col / m, c = col % m;
     double a = 0.0;
     for (int p = 0; p < npix; ++p) {
-        const Cx<T> v = V[(long)s * npix * m + (long)p * m + c];
+        const Cx<T> v = V[(long)s * npix * ld + (long)p * ld + c0 + c];
         a += (double)v.re * v.re + (double)v.im * v.im;
     }
     sc[col] = a > 0 ? (float)(1.0 / sqrt(a)) : 0.0f;
@@ -505,16 +507,18 @@ static dim3 conv_grid(int npix, int mt) { return dim3(ceil_div(npix, 4), ceil_di
 
 template <typename T>
 void net_encode(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* V, const float* scale, const zd* shifts,
-                const int* sides, float* x) {
+                const int* sides, float* x, int ld, int c0) {
     const long tot = (long)N.npix() * m * nsys;
-    k_net_encode<T><<<ceil_div(tot, 256), 256, 0, st>>>(N.npix(), m, nsys, N.cin, V, scale, shifts, sides,
-                                                         N.inv_alpha, N.fields, x);
+    k_net_encode<T><<<ceil_div(tot, 256), 256, 0, st>>>(N.npix(), m, nsys, N.cin, V, ld > 0 ? ld : m, c0, scale,
+                                                         shifts, sides, N.inv_alpha, N.fields, x);
     FH_LAUNCH_CHECK();
 }
 template <typename T>
-void net_decode(hipStream_t st, const NetDev& N, int m, int nsys, const float* o, const float* scale, Cx<T>* Out) {
+void net_decode(hipStream_t st, const NetDev& N, int m, int nsys, const float* o, const float* scale, Cx<T>* Out,
+                int ld, int c0) {
     const long tot = (long)N.npix() * m * nsys;
-    k_net_decode<T><<<ceil_div(tot, 256), 256, 0, st>>>(N.npix(), m, nsys, N.oscale, o, scale, Out);
+    k_net_decode<T><<<ceil_div(tot, 256), 256, 0, st>>>(N.npix(), m, nsys, N.oscale, o, scale, Out, ld > 0 ? ld : m,
+                                                         c0);
     FH_LAUNCH_CHECK();
 }
 template <typename T>
@@ -524,17 +528,17 @@ void net_target(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* E
     FH_LAUNCH_CHECK();
 }
 template <typename T>
-void net_inv_colnorm(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* V, float* sc) {
-    k_inv_colnorm<T><<<ceil_div(m * nsys, 64), 64, 0, st>>>(N.npix(), m, nsys, V, sc);
+void net_inv_colnorm(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* V, float* sc, int ld, int c0) {
+    k_inv_colnorm<T><<<ceil_div(m * nsys, 64), 64, 0, st>>>(N.npix(), m, nsys, V, ld > 0 ? ld : m, c0, sc);
     FH_LAUNCH_CHECK();
 }
-template void net_encode<double>(hipStream_t, const NetDev&, int, int, const zd*, const float*, const zd*, const int*, float*);
-template void net_encode<float>(hipStream_t, const NetDev&, int, int, const cf*, const float*, const zd*, const int*, float*);
-template void net_decode<double>(hipStream_t, const NetDev&, int, int, const float*, const float*, zd*);
-template void net_decode<float>(hipStream_t, const NetDev&, int, int, const float*, const float*, cf*);
+template void net_encode<double>(hipStream_t, const NetDev&, int, int, const zd*, const float*, const zd*, const int*, float*, int, int);
+template void net_encode<float>(hipStream_t, const NetDev&, int, int, const cf*, const float*, const zd*, const int*, float*, int, int);
+template void net_decode<double>(hipStream_t, const NetDev&, int, int, const float*, const float*, zd*, int, int);
+template void net_decode<float>(hipStream_t, const NetDev&, int, int, const float*, const float*, cf*, int, int);
 template void net_target<double>(hipStream_t, const NetDev&, int, int, const zd*, const float*, float*);
-template void net_inv_colnorm<double>(hipStream_t, const NetDev&, int, int, const zd*, float*);
-template void net_inv_colnorm<float>(hipStream_t, const NetDev&, int, int, const cf*, float*);
+template void net_inv_colnorm<double>(hipStream_t, const NetDev&, int, int, const zd*, float*, int, int);
+template void net_inv_colnorm<float>(hipStream_t, const NetDev&, int, int, const cf*, float*, int, int);
 
 template <int TAPS>
 static void forward_t(hipStream_t st, const NetDev& N, int mt, const float* x, float* a1, float* a2, float* out,

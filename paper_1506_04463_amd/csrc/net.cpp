@@ -104,21 +104,40 @@ static void upload_sys(Ctx& c, NetState& S, int nsys, const double* shifts, cons
     FH_HIP(hipStreamSynchronize(c.stream));
 }
 
+// Activation workspace of the forward pass: about 300 bytes per (pixel, column)
+// (FP32 inputs and hidden layers, their BF16 hi / lo splits, the output).  A
+// pass covers at most NET_PASS_BYTES of it: the systems in groups, or one
+// system in windows of its columns (a multiple of 16) when its m columns do
+// not fit.
+constexpr double NET_PASS_BYTES = 6e9;
+
 template <typename T>
 void net_apply(Ctx& c, NetState& S, int nsys, int m, const Cx<T>* V, const zd* shifts_dev, const int* sides_dev,
                Cx<T>* Out, bool unit_columns) {
     const long npix = (long)S.d.npix();
-    const int mt = nsys * m;
-    ensure_acts(S, npix, mt);
-    float* sc = nullptr;
-    if (!unit_columns) {
-        sc = (float*)S.scale.ensure(sizeof(float) * mt);
-        net_inv_colnorm<T>(c.stream, S.d, m, nsys, V, sc);
+    const double per_col = (double)npix * (4.0 * (S.d.cin + 2 * NET_HID + 2) + 4.0 * 2 * 16);
+    const int cap = std::max(16, (int)(NET_PASS_BYTES / per_col) / 16 * 16);
+    const int mc = std::min(m, cap);                        // columns of a window
+    const int gs = std::max(1, std::min(nsys, cap / std::max(1, mc)));   // systems of a group
+    const long blk = npix * m;
+    for (int s0 = 0; s0 < nsys; s0 += gs) {
+        const int g = std::min(gs, nsys - s0);
+        for (int c0 = 0; c0 < m; c0 += mc) {
+            const int w = std::min(mc, m - c0);
+            const int mt = g * w;
+            ensure_acts(S, npix, mt);
+            float* sc = nullptr;
+            if (!unit_columns) {
+                sc = (float*)S.scale.ensure(sizeof(float) * mt);
+                net_inv_colnorm<T>(c.stream, S.d, w, g, V + s0 * blk, sc, m, c0);
+            }
+            net_encode<T>(c.stream, S.d, w, g, V + s0 * blk, sc, shifts_dev + s0, sides_dev + s0, (float*)S.x.p, m,
+                          c0);
+            net_forward(c.stream, S.d, mt, (const float*)S.x.p, (float*)S.a1.p, (float*)S.a2.p, (float*)S.out.p,
+                        (uint16_t*)S.s1.p, (uint16_t*)S.s2.p);
+            net_decode<T>(c.stream, S.d, w, g, (const float*)S.out.p, sc, Out + s0 * blk, m, c0);
+        }
     }
-    net_encode<T>(c.stream, S.d, m, nsys, V, sc, shifts_dev, sides_dev, (float*)S.x.p);
-    net_forward(c.stream, S.d, mt, (const float*)S.x.p, (float*)S.a1.p, (float*)S.a2.p, (float*)S.out.p,
-                (uint16_t*)S.s1.p, (uint16_t*)S.s2.p);
-    net_decode<T>(c.stream, S.d, m, nsys, (const float*)S.out.p, sc, Out);
 }
 template void net_apply<double>(Ctx&, NetState&, int, int, const zd*, const zd*, const int*, zd*, bool);
 template void net_apply<float>(Ctx&, NetState&, int, int, const cf*, const zd*, const int*, cf*, bool);

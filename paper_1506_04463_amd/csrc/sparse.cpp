@@ -732,7 +732,47 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
     hipStream_t st = c.stream;
     const int n = S.n;
     const long blk = (long)n * m;
-    if (needs_factors(o)) ensure_factors(c, S, ne, z, o.precision == FH_PREC_MIXED, o, rep);
+    // Real A and a node set symmetric about the real axis (each lower node the
+    // conjugate of an upper one, with the conjugate weight): for real A,
+    // (conj(z) - A)^{-1} b = conj((z - A)^{-1} conj(b)) and
+    // (conj(z) - A)^{-H} b = conj((z - A)^{-H} conj(b)), and the ILU(0) of
+    // conj(z) - A is the conjugate of that of z - A, so only the upper (and
+    // real-axis) nodes are factorized: a lower node's systems are solved as
+    // its upper partner's with conjugated right-hand sides, and their
+    // solutions conjugated back (the paper's real non-symmetric case with a
+    // contour symmetric about the real axis: n_e/2 factorizations).
+    std::vector<int> fmap(ne), flip(ne, 0);
+    std::vector<cplx> fz;
+    for (int j = 0; j < ne; ++j) fmap[j] = j;
+    bool paired = false;
+    if (o.conj_pairs && !S.A.complex_vals) {
+        std::vector<int> partner(ne, -1);
+        bool ok = true;
+        for (int j = 0; j < ne && ok; ++j) {
+            if (z[j].imag() == 0.0) continue;
+            for (int k = 0; k < ne; ++k) {
+                const double tz = 1e-13 * (1.0 + std::abs(z[j])), tw = 1e-13 * (1.0 + std::abs(w[j]));
+                if (k != j && std::abs(z[k] - std::conj(z[j])) <= tz && std::abs(w[k] - std::conj(w[j])) <= tw) {
+                    partner[j] = k;
+                    break;
+                }
+            }
+            ok = partner[j] >= 0;
+        }
+        if (ok) {
+            paired = true;
+            std::vector<int> fidx(ne, -1);
+            for (int j = 0; j < ne; ++j)
+                if (z[j].imag() >= 0.0) { fidx[j] = (int)fz.size(); fz.push_back(z[j]); }
+            for (int j = 0; j < ne; ++j) {
+                if (z[j].imag() >= 0.0) fmap[j] = fidx[j];
+                else { fmap[j] = fidx[partner[j]]; flip[j] = 1; }
+            }
+        }
+    }
+    if (!paired) fz.assign(z, z + ne);
+    const int nf = (int)fz.size();
+    if (needs_factors(o)) ensure_factors(c, S, nf, fz.data(), o.precision == FH_PREC_MIXED, o, rep);
     const int g = filter_chunk(S, ne, m, o);
     zd* Bb = (zd*)S.bufB.ensure(sizeof(zd) * blk * 2 * g);
     zd* Xb = (zd*)S.bufX.ensure(sizeof(zd) * blk * 2 * g);
@@ -782,8 +822,15 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
         if (!right_only) replicate<double>(st, blk, Rl, Bb + gc * blk, gc);
         std::vector<int> node_of(sides * gc);
         std::vector<cplx> zsys(sides * gc);
-        for (int q = 0; q < sides * gc; ++q) { node_of[q] = j0 + q % gc; zsys[q] = z[j0 + q % gc]; }
+        for (int q = 0; q < sides * gc; ++q) {
+            const int j = j0 + q % gc;
+            node_of[q] = fmap[j];
+            zsys[q] = paired ? fz[fmap[j]] : z[j];
+            if (flip[j]) conj_copy(st, blk, Bb + (long)q * blk, Bb + (long)q * blk);   // conj(b)
+        }
         const SolveStats sc = solve_batch(c, S, sides * gc, gc, node_of.data(), zsys.data(), m, Bb, Xb, o);
+        for (int q = 0; q < sides * gc; ++q)
+            if (flip[j0 + q % gc]) conj_copy(st, blk, Xb + (long)q * blk, Xb + (long)q * blk);
         s.steps += sc.steps;
         s.cycles += sc.cycles;
         s.relres = std::max(s.relres, sc.relres);

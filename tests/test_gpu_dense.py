@@ -375,3 +375,23 @@ def test_feast_confirm_option_returns_every_converged_pair(handle):
     assert np.max(np.abs(lit["lam"][:, None] - con["lam"][None, :]).min(axis=1)) < 1e-10 * cont.alpha()
     X, Xh = con["X"].cpu().numpy(), con["Xh"].cpu().numpy()
     assert np.max(np.abs(Xh.conj().T @ X - np.eye(6))) < 1e-10
+
+
+def test_biortho_factors_clustered_bq_regression(handle):
+    """Regression: a B_Q recorded when the 64^3 convection-diffusion-reaction
+    workload (no preconditioner) failed with status 7 at its 12th iteration:
+    72 eigenvalues rho_a^2 = 1 within about 1e-8 (the converged pairs), on
+    which the shifted QR iteration's local deflation test stalled at a
+    trailing subdiagonal entry of 1e-11 for its whole budget, on both basis
+    orders.  The decomposition now succeeds: the eigenvalues equal LAPACK's
+    (to the cluster's conditioning) and the factors bi-orthonormalize B_Q."""
+    import os
+    BQ = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "bq_cluster_convdiff3d64.npy"))
+    m = BQ.shape[0]
+    gam, S, Sh, mt = fh.biortho_factors(handle, _cuda(BQ))
+    gam, S, Sh = gam.cpu().numpy(), S.cpu().numpy(), Sh.cpu().numpy()
+    ref = sla.eigvals(BQ)
+    assert np.max(np.abs(gam[:, None] - ref[None, :]).min(axis=1)) < 1e-7
+    assert mt == m
+    G = Sh[:, :mt].conj().T @ BQ @ S[:, :mt]
+    assert np.max(np.abs(G - np.eye(mt))) < 1e-6

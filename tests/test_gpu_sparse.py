@@ -468,3 +468,33 @@ def test_feast_convdiff_full_size_closed_form(handle):
     rr = np.abs(As @ X - X * lam).sum(axis=0) / (nA * np.abs(X).sum(axis=0))
     rl = np.abs(As.T @ Xh - Xh * np.conj(lam)).sum(axis=0) / (nA * np.abs(Xh).sum(axis=0))
     assert rr.max() <= 1e-10 and rl.max() <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_filter_real_conjugate_node_pairs(handle, precision):
+    """Real A and an ellipse centred on the real axis: the nodes pair up as
+    conjugates, so only the 8 upper nodes are factorized (opts.conj_pairs,
+    the paper's real non-symmetric case with a contour symmetric about the
+    real axis) and a lower node's systems are solved as the conjugates of its
+    partner's; the filter equals the one that factorizes all 16 nodes, and the
+    oracle's."""
+    p = _small_convdiff()
+    z, w = ct.ellipse_nodes(p.contour.center, p.contour.a, p.contour.ratio, 0.0, 16)
+    Qo, Qho = F.contour_filter(L.csr_matrix(p.A), None, z, w, p.Y0, p.Yh0)
+    out = {}
+    for pairs in (1, 0):
+        prob = fh.Problem(handle, _csr(p.A))
+        opts = fh.default_opts(p.m0, solver=1, precond=2, inner_tol=1e-10, restart=30, max_restarts=400,
+                               precision=precision, mixed_inner_tol=1e-5, max_refine=30, conj_pairs=pairs)
+        Q, Qh, rep = fh.contour_filter(prob, z, w, _cuda(p.Y0), _cuda(p.Yh0), opts)
+        out[pairs] = (Q.cpu().numpy(), Qh.cpu().numpy(), rep)
+    assert out[1][2]["n_factor"] == 8 and out[0][2]["n_factor"] == 16
+    assert out[1][2]["n_solve"] == out[0][2]["n_solve"] == 32
+    for k in (0, 1):
+        a, b = out[1][k], out[0][k]
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+    Ad = W.csr_to_dense(p.A)
+    kap = max(np.linalg.cond(zj * np.eye(p.n) - Ad) for zj in z)
+    tol = 16 * kap * 1e-10
+    assert np.max(np.abs(out[1][0] - Qo)) <= tol * np.max(np.abs(Qo))
+    assert np.max(np.abs(out[1][1] - Qho)) <= tol * np.max(np.abs(Qho))
