@@ -49,15 +49,19 @@ def test_headline_configuration_reduced_grid(case, sym):
     alpha = cont.alpha()
     h = fh.Handle(0)
     prob = fh.Problem(h, _csr(p.A))
+    # confirmed exit (opts.confirm): with the inexact inner solves a true pair
+    # can still be flagged spurious when the paper's test first passes (22 of
+    # the 23 here), which the oracle's exact solves do not see
     o = fh.default_opts(p.m0, solver=1, precond=fh.FH_PC_ILU0, restart=30, max_restarts=2, inner_tol=1e-3,
                         precision=fh.FH_PREC_MIXED, mixed_inner_tol=1e-3, max_refine=1, max_iter=40, eps=1e-9, orth=2,
-                        sym=sym)
+                        sym=sym, confirm=1)
     out = fh.feast(prob, c.center, c.a, c.ratio, 0.0, 24, _cuda(p.Y0), _cuda(p.Yh0), o)
     assert out["info"] == 0, out["report"]
     lam = out["lam"]
     m = len(lam)
     assert m == len(ref.lam)
-    # element by element: the oracle's eigenvalues and ARPACK's (both sorted by (Re, Im))
+    # element by element: the oracle's eigenvalues and ARPACK's (both sorted by
+    # (Re, Im); the eigenvalues here are distinct in their real parts)
     assert np.max(np.abs(lam - ref.lam)) < 1e-10 * alpha
     u = eigs - c.center
     truth = np.sort_complex(eigs[(u.real / c.a) ** 2 + (u.imag / (c.ratio * c.a)) ** 2 < 1])
