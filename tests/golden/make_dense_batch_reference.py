@@ -3,8 +3,8 @@ generalized problems of the third configuration (workloads.gen_dense_batch
 with the radius scaled as 0.3 sqrt(256 / n_i)), the eigenvalues of (A_i, B_i)
 inside its circle, from LAPACK's QZ on the whole pencil
 (oracle.reference.dense_generalized_eigenvalues), and the distance of the
-nearest eigenvalue outside (a measure of the convergence rate).  About a
-quarter of an hour of CPU.
+nearest eigenvalue outside (a measure of the convergence rate).  About an hour
+of CPU on one core.
 
     python tests/golden/make_dense_batch_reference.py
 """

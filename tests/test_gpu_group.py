@@ -202,3 +202,39 @@ def test_graph_mixed_filter_repeated_calls(handle):
         Qg, Qhg, _ = fh.contour_filter(prob, z, w, Y, Yh, graph)
         torch.cuda.synchronize()
         assert torch.equal(Qe, Qg) and torch.equal(Qhe, Qhg)
+
+
+def test_feast_batched_full_dense_batch_against_qz():
+    """The third configuration at full size: 64 dense generalized problems,
+    n_i in [256, 2048], Ne = 8, m0 = 32, circles scaled to about 23
+    eigenvalues, in one batched call in the launch configuration of its
+    benchmark (complex-FP32 grouped LU on MFMA, FP64 refinement to 1e-10,
+    graph replay), to eq:res <= 1e-10 with the confirmed exit: every problem
+    returns exactly the eigenvalues LAPACK's QZ puts inside its circle
+    (tests/golden, written by a script that calls the oracle)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "dense_batch64_inside.json")) as f:
+        gold = json.load(f)["problems"]
+    ps = W.gen_dense_batch(count=64, nmin=256, nmax=2048, ne=8, m0=32, seed=3, scaled_radius=True)
+    h = fh.Handle(0)
+    probs = [fh.Problem(h, _cuda(p.A), _cuda(p.B)) for p in ps]
+    conts = [(p.contour.center, p.contour.a, 1.0, 0.0, 8) for p in ps]
+    o = fh.default_opts(32, eps=1e-10, max_iter=60, precision=fh.FH_PREC_MIXED, inner_tol=1e-10, max_refine=6,
+                        graph=1, confirm=1)
+    rc, outs = fh.feast_batched(probs, conts, [_cuda(p.Y0) for p in ps], [_cuda(p.Yh0) for p in ps], o)
+    assert rc == 0
+    total = 0
+    for p, g, out in zip(ps, gold, outs):
+        assert g["n"] == p.n
+        truth = np.array([complex(a, b) for a, b in g["inside"]])
+        lam = out["lam"]
+        alpha = abs(p.contour.center) + p.contour.a
+        assert out["info"] == 0 and len(lam) == len(truth), (p.n, len(lam), len(truth))
+        # eigenvalue error <= cond(lambda) * eq:res * alpha, with cond(lambda)
+        # of a random pencil above 1; the inside eigenvalues are at least
+        # 6e-3 alpha apart, so a match to 1e-8 alpha is one to one
+        d = np.abs(lam[:, None] - truth[None, :])
+        assert np.max(d.min(axis=1)) < 1e-8 * alpha and np.max(d.min(axis=0)) < 1e-8 * alpha
+        total += len(lam)
+    assert total > 64 * 10
