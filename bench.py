@@ -357,7 +357,7 @@ def csym(args):
             "higher_is_better": True, "dtype": "c64 inner solves + c128 refinement/Rayleigh-Ritz",
             "data": "synthetic",
             "config": {"workload": "complex-symmetric Schroedinger-type 256x256 (n=65536), Ne=16, m0=64, "
-                                   "GMRES(30)x2 + ILU(0), c64 + FP64 refinement"},
+                                   "GMRES(30)x2 + ILU(0), c64 solves + FP64 residual form"},
             "sym": res[1], "general": res[0],
             "speedup_per_iteration": res[0]["ms_per_iteration"] / res[1]["ms_per_iteration"],
             "same_eigenvalue_count": same, "max_dlam_over_alpha": dl, "count_estimate": count}
@@ -672,10 +672,13 @@ def schrodinger(args):
                                f"Ne={ne}, m0={p.m0}",
                    "solver": "GMRES(30) x 2 cycles + ILU(0), DCGS2, right solves only (sym), residual form",
                    "rhs_per_iteration": rhs},
-        "rhs_per_s": rhs * 1000.0 / ms_mx,
-        "rhs_solve": f"{ne} x {p.m0} right-hand sides per iteration, each 2 GMRES(30) cycles; worst relative "
-                     f"residual of the last timed filter {rep_mx['inner_relres']:.2e} (the FEAST exit, "
-                     f"eq:res <= {EPS_ITER:g}, is what the eigenpairs are held to)",
+        # the filter's solves run a fixed Krylov budget, not to a tolerance:
+        # this rate counts right-hand sides processed, not solved to 1e-10
+        "rhs_per_s_fixed_budget": rhs * 1000.0 / ms_mx,
+        "rhs_solve": f"{ne} x {p.m0} right-hand sides per iteration, each a fixed budget of 2 GMRES(30) cycles "
+                     f"(no per-solve tolerance); worst relative residual of the last timed filter "
+                     f"{rep_mx['inner_relres']:.2e}, relative to the residual-form right-hand side.  The "
+                     f"eigenpairs are held to the FEAST exit, eq:res <= {EPS_ITER:g} (see validity)",
         "plain_fp64": plain,
         "speedup_vs_fp64": None if plain is None else plain["ms_per_step"] / ms_mx,
         "validity": valid, "roofline": roof, "kernels": kernels, "cpu_baseline": cpu}
@@ -952,13 +955,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 inner solves + c128 refinement/Rayleigh-Ritz",
+        "dtype": "c64 inner solves + c128 residual check, residual form and Rayleigh-Ritz",
         "data": "synthetic",
         "config": {"workload": "convdiff2d 256x256 (n=65536, nnz=326656), Pe 20 along (1,0.5), ellipse around 41 "
-                               "eigenvalues, Ne=16, m0=64, GMRES(30)x2 + ILU(0), c64 + FP64 refinement",
+                               "eigenvalues, Ne=16, m0=64, GMRES(30)x2 + ILU(0), c64 solves + FP64 residual form",
                    "rhs_per_iteration": rhs,
-                   "orthogonalization": {0: "CGS2", 1: "CGS", 2: "DCGS2 (c64 solves)"}[ORTH]},
-        "rhs_per_s": rhs * 1000.0 / ms_mx,
+                   "orthogonalization": {0: "CGS2", 1: "CGS", 2: "DCGS2"}[ORTH]},
+        # fixed Krylov budget per right-hand side (2 GMRES(30) cycles), not a tolerance
+        "rhs_per_s_fixed_budget": rhs * 1000.0 / ms_mx,
         "plain_fp64": plain,
         "speedup_vs_fp64": None if plain is None else plain["ms_per_step"] / ms_mx,
         "time_to_solution_speedup_vs_fp64": (None if plain is None or valid is None or "time_to_solution" not in plain

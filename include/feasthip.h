@@ -183,6 +183,9 @@ typedef struct {
     double t_iter_ms;     /* time of the last full FEAST iteration            */
     long long n_fallback; /* solves whose learned preconditioner was replaced
                              by the fallback (cumulative)                     */
+    int n_bq_retry;       /* B_Q eigendecompositions that exhausted the shifted
+                             QR budget and were run again on the reversed
+                             basis order (cumulative)                         */
 } fh_report;
 
 /* ---- handle -----------------------------------------------------------

@@ -70,7 +70,7 @@ class fh_report(C.Structure):
     _fields_ = [("info", C.c_int), ("m", C.c_int), ("iters", C.c_int), ("m0_final", C.c_int),
                 ("bad_node", C.c_int), ("m_s", C.c_int), ("n_factor", C.c_longlong), ("n_solve", C.c_longlong),
                 ("inner_steps", C.c_longlong), ("inner_relres", C.c_double), ("t_filter_ms", C.c_double),
-                ("t_iter_ms", C.c_double), ("n_fallback", C.c_longlong)]
+                ("t_iter_ms", C.c_double), ("n_fallback", C.c_longlong), ("n_bq_retry", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

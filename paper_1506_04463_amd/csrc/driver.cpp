@@ -253,6 +253,10 @@ struct FeastRun {
     int *ints, *perm;
     int mcur = 0, it = 0, info = FH_NOT_CONVERGED, m_s = 0, prev_nconv = -1;
     bool converged = false, prev_pass = false, done = false;
+    const bool force_bq_retry = [] {
+        const char* e = std::getenv("FH_TEST_BQ_REVERSED");
+        return e && e[0] == '1';
+    }();
     std::vector<cplx> rho_prev, hlam, hbq, rho;
     std::vector<char> inside_prev, inside;
     std::vector<double> res, hn, hd, hn2, hd2;
@@ -377,6 +381,7 @@ struct FeastRun {
     // AUr is free at this point of the iteration (steps 3.e-3.f fill it).
     void retry_bq_reversed(int* hi) {
         const int m = mcur;
+        if (rep) ++rep->n_bq_retry;
         std::vector<cplx> rb((size_t)m * m);
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < m; ++j) rb[(size_t)i * m + j] = hbq[(size_t)(m - 1 - i) * m + (m - 1 - j)];
@@ -407,7 +412,9 @@ struct FeastRun {
         }
         int hi[2];
         to_host(c, hi, ints, 2);
-        if (hi[1] == 1) retry_bq_reversed(hi);
+        // FH_TEST_BQ_REVERSED=1 (test switch) takes the retry at every
+        // iteration, so that its row reversal of S and Sh is exercised
+        if (hi[1] == 1 || (hi[1] == 0 && force_bq_retry)) retry_bq_reversed(hi);
         if (hi[1] != 0) {
             // diagnostics: FH_DUMP_BQ=<path> writes the matrix whose
             // eigendecomposition failed (m, then m x m complex row-major)

@@ -53,7 +53,10 @@ struct IluApplyArgs {
     const Cx<T>* bval[2] = {nullptr, nullptr};
     const Cx<T>* bdiag[2] = {nullptr, nullptr};
     const Cx<T>* dinv = nullptr;                 // Jacobi: [node][n] (null: identity)
+    Cx<T>* junk = nullptr;   // write target of the pipelined sweep's fill and drain levels
+                             // (ILU_JUNK entries, written by every workgroup, never read)
 };
+constexpr int ILU_JUNK = 4096;
 
 struct NetState;
 
@@ -78,6 +81,7 @@ struct SparseState {
     DBuf pk64[6], pk32[6];          // packed sweep values: L, U, Udiag, UT, UTdiag, LT
     int ilu_cw64 = 4, ilu_cw32 = 8;  // columns per workgroup of the ILU sweeps (measured best at m = 64)
     // batch descriptors and GMRES workspace
+    DBuf junk;   // see IluApplyArgs::junk
     DBuf node_of, side_of, shifts64, shifts32, coef, rho, bufB, bufX, bufR, bufT, b32, x32;
     DBuf V, Z, Hs, cs, sn, g, resid, vscale, kuse, y, h1, h2, hnorm, beta, bnorm, part, bn64, rn64, sc64;
     DBuf Hraw, htent, tau, dcoef, scv, scw, dots;   // DCGS2

@@ -654,7 +654,8 @@ template <typename T, int P, int KM, int NT, int FR>
 __device__ __forceinline__ void sweep_pipe(const SweepDev& sw, int n, int m, int c0, int cw,
                                            const Cx<T>* __restrict__ val, const Cx<T>* __restrict__ dval,
                                            const Cx<T>* In, Cx<T>* Os, Cx<T>* ring, int ring_stride,
-                                           int* fslot_l, Cx<T>* fv_l, Cx<T>* fd_l, int wmax) {
+                                           int* fslot_l, Cx<T>* fv_l, Cx<T>* fd_l, int wmax, Cx<T>* junk) {
+    static_assert(NT * P <= ILU_JUNK, "junk buffer too small for one level's items");
     const int nlev = sw.nlev;
     if (nlev <= 0) return;
     using CI = const __attribute__((address_space(4))) int;
@@ -672,7 +673,7 @@ __device__ __forceinline__ void sweep_pipe(const SweepDev& sw, int n, int m, int
     }
     // level position of item q (or, for q < 0, of this thread's row) of level l, clamped
     auto pos_of = [&](int l, int r) {
-        const int L = min(l, nlev - 1);
+        const int L = min(max(l, 0), nlev - 1);
         const int t0 = lp[L], rows = lp[L + 1] - t0;
         return min(t0 + min(r, rows - 1), n - 1);
     };
@@ -727,10 +728,12 @@ __device__ __forceinline__ void sweep_pipe(const SweepDev& sw, int n, int m, int
         put_fac(b, (l + 1) & 1);
         load_row(l + 6, c);
         load_fac(l + 4, a);
-        const int rows = lp[l + 1] - lp[l];
+        const int Lc = max(l, 0);
+        const int rows = lp[Lc + 1] - lp[Lc];
         const Cx<T>* prev = ring + (long)((l + 1) & 1) * ring_stride;
         Cx<T>* cur = ring + (long)(l & 1) * ring_stride;
         const int fb = (l & 1) * wmax;
+        const bool real = l >= 0 && l < nlev;
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             const int pos = min(ediv[q], rows - 1);
@@ -744,41 +747,52 @@ __device__ __forceinline__ void sweep_pipe(const SweepDev& sw, int n, int m, int
             }
             if (hasd) v = fd_l[fb + pos] * v;
             cur[pos * cw + emod[q]] = v;
-            Os[a.off[q]] = v;
+            // fill and drain levels write to the junk buffer (a select, not a branch)
+            Cx<T>* dst = real ? Os + a.off[q] : junk + (tid + NT * q);
+            *dst = v;
         }
         lds_barrier();
     };
+    // One loop, one exit: the loop starts at level -8, and its first eight
+    // levels only fill the pipeline (their loads repeat level 0's rows, their
+    // results go to the junk buffer, and the factor data they read from LDS is
+    // the "no dependency" record written here); up to three drain levels past
+    // the last repeat its rows in the same way.  The compiler inserts its
+    // waits for loads in flight by merging every path into the loop header:
+    // a prologue of its own, or a break after each unrolled level, would merge
+    // histories with fewer loads issued since and make the header wait for
+    // loads of the previous level.
+    auto blank = [&](SP& sp) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) sp.row[q] = 0;
+#pragma unroll
+        for (int f = 0; f < FR; ++f) {
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                sp.fslot[f][k] = -1;
+                sp.fv[f][k] = czero<T>();
+            }
+            sp.fd[f] = czero<T>();
+        }
+    };
     SP s0, s1, s2, s3;
-    // The loads of levels 0-5 in the order the loop issues them (as if levels
-    // -6 to -1 ran): at the loop entry the compiler merges this order with the
-    // loop's own, and waits by the one with fewer loads issued since
-    // (scheduling barriers keep that order).
-    load_row(0, s0);
-    load_row(1, s1);
-    load_row(2, s2);
-    load_fac(0, s0);
-    __builtin_amdgcn_sched_barrier(0);
-    load_x(s0);
-    load_row(3, s3);
-    load_fac(1, s1);
-    __builtin_amdgcn_sched_barrier(0);
-    load_x(s1);
-    load_row(4, s0);
-    load_fac(2, s2);
-    __builtin_amdgcn_sched_barrier(0);
-    load_x(s2);
-    put_fac(s0, 0);
-    load_row(5, s1);
-    load_fac(3, s3);
-    __builtin_amdgcn_sched_barrier(0);
+    blank(s0);
+    blank(s1);
+    blank(s2);
+    blank(s3);
+    for (int i = tid; i < 2 * wmax; i += NT) {
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            fslot_l[i * KM + k] = -1;
+            fv_l[i * KM + k] = czero<T>();
+        }
+        fd_l[i] = czero<T>();
+    }
     __syncthreads();
-    for (int l = 0; l < nlev; l += 4) {
+    for (int l = -8; l < nlev; l += 4) {
         level(l, s0, s1, s2, s3);
-        if (l + 1 >= nlev) break;
         level(l + 1, s1, s2, s3, s0);
-        if (l + 2 >= nlev) break;
         level(l + 2, s2, s3, s0, s1);
-        if (l + 3 >= nlev) break;
         level(l + 3, s3, s0, s1, s2);
     }
 }
@@ -816,13 +830,13 @@ __global__ __launch_bounds__(NT) void k_ilu_apply_pipe(IluApplyArgs<T> a, const 
     const Cx<T>* bv = a.bval[side] + (long)node * B.K * a.n;
     const Cx<T>* bd = a.bdiag[side] ? a.bdiag[side] + (long)node * a.n : nullptr;
     sweep_pipe<T, P, KM, NT, FR>(F, a.n, a.m, c0, cw, fv, fd, X + base, Out + base, ring, ring_stride, fslot_l, fv_l,
-                                 fd_l, wmax);
+                                 fd_l, wmax, a.junk);
     // the backward sweep starts with the rows other waves stored last in the
     // forward sweep, whose stores the sweep loop leaves in flight
     __threadfence();
     __syncthreads();
     sweep_pipe<T, P, KM, NT, FR>(B, a.n, a.m, c0, cw, bv, bd, Out + base, Out + base, ring, ring_stride, fslot_l, fv_l,
-                                 fd_l, wmax);
+                                 fd_l, wmax, a.junk);
 }
 
 template <typename T, int P, int KM, int NT>
@@ -903,7 +917,7 @@ void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<
     }
     const size_t sh = ring_bytes + fac_bytes;
     const bool pipe = lds && sizeof(T) == 4 && K <= 2 && kmin >= 1 && wmax <= 1024 && (long)wmax * a.cw <= 2048 &&
-                      (long)a.n * a.m < (1L << 31) && sh <= (size_t)lds_max;
+                      (long)a.n * a.m < (1L << 31) && sh <= (size_t)lds_max && a.junk != nullptr;
     if (pipe) {
         if constexpr (sizeof(T) == 4) {
             const int stride = wmax * a.cw;

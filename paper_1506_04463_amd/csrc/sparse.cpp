@@ -402,6 +402,7 @@ static IluApplyArgs<T> ilu_args(SparseState& S, int m, int precond) {
     a.bval[1] = (const Cx<T>*)pk[5].p;
     a.bdiag[1] = nullptr;
     if (precond == FH_PC_JACOBI) a.dinv = (const Cx<T>*)(d ? S.jd64.p : S.jd32.p);
+    a.junk = (Cx<T>*)S.junk.ensure(sizeof(Cx<double>) * ILU_JUNK);
     return a;
 }
 

@@ -306,12 +306,14 @@ def test_feast_batched_multi_contour_one_matrix(handle, prec):
 
 def test_feast_fp64_bq_qr_retry_unit_disk_circle(handle):
     """A case whose B_Q made the shifted QR iteration exhaust its budget at
-    iteration 6 (status 7) before the reversed-order retry: the 4000 x 4000
-    matrix with eigenvalues area-uniform in the unit disk, the circle at
-    0.5 - 0.3i with its radius in the widest eigenvalue gap near 0.17
-    (156 eigenvalues inside), m0 = 200, Ne = 16, FP64 direct solves.  FEAST
-    now meets eps = 1e-7 and returns exactly the prescribed eigenvalues
-    (confirmed exit, opts.confirm)."""
+    iteration 6 (status 7) when the iteration had neither the reversed-order
+    retry nor the stall deflation for clusters: the 4000 x 4000 matrix with
+    eigenvalues area-uniform in the unit disk, the circle at 0.5 - 0.3i with
+    its radius in the widest eigenvalue gap near 0.17 (156 eigenvalues
+    inside), m0 = 200, Ne = 16, FP64 direct solves.  FEAST meets eps = 1e-7
+    and returns exactly the prescribed eigenvalues (confirmed exit,
+    opts.confirm).  With the stall deflation the first attempt converges; the
+    retry itself is covered by the forced-retry test below."""
     n, m0 = 4000, 200
     A, lam = W.dense_unit_disk(n, 12)
     c = 0.5 - 0.3j
@@ -330,6 +332,37 @@ def test_feast_fp64_bq_qr_retry_unit_disk_circle(handle):
     got = np.sort_complex(out["lam"])
     assert len(got) == len(truth)
     np.testing.assert_allclose(got, truth, rtol=0, atol=1e-9)
+    # the returned vectors are bi-orthonormal to the accuracy the reduced
+    # eigenvectors allow: 156 clustered eigenvalues of a non-normal matrix
+    # (measured 8e-7; a wrong pairing of left and right vectors gives O(1))
+    X, Xh = out["X"], out["Xh"]
+    G = (Xh.conj().T @ X).cpu().numpy()
+    assert np.max(np.abs(G - np.eye(len(got)))) < 1e-5
+
+
+def test_feast_forced_bq_retry_gives_the_same_pairs(handle, monkeypatch):
+    """The reversed-order retry of the B_Q eigendecomposition (J B_Q J, then
+    the rows of S and Sh reversed) forced at every iteration through the
+    library's test switch FH_TEST_BQ_REVERSED: same exit, same eigenvalues,
+    bi-orthonormal vectors, and the report counts one retry per iteration."""
+    p = W.dense_prescribed(n=300, n_in=12, center=0.1 + 0.1j, radius=0.25, ne=8, m0=24, seed=5)
+    prob = fh.Problem(handle, _cuda(p.A))
+    o = fh.default_opts(24, precision=fh.FH_PREC_FP64, eps=1e-12, max_iter=40)
+    c = p.contour
+    args = (prob, c.center, c.a, 1.0, 0.0, 8)
+    plain = fh.feast(*args, _cuda(p.Y0), _cuda(p.Yh0), o)
+    monkeypatch.setenv("FH_TEST_BQ_REVERSED", "1")
+    forced = fh.feast(*args, _cuda(p.Y0), _cuda(p.Yh0), o)
+    monkeypatch.delenv("FH_TEST_BQ_REVERSED")
+    assert plain["info"] == 0 and forced["info"] == 0
+    assert plain["report"]["n_bq_retry"] == 0
+    assert forced["report"]["n_bq_retry"] == forced["report"]["iters"]
+    a, b = np.sort_complex(plain["lam"]), np.sort_complex(forced["lam"])
+    assert len(a) == len(b) == 12
+    np.testing.assert_allclose(b, a, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(b, np.sort_complex(p.info["lam"][:12]), rtol=0, atol=1e-10)
+    G = (forced["Xh"].conj().T @ forced["X"]).cpu().numpy()
+    assert np.max(np.abs(G - np.eye(12))) < 1e-10
 
 
 @pytest.mark.parametrize("seed,n,n_in,m0", [(1, 120, 6, 24), (9, 150, 8, 30)])
