@@ -249,7 +249,8 @@ def learned3d(args):
     z = np.array([80.0 + 40.0j, 80.0 + 40.0j])
     B = torch.randn((2, A["n"], m), dtype=torch.complex128, device="cuda")
     res = {}
-    for name, pc in (("learned", fh.FH_PC_LEARNED), ("ilu0", fh.FH_PC_ILU0)):
+    for name, pc in (("learned", fh.FH_PC_LEARNED), ("learned_bf16", fh.FH_PC_LEARNED), ("ilu0", fh.FH_PC_ILU0)):
+        net.set_activations(name == "learned_bf16")
         o = fh.default_opts(m, precond=pc, restart=4, max_restarts=1, inner_tol=1e-300, precision=fh.FH_PREC_MIXED,
                             mixed_inner_tol=1e-300, max_refine=1, fallback=fh.FH_PC_NONE, save_factors=1)
         fh.shifted_solve(prob, z, [0, 1], B, o)          # warm-up (factors, code objects)
@@ -264,8 +265,9 @@ def learned3d(args):
     fw = res["learned"].get("net_forward")
     line = {"metric": "learned preconditioner apply cost, 64^3 grid", "columns_per_apply": cols,
             "gflop_per_column": None if fw is None else fw["TFLOPs"] * fw["ms_avg"] * 1e-3 * 1e12 / cols / 1e9,
-            "net_forward": fw, "ilu_apply": res["ilu0"].get("ilu_apply_c64"), "spmm": res["ilu0"].get("spmm_c64"),
-            "peak_fp32_vector_tflops": 157.3}
+            "net_forward": fw, "net_forward_bf16_activations": res["learned_bf16"].get("net_forward"),
+            "ilu_apply": res["ilu0"].get("ilu_apply_c64"), "spmm": res["ilu0"].get("spmm_c64"),
+            "peak_bf16_mfma_tflops": 2500.0}
     print(json.dumps(line))
 
 

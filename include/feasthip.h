@@ -343,6 +343,19 @@ int fh_reduced_eig(fh_handle h, int m, const void* AU, const void* BU, void* lam
 int fh_shifted_apply(fh_handle h, fh_problem p, int side, int nsys, const double* shifts, int m,
                      const void* X, void* Out);
 
+/* Training pairs of the learned preconditioner (not part of the paper's
+ * method; the pairs of the residual-norm loss): for s = 0..nsys-1, with
+ * M_s = shift_s I - op(A) (op = A for side 0, A^H for side 1),
+ *   R_s = B_s - M_s X_s    (residual of the iterate X_s)
+ *   E_s = Xt_s - X_s       (its error against the exact solution Xt_s)
+ * so that M_s E_s = R_s up to rounding when B_s = M_s Xt_s.  CSR problems
+ * only.  Every block is n x m (device, contiguous, system-major, complex
+ * double); shifts: host complex array of length nsys.  R and E must not
+ * overlap the inputs.  Returns FH_OK, or -k for an invalid argument k (-2
+ * for a dense problem). */
+int fh_residual_pair(fh_handle h, fh_problem p, int side, int nsys, const double* shifts, int m, const void* B,
+                     const void* X, const void* Xt, void* R, void* E);
+
 /* ILU(0) of (z B - A) for a CSR problem (natural ordering): factor values
  * aligned with A's CSR pattern (L strictly left of the diagonal, unit
  * diagonal implied; U on and right of it).  lu: device complex, nnz. */
@@ -417,6 +430,14 @@ int fh_net_set_params(fh_handle h, fh_net net, const float* params);
 /* replace the constant input fields (host [nfields][n], as at creation), e.g.
  * to train one network on the operators of several coefficient fields */
 int fh_net_set_fields(fh_handle h, fh_net net, const double* fields);
+/* activations of the network's inference passes (fh_net_forward and the
+ * preconditioner applications inside the Krylov solves): 0 (default) = FP32,
+ * each activation entering the MFMA layers as two BF16 terms (FP32-level
+ * accuracy); 1 = BF16, one term (the inputs of the first two layers rounded
+ * to BF16: half the operand loads and MFMA work, about 3 significant
+ * digits).  Training passes always use FP32 activations.  Returns FH_OK,
+ * -1 for a null net, -2 for another mode. */
+int fh_net_set_activations(fh_net net, int bf16);
 /* Out_s = network(V_s) for nsys blocks (device, [nsys][n][m] complex);
  * z, sides as in fh_shifted_solve. */
 int fh_net_forward(fh_handle h, fh_net net, int nsys, int m, const double* z, const int* sides,

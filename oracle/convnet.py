@@ -65,12 +65,25 @@ def conv3x3_backward(x, w, gout):
     return gxp[tuple(slice(1, -1) for _ in range(d))], gw, gb
 
 
-def forward(params, x):
-    """params: list of (w, b) for the 3 layers; returns output and cache."""
+def bf16_round(a):
+    """Nearest bfloat16 value (8 significant bits, float32's exponent range,
+    ties to even) of the float32 rounding of a, returned as float64."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward(params, x, act_round=None):
+    """params: list of (w, b) for the 3 layers; returns output and cache.
+
+    act_round (optional): a rounding applied to the inputs of the first two
+    layers (x and a1), for an inference mode that stores those activations
+    in a narrower format."""
     (w1, b1), (w2, b2), (w3, b3) = params
-    z1 = conv3x3(x, w1, b1)
+    r = act_round if act_round is not None else (lambda v: v)
+    z1 = conv3x3(r(x), w1, b1)
     a1 = np.maximum(z1, 0.0)
-    z2 = conv3x3(a1, w2, b2)
+    z2 = conv3x3(r(a1), w2, b2)
     a2 = np.maximum(z2, 0.0)
     out = conv3x3(a2, w3, b3)
     return out, (x, z1, a1, z2, a2)

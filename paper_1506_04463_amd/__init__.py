@@ -153,6 +153,7 @@ def lib():
         "fh_count_estimate": (i, [vp, vp, i, dp, dp, i, vp, vp, dp, vp]),
         "fh_reduced_eig": (i, [vp, i, vp, vp, vp, vp, vp]),
         "fh_shifted_apply": (i, [vp, vp, i, i, dp, i, vp, vp]),
+        "fh_residual_pair": (i, [vp, vp, i, i, dp, i, vp, vp, vp, vp, vp]),
         "fh_ilu0": (i, [vp, vp, d, d, vp]),
         "fh_ilu0_apply": (i, [vp, vp, d, d, i, i, vp, vp]),
         "fh_ilu0_apply_c64": (i, [vp, vp, d, d, i, i, vp, vp]),
@@ -166,6 +167,7 @@ def lib():
         "fh_net_set_params": (i, [vp, vp, C.POINTER(C.c_float)]),
         "fh_net_forward": (i, [vp, vp, i, i, dp, ip, vp, vp]),
         "fh_net_set_fields": (i, [vp, vp, dp]),
+        "fh_net_set_activations": (i, [vp, i]),
         "fh_net_train_step": (i, [vp, vp, vp, i, i, dp, ip, vp, vp, d, i, dp, C.POINTER(C.c_float)]),
         "fh_problem_set_net": (i, [vp, vp]),
         "fh_profile": (i, [vp, i]),
@@ -506,6 +508,19 @@ def shifted_apply(prob: Problem, side, shifts, X):
     return Out
 
 
+def residual_pair(prob: Problem, side, shifts, B, X, Xt):
+    """(R, E) with R_s = B_s - M_s X_s and E_s = Xt_s - X_s, M_s = shift_s - op(A)
+    (op = A or A^H), for (nsys, n, m) complex128 tensors (CSR problems)."""
+    torch = _torch()
+    nsys, n, m = X.shape
+    R = torch.empty_like(X)
+    E = torch.empty_like(X)
+    sk, sp = _cbuf(shifts)
+    prob.handle.check(lib().fh_residual_pair(prob.handle._h, prob._p, side, nsys, sp, m, _dptr(B), _dptr(X), _dptr(Xt),
+                                             _dptr(R), _dptr(E)), "fh_residual_pair")
+    return R, E
+
+
 def ilu0(prob: Problem, z):
     torch = _torch()
     nnz = prob._keep[0].colind.numel()
@@ -617,6 +632,12 @@ class Net:
         self._fields = f
         self.handle.check(lib().fh_net_set_fields(self.handle._h, self._n, f.ctypes.data_as(C.POINTER(C.c_double))),
                           "fh_net_set_fields")
+
+    def set_activations(self, bf16: bool):
+        """BF16 (True) or FP32 (False, the default) activations in inference passes."""
+        rc = lib().fh_net_set_activations(self._n, 1 if bf16 else 0)
+        if rc != 0:
+            raise FeastError(rc, "fh_net_set_activations")
 
     def forward(self, z, sides, V):
         """V: (nsys, n, m) complex128 -> network output of the same shape."""

@@ -485,6 +485,27 @@ int fh_shifted_apply(fh_handle h, fh_problem p, int side, int nsys, const double
     FH_API_END(h)
 }
 
+int fh_residual_pair(fh_handle h, fh_problem p, int side, int nsys, const double* shifts, int m, const void* B,
+                     const void* X, const void* Xt, void* R, void* E) {
+    if (!h) return -1;
+    if (!p || p->dense) return -2;
+    if (side != 0 && side != 1) return -3;
+    if (nsys < 1) return -4;
+    if (!shifts) return -5;
+    if (m < 1) return -6;
+    if (!B) return -7;
+    if (!X) return -8;
+    if (!Xt) return -9;
+    if (!R) return -10;
+    if (!E) return -11;
+    FH_API_BEGIN(h)
+    set_device(h);
+    sparse_residual_pair(*h, *p, side, nsys, reinterpret_cast<const cplx*>(shifts), m, (const zd*)B, (const zd*)X,
+                         (const zd*)Xt, (zd*)R, (zd*)E);
+    return FH_OK;
+    FH_API_END(h)
+}
+
 int fh_ilu0(fh_handle h, fh_problem p, double z_re, double z_im, void* lu) {
     if (!h) return -1;
     if (!p || p->dense) return -2;
@@ -675,6 +696,13 @@ int fh_net_set_fields(fh_handle h, fh_net net, const double* fields) {
     if (net_field_count(net->st) > 0) net_set_fields(*h, *net->st, fields);
     return FH_OK;
     FH_API_END(h)
+}
+
+int fh_net_set_activations(fh_net net, int bf16) {
+    if (!net) return -1;
+    if (bf16 != 0 && bf16 != 1) return -2;
+    net_set_activations(*net->st, bf16);
+    return FH_OK;
 }
 
 int fh_net_forward(fh_handle h, fh_net net, int nsys, int m, const double* z, const int* sides, const void* V,

@@ -90,6 +90,8 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m0
                    zd* Q, zd* Qh, const fh_opts& o, fh_report* rep, const cplx* lam);
 void sparse_apply_A(Ctx& c, Prob& p, int side, int m, const zd* X, zd* Out);
 void sparse_shifted_apply(Ctx& c, Prob& p, int side, int nsys, const cplx* shifts, int m, const zd* X, zd* Out);
+void sparse_residual_pair(Ctx& c, Prob& p, int side, int nsys, const cplx* shifts, int m, const zd* B, const zd* X,
+                          const zd* Xt, zd* R, zd* E);
 void sparse_ilu0(Ctx& c, Prob& p, cplx z, zd* lu_out);
 void sparse_ilu0_apply(Ctx& c, Prob& p, cplx z, int side, int m, const zd* X, zd* Out);
 void sparse_ilu0_apply32(Ctx& c, Prob& p, cplx z, int side, int m, const cf* X, cf* Out);
@@ -113,6 +115,7 @@ int net_param_count(const NetState* s);
 int net_grid_size(const NetState* s);
 void net_set_params(Ctx& c, NetState& S, const float* host);
 void net_set_fields(Ctx& c, NetState& S, const double* fields);
+void net_set_activations(NetState& S, int bf16);
 int net_field_count(const NetState* s);
 void net_get_params(Ctx& c, NetState& S, float* host);
 void net_forward_host(Ctx& c, NetState& S, int nsys, int m, const zd* X, const double* shifts, const int* sides, zd* Out);

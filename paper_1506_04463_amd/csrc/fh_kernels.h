@@ -48,6 +48,9 @@ void cast(hipStream_t st, long len, const Cx<S>* src, Cx<D>* dst);
 // Out = s X - Out (elementwise, len entries)
 void shift_combine(hipStream_t st, long len, zd s, const zd* X, zd* Out);
 
+// Out = A - B (elementwise, len entries)
+void sub(hipStream_t st, long len, const zd* A, const zd* B, zd* Out);
+
 // dst[i][k] = src[i][perm[k]] for k < mout (rows n; lds, ldd leading dims)
 void gather_cols(hipStream_t st, int n, int mout, const zd* src, long lds, const int* perm_dev, zd* dst,
                  long ldd);

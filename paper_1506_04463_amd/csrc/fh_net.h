@@ -19,6 +19,7 @@ struct NetDev {
     int taps = 9;                // 9 (2D grid, nz = 1) or 27 (3D grid)
     double inv_alpha = 1.0;
     float oscale = 1.0f;         // output scale: e = ||r|| oscale (o_0 + i o_1)
+    int bf16_act = 0;            // inference passes: 1 = BF16 activations, 0 = FP32 (two BF16 terms)
     int off_w1 = 0, off_b1 = 0, off_w2 = 0, off_b2 = 0, off_w3 = 0, off_b3 = 0;
     float* w = nullptr;          // FP32 master parameters
     uint16_t* wb = nullptr;      // BF16 copy used by the kernels
@@ -39,9 +40,11 @@ void net_target(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* E
 template <typename T>
 void net_inv_colnorm(hipStream_t st, const NetDev& N, int m, int nsys, const Cx<T>* V, float* sc, int ld = 0,
                      int c0 = 0);
-// s1, s2: split (BF16 hi / lo) workspaces of 2 x npix x 16 x mt entries each
+// s1, s2: split (BF16 hi / lo) workspaces of 2 x npix x 16 x mt entries each;
+// bf16_act: single-term BF16 inputs of the MFMA layers, a1 not written
+// (inference only: the backward pass needs the FP32 form)
 void net_forward(hipStream_t st, const NetDev& N, int mt, const float* x, float* a1, float* a2, float* out,
-                 uint16_t* s1, uint16_t* s2);
+                 uint16_t* s1, uint16_t* s2, bool bf16_act = false);
 void net_backward(hipStream_t st, const NetDev& N, int mt, const float* x, const float* a1, const float* a2,
                   const float* gout, float* g2, float* g1, float* grad, DBuf& part, uint16_t* s1);
 double net_loss(hipStream_t st, const NetDev& N, int mt, const float* out, const float* tgt, float* gout, DBuf& scratch);

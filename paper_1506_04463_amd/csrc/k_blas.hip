@@ -324,6 +324,16 @@ void shift_combine(hipStream_t st, long len, zd s, const zd* X, zd* Out) {
     FH_LAUNCH_CHECK();
 }
 
+__global__ void k_sub(long len, const zd* __restrict__ A, const zd* __restrict__ B, zd* __restrict__ Out) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < len) Out[e] = A[e] - B[e];
+}
+void sub(hipStream_t st, long len, const zd* A, const zd* B, zd* Out) {
+    if (len <= 0) return;
+    k_sub<<<ceil_div(len, 256), 256, 0, st>>>(len, A, B, Out);
+    FH_LAUNCH_CHECK();
+}
+
 __global__ void k_gather_cols(int n, int mout, const zd* __restrict__ src, long lds, const int* __restrict__ perm,
                               zd* __restrict__ dst, long ldd) {
     long e = (long)blockIdx.x * blockDim.x + threadIdx.x;

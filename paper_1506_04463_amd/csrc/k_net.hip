@@ -139,7 +139,8 @@ __device__ __forceinline__ void split_bf16(float v, short& hi, short& lo) {
 }
 
 // split arrays of x[p][ci][col] (cin <= 16 channels, zero padded to 16):
-// hi/lo[((p * 4 + cq) * mt + col) * 4 + j] for ci = 4 cq + j
+// hi/lo[((p * 4 + cq) * mt + col) * 4 + j] for ci = 4 cq + j (lo may be null:
+// BF16 activations, the hi term only)
 __global__ void k_split16(long npix, int mt, int cin, const float* __restrict__ x, bf16x4_t* __restrict__ hi,
                           bf16x4_t* __restrict__ lo) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;   // (p, cq, col)
@@ -159,7 +160,7 @@ __global__ void k_split16(long npix, int mt, int cin, const float* __restrict__ 
         l[j] = b;
     }
     hi[e] = h;
-    lo[e] = l;
+    if (lo) lo[e] = l;
 }
 
 // One kernel for both directions.  Forward: y[p][co][col] = act(b[co] +
@@ -171,7 +172,7 @@ __global__ void k_split16(long npix, int mt, int cin, const float* __restrict__ 
 // it loads the MFMA_PPW + 2 input blocks of the row window once and uses each
 // for up to three taps and three output pixels (a neighbour outside the grid
 // contributes a zero operand).
-template <int TAPS, bool BWD>
+template <int TAPS, bool BWD, int NTERM = 2>
 __global__ __launch_bounds__(256) void k_conv16_mfma(int nz, int ny, int nx, int mt, int cin,
                                                      const bf16x4_t* __restrict__ xhi, const bf16x4_t* __restrict__ xlo,
                                                      const uint16_t* __restrict__ w, const uint16_t* __restrict__ b,
@@ -218,9 +219,12 @@ __global__ __launch_bounds__(256) void k_conv16_mfma(int nz, int ny, int nx, int
             const int qx = px0 - 1 + u;
             const bool in = plane && qx >= 0 && qx < nx;
             const long e = ((in ? rowbase + qx : 0L) * 4 + kq) * mt + (colok ? col : 0);
-            const bf16x4_t hl = xhi[e], ll = xlo[e];
+            const bf16x4_t hl = xhi[e];
             hi[u] = in ? hl : zero4;
-            lo[u] = in ? ll : zero4;
+            if (NTERM == 2) {
+                const bf16x4_t ll = xlo[e];
+                lo[u] = in ? ll : zero4;
+            }
         }
 #pragma unroll
         for (int i = 0; i < PP; ++i)
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(256) void k_conv16_mfma(int nz, int ny, int nx, int
                 const int tap = (TAPS == 27 ? (dz + 1) * 9 : 0) + (dy + 1) * 3 + (dx + 1);
                 const int u = i + 1 + sg * dx;
                 acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[tap], hi[u], acc[i], 0, 0, 0);
-                acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[tap], lo[u], acc[i], 0, 0, 0);
+                if (NTERM == 2) acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[tap], lo[u], acc[i], 0, 0, 0);
             }
     }
     if (!colok) return;
@@ -250,7 +254,7 @@ __global__ __launch_bounds__(256) void k_conv16_mfma(int nz, int ny, int nx, int
             for (int v = 0; v < 4; ++v) {
                 float o = acc[i][v] + bias[v];
                 if (relu) o = fmaxf(o, 0.0f);
-                yp[(long)(4 * kq + v) * mt] = o;
+                if (y) yp[(long)(4 * kq + v) * mt] = o;
                 short a, c;
                 split_bf16(o, a, c);
                 h[v] = a;
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(256) void k_conv16_mfma(int nz, int ny, int nx, int
             if (yhi) {
                 const long e = (p * 4 + kq) * mt + col;
                 yhi[e] = h;
-                ylo[e] = l;
+                if (ylo) ylo[e] = l;
             }
         } else {
             const float* mp = mask ? mask + p * 16 * mt + col : nullptr;
@@ -542,7 +546,7 @@ template void net_inv_colnorm<float>(hipStream_t, const NetDev&, int, int, const
 
 template <int TAPS>
 static void forward_t(hipStream_t st, const NetDev& N, int mt, const float* x, float* a1, float* a2, float* out,
-                      uint16_t* s1, uint16_t* s2) {
+                      uint16_t* s1, uint16_t* s2, bool bf16_act) {
     const int npix = N.npix();
     dim3 blk(64, 4), g = conv_grid(npix, mt), gm = mfma_grid(N, mt);
     static_assert(NET_HID == 16 && NET_MAX_CIN <= 16, "the MFMA convolutions are 16-channel blocks");
@@ -551,6 +555,25 @@ static void forward_t(hipStream_t st, const NetDev& N, int mt, const float* x, f
     bf16x4_t* x_lo = (bf16x4_t*)(s1 + half);
     bf16x4_t* a_hi = (bf16x4_t*)s2;
     bf16x4_t* a_lo = (bf16x4_t*)(s2 + half);
+    if (bf16_act) {
+        // inference with BF16 activations: the inputs of the two MFMA layers
+        // are single BF16 terms (half the operand loads and MFMAs), the first
+        // layer's FP32 output (needed only by the backward pass) is not stored
+        k_split16<<<ceil_div((size_t)npix * 4 * mt, 256), 256, 0, st>>>(npix, mt, N.cin, x, x_hi, nullptr);
+        FH_LAUNCH_CHECK();
+        k_conv16_mfma<TAPS, false, 1><<<gm, 256, 0, st>>>(N.nz, N.ny, N.nx, mt, N.cin, x_hi, nullptr,
+                                                          N.wb + N.off_w1, N.wb + N.off_b1, 1, nullptr, nullptr,
+                                                          a_hi, nullptr);
+        FH_LAUNCH_CHECK();
+        k_conv16_mfma<TAPS, false, 1><<<gm, 256, 0, st>>>(N.nz, N.ny, N.nx, mt, NET_HID, a_hi, nullptr,
+                                                          N.wb + N.off_w2, N.wb + N.off_b2, 1, nullptr, a2, nullptr,
+                                                          nullptr);
+        FH_LAUNCH_CHECK();
+        k_conv_fwd<2, TAPS><<<g, blk, 0, st>>>(N.nz, N.ny, N.nx, mt, NET_HID, a2, N.wb + N.off_w3, N.wb + N.off_b3, 0,
+                                               out);
+        FH_LAUNCH_CHECK();
+        return;
+    }
     k_split16<<<ceil_div((size_t)npix * 4 * mt, 256), 256, 0, st>>>(npix, mt, N.cin, x, x_hi, x_lo);
     FH_LAUNCH_CHECK();
     k_conv16_mfma<TAPS, false><<<gm, 256, 0, st>>>(N.nz, N.ny, N.nx, mt, N.cin, x_hi, x_lo, N.wb + N.off_w1,
@@ -564,11 +587,11 @@ static void forward_t(hipStream_t st, const NetDev& N, int mt, const float* x, f
 }
 
 void net_forward(hipStream_t st, const NetDev& N, int mt, const float* x, float* a1, float* a2, float* out,
-                 uint16_t* s1, uint16_t* s2) {
+                 uint16_t* s1, uint16_t* s2, bool bf16_act) {
     const int npix = N.npix();
     hipEvent_t ev = prof_begin(st);
-    if (N.taps == 27) forward_t<27>(st, N, mt, x, a1, a2, out, s1, s2);
-    else forward_t<9>(st, N, mt, x, a1, a2, out, s1, s2);
+    if (N.taps == 27) forward_t<27>(st, N, mt, x, a1, a2, out, s1, s2, bf16_act);
+    else forward_t<9>(st, N, mt, x, a1, a2, out, s1, s2, bf16_act);
     const double macs = (double)N.taps * (N.cin * NET_HID + NET_HID * NET_HID + NET_HID * 2) * npix * mt;
     prof_end(st, ev, "net_forward", 4.0 * npix * mt * (N.cin + 2 * NET_HID + 2) * 2, 2 * macs);
 }

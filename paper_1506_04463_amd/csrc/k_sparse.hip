@@ -69,9 +69,16 @@ __global__ __launch_bounds__(256) void k_spmm_rows(int n, int m, int cb, int ncb
     __shared__ TA s_val[MAXR * SL];
     const int tx = threadIdx.x, ty = threadIdx.y, ry = blockDim.y;
     const int rows = ry * RPT;
-    const int r0 = blockIdx.x * rows;
-    const int s = blockIdx.y / ncb;
-    const int c = (blockIdx.y % ncb) * cb + tx;
+    // Workgroups are dealt round-robin to the 8 XCDs (one L2 each): give each
+    // XCD a contiguous range of row blocks, so that the gathered neighbour rows
+    // (up to a grid line away) are read from the L2 that fetched them last
+    long lin = blockIdx.x + (long)blockIdx.y * gridDim.x;
+    const long G = (long)gridDim.x * gridDim.y;
+    if (G % 8 == 0) lin = (lin % 8) * (G / 8) + lin / 8;
+    const int bx = (int)(lin % gridDim.x), by = (int)(lin / gridDim.x);
+    const int r0 = bx * rows;
+    const int s = by / ncb;
+    const int c = (by % ncb) * cb + tx;
     const bool act = c < m;
     const int tid = ty * cb + tx, nt = cb * ry;
     for (int idx = tid; idx < rows * SL; idx += nt) {
@@ -685,7 +692,7 @@ __device__ __forceinline__ void sweep_pipe(const SweepDev& sw, int n, int m, int
     auto load_x = [&](SP& s) {
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-            s.off[q] = s.row[q] * m + c0 + emod[q];
+            s.off[q] = (int)__umul24((unsigned)s.row[q], (unsigned)m) + c0 + emod[q];   // as in sweep_vec
             s.x[q] = In[s.off[q]];
         }
     };
@@ -839,6 +846,173 @@ __global__ __launch_bounds__(NT) void k_ilu_apply_pipe(IluApplyArgs<T> a, const 
                                  fd_l, wmax, a.junk);
 }
 
+// Complex-FP32 sweep with two columns per lane.  A lane owns P items of a
+// level, each two adjacent columns of one row (one 16-byte load and store);
+// the lanes of a row (cw / 2 of them) each load that row's factor data into
+// their own registers, four levels ahead, so no factor data passes through
+// LDS: per item and level the LDS traffic is the KM dependency reads from the
+// previous level's ring and one write.  Same pipeline as sweep_pipe (row
+// indices six levels ahead, inputs three, factor data issued after the
+// level's own use of its slot), one loop with fill and drain levels.
+__device__ __forceinline__ void c2_fms(float4& acc, float2 a, float4 b) {   // acc -= a * b (both columns)
+    acc.x -= a.x * b.x - a.y * b.y;
+    acc.y -= a.x * b.y + a.y * b.x;
+    acc.z -= a.x * b.z - a.y * b.w;
+    acc.w -= a.x * b.w + a.y * b.z;
+}
+__device__ __forceinline__ float4 c2_mul(float2 a, float4 b) {
+    return make_float4(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x, a.x * b.z - a.y * b.w, a.x * b.w + a.y * b.z);
+}
+
+template <int P, int KM>
+struct SwVec {
+    int row[P];           // row indices (six levels ahead)
+    float4 x[P];          // inputs (three levels ahead)
+    int off[P];           // float4 offsets of those inputs / outputs
+    int fslot[P][KM];     // factor data of the items' rows (four levels ahead)
+    float2 fv[P][KM];
+    float2 fd[P];
+};
+
+template <int P, int KM, int NT>
+__device__ __forceinline__ void sweep_vec(const SweepDev& sw, int n, int m2, int c02, int lpr,
+                                          const float2* __restrict__ val, const float2* __restrict__ dval,
+                                          const float4* In, float4* Os, float4* ring, int ring_stride, float4* junk) {
+    static_assert(NT * P <= ILU_JUNK / 2, "junk buffer too small for one level's items");
+    const int nlev = sw.nlev;
+    if (nlev <= 0) return;
+    using CI = const __attribute__((address_space(4))) int;
+    CI* lp = (CI*)sw.lev_ptr;
+    const int K = sw.K;
+    const bool hasd = dval != nullptr;
+    const float2* dsrc = hasd ? dval : val;
+    const int tid = threadIdx.x;
+    int ediv[P], emod[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int e0 = tid + NT * q;
+        ediv[q] = e0 / lpr;
+        emod[q] = e0 % lpr;
+    }
+    auto pos_of = [&](int l, int r) {
+        const int L = min(max(l, 0), nlev - 1);
+        const int t0 = lp[L], rows = lp[L + 1] - t0;
+        return min(t0 + min(r, rows - 1), n - 1);
+    };
+    using SV = SwVec<P, KM>;
+    auto load_row = [&](int l, SV& s) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) s.row[q] = sw.rows[pos_of(l, ediv[q])];
+    };
+    auto load_x = [&](SV& s) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            // 24-bit multiply: a 32-bit multiply-add becomes a 64-bit one whose
+            // unused high addend half the compiler may take from a register a
+            // load is still filling, and then it waits for that load
+            s.off[q] = (int)__umul24((unsigned)s.row[q], (unsigned)m2) + c02 + emod[q];
+            s.x[q] = In[s.off[q]];
+        }
+    };
+    auto load_fac = [&](int l, SV& s) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int t = pos_of(l, ediv[q]);
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                const int kk = k < K ? k : 0;
+                s.fslot[q][k] = sw.ell_slot[(long)kk * n + t];
+                s.fv[q][k] = val[(long)kk * n + t];
+            }
+            s.fd[q] = dsrc[t];
+        }
+    };
+    const int lw = ring_stride;   // float4 entries of one ring level
+    auto level = [&](int l, SV& a, SV& c, SV& d) {
+        load_x(d);
+        load_row(l + 6, c);
+        const int Lc = min(max(l, 0), nlev - 1);
+        const int rows = lp[Lc + 1] - lp[Lc];
+        const float4* prev = ring + (long)((l + 1) & 1) * lw;
+        float4* cur = ring + (long)(l & 1) * lw;
+        const bool real = l >= 0 && l < nlev;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int pos = min(ediv[q], rows - 1);
+            float4 v = a.x[q];
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                const int sl = a.fslot[q][k];
+                const bool dep = k < K && sl >= 0;
+                const float4 pv = prev[(dep ? sl : 0) * lpr + emod[q]];
+                c2_fms(v, a.fv[q][k], dep ? pv : make_float4(0.f, 0.f, 0.f, 0.f));
+            }
+            if (hasd) v = c2_mul(a.fd[q], v);
+            cur[pos * lpr + emod[q]] = v;
+            float4* dst = real ? Os + a.off[q] : junk + (tid + NT * q);
+            *dst = v;
+        }
+        load_fac(l + 4, a);
+        lds_barrier();
+    };
+    auto blank = [&](SV& sv) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            sv.row[q] = 0;
+            sv.off[q] = 0;
+            sv.x[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                sv.fslot[q][k] = -1;
+                sv.fv[q][k] = make_float2(0.f, 0.f);
+            }
+            sv.fd[q] = make_float2(0.f, 0.f);
+        }
+    };
+    SV s0, s1, s2, s3;
+    blank(s0);
+    blank(s1);
+    blank(s2);
+    blank(s3);
+    // an opaque start level: with a known one the compiler peels the fill
+    // levels into a prologue, which meets the loop header with its own history
+    // of loads in flight
+    int lstart = -8;
+    asm volatile("" : "+s"(lstart));
+    for (int l = lstart; l < nlev; l += 4) {
+        level(l, s0, s2, s3);
+        level(l + 1, s1, s3, s0);
+        level(l + 2, s2, s0, s1);
+        level(l + 3, s3, s1, s2);
+    }
+}
+
+template <int P, int KM, int NT>
+__global__ __launch_bounds__(NT) void k_ilu_apply_vec(IluApplyArgs<float> a, const Cx<float>* __restrict__ X,
+                                                      Cx<float>* Out, int ring_stride) {
+    extern __shared__ unsigned char dsm[];
+    float4* ring = reinterpret_cast<float4*>(dsm);   // [2][wmax][cw / 2]
+    const int2 sb = xcd_block();
+    const int s = sb.x;
+    const int c0 = sb.y * a.cw;
+    const int lpr = a.cw / 2;
+    const int node = a.node_of[s], side = a.side_of[s];
+    const long base = (long)s * a.n * a.m / 2;      // float4 units
+    const SweepDev& F = a.fwd[side];
+    const SweepDev& B = a.bwd[side];
+    const float2* fv = reinterpret_cast<const float2*>(a.fval[side] + (long)node * F.K * a.n);
+    const float2* fd = a.fdiag[side] ? reinterpret_cast<const float2*>(a.fdiag[side] + (long)node * a.n) : nullptr;
+    const float2* bv = reinterpret_cast<const float2*>(a.bval[side] + (long)node * B.K * a.n);
+    const float2* bd = a.bdiag[side] ? reinterpret_cast<const float2*>(a.bdiag[side] + (long)node * a.n) : nullptr;
+    const float4* Xv = reinterpret_cast<const float4*>(X) + base;
+    float4* Ov = reinterpret_cast<float4*>(Out) + base;
+    float4* junk = reinterpret_cast<float4*>(a.junk);
+    sweep_vec<P, KM, NT>(F, a.n, a.m / 2, c0 / 2, lpr, fv, fd, Xv, Ov, ring, ring_stride, junk);
+    __threadfence();
+    __syncthreads();
+    sweep_vec<P, KM, NT>(B, a.n, a.m / 2, c0 / 2, lpr, bv, bd, Ov, Ov, ring, ring_stride, junk);
+}
+
 template <typename T, int P, int KM, int NT>
 __global__ __launch_bounds__(NT) void k_ilu_apply_lds(IluApplyArgs<T> a, const Cx<T>* __restrict__ X, Cx<T>* Out,
                                                       int ring_stride) {
@@ -917,8 +1091,24 @@ void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<
     }
     const size_t sh = ring_bytes + fac_bytes;
     const bool pipe = lds && sizeof(T) == 4 && K <= 2 && kmin >= 1 && wmax <= 1024 && (long)wmax * a.cw <= 2048 &&
-                      (long)a.n * a.m < (1L << 31) && sh <= (size_t)lds_max && a.junk != nullptr;
-    if (pipe) {
+                      (long)a.n * a.m < (1L << 31) && a.n < (1 << 24) && a.m < (1 << 24) &&
+                      sh <= (size_t)lds_max && a.junk != nullptr;
+    // two columns per lane (16-byte accesses, factor data in registers) when
+    // the column block is even, divides the row length (no partial block) and
+    // a level's items fit one 512-thread batch of two items per thread
+    static int vec_on = -1;
+    if (vec_on < 0) {
+        const char* e = std::getenv("FH_ILU_VEC");
+        vec_on = e ? (std::atoi(e) != 0) : 1;
+    }
+    const bool vec = pipe && vec_on && a.cw % 2 == 0 && a.m % a.cw == 0 && (long)wmax * (a.cw / 2) <= 1024;
+    if (vec) {
+        if constexpr (sizeof(T) == 4) {
+            const int stride = wmax * (a.cw / 2);
+            const size_t shv = 2 * sizeof(float4) * (size_t)stride;
+            k_ilu_apply_vec<2, 2, 512><<<grid, 512, shv, st>>>(a, X, Out, stride);
+        }
+    } else if (pipe) {
         if constexpr (sizeof(T) == 4) {
             const int stride = wmax * a.cw;
             auto go = [&](auto kern, int nt) {

@@ -74,6 +74,8 @@ void net_set_fields(Ctx& c, NetState& S, const double* fields) {
     FH_HIP(hipStreamSynchronize(c.stream));
 }
 
+void net_set_activations(NetState& S, int bf16) { S.d.bf16_act = bf16; }
+
 void net_set_params(Ctx& c, NetState& S, const float* host) {
     FH_HIP(hipMemcpyAsync(S.d.w, host, sizeof(float) * S.d.np, hipMemcpyHostToDevice, c.stream));
     FH_HIP(hipMemsetAsync(S.d.mom, 0, sizeof(float) * S.d.np, c.stream));
@@ -134,7 +136,7 @@ void net_apply(Ctx& c, NetState& S, int nsys, int m, const Cx<T>* V, const zd* s
             net_encode<T>(c.stream, S.d, w, g, V + s0 * blk, sc, shifts_dev + s0, sides_dev + s0, (float*)S.x.p, m,
                           c0);
             net_forward(c.stream, S.d, mt, (const float*)S.x.p, (float*)S.a1.p, (float*)S.a2.p, (float*)S.out.p,
-                        (uint16_t*)S.s1.p, (uint16_t*)S.s2.p);
+                        (uint16_t*)S.s1.p, (uint16_t*)S.s2.p, S.d.bf16_act != 0);
             net_decode<T>(c.stream, S.d, w, g, (const float*)S.out.p, sc, Out + s0 * blk, m, c0);
         }
     }

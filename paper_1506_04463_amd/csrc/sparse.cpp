@@ -873,6 +873,19 @@ void sparse_shifted_apply(Ctx& c, Prob& p, int side, int nsys, const cplx* shift
     spmm<double>(c.stream, side ? S.AT : S.A, side == 1, S.n, m, nsys, d, 1.0, X, nullptr, Out);
 }
 
+void sparse_residual_pair(Ctx& c, Prob& p, int side, int nsys, const cplx* shifts, int m, const zd* B, const zd* X,
+                          const zd* Xt, zd* R, zd* E) {
+    SparseState& S = *p.sp;
+    std::vector<zd> h(nsys);
+    for (int s = 0; s < nsys; ++s) h[s] = zd{shifts[s].real(), shifts[s].imag()};
+    zd* d = (zd*)S.shifts64.ensure(sizeof(zd) * nsys);
+    FH_HIP(hipMemcpyAsync(d, h.data(), sizeof(zd) * nsys, hipMemcpyHostToDevice, c.stream));
+    // R = -(shift X - op(A) X) + B
+    spmm<double>(c.stream, side ? S.AT : S.A, side == 1, S.n, m, nsys, d, -1.0, X, B, R);
+    sub(c.stream, (long)nsys * S.n * m, Xt, X, E);
+    FH_HIP(hipStreamSynchronize(c.stream));
+}
+
 void sparse_ilu0(Ctx& c, Prob& p, cplx z, zd* lu_out) {
     SparseState& S = *p.sp;
     fh_opts o;

@@ -13,8 +13,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (FH_PC_ILU0, FH_PC_LEARNED, FH_PC_NONE, FH_PREC_FP64, Net, Problem, default_opts, shifted_apply,
-               shifted_solve)
+from . import (FH_PC_ILU0, FH_PC_LEARNED, FH_PC_NONE, FH_PREC_FP64, Net, Problem, default_opts, residual_pair,
+               shifted_apply, shifted_solve)
 
 
 def _torch():
@@ -50,6 +50,20 @@ def apply_op(prob: Problem, zs, sides, X):
     return out
 
 
+def pairs(prob: Problem, zs, sides, B, X, Xt):
+    """(B_s - M_s X_s, Xt_s - X_s) for every system (right systems first), by the library."""
+    torch = _torch()
+    sides = np.asarray(sides)
+    nr = int(np.count_nonzero(sides == 0))
+    R = torch.empty_like(X)
+    E = torch.empty_like(X)
+    for lo, hi, side, sh in ((0, nr, 0, zs[:nr]), (nr, len(sides), 1, np.conj(zs[nr:]))):
+        if hi > lo:
+            R[lo:hi], E[lo:hi] = residual_pair(prob, side, sh, B[lo:hi].contiguous(), X[lo:hi].contiguous(),
+                                               Xt[lo:hi].contiguous())
+    return R, E
+
+
 def harvest(prob: Problem, z, m=8, seed=0, steps=(0, 2, 5, 10)):
     """Pairs from plain GMRES: for each k in steps, (r_k, e_k) for all 2 ne systems.
 
@@ -68,8 +82,9 @@ def harvest(prob: Problem, z, m=8, seed=0, steps=(0, 2, 5, 10)):
             o = default_opts(m, precision=FH_PREC_FP64, precond=FH_PC_NONE, restart=int(k), max_restarts=1,
                              inner_tol=1e-300)
             xk, _ = shifted_solve(prob, zs, sides, B, o)
-            Rs.append(B - apply_op(prob, zs, sides, xk))
-            Es.append(xs - xk)
+            r, e = pairs(prob, zs, sides, B, xk, xs)
+            Rs.append(r)
+            Es.append(e)
         Z.append(zs)
         S.append(sides)
     return dict(z=np.concatenate(Z), sides=np.concatenate(S), R=torch.cat(Rs).contiguous(),

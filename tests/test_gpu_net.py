@@ -85,6 +85,45 @@ def test_forward_matches_oracle(handle, ny, nx, nf, m, sides):
     np.testing.assert_allclose(got / scale, ref / scale, rtol=0, atol=2e-5)
 
 
+@pytest.mark.parametrize("nz,ny,nx,nf,m,sides", [(1, 12, 10, 1, 5, [0, 0, 1]), (1, 16, 16, 2, 33, [0, 1]),
+                                                   (3, 4, 5, 3, 4, [0, 1])])
+def test_forward_bf16_activations_match_oracle(handle, nz, ny, nx, nf, m, sides):
+    """Inference with BF16 activations against the oracle with the same
+    rounding of the first two layers' inputs (CN.forward with act_round =
+    CN.bf16_round).  The kernel rounds FP32 sums and the oracle FP64 ones: where
+    a value lies within FP32 rounding of a BF16 halfway point the two round
+    apart, which moves that activation by one BF16 ulp (2^-8 relative) and an
+    output by a small share of that (the first layer's 144-432 terms, the
+    second's 144-432); so almost every output agrees to FP32 accuracy and
+    none differs by more than 1e-3 of the column's scale.  Training passes keep FP32
+    activations, and switching back restores the FP32 forward."""
+    rng = np.random.default_rng(nz * 1000 + ny * 100 + m)
+    n, nsys = nz * ny * nx, len(sides)
+    fields = rng.standard_normal((nf, n)) if nf else None
+    alpha, osc = 37.5, 0.25
+    net = fh.Net(handle, ny, nx, fields=fields, alpha=alpha, out_scale=osc, seed=5 + nf, nz=nz)
+    V = rng.standard_normal((nsys, n, m)) + 1j * rng.standard_normal((nsys, n, m))
+    z = rng.standard_normal(nsys) * 40 + 1j * rng.standard_normal(nsys) * 10
+    x, nr = _oracle_input(V, z, sides, alpha, ny, nx, fields, nz=None if nz == 1 else nz)
+
+    def ref_of(o):
+        return osc * (o[..., 0, :] + 1j * o[..., 1, :]).reshape(n, nsys * m) * nr[None, :]
+
+    ref16 = ref_of(CN.forward(_params(net), x, act_round=CN.bf16_round)[0])
+    ref32 = ref_of(CN.forward(_params(net), x)[0])
+    net.set_activations(True)
+    got16 = np.concatenate(list(net.forward(z, sides, _cuda(V)).cpu().numpy()), axis=1)
+    net.set_activations(False)
+    got32 = np.concatenate(list(net.forward(z, sides, _cuda(V)).cpu().numpy()), axis=1)
+    scale = np.abs(ref32).max(axis=0, keepdims=True)
+    d16 = np.abs(got16 - ref16) / scale
+    assert d16.max() < 1e-3, d16.max()
+    assert np.quantile(d16, 0.99) < 2e-5, np.quantile(d16, 0.99)
+    np.testing.assert_allclose(got32 / scale, ref32 / scale, rtol=0, atol=2e-5)
+    # the modes differ by the BF16 rounding itself
+    assert np.abs(got16 - got32).max() / scale.max() > 1e-4
+
+
 @pytest.mark.parametrize("ny,nx,nf,m,sides", CASES)
 def test_gradients_match_oracle(handle, ny, nx, nf, m, sides):
     rng = np.random.default_rng(ny * 7 + m)

@@ -62,6 +62,29 @@ def test_shifted_apply(handle, name, m):
         np.testing.assert_allclose(out, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("m", [3, 16])
+def test_residual_pair(handle, m):
+    """The learned preconditioner's training pairs, by the library: R = B - M X
+    and E = Xt - X against their definitions with the dense operator, and
+    M E = R when B = M Xt."""
+    A = PROBS["convdiff"]()
+    n = A["n"]
+    Ad = W.csr_to_dense(A).astype(np.complex128)
+    prob = fh.Problem(handle, _csr(A))
+    shifts = np.array([300.0 + 40j, -20.0 + 5j])
+    Xt = np.stack([W.subspace(n, m, 30 + s) for s in range(2)])
+    X = np.stack([W.subspace(n, m, 40 + s) for s in range(2)])
+    for side, op in ((0, Ad), (1, Ad.conj().T)):
+        B = np.stack([shifts[s] * Xt[s] - op @ Xt[s] for s in range(2)])
+        R, E = fh.residual_pair(prob, side, shifts, _cuda(B), _cuda(X), _cuda(Xt))
+        R, E = R.cpu().numpy(), E.cpu().numpy()
+        ref = np.stack([B[s] - (shifts[s] * X[s] - op @ X[s]) for s in range(2)])
+        np.testing.assert_allclose(R, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+        np.testing.assert_array_equal(E, Xt - X)
+        ME = np.stack([shifts[s] * E[s] - op @ E[s] for s in range(2)])
+        np.testing.assert_allclose(ME, R, rtol=0, atol=1e-11 * np.abs(R).max())
+
+
 @pytest.mark.parametrize("name", list(PROBS))
 def test_ilu0_factor_matches_oracle(handle, name):
     A = PROBS[name]()

@@ -136,3 +136,48 @@ def test_conv3d_direct_sum_and_gradients():
         wm[layer][0][idx] -= h
         fd = (N.loss_and_grad(wp, x, t)[0] - N.loss_and_grad(wm, x, t)[0]) / (2 * h)
         assert abs(fd - grads[layer][0][idx]) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_bf16_round_definition():
+    """bfloat16 rounding against values fixed by the format: representable
+    values are unchanged, halfway cases go to the even neighbour, the nearest
+    neighbour otherwise, and the float32 exponent range is kept."""
+    ulp = 2.0 ** -7                                  # spacing of bfloat16 in [1, 2)
+    exact = np.array([0.0, 1.0, -1.5, 1.0 + ulp, 3.0 * 2.0 ** 100, 2.0 ** -126, 255.0])
+    np.testing.assert_array_equal(N.bf16_round(exact), exact)
+    # halfway: 1 + ulp/2 lies between 1 (even) and 1 + ulp (odd) -> 1
+    assert N.bf16_round(1.0 + ulp / 2) == 1.0
+    # halfway between 1 + ulp (odd) and 1 + 2 ulp (even) -> 1 + 2 ulp
+    assert N.bf16_round(1.0 + 1.5 * ulp) == 1.0 + 2 * ulp
+    # nearest otherwise, both signs
+    assert N.bf16_round(1.0 + 0.6 * ulp) == 1.0 + ulp
+    assert N.bf16_round(-(1.0 + 0.4 * ulp)) == -1.0
+    # at most half a bfloat16 ulp from the float32 value: 2^-8 relative (the
+    # ulp of [2^e, 2^(e+1)) is 2^(e-7)), and a bfloat16 value (low 16 bits zero)
+    v = np.random.default_rng(3).standard_normal(10000) * 10.0 ** np.random.default_rng(4).uniform(-20, 20, 10000)
+    r = N.bf16_round(v)
+    f = np.float32(v).astype(np.float64)
+    assert np.all(np.abs(r - f) <= 2.0 ** -8 * np.abs(f))
+    assert np.all(np.float32(r).view(np.uint32) & 0xFFFF == 0)
+    # and the nearest one: the neighbour on the other side is farther
+    step = 2.0 ** (np.floor(np.log2(np.abs(r))) - 7)
+    other = r + np.sign(f - r) * step
+    assert np.all(np.abs(other - f) >= np.abs(r - f))
+
+
+def test_forward_with_activation_rounding():
+    """forward(..., act_round) equals the layer-by-layer composition with the
+    rounding applied to the first two layers' inputs (and not the third's)."""
+    rng = np.random.default_rng(8)
+    params = [(rng.standard_normal((4, 3, 3, 3)), rng.standard_normal(4)),
+              (rng.standard_normal((4, 4, 3, 3)), rng.standard_normal(4)),
+              (rng.standard_normal((2, 4, 3, 3)), rng.standard_normal(2))]
+    x = rng.standard_normal((5, 6, 3, 2))
+    got, _ = N.forward(params, x, act_round=N.bf16_round)
+    (w1, b1), (w2, b2), (w3, b3) = params
+    a1 = np.maximum(N.conv3x3(N.bf16_round(x), w1, b1), 0.0)
+    a2 = np.maximum(N.conv3x3(N.bf16_round(a1), w2, b2), 0.0)
+    np.testing.assert_array_equal(got, N.conv3x3(a2, w3, b3))
+    plain, _ = N.forward(params, x)
+    assert np.abs(got - plain).max() > 0                      # the rounding is not a no-op
+    assert np.abs(got - plain).max() < 0.05 * np.abs(plain).max()
