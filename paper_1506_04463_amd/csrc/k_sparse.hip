@@ -855,10 +855,10 @@ __global__ __launch_bounds__(NT) void k_ilu_apply_pipe(IluApplyArgs<T> a, const 
 // indices six levels ahead, inputs three, factor data issued after the
 // level's own use of its slot), one loop with fill and drain levels.
 __device__ __forceinline__ void c2_fms(float4& acc, float2 a, float4 b) {   // acc -= a * b (both columns)
-    acc.x -= a.x * b.x - a.y * b.y;
-    acc.y -= a.x * b.y + a.y * b.x;
-    acc.z -= a.x * b.z - a.y * b.w;
-    acc.w -= a.x * b.w + a.y * b.z;
+    acc.x = fmaf(-a.x, b.x, fmaf(a.y, b.y, acc.x));
+    acc.y = fmaf(-a.x, b.y, fmaf(-a.y, b.x, acc.y));
+    acc.z = fmaf(-a.x, b.z, fmaf(a.y, b.w, acc.z));
+    acc.w = fmaf(-a.x, b.w, fmaf(-a.y, b.z, acc.w));
 }
 __device__ __forceinline__ float4 c2_mul(float2 a, float4 b) {
     return make_float4(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x, a.x * b.z - a.y * b.w, a.x * b.w + a.y * b.z);
@@ -867,15 +867,27 @@ __device__ __forceinline__ float4 c2_mul(float2 a, float4 b) {
 template <int P, int KM>
 struct SwVec {
     int row[P];           // row indices (six levels ahead)
+    int pos[P];           // their positions in the packed level order (for the factor data)
     float4 x[P];          // inputs (three levels ahead)
-    int off[P];           // float4 offsets of those inputs / outputs
+    unsigned off[P];      // byte offsets of those inputs / outputs
     int fslot[P][KM];     // factor data of the items' rows (four levels ahead)
     float2 fv[P][KM];
     float2 fd[P];
 };
 
-template <int P, int KM, int NT>
-__device__ __forceinline__ void sweep_vec(const SweepDev& sw, int n, int m2, int c02, int lpr,
+// loads and stores by a uniform base and a 32-bit byte offset (the address
+// form with the base in scalar registers: no 64-bit address arithmetic per lane)
+template <typename V>
+__device__ __forceinline__ V ld_at(const void* base, unsigned off) {
+    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename V>
+__device__ __forceinline__ void st_at(void* base, unsigned off, V v) {
+    *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + off) = v;
+}
+
+template <int P, int KM, int NT, int LPR>
+__device__ __forceinline__ void sweep_vec(const SweepDev& sw, int n, int m2, int c02,
                                           const float2* __restrict__ val, const float2* __restrict__ dval,
                                           const float4* In, float4* Os, float4* ring, int ring_stride, float4* junk) {
     static_assert(NT * P <= ILU_JUNK / 2, "junk buffer too small for one level's items");
@@ -891,18 +903,21 @@ __device__ __forceinline__ void sweep_vec(const SweepDev& sw, int n, int m2, int
 #pragma unroll
     for (int q = 0; q < P; ++q) {
         const int e0 = tid + NT * q;
-        ediv[q] = e0 / lpr;
-        emod[q] = e0 % lpr;
+        ediv[q] = e0 / LPR;
+        emod[q] = e0 % LPR;
     }
-    auto pos_of = [&](int l, int r) {
+    using SV = SwVec<P, KM>;
+    // rows (and packed positions) of level l's items; an item past the end of a
+    // narrower level repeats the level's last row; fill and drain levels repeat
+    // the first or last level
+    auto load_row = [&](int l, SV& s) {
         const int L = min(max(l, 0), nlev - 1);
         const int t0 = lp[L], rows = lp[L + 1] - t0;
-        return min(t0 + min(r, rows - 1), n - 1);
-    };
-    using SV = SwVec<P, KM>;
-    auto load_row = [&](int l, SV& s) {
 #pragma unroll
-        for (int q = 0; q < P; ++q) s.row[q] = sw.rows[pos_of(l, ediv[q])];
+        for (int q = 0; q < P; ++q) {
+            s.pos[q] = min(t0 + min(ediv[q], rows - 1), n - 1);
+            s.row[q] = ld_at<int>(sw.rows, (unsigned)s.pos[q] * 4u);
+        }
     };
     auto load_x = [&](SV& s) {
 #pragma unroll
@@ -910,21 +925,22 @@ __device__ __forceinline__ void sweep_vec(const SweepDev& sw, int n, int m2, int
             // 24-bit multiply: a 32-bit multiply-add becomes a 64-bit one whose
             // unused high addend half the compiler may take from a register a
             // load is still filling, and then it waits for that load
-            s.off[q] = (int)__umul24((unsigned)s.row[q], (unsigned)m2) + c02 + emod[q];
-            s.x[q] = In[s.off[q]];
+            s.off[q] = (__umul24((unsigned)s.row[q], (unsigned)m2) + (unsigned)(c02 + emod[q])) * 16u;
+            s.x[q] = ld_at<float4>(In, s.off[q]);
         }
     };
-    auto load_fac = [&](int l, SV& s) {
+    auto load_fac = [&](SV& s) {          // factor data at the positions s.pos
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-            const int t = pos_of(l, ediv[q]);
+            const unsigned t = (unsigned)s.pos[q];
 #pragma unroll
             for (int k = 0; k < KM; ++k) {
-                const int kk = k < K ? k : 0;
-                s.fslot[q][k] = sw.ell_slot[(long)kk * n + t];
-                s.fv[q][k] = val[(long)kk * n + t];
+                const unsigned kk = k < K ? (unsigned)k : 0u;
+                const unsigned e = kk * (unsigned)n + t;
+                s.fslot[q][k] = ld_at<int>(sw.ell_slot, e * 4u);
+                s.fv[q][k] = ld_at<float2>(val, e * 8u);
             }
-            s.fd[q] = dsrc[t];
+            s.fd[q] = ld_at<float2>(dsrc, t * 8u);
         }
     };
     const int lw = ring_stride;   // float4 entries of one ring level
@@ -936,29 +952,31 @@ __device__ __forceinline__ void sweep_vec(const SweepDev& sw, int n, int m2, int
         const float4* prev = ring + (long)((l + 1) & 1) * lw;
         float4* cur = ring + (long)(l & 1) * lw;
         const bool real = l >= 0 && l < nlev;
+        float4* obase = real ? Os : junk;
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             const int pos = min(ediv[q], rows - 1);
             float4 v = a.x[q];
 #pragma unroll
             for (int k = 0; k < KM; ++k) {
-                const int sl = a.fslot[q][k];
-                const bool dep = k < K && sl >= 0;
-                const float4 pv = prev[(dep ? sl : 0) * lpr + emod[q]];
-                c2_fms(v, a.fv[q][k], dep ? pv : make_float4(0.f, 0.f, 0.f, 0.f));
+                // an absent dependency reads position 0 with a zero factor (not
+                // at load time: the select would wait for the load just issued)
+                const bool dep = k < K && a.fslot[q][k] >= 0;
+                const float2 f = dep ? a.fv[q][k] : make_float2(0.f, 0.f);
+                c2_fms(v, f, prev[(dep ? a.fslot[q][k] : 0) * LPR + emod[q]]);
             }
             if (hasd) v = c2_mul(a.fd[q], v);
-            cur[pos * lpr + emod[q]] = v;
-            float4* dst = real ? Os + a.off[q] : junk + (tid + NT * q);
-            *dst = v;
+            cur[pos * LPR + emod[q]] = v;
+            st_at<float4>(obase, real ? a.off[q] : (unsigned)(tid + NT * q) * 16u, v);
         }
-        load_fac(l + 4, a);
+        load_fac(a);          // level l + 4: a.pos was set by load_row two levels ago
         lds_barrier();
     };
     auto blank = [&](SV& sv) {
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             sv.row[q] = 0;
+            sv.pos[q] = 0;
             sv.off[q] = 0;
             sv.x[q] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
@@ -974,6 +992,11 @@ __device__ __forceinline__ void sweep_vec(const SweepDev& sw, int n, int m2, int
     blank(s1);
     blank(s2);
     blank(s3);
+    // an absent dependency reads position 0 of the previous level with a zero
+    // factor, exact for finite values; the ring starts at zero so that the fill
+    // levels (and the first level, which has no dependencies) read finite values
+    for (int i = tid; i < 2 * lw; i += NT) ring[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
     // an opaque start level: with a known one the compiler peels the fill
     // levels into a prologue, which meets the loop header with its own history
     // of loads in flight
@@ -987,7 +1010,8 @@ __device__ __forceinline__ void sweep_vec(const SweepDev& sw, int n, int m2, int
     }
 }
 
-template <int P, int KM, int NT>
+// LPR: lanes per row (the workgroup's column block / 2)
+template <int P, int KM, int NT, int LPR>
 __global__ __launch_bounds__(NT) void k_ilu_apply_vec(IluApplyArgs<float> a, const Cx<float>* __restrict__ X,
                                                       Cx<float>* Out, int ring_stride) {
     extern __shared__ unsigned char dsm[];
@@ -995,7 +1019,6 @@ __global__ __launch_bounds__(NT) void k_ilu_apply_vec(IluApplyArgs<float> a, con
     const int2 sb = xcd_block();
     const int s = sb.x;
     const int c0 = sb.y * a.cw;
-    const int lpr = a.cw / 2;
     const int node = a.node_of[s], side = a.side_of[s];
     const long base = (long)s * a.n * a.m / 2;      // float4 units
     const SweepDev& F = a.fwd[side];
@@ -1007,10 +1030,10 @@ __global__ __launch_bounds__(NT) void k_ilu_apply_vec(IluApplyArgs<float> a, con
     const float4* Xv = reinterpret_cast<const float4*>(X) + base;
     float4* Ov = reinterpret_cast<float4*>(Out) + base;
     float4* junk = reinterpret_cast<float4*>(a.junk);
-    sweep_vec<P, KM, NT>(F, a.n, a.m / 2, c0 / 2, lpr, fv, fd, Xv, Ov, ring, ring_stride, junk);
+    sweep_vec<P, KM, NT, LPR>(F, a.n, a.m / 2, c0 / 2, fv, fd, Xv, Ov, ring, ring_stride, junk);
     __threadfence();
     __syncthreads();
-    sweep_vec<P, KM, NT>(B, a.n, a.m / 2, c0 / 2, lpr, bv, bd, Ov, Ov, ring, ring_stride, junk);
+    sweep_vec<P, KM, NT, LPR>(B, a.n, a.m / 2, c0 / 2, bv, bd, Ov, Ov, ring, ring_stride, junk);
 }
 
 template <typename T, int P, int KM, int NT>
@@ -1101,12 +1124,16 @@ void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<
         const char* e = std::getenv("FH_ILU_VEC");
         vec_on = e ? (std::atoi(e) != 0) : 1;
     }
-    const bool vec = pipe && vec_on && a.cw % 2 == 0 && a.m % a.cw == 0 && (long)wmax * (a.cw / 2) <= 1024;
+    // (32-bit byte offsets: one system's block below 4 GB)
+    const bool vec = pipe && vec_on && (a.cw == 2 || a.cw == 4 || a.cw == 8) && a.m % a.cw == 0 &&
+                     (long)wmax * (a.cw / 2) <= 1024 && (long)a.n * a.m * 8 < (1L << 32);
     if (vec) {
         if constexpr (sizeof(T) == 4) {
             const int stride = wmax * (a.cw / 2);
             const size_t shv = 2 * sizeof(float4) * (size_t)stride;
-            k_ilu_apply_vec<2, 2, 512><<<grid, 512, shv, st>>>(a, X, Out, stride);
+            if (a.cw == 2) k_ilu_apply_vec<2, 2, 512, 1><<<grid, 512, shv, st>>>(a, X, Out, stride);
+            else if (a.cw == 4) k_ilu_apply_vec<2, 2, 512, 2><<<grid, 512, shv, st>>>(a, X, Out, stride);
+            else k_ilu_apply_vec<2, 2, 512, 4><<<grid, 512, shv, st>>>(a, X, Out, stride);
         }
     } else if (pipe) {
         if constexpr (sizeof(T) == 4) {
