@@ -35,6 +35,8 @@ struct SweepDev {
     const int* ell_pos = nullptr;   // K * n: position of the value in the LU factor (-1 = empty)
     const int* dpos = nullptr;      // n: position of the pivot (non-unit sweeps) or null
     const int* ell_slot = nullptr;  // K * n: position of the dependency within the previous level (-1: none)
+    const int* ppos = nullptr;      // n: position of the row in the forward L sweep's packed order (the order
+                                    // of the blocked vector layout of the two-column sweep)
     int nlev = 0, K = 0;
     int wmax = 0;                   // widest level (rows)
     bool adjacent = false;          // every dependency lies in the level just before
@@ -55,6 +57,8 @@ struct IluApplyArgs {
     const Cx<T>* dinv = nullptr;                 // Jacobi: [node][n] (null: identity)
     Cx<T>* junk = nullptr;   // write target of the pipelined sweep's fill and drain levels
                              // (ILU_JUNK entries, written by every workgroup, never read)
+    DBuf* blk = nullptr;     // workspace of the blocked layout (nsys x n x m entries, grown on use;
+                             // null: natural layout only)
 };
 constexpr int ILU_JUNK = 4096;
 
@@ -82,6 +86,7 @@ struct SparseState {
     int ilu_cw64 = 4, ilu_cw32 = 8;  // columns per workgroup of the ILU sweeps (measured best at m = 64)
     // batch descriptors and GMRES workspace
     DBuf junk;   // see IluApplyArgs::junk
+    DBuf blk;    // see IluApplyArgs::blk
     DBuf node_of, side_of, shifts64, shifts32, coef, rho, bufB, bufX, bufR, bufT, b32, x32;
     DBuf V, Z, Hs, cs, sn, g, resid, vscale, kuse, y, h1, h2, hnorm, beta, bnorm, part, bn64, rn64, sc64;
     DBuf Hraw, htent, tau, dcoef, scv, scw, dots;   // DCGS2

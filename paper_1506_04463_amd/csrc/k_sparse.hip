@@ -886,7 +886,10 @@ __device__ __forceinline__ void st_at(void* base, unsigned off, V v) {
     *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + off) = v;
 }
 
-template <int P, int KM, int NT, int LPR>
+// BLK: In / Os in the blocked layout (the workgroup's column block of every
+// row contiguous, rows in the forward L sweep's packed order: a level's rows
+// are one contiguous run); else the natural layout [row][m]
+template <int P, int KM, int NT, int LPR, bool BLK>
 __device__ __forceinline__ void sweep_vec(const SweepDev& sw, int n, int m2, int c02,
                                           const float2* __restrict__ val, const float2* __restrict__ dval,
                                           const float4* In, float4* Os, float4* ring, int ring_stride, float4* junk) {
@@ -916,7 +919,7 @@ __device__ __forceinline__ void sweep_vec(const SweepDev& sw, int n, int m2, int
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             s.pos[q] = min(t0 + min(ediv[q], rows - 1), n - 1);
-            s.row[q] = ld_at<int>(sw.rows, (unsigned)s.pos[q] * 4u);
+            s.row[q] = ld_at<int>(BLK ? sw.ppos : sw.rows, (unsigned)s.pos[q] * 4u);
         }
     };
     auto load_x = [&](SV& s) {
@@ -925,7 +928,8 @@ __device__ __forceinline__ void sweep_vec(const SweepDev& sw, int n, int m2, int
             // 24-bit multiply: a 32-bit multiply-add becomes a 64-bit one whose
             // unused high addend half the compiler may take from a register a
             // load is still filling, and then it waits for that load
-            s.off[q] = (__umul24((unsigned)s.row[q], (unsigned)m2) + (unsigned)(c02 + emod[q])) * 16u;
+            s.off[q] = BLK ? ((unsigned)s.row[q] * LPR + (unsigned)emod[q]) * 16u
+                           : (__umul24((unsigned)s.row[q], (unsigned)m2) + (unsigned)(c02 + emod[q])) * 16u;
             s.x[q] = ld_at<float4>(In, s.off[q]);
         }
     };
@@ -1011,16 +1015,18 @@ __device__ __forceinline__ void sweep_vec(const SweepDev& sw, int n, int m2, int
 }
 
 // LPR: lanes per row (the workgroup's column block / 2)
-template <int P, int KM, int NT, int LPR>
-__global__ __launch_bounds__(NT) void k_ilu_apply_vec(IluApplyArgs<float> a, const Cx<float>* __restrict__ X,
-                                                      Cx<float>* Out, int ring_stride) {
+// (X and Out may be the same block: the blocked sweep runs in place)
+template <int P, int KM, int NT, int LPR, bool BLK>
+__global__ __launch_bounds__(NT) void k_ilu_apply_vec(IluApplyArgs<float> a, const Cx<float>* X, Cx<float>* Out,
+                                                      int ring_stride) {
     extern __shared__ unsigned char dsm[];
     float4* ring = reinterpret_cast<float4*>(dsm);   // [2][wmax][cw / 2]
     const int2 sb = xcd_block();
     const int s = sb.x;
     const int c0 = sb.y * a.cw;
     const int node = a.node_of[s], side = a.side_of[s];
-    const long base = (long)s * a.n * a.m / 2;      // float4 units
+    // float4 units: the system's block, or (blocked) the system's column block
+    const long base = BLK ? ((long)s * (a.m / a.cw) + sb.y) * a.n * LPR : (long)s * a.n * a.m / 2;
     const SweepDev& F = a.fwd[side];
     const SweepDev& B = a.bwd[side];
     const float2* fv = reinterpret_cast<const float2*>(a.fval[side] + (long)node * F.K * a.n);
@@ -1030,10 +1036,10 @@ __global__ __launch_bounds__(NT) void k_ilu_apply_vec(IluApplyArgs<float> a, con
     const float4* Xv = reinterpret_cast<const float4*>(X) + base;
     float4* Ov = reinterpret_cast<float4*>(Out) + base;
     float4* junk = reinterpret_cast<float4*>(a.junk);
-    sweep_vec<P, KM, NT, LPR>(F, a.n, a.m / 2, c0 / 2, fv, fd, Xv, Ov, ring, ring_stride, junk);
+    sweep_vec<P, KM, NT, LPR, BLK>(F, a.n, a.m / 2, c0 / 2, fv, fd, Xv, Ov, ring, ring_stride, junk);
     __threadfence();
     __syncthreads();
-    sweep_vec<P, KM, NT, LPR>(B, a.n, a.m / 2, c0 / 2, bv, bd, Ov, Ov, ring, ring_stride, junk);
+    sweep_vec<P, KM, NT, LPR, BLK>(B, a.n, a.m / 2, c0 / 2, bv, bd, Ov, Ov, ring, ring_stride, junk);
 }
 
 template <typename T, int P, int KM, int NT>
@@ -1085,6 +1091,71 @@ __global__ __launch_bounds__(256) void k_ilu_apply(IluApplyArgs<T> a, const Cx<T
     }
 }
 
+// Natural [system][row][m] <-> blocked [system][column block][position][cw]
+// layout of complex-FP32 blocks (float4 = two columns; LPR = cw / 2 float4 per
+// row and block; position = the row's place in the order `rows`).  A
+// workgroup moves BLK_T positions of one system through an LDS tile, so that
+// both sides are runs: whole rows on the natural side, BLK_T x LPR float4 per
+// column block on the blocked side.  IN: natural -> blocked, else back.
+constexpr int BLK_T = 32;
+template <bool IN, int TT, int NT>
+__global__ __launch_bounds__(NT) void k_blk_perm(int n, int m2, int lpr, const int* __restrict__ rows,
+                                                 const float4* __restrict__ src, float4* __restrict__ dst) {
+    extern __shared__ unsigned char dsm[];
+    float4* tile = reinterpret_cast<float4*>(dsm);   // [TT][m2 + 1]
+    const int ld = m2 + 1;
+    const int t0 = blockIdx.x * TT, s = blockIdx.y;
+    const int nt = min(TT, n - t0);
+    const int ncb = m2 / lpr;
+    const long nat = (long)s * n * m2;              // system s, natural
+    const long blk = (long)s * ncb * n * lpr;       // system s, blocked
+    const int tot = nt * m2;
+    if (IN) {
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int i = e / m2, j = e - i * m2;
+            tile[i * ld + j] = src[nat + (long)rows[t0 + i] * m2 + j];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int cb = e / (nt * lpr), r = e - cb * nt * lpr, i = r / lpr, k = r - i * lpr;
+            dst[blk + ((long)cb * n + t0 + i) * lpr + k] = tile[i * ld + cb * lpr + k];
+        }
+    } else {
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int cb = e / (nt * lpr), r = e - cb * nt * lpr, i = r / lpr, k = r - i * lpr;
+            tile[i * ld + cb * lpr + k] = src[blk + ((long)cb * n + t0 + i) * lpr + k];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int i = e / m2, j = e - i * m2;
+            dst[nat + (long)rows[t0 + i] * m2 + j] = tile[i * ld + j];
+        }
+    }
+}
+template <int TT, int NT>
+static void blk_perm_t(hipStream_t st, bool in, int nsys, int n, int m, int cw, const int* rows, const void* src,
+                       void* dst) {
+    const int m2 = m / 2;
+    dim3 grid(ceil_div(n, TT), nsys);
+    const size_t sh = sizeof(float4) * TT * (size_t)(m2 + 1);
+    if (in) k_blk_perm<true, TT, NT><<<grid, NT, sh, st>>>(n, m2, cw / 2, rows, (const float4*)src, (float4*)dst);
+    else k_blk_perm<false, TT, NT><<<grid, NT, sh, st>>>(n, m2, cw / 2, rows, (const float4*)src, (float4*)dst);
+    FH_LAUNCH_CHECK();
+}
+// tile shape (rows x threads); FH_BLK_CFG selects another for tuning runs
+static void blk_perm(hipStream_t st, bool in, int nsys, int n, int m, int cw, const int* rows, const void* src,
+                     void* dst) {
+    static int cfg = -1;
+    if (cfg < 0) {
+        const char* e = std::getenv("FH_BLK_CFG");
+        cfg = e ? std::atoi(e) : 0;
+    }
+    if (cfg == 1) blk_perm_t<16, 256>(st, in, nsys, n, m, cw, rows, src, dst);
+    else if (cfg == 2) blk_perm_t<32, 512>(st, in, nsys, n, m, cw, rows, src, dst);
+    else if (cfg == 3) blk_perm_t<16, 128>(st, in, nsys, n, m, cw, rows, src, dst);
+    else blk_perm_t<BLK_T, 256>(st, in, nsys, n, m, cw, rows, src, dst);
+}
+
 template <typename T>
 void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<T>* Out, const T* scale) {
     if (nsys <= 0) return;
@@ -1127,13 +1198,30 @@ void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<
     // (32-bit byte offsets: one system's block below 4 GB)
     const bool vec = pipe && vec_on && (a.cw == 2 || a.cw == 4 || a.cw == 8) && a.m % a.cw == 0 &&
                      (long)wmax * (a.cw / 2) <= 1024 && (long)a.n * a.m * 8 < (1L << 32);
+    // blocked layout when a workgroup owns at most four columns of a row (a
+    // row access of 32 bytes or less would be one short request per row):
+    // permute in, sweep in place, permute back (tile of BLK_T rows in LDS)
+    static int blk_on = -1;
+    if (blk_on < 0) {
+        const char* e = std::getenv("FH_ILU_BLK");
+        blk_on = e ? (std::atoi(e) != 0) : 1;
+    }
+    const bool blocked = vec && blk_on && a.blk != nullptr && a.cw <= 4 &&
+                         sizeof(float4) * BLK_T * (size_t)(a.m / 2 + 1) <= 65536;
     if (vec) {
         if constexpr (sizeof(T) == 4) {
             const int stride = wmax * (a.cw / 2);
             const size_t shv = 2 * sizeof(float4) * (size_t)stride;
-            if (a.cw == 2) k_ilu_apply_vec<2, 2, 512, 1><<<grid, 512, shv, st>>>(a, X, Out, stride);
-            else if (a.cw == 4) k_ilu_apply_vec<2, 2, 512, 2><<<grid, 512, shv, st>>>(a, X, Out, stride);
-            else k_ilu_apply_vec<2, 2, 512, 4><<<grid, 512, shv, st>>>(a, X, Out, stride);
+            if (blocked) {
+                Cx<T>* P = (Cx<T>*)a.blk->ensure(sizeof(Cx<T>) * (size_t)nsys * a.n * a.m);
+                const int* order = a.fwd[0].rows;    // the forward L sweep's packed order
+                blk_perm(st, true, nsys, a.n, a.m, a.cw, order, X, P);
+                if (a.cw == 2) k_ilu_apply_vec<2, 2, 512, 1, true><<<grid, 512, shv, st>>>(a, P, P, stride);
+                else k_ilu_apply_vec<2, 2, 512, 2, true><<<grid, 512, shv, st>>>(a, P, P, stride);
+                blk_perm(st, false, nsys, a.n, a.m, a.cw, order, P, Out);
+            } else if (a.cw == 2) k_ilu_apply_vec<2, 2, 512, 1, false><<<grid, 512, shv, st>>>(a, X, Out, stride);
+            else if (a.cw == 4) k_ilu_apply_vec<2, 2, 512, 2, false><<<grid, 512, shv, st>>>(a, X, Out, stride);
+            else k_ilu_apply_vec<2, 2, 512, 4, false><<<grid, 512, shv, st>>>(a, X, Out, stride);
         }
     } else if (pipe) {
         if constexpr (sizeof(T) == 4) {

@@ -48,9 +48,17 @@ static void level_order(const std::vector<int>& lev, int n, std::vector<int>& pt
 // factor on the M pattern); dpos_of(i) is the pivot position or -1 (unit).
 template <typename F, typename D>
 static SweepDev build_sweep(SparseState& S, const std::vector<int>& lev, int n, bool conjv, F entries, D dpos_of,
-                            hipStream_t st) {
+                            hipStream_t st, std::vector<int>* posL) {
     std::vector<int> ptr, rows;
     level_order(lev, n, ptr, rows);
+    // blocked-layout positions: the forward L sweep (built first) defines the
+    // order, every sweep addresses a row by its position in it
+    if (posL->empty()) {
+        posL->assign(n, 0);
+        for (int t = 0; t < n; ++t) (*posL)[rows[t]] = t;
+    }
+    std::vector<int> pp(n);
+    for (int t = 0; t < n; ++t) pp[t] = (*posL)[rows[t]];
     int K = 0;
     std::vector<int> cols, pos;
     for (int i = 0; i < n; ++i) {
@@ -76,6 +84,7 @@ static SweepDev build_sweep(SparseState& S, const std::vector<int>& lev, int n, 
     SweepDev sw;
     sw.lev_ptr = dev_ints(S, ptr, st);
     sw.rows = dev_ints(S, rows, st);
+    sw.ppos = dev_ints(S, pp, st);
     sw.nlev = (int)ptr.size() - 1;
     sw.K = K;
     sw.conj = conjv;
@@ -213,10 +222,11 @@ void sparse_prepare(Ctx& c, Prob& p) {
         lev[i] = l;
     }
     S->levL = levels_dev(*S, lev, n, st);
+    std::vector<int> posL;
     S->swL = build_sweep(*S, lev, n, false,
         [&](int i, std::vector<int>& c, std::vector<int>& ps) {
             for (int q = mrp[i]; q < mdiag[i]; ++q) { c.push_back(mci[q]); ps.push_back(q); } },
-        [&](int) { return -1; }, st);
+        [&](int) { return -1; }, st, &posL);
     for (int i = n - 1; i >= 0; --i) {       // U (backward)
         int l = 0;
         for (int q = mdiag[i] + 1; q < mrp[i + 1]; ++q) l = std::max(l, lev[mci[q]] + 1);
@@ -226,7 +236,7 @@ void sparse_prepare(Ctx& c, Prob& p) {
     S->swU = build_sweep(*S, lev, n, false,
         [&](int i, std::vector<int>& c, std::vector<int>& ps) {
             for (int q = mdiag[i] + 1; q < mrp[i + 1]; ++q) { c.push_back(mci[q]); ps.push_back(q); } },
-        [&](int i) { return mdiag[i]; }, st);
+        [&](int i) { return mdiag[i]; }, st, &posL);
     for (int i = 0; i < n; ++i) {            // U^H: lower part of M^T (forward)
         int l = 0;
         for (int q = trp[i]; q < tdiag[i]; ++q) l = std::max(l, lev[tci[q]] + 1);
@@ -236,7 +246,7 @@ void sparse_prepare(Ctx& c, Prob& p) {
     S->swUT = build_sweep(*S, lev, n, true,
         [&](int i, std::vector<int>& c, std::vector<int>& ps) {
             for (int q = trp[i]; q < tdiag[i]; ++q) { c.push_back(tci[q]); ps.push_back(t2m[q]); } },
-        [&](int i) { return mdiag[i]; }, st);
+        [&](int i) { return mdiag[i]; }, st, &posL);
     for (int i = n - 1; i >= 0; --i) {       // L^H: upper part of M^T (backward)
         int l = 0;
         for (int q = tdiag[i] + 1; q < trp[i + 1]; ++q) l = std::max(l, lev[tci[q]] + 1);
@@ -246,7 +256,7 @@ void sparse_prepare(Ctx& c, Prob& p) {
     S->swLT = build_sweep(*S, lev, n, true,
         [&](int i, std::vector<int>& c, std::vector<int>& ps) {
             for (int q = tdiag[i] + 1; q < trp[i + 1]; ++q) { c.push_back(tci[q]); ps.push_back(t2m[q]); } },
-        [&](int) { return -1; }, st);
+        [&](int) { return -1; }, st, &posL);
     S->mrowptr = dev_ints(*S, mrp, st);
     S->mcol = dev_ints(*S, mci, st);
     S->mdiag = dev_ints(*S, mdiag, st);
@@ -403,6 +413,7 @@ static IluApplyArgs<T> ilu_args(SparseState& S, int m, int precond) {
     a.bdiag[1] = nullptr;
     if (precond == FH_PC_JACOBI) a.dinv = (const Cx<T>*)(d ? S.jd64.p : S.jd32.p);
     a.junk = (Cx<T>*)S.junk.ensure(sizeof(Cx<double>) * ILU_JUNK);
+    if (!d) a.blk = &S.blk;
     return a;
 }
 
@@ -622,6 +633,7 @@ static SolveStats solve_batch(Ctx& c, SparseState& S, int nsys, int nright, cons
         S.bufR.release();
         S.b32.release();
         S.x32.release();
+        S.blk.release();
         if (precond != FH_PC_LEARNED) S.Zf.release();
         return gmres<double>(c, S, b, sh64, B64, X64, restart, std::max(1, o.max_restarts), o.inner_tol, precond, bn,
                              o.fallback, o.orth == 1 ? 1 : (o.orth == 2 ? 3 : 2));
@@ -710,7 +722,8 @@ static int filter_chunk(const SparseState& S, int ne, int m, const fh_opts& o) {
     const bool flex = o.precond == FH_PC_LEARNED;
     const double b = o.precision == FH_PREC_MIXED ? 8.0 : 16.0;       // bytes of a Krylov entry
     double per_sys = elems * (b * (restart + 2 + (flex ? restart : 0)) + 2 * 16.0);
-    if (o.precision == FH_PREC_MIXED) per_sys += elems * (16.0 + 2 * 8.0);   // FP64 residual, FP32 rhs / solution
+    // FP64 residual, FP32 rhs / solution, blocked-layout copy of the ILU(0) sweep
+    if (o.precision == FH_PREC_MIXED) per_sys += elems * (16.0 + 3 * 8.0);
     size_t freeb = 0, total = 0;
     FH_HIP(hipMemGetInfo(&freeb, &total));
     const double budget = 0.65 * (double)total;

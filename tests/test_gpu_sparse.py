@@ -127,14 +127,17 @@ def test_ilu0_apply_c64_both_sides(handle, name, m):
         np.testing.assert_allclose(out, ref, rtol=0, atol=2e-5 * np.abs(ref).max())
 
 
-@pytest.mark.parametrize("N,m", [(160, 5), (160, 64), (600, 16)])
+@pytest.mark.parametrize("N,m", [(160, 5), (160, 64), (600, 16), (500, 16), (1024, 6)])
 def test_ilu0_apply_c64_many_levels(handle, N, m):
     """160 x 160 grid: 319 dependent levels per sweep (not a multiple of the
     sweep's four-level unrolling), levels up to 160 rows wide (1,280 items per
     workgroup at 8 columns); 600 x 600: levels of up to 600 rows, wider than
     the 512-thread workgroup (two rows of factor data per thread, three
-    columns per workgroup).  Checked by the defining property L U y = x with
-    the oracle's factors, and against the complex-FP64 apply."""
+    columns per workgroup); 500 x 500 (four columns per workgroup) and
+    1024 x 1024 (two): the two-column sweep on the blocked layout (rows in
+    level order, each workgroup's columns contiguous).  Checked by the
+    defining property L U y = x with the oracle's factors, and against the
+    complex-FP64 apply."""
     A = W.convdiff2d_csr(N, 20.0, 10.0)
     n = A["n"]
     prob = fh.Problem(handle, _csr(A))
