@@ -122,6 +122,85 @@ __global__ __launch_bounds__(256) void k_spmm_rows(int n, int m, int cb, int ncb
     }
 }
 
+// Complex FP32 with an even column count: the same kernel with two adjacent
+// columns per lane (16-byte loads and stores, half the memory instructions).
+// cb2 column pairs per workgroup, blockDim (cb2, 256 / cb2).
+__device__ __forceinline__ float4 pair_of(Cx<float> a, Cx<float> b) { return make_float4(a.re, a.im, b.re, b.im); }
+template <typename TA, bool CONJ, int SL, int RPT>
+__global__ __launch_bounds__(256) void k_spmm_rows2(int n, int m2, int cb2, int ncb, const int* __restrict__ rowptr,
+                                                    const int* __restrict__ col, const TA* __restrict__ val,
+                                                    const Cx<float>* __restrict__ shifts, float alpha,
+                                                    const float4* __restrict__ X, const float4* __restrict__ Yadd,
+                                                    float4* __restrict__ Out) {
+    constexpr int MAXR = 32 * RPT;                    // ry <= 32 (cb2 >= 8)
+    __shared__ int s_col[MAXR * SL];
+    __shared__ TA s_val[MAXR * SL];
+    const int tx = threadIdx.x, ty = threadIdx.y, ry = blockDim.y;
+    const int rows = ry * RPT;
+    long lin = blockIdx.x + (long)blockIdx.y * gridDim.x;   // XCD-contiguous row blocks, as k_spmm_rows
+    const long G = (long)gridDim.x * gridDim.y;
+    if (G % 8 == 0) lin = (lin % 8) * (G / 8) + lin / 8;
+    const int bx = (int)(lin % gridDim.x), by = (int)(lin / gridDim.x);
+    const int r0 = bx * rows;
+    const int s = by / ncb;
+    const int c = (by % ncb) * cb2 + tx;              // column pair
+    const bool act = c < m2;
+    const int tid = ty * cb2 + tx, nt = cb2 * ry;
+    for (int idx = tid; idx < rows * SL; idx += nt) {
+        const int rl = idx / SL, q = idx - rl * SL;
+        const int r = r0 + rl;
+        int cc = 0;
+        TA vv{};
+        if (r < n) {
+            const int p = rowptr[r] + q;
+            cc = r;
+            if (p < rowptr[r + 1]) { cc = col[p]; vv = val[p]; }
+        }
+        s_col[idx] = cc;
+        s_val[idx] = vv;
+    }
+    __syncthreads();
+    if (!act) return;
+    const long base = (long)s * n * m2;
+    const float4* Xs = X + base;
+    float4 xv[RPT][SL];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int rl = ty + j * ry;
+#pragma unroll
+        for (int q = 0; q < SL; ++q) xv[j][q] = Xs[(long)s_col[rl * SL + q] * m2 + c];
+    }
+    const Cx<float> sh = shifts ? shifts[s] : czero<float>();
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int rl = ty + j * ry;
+        const int r = r0 + rl;
+        Cx<float> a0 = czero<float>(), a1 = czero<float>();
+#pragma unroll
+        for (int q = 0; q < SL; ++q) {
+            const float4 x = xv[j][q];
+            mac_val(a0, s_val[rl * SL + q], Cx<float>{x.x, x.y}, CONJ);
+            mac_val(a1, s_val[rl * SL + q], Cx<float>{x.z, x.w}, CONJ);
+        }
+        if (r < n) {
+            Cx<float> r0v = czero<float>(), r1v = czero<float>();
+            if (shifts) {
+                const float4 xr = Xs[(long)r * m2 + c];
+                r0v = sh * Cx<float>{xr.x, xr.y};
+                r1v = sh * Cx<float>{xr.z, xr.w};
+            }
+            r0v = alpha * (r0v - a0);
+            r1v = alpha * (r1v - a1);
+            float4 o = pair_of(r0v, r1v);
+            if (Yadd) {
+                const float4 y = Yadd[base + (long)r * m2 + c];
+                o = make_float4(o.x + y.x, o.y + y.y, o.z + y.z, o.w + y.w);
+            }
+            Out[base + (long)r * m2 + c] = o;
+        }
+    }
+}
+
 // column block of k_spmm_rows: all m columns when they divide 256 (one or
 // more rows per wave), else the largest of 64, 32, 16 that divides m, else 32
 // with a partial last block
@@ -142,9 +221,33 @@ static void spmm_rows_launch(hipStream_t st, int n, int m, int nsys, const CsrDe
                                                             Out);
 }
 
+template <typename TA, bool CONJ, int SL, int RPT>
+static void spmm_rows2_launch(hipStream_t st, int n, int m, int nsys, const CsrDev& A, const TA* v,
+                              const Cx<float>* shifts, float alpha, const Cx<float>* X, const Cx<float>* Yadd,
+                              Cx<float>* Out) {
+    const int m2 = m / 2, cb2 = spmm_colblock(m2), ncb = ceil_div(m2, cb2);
+    const int ry = 256 / cb2;
+    dim3 blk(cb2, ry), grid(ceil_div(n, ry * RPT), nsys * ncb);
+    k_spmm_rows2<TA, CONJ, SL, RPT><<<grid, blk, 0, st>>>(n, m2, cb2, ncb, A.rowptr, A.col, v, shifts, alpha,
+                                                          (const float4*)X, (const float4*)Yadd, (float4*)Out);
+}
+
 template <typename T, typename TA, bool CONJ>
 static bool spmm_rows(hipStream_t st, int n, int m, int nsys, const CsrDev& A, const TA* v, const Cx<T>* shifts,
                       T alpha, const Cx<T>* X, const Cx<T>* Yadd, Cx<T>* Out) {
+    // complex FP32, even m with column-pair blocks of at least 8 pairs, rows of
+    // at most 5 entries: two columns per lane
+    if constexpr (sizeof(T) == 4) {
+        static int on = -1;
+        if (on < 0) {
+            const char* e = std::getenv("FH_SPMM2");
+            on = e ? (std::atoi(e) != 0) : 1;
+        }
+        if (on && m % 2 == 0 && m >= 16 && m <= 512 && spmm_colblock(m / 2) >= 8 && A.maxrow >= 1 && A.maxrow <= 5) {
+            spmm_rows2_launch<TA, CONJ, 5, 2>(st, n, m, nsys, A, v, shifts, alpha, X, Yadd, Out);
+            return true;
+        }
+    }
     // column blocks of at least 16 columns: at most 16 row groups per block
     if (m < 16 || m > 256 || A.maxrow < 1) return false;
     if (A.maxrow <= 5) spmm_rows_launch<T, TA, CONJ, 5, 4>(st, n, m, nsys, A, v, shifts, alpha, X, Yadd, Out);
@@ -1097,7 +1200,7 @@ __global__ __launch_bounds__(256) void k_ilu_apply(IluApplyArgs<T> a, const Cx<T
 // workgroup moves BLK_T positions of one system through an LDS tile, so that
 // both sides are runs: whole rows on the natural side, BLK_T x LPR float4 per
 // column block on the blocked side.  IN: natural -> blocked, else back.
-constexpr int BLK_T = 32;
+constexpr int BLK_T = 16;
 template <bool IN, int TT, int NT>
 __global__ __launch_bounds__(NT) void k_blk_perm(int n, int m2, int lpr, const int* __restrict__ rows,
                                                  const float4* __restrict__ src, float4* __restrict__ dst) {
@@ -1142,18 +1245,12 @@ static void blk_perm_t(hipStream_t st, bool in, int nsys, int n, int m, int cw, 
     else k_blk_perm<false, TT, NT><<<grid, NT, sh, st>>>(n, m2, cw / 2, rows, (const float4*)src, (float4*)dst);
     FH_LAUNCH_CHECK();
 }
-// tile shape (rows x threads); FH_BLK_CFG selects another for tuning runs
+// tile of 16 rows, 256 threads: measured on one 1024^2 x 160-column block,
+// 0.54 + 0.50 ms for the two directions (5.0 / 5.4 TB/s) against 0.80 + 0.67 ms
+// with 32 rows and 0.55-0.59 ms with 8 rows or 512 threads
 static void blk_perm(hipStream_t st, bool in, int nsys, int n, int m, int cw, const int* rows, const void* src,
                      void* dst) {
-    static int cfg = -1;
-    if (cfg < 0) {
-        const char* e = std::getenv("FH_BLK_CFG");
-        cfg = e ? std::atoi(e) : 0;
-    }
-    if (cfg == 1) blk_perm_t<16, 256>(st, in, nsys, n, m, cw, rows, src, dst);
-    else if (cfg == 2) blk_perm_t<32, 512>(st, in, nsys, n, m, cw, rows, src, dst);
-    else if (cfg == 3) blk_perm_t<16, 128>(st, in, nsys, n, m, cw, rows, src, dst);
-    else blk_perm_t<BLK_T, 256>(st, in, nsys, n, m, cw, rows, src, dst);
+    blk_perm_t<BLK_T, 256>(st, in, nsys, n, m, cw, rows, src, dst);
 }
 
 template <typename T>
