@@ -181,8 +181,11 @@ typedef struct {
     double inner_relres;  /* worst final relative residual of the last filter  */
     double t_filter_ms;   /* time of the last contour integration             */
     double t_iter_ms;     /* time of the last full FEAST iteration            */
-    long long n_fallback; /* solves whose learned preconditioner was replaced
-                             by the fallback (cumulative)                     */
+    long long n_fallback; /* solves a fallback took over (cumulative): sparse,
+                             the learned preconditioner replaced by
+                             opts.fallback; dense complex FP32, systems whose
+                             refinement stalled above inner_tol, solved again
+                             with FP64 factors                                */
     int n_bq_retry;       /* B_Q eigendecompositions that exhausted the shifted
                              QR budget and were run again on the reversed
                              basis order (cumulative)                         */

@@ -322,6 +322,48 @@ static void run_graph(Ctx& c, hipGraphExec_t& exec, const std::function<void(hip
     FH_HIP(hipStreamWaitEvent(c.stream, c.gev[1], 0));
 }
 
+// FP64 fallback of a complex-FP32 group: the systems `bad` (whose FP32
+// refinement stalled above the inner tolerance: a node so close to an
+// eigenvalue that cond(z B - A) u_32 approaches 1) are factored in FP64 (once,
+// while the set stays the same) and solved directly; their solutions replace
+// the refined ones in G.Xv / G.Xhv.
+static void dg_fp64_fallback(Ctx& c, DenseGroup& G, const std::vector<int>& bad, const fh_opts& o) {
+    hipStream_t st = c.stream;
+    if (!G.fb64 || G.fb_sys != bad) {
+        G.fb64.reset(new DenseGroup());
+        std::vector<Prob*> probs;
+        std::vector<std::vector<std::complex<double>>> zs;
+        for (int s : bad) {
+            if (probs.empty() || probs.back() != G.prob[s]) {
+                probs.push_back(G.prob[s]);
+                zs.emplace_back();
+            }
+            zs.back().push_back(G.z[s]);
+        }
+        dg_build(c, *G.fb64, probs, zs, false, nullptr);
+        G.fb_sys = bad;
+    }
+    DenseGroup& F = *G.fb64;
+    std::vector<int> m(bad.size());
+    for (size_t k = 0; k < bad.size(); ++k) m[k] = G.m[bad[k]];
+    dg_layout(c, F, m);
+    for (size_t k = 0; k < bad.size(); ++k) {
+        const int s = bad[k];
+        const size_t bytes = sizeof(zd) * (size_t)G.n[s] * G.m[s];
+        FH_HIP(hipMemcpyAsync((zd*)F.Bv.p + F.voff[k], (const zd*)G.Bv.p + G.voff[s], bytes, hipMemcpyDeviceToDevice, st));
+        FH_HIP(hipMemcpyAsync((zd*)F.Bhv.p + F.voff[k], (const zd*)G.Bhv.p + G.voff[s], bytes, hipMemcpyDeviceToDevice,
+                              st));
+    }
+    dg_solve(c, F, o, nullptr);
+    for (size_t k = 0; k < bad.size(); ++k) {
+        const int s = bad[k];
+        const size_t bytes = sizeof(zd) * (size_t)G.n[s] * G.m[s];
+        FH_HIP(hipMemcpyAsync((zd*)G.Xv.p + G.voff[s], (const zd*)F.Xv.p + F.voff[k], bytes, hipMemcpyDeviceToDevice, st));
+        FH_HIP(hipMemcpyAsync((zd*)G.Xhv.p + G.voff[s], (const zd*)F.Xhv.p + F.voff[k], bytes, hipMemcpyDeviceToDevice,
+                              st));
+    }
+}
+
 double dg_solve(Ctx& c, DenseGroup& G, const fh_opts& o, fh_report* rep) {
     const long tot = G.vtot;
     const int cnt = G.count;
@@ -367,7 +409,7 @@ double dg_solve(Ctx& c, DenseGroup& G, const fh_opts& o, fh_report* rep) {
     FH_HIP(hipMemcpyAsync(zr, hz0.data(), sizeof(zd) * 2 * cnt, hipMemcpyHostToDevice, st0));
     set_colnorm(st0, cnt, G.mmax, off, dn, dm, Bv, nrm);
     set_colnorm(st0, cnt, G.mmax, off, dn, dm, Bhv, nrm + C);
-    std::vector<double> hb(2 * (size_t)C), hr(2 * (size_t)C);
+    std::vector<double> hb(2 * (size_t)C), hr(2 * (size_t)C), h1;
     FH_HIP(hipMemcpyAsync(hb.data(), nrm, sizeof(double) * 2 * C, hipMemcpyDeviceToHost, st0));
     // one refinement step: d = LU32^{-1} r in complex FP32, x += d, r = b - (z B - A) x in FP64
     auto body = [&](hipStream_t st, bool first) {
@@ -402,10 +444,37 @@ double dg_solve(Ctx& c, DenseGroup& G, const fh_opts& o, fh_report* rep) {
         const double prev = worst;
         worst = 0.0;
         for (int q = 0; q < 2 * C; ++q) worst = std::max(worst, hb[q] > 0 ? hr[q] / hb[q] : 0.0);
+        if (first) h1 = hr;
         if (rep) rep->inner_steps += 1;
         if (!(worst > o.inner_tol)) break;
         // stop at the FP64 rounding floor: a step that does not halve the residual
         if (it > 0 && !(worst < 0.5 * prev)) break;
+    }
+    if (steps > 1 && worst > o.inner_tol) {
+        // the refinement ended (stalled, or out of steps) above the
+        // tolerance: systems still above it that gained less than a factor of
+        // 1,000 over their first complex-FP32 solve (the FP32 factors contract
+        // slowly or not at all; a system that reached its FP64 rounding floor
+        // has gained far more) get FP64 factors.  A single refinement step
+        // (max_refine = 1) asks for the plain FP32 solve and never falls back.
+        std::vector<int> bad;
+        double rest = 0.0;
+        for (int s = 0; s < cnt; ++s) {
+            double rs = 0.0, r1 = 0.0;
+            for (int col = 0; col < G.m[s]; ++col)
+                for (int side = 0; side < 2; ++side) {
+                    const int q = side * C + s * G.mmax + col;
+                    rs = std::max(rs, hb[q] > 0 ? hr[q] / hb[q] : 0.0);
+                    r1 = std::max(r1, hb[q] > 0 ? h1[q] / hb[q] : 0.0);
+                }
+            if (rs > o.inner_tol && rs > 1e-3 * r1) bad.push_back(s);
+            else rest = std::max(rest, rs);
+        }
+        if (!bad.empty()) {
+            dg_fp64_fallback(c, G, bad, o);
+            if (rep) rep->n_fallback += (long long)bad.size();
+            worst = rest;   // the FP64 solves are direct
+        }
     }
     if (rep) rep->inner_relres = worst;
     return worst;

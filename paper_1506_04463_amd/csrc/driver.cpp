@@ -694,6 +694,11 @@ int feast_batched(Ctx& c, int count, Prob* const* probs, const fh_contour* cts, 
         }
         fh_report srep{};
         dg_solve(c, G, o, &srep);
+        // systems solved again with FP64 factors, attributed to their problems
+        if (reps && srep.n_fallback > 0)
+            for (int s : G.fb_sys)
+                for (int i = 0; i < count; ++i)
+                    if (s >= first[i] && s < first[i] + cts[i].ne) reps[i].n_fallback += 1;
         for (int i = 0; i < count; ++i) {
             FeastRun& r = *runs[i];
             if (r.done) continue;

@@ -9,6 +9,7 @@
 // triangular-block launches; the FP64 residuals keep the refinement exact.
 #pragma once
 #include <complex>
+#include <memory>
 
 #include "fh_group.h"
 #include "fh_internal.h"
@@ -39,6 +40,11 @@ struct DenseGroup {
     // captured launch sequences (valid for the current layout)
     hipGraphExec_t g_fp64 = nullptr, g_first = nullptr, g_next = nullptr;
     DBuf zb;                        // shifts of the residual initialisation
+    // complex-FP32 groups: FP64 factors of the systems whose refinement
+    // stalled above the inner tolerance (built on demand, kept while the set
+    // of such systems does not change)
+    std::unique_ptr<DenseGroup> fb64;
+    std::vector<int> fb_sys;
     void drop_graphs() {
         for (hipGraphExec_t* g : {&g_fp64, &g_first, &g_next})
             if (*g) {

@@ -58,6 +58,46 @@ def test_mixed_filter_matches_oracle(handle, n, m0, ne, gen):
     assert rep["n_factor"] == ne
 
 
+def test_mixed_filter_fp64_fallback_near_eigenvalue(handle):
+    """An eigenvalue 1e-9 outside node 0 (cond(z_0 - A) about 1e10): the
+    complex-FP32 factors of that node do not contract, the refinement stalls,
+    and that system alone is solved again with FP64 factors (n_fallback = 1);
+    the filter then matches the FP64 oracle.  The same call with one
+    refinement step (no stall test) keeps the FP32 result."""
+    n, m0, ne = 200, 12, 8
+    rng = np.random.default_rng(21)
+    c, r = 0.1 + 0.1j, 0.25
+    z, w = ct.ellipse_nodes(c, r, 1.0, 0.0, ne)
+    u = (z[0] - c) / abs(z[0] - c)
+    lam = [z[0] + 1e-9 * u]
+    while len(lam) < 6:                                   # inside, away from the circle
+        x = c + 0.2 * r * np.sqrt(rng.uniform()) * np.exp(2j * np.pi * rng.uniform())
+        lam.append(x)
+    while len(lam) < n:                                   # outside, away from the circle
+        x = np.sqrt(rng.uniform()) * np.exp(2j * np.pi * rng.uniform())
+        if abs(x - c) > 1.5 * r:
+            lam.append(x)
+    lam = np.array(lam)
+    V = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    V /= np.linalg.norm(V, axis=0)
+    A = np.linalg.solve(V.T, (V * lam[None, :]).T).T
+    Y, Yh = W.subspace(n, m0, 3), W.subspace(n, m0, 4)
+    Qo, Qho = F.contour_filter(A, None, z, w, Y, Yh)
+    prob = fh.Problem(handle, _cuda(A))
+    o = fh.default_opts(m0, precision=fh.FH_PREC_MIXED, inner_tol=1e-10, max_refine=8, save_factors=0)
+    Q, Qh, rep = fh.contour_filter(prob, z, w, _cuda(Y), _cuda(Yh), o)
+    assert rep["n_fallback"] == 1
+    Q, Qh = Q.cpu().numpy(), Qh.cpu().numpy()
+    # two FP64 solvers of systems with condition up to about 1e12 agree to
+    # cond * eps; the stalled complex-FP32 result is off by O(1)
+    tol = 10 * _kappa_max(A, None, z) * np.finfo(float).eps
+    assert np.linalg.norm(Q - Qo) / np.linalg.norm(Qo) < tol
+    assert np.linalg.norm(Qh - Qho) / np.linalg.norm(Qho) < tol
+    o1 = fh.default_opts(m0, precision=fh.FH_PREC_MIXED, inner_tol=1e-10, max_refine=1, save_factors=0)
+    _, _, rep1 = fh.contour_filter(prob, z, w, _cuda(Y), _cuda(Yh), o1)
+    assert rep1["n_fallback"] == 0
+
+
 def test_mixed_filter_single_step_is_fp32_accurate(handle):
     """One refinement step is a plain complex-FP32 solve: its relative
     residual is at the FP32 level, far above FP64's, which the next steps
