@@ -165,7 +165,23 @@ typedef struct {
                              real non-symmetric with a contour symmetric about
                              the real axis: n_e/2 factorizations; Table
                              tab:solve).  The solves stay 2 n_e: the start
-                             block is complex.  0 = factorize every node */
+                             block is complex.
+                             2 = the same factorizations, and n_e solves
+                             instead of 2 n_e (n_e/2 with sym = 1; the
+                             table's n_e total solves): fh_feast drops the
+                             imaginary part of the start blocks (not with
+                             resume), so that in exact arithmetic every
+                             search subspace is closed under conjugation; before
+                             each filter it pairs the Ritz values as
+                             conjugates, makes the pairs exact (x_k =
+                             conj(x_i), lambda_k = conj(lambda_i), the vectors
+                             of real Ritz values real: a change at rounding
+                             level), and solves only the upper nodes' systems,
+                             a lower node's solution being the conjugate of
+                             its partner's for the partner column.  fh_filter
+                             does the same when Y and Yh are real (zero
+                             imaginary parts), else it behaves as with 1.
+                             0 = factorize every node */
 } fh_opts;
 
 typedef struct {

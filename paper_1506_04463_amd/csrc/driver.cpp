@@ -108,6 +108,43 @@ static cplx rational(int ne, const cplx* z, const cplx* w, cplx lam) {
 
 static void sync(Ctx& c) { FH_HIP(hipStreamSynchronize(c.stream)); }
 
+// Column partners of Ritz values that come in conjugate pairs (a real pencil
+// whose search subspace is closed under conjugation): i and k are partners
+// when each is the other's nearest conjugate (k = i for a real value); the
+// columns left over are paired greedily, each with the nearest conjugate
+// among them, so the result is always an involution.  Non-finite values stay
+// alone.
+static std::vector<int> conj_partners(const cplx* lam, int m) {
+    auto fin = [&](int i) { return std::isfinite(lam[i].real()) && std::isfinite(lam[i].imag()); };
+    std::vector<int> cp(m, -1), near(m);
+    for (int i = 0; i < m; ++i) {
+        near[i] = i;
+        if (!fin(i)) continue;
+        double bd = std::abs(lam[i] - std::conj(lam[i]));
+        for (int k = 0; k < m; ++k)
+            if (k != i && fin(k)) {
+                const double d = std::abs(lam[k] - std::conj(lam[i]));
+                if (d < bd) { bd = d; near[i] = k; }
+            }
+    }
+    for (int i = 0; i < m; ++i)
+        if (near[near[i]] == i) cp[i] = near[i];
+    for (int i = 0; i < m; ++i) {
+        if (cp[i] >= 0) continue;
+        int best = i;
+        double bd = fin(i) ? std::abs(lam[i] - std::conj(lam[i])) : 0.0;
+        if (fin(i))
+            for (int k = i + 1; k < m; ++k)
+                if (cp[k] < 0 && fin(k)) {
+                    const double d = std::abs(lam[k] - std::conj(lam[i]));
+                    if (d < bd) { bd = d; best = k; }
+                }
+        cp[i] = best;
+        cp[best] = i;
+    }
+    return cp;
+}
+
 // FH_VERBOSE=1 prints one line per FEAST iteration to stderr
 static int verbose() {
     static const int v = [] {
@@ -179,10 +216,10 @@ static void dense_factor(Ctx& c, Prob& p, int ne, const cplx* z, const fh_opts& 
 
 
 void filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m0, const zd* Y, const zd* Yh, zd* Q,
-            zd* Qh, const fh_opts& o, fh_report* rep, const cplx* lam) {
+            zd* Qh, const fh_opts& o, fh_report* rep, const cplx* lam, const int* cpart) {
     auto t0 = std::chrono::steady_clock::now();
     if (!p.dense) {
-        sparse_filter(c, p, ne, z, w, m0, Y, Yh, Q, Qh, o, rep, lam);
+        sparse_filter(c, p, ne, z, w, m0, Y, Yh, Q, Qh, o, rep, lam, cpart);
     } else if (o.precision == FH_PREC_MIXED) {
         dense_filter_group(c, p, ne, z, w, m0, Y, Yh, Q, Qh, o, rep);
     } else {
@@ -313,11 +350,54 @@ struct FeastRun {
         hd2.assign(m0in, 0.0);
         // resume: the start columns are Ritz vectors whose values are passed in lambda
         if (o.resume) to_host(c, reinterpret_cast<zd*>(hlam.data()), lambda, m0in);
+        // conj_pairs = 2: a real start block (its imaginary part dropped) makes
+        // every later subspace closed under conjugation
+        half = sparse_conj_closed(p, ne, z.data(), w.data(), o);
+        if (half && !o.resume) {
+            real_part(c.stream, (long)big, Ycur);
+            real_part(c.stream, (long)big, Yhcur);
+        }
     }
 
     // Ritz values of the current columns (residual form of the iterative
     // filter from the second iteration on), or nullptr
-    const cplx* filter_lambda() const { return ((it >= 1 || o.resume) && !p.dense) ? hlam.data() : nullptr; }
+    const cplx* filter_lambda() const {
+        if (!((it >= 1 || o.resume) && !p.dense)) return nullptr;
+        return half ? flam.data() : hlam.data();
+    }
+
+    // conj_pairs = 2 (real CSR matrix, nodes in conjugate pairs): before each
+    // filter, pair the Ritz values as conjugates and make the pairs exact,
+    // x_k = conj(x_i), xh_k = conj(xh_i), lambda_k = conj(lambda_i), and the
+    // vectors of real Ritz values real.  In exact arithmetic the subspace of a
+    // real start block stays closed under conjugation, so this changes the
+    // columns by rounding only; the filter then solves n_e/2 nodes per side.
+    // Returns the column partners, or nullptr when the mode is off.
+    bool half = false;
+    std::vector<int> cpart;
+    std::vector<cplx> flam;
+    DBuf cpdev;
+    const int* prepare_filter() {
+        if (!half) return nullptr;
+        const int m = mcur;
+        if (!filter_lambda_needed()) {
+            cpart.resize(m);
+            std::iota(cpart.begin(), cpart.end(), 0);   // real start block
+            return cpart.data();
+        }
+        cpart = conj_partners(hlam.data(), m);
+        flam.assign(hlam.begin(), hlam.begin() + m);
+        for (int i = 0; i < m; ++i) {
+            const int k = cpart[i];
+            if (k == i && std::isfinite(flam[i].real())) flam[i] = cplx(flam[i].real(), 0.0);
+            else if (k > i) flam[k] = std::conj(flam[i]);
+        }
+        int* d = (int*)cpdev.ensure(sizeof(int) * m);
+        to_dev(c, d, cpart.data(), m);
+        conj_close_cols(c.stream, n, m, Ycur, Yhcur, d, c.partial);
+        return cpart.data();
+    }
+    bool filter_lambda_needed() const { return it >= 1 || o.resume; }
 
     // Steps 2-5 of iteration it+1 (Q, Qh filled), in phases so that many runs
     // can share one launch of each small eigensolver: GPU work is enqueued by
@@ -614,7 +694,8 @@ int feast(Ctx& c, Prob& p, const fh_contour& ct, const cplx* zin, const cplx* wi
     for (;;) {
         r.t0 = std::chrono::steady_clock::now();
         // step 1: contour integration
-        filter(c, p, r.ne, r.z.data(), r.w.data(), r.mcur, r.Ycur, r.Yhcur, r.Q, r.Qh, o, rep, r.filter_lambda());
+        const int* cp = r.prepare_filter();
+        filter(c, p, r.ne, r.z.data(), r.w.data(), r.mcur, r.Ycur, r.Yhcur, r.Q, r.Qh, o, rep, r.filter_lambda(), cp);
         if (r.step()) break;
     }
     return r.finish(Yio, Yhio, lambda, res_out);

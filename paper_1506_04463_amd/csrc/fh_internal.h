@@ -76,8 +76,12 @@ struct Prob {
 using cplx = std::complex<double>;
 
 // driver.cpp
+// cpart (sparse problems with conj_pairs = 2): host array of m0 column
+// partners, an involution, with Y[:, cpart[i]] = conj(Y[:, i]), the same for
+// Yh, and lam[cpart[i]] = conj(lam[i]); the filter then solves the upper
+// nodes' systems only.  nullptr: no such promise.
 void filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m0, const zd* Y, const zd* Yh, zd* Q,
-            zd* Qh, const fh_opts& o, fh_report* rep, const cplx* lam = nullptr);
+            zd* Qh, const fh_opts& o, fh_report* rep, const cplx* lam = nullptr, const int* cpart = nullptr);
 int feast(Ctx& c, Prob& p, const fh_contour& ct, const cplx* z, const cplx* w, const fh_opts& o, zd* Y, zd* Yh,
           zd* lambda, double* res, fh_report* rep);
 void apply_A(Ctx& c, Prob& p, int side, int m, const zd* X, zd* Out);
@@ -87,7 +91,10 @@ void contour_nodes(const fh_contour& ct, std::vector<cplx>& z, std::vector<cplx>
 // sparse.cpp
 void sparse_prepare(Ctx& c, Prob& p);
 void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m0, const zd* Y, const zd* Yh,
-                   zd* Q, zd* Qh, const fh_opts& o, fh_report* rep, const cplx* lam);
+                   zd* Q, zd* Qh, const fh_opts& o, fh_report* rep, const cplx* lam, const int* cpart = nullptr);
+// true when conj_pairs = 2 applies to a FEAST run on this problem: a CSR
+// matrix with real values and nodes that pair up as conjugates
+bool sparse_conj_closed(const Prob& p, int ne, const cplx* z, const cplx* w, const fh_opts& o);
 void sparse_apply_A(Ctx& c, Prob& p, int side, int m, const zd* X, zd* Out);
 void sparse_shifted_apply(Ctx& c, Prob& p, int side, int nsys, const cplx* shifts, int m, const zd* X, zd* Out);
 void sparse_residual_pair(Ctx& c, Prob& p, int side, int nsys, const cplx* shifts, int m, const zd* B, const zd* X,

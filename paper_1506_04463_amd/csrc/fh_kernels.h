@@ -41,6 +41,15 @@ void conj_copy(hipStream_t st, long len, const zd* src, zd* dst);
 // the filter of the left block conj(Y) D that satisfies yh_c^H y_c = 1
 void conj_copy_bilin(hipStream_t st, int n, int m, const zd* Y, const zd* Q, zd* Qh, DBuf& part);
 
+// Make the columns of X (n x m) closed under conjugation, in place: cp_dev is
+// an involution on the columns; a pair (i, k = cp[i] > i) gets x_k = conj(x_i),
+// a column with cp[c] = c is rotated by the phase that makes x_c^T x_c real
+// positive and its imaginary part dropped.  Xh (or nullptr) takes the same
+// operations with X's phases.
+void conj_close_cols(hipStream_t st, int n, int m, zd* X, zd* Xh, const int* cp_dev, DBuf& part);
+// X = Re(X) in place (len entries)
+void real_part(hipStream_t st, long len, zd* X);
+
 // cast between complex precisions
 template <typename D, typename S>
 void cast(hipStream_t st, long len, const Cx<S>* src, Cx<D>* dst);

@@ -90,6 +90,7 @@ struct SparseState {
     DBuf node_of, side_of, shifts64, shifts32, coef, rho, bufB, bufX, bufR, bufT, b32, x32;
     DBuf V, Z, Hs, cs, sn, g, resid, vscale, kuse, y, h1, h2, hnorm, beta, bnorm, part, bn64, rn64, sc64;
     DBuf Hraw, htent, tau, dcoef, scv, scw, dots;   // DCGS2
+    DBuf cpd, coefp, flag;   // conjugation-closed filter: column partners, upper/lower weights, real-input flag
     DBuf aval32, atval64, atval32, bn32, Zf;
     NetState* net = nullptr;   // attached learned preconditioner (not owned)
     ~SparseState() {
@@ -149,6 +150,12 @@ void axpy_cols(hipStream_t st, int n, int m, int nsys, const Cx<T>* Z, const dou
 // Q = (add ? Q : 0) + Y diag(rho) (when Y) + sum_j E_j diag(coef_j)
 void filter_accum(hipStream_t st, int ne, int n, int m, const zd* E, const zd* coef, const zd* Y, const zd* rho, zd* Q,
                   bool add);
+// the same with conjugation-closed columns: E holds the upper nodes' solutions
+// only, node j's lower partner adds cl_j[c] conj(E_j[:, cp[c]]) to column c
+void filter_accum_pair(hipStream_t st, int ne, int n, int m, const zd* E, const zd* cu, const zd* cl, const int* cp,
+                       const zd* Y, const zd* rho, zd* Q, bool add);
+// *flag_dev |= 1 when some entry of X (len) has a nonzero imaginary part
+void any_imag(hipStream_t st, long len, const zd* X, int* flag_dev);
 void ritz_residual(hipStream_t st, const CsrDev& A, bool conj_t, int n, int m, const zd* lam, bool conj_lam,
                    const zd* X, zd* Out);
 void jacobi_diag(hipStream_t st, const SparseState& S, int ne, const zd* mvals, zd* jd);

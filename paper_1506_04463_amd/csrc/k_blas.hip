@@ -297,6 +297,67 @@ void conj_copy_bilin(hipStream_t st, int n, int m, const zd* Y, const zd* Q, zd*
     FH_LAUNCH_CHECK();
 }
 
+// Conjugation-closed columns, in place.  cp is an involution on the m
+// columns: a pair (i, k = cp[i] > i) gets x_k = conj(x_i); a column with
+// cp[c] = c is made real as Re(x_c e^{-i phi_c / 2}), phi_c = arg(x_c^T x_c):
+// for x_c = e^{i t} r with r real, x_c^T x_c = e^{2 i t} r^T r, so the product
+// is +-r (the real eigenvector of a real eigenvalue, up to its sign).  A
+// second block (the left vectors, xh_c^H x_c = 1) takes the same operations
+// with the phases of the first, which keeps xh_c^H x_c = 1.
+__global__ void k_conj_phase(int nch, int m, const zd* __restrict__ part, const int* __restrict__ cp,
+                             zd* __restrict__ ph) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    zd s = czero<double>();
+    for (int ch = 0; ch < nch; ++ch) s = s + part[(long)ch * m + c];
+    zd p = cx(1.0, 0.0);
+    if (cp[c] == c && cabs(s) > 0.0 && std::isfinite(cabs(s))) {
+        const double h = 0.5 * atan2(s.im, s.re);
+        p = cx(cos(h), -sin(h));
+    }
+    ph[c] = p;
+}
+__global__ void k_conj_close(long len, int m, const int* __restrict__ cp, const zd* __restrict__ ph,
+                             zd* __restrict__ X) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= len) return;
+    const int c = e % m, pc = cp[c];
+    if (pc == c) {
+        const zd v = X[e] * ph[c];
+        X[e] = cx(v.re, 0.0);
+    } else if (pc < c) {
+        X[e] = conj(X[e - c + pc]);
+    }
+}
+void conj_close_cols(hipStream_t st, int n, int m, zd* X, zd* Xh, const int* cp_dev, DBuf& part) {
+    if (n <= 0 || m <= 0) return;
+    const int rows = 256, nch = ceil_div(n, rows);
+    zd* P = (zd*)part.ensure(sizeof(zd) * ((size_t)nch * m + m));
+    zd* ph = P + (size_t)nch * m;
+    k_bilin_partial<<<nch, ((m + 63) / 64) * 64, 0, st>>>(n, m, X, rows, P);
+    FH_LAUNCH_CHECK();
+    k_conj_phase<<<ceil_div(m, 64), 64, 0, st>>>(nch, m, P, cp_dev, ph);
+    FH_LAUNCH_CHECK();
+    const long len = (long)n * m;
+    k_conj_close<<<ceil_div(len, 256), 256, 0, st>>>(len, m, cp_dev, ph, X);
+    FH_LAUNCH_CHECK();
+    if (Xh) {
+        k_conj_close<<<ceil_div(len, 256), 256, 0, st>>>(len, m, cp_dev, ph, Xh);
+        FH_LAUNCH_CHECK();
+    }
+}
+
+// X = Re(X) in place
+__global__ void k_real_part(long len, zd* __restrict__ X) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < len) X[e].im = 0.0;
+}
+void real_part(hipStream_t st, long len, zd* X) {
+    if (len <= 0) return;
+    k_real_part<<<ceil_div(len, 256), 256, 0, st>>>(len, X);
+    FH_LAUNCH_CHECK();
+}
+
 template <typename D, typename S>
 __global__ void k_cast(long len, const Cx<S>* __restrict__ src, Cx<D>* __restrict__ dst) {
     long e = (long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -2250,6 +2250,46 @@ void filter_accum(hipStream_t st, int ne, int n, int m, const zd* E, const zd* c
     FH_LAUNCH_CHECK();
 }
 
+// Conjugation-closed columns: E_j (j < ne) are the solutions at the upper
+// nodes only.  Column c of the lower partner of node j is conj(E_j[:, cp[c]]),
+// so Q[:, c] += cu_j[c] E_j[:, c] + cl_j[c] conj(E_j[:, cp[c]]).
+__global__ void k_filter_accum_pair(int ne, int n, int m, const zd* __restrict__ E, const zd* __restrict__ cu,
+                                    const zd* __restrict__ cl, const int* __restrict__ cp, const zd* __restrict__ Y,
+                                    const zd* __restrict__ rho, int add, zd* __restrict__ Q) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)n * m) return;
+    const int c = e % m;
+    const long ep = e - c + cp[c];
+    zd acc = add ? Q[e] : czero<double>();
+    if (Y) cfma(acc, rho[c], Y[e]);
+    for (int j = 0; j < ne; ++j) {
+        const zd* Ej = E + (long)j * n * m;
+        cfma(acc, cu[(long)j * m + c], Ej[e]);
+        cfma(acc, cl[(long)j * m + c], conj(Ej[ep]));
+    }
+    Q[e] = acc;
+}
+void filter_accum_pair(hipStream_t st, int ne, int n, int m, const zd* E, const zd* cu, const zd* cl, const int* cp,
+                       const zd* Y, const zd* rho, zd* Q, bool add) {
+    k_filter_accum_pair<<<ceil_div((size_t)n * m, 256), 256, 0, st>>>(ne, n, m, E, cu, cl, cp, Y, rho, add ? 1 : 0,
+                                                                        Q);
+    FH_LAUNCH_CHECK();
+}
+
+// flag = 1 if any entry of X (len) has a nonzero imaginary part (flag zeroed by the caller)
+__global__ void k_any_imag(long len, const zd* __restrict__ X, int* __restrict__ flag) {
+    int any = 0;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (long)gridDim.x * blockDim.x)
+        any |= X[e].im != 0.0;
+    if (__any(any) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+void any_imag(hipStream_t st, long len, const zd* X, int* flag_dev) {
+    if (len <= 0) return;
+    const int grid = (int)std::min<long>(ceil_div(len, 256), 4096);
+    k_any_imag<<<grid, 256, 0, st>>>(len, X, flag_dev);
+    FH_LAUNCH_CHECK();
+}
+
 // R = A Y - Y diag(lam)  (left: A^H Yh - Yh diag(conj lam)); computed as
 // spmm with shifts per column -> use a column-shift variant
 template <typename TA, bool CONJ>

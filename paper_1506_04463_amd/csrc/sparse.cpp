@@ -731,8 +731,48 @@ static int filter_chunk(const SparseState& S, int ne, int m, const fh_opts& o) {
     return std::max(1, std::min(ne, g));
 }
 
+// Nodes symmetric about the real axis: each node off the axis has a partner
+// z_k = conj(z_j) with w_k = conj(w_j).  fz: the upper and real-axis nodes;
+// fmap[j]: index in fz of node j (a lower node: of its partner); flip[j] = 1
+// for a lower node.  False (and fmap the identity) when some node has no
+// partner.
+static bool pair_nodes(int ne, const cplx* z, const cplx* w, std::vector<int>& fmap, std::vector<int>& flip,
+                       std::vector<cplx>& fz) {
+    fmap.resize(ne);
+    flip.assign(ne, 0);
+    fz.clear();
+    for (int j = 0; j < ne; ++j) fmap[j] = j;
+    std::vector<int> partner(ne, -1);
+    for (int j = 0; j < ne; ++j) {
+        if (z[j].imag() == 0.0) continue;
+        for (int k = 0; k < ne; ++k) {
+            const double tz = 1e-13 * (1.0 + std::abs(z[j])), tw = 1e-13 * (1.0 + std::abs(w[j]));
+            if (k != j && std::abs(z[k] - std::conj(z[j])) <= tz && std::abs(w[k] - std::conj(w[j])) <= tw) {
+                partner[j] = k;
+                break;
+            }
+        }
+        if (partner[j] < 0) return false;
+    }
+    std::vector<int> fidx(ne, -1);
+    for (int j = 0; j < ne; ++j)
+        if (z[j].imag() >= 0.0) { fidx[j] = (int)fz.size(); fz.push_back(z[j]); }
+    for (int j = 0; j < ne; ++j) {
+        if (z[j].imag() >= 0.0) fmap[j] = fidx[j];
+        else { fmap[j] = fidx[partner[j]]; flip[j] = 1; }
+    }
+    return true;
+}
+
+bool sparse_conj_closed(const Prob& p, int ne, const cplx* z, const cplx* w, const fh_opts& o) {
+    if (p.dense || o.conj_pairs != 2 || p.sp->A.complex_vals) return false;
+    std::vector<int> fmap, flip;
+    std::vector<cplx> fz;
+    return pair_nodes(ne, z, w, fmap, flip, fz);
+}
+
 void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m, const zd* Y, const zd* Yh, zd* Q,
-                   zd* Qh, const fh_opts& o, fh_report* rep, const cplx* lam) {
+                   zd* Qh, const fh_opts& o, fh_report* rep, const cplx* lam, const int* cpart) {
     FH_REQUIRE(m >= 1 && m <= 256, -6, "sparse filter: m0 must be in [1, 256]");
     SparseState& S = *p.sp;
     // complex symmetric problems: the left subspace is the conjugate of the
@@ -755,39 +795,49 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
     // its upper partner's with conjugated right-hand sides, and their
     // solutions conjugated back (the paper's real non-symmetric case with a
     // contour symmetric about the real axis: n_e/2 factorizations).
-    std::vector<int> fmap(ne), flip(ne, 0);
+    std::vector<int> fmap, flip;
     std::vector<cplx> fz;
-    for (int j = 0; j < ne; ++j) fmap[j] = j;
-    bool paired = false;
-    if (o.conj_pairs && !S.A.complex_vals) {
-        std::vector<int> partner(ne, -1);
-        bool ok = true;
-        for (int j = 0; j < ne && ok; ++j) {
-            if (z[j].imag() == 0.0) continue;
-            for (int k = 0; k < ne; ++k) {
-                const double tz = 1e-13 * (1.0 + std::abs(z[j])), tw = 1e-13 * (1.0 + std::abs(w[j]));
-                if (k != j && std::abs(z[k] - std::conj(z[j])) <= tz && std::abs(w[k] - std::conj(w[j])) <= tw) {
-                    partner[j] = k;
-                    break;
-                }
-            }
-            ok = partner[j] >= 0;
-        }
-        if (ok) {
-            paired = true;
-            std::vector<int> fidx(ne, -1);
-            for (int j = 0; j < ne; ++j)
-                if (z[j].imag() >= 0.0) { fidx[j] = (int)fz.size(); fz.push_back(z[j]); }
-            for (int j = 0; j < ne; ++j) {
-                if (z[j].imag() >= 0.0) fmap[j] = fidx[j];
-                else { fmap[j] = fidx[partner[j]]; flip[j] = 1; }
+    const bool paired = o.conj_pairs && !S.A.complex_vals && pair_nodes(ne, z, w, fmap, flip, fz);
+    if (!paired) {
+        fz.assign(z, z + ne);
+        fmap.resize(ne);
+        flip.assign(ne, 0);
+        for (int j = 0; j < ne; ++j) fmap[j] = j;
+    }
+    const int nf = (int)fz.size();
+    // Conjugation-closed right-hand sides (conj_pairs = 2): when column
+    // cp[i] of the right-hand side block is the conjugate of column i, the
+    // conjugated right-hand sides a lower node needs are columns of the block
+    // itself, so conj((z - A)^{-1} conj(r_i)) = conj(E[:, cp[i]]) with E the
+    // upper node's solution: only the upper nodes' systems are solved, n_e/2
+    // per side (Table tab:solve, real non-symmetric with a contour symmetric
+    // about the real axis: n_e/2 factorizations and n_e solves).  The FEAST
+    // driver passes cp for its symmetrized Ritz vectors; a direct call with
+    // real Y and Yh (no Ritz values) uses cp = identity.
+    std::vector<int> cp;
+    if (paired && o.conj_pairs == 2) {
+        if (cpart) {
+            cp.assign(cpart, cpart + m);
+            for (int i = 0; i < m; ++i)
+                FH_REQUIRE(cp[i] >= 0 && cp[i] < m && cp[cp[i]] == i, -3, "column partners must be an involution");
+        } else if (!lam) {
+            int* fl = (int*)S.flag.ensure(sizeof(int));
+            FH_HIP(hipMemsetAsync(fl, 0, sizeof(int), st));
+            any_imag(st, blk, Y, fl);
+            if (!right_only) any_imag(st, blk, Yh, fl);
+            int h = 1;
+            FH_HIP(hipMemcpyAsync(&h, fl, sizeof(int), hipMemcpyDeviceToHost, st));
+            FH_HIP(hipStreamSynchronize(st));
+            if (h == 0) {
+                cp.resize(m);
+                for (int i = 0; i < m; ++i) cp[i] = i;
             }
         }
     }
-    if (!paired) fz.assign(z, z + ne);
-    const int nf = (int)fz.size();
+    const bool half = !cp.empty();
     if (needs_factors(o)) ensure_factors(c, S, nf, fz.data(), o.precision == FH_PREC_MIXED, o, rep);
-    const int g = filter_chunk(S, ne, m, o);
+    const int nnode = half ? nf : ne;      // nodes whose systems are solved
+    const int g = filter_chunk(S, nnode, m, o);
     zd* Bb = (zd*)S.bufB.ensure(sizeof(zd) * blk * 2 * g);
     zd* Xb = (zd*)S.bufX.ensure(sizeof(zd) * blk * 2 * g);
     zd* T = (zd*)S.bufT.ensure(sizeof(zd) * blk * 2);
@@ -819,7 +869,28 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
             }
     }
     zd* cd = (zd*)S.coef.ensure(sizeof(zd) * coef.size());
-    FH_HIP(hipMemcpyAsync(cd, coef.data(), sizeof(zd) * coef.size(), hipMemcpyHostToDevice, st));
+    zd *cu = nullptr, *cl = nullptr;
+    int* cpd = nullptr;
+    if (half) {
+        // cu[side][f][i] / cl[side][f][i]: weights of upper node f and of its
+        // lower partner (zero for a real-axis node)
+        std::vector<cplx> cuh(2 * (size_t)nf * m, 0.0), clh(2 * (size_t)nf * m, 0.0);
+        for (int sd = 0; sd < 2; ++sd)
+            for (int j = 0; j < ne; ++j) {
+                std::vector<cplx>& dst = flip[j] ? clh : cuh;
+                for (int i = 0; i < m; ++i)
+                    dst[(size_t)sd * nf * m + (size_t)fmap[j] * m + i] = coef[(size_t)sd * ne * m + (size_t)j * m + i];
+            }
+        zd* cpb = (zd*)S.coefp.ensure(sizeof(zd) * 4 * (size_t)nf * m);
+        cu = cpb;
+        cl = cpb + 2 * (size_t)nf * m;
+        FH_HIP(hipMemcpyAsync(cu, cuh.data(), sizeof(zd) * cuh.size(), hipMemcpyHostToDevice, st));
+        FH_HIP(hipMemcpyAsync(cl, clh.data(), sizeof(zd) * clh.size(), hipMemcpyHostToDevice, st));
+        cpd = (int*)S.cpd.ensure(sizeof(int) * m);
+        FH_HIP(hipMemcpyAsync(cpd, cp.data(), sizeof(int) * m, hipMemcpyHostToDevice, st));
+    } else {
+        FH_HIP(hipMemcpyAsync(cd, coef.data(), sizeof(zd) * coef.size(), hipMemcpyHostToDevice, st));
+    }
     zd* rd = nullptr;
     if (lam) {
         rd = (zd*)S.rho.p;
@@ -828,33 +899,44 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
     const zd* Rr = lam ? T : Y;            // right-hand sides: residuals (or Y), replicated per node
     const zd* Rl = lam ? T + blk : Yh;
     SolveStats s;
-    // nodes [j0, j1) at a time: their right and left systems in one batch
+    // nodes [j0, j1) at a time (of fz when half, else of z): their right and
+    // left systems in one batch
     const int sides = right_only ? 1 : 2;
-    for (int j0 = 0; j0 < ne; j0 += g) {
-        const int j1 = std::min(ne, j0 + g), gc = j1 - j0;
+    for (int j0 = 0; j0 < nnode; j0 += g) {
+        const int j1 = std::min(nnode, j0 + g), gc = j1 - j0;
         replicate<double>(st, blk, Rr, Bb, gc);
         if (!right_only) replicate<double>(st, blk, Rl, Bb + gc * blk, gc);
         std::vector<int> node_of(sides * gc);
         std::vector<cplx> zsys(sides * gc);
         for (int q = 0; q < sides * gc; ++q) {
             const int j = j0 + q % gc;
-            node_of[q] = fmap[j];
-            zsys[q] = paired ? fz[fmap[j]] : z[j];
-            if (flip[j]) conj_copy(st, blk, Bb + (long)q * blk, Bb + (long)q * blk);   // conj(b)
+            node_of[q] = half ? j : fmap[j];
+            zsys[q] = half ? fz[j] : paired ? fz[fmap[j]] : z[j];
+            if (!half && flip[j]) conj_copy(st, blk, Bb + (long)q * blk, Bb + (long)q * blk);   // conj(b)
         }
         const SolveStats sc = solve_batch(c, S, sides * gc, gc, node_of.data(), zsys.data(), m, Bb, Xb, o);
-        for (int q = 0; q < sides * gc; ++q)
-            if (flip[j0 + q % gc]) conj_copy(st, blk, Xb + (long)q * blk, Xb + (long)q * blk);
+        if (!half)
+            for (int q = 0; q < sides * gc; ++q)
+                if (flip[j0 + q % gc]) conj_copy(st, blk, Xb + (long)q * blk, Xb + (long)q * blk);
         s.steps += sc.steps;
         s.cycles += sc.cycles;
         s.relres = std::max(s.relres, sc.relres);
         s.fallback |= sc.fallback;
         const bool first = j0 == 0;
-        filter_accum(st, gc, n, m, Xb, cd + (size_t)j0 * m, (lam && first) ? Y : nullptr, first ? rd : nullptr, Q,
-                     !first);
-        if (!right_only)
-            filter_accum(st, gc, n, m, Xb + gc * blk, cd + (size_t)(ne + j0) * m, (lam && first) ? Yh : nullptr,
-                         (first && rd) ? rd + m : nullptr, Qh, !first);
+        const zd* Yr = (lam && first) ? Y : nullptr;
+        const zd* Yl = (lam && first) ? Yh : nullptr;
+        const zd* rr = first ? rd : nullptr;
+        const zd* rl = (first && rd) ? rd + m : nullptr;
+        if (half) {
+            const size_t ls = (size_t)nf * m;
+            filter_accum_pair(st, gc, n, m, Xb, cu + (size_t)j0 * m, cl + (size_t)j0 * m, cpd, Yr, rr, Q, !first);
+            if (!right_only)
+                filter_accum_pair(st, gc, n, m, Xb + gc * blk, cu + ls + (size_t)j0 * m, cl + ls + (size_t)j0 * m, cpd,
+                                  Yl, rl, Qh, !first);
+        } else {
+            filter_accum(st, gc, n, m, Xb, cd + (size_t)j0 * m, Yr, rr, Q, !first);
+            if (!right_only) filter_accum(st, gc, n, m, Xb + gc * blk, cd + (size_t)(ne + j0) * m, Yl, rl, Qh, !first);
+        }
     }
     // complex symmetric: the left block is taken as conj(Y) D with
     // D = diag(conj(1 / (y_c^T y_c))), the scaling with yh_c^H y_c = 1 that
@@ -862,8 +944,8 @@ void sparse_filter(Ctx& c, Prob& p, int ne, const cplx* z, const cplx* w, int m,
     if (sym && Qh) conj_copy_bilin(st, n, m, Y, Q, Qh, c.partial2);
     FH_HIP(hipStreamSynchronize(st));
     if (rep) {
-        rep->n_fallback += s.fallback ? sides * ne : 0;
-        rep->n_solve += sides * ne;
+        rep->n_fallback += s.fallback ? sides * nnode : 0;
+        rep->n_solve += sides * nnode;
         rep->inner_steps = s.steps;
         rep->inner_relres = s.relres;
     }

@@ -524,3 +524,94 @@ def test_filter_real_conjugate_node_pairs(handle, precision):
     tol = 16 * kap * 1e-10
     assert np.max(np.abs(out[1][0] - Qo)) <= tol * np.max(np.abs(Qo))
     assert np.max(np.abs(out[1][1] - Qho)) <= tol * np.max(np.abs(Qho))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_filter_real_blocks_halve_the_solves(handle, precision):
+    """conj_pairs = 2 with real Y and Yh: a lower node's solution is the
+    conjugate of its upper partner's, so only the 8 upper nodes' systems are
+    solved per side (16 instead of 32, the n_e total solves of Table
+    tab:solve's real non-symmetric row with a contour symmetric about the real
+    axis); the filter equals the conj_pairs = 1 filter and the oracle's.
+    Complex blocks fall back to the solves of conj_pairs = 1."""
+    p = _small_convdiff()
+    z, w = ct.ellipse_nodes(p.contour.center, p.contour.a, p.contour.ratio, 0.0, 16)
+    Yr, Yhr = p.Y0.real.astype(np.complex128), p.Yh0.real.astype(np.complex128)
+    Qo, Qho = F.contour_filter(L.csr_matrix(p.A), None, z, w, Yr, Yhr)
+    out = {}
+    for pairs in (2, 1):
+        prob = fh.Problem(handle, _csr(p.A))
+        opts = fh.default_opts(p.m0, solver=1, precond=2, inner_tol=1e-10, restart=30, max_restarts=400,
+                               precision=precision, mixed_inner_tol=1e-5, max_refine=30, conj_pairs=pairs)
+        Q, Qh, rep = fh.contour_filter(prob, z, w, _cuda(Yr), _cuda(Yhr), opts)
+        out[pairs] = (Q.cpu().numpy(), Qh.cpu().numpy(), rep)
+    assert out[2][2]["n_factor"] == out[1][2]["n_factor"] == 8
+    assert out[2][2]["n_solve"] == 16 and out[1][2]["n_solve"] == 32
+    for k in (0, 1):
+        a, b = out[2][k], out[1][k]
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+    Ad = W.csr_to_dense(p.A)
+    kap = max(np.linalg.cond(zj * np.eye(p.n) - Ad) for zj in z)
+    tol = 16 * kap * 1e-10
+    assert np.max(np.abs(out[2][0] - Qo)) <= tol * np.max(np.abs(Qo))
+    assert np.max(np.abs(out[2][1] - Qho)) <= tol * np.max(np.abs(Qho))
+    # complex blocks: every node's systems are solved
+    prob = fh.Problem(handle, _csr(p.A))
+    opts = fh.default_opts(p.m0, solver=1, precond=2, inner_tol=1e-10, restart=30, max_restarts=400,
+                           precision=precision, mixed_inner_tol=1e-5, max_refine=30, conj_pairs=2)
+    Q, Qh, rep = fh.contour_filter(prob, z, w, _cuda(p.Y0), _cuda(p.Yh0), opts)
+    assert rep["n_solve"] == 32
+
+
+def _real_3d(N=10, m_target=14):
+    v = W.smooth_field3d(N, 4000)
+    A = W.convdiff3d_csr(N, v)
+    lam = np.linalg.eigvals(W.csr_to_dense(A))
+    cont, inside = W.lowest_contour(lam, m_target, window=3)
+    return A, lam, cont, inside
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_feast_conjugation_closed_subspace_halves_the_solves(handle, precision):
+    """FEAST on a real non-symmetric 3D convection-diffusion operator (n =
+    1,000) whose eigenvalues inside the ellipse include complex-conjugate
+    pairs, from real start blocks: with conj_pairs = 2 the driver pairs the
+    Ritz values as conjugates before each filter and solves only the upper
+    nodes' systems, n_e per iteration for both sides instead of 2 n_e (Table
+    tab:solve); the eigenpairs equal the oracle's (direct solves, same real
+    start) and those of conj_pairs = 1."""
+    A, lam, cont, inside = _real_3d()
+    assert np.count_nonzero(np.abs(lam[np.argsort(lam.real)][:inside].imag) > 1e-6) >= 4
+    n, m0, ne = A["n"], 24, 16
+    Y0, Yh0 = W.subspace(n, m0, 5).real.astype(np.complex128), W.subspace(n, m0, 6).real.astype(np.complex128)
+    c = F.Contour(cont.center, cont.a, cont.ratio, 0.0, ne)
+    alpha = c.alpha()
+    ref = F.feast(L.csr_matrix(A), None, c, Y0, Yh0, eps=1e-12, max_iter=30)
+    assert ref.info == 0 and len(ref.lam) == inside
+    Ad = W.csr_to_dense(A)
+    nA = np.abs(Ad).sum(axis=0).max()
+    out = {}
+    for pairs in (2, 1):
+        prob = fh.Problem(handle, _csr(A))
+        opts = fh.default_opts(m0, solver=1, precond=2, inner_tol=1e-3, restart=30, max_restarts=2,
+                               precision=precision, mixed_inner_tol=1e-3, max_refine=3, eps=1e-11, max_iter=60,
+                               conj_pairs=pairs, confirm=1)
+        r = fh.feast(prob, cont.center, cont.a, cont.ratio, 0.0, ne, _cuda(Y0), _cuda(Yh0), opts)
+        assert r["info"] == 0, r["report"]
+        rep = r["report"]
+        assert rep["n_factor"] == ne // 2
+        assert rep["n_solve"] == (1 if pairs == 2 else 2) * ne * rep["iters"], rep
+        assert len(r["lam"]) == inside
+        # conjugate pairs share their real part, so the (Re, Im) order of the
+        # two lists may differ at rounding level: match each value to its nearest
+        d = np.abs(r["lam"][:, None] - ref.lam[None, :])
+        assert max(d.min(axis=1).max(), d.min(axis=0).max()) < 1e-10 * alpha
+        X, Xh = r["X"].cpu().numpy(), r["Xh"].cpu().numpy()
+        np.testing.assert_allclose(Xh.conj().T @ X, np.eye(inside), atol=1e-10)
+        lm = r["lam"]
+        rr = np.abs(Ad @ X - X * lm).sum(axis=0) / (nA * np.abs(X).sum(axis=0))
+        rl = np.abs(Ad.T @ Xh - Xh * np.conj(lm)).sum(axis=0) / (nA * np.abs(Xh).sum(axis=0))
+        assert rr.max() <= 1e-10 and rl.max() <= 1e-10
+        out[pairs] = rep["iters"]
+    print(f"iterations: oracle {ref.iters}, conj_pairs=2 {out[2]}, conj_pairs=1 {out[1]}")
+    assert out[2] <= out[1] + 1

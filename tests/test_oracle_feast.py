@@ -275,6 +275,80 @@ def test_complex_symmetric_left_filter_is_conjugate():
     assert np.linalg.norm(Qh2 - np.conj(Q2)) > 1e-3 * np.linalg.norm(Q2)
 
 
+def _real_3d_problem(N=6):
+    """Real non-symmetric 3D convection-diffusion-reaction operator and an
+    ellipse centred on the real axis around its lowest eigenvalues, among
+    which are complex-conjugate pairs."""
+    v = W.smooth_field3d(N, 4000)
+    A = W.convdiff3d_csr(N, v)
+    lam = np.linalg.eigvals(W.csr_to_dense(A))
+    cont, inside = W.lowest_contour(lam, 10)
+    return A, lam, cont, inside
+
+
+def test_filter_of_conjugation_closed_blocks_is_conjugation_closed():
+    """Real A and nodes symmetric about the real axis (each lower node the
+    conjugate of an upper one, with the conjugate weight): for real blocks the
+    filter is real, and when column k of the block is the conjugate of column
+    i, column k of the filter is the conjugate of column i, on both sides
+    (the reduced-workload case of the paper, real non-symmetric with a
+    contour symmetric about the real axis: a lower node's solutions are the
+    conjugates of its partner's, so n_e solves give both subspaces).  The
+    oracle solves every node directly."""
+    A, lam, cont, inside = _real_3d_problem()
+    assert np.count_nonzero(np.abs(lam.imag) > 1e-6) > 0
+    z, w = ct.ellipse_nodes(cont.center, cont.a, cont.ratio, 0.0, 16)
+    assert np.abs(z[:, None] - np.conj(z)[None, :]).min(axis=1).max() < 1e-12 * cont.a
+    Asp = L.csr_matrix(A)
+    n = A["n"]
+    Yr, Yhr = W.subspace(n, 6, 7).real, W.subspace(n, 6, 8).real
+    Q, Qh = F.contour_filter(Asp, None, z, w, Yr, Yhr)
+    assert np.abs(Q.imag).max() <= 1e-13 * np.abs(Q).max()
+    assert np.abs(Qh.imag).max() <= 1e-13 * np.abs(Qh).max()
+    # columns (0, 3) and (1, 4) conjugate pairs, 2 and 5 real
+    Y, Yh = W.subspace(n, 6, 9), W.subspace(n, 6, 10)
+    for Z in (Y, Yh):
+        Z[:, 3], Z[:, 4] = np.conj(Z[:, 0]), np.conj(Z[:, 1])
+        Z[:, 2], Z[:, 5] = Z[:, 2].real, Z[:, 5].real
+    Q, Qh = F.contour_filter(Asp, None, z, w, Y, Yh)
+    for M in (Q, Qh):
+        sc = np.abs(M).max()
+        assert np.abs(M[:, 3] - np.conj(M[:, 0])).max() <= 1e-13 * sc
+        assert np.abs(M[:, 4] - np.conj(M[:, 1])).max() <= 1e-13 * sc
+        assert np.abs(M[:, [2, 5]].imag).max() <= 1e-13 * sc
+    # a contour off the real axis breaks the identity (the check has teeth)
+    z2, w2 = ct.ellipse_nodes(cont.center + 0.2j * cont.a, cont.a, cont.ratio, 0.0, 16)
+    Q2, _ = F.contour_filter(Asp, None, z2, w2, Yr, Yhr)
+    assert np.abs(Q2.imag).max() > 1e-3 * np.abs(Q2).max()
+
+
+def test_feast_from_real_start_keeps_conjugate_ritz_pairs():
+    """From real start blocks every FEAST iterate of a real pencil under a
+    contour symmetric about the real axis spans a subspace closed under
+    conjugation, so at every iteration the m0 Ritz values (inside and
+    outside) come in conjugate pairs or are real, and the converged pairs are
+    the operator's eigenvalues inside the ellipse."""
+    A, lam, cont, inside = _real_3d_problem()
+    n = A["n"]
+    c = F.Contour(cont.center, cont.a, cont.ratio, 0.0, 16)
+    res = F.feast(L.csr_matrix(A), None, c, W.subspace(n, 16, 3).real, W.subspace(n, 16, 4).real, eps=1e-12,
+                  max_iter=30, keep_history=True)
+    assert res.info == 0 and len(res.lam) == inside
+    alpha = c.alpha()
+    truth = lam[c.inside(lam)]
+    assert np.max(np.abs(res.lam[:, None] - truth[None, :]).min(axis=1)) < 1e-10 * alpha
+    for rec in res.history:
+        rl = rec["lam"]
+        fin = rl[np.isfinite(rl)]
+        gap = np.abs(fin[:, None] - np.conj(fin)[None, :]).min(axis=1)
+        assert gap.max() <= 1e-8 * alpha, gap.max()
+    # a complex start block has no such pairing in its first iterate
+    res2 = F.feast(L.csr_matrix(A), None, c, W.subspace(n, 16, 3), W.subspace(n, 16, 4), eps=1e-12, max_iter=1,
+                   keep_history=True)
+    rl = res2.history[0]["lam"]
+    assert np.abs(rl[:, None] - np.conj(rl)[None, :]).min(axis=1).max() > 1e-6 * alpha
+
+
 def test_count_estimate_exact_trace_and_probes():
     """The eigenvalue-count estimator: with the identity as probe block (p = n)
     it is exactly trace(rho_a) / n, and for the trapezoid circle rho_a has the
