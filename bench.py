@@ -39,6 +39,7 @@ PEAK_HBM_GBS = 8000.0
 EPS_ITER = 1e-9
 EPS_DENSE = 1e-10   # dense batch: the residual level the throughput metric is stated at
 ORTH = 2            # GMRES orthogonalization (fh_opts.orth), set by --orth
+BATCH_NODES = 0     # headline workload: nodes per filter chunk (0: as many as fit), set by --batch-nodes
 
 
 def _problem():
@@ -46,14 +47,16 @@ def _problem():
     return W.convdiff2d(N=256, bx=20.0, by=10.0, m_in=41, ne=16, m0=64, ratio=0.3, seed=2)
 
 
-def _opts(fh, m0, precision, max_iter, eps, resume=0):
+def _opts(fh, m0, precision, max_iter, eps, resume=0, conj_pairs=1):
     # GMRES(30), two cycles per solve, residual-form filter; the mixed path runs
     # one complex-FP32 solve per filter followed by its FP64 residual check.
     # orth = 2 (delayed reorthogonalization) acts on the complex-FP32 solves
     # only; FP64 solves keep classical Gram-Schmidt with reorthogonalization.
+    # conj_pairs = 2: real start blocks, conjugate Ritz pairs, n_e solves per
+    # iteration instead of 2 n_e (real matrix, ellipse centred on the real axis).
     return fh.default_opts(m0, solver=fh.FH_SOLVER_BGMRES, precond=fh.FH_PC_ILU0, restart=30, max_restarts=2,
                            inner_tol=1e-3, precision=precision, mixed_inner_tol=1e-3, max_refine=1,
-                           max_iter=max_iter, eps=eps, resume=resume, orth=ORTH)
+                           max_iter=max_iter, eps=eps, resume=resume, orth=ORTH, conj_pairs=conj_pairs)
 
 
 def _traffic(kernel, workload="convdiff256"):
@@ -71,22 +74,28 @@ def _traffic(kernel, workload="convdiff256"):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def run_path(fh, torch, handle, prob, p, precision, steps, warmup, profile=False):
+def _start(torch, p, conj_pairs):
+    """Seeded start blocks on the device (their real parts with conj_pairs = 2)."""
+    Y0, Yh0 = (p.Y0.real.astype(np.complex128), p.Yh0.real.astype(np.complex128)) if conj_pairs == 2 else (p.Y0, p.Yh0)
+    return torch.from_numpy(Y0).cuda(), torch.from_numpy(Yh0).cuda()
+
+
+def run_path(fh, torch, handle, prob, p, precision, steps, warmup, profile=False, conj_pairs=1):
     """W warm-up iterations from the seeded start, then exactly K timed ones."""
     c = p.contour
-    Y0 = torch.from_numpy(p.Y0).cuda()
-    Yh0 = torch.from_numpy(p.Yh0).cuda()
+    Y0, Yh0 = _start(torch, p, conj_pairs)
     ritz = None
     resume = 0
     if warmup > 0:
-        out = fh.feast(prob, c.center, c.a, c.ratio, c.angle, c.ne, Y0, Yh0, _opts(fh, p.m0, precision, warmup, 1e-300))
+        out = fh.feast(prob, c.center, c.a, c.ratio, c.angle, c.ne, Y0, Yh0,
+                       _opts(fh, p.m0, precision, warmup, 1e-300, conj_pairs=conj_pairs))
         Y0, Yh0, ritz, resume = out["Y"].contiguous(), out["Yh"].contiguous(), out["ritz"], 1
     if profile:
         handle.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = fh.feast(prob, c.center, c.a, c.ratio, c.angle, c.ne, Y0, Yh0,
-                   _opts(fh, Y0.shape[1], precision, steps, 1e-300, resume), ritz0=ritz)
+                   _opts(fh, Y0.shape[1], precision, steps, 1e-300, resume, conj_pairs), ritz0=ritz)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     stats = handle.profile_stats() if profile else None
@@ -95,15 +104,15 @@ def run_path(fh, torch, handle, prob, p, precision, steps, warmup, profile=False
     return dt, out, stats
 
 
-def solve_to_convergence(fh, torch, prob, p, precision):
+def solve_to_convergence(fh, torch, prob, p, precision, conj_pairs=1):
     """Untimed for the metric: a fresh solve from the seeded start to eq:res <= EPS_ITER
     (time-to-solution), then the returned eigenpairs are checked."""
     c = p.contour
-    Y0 = torch.from_numpy(p.Y0).cuda()
-    Yh0 = torch.from_numpy(p.Yh0).cuda()
+    Y0, Yh0 = _start(torch, p, conj_pairs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    fin = fh.feast(prob, c.center, c.a, c.ratio, c.angle, c.ne, Y0, Yh0, _opts(fh, p.m0, precision, 60, EPS_ITER))
+    fin = fh.feast(prob, c.center, c.a, c.ratio, c.angle, c.ne, Y0, Yh0,
+                   _opts(fh, p.m0, precision, 60, EPS_ITER, conj_pairs=conj_pairs))
     torch.cuda.synchronize()
     tts = time.perf_counter() - t0
     alpha = abs(c.center) + max(c.a, c.ratio * c.a)
@@ -114,6 +123,7 @@ def solve_to_convergence(fh, torch, prob, p, precision):
     normA = float(np.max(np.bincount(A["colind"], weights=np.abs(A["val"]), minlength=A["n"])))
     max_res = float(np.max(fin["res"])) if len(fin["res"]) else None
     return {"converged": fin["info"] == 0, "m": int(len(fin["lam"])), "m_expected": int(len(exact)),
+            "solves": int(fin["report"]["n_solve"]), "factorizations": int(fin["report"]["n_factor"]),
             "max_eq_res": max_res,
             # ||Ax - lam x||_1 / (||A||_1 ||x||_1) = eq:res * alpha / ||A||_1 for B = I
             "max_rel_residual": None if max_res is None else max_res * alpha / normA,
@@ -530,7 +540,8 @@ def _c5_opts(fh, m0, precision, max_iter, eps, resume=0, precond=None):
     # conj(Y) D (complex symmetric, opts.sym = 1) on both precisions
     return fh.default_opts(m0, solver=fh.FH_SOLVER_BGMRES, precond=fh.FH_PC_ILU0 if precond is None else precond,
                            restart=30, max_restarts=2, inner_tol=1e-3, precision=precision, mixed_inner_tol=1e-3,
-                           max_refine=1, max_iter=max_iter, eps=eps, resume=resume, orth=2, sym=1)
+                           max_refine=1, max_iter=max_iter, eps=eps, resume=resume, orth=2, sym=1,
+                           batch_nodes=BATCH_NODES)
 
 
 def _c5_cpu_baseline(p, sample_cols=8):
@@ -827,17 +838,23 @@ def convdiff3d_learned(args):
     runs = {}
     u = (eigs - c.center)
     ref_in = eigs[(u.real / c.a) ** 2 + (u.imag / (c.ratio * c.a)) ** 2 < 1.0]
-    for name, pc in (("learned", fh.FH_PC_LEARNED), ("ilu0", fh.FH_PC_ILU0), ("jacobi", fh.FH_PC_JACOBI),
-                     ("none", fh.FH_PC_NONE)):
+    # ilu0-conj: ILU(0) with n_e solves per iteration instead of 2 n_e (real
+    # start blocks, conjugate Ritz pairs; the matrix is real and the ellipse
+    # centred on the real axis)
+    for name, pc, cpairs in (("learned", fh.FH_PC_LEARNED, 1), ("ilu0", fh.FH_PC_ILU0, 1),
+                             ("ilu0-conj", fh.FH_PC_ILU0, 2), ("jacobi", fh.FH_PC_JACOBI, 1),
+                             ("none", fh.FH_PC_NONE, 1)):
         if name not in want:
             continue
         o = fh.default_opts(p.m0, solver=fh.FH_SOLVER_BGMRES, precond=pc, restart=30, max_restarts=2,
                             inner_tol=1e-3, precision=fh.FH_PREC_MIXED, mixed_inner_tol=1e-3, max_refine=1,
-                            max_iter=args.max_iter, eps=EPS_ITER, orth=2, fallback=fh.FH_PC_ILU0, confirm=1)
+                            max_iter=args.max_iter, eps=EPS_ITER, orth=2, fallback=fh.FH_PC_ILU0, confirm=1,
+                            conj_pairs=cpairs)
+        y0, yh0 = (Y0, Yh0) if cpairs == 1 else (Y0.real.to(Y0.dtype), Yh0.real.to(Yh0.dtype))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         try:
-            out = fh.feast(prob, c.center, c.a, c.ratio, 0.0, c.ne, Y0, Yh0, o)
+            out = fh.feast(prob, c.center, c.a, c.ratio, 0.0, c.ne, y0, yh0, o)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t1
             lam = out["lam"]
@@ -845,7 +862,8 @@ def convdiff3d_learned(args):
             r = {"info": out["info"], "iterations": out["report"]["iters"], "seconds": dt,
                  "s_per_iteration": dt / max(1, out["report"]["iters"]), "m": int(len(lam)),
                  "m_reference_inside": int(len(ref_in)), "max_dlam_over_alpha": d,
-                 "fallback_solves": out["report"]["n_fallback"], "last_inner_relres": out["report"]["inner_relres"]}
+                 "fallback_solves": out["report"]["n_fallback"], "last_inner_relres": out["report"]["inner_relres"],
+                 "solves": out["report"]["n_solve"], "factorizations": out["report"]["n_factor"]}
         except fh.FeastError as e:
             r = {"error": str(e), "seconds": time.perf_counter() - t1}
         runs[name] = r
@@ -876,10 +894,12 @@ def main():
     ap.add_argument("--grid3d", type=int, default=64, help="convdiff3d: grid points per side")
     ap.add_argument("--train-fields", type=int, default=32, help="convdiff3d: training convection fields")
     ap.add_argument("--epochs", type=int, default=20, help="convdiff3d: training epochs")
-    ap.add_argument("--preconds", default="learned,ilu0,jacobi,none", help="convdiff3d: preconditioners to run")
+    ap.add_argument("--preconds", default="learned,ilu0,ilu0-conj,jacobi,none", help="convdiff3d: preconditioners to run")
     ap.add_argument("--eigs", default=None, help="headline workload: reference eigenvalues (.npy or the golden "
                                                  "JSON; default the 1024 x 1024 one)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
+    ap.add_argument("--batch-nodes", type=int, default=0, help="headline workload: quadrature nodes solved "
+                                                               "together (fh_opts.batch_nodes; 0 = as many as fit)")
     ap.add_argument("--tts", action="store_true", help="contour-grid: also run the batched path to eq:res <= 1e-7")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-validate", action="store_true")
@@ -895,8 +915,9 @@ def main():
                     help="GMRES orthogonalization: 0 CGS2, 1 one projection, 2 delayed reorthogonalization "
                          "(complex-FP32 solves; FP64 solves use CGS2)")
     args = ap.parse_args()
-    global ORTH
+    global ORTH, BATCH_NODES
     ORTH = args.orth
+    BATCH_NODES = args.batch_nodes
     if args.steps is None:
         args.steps = 2 if args.workload == "schrodinger" else 16
     if args.warmup is None:
@@ -946,10 +967,18 @@ def main():
         ms_64 = 1000.0 * dt_64 / args.steps
         plain = {"value": 1000.0 / ms_64, "ms_per_step": ms_64}
         print(f"[bench] fp64: {ms_64:.1f} ms/iteration", file=sys.stderr, flush=True)
+    # the same mixed path with n_e solves per iteration instead of 2 n_e
+    dt_h, _, _ = run_path(fh, torch, handle, prob, p, fh.FH_PREC_MIXED, args.steps, args.warmup, conj_pairs=2)
+    half = {"ms_per_step": 1000.0 * dt_h / args.steps, "solves_per_iteration": 16,
+            "speedup_vs_2ne_solves": dt_mx / dt_h}
+    print(f"[bench] mixed, conj_pairs=2 (n_e solves): {half['ms_per_step']:.1f} ms/iteration", file=sys.stderr,
+          flush=True)
     valid = None
     if not args.no_validate:
         valid = solve_to_convergence(fh, torch, prob, p, fh.FH_PREC_MIXED)
         print(f"[bench] validation: {valid}", file=sys.stderr, flush=True)
+        half["time_to_solution"] = solve_to_convergence(fh, torch, prob, p, fh.FH_PREC_MIXED, conj_pairs=2)
+        print(f"[bench] validation, conj_pairs=2: {half['time_to_solution']}", file=sys.stderr, flush=True)
         if plain is not None:
             v64 = solve_to_convergence(fh, torch, prob, p, fh.FH_PREC_FP64)
             plain["time_to_solution"] = v64
@@ -989,6 +1018,9 @@ def main():
         # fixed Krylov budget per right-hand side (2 GMRES(30) cycles), not a tolerance
         "rhs_per_s_fixed_budget": rhs * 1000.0 / ms_mx,
         "plain_fp64": plain,
+        # real matrix and an ellipse centred on the real axis: real start blocks,
+        # conjugate Ritz pairs, 16 solves per iteration instead of 32 (Table tab:solve)
+        "conj_subspace": half,
         "speedup_vs_fp64": None if plain is None else plain["ms_per_step"] / ms_mx,
         "time_to_solution_speedup_vs_fp64": (None if plain is None or valid is None or "time_to_solution" not in plain
                                              else plain["time_to_solution"]["time_to_solution_s"] /
