@@ -1259,6 +1259,17 @@ void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<
     FH_REQUIRE(scale == nullptr, -1, "ilu_apply: input scaling is not supported");
     dim3 grid(ceil_div(a.m, a.cw), nsys);
     const int K = std::max(std::max(a.fwd[0].K, a.bwd[0].K), std::max(a.fwd[1].K, a.bwd[1].K));
+    // timing of the sweeps: X read, Out written by the forward sweep, read and
+    // rewritten by the backward sweep; packed factor values and indices once
+    // per system
+    auto prof_sweep = [&](hipEvent_t e) {
+        if (!e) return;
+        const double vec = (double)nsys * a.n * a.m * sizeof(Cx<T>);
+        const double fac = (double)a.n * (a.fwd[0].K + a.bwd[0].K) * (sizeof(Cx<T>) + 4) +
+                           (double)a.n * (sizeof(Cx<T>) + 8);
+        prof_end(st, e, std::string("ilu_apply_") + (sizeof(T) == 8 ? "c128" : "c64"), 4 * vec + nsys * fac,
+                 (double)nsys * a.m * 8.0 * a.n * (a.fwd[0].K + a.bwd[0].K + 1));
+    };
     hipEvent_t ev = prof_begin(st);
     bool lds = K <= 4;
     int wmax = 0, kmin = K;
@@ -1310,12 +1321,23 @@ void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<
             const int stride = wmax * (a.cw / 2);
             const size_t shv = 2 * sizeof(float4) * (size_t)stride;
             if (blocked) {
+                // three launches, timed one by one: permutation in (the block
+                // read and written once, plus the row order), the two sweeps
+                // (the apply's own bytes, below), permutation out
                 Cx<T>* P = (Cx<T>*)a.blk->ensure(sizeof(Cx<T>) * (size_t)nsys * a.n * a.m);
                 const int* order = a.fwd[0].rows;    // the forward L sweep's packed order
-                blk_perm(st, true, nsys, a.n, a.m, a.cw, order, X, P);
+                const double pbytes = 2.0 * nsys * a.n * a.m * sizeof(Cx<T>) + 4.0 * a.n;
+                blk_perm(st, true, nsys, a.n, a.m, a.cw, order, X, P);   // timed from the event above
+                prof_end(st, ev, "blk_perm_in_c64", pbytes);
+                ev = prof_begin(st);
                 if (a.cw == 2) k_ilu_apply_vec<2, 2, 512, 1, true><<<grid, 512, shv, st>>>(a, P, P, stride);
                 else k_ilu_apply_vec<2, 2, 512, 2, true><<<grid, 512, shv, st>>>(a, P, P, stride);
+                FH_LAUNCH_CHECK();
+                prof_sweep(ev);
+                ev = prof_begin(st);
                 blk_perm(st, false, nsys, a.n, a.m, a.cw, order, P, Out);
+                prof_end(st, ev, "blk_perm_out_c64", pbytes);
+                return;
             } else if (a.cw == 2) k_ilu_apply_vec<2, 2, 512, 1, false><<<grid, 512, shv, st>>>(a, X, Out, stride);
             else if (a.cw == 4) k_ilu_apply_vec<2, 2, 512, 2, false><<<grid, 512, shv, st>>>(a, X, Out, stride);
             else k_ilu_apply_vec<2, 2, 512, 4, false><<<grid, 512, shv, st>>>(a, X, Out, stride);
@@ -1351,15 +1373,7 @@ void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<
     else if (K <= 32) k_ilu_apply<T, 1, 32><<<grid, 256, 0, st>>>(a, X, Out);
     else throw Error(-1, "ILU(0) sweeps support at most 32 off-diagonal entries per triangular row");
     FH_LAUNCH_CHECK();
-    if (ev) {
-        // X read, Out written by the forward sweep, read and rewritten by the
-        // backward sweep; packed factor values and indices once per system
-        const double vec = (double)nsys * a.n * a.m * sizeof(Cx<T>);
-        const double fac = (double)a.n * (a.fwd[0].K + a.bwd[0].K) * (sizeof(Cx<T>) + 4) +
-                           (double)a.n * (sizeof(Cx<T>) + 8);
-        prof_end(st, ev, std::string("ilu_apply_") + (sizeof(T) == 8 ? "c128" : "c64"), 4 * vec + nsys * fac,
-                 (double)nsys * a.m * 8.0 * a.n * (a.fwd[0].K + a.bwd[0].K + 1));
-    }
+    prof_sweep(ev);
 }
 template void ilu_apply<double>(hipStream_t, const IluApplyArgs<double>&, int, zd*, zd*, const double*);
 template void ilu_apply<float>(hipStream_t, const IluApplyArgs<float>&, int, cf*, cf*, const float*);
