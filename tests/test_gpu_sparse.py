@@ -615,3 +615,45 @@ def test_feast_conjugation_closed_subspace_halves_the_solves(handle, precision):
         out[pairs] = rep["iters"]
     print(f"iterations: oracle {ref.iters}, conj_pairs=2 {out[2]}, conj_pairs=1 {out[1]}")
     assert out[2] <= out[1] + 1
+
+
+def test_feast_real_symmetric_quarter_of_the_solves(handle):
+    """Real symmetric A (a 2D Laplacian plus a seeded real potential) under a
+    circle centred on the real axis: sym = 1 skips the left systems and
+    conj_pairs = 2 the lower nodes', so FEAST solves n_e/2 systems per
+    iteration with n_e/2 factorizations (Table tab:solve, real symmetric with
+    a contour symmetric about the real axis) instead of 2 n_e; the
+    eigenvalues equal the oracle's (direct solves, real start blocks) and
+    LAPACK's symmetric eigensolver."""
+    base = W.convdiff2d_csr(16, 0.0, 0.0)
+    rng = np.random.default_rng(21)
+    Ad = W.csr_to_dense(base) + np.diag(rng.uniform(0.0, 400.0, base["n"]))
+    Asp = sp.csr_matrix(Ad)
+    Asp.sort_indices()
+    A = {"n": base["n"], "rowptr": Asp.indptr.astype(np.int32), "colind": Asp.indices.astype(np.int32),
+         "val": Asp.data.astype(np.float64)}
+    ev = np.linalg.eigvalsh(Ad)
+    # the circle through the midpoints of the gaps below ev[10] and above ev[17]
+    lo, hi = 0.5 * (ev[9] + ev[10]), 0.5 * (ev[17] + ev[18])
+    c, r = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    ne, m0 = 16, 16
+    cont = F.Contour(c, r, 1.0, 0.0, ne)
+    inside = ev[np.abs(ev - c) < r]
+    assert len(inside) == 8
+    Y0 = W.subspace(A["n"], m0, 1).real.astype(np.complex128)
+    ref = F.feast(L.csr_matrix(A), None, cont, Y0, Y0.copy(), eps=1e-12, max_iter=40)
+    assert ref.info == 0 and len(ref.lam) == 8
+    assert np.max(np.abs(np.sort(ref.lam.real) - inside)) < 1e-10 * cont.alpha()
+    for pairs in (2, 1):
+        prob = fh.Problem(handle, _csr(A))
+        opts = fh.default_opts(m0, solver=1, precond=2, inner_tol=1e-3, restart=30, max_restarts=2, eps=1e-12,
+                               max_iter=40, sym=1, confirm=1, conj_pairs=pairs)
+        out = fh.feast(prob, c, r, 1.0, 0.0, ne, _cuda(Y0), _cuda(Y0), opts)
+        rep = out["report"]
+        assert out["info"] == 0, rep
+        assert rep["n_factor"] == ne // 2
+        assert rep["n_solve"] == rep["iters"] * (ne // 2 if pairs == 2 else ne), rep
+        assert len(out["lam"]) == 8
+        dl = np.abs(out["lam"][:, None] - ref.lam[None, :])
+        assert max(dl.min(axis=1).max(), dl.min(axis=0).max()) < 1e-10 * cont.alpha()
+        assert np.max(np.abs(np.sort(out["lam"].real) - inside)) < 1e-10 * cont.alpha()
