@@ -505,7 +505,9 @@ def contour_grid(args):
 def copy_calibration():
     """A plain device copy of a known size (1 GiB read, 1 GiB written), run
     three times: the reference for scaling the FETCH_SIZE / WRITE_SIZE
-    counters of rocprofv3 into HBM bytes."""
+    counters of rocprofv3 into HBM bytes.  Then the bandwidth a plain copy
+    reaches (4 GiB blocks, timed with events, read + written bytes): the
+    practical ceiling beside the 8 TB/s peak."""
     import torch
     nbytes = 1 << 30
     x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -513,7 +515,22 @@ def copy_calibration():
     for _ in range(3):
         y.copy_(x)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
+    big = 4 << 30
+    a = torch.ones(big // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3,
+                      "copy_4gib_ms": ms, "copy_GBps_read_plus_write": 2 * big / (ms * 1e-3) / 1e9,
+                      "frac_of_8TBps": 2 * big / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}))
 
 
 # --------------------------------------------------------------------------
