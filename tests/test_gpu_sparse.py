@@ -356,12 +356,13 @@ def test_feast_general_full_size_graded_bq(handle):
     assert out["info"] == 2 and out["report"]["iters"] == 6
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_count_estimate_sparse_parity(handle, precision):
+@pytest.mark.parametrize("precision,pairs", [(0, 1), (1, 1), (1, 2)])
+def test_count_estimate_sparse_parity(handle, precision, pairs):
     """Eigenvalue-count estimate (right solves only) against the oracle's with
     the same Rademacher probes.  On this strongly non-normal operator the
     estimator's spread is huge (64 probes: about -757 for 8 eigenvalues), so
-    only parity is checked; the bound scales with the probes' products."""
+    only parity is checked; the bound scales with the probes' products.
+    conj_pairs = 2: the probes are real, so only the 8 upper nodes are solved."""
     p = _small_convdiff()
     z, w = ct.ellipse_nodes(p.contour.center, p.contour.a, p.contour.ratio, 0.0, 16)
     rng = np.random.default_rng(2)
@@ -372,9 +373,9 @@ def test_count_estimate_sparse_parity(handle, precision):
     prob = fh.Problem(handle, _csr(p.A))
     tau = 1e-10
     opts = fh.default_opts(64, solver=1, precond=2, inner_tol=tau, restart=30, max_restarts=400,
-                           precision=precision, mixed_inner_tol=1e-5, max_refine=30)
+                           precision=precision, mixed_inner_tol=1e-5, max_refine=30, conj_pairs=pairs)
     est, rep = fh.count_estimate(prob, z, w, _cuda(V), opts)
-    assert rep["n_solve"] == 16
+    assert rep["n_solve"] == (8 if pairs == 2 else 16)
     assert rep["inner_relres"] <= tau
     Ad = W.csr_to_dense(p.A)
     kap = max(np.linalg.cond(zj * np.eye(p.n) - Ad) for zj in z)
