@@ -471,15 +471,17 @@ def contour_grid(args):
               + (f" ({errors} contours failed)" if errors else ""), file=sys.stderr, flush=True)
     tts = None
     if args.tts:
-        # to eq:res <= 1e-7 (confirmed exit), the batched complex-FP32 path:
-        # systems whose FP32 refinement stalls are solved with FP64 factors
+        # to eq:res <= 1e-7, the batched complex-FP32 path: systems whose FP32
+        # refinement stalls are solved with FP64 factors.  Exit: --confirm 1
+        # (confirmed by a second passing iteration) or 2 (the paper's exit
+        # iteration, every converged inside pair returned)
         ot = fh.default_opts(m0, precision=fh.FH_PREC_MIXED, eps=1e-7, max_iter=40, inner_tol=EPS_DENSE,
-                             max_refine=6, graph=1, confirm=1)
+                             max_refine=6, graph=1, confirm=args.confirm)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rc2, outs2 = fh.feast_batched([prob] * k, conts, Y0s, Yh0s, ot)
         torch.cuda.synchronize()
-        tts = {"seconds": time.perf_counter() - t0, "status": rc2, "contours": []}
+        tts = {"seconds": time.perf_counter() - t0, "status": rc2, "confirm": args.confirm, "contours": []}
         for name, out, t in zip(names, outs2, truth):
             lamv = out["lam"]
             d = np.abs(lamv[:, None] - t[None, :]) if len(lamv) and len(t) else np.zeros((0, 0))
@@ -489,7 +491,8 @@ def contour_grid(args):
                                     "max_dlam": float(d.min(axis=1).max()) if d.size else None,
                                     "fp64_fallback_systems": int(out["report"]["n_fallback"])})
         nconv = sum(1 for c_ in tts["contours"] if c_["info"] == 0 and c_["m"] == c_["m_true"])
-        print(f"[bench] contour grid to eq:res <= 1e-7 (batched c64 + FP64 fallback): {tts['seconds']:.1f} s, "
+        print(f"[bench] contour grid to eq:res <= 1e-7 (batched c64 + FP64 fallback, confirm={args.confirm}): "
+              f"{tts['seconds']:.1f} s, "
               f"{nconv} of {k} contours converged with all their eigenvalues", file=sys.stderr, flush=True)
     line = {"metric": "multi-contour FEAST (12 contours, one matrix): FEAST iterations of all contours per second",
             "value": K / t_fast, "unit": "batched iterations/s", "n_gpus": 1, "steps": K, "warmup": 1,
@@ -918,6 +921,8 @@ def main():
     ap.add_argument("--batch-nodes", type=int, default=0, help="headline workload: quadrature nodes solved "
                                                                "together (fh_opts.batch_nodes; 0 = as many as fit)")
     ap.add_argument("--tts", action="store_true", help="contour-grid: also run the batched path to eq:res <= 1e-7")
+    ap.add_argument("--confirm", type=int, default=1, choices=[0, 1, 2],
+                    help="contour-grid --tts: exit rule (fh_opts.confirm)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-validate", action="store_true")
     ap.add_argument("--columns", type=int, default=128, help="learned3d: columns per system")

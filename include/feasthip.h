@@ -154,7 +154,13 @@ typedef struct {
                              test passes only because flagged pairs were
                              passed over, the next iteration must pass with
                              the same number of converged inside pairs, and
-                             every inside pair below eps is returned */
+                             every inside pair below eps is returned.  2 =
+                             the paper's exit iteration, and every inside pair
+                             below eps is returned (not only the m of step
+                             5.d): for runs where the number of flagged pairs
+                             changes from one iteration to the next, so that
+                             1 finds no confirming iteration, while the paper's
+                             m = m_r - m_s leaves converged pairs out */
     int conj_pairs;       /* sparse problems with real A (FH_R64): 1 (default)
                              = when the nodes are symmetric about the real
                              axis (each lower node the conjugate of an upper

@@ -592,7 +592,7 @@ struct FeastRun {
         else sel.clear();
         converged = m > 0;
         for (int i : sel) converged = converged && (res[i] < o.eps);
-        if (o.confirm) {
+        if (o.confirm == 1) {
             // optional stricter exit (not the paper's rule): an exit that relies
             // on spurious flags (some inside pair above eps, passed over as
             // flagged) must be confirmed by the next iteration with the same
@@ -655,7 +655,8 @@ struct FeastRun {
 
     // step 5.d: the m = m_r - m_s converged pairs of step 5.c (the m smallest
     // inside residuals) in the first m columns, sorted by (Re, Im).  With
-    // opts.confirm every inside pair whose residual meets eps is returned.
+    // opts.confirm (1 or 2) every inside pair whose residual meets eps is
+    // returned.
     // The remaining Ritz vectors follow in columns m..m0_final-1 so that the
     // whole search subspace can be reused as a start (resume).
     int finish(zd* Yio, zd* Yhio, zd* lambda, double* res_out) {

@@ -408,6 +408,18 @@ def test_feast_confirm_option_returns_every_converged_pair(handle):
     assert np.max(np.abs(lit["lam"][:, None] - con["lam"][None, :]).min(axis=1)) < 1e-10 * cont.alpha()
     X, Xh = con["X"].cpu().numpy(), con["Xh"].cpu().numpy()
     assert np.max(np.abs(Xh.conj().T @ X - np.eye(6))) < 1e-10
+    # confirm = 2: the paper's exit iteration, every converged inside pair
+    # returned -- as many as the oracle's iterate has inside pairs below eps
+    rec = ref.history[-1]
+    n_conv = int(np.count_nonzero(rec["inside"] & (rec["res"] < 1e-12)))
+    assert n_conv >= 5
+    c2 = fh.feast(prob, p.contour.center, p.contour.a, 1.0, 0.0, 8, _cuda(p.Y0), _cuda(p.Yh0),
+                  fh.default_opts(24, eps=1e-12, max_iter=60, confirm=2))
+    assert c2["info"] == 0 and c2["report"]["iters"] == lit["report"]["iters"] == ref.iters
+    assert len(c2["lam"]) == n_conv
+    d = np.abs(c2["lam"][:, None] - lam_true[None, :]).min(axis=1)
+    assert d.max() < 1e-10 * cont.alpha()
+    assert np.max(np.abs(lit["lam"][:, None] - c2["lam"][None, :]).min(axis=1)) < 1e-10 * cont.alpha()
 
 
 def test_biortho_factors_clustered_bq_regression(handle):
