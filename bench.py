@@ -50,8 +50,8 @@ def _problem():
 def _opts(fh, m0, precision, max_iter, eps, resume=0, conj_pairs=1):
     # GMRES(30), two cycles per solve, residual-form filter; the mixed path runs
     # one complex-FP32 solve per filter followed by its FP64 residual check.
-    # orth = 2 (delayed reorthogonalization) acts on the complex-FP32 solves
-    # only; FP64 solves keep classical Gram-Schmidt with reorthogonalization.
+    # orth = 2 (delayed reorthogonalization, two passes over the basis per
+    # Krylov step) applies to the complex-FP32 and the FP64 solves alike.
     # conj_pairs = 2: real start blocks, conjugate Ritz pairs, n_e solves per
     # iteration instead of 2 n_e (real matrix, ellipse centred on the real axis).
     return fh.default_opts(m0, solver=fh.FH_SOLVER_BGMRES, precond=fh.FH_PC_ILU0, restart=30, max_restarts=2,
@@ -935,7 +935,7 @@ def main():
     ap.add_argument("--count", type=int, default=64, help="dense-batch: number of problems")
     ap.add_argument("--orth", type=int, default=2, choices=[0, 1, 2],
                     help="GMRES orthogonalization: 0 CGS2, 1 one projection, 2 delayed reorthogonalization "
-                         "(complex-FP32 solves; FP64 solves use CGS2)")
+                         "(both precisions)")
     args = ap.parse_args()
     global ORTH, BATCH_NODES
     ORTH = args.orth
