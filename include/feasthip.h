@@ -42,7 +42,8 @@ extern "C" {
 #define FH_OK                0
 #define FH_NO_EIG_INSIDE     1   /* no Ritz value inside the contour after max_iter  */
 #define FH_NOT_CONVERGED     2   /* max_iter reached; best pairs and res are filled   */
-#define FH_M0_TOO_SMALL      3   /* m_r >= m0 at exit: the subspace is probably < m   */
+#define FH_M0_TOO_SMALL      3   /* max_iter reached with all m0 Ritz values inside
+                                    the contour: m0 is probably not above m        */
 #define FH_SINGULAR_SHIFT    4   /* zero pivot / breakdown at a node (bad_node = j)   */
 #define FH_INNER_FAILED      5   /* an iterative inner solve missed its tolerance     */
 #define FH_NONFINITE         6   /* non-finite input or state                          */

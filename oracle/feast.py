@@ -248,7 +248,11 @@ def feast(A, B, cont: Contour, Y0, Yh0, eps=1e-12, max_iter=50, keep_history=Fal
           z=None, w=None):
     """Non-Hermitian FEAST (complete algorithm figure).
 
-    info: 0 converged, 1 no eigenvalue inside after max_iter, 2 max_iter reached.
+    info: 0 converged, 1 no eigenvalue inside after max_iter, 2 max_iter reached,
+    3 max_iter reached with every one of the m0 Ritz values inside the contour
+    (m0 is then probably not above the number of eigenvalues inside, which the
+    method requires: m0 >= m in step 0 of the complete algorithm figure; Section
+    2.3 on the slow convergence of too small an m0).
     """
     if z is None:
         z, w = cont.nodes()
@@ -282,6 +286,7 @@ def feast(A, B, cont: Contour, Y0, Yh0, eps=1e-12, max_iter=50, keep_history=Fal
         Y, Yh = rec["Y"], rec["Yh"]
         rho_prev = rec["rho"]
         prev_inside = rec["inside"]
-    info = 1 if not np.any(rec["inside"]) else 2
+    n_inside = int(np.count_nonzero(rec["inside"]))
+    info = 1 if n_inside == 0 else (3 if n_inside >= Y0.shape[1] else 2)
     return FeastResult(info, rec["lam"], rec["Y"], rec["Yh"], rec["res"], max_iter, rec["m0t"],
                        hist, counters)

@@ -22,6 +22,8 @@ FH_R64, FH_C128 = 0, 1
 FH_PREC_FP64, FH_PREC_MIXED = 0, 1
 FH_SOLVER_LU, FH_SOLVER_BGMRES = 0, 1
 FH_PC_NONE, FH_PC_JACOBI, FH_PC_ILU0, FH_PC_LEARNED = 0, 1, 2, 3
+# fh_feast status codes (include/feasthip.h)
+FH_OK, FH_NO_EIG_INSIDE, FH_NOT_CONVERGED, FH_M0_TOO_SMALL = 0, 1, 2, 3
 NET_HIDDEN = 16
 NET_FIXED_CHANNELS = 5
 

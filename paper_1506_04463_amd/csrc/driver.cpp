@@ -633,7 +633,9 @@ struct FeastRun {
         rho_prev.assign(rho.begin(), rho.begin() + mt);
         inside_prev.assign(inside.begin(), inside.begin() + mt);
         if (it == o.max_iter) {
-            info = (m_r == 0) ? FH_NO_EIG_INSIDE : FH_NOT_CONVERGED;
+            // every one of the m0 Ritz values inside: m0 is probably not above
+            // the number of eigenvalues inside (the method needs m0 >= m)
+            info = (m_r == 0) ? FH_NO_EIG_INSIDE : (m_r >= m0in ? FH_M0_TOO_SMALL : FH_NOT_CONVERGED);
             done = true;
             return true;
         }

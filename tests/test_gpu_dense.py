@@ -440,3 +440,28 @@ def test_biortho_factors_clustered_bq_regression(handle):
     assert mt == m
     G = Sh[:, :mt].conj().T @ BQ @ S[:, :mt]
     assert np.max(np.abs(G - np.eye(mt))) < 1e-6
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_feast_degenerate_contours(handle, seed):
+    """A contour around no eigenvalue returns no converged pair, with status 1
+    (no Ritz value inside at the end) or 2 (some, all unconverged filter
+    noise), as the oracle does; m0 = 6 under a contour with 10 eigenvalues
+    inside ends with every Ritz value inside and status 3, the oracle's."""
+    cont = F.Contour(0.1 + 0.1j, 0.25, 1.0, 0.0, 8)
+    p = W.dense_prescribed(n=120, n_in=0, center=0.1 + 0.1j, radius=0.25, ne=8, m0=8, seed=seed)
+    ref = F.feast(p.A, None, cont, p.Y0, p.Yh0, eps=1e-12, max_iter=8)
+    prob = fh.Problem(handle, _cuda(p.A))
+    out = fh.feast(prob, cont.center, cont.a, 1.0, 0.0, 8, _cuda(p.Y0), _cuda(p.Yh0),
+                   fh.default_opts(8, eps=1e-12, max_iter=8))
+    ritz = out["ritz"].cpu().numpy()
+    n_in = int(np.count_nonzero(np.abs(ritz - cont.center) < cont.a))
+    assert ref.info in (fh.FH_NO_EIG_INSIDE, fh.FH_NOT_CONVERGED)
+    assert out["info"] == (fh.FH_NO_EIG_INSIDE if n_in == 0 else fh.FH_NOT_CONVERGED)
+    assert out["report"]["iters"] == 8
+    p = W.dense_prescribed(n=120, n_in=10, center=0.1 + 0.1j, radius=0.25, ne=8, m0=6, seed=seed)
+    ref = F.feast(p.A, None, cont, p.Y0, p.Yh0, eps=1e-12, max_iter=8)
+    prob = fh.Problem(handle, _cuda(p.A))
+    out = fh.feast(prob, cont.center, cont.a, 1.0, 0.0, 8, _cuda(p.Y0), _cuda(p.Yh0),
+                   fh.default_opts(6, eps=1e-12, max_iter=8))
+    assert ref.info == out["info"] == fh.FH_M0_TOO_SMALL

@@ -479,3 +479,24 @@ def test_feast_returns_exactly_the_exit_pairs():
     want = np.sort(h["res"][h["inside"]])[: h["m"]]
     np.testing.assert_array_equal(np.sort(r.res), want)
     assert np.all(r.res < 1e-12)
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_feast_degenerate_contours(seed):
+    """Degenerate cases of the method.  A contour around no eigenvalue: no
+    pair is ever returned as converged (the Ritz values that wander inside
+    are filter noise, flagged spurious or above eps), and the status says
+    whether any Ritz value was inside at the end (1: none, 2: some).  m0
+    below the number of eigenvalues inside (10 inside, m0 = 6; the method
+    needs m0 >= m): no convergence, and at the iteration limit every Ritz
+    value is inside, status 3."""
+    cont = F.Contour(0.1 + 0.1j, 0.25, 1.0, 0.0, 8)
+    p = W.dense_prescribed(n=120, n_in=0, center=0.1 + 0.1j, radius=0.25, ne=8, m0=8, seed=seed)
+    assert not np.any(np.abs(p.info["lam"] - (0.1 + 0.1j)) < 0.25)
+    r = F.feast(p.A, None, cont, p.Y0, p.Yh0, eps=1e-12, max_iter=8)
+    n_in = int(np.count_nonzero(r.history[-1]["inside"]))
+    assert r.info == (1 if n_in == 0 else 2)
+    assert all(h["m"] <= 0 or not np.all(np.sort(h["res"][h["inside"]])[: h["m"]] < 1e-12) for h in r.history)
+    p = W.dense_prescribed(n=120, n_in=10, center=0.1 + 0.1j, radius=0.25, ne=8, m0=6, seed=seed)
+    r = F.feast(p.A, None, cont, p.Y0, p.Yh0, eps=1e-12, max_iter=8)
+    assert r.info == 3 and int(np.count_nonzero(r.history[-1]["inside"])) == 6
