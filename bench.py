@@ -179,9 +179,11 @@ def dense_batch(args):
     print(f"[bench] dense batch: {count} problems, n in [{min(ns)}, {max(ns)}], Ne=8, m0=32", file=sys.stderr,
           flush=True)
     # FP64 refinement of each complex-FP32 solve to the outer target (the same
-    # iterations and eigenvalues as refining to 1e-12, measured)
+    # iterations and eigenvalues as refining to 1e-12, measured); confirmed
+    # exit on both paths, so that every problem returns all of its pairs
+    # (the literal exit can stop while spurious flags hide some of them)
     o = fh.default_opts(32, eps=EPS_DENSE, max_iter=60, precision=fh.FH_PREC_MIXED, inner_tol=EPS_DENSE, max_refine=6,
-                        graph=1)
+                        graph=1, confirm=1)
     # warm-up on a small batch (autotuner, code objects)
     fh.feast_batched(probs[:2], conts[:2], Y0[:2], Yh0[:2], o)
     handle.profile(True)
@@ -199,7 +201,7 @@ def dense_batch(args):
     rhs = sum(2 * 8 * 32 * it for it in iters)
     plain = None
     if not args.no_fp64:
-        o64 = fh.default_opts(32, eps=EPS_DENSE, max_iter=60)
+        o64 = fh.default_opts(32, eps=EPS_DENSE, max_iter=60, confirm=1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         lam64 = []

@@ -264,8 +264,12 @@ __global__ __launch_bounds__(256) void k_ggemm_mfma(const GItem<float>* __restri
     const int m0 = (tl / it.tiles_n) * TS, n0 = (tl % it.tiles_n) * TS;
     constexpr int KT = 16;
     constexpr int NBK = TS / 32;          // 16x16 blocks per wave along each dimension
-    __shared__ float Ar[TS][KT + 1], Ai[TS][KT + 1];
-    __shared__ float Br[KT][TS + 1], Bi[KT][TS + 1];
+    constexpr int NE = TS * KT / 256;     // tile entries of A (and of B) per thread
+    // two stages: the next K tile is loaded into registers while the MFMAs
+    // work on the current one, then stored into the other stage (one
+    // barrier per K tile)
+    __shared__ float Ar[2][TS][KT + 1], Ai[2][TS][KT + 1];
+    __shared__ float Br[2][KT][TS + 1], Bi[2][KT][TS + 1];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wr = (wave >> 1) * (TS / 2), wc = (wave & 1) * (TS / 2);
     const int li = lane & 15, lk = lane >> 4;
@@ -277,34 +281,55 @@ __global__ __launch_bounds__(256) void k_ggemm_mfma(const GItem<float>* __restri
             accr[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
             acci[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
         }
-    for (int k0 = 0; k0 < it.K; k0 += KT) {
-        for (int e = tid; e < TS * KT; e += 256) {
+    cf ra[NE], rb[NE];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const int e = tid + 256 * q;
             int i, kk;
             if (!CA) { i = e / KT; kk = e % KT; } else { kk = e / TS; i = e % TS; }
             const int gi = m0 + i, gk = k0 + kk;
             cf v = czero<float>();
             if (gi < it.M && gk < it.K) v = CA ? conj(it.A[(long)gk * it.lda + gi]) : it.A[(long)gi * it.lda + gk];
-            Ar[i][kk] = v.re;
-            Ai[i][kk] = v.im;
+            ra[q] = v;
             const int kb = e / TS, j = e % TS;
             cf u = czero<float>();
             if (n0 + j < it.N && k0 + kb < it.K) u = it.B[(long)(k0 + kb) * it.ldb + n0 + j];
-            Br[kb][j] = u.re;
-            Bi[kb][j] = u.im;
+            rb[q] = u;
         }
-        __syncthreads();
+    };
+    auto store = [&](int st) {
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const int e = tid + 256 * q;
+            int i, kk;
+            if (!CA) { i = e / KT; kk = e % KT; } else { kk = e / TS; i = e % TS; }
+            Ar[st][i][kk] = ra[q].re;
+            Ai[st][i][kk] = ra[q].im;
+            const int kb = e / TS, j = e % TS;
+            Br[st][kb][j] = rb[q].re;
+            Bi[st][kb][j] = rb[q].im;
+        }
+    };
+    load(0);
+    store(0);
+    __syncthreads();
+    int st = 0;
+    for (int k0 = 0; k0 < it.K; k0 += KT) {
+        const bool more = k0 + KT < it.K;
+        if (more) load(k0 + KT);
 #pragma unroll
         for (int kq = 0; kq < KT; kq += 4) {
             float are[2], aim[2], bre[2], bim[2];
 #pragma unroll
             for (int a = 0; a < NBK; ++a) {
-                are[a] = Ar[wr + 16 * a + li][kq + lk];
-                aim[a] = Ai[wr + 16 * a + li][kq + lk];
+                are[a] = Ar[st][wr + 16 * a + li][kq + lk];
+                aim[a] = Ai[st][wr + 16 * a + li][kq + lk];
             }
 #pragma unroll
             for (int b = 0; b < NBK; ++b) {
-                bre[b] = Br[kq + lk][wc + 16 * b + li];
-                bim[b] = Bi[kq + lk][wc + 16 * b + li];
+                bre[b] = Br[st][kq + lk][wc + 16 * b + li];
+                bim[b] = Bi[st][kq + lk][wc + 16 * b + li];
             }
 #pragma unroll
             for (int a = 0; a < NBK; ++a)
@@ -316,7 +341,9 @@ __global__ __launch_bounds__(256) void k_ggemm_mfma(const GItem<float>* __restri
                     acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aim[a], bre[b], acci[a][b], 0, 0, 0);
                 }
         }
+        if (more) store(st ^ 1);
         __syncthreads();
+        st ^= 1;
     }
 #pragma unroll
     for (int a = 0; a < NBK; ++a)
