@@ -92,6 +92,12 @@ struct SparseState {
     DBuf Hraw, htent, tau, dcoef, scv, scw, dots;   // DCGS2
     DBuf cpd, coefp, flag;   // conjugation-closed filter: column partners, upper/lower weights, real-input flag
     DBuf aval32, atval64, atval32, bn32, Zf;
+    // the operator's rows in the blocked layout's position order (ELL with
+    // SPMM_BLK_SL slots: neighbour positions and FP32 values, of A and of
+    // A^T), built on first use by the product that reads the blocked sweep's
+    // output (ilu_apply with SpmmAfter)
+    DBuf bpos, bcolA, bvalA, bcolAT, bvalAT;
+    bool bell_ready = false;
     NetState* net = nullptr;   // attached learned preconditioner (not owned)
     ~SparseState() {
         for (DBuf* b : owned) delete b;
@@ -106,8 +112,23 @@ void form_mvals(hipStream_t st, const SparseState& S, int ne, const zd* z_dev, z
 void ilu0_factor(hipStream_t st, const SparseState& S, int ne, zd* lu, zd* luT, zd* dinv);
 void pack_sweep_vals(hipStream_t st, const SweepDev& sw, int n, int ne, long nnzM, const zd* lu, zd* ell, zd* diag);
 void to_single(hipStream_t st, long len, const zd* s, cf* d);
+// The operator product that follows the preconditioner in a Krylov step,
+// W_s = alpha (sh_s Z_s - op(A) Z_s) for Z = the preconditioner's output
+// (systems [0, nright) with A, the rest with A^H, as apply_M).  Given to
+// ilu_apply, it is computed straight from the blocked layout of the
+// two-column sweep when that layout is used (no move of Z back to the
+// natural layout); ilu_apply then returns true and Out is not written.
+struct SpmmAfter {
+    SparseState* S = nullptr;
+    int nright = 0;
+    const cf* shifts = nullptr;
+    float alpha = 1.f;
+    cf* W = nullptr;
+};
+constexpr int SPMM_BLK_SL = 5;
 template <typename T>
-void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<T>* Out, const T* scale);
+bool ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<T>* Out, const T* scale,
+               const SpmmAfter* after = nullptr);
 template <typename T>
 void jacobi_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<T>* Out, const T* scale);
 template <typename T>

@@ -1253,9 +1253,164 @@ static void blk_perm(hipStream_t st, bool in, int nsys, int n, int m, int cw, co
     blk_perm_t<BLK_T, 256>(st, in, nsys, n, m, cw, rows, src, dst);
 }
 
+// ---------------------------------------------------------------------------
+// The operator product after the blocked sweep: Out_s = alpha (sh_s Z_s -
+// op(A) Z_s) with Z in the blocked layout [system][column block][position]
+// [lpr] and Out natural.  The rows are taken in position order from an ELL
+// copy of the operator (SL slots per row: neighbour positions and values,
+// empty slots the row itself with weight 0, as in k_spmm_rows2, whose
+// arithmetic this repeats entry by entry).  A workgroup takes BLK_T
+// consecutive positions and every column: on a level-ordered grid the
+// neighbours of a run of positions lie in runs of the levels on either
+// side, and the results leave through an LDS tile as whole natural rows.
+// ---------------------------------------------------------------------------
+__global__ void k_inv_perm(int n, const int* __restrict__ rows, int* __restrict__ pos) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) pos[rows[t]] = t;
+}
+
+template <typename TA>
+__global__ void k_blk_ell(int n, const int* __restrict__ rows, const int* __restrict__ pos,
+                          const int* __restrict__ rowptr, const int* __restrict__ col, const TA* __restrict__ val,
+                          int* __restrict__ bcol, TA* __restrict__ bval) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int i = rows[t], p0 = rowptr[i], p1 = rowptr[i + 1];
+#pragma unroll
+    for (int q = 0; q < SPMM_BLK_SL; ++q) {
+        const int p = p0 + q;
+        const bool has = p < p1;
+        bcol[(long)t * SPMM_BLK_SL + q] = has ? pos[col[p]] : t;
+        bval[(long)t * SPMM_BLK_SL + q] = has ? val[p] : TA{};
+    }
+}
+
+template <typename TA, bool CONJ>
+__global__ __launch_bounds__(256) void k_spmm_blk(int n, int m2, int lpr, const int* __restrict__ rows,
+                                                  const int* __restrict__ bcol, const TA* __restrict__ bval,
+                                                  const Cx<float>* __restrict__ shifts, float alpha,
+                                                  const float4* __restrict__ Z, float4* __restrict__ Out) {
+    constexpr int SL = SPMM_BLK_SL;
+    extern __shared__ unsigned char dsm[];
+    float4* tile = reinterpret_cast<float4*>(dsm);   // [BLK_T][m2 + 1]
+    __shared__ int s_col[BLK_T * SL];
+    __shared__ TA s_val[BLK_T * SL];
+    const int ld = m2 + 1;
+    const int t0 = blockIdx.x * BLK_T, s = blockIdx.y;
+    const int nt = min(BLK_T, n - t0);
+    const int ncb = m2 / lpr;
+    const long nat = (long)s * n * m2;
+    const long blk = (long)s * ncb * n * lpr;
+    for (int e = threadIdx.x; e < nt * SL; e += blockDim.x) {
+        s_col[e] = bcol[(long)t0 * SL + e];
+        s_val[e] = bval[(long)t0 * SL + e];
+    }
+    __syncthreads();
+    const Cx<float> sh = shifts[s];
+    const int tot = nt * m2;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int cb = e / (nt * lpr), r = e - cb * nt * lpr, i = r / lpr, k = r - i * lpr;
+        const float4* Zc = Z + blk + (long)cb * n * lpr + k;
+        float4 xv[SL];
+#pragma unroll
+        for (int q = 0; q < SL; ++q) xv[q] = Zc[(long)s_col[i * SL + q] * lpr];
+        const float4 xr = Zc[(long)(t0 + i) * lpr];
+        Cx<float> a0 = czero<float>(), a1 = czero<float>();
+#pragma unroll
+        for (int q = 0; q < SL; ++q) {
+            mac_val(a0, s_val[i * SL + q], Cx<float>{xv[q].x, xv[q].y}, CONJ);
+            mac_val(a1, s_val[i * SL + q], Cx<float>{xv[q].z, xv[q].w}, CONJ);
+        }
+        Cx<float> r0v = sh * Cx<float>{xr.x, xr.y};
+        Cx<float> r1v = sh * Cx<float>{xr.z, xr.w};
+        r0v = alpha * (r0v - a0);
+        r1v = alpha * (r1v - a1);
+        tile[i * ld + cb * lpr + k] = pair_of(r0v, r1v);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int i = e / m2, j = e - i * m2;
+        Out[nat + (long)rows[t0 + i] * m2 + j] = tile[i * ld + j];
+    }
+}
+
+// the ELL copies of A and A^T in position order (once per problem)
+static void ensure_blk_ell(hipStream_t st, SparseState& S, const int* order) {
+    if (S.bell_ready) return;
+    const int n = S.n;
+    const bool cv = S.A.complex_vals;
+    const size_t vb = cv ? sizeof(cf) : sizeof(float);
+    int* pos = (int*)S.bpos.ensure(sizeof(int) * (size_t)n);
+    k_inv_perm<<<ceil_div(n, 256), 256, 0, st>>>(n, order, pos);
+    FH_LAUNCH_CHECK();
+    for (int tr = 0; tr < 2; ++tr) {
+        const CsrDev& A = tr ? S.AT : S.A;
+        int* bc = (int*)(tr ? S.bcolAT : S.bcolA).ensure(sizeof(int) * (size_t)n * SPMM_BLK_SL);
+        void* bv = (tr ? S.bvalAT : S.bvalA).ensure(vb * (size_t)n * SPMM_BLK_SL);
+        if (cv)
+            k_blk_ell<cf><<<ceil_div(n, 256), 256, 0, st>>>(n, order, pos, A.rowptr, A.col, (const cf*)A.val32, bc,
+                                                            (cf*)bv);
+        else
+            k_blk_ell<float><<<ceil_div(n, 256), 256, 0, st>>>(n, order, pos, A.rowptr, A.col,
+                                                               (const float*)A.val32, bc, (float*)bv);
+        FH_LAUNCH_CHECK();
+    }
+    S.bell_ready = true;
+}
+
+// the product of `f` from the blocked block P (nsys systems, cw columns per
+// block); false when it does not apply (then nothing is launched)
+static bool spmm_after_blocked(hipStream_t st, const SpmmAfter& f, int nsys, int n, int m, int cw, const int* order,
+                               const cf* P) {
+    const char* e = std::getenv("FH_SPMM_BLK");
+    if (e && std::atoi(e) == 0) return false;
+    const char* e2 = std::getenv("FH_SPMM2");
+    if (e2 && std::atoi(e2) == 0) return false;
+    SparseState& S = *f.S;
+    // the selection of the row-staged two-column product (k_spmm_rows2)
+    const bool ok2 = m % 2 == 0 && m >= 16 && m <= 512 && spmm_colblock(m / 2) >= 8;
+    const bool okA = S.A.maxrow >= 1 && S.A.maxrow <= SPMM_BLK_SL;
+    const bool okT = nsys == f.nright || (S.AT.maxrow >= 1 && S.AT.maxrow <= SPMM_BLK_SL);
+    const int m2 = m / 2, lpr = cw / 2;
+    const size_t sh = sizeof(float4) * BLK_T * (size_t)(m2 + 1);
+    const size_t sh_static = (size_t)BLK_T * SPMM_BLK_SL * (sizeof(int) + sizeof(cf));
+    if (!ok2 || !okA || !okT || S.n != n || cw % 2 != 0 || m2 % lpr != 0 || sh + sh_static > 65536) return false;
+    ensure_blk_ell(st, S, order);
+    const long sysf4 = (long)n * m2;   // float4 per system, both layouts
+    const bool cv = S.A.complex_vals;
+    hipEvent_t ev = prof_begin(st);
+    for (int tr = 0; tr < 2; ++tr) {
+        const int s0 = tr ? f.nright : 0, ns = tr ? nsys - f.nright : f.nright;
+        if (ns <= 0) continue;
+        dim3 grid(ceil_div(n, BLK_T), ns);
+        const int* bc = (const int*)(tr ? S.bcolAT : S.bcolA).p;
+        const void* bv = (tr ? S.bvalAT : S.bvalA).p;
+        const float4* z = (const float4*)P + s0 * sysf4;
+        float4* w = (float4*)f.W + s0 * sysf4;
+        if (cv) {
+            if (tr) k_spmm_blk<cf, true><<<grid, 256, sh, st>>>(n, m2, lpr, order, bc, (const cf*)bv, f.shifts + s0,
+                                                                f.alpha, z, w);
+            else k_spmm_blk<cf, false><<<grid, 256, sh, st>>>(n, m2, lpr, order, bc, (const cf*)bv, f.shifts + s0,
+                                                              f.alpha, z, w);
+        } else {
+            k_spmm_blk<float, false><<<grid, 256, sh, st>>>(n, m2, lpr, order, bc, (const float*)bv, f.shifts + s0,
+                                                            f.alpha, z, w);
+        }
+        FH_LAUNCH_CHECK();
+    }
+    if (ev) {
+        const double vec = (double)nsys * n * m * sizeof(cf);
+        const double ell = (double)n * SPMM_BLK_SL * (4.0 + (cv ? sizeof(cf) : sizeof(float))) + 4.0 * n;
+        prof_end(st, ev, "spmm_blk_c64", 2 * vec + (f.nright < nsys && f.nright > 0 ? 2 : 1) * ell,
+                 (double)nsys * m * 8.0 * (SPMM_BLK_SL + 1) * n);
+    }
+    return true;
+}
+
 template <typename T>
-void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<T>* Out, const T* scale) {
-    if (nsys <= 0) return;
+bool ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<T>* Out, const T* scale,
+               const SpmmAfter* after) {
+    if (nsys <= 0) return false;
     FH_REQUIRE(scale == nullptr, -1, "ilu_apply: input scaling is not supported");
     dim3 grid(ceil_div(a.m, a.cw), nsys);
     const int K = std::max(std::max(a.fwd[0].K, a.bwd[0].K), std::max(a.fwd[1].K, a.bwd[1].K));
@@ -1334,10 +1489,12 @@ void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<
                 else k_ilu_apply_vec<2, 2, 512, 2, true><<<grid, 512, shv, st>>>(a, P, P, stride);
                 FH_LAUNCH_CHECK();
                 prof_sweep(ev);
+                // the operator product straight from the blocked layout
+                if (after && spmm_after_blocked(st, *after, nsys, a.n, a.m, a.cw, order, P)) return true;
                 ev = prof_begin(st);
                 blk_perm(st, false, nsys, a.n, a.m, a.cw, order, P, Out);
                 prof_end(st, ev, "blk_perm_out_c64", pbytes);
-                return;
+                return false;
             } else if (a.cw == 2) k_ilu_apply_vec<2, 2, 512, 1, false><<<grid, 512, shv, st>>>(a, X, Out, stride);
             else if (a.cw == 4) k_ilu_apply_vec<2, 2, 512, 2, false><<<grid, 512, shv, st>>>(a, X, Out, stride);
             else k_ilu_apply_vec<2, 2, 512, 4, false><<<grid, 512, shv, st>>>(a, X, Out, stride);
@@ -1374,9 +1531,12 @@ void ilu_apply(hipStream_t st, const IluApplyArgs<T>& a, int nsys, Cx<T>* X, Cx<
     else throw Error(-1, "ILU(0) sweeps support at most 32 off-diagonal entries per triangular row");
     FH_LAUNCH_CHECK();
     prof_sweep(ev);
+    return false;
 }
-template void ilu_apply<double>(hipStream_t, const IluApplyArgs<double>&, int, zd*, zd*, const double*);
-template void ilu_apply<float>(hipStream_t, const IluApplyArgs<float>&, int, cf*, cf*, const float*);
+template bool ilu_apply<double>(hipStream_t, const IluApplyArgs<double>&, int, zd*, zd*, const double*,
+                                const SpmmAfter*);
+template bool ilu_apply<float>(hipStream_t, const IluApplyArgs<float>&, int, cf*, cf*, const float*,
+                               const SpmmAfter*);
 
 // Jacobi: Out = D^{-1} X (side 0) or D^{-H} X (side 1), D = diag(z - A) per node
 template <typename T>

@@ -448,6 +448,29 @@ static void apply_P(Ctx& c, SparseState& S, const Batch& b, int precond, Cx<T>* 
     }
 }
 
+// Z = P^{-1} V_k and W = M Z of a Krylov step with the fixed ILU(0)
+// preconditioner in complex FP32: when the sweep runs in its blocked layout
+// the product reads that layout directly (Z is then not written).  False
+// when the step is not of that kind (nothing done).
+template <typename T>
+static bool ilu_step(Ctx& c, SparseState& S, const Batch& b, int precond, bool flex, const Cx<T>* shifts,
+                     Cx<T>* Vk, Cx<T>* Zk, Cx<T>* W) {
+    if constexpr (sizeof(T) == 4) {
+        if (flex || precond != FH_PC_ILU0) return false;
+        SpmmAfter f;
+        f.S = &S;
+        f.nright = b.nright;
+        f.shifts = shifts;
+        f.alpha = 1.f;
+        f.W = W;
+        const IluApplyArgs<T> a = ilu_args<T>(S, b.m, precond);
+        if (!ilu_apply<T>(c.stream, a, b.nsys, Vk, Zk, nullptr, &f)) apply_M<T>(c, S, b, shifts, T(1), Zk, nullptr, W);
+        return true;
+    } else {
+        return false;
+    }
+}
+
 struct SolveStats {
     long long steps = 0;
     double relres = 0.0;
@@ -548,8 +571,10 @@ static SolveStats gmres(Ctx& c, SparseState& S, const Batch& b, const Cx<T>* shi
             Cx<T>* Vk = V + (long)k * vstride;
             Cx<T>* Vk1 = V + (long)(k + 1) * vstride;
             Cx<T>* Zk = flex ? Zf + (long)k * vstride : Z;
-            apply_P<T>(c, S, b, precond, Vk, Zk, (const T*)nullptr);    // Z = P^{-1} V_k
-            apply_M<T>(c, S, b, shifts, T(1), Zk, nullptr, Vk1);        // W = M Z
+            if (!ilu_step<T>(c, S, b, precond, flex, shifts, Vk, Zk, Vk1)) {
+                apply_P<T>(c, S, b, precond, Vk, Zk, (const T*)nullptr);    // Z = P^{-1} V_k
+                apply_M<T>(c, S, b, shifts, T(1), Zk, nullptr, Vk1);        // W = M Z
+            }
             kexec = k + 1;
             stats.steps++;
             if (delayed) {
