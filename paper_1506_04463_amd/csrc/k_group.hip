@@ -202,7 +202,10 @@ __global__ __launch_bounds__(256) void k_ggemm_fma(const GItem<T>* __restrict__ 
     for (int a = 0; a < RA; ++a)
 #pragma unroll
         for (int b = 0; b < RB; ++b) acc[a][b] = czero<T>();
-    for (int k0 = 0; k0 < it.K; k0 += KT) {
+    // the next K tile is loaded into registers while the FMAs work on the
+    // current one from LDS
+    Cx<T> ra[RA], rb[RB];
+    auto load = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < RA; ++q) {
             const int e = tid + 256 * q;
@@ -211,7 +214,7 @@ __global__ __launch_bounds__(256) void k_ggemm_fma(const GItem<T>* __restrict__ 
             const int gi = m0 + i, gk = k0 + kk;
             Cx<T> v = czero<T>();
             if (gi < it.M && gk < it.K) v = CA ? conj(it.A[(long)gk * it.lda + gi]) : it.A[(long)gi * it.lda + gk];
-            As[kk][i] = v;
+            ra[q] = v;
         }
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
@@ -219,10 +222,30 @@ __global__ __launch_bounds__(256) void k_ggemm_fma(const GItem<T>* __restrict__ 
             const int kb = e / TN, j = e % TN;
             Cx<T> u = czero<T>();
             if (n0 + j < it.N && k0 + kb < it.K) u = it.B[(long)(k0 + kb) * it.ldb + n0 + j];
-            Bs[kb][j] = u;
+            rb[q] = u;
         }
-        __syncthreads();
+    };
+    auto store = [&]() {
 #pragma unroll
+        for (int q = 0; q < RA; ++q) {
+            const int e = tid + 256 * q;
+            int i, kk;
+            if (!CA) { i = e / KT; kk = e % KT; } else { kk = e / TM; i = e % TM; }
+            As[kk][i] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int e = tid + 256 * q;
+            Bs[e / TN][e % TN] = rb[q];
+        }
+    };
+    load(0);
+    store();
+    __syncthreads();
+    for (int k0 = 0; k0 < it.K; k0 += KT) {
+        const bool more = k0 + KT < it.K;
+        if (more) load(k0 + KT);
+#pragma unroll 2
         for (int kk = 0; kk < KT; ++kk) {
             Cx<T> av[RA], bv[RB];
 #pragma unroll
@@ -235,6 +258,10 @@ __global__ __launch_bounds__(256) void k_ggemm_fma(const GItem<T>* __restrict__ 
                 for (int b = 0; b < RB; ++b) cfma(acc[a][b], av[a], bv[b]);
         }
         __syncthreads();
+        if (more) {
+            store();
+            __syncthreads();
+        }
     }
 #pragma unroll
     for (int a = 0; a < RA; ++a) {
