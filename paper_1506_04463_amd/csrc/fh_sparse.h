@@ -97,6 +97,8 @@ struct SparseState {
     // A^T), built on first use by the product that reads the blocked sweep's
     // output (ilu_apply with SpmmAfter)
     DBuf bpos, bcolA, bvalA, bcolAT, bvalAT;
+    DBuf btiles;           // int2 (first position, count) per workgroup of that product
+    int btiles_n = 0;
     bool bell_ready = false;
     NetState* net = nullptr;   // attached learned preconditioner (not owned)
     ~SparseState() {

@@ -1260,9 +1260,12 @@ static void blk_perm(hipStream_t st, bool in, int nsys, int n, int m, int cw, co
 // copy of the operator (SL slots per row: neighbour positions and values,
 // empty slots the row itself with weight 0, as in k_spmm_rows2, whose
 // arithmetic this repeats entry by entry).  A workgroup takes BLK_T
-// consecutive positions and every column: on a level-ordered grid the
-// neighbours of a run of positions lie in runs of the levels on either
-// side, and the results leave through an LDS tile as whole natural rows.
+// consecutive positions of one level and every column: on a level-ordered
+// grid the neighbours of a run of positions lie in runs of the levels on
+// either side, and the results leave through an LDS tile as whole natural
+// rows.  The tiles are dealt to the 8 XCDs by their place within their level
+// (workgroup w runs on XCD w mod 8), so that the tiles that read the same
+// runs of neighbouring levels share one L2.
 // ---------------------------------------------------------------------------
 __global__ void k_inv_perm(int n, const int* __restrict__ rows, int* __restrict__ pos) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1286,18 +1289,19 @@ __global__ void k_blk_ell(int n, const int* __restrict__ rows, const int* __rest
 }
 
 template <typename TA, bool CONJ>
-__global__ __launch_bounds__(256) void k_spmm_blk(int n, int m2, int lpr, const int* __restrict__ rows,
-                                                  const int* __restrict__ bcol, const TA* __restrict__ bval,
-                                                  const Cx<float>* __restrict__ shifts, float alpha,
-                                                  const float4* __restrict__ Z, float4* __restrict__ Out) {
+__global__ __launch_bounds__(256) void k_spmm_blk(int n, int m2, int lpr, const int2* __restrict__ tiles,
+                                                  const int* __restrict__ rows, const int* __restrict__ bcol,
+                                                  const TA* __restrict__ bval, const Cx<float>* __restrict__ shifts,
+                                                  float alpha, const float4* __restrict__ Z, float4* __restrict__ Out) {
     constexpr int SL = SPMM_BLK_SL;
     extern __shared__ unsigned char dsm[];
     float4* tile = reinterpret_cast<float4*>(dsm);   // [BLK_T][m2 + 1]
     __shared__ int s_col[BLK_T * SL];
     __shared__ TA s_val[BLK_T * SL];
     const int ld = m2 + 1;
-    const int t0 = blockIdx.x * BLK_T, s = blockIdx.y;
-    const int nt = min(BLK_T, n - t0);
+    const int2 tl = tiles[blockIdx.x];                // (first position, count <= BLK_T); count 0: padding
+    const int t0 = tl.x, nt = tl.y, s = blockIdx.y;
+    if (nt <= 0) return;
     const int ncb = m2 / lpr;
     const long nat = (long)s * n * m2;
     const long blk = (long)s * ncb * n * lpr;
@@ -1355,6 +1359,31 @@ static void ensure_blk_ell(hipStream_t st, SparseState& S, const int* order) {
                                                                (const float*)A.val32, bc, (float*)bv);
         FH_LAUNCH_CHECK();
     }
+    // tiles of at most BLK_T positions within one level; the tiles of a
+    // level are split into 8 contiguous groups by their place in it, group x
+    // goes to the workgroups w with w mod 8 = x, in level order
+    const SweepDev& sw = S.swL;
+    std::vector<int> lp(sw.nlev + 1);
+    FH_HIP(hipMemcpyAsync(lp.data(), sw.lev_ptr, sizeof(int) * lp.size(), hipMemcpyDeviceToHost, st));
+    FH_HIP(hipStreamSynchronize(st));
+    std::vector<std::vector<int2>> lists(8);
+    for (int l = 0; l < sw.nlev; ++l) {
+        const int a = lp[l], b = lp[l + 1], ntl = ceil_div(b - a, BLK_T);
+        for (int j = 0; j < ntl; ++j) {
+            const int x = (int)((long)j * 8 / ntl);
+            const int t0 = a + j * BLK_T;
+            lists[x].push_back(int2{t0, std::min(BLK_T, b - t0)});
+        }
+    }
+    size_t len = 0;
+    for (const auto& v : lists) len = std::max(len, v.size());
+    std::vector<int2> tl(8 * len, int2{0, 0});
+    for (int x = 0; x < 8; ++x)
+        for (size_t q = 0; q < lists[x].size(); ++q) tl[q * 8 + x] = lists[x][q];
+    int2* dt = (int2*)S.btiles.ensure(sizeof(int2) * std::max<size_t>(1, tl.size()));
+    FH_HIP(hipMemcpyAsync(dt, tl.data(), sizeof(int2) * tl.size(), hipMemcpyHostToDevice, st));
+    FH_HIP(hipStreamSynchronize(st));
+    S.btiles_n = (int)tl.size();
     S.bell_ready = true;
 }
 
@@ -1382,19 +1411,20 @@ static bool spmm_after_blocked(hipStream_t st, const SpmmAfter& f, int nsys, int
     for (int tr = 0; tr < 2; ++tr) {
         const int s0 = tr ? f.nright : 0, ns = tr ? nsys - f.nright : f.nright;
         if (ns <= 0) continue;
-        dim3 grid(ceil_div(n, BLK_T), ns);
+        dim3 grid(S.btiles_n, ns);
+        const int2* tiles = (const int2*)S.btiles.p;
         const int* bc = (const int*)(tr ? S.bcolAT : S.bcolA).p;
         const void* bv = (tr ? S.bvalAT : S.bvalA).p;
         const float4* z = (const float4*)P + s0 * sysf4;
         float4* w = (float4*)f.W + s0 * sysf4;
         if (cv) {
-            if (tr) k_spmm_blk<cf, true><<<grid, 256, sh, st>>>(n, m2, lpr, order, bc, (const cf*)bv, f.shifts + s0,
-                                                                f.alpha, z, w);
-            else k_spmm_blk<cf, false><<<grid, 256, sh, st>>>(n, m2, lpr, order, bc, (const cf*)bv, f.shifts + s0,
-                                                              f.alpha, z, w);
+            if (tr) k_spmm_blk<cf, true><<<grid, 256, sh, st>>>(n, m2, lpr, tiles, order, bc, (const cf*)bv,
+                                                                f.shifts + s0, f.alpha, z, w);
+            else k_spmm_blk<cf, false><<<grid, 256, sh, st>>>(n, m2, lpr, tiles, order, bc, (const cf*)bv,
+                                                              f.shifts + s0, f.alpha, z, w);
         } else {
-            k_spmm_blk<float, false><<<grid, 256, sh, st>>>(n, m2, lpr, order, bc, (const float*)bv, f.shifts + s0,
-                                                            f.alpha, z, w);
+            k_spmm_blk<float, false><<<grid, 256, sh, st>>>(n, m2, lpr, tiles, order, bc, (const float*)bv,
+                                                            f.shifts + s0, f.alpha, z, w);
         }
         FH_LAUNCH_CHECK();
     }
