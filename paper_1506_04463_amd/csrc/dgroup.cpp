@@ -9,10 +9,9 @@
 namespace fh {
 
 // ---------------------------------------------------------------------------
-// autotuner: time the two MFMA tiles, each with a workgroup per tile and
-// with a persistent grid, on a GEMM of the given shape (C -= A B with M x K
-// and K x N operands in scratch memory) and keep the fastest per shape class
-// for the life of the handle
+// autotuner: time the two MFMA tiles on a GEMM of the given shape (C -= A B
+// with M x K and K x N operands in scratch memory) and keep the faster one
+// per shape class for the life of the handle
 // ---------------------------------------------------------------------------
 static int autotune_tile(Ctx& c, int M, int N, int K, int copies) {
     auto cls = [](int v) {
@@ -35,7 +34,7 @@ static int autotune_tile(Ctx& c, int M, int N, int K, int copies) {
     FH_HIP(hipEventCreate(&e1));
     float best = 1e30f;
     int pick = GTILE_64;
-    for (int tile : {(int)GTILE_64, (int)GTILE_32, GTILE_64 | GTILE_PERSIST, GTILE_32 | GTILE_PERSIST}) {
+    for (int tile : {GTILE_64, GTILE_32}) {
         GroupPlan<float> plan;
         group_gemm_plan<float>(plan, false, items, tile);
         plan.run(c.stream);   // warm-up

@@ -48,10 +48,8 @@ struct GOp {
     int narrow = 0;     // FP64 GEMM: 128 x 32 tiles (every item has at most 32 columns)
 };
 
-// GEMM tile used by the grouped MFMA kernel (chosen by the autotuner);
-// GTILE_PERSIST or-ed in: a persistent launch (as many workgroups as the
-// device holds at once, each looping over the tiles of every item)
-enum { GTILE_64 = 0, GTILE_32 = 1, GTILE_PERSIST = 2 };
+// GEMM tile used by the grouped MFMA kernel (chosen by the autotuner)
+enum { GTILE_64 = 0, GTILE_32 = 1 };
 
 template <typename T>
 struct GroupPlan {

@@ -283,12 +283,9 @@ __global__ __launch_bounds__(256) void k_ggemm_fma(const GItem<T>* __restrict__ 
 // each as 2 x 2 blocks of 16 x 16; TS = 32: each wave one 16 x 16 block.
 // Lane l of a 16x16x4 MFMA supplies A[l % 16][l / 16] and B[l / 16][l % 16];
 // its 4 results are D[4 (l / 16) + v][l % 16].
-// The workgroups loop over the tiles t = blockIdx.x, blockIdx.x + gridDim.x,
-// ... < ntiles: one tile each when the grid has a workgroup per tile, or a
-// persistent grid sized to the device (GTILE_PERSIST).
 template <bool CA, int TS>
-__global__ __launch_bounds__(256) void k_ggemm_mfma(const GItem<float>* __restrict__ items, int nitems, int ntiles) {
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+__global__ __launch_bounds__(256) void k_ggemm_mfma(const GItem<float>* __restrict__ items, int nitems) {
+    const int t = blockIdx.x;
     const GItem<float> it = items[find_item(items, nitems, t)];
     const int tl = t - it.tile0;
     const int m0 = (tl / it.tiles_n) * TS, n0 = (tl % it.tiles_n) * TS;
@@ -390,7 +387,6 @@ __global__ __launch_bounds__(256) void k_ggemm_mfma(const GItem<float>* __restri
                     c = r;
                 }
             }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -474,7 +470,7 @@ void add_cast(hipStream_t st, long len, const cf* x, zd* y) {
 // ---------------------------------------------------------------------------
 // plans
 // ---------------------------------------------------------------------------
-static int tile_of(int tile) { return (tile & GTILE_32) ? 32 : 64; }
+static int tile_of(int tile) { return tile == GTILE_32 ? 32 : 64; }
 
 template <typename T>
 static void launch_gemm(hipStream_t st, const GOp& op, const void* list, int tile);
@@ -497,22 +493,12 @@ template <>
 void launch_gemm<float>(hipStream_t st, const GOp& op, const void* list, int tile) {
     const GItem<float>* it = (const GItem<float>*)list;
     const bool c = op.kind == GOP_GEMM_C;
-    // persistent grid: the workgroups the device holds at once (64 x 64 tiles:
-    // 4 per CU, 34 KB of LDS each; 32 x 32: 8 per CU)
-    static int ncu = 0;
-    if (ncu == 0) {
-        int dev = 0;
-        FH_HIP(hipGetDevice(&dev));
-        FH_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    }
-    const bool t32 = (tile & GTILE_32) != 0;
-    const int grid = (tile & GTILE_PERSIST) ? std::max(1, std::min(op.tiles, ncu * (t32 ? 8 : 4))) : op.tiles;
-    if (t32) {
-        if (c) k_ggemm_mfma<true, 32><<<grid, 256, 0, st>>>(it, op.count, op.tiles);
-        else k_ggemm_mfma<false, 32><<<grid, 256, 0, st>>>(it, op.count, op.tiles);
+    if (tile == GTILE_32) {
+        if (c) k_ggemm_mfma<true, 32><<<op.tiles, 256, 0, st>>>(it, op.count);
+        else k_ggemm_mfma<false, 32><<<op.tiles, 256, 0, st>>>(it, op.count);
     } else {
-        if (c) k_ggemm_mfma<true, 64><<<grid, 256, 0, st>>>(it, op.count, op.tiles);
-        else k_ggemm_mfma<false, 64><<<grid, 256, 0, st>>>(it, op.count, op.tiles);
+        if (c) k_ggemm_mfma<true, 64><<<op.tiles, 256, 0, st>>>(it, op.count);
+        else k_ggemm_mfma<false, 64><<<op.tiles, 256, 0, st>>>(it, op.count);
     }
     FH_LAUNCH_CHECK();
 }
@@ -535,7 +521,7 @@ void GroupPlan<T>::run(hipStream_t st) const {
                 hipEvent_t ev = prof_begin(st);
                 launch_gemm<T>(st, op, list, tile);
                 if (ev)
-                    prof_end(st, ev, std::is_same<T, float>::value ? ((tile & GTILE_32) ? "ggemm_c64_mfma32" : "ggemm_c64_mfma64")
+                    prof_end(st, ev, std::is_same<T, float>::value ? (tile == GTILE_32 ? "ggemm_c64_mfma32" : "ggemm_c64_mfma64")
                                                                    : "ggemm_c128_fma",
                              op.bytes, op.flops);
                 break;
