@@ -625,7 +625,7 @@ def schrodinger(args):
     iteration; the fast run then continues to eq:res <= 1e-9 and its
     eigenpairs are checked against the reference eigenvalues (ARPACK
     shift-invert, tests/golden) and for X^H X = I, Xh = conj(X) and the
-    spec residual."""
+    1-norm residual of the eigenpair gate."""
     import torch
     import workloads as W
     import paper_1506_04463_amd as fh
@@ -758,7 +758,7 @@ def _hbm_target(kernels, target=0.6):
 def _c5_validate(fh, torch, prob, p, fin, eigs, alpha):
     """Returned eigenpairs against the reference eigenvalues inside the
     contour (count and complex distance), X^H X = I, Xh parallel to conj(X)
-    and the spec residual ||A x - lam x||_1 / (||A||_1 ||x||_1) of both
+    and the 1-norm residual ||A x - lam x||_1 / (||A||_1 ||x||_1) of both
     sides, with A x from the library's sparse product."""
     c = p.contour
     u = (eigs - c.center) * np.exp(-1j * c.angle)

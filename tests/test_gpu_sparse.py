@@ -218,7 +218,7 @@ def test_feast_sparse_convdiff_small(handle, precision, precond, orth, batch_nod
     oracle's direct-solve FEAST and the closed-form spectrum.  The exit
     threshold is eq:res <= 1e-11: with inexact inner solves eq:res levels off
     between 1e-13 and 2e-11 on this grid, so 1e-12 would be met only at a
-    favourable iteration; the spec residual gate below stays 1e-10.
+    favourable iteration; the 1-norm residual gate below stays 1e-10.
     (0, 1, ...): Jacobi instead of ILU(0); (0, 2, 2, 0): delayed
     reorthogonalization in FP64."""
     p = _small_convdiff(N=24, m_in=10, m0=20)
@@ -474,7 +474,7 @@ def test_feast_convdiff_full_size_closed_form(handle):
     m0 = 64) in the launch configuration of its benchmark (complex-FP32
     GMRES(30) x 2 + ILU(0), DCGS2, residual form), to eq:res <= 1e-9: the 41
     eigenvalues inside equal the closed-form spectrum to 1e-10 alpha, Xh^H X = I,
-    spec residuals of both sides <= 1e-10."""
+    1-norm residuals of both sides <= 1e-10."""
     p = W.convdiff2d(N=256, bx=20.0, by=10.0, m_in=41, ne=16, m0=64, ratio=0.3, seed=2)
     c = p.contour
     prob = fh.Problem(handle, _csr(p.A))
